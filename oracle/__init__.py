@@ -1,0 +1,345 @@
+"""FP64 CPU oracle for fan-beam coded-aperture coherent-scatter reconstruction.
+
+TEST INFRASTRUCTURE.  Only tests/, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library (``paper_1603_06400_amd``) and neither imports the
+other; both consume ``paper_1603_06400_amd.inputs`` (seeded inputs only).
+
+Layers, each following the paper (Odinaka et al., arXiv:1603.06400):
+
+* ``forward`` / ``adjoint`` / ``dense`` -- the system matrix of Sec. II eq. 2
+  evaluated per triple in double precision by ``csx_oracle.c`` (Alg. 1 and
+  Alg. 3 without any optimisation).
+* ``objective`` -- J(f) = L(f) + beta R(f) of Sec. V (eqs. overall_objective,
+  standard_EPR) with the quadratic potential psi(t) = t^2/2.
+* ``surrogate_coefficients`` / ``lemma_minimizer`` / ``recon_step`` /
+  ``recon`` -- the separable-surrogate EM-type update of Sec. VI, Alg. 5 and
+  App. B-C (eqs. grad_sep_obj, f_update, Lemma 1).
+
+Parity status: every function here is pinned by tests in tests/test_oracle_*.py
+(closed forms, brute force, invariants); the absolute normalisation C has no
+numeric value in the paper and is an input.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+from scipy.special import gammaln
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "csx_oracle.c")
+_LIBDIR = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_LIBDIR, "libcsx_oracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle (gcc, OpenMP, no fast-math, no FMA contraction)."""
+    os.makedirs(_LIBDIR, exist_ok=True)
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        gp = P(_OrcGeom)
+        dp = P(ctypes.c_double)
+        ip = P(ctypes.c_int)
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_max_threads.restype = ctypes.c_int
+        lib.orc_pair_factors.argtypes = [gp, ctypes.c_int, ctypes.c_int, dp]
+        lib.orc_spectral_factor.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        lib.orc_spectral_factor.restype = ctypes.c_double
+        lib.orc_forward.argtypes = [gp, dp, dp]
+        lib.orc_forward_pixels.argtypes = [gp, dp, ip, ctypes.c_int, dp]
+        lib.orc_adjoint.argtypes = [gp, dp, dp]
+        lib.orc_adjoint_voxels.argtypes = [gp, dp, ip, ctypes.c_int, dp]
+        lib.orc_dense.argtypes = [gp, dp]
+        lib.orc_census.argtypes = [gp, dp]
+        lib.orc_margins.argtypes = [gp, dp]
+        _lib = lib
+    return _lib
+
+
+class _OrcGeom(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("nz", ctypes.c_int),
+        ("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
+        ("z_min", ctypes.c_double), ("z_max", ctypes.c_double),
+        ("nq", ctypes.c_int), ("q", ctypes.POINTER(ctypes.c_double)),
+        ("ndx", ctypes.c_int), ("ndy", ctypes.c_int),
+        ("det_pitch", ctypes.c_double), ("det_z", ctypes.c_double),
+        ("mask_z", ctypes.c_double), ("mask_pitch", ctypes.c_double),
+        ("mask_nx", ctypes.c_int), ("mask_ny", ctypes.c_int),
+        ("mask", ctypes.POINTER(ctypes.c_ubyte)),
+        ("ne", ctypes.c_int), ("e_lo", ctypes.c_double), ("e_hi", ctypes.c_double),
+        ("phi", ctypes.POINTER(ctypes.c_double)),
+        ("C", ctypes.c_double), ("hc", ctypes.c_double),
+    ]
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Oracle:
+    """Binds one scan geometry (an ``inputs.ScanGeometry``) to the C oracle."""
+
+    def __init__(self, geom, phi: Optional[np.ndarray] = None):
+        self.geom = geom
+        self._q = np.ascontiguousarray(geom.q, dtype=np.float64)
+        self._phi = np.ascontiguousarray(geom.phi if phi is None else phi, dtype=np.float64)
+        self._mask = np.ascontiguousarray(geom.mask, dtype=np.uint8)
+        s = _OrcGeom()
+        s.nx, s.nz = geom.nx, geom.nz
+        s.x_min, s.x_max, s.z_min, s.z_max = geom.x_min, geom.x_max, geom.z_min, geom.z_max
+        s.nq, s.q = self._q.shape[0], _dptr(self._q)
+        s.ndx, s.ndy, s.det_pitch, s.det_z = geom.ndx, geom.ndy, geom.det_pitch, geom.det_z
+        s.mask_z, s.mask_pitch = geom.mask_z, geom.mask_pitch
+        s.mask_ny, s.mask_nx = self._mask.shape
+        s.mask = self._mask.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
+        s.ne, s.e_lo, s.e_hi, s.phi = self._phi.shape[0], geom.e_lo, geom.e_hi, _dptr(self._phi)
+        s.C, s.hc = geom.C, geom.hc
+        self._s = s
+        self._lib = _load()
+
+    # ---- system matrix -------------------------------------------------------------
+    def pair(self, j: int, i: int) -> dict:
+        out = np.zeros(9)
+        self._lib.orc_pair_factors(ctypes.byref(self._s), int(j), int(i), _dptr(out))
+        keys = ["Gso", "God", "T", "dtheta", "sin", "cos", "sin_half", "cos_half", "kappa"]
+        return dict(zip(keys, out.tolist()))
+
+    def spectral_factor(self, j: int, i: int, q: float) -> float:
+        return float(self._lib.orc_spectral_factor(ctypes.byref(self._s), int(j), int(i), float(q)))
+
+    def forward(self, f: np.ndarray) -> np.ndarray:
+        g = self.geom
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(g.nz, g.nx, g.nq)
+        out = np.zeros((g.ndy, g.ndx))
+        self._lib.orc_forward(ctypes.byref(self._s), _dptr(f), _dptr(out))
+        return out
+
+    def forward_pixels(self, f: np.ndarray, pix: Sequence[int]) -> np.ndarray:
+        g = self.geom
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(g.nz, g.nx, g.nq)
+        pix = np.ascontiguousarray(pix, dtype=np.int32)
+        out = np.zeros(pix.shape[0])
+        self._lib.orc_forward_pixels(ctypes.byref(self._s), _dptr(f),
+                                     pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                     int(pix.shape[0]), _dptr(out))
+        return out
+
+    def adjoint(self, y: np.ndarray) -> np.ndarray:
+        g = self.geom
+        y = np.ascontiguousarray(y, dtype=np.float64).reshape(g.ndy, g.ndx)
+        out = np.zeros((g.nz, g.nx, g.nq))
+        self._lib.orc_adjoint(ctypes.byref(self._s), _dptr(y), _dptr(out))
+        return out
+
+    def adjoint_voxels(self, y: np.ndarray, vox: Sequence[int]) -> np.ndarray:
+        g = self.geom
+        y = np.ascontiguousarray(y, dtype=np.float64).reshape(g.ndy, g.ndx)
+        vox = np.ascontiguousarray(vox, dtype=np.int32)
+        out = np.zeros((vox.shape[0], g.nq))
+        self._lib.orc_adjoint_voxels(ctypes.byref(self._s), _dptr(y),
+                                     vox.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                     int(vox.shape[0]), _dptr(out))
+        return out
+
+    def dense(self) -> np.ndarray:
+        g = self.geom
+        H = np.zeros((g.npix, g.nvox * g.nq))
+        self._lib.orc_dense(ctypes.byref(self._s), _dptr(H))
+        return H
+
+    def census(self) -> dict:
+        out = np.zeros(4)
+        self._lib.orc_census(ctypes.byref(self._s), _dptr(out))
+        return {"pairs": out[0], "open_pairs": out[1], "open_triples_in_band": out[2],
+                "open_pairs_in_band": out[3]}
+
+    def margins(self) -> dict:
+        out = np.zeros(2)
+        self._lib.orc_margins(ctypes.byref(self._s), _dptr(out))
+        return {"mask_edge_mm": out[0], "bin_edge": out[1]}
+
+    # ---- solver (Sec. V-VI, App. B-C) -------------------------------------------------
+    def sensitivity(self) -> np.ndarray:
+        """b^(1) = Back_project(1) (Alg. 5, precompute line)."""
+        g = self.geom
+        return self.adjoint(np.ones((g.ndy, g.ndx)))
+
+    def recon_step(self, y, r, fhat, beta, b1=None):
+        """One iteration of Alg. 5 from fhat; returns (f_next, J(fhat))."""
+        g = self.geom
+        y = np.asarray(y, dtype=np.float64).reshape(g.ndy, g.ndx)
+        r = np.zeros_like(y) if r is None else np.asarray(r, dtype=np.float64).reshape(y.shape)
+        fhat = np.asarray(fhat, dtype=np.float64).reshape(g.nz, g.nx, g.nq)
+        if b1 is None:
+            b1 = self.sensitivity()
+        z = self.forward(fhat) + r
+        J = objective_from_mean(y, z, fhat, beta)
+        b2 = self.adjoint(poisson_ratio(y, z))
+        return em_update(fhat, b1, b2, beta), J
+
+    def recon(self, y, r, f0, n_iter, beta):
+        """Alg. 5: n_iter iterations from f0; returns (f_T, [J(f^0), ..., J(f^T)])."""
+        b1 = self.sensitivity()
+        f = np.asarray(f0, dtype=np.float64).copy()
+        hist = []
+        for _ in range(n_iter):
+            f, J = self.recon_step(y, r, f, beta, b1=b1)
+            hist.append(J)
+        g = self.geom
+        rr = np.zeros((g.ndy, g.ndx)) if r is None else np.asarray(r, dtype=np.float64).reshape(g.ndy, g.ndx)
+        hist.append(objective_from_mean(np.asarray(y, dtype=np.float64).reshape(g.ndy, g.ndx),
+                                        self.forward(f) + rr, f, beta))
+        return f, np.array(hist)
+
+    def objective(self, y, r, f, beta) -> float:
+        g = self.geom
+        y = np.asarray(y, dtype=np.float64).reshape(g.ndy, g.ndx)
+        r = np.zeros_like(y) if r is None else np.asarray(r, dtype=np.float64).reshape(y.shape)
+        return objective_from_mean(y, self.forward(f) + r, f, beta)
+
+
+# ---- pieces of the objective and the update ----------------------------------------------
+
+def uniform_start(y: np.ndarray, b1: np.ndarray) -> np.ndarray:
+    """f^0 = sum(y) / sum(b^(1)) in every voxel and q (uniform initial image)."""
+    return np.full(b1.shape, float(np.sum(y)) / float(np.sum(b1)))
+
+
+def neighbour_diffs(f: np.ndarray):
+    """Differences f_j - f_k over the 4 in-slice neighbours (+-x, +-z) at the same q,
+    returned per direction with zeros where the neighbour does not exist, and the
+    neighbour count |N_j| per voxel."""
+    f = np.asarray(f, dtype=np.float64)
+    nz, nx = f.shape[0], f.shape[1]
+    d = np.zeros((4,) + f.shape)
+    cnt = np.zeros((nz, nx))
+    d[0, :, 1:] = f[:, 1:] - f[:, :-1]
+    d[1, :, :-1] = f[:, :-1] - f[:, 1:]
+    d[2, 1:] = f[1:] - f[:-1]
+    d[3, :-1] = f[:-1] - f[1:]
+    cnt[:, 1:] += 1
+    cnt[:, :-1] += 1
+    cnt[1:] += 1
+    cnt[:-1] += 1
+    return d, cnt
+
+
+def penalty(f: np.ndarray) -> float:
+    """R(f) = sum_j sum_{k in N_j} w_jk psi(f_j - f_k), psi(t) = t^2/2, w = 1
+    (Sec. V eq. standard_EPR; every neighbour pair appears once from each side)."""
+    d, _ = neighbour_diffs(f)
+    return float(np.sum(0.5 * d * d))
+
+
+def poisson_ratio(y: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """y / z with 0/z = 0 (the data term's back-projected ratio, Alg. 5)."""
+    out = np.zeros_like(z)
+    nz = y > 0
+    out[nz] = y[nz] / z[nz]
+    return out
+
+
+def data_fit(y: np.ndarray, z: np.ndarray) -> float:
+    """L = sum_i (l_i + r_i) - y_i ln(l_i + r_i) + ln(y_i!) with z = l + r and 0 ln 0 = 0."""
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    if np.any((z <= 0) & (y > 0)):
+        return float("inf")
+    ylog = np.zeros_like(z)
+    nz = y > 0
+    ylog[nz] = y[nz] * np.log(z[nz])
+    return float(np.sum(z - ylog + gammaln(y + 1.0)))
+
+
+def objective_from_mean(y, z, f, beta) -> float:
+    """J(f) = L(f) + beta R(f) (Sec. V eq. overall_objective)."""
+    return data_fit(y, z) + beta * penalty(f)
+
+
+def surrogate_coefficients(fhat, b1, b2, beta):
+    """b^(3)..b^(6) and chi^(1..3) of App. B for the quadratic potential
+    (psi'(t) = t, omega = psi'(t)/t = 1) with symmetric 4-neighbourhoods and w = 1."""
+    fhat = np.asarray(fhat, dtype=np.float64)
+    d, cnt = neighbour_diffs(fhat)
+    b3 = 2.0 * cnt[:, :, None] * np.ones_like(fhat)   # 2 sum_k w omega
+    b4 = b3.copy()                                     # same set for a symmetric N
+    b5 = d.sum(axis=0)                                 # sum_k w psi'(fhat_j - fhat_k)
+    b6 = b5.copy()
+    chi1 = beta * (b3 + b4)
+    chi2 = b1 + beta * (-fhat * (b3 + b4) + b5 + b6)
+    chi3 = fhat * b2
+    return chi1, chi2, chi3
+
+
+def lemma_minimizer(a, b, c):
+    """Minimiser of (1/2) a x^2 + b x - c ln x on [0, inf] (App. C, Lemma 1).
+
+    a > 0: the positive root of a x^2 + b x - c = 0, written for b > 0 as
+    2c / (b + sqrt(b^2 + 4ac)) (multiply the Lemma's form by its conjugate; no
+    cancellation) and for b <= 0 as the Lemma's (-b + sqrt(b^2 + 4ac)) / (2a).
+    a = 0, b > 0: c / b.  a = 0, b <= 0: +inf.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    a, b, c = np.broadcast_arrays(a, b, c)
+    disc = np.sqrt(b * b + 4.0 * a * c)
+    out = np.empty(a.shape)
+    pos = b > 0
+    out[pos] = 2.0 * c[pos] / (b[pos] + disc[pos])
+    neg = ~pos
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out[neg] = np.where(a[neg] > 0, (-b[neg] + disc[neg]) / (2.0 * a[neg]), np.inf)
+    return out
+
+
+def em_update(fhat, b1, b2, beta):
+    """f^{t+1} from eq. f_update (App. B) via Lemma 1.
+
+    Lemma 1's unbounded case (chi1 = 0, chi2 <= 0) needs beta = 0 and a voxel
+    that no pixel sees (b^(1)_j = 0); such a voxel keeps its previous value."""
+    fhat = np.asarray(fhat, dtype=np.float64)
+    chi1, chi2, chi3 = surrogate_coefficients(fhat, b1, b2, beta)
+    out = lemma_minimizer(chi1, chi2, chi3)
+    stuck = (chi1 <= 0) & (chi2 <= 0)
+    return np.where(stuck, fhat, out)
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round to bfloat16 (round to nearest, ties to even) via float32, returned as
+    float64: the table values the reduced-precision form is defined on."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = ((u + 0x7FFF + lsb) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
