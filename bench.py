@@ -1,0 +1,161 @@
+"""Throughput benchmark of the reconstruction hot path on one MI355X.
+
+A step is one iteration of the EM-type algorithm (Alg. 5) on the 128 x 128
+voxel x 64 q slice with a 128 x 128 detector: forward projection, Poisson
+ratio and float64 data-fit terms, back projection, separable-surrogate update
+and the float64 objective, all in the HIP library.  The metric counts the
+nominal voxel*pixel*q evaluations of one forward plus one adjoint
+(2 * 16384 * 16384 * 64 = 3.436e10) per step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.  The roofline entry uses the work model of the direct
+evaluation (4 VALU lane-ops per open in-band triple, 60 per open pair, 10 per
+pair), the event-timed average duration of the dominant operator inside the
+timed region, and the non-packed FP32 VALU issue rate of the chip.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "slice128"
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: 3.93e13 lane-ops/s
+OPS_PER_TRIPLE, OPS_PER_OPEN_PAIR, OPS_PER_PAIR = 4.0, 60.0, 10.0
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+SRC = os.path.join(ROOT, "paper_1603_06400_amd", "csrc", "csx.hip")
+
+
+def source_hash() -> str:
+    with open(SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def algorithmic_ops(census: dict) -> float:
+    return (OPS_PER_TRIPLE * census["open_triples_in_band"] + OPS_PER_OPEN_PAIR * census["open_pairs"]
+            + OPS_PER_PAIR * census["pairs"])
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_slice128.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(g, f, y, n_pix=4096, n_vox=4096):
+    """The FP64 oracle on a bounded sample of the same workload: forward at
+    n_pix sampled pixels and adjoint at n_vox sampled voxels."""
+    import oracle
+    o = oracle.Oracle(g)
+    rng = np.random.Generator(np.random.PCG64(5))
+    pix = rng.choice(g.npix, n_pix, replace=False)
+    vox = rng.choice(g.nvox, n_vox, replace=False)
+    t0 = time.perf_counter()
+    o.forward_pixels(f, pix)
+    t1 = time.perf_counter()
+    o.adjoint_voxels(y, vox)
+    t2 = time.perf_counter()
+    evals = (n_pix + n_vox) * g.nvox * g.nq   # each sampled output sums over the other side
+    return {"value": evals / (t2 - t0), "unit": "evals/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle: forward at {n_pix} random pixels + adjoint at {n_vox} random "
+                      f"voxels of the {WORKLOAD} workload ({evals:.3e} evals, "
+                      f"{t1 - t0:.1f} s + {t2 - t1:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(independent scans shard across GPUs without communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1603_06400_amd import csx, inputs
+
+    w = inputs.workload(WORKLOAD)
+    z = np.load(os.path.join(GOLDEN, f"{WORKLOAD}_counts.npz"))
+    g = w.geom.with_(C=float(z["C"]))
+    y = z["y"].astype(np.float64)
+    with open(os.path.join(GOLDEN, f"{WORKLOAD}_census.json")) as fh:
+        census = json.load(fh)
+    torch.cuda.set_device(0)
+    geo = csx.Geometry(g)
+    y_d = torch.tensor(y, dtype=torch.float32, device="cuda")
+    f_d = geo.new_image()
+    J = torch.zeros(max(1, args.steps), dtype=torch.float64, device="cuda")
+
+    # f^0 and the sensitivity image (uniform start, zero iterations)
+    geo.recon(y_d, f_d, 0, w.beta, init_uniform=True)
+    for _ in range(args.warmup):
+        geo.recon_step(y_d, f_d, w.beta, J=J[:1])
+    torch.cuda.synchronize()
+
+    geo.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        geo.recon_step(y_d, f_d, w.beta, J=J[k:k + 1])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = geo.timing_read()
+    geo.timing_enable(False)
+
+    ms_step = (t1 - t0) * 1e3 / max(1, args.steps)
+    nominal = 2.0 * g.nvox * g.npix * g.nq
+    value = nominal / (ms_step * 1e-3)
+    Jh = J.cpu().numpy()
+
+    fwd_ms = tim["forward_ms"] / max(1, tim["forward_n"])
+    adj_ms = tim["adjoint_ms"] / max(1, tim["adjoint_n"])
+    ops = algorithmic_ops(census)
+    if adj_ms >= fwd_ms:
+        dom, dom_ms, kname = "adjoint", adj_ms, "k_adjoint"
+    else:
+        dom, dom_ms, kname = "forward", fwd_ms, "k_forward"
+    achieved = ops / (dom_ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": stored_traffic(kname),
+                "ops_per_launch": ops, "forward_ms": fwd_ms, "adjoint_ms": adj_ms}
+
+    out = {
+        "metric": "fwd+adjoint voxel*pixel*energy evals/s at 128^2 x 64q (one Alg. 5 iteration per step)",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "voxels": [g.nz, g.nx], "nq": g.nq, "detector": [g.ndy, g.ndx],
+                   "ne": g.ne, "mask_open": float(g.mask.mean()), "beta": w.beta,
+                   "nominal_evals_per_step": nominal},
+        "roofline": roofline,
+        "objective_first_last": [float(Jh[0]), float(Jh[-1])] if args.steps else None,
+    }
+    if not args.no_cpu_baseline:
+        f_true = inputs.phantom(w.geom, w.phantom_seed, w.n_rect)
+        out["cpu_baseline"] = cpu_baseline(g, f_true, y)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

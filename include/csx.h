@@ -1,0 +1,160 @@
+/*
+ * csx.h -- C ABI of the MI355X (gfx950) fan-beam coded-aperture
+ * coherent-scatter reconstruction library (libcsx.so).
+ *
+ * The calls follow the paper's statement of the problem (Odinaka et al.,
+ * arXiv:1603.06400):
+ *   csx_init_geometry  -- the system description of Sec. II and App. A
+ *                         (source at the origin, fan slice of voxels, secondary
+ *                         mask plane, energy-integrating detector, spectrum),
+ *                         with the per-voxel and spectrum tables that Alg. 2's
+ *                         "Precompute" lines keep offline.
+ *   csx_forward        -- Forward_project: g = A f, eqs. 1-2 (Alg. 1 / Alg. 2).
+ *   csx_backproject    -- Back_project: b = A^T y (Alg. 3 / Alg. 4).
+ *   csx_recon_step     -- one iteration of the EM-type algorithm (Alg. 5) for
+ *                         the Poisson model y_i ~ Poisson((A f)_i + r_i) of
+ *                         Sec. V with the penalised objective J = L + beta R,
+ *                         closed-form update of App. B eq. f_update.
+ *   csx_recon          -- Alg. 5 for n_iter iterations.
+ *
+ * Frame: source focal spot at the origin, fan plane y = 0, depth along +z (the
+ * paper's axes renamed: paper x -> z, paper y -> x, paper z -> y).  Lengths in
+ * mm, energies in keV, q in the inverse of the unit of hc (nm^-1 with
+ * hc = 1.23984193 keV nm).
+ *
+ * Layouts (row-major, all device buffers are float32 unless stated):
+ *   image  f, b : [nz][nx][nq]   voxel (ix, iz) at x = x_min + (ix+1/2) dx,
+ *                                z = z_min + (iz+1/2) dz, q fastest
+ *   detector g, y, r : [ndy][ndx] pixel (a, b) at x' = (a - ndx/2 + 1/2) p,
+ *                                y' = (b - ndy/2 + 1/2) p, z' = det_z
+ *
+ * Ownership: the caller owns every data buffer; the library owns only the
+ * geometry handle, its device tables and its workspace, and never frees caller
+ * memory.  Device calls are asynchronous on the HIP stream passed as
+ * `stream` (NULL = the default stream).  Calls that share one handle use its
+ * workspace and must not run concurrently.
+ *
+ * Errors: every call returns a csx_status; no exception crosses the ABI.
+ * Argument validation happens before any HIP call.  csx_last_error() returns
+ * a thread-local message describing the last failure.
+ */
+#ifndef CSX_H
+#define CSX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CSX_OK = 0,
+    CSX_EINVAL = -1,   /* bad argument (null pointer, size, NaN, negative count) */
+    CSX_EGEOM = -2,    /* descriptor violates the geometry's requirements */
+    CSX_EHIP = -3,     /* a HIP runtime call failed (no device, launch error) */
+    CSX_ENOMEM = -4,   /* device or host allocation failed */
+    CSX_ENUMERIC = -5  /* y_i > 0 where the model mean (A f + r)_i is 0 */
+} csx_status;
+
+enum { CSX_TABLE_F32 = 0, CSX_TABLE_BF16 = 1 };
+
+/* System description (all host memory, copied by csx_init_geometry).
+ * Requirements (else CSX_EGEOM): all counts >= 1; ndy even (no pixel on the
+ * fan plane, and pixel rows pair up under the y -> -y mirror); 0 < z_min <
+ * z_max < mask_z < det_z; x_min < x_max; positive pitches, hc; e_lo < e_hi;
+ * finite non-negative phi and C; finite positive q; mask values 0 or 1. */
+typedef struct {
+    int nx, nz;                   /* voxels across / along the fan's central ray */
+    double x_min, x_max;          /* mm, cell-centred voxel grid */
+    double z_min, z_max;          /* mm */
+    int nq;                       /* momentum-transfer nodes */
+    const double *q;              /* [nq] */
+    int ndx, ndy;                 /* detector pixels along x, y; ndy even */
+    double det_pitch;             /* mm, square pixels */
+    double det_z;                 /* mm, detector plane */
+    double mask_z;                /* mm, secondary-mask plane */
+    double mask_pitch;            /* mm, square mask cells */
+    int mask_nx;                  /* mask period along x (cells) */
+    int mask_ny;                  /* mask rows, centred on y = 0; outside rows are opaque */
+    const unsigned char *mask;    /* [mask_ny][mask_nx], 0 = blocked, 1 = open */
+    int ne;                       /* spectrum histogram bins on [e_lo, e_hi) */
+    double e_lo, e_hi;            /* keV */
+    const double *phi;            /* [ne] flux per bin */
+    double C;                     /* normalisation constant C of App. A */
+    double hc;                    /* keV * (unit of 1/q) */
+    int table_dtype;              /* CSX_TABLE_F32, or CSX_TABLE_BF16: spectrum table
+                                     rounded to bfloat16 (round-to-nearest-even) and
+                                     mask stored as bits; accumulation stays float32 */
+} csx_geometry_desc;
+
+typedef struct csx_geometry csx_geometry;
+
+/* Sizes and kernel facts of a handle. */
+typedef struct {
+    int nvox, npix, nq;
+    int symmetric_lr;             /* 1 when the x -> -x mirror is exploited */
+    int table_dtype;
+    int64_t workspace_bytes;      /* device memory the handle holds */
+} csx_info;
+
+/* Checks a descriptor without touching the GPU.  Returns CSX_OK, CSX_EINVAL or
+ * CSX_EGEOM. */
+csx_status csx_validate_desc(const csx_geometry_desc *desc);
+
+/* Builds the device tables and workspace for one system on the current HIP
+ * device.  *out receives a handle owned by the caller (free with
+ * csx_free_geometry).  Synchronous. */
+csx_status csx_init_geometry(const csx_geometry_desc *desc, csx_geometry **out);
+
+/* Releases the handle and its device memory (NULL is a no-op). */
+void csx_free_geometry(csx_geometry *h);
+
+csx_status csx_get_info(const csx_geometry *h, csx_info *out);
+
+/* Forward_project (Sec. II eqs. 1-2): g_i = sum_j sum_m H(i, j, q_m) f_jm with
+ * H = C Gso God T dtheta S(theta, q).  f: device [nz][nx][nq]; g: device
+ * [ndy][ndx], overwritten.  Asynchronous on `stream`. */
+csx_status csx_forward(csx_geometry *h, const float *f, float *g, void *stream);
+
+/* Back_project (Alg. 3): b_jm = sum_i H(i, j, q_m) y_i.  y: device [ndy][ndx];
+ * b: device [nz][nx][nq], overwritten.  Asynchronous on `stream`. */
+csx_status csx_backproject(csx_geometry *h, const float *y, float *b, void *stream);
+
+/* One iteration of Alg. 5 from f^t (in f) to f^{t+1} (written back to f):
+ *   z = A f^t + r,  b2 = A^T (y / z)  (0 where y_i = 0),
+ *   f^{t+1}_j = minimiser of the separable surrogate (App. B eq. f_update,
+ *   Lemma 1), quadratic potential psi(t) = t^2/2, 4 in-slice neighbours
+ *   (+-x, +-z) at the same q, unit weights.
+ * y: device [ndy][ndx] counts (>= 0); r: device [ndy][ndx] background or NULL
+ * (= 0); f: device image, in/out; beta >= 0.  J_out: NULL, or a device double
+ * that receives J(f^t) = L(f^t) + beta R(f^t) in float64 (+inf when some
+ * y_i > 0 has zero model mean).  The first call on a handle also computes the
+ * sensitivity image b1 = A^T 1 and keeps it.  Asynchronous on `stream`. */
+csx_status csx_recon_step(csx_geometry *h, const float *y, const float *r, float *f,
+                          double beta, double *J_out, void *stream);
+
+/* Alg. 5 for n_iter >= 0 iterations.  init_uniform != 0 first sets
+ * f^0 = sum(y) / sum(A^T 1) everywhere (f is then output only).
+ * J_hist: NULL or host double[n_iter + 1] receiving J(f^0) .. J(f^n_iter).
+ * Synchronises `stream` before returning.  Returns CSX_ENUMERIC if some
+ * y_i > 0 met a zero model mean. */
+csx_status csx_recon(csx_geometry *h, const float *y, const float *r, float *f,
+                     int init_uniform, int n_iter, double beta, double *J_hist, void *stream);
+
+/* Kernel timing (for measurement): while enabled, every forward and adjoint
+ * operator launch on this handle is bracketed by HIP events recorded on the
+ * caller's stream.  csx_timing_read synchronises those events and returns the
+ * summed durations (ms) and launch counts since the last enable, per operator:
+ * ms[0], n[0] = forward kernels (including the split reduction), ms[1], n[1] =
+ * adjoint kernels.  Off by default; enabling resets the counters. */
+csx_status csx_timing_enable(csx_geometry *h, int on);
+csx_status csx_timing_read(csx_geometry *h, double ms[2], int n[2]);
+
+/* Thread-local description of the last error ("" if none). */
+const char *csx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSX_H */

@@ -1,0 +1,217 @@
+"""Python binding of libcsx.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module checks tensor shapes,
+dtypes and devices, passes ``data_ptr()`` and the current HIP stream, and turns
+status codes into exceptions.  PyTorch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+from .build import LIB
+
+CSX_OK, CSX_EINVAL, CSX_EGEOM, CSX_EHIP, CSX_ENOMEM, CSX_ENUMERIC = 0, -1, -2, -3, -4, -5
+TABLE_F32, TABLE_BF16 = 0, 1
+_NAMES = {CSX_EINVAL: "EINVAL", CSX_EGEOM: "EGEOM", CSX_EHIP: "EHIP", CSX_ENOMEM: "ENOMEM",
+          CSX_ENUMERIC: "ENUMERIC"}
+
+
+class CsxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"csx {_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("nz", ctypes.c_int),
+        ("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
+        ("z_min", ctypes.c_double), ("z_max", ctypes.c_double),
+        ("nq", ctypes.c_int), ("q", ctypes.POINTER(ctypes.c_double)),
+        ("ndx", ctypes.c_int), ("ndy", ctypes.c_int),
+        ("det_pitch", ctypes.c_double), ("det_z", ctypes.c_double),
+        ("mask_z", ctypes.c_double), ("mask_pitch", ctypes.c_double),
+        ("mask_nx", ctypes.c_int), ("mask_ny", ctypes.c_int),
+        ("mask", ctypes.POINTER(ctypes.c_ubyte)),
+        ("ne", ctypes.c_int), ("e_lo", ctypes.c_double), ("e_hi", ctypes.c_double),
+        ("phi", ctypes.POINTER(ctypes.c_double)),
+        ("C", ctypes.c_double), ("hc", ctypes.c_double),
+        ("table_dtype", ctypes.c_int),
+    ]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("nvox", ctypes.c_int), ("npix", ctypes.c_int), ("nq", ctypes.c_int),
+                ("symmetric_lr", ctypes.c_int), ("table_dtype", ctypes.c_int),
+                ("workspace_bytes", ctypes.c_int64)]
+
+
+EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_get_info",
+           "csx_forward", "csx_backproject", "csx_recon_step", "csx_recon",
+           "csx_timing_enable", "csx_timing_read", "csx_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libcsx.so; raises if the library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(f"{LIB} is missing: run paper_1603_06400_amd.build.build() first")
+        L = ctypes.CDLL(LIB)
+        vp = ctypes.c_void_p
+        dp = ctypes.POINTER(_Desc)
+        L.csx_validate_desc.argtypes = [dp]
+        L.csx_validate_desc.restype = ctypes.c_int
+        L.csx_init_geometry.argtypes = [dp, ctypes.POINTER(vp)]
+        L.csx_init_geometry.restype = ctypes.c_int
+        L.csx_free_geometry.argtypes = [vp]
+        L.csx_free_geometry.restype = None
+        L.csx_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.csx_get_info.restype = ctypes.c_int
+        L.csx_forward.argtypes = [vp, vp, vp, vp]
+        L.csx_forward.restype = ctypes.c_int
+        L.csx_backproject.argtypes = [vp, vp, vp, vp]
+        L.csx_backproject.restype = ctypes.c_int
+        L.csx_recon_step.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
+        L.csx_recon_step.restype = ctypes.c_int
+        L.csx_recon.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double), vp]
+        L.csx_recon.restype = ctypes.c_int
+        L.csx_timing_enable.argtypes = [vp, ctypes.c_int]
+        L.csx_timing_enable.restype = ctypes.c_int
+        L.csx_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+        L.csx_timing_read.restype = ctypes.c_int
+        L.csx_last_error.argtypes = []
+        L.csx_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != CSX_OK:
+        raise CsxError(code, lib().csx_last_error().decode())
+
+
+def make_desc(geom, table_dtype: int = TABLE_F32):
+    """ctypes descriptor for an ``inputs.ScanGeometry``; returns (desc, keepalive)."""
+    q = np.ascontiguousarray(geom.q, dtype=np.float64)
+    phi = np.ascontiguousarray(geom.phi, dtype=np.float64)
+    mask = np.ascontiguousarray(geom.mask, dtype=np.uint8)
+    d = _Desc()
+    d.nx, d.nz = geom.nx, geom.nz
+    d.x_min, d.x_max, d.z_min, d.z_max = geom.x_min, geom.x_max, geom.z_min, geom.z_max
+    d.nq, d.q = q.shape[0], q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.ndx, d.ndy, d.det_pitch, d.det_z = geom.ndx, geom.ndy, geom.det_pitch, geom.det_z
+    d.mask_z, d.mask_pitch = geom.mask_z, geom.mask_pitch
+    d.mask_ny, d.mask_nx = mask.shape
+    d.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
+    d.ne, d.e_lo, d.e_hi = phi.shape[0], geom.e_lo, geom.e_hi
+    d.phi = phi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.C, d.hc, d.table_dtype = geom.C, geom.hc, table_dtype
+    return d, (q, phi, mask)
+
+
+def validate(geom, table_dtype: int = TABLE_F32) -> None:
+    d, keep = make_desc(geom, table_dtype)
+    _check(lib().csx_validate_desc(ctypes.byref(d)))
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, numel: int, name: str) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous float32")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Geometry:
+    """A scan geometry resident on the current GPU (wraps a csx_geometry handle)."""
+
+    def __init__(self, geom, table_dtype: int = TABLE_F32):
+        self.geom = geom
+        self.table_dtype = table_dtype
+        self.nvox, self.npix, self.nq = geom.nx * geom.nz, geom.ndx * geom.ndy, int(len(geom.q))
+        self.image_shape = (geom.nz, geom.nx, self.nq)
+        self.detector_shape = (geom.ndy, geom.ndx)
+        d, keep = make_desc(geom, table_dtype)
+        h = ctypes.c_void_p()
+        _check(lib().csx_init_geometry(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().csx_free_geometry(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        out = _Info()
+        _check(lib().csx_get_info(self._h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in _Info._fields_}
+
+    def timing_enable(self, on: bool = True) -> None:
+        _check(lib().csx_timing_enable(self._h, int(bool(on))))
+
+    def timing_read(self) -> dict:
+        """Summed event times (ms) and launch counts of forward / adjoint kernels."""
+        ms = (ctypes.c_double * 2)()
+        n = (ctypes.c_int * 2)()
+        _check(lib().csx_timing_read(self._h, ms, n))
+        return {"forward_ms": ms[0], "forward_n": n[0], "adjoint_ms": ms[1], "adjoint_n": n[1]}
+
+    def new_image(self) -> torch.Tensor:
+        return torch.empty(self.image_shape, dtype=torch.float32, device="cuda")
+
+    def new_detector(self) -> torch.Tensor:
+        return torch.empty(self.detector_shape, dtype=torch.float32, device="cuda")
+
+    def forward(self, f: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.new_detector() if out is None else out
+        _check(lib().csx_forward(self._h, _dev(f, self.nvox * self.nq, "f"),
+                                 _dev(out, self.npix, "g"), _stream()))
+        return out
+
+    def backproject(self, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.new_image() if out is None else out
+        _check(lib().csx_backproject(self._h, _dev(y, self.npix, "y"),
+                                     _dev(out, self.nvox * self.nq, "b"), _stream()))
+        return out
+
+    def recon_step(self, y: torch.Tensor, f: torch.Tensor, beta: float,
+                   r: Optional[torch.Tensor] = None, J: Optional[torch.Tensor] = None) -> None:
+        """In-place Alg. 5 iteration on f; J (device float64 scalar) receives J(f^t)."""
+        rp = ctypes.c_void_p(None) if r is None else _dev(r, self.npix, "r")
+        if J is not None and (J.dtype != torch.float64 or J.device.type != "cuda" or J.numel() < 1):
+            raise ValueError("J must be a CUDA float64 tensor")
+        jp = ctypes.c_void_p(None) if J is None else ctypes.c_void_p(J.data_ptr())
+        _check(lib().csx_recon_step(self._h, _dev(y, self.npix, "y"), rp,
+                                    _dev(f, self.nvox * self.nq, "f"), float(beta), jp, _stream()))
+
+    def recon(self, y: torch.Tensor, f: torch.Tensor, n_iter: int, beta: float,
+              r: Optional[torch.Tensor] = None, init_uniform: bool = True) -> np.ndarray:
+        """Alg. 5 for n_iter iterations in place on f; returns J(f^0..f^n) (float64)."""
+        rp = ctypes.c_void_p(None) if r is None else _dev(r, self.npix, "r")
+        hist = np.zeros(n_iter + 1, dtype=np.float64)
+        _check(lib().csx_recon(self._h, _dev(y, self.npix, "y"), rp,
+                               _dev(f, self.nvox * self.nq, "f"), int(bool(init_uniform)),
+                               int(n_iter), float(beta),
+                               hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+        return hist

@@ -1,0 +1,57 @@
+"""Shared helpers of the GPU parity tests (inputs from the seeded generators,
+expected values from the oracle)."""
+import os
+
+import numpy as np
+
+from paper_1603_06400_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def workload_data(name):
+    """(workload, geometry with the stored C, f_true, counts y) of a workload."""
+    w = inputs.workload(name)
+    z = np.load(os.path.join(GOLDEN, f"{name}_counts.npz"))
+    g = w.geom.with_(C=float(z["C"]))
+    f = inputs.phantom(w.geom, w.phantom_seed, w.n_rect)
+    return w, g, f, z["y"].astype(np.float64)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
+
+
+def assert_parity(got, ref, tol=1e-5, elem_tol=1e-4, what=""):
+    """rel-L2 within tol, and every element within elem_tol of the largest
+    reference magnitude (catches a wrong tile or a ragged-tail slip)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape, (what, got.shape, ref.shape)
+    assert np.all(np.isfinite(got)), what
+    e = rel_l2(got, ref)
+    assert e <= tol, f"{what}: rel-L2 {e:.3e} > {tol:.1e}"
+    scale = float(np.max(np.abs(ref))) if ref.size else 0.0
+    if scale > 0:
+        worst = float(np.max(np.abs(got - ref)))
+        assert worst <= elem_tol * scale, f"{what}: max abs err {worst:.3e} > {elem_tol:.0e} * {scale:.3e}"
+    else:
+        assert np.all(got == 0), what
+    return e
+
+
+def ragged_geometry(seed, nx, nz, ndx, ndy, nq, ne=None, x=(-37.0, 41.0), open_frac=0.5,
+                    mask_nx=16, mask_ny=None, det_pitch=1.0):
+    """Off-centre, non-power-of-two geometry of the synthetic family."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ne = nq if ne is None else ne
+    mask_ny = ndy if mask_ny is None else mask_ny
+    m = (rng.uniform(size=(mask_ny, mask_nx)) < open_frac).astype(np.uint8)
+    return inputs.ScanGeometry(
+        nx=nx, nz=nz, x_min=x[0], x_max=x[1], z_min=400.0, z_max=600.0,
+        q=inputs.q_bin_centres(nq), ndx=ndx, ndy=ndy, det_pitch=det_pitch, det_z=800.0,
+        mask_z=700.0, mask_pitch=1.0, mask=m, e_lo=20.0, e_hi=160.0,
+        phi=inputs.kramers_histogram(ne), C=1e7)

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerance: rel-L2 <= 1e-5 for g, b and one reconstruction step (FP32 kernels
+vs FP64 oracle), plus an element-wise cap of 1e-4 of the largest reference
+magnitude.  Sizes span several tiles of every kernel and ragged tails; the
+full 128^2 x 64q slice is checked on sampled outputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1603_06400_amd import csx, inputs
+
+from .gpu_helpers import assert_parity, ragged_geometry, rel_l2, workload_data
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+RAGGED = [
+    # (seed, nx, nz, ndx, ndy, nq)
+    (1, 10, 7, 12, 10, 24),     # one partial q chunk, ragged pixel-pair and voxel tails
+    (2, 9, 5, 9, 6, 64),        # odd nx and ndx, exactly one q chunk
+    (3, 12, 11, 14, 18, 80),    # two q chunks
+    (4, 33, 3, 7, 2, 40),       # a single detector row pair
+    (5, 3, 70, 31, 22, 17),     # tall slice, ragged everything
+]
+
+
+@pytest.mark.parametrize("case", RAGGED, ids=[f"r{c[0]}" for c in RAGGED])
+def test_forward_adjoint_ragged(oracle_mod, case):
+    seed, nx, nz, ndx, ndy, nq = case
+    print(f"[ragged {case}]", flush=True)
+    g = ragged_geometry(seed, nx, nz, ndx, ndy, nq)
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    f = inputs.random_image(g, 100 + seed)
+    y = inputs.random_detector(g, 200 + seed)
+    assert_parity(host(geo.forward(dev(f))), o.forward(f), what="forward")
+    assert_parity(host(geo.backproject(dev(y))), o.adjoint(y), what="adjoint")
+
+
+@pytest.mark.parametrize("name", ["slice32"])
+def test_workload_operators(oracle_mod, name):
+    w, g, f, y = workload_data(name)
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    e1 = assert_parity(host(geo.forward(dev(f))), o.forward(f), what="forward phantom")
+    e2 = assert_parity(host(geo.backproject(dev(y))), o.adjoint(y), what="adjoint counts")
+    fr = inputs.random_image(g, 5)
+    e3 = assert_parity(host(geo.forward(dev(fr))), o.forward(fr), what="forward random")
+    print(f"{name}: fwd {e1:.2e} adj {e2:.2e} fwd-rand {e3:.2e}")
+
+
+def test_slice128_sampled_outputs(oracle_mod):
+    """Full-size slice in the launch configuration the benchmark times:
+    256 sampled pixels of g and 48 sampled voxels (all q) of A^T y."""
+    w, g, f, y = workload_data("slice128")
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    rng = np.random.Generator(np.random.PCG64(77))
+    pix = np.sort(rng.choice(g.npix, 256, replace=False))
+    vox = np.sort(rng.choice(g.nvox, 48, replace=False))
+    gg = host(geo.forward(dev(f))).ravel()
+    assert_parity(gg[pix], o.forward_pixels(f, pix), what="forward sampled")
+    bb = host(geo.backproject(dev(y))).reshape(g.nvox, g.nq)
+    assert_parity(bb[vox], o.adjoint_voxels(y, vox), what="adjoint sampled")
+    # properties at full size: finite, non-negative, adjoint identity
+    assert np.all(gg >= 0) and np.all(bb >= 0)
+    fr = inputs.random_image(g, 9)
+    yr = inputs.random_detector(g, 10)
+    lhs = float(np.sum(host(geo.forward(dev(fr))) * yr))
+    rhs = float(np.sum(fr * host(geo.backproject(dev(yr)))))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_adjoint_identity_fp32(oracle_mod):
+    w, g, f, y = workload_data("slice32")
+    geo = csx.Geometry(g)
+    fr = inputs.random_image(g, 1)
+    yr = inputs.random_detector(g, 2)
+    lhs = float(np.sum(host(geo.forward(dev(fr))) * yr))
+    rhs = float(np.sum(fr * host(geo.backproject(dev(yr)))))
+    assert abs(lhs - rhs) <= 2e-6 * abs(lhs)
+
+
+def test_deterministic_repeat():
+    w, g, f, y = workload_data("slice32")
+    geo = csx.Geometry(g)
+    fd, yd = dev(f), dev(y)
+    a1, a2 = host(geo.forward(fd)), host(geo.forward(fd))
+    b1, b2 = host(geo.backproject(yd)), host(geo.backproject(yd))
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
+@pytest.mark.parametrize("beta", [1e-3, 0.0])
+def test_recon_step_parity(oracle_mod, beta):
+    w, g, f, y = workload_data("slice32")
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    f0 = oracle_mod.uniform_start(y, o.sensitivity())
+    fd = dev(f0)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    geo.recon_step(dev(y), fd, beta, J=J)
+    ref_f, ref_J = o.recon_step(y, None, f0, beta)
+    assert_parity(host(fd), ref_f, what="recon_step f")
+    assert abs(J.item() - ref_J) <= 1e-7 * abs(ref_J)
+
+
+def test_recon_matches_oracle_iterations(oracle_mod):
+    w, g, f, y = workload_data("slice32")
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    fd = torch.empty((g.nz, g.nx, g.nq), dtype=torch.float32, device="cuda")
+    Jg = geo.recon(dev(y), fd, w.n_iter, w.beta, init_uniform=True)
+    f0 = oracle_mod.uniform_start(y, o.sensitivity())
+    ref_f, ref_J = o.recon(y, None, f0, w.n_iter, w.beta)
+    e = rel_l2(host(fd), ref_f)
+    assert e <= 1e-4, e
+    np.testing.assert_allclose(Jg, ref_J, rtol=1e-7)
+    assert np.all(np.diff(Jg) <= 1e-7 * np.abs(Jg[1:]))
+
+
+def test_recon_resume_equals_continuous():
+    w, g, f, y = workload_data("slice32")
+    geo = csx.Geometry(g)
+    yd = dev(y)
+    fa = torch.empty((g.nz, g.nx, g.nq), dtype=torch.float32, device="cuda")
+    Ja = geo.recon(yd, fa, 6, w.beta)
+    fb = torch.empty_like(fa)
+    Jb1 = geo.recon(yd, fb, 3, w.beta)
+    Jb2 = geo.recon(yd, fb, 3, w.beta, init_uniform=False)
+    assert torch.equal(fa, fb)
+    np.testing.assert_array_equal(Ja[:4], Jb1)
+    np.testing.assert_array_equal(Ja[3:], Jb2)
+
+
+def test_zero_mean_with_counts_is_an_error():
+    g = ragged_geometry(7, 6, 6, 8, 8, 16)
+    g = g.with_(mask=np.zeros_like(g.mask))        # every pair blocked: A f = 0
+    geo = csx.Geometry(g)
+    fd = torch.ones((g.nz, g.nx, g.nq), dtype=torch.float32, device="cuda")
+    y = torch.zeros(g.ndy, g.ndx, dtype=torch.float32, device="cuda")
+    assert np.all(host(geo.forward(fd)) == 0)
+    y[0, 0] = 3.0
+    with pytest.raises(csx.CsxError) as ei:
+        geo.recon(y, fd, 1, 1e-3, init_uniform=False)
+    assert ei.value.code == csx.CSX_ENUMERIC
+    y[0, 0] = -1.0
+    with pytest.raises(csx.CsxError) as ei:
+        geo.recon(y, fd, 1, 1e-3, init_uniform=False)
+    assert ei.value.code == csx.CSX_EINVAL
+
+
+def test_binding_rejects_wrong_buffers():
+    w, g, f, y = workload_data("slice32")
+    geo = csx.Geometry(g)
+    with pytest.raises(ValueError):
+        geo.forward(torch.zeros(10, device="cuda"))
+    with pytest.raises(ValueError):
+        geo.forward(torch.zeros(g.nz, g.nx, g.nq, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        geo.forward(torch.zeros(g.nz, g.nx, g.nq))
+
+
+@pytest.mark.parametrize("name", ["slice128_open1", "slice128_open01"])
+def test_sparse_masks_sampled(oracle_mod, name):
+    w, g, f, y = workload_data(name)
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    rng = np.random.Generator(np.random.PCG64(78))
+    pix = np.sort(rng.choice(g.npix, 128, replace=False))
+    vox = np.sort(rng.choice(g.nvox, 24, replace=False))
+    gg = host(geo.forward(dev(f))).ravel()
+    ref = o.forward_pixels(f, pix)
+    if np.any(ref > 0):
+        assert_parity(gg[pix], ref, what="forward sampled")
+    else:
+        assert np.all(gg[pix] == 0)
+    yr = inputs.random_detector(g, 3)
+    bb = host(geo.backproject(dev(yr))).reshape(g.nvox, g.nq)
+    assert_parity(bb[vox], o.adjoint_voxels(yr, vox), what="adjoint sampled")
