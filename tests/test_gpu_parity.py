@@ -11,7 +11,7 @@ import torch
 
 from paper_1603_06400_amd import csx, inputs
 
-from .gpu_helpers import assert_parity, ragged_geometry, rel_l2, workload_data
+from .gpu_helpers import assert_parity, objective_tolerance, ragged_geometry, rel_l2, workload_data
 
 pytestmark = pytest.mark.gpu
 
@@ -26,21 +26,23 @@ def host(t):
 
 
 RAGGED = [
-    # (seed, nx, nz, ndx, ndy, nq)
-    (1, 10, 7, 12, 10, 24),     # one partial q chunk, ragged pixel-pair and voxel tails
-    (2, 9, 5, 9, 6, 64),        # odd nx and ndx, exactly one q chunk
-    (3, 12, 11, 14, 18, 80),    # two q chunks
-    (4, 33, 3, 7, 2, 40),       # a single detector row pair
-    (5, 3, 70, 31, 22, 17),     # tall slice, ragged everything
+    # (seed, nx, nz, ndx, ndy, nq, z_min): z_min chosen so every mask crossing
+    # sits >= 2e-4 mm from a cell edge
+    (1, 10, 7, 12, 10, 24, 402.57),     # one partial q chunk, ragged pixel-pair and voxel tails
+    (2, 9, 5, 9, 6, 64, 404.77),        # odd nx and ndx, exactly one q chunk
+    (3, 12, 11, 14, 18, 80, 402.57),    # two q chunks
+    (4, 33, 3, 7, 2, 40, 402.57),       # a single detector row pair
+    (5, 3, 70, 31, 22, 17, 401.9),      # tall slice, ragged everything
 ]
 
 
 @pytest.mark.parametrize("case", RAGGED, ids=[f"r{c[0]}" for c in RAGGED])
 def test_forward_adjoint_ragged(oracle_mod, case):
-    seed, nx, nz, ndx, ndy, nq = case
     print(f"[ragged {case}]", flush=True)
-    g = ragged_geometry(seed, nx, nz, ndx, ndy, nq)
+    g = ragged_geometry(*case)
+    seed = case[0]
     o = oracle_mod.Oracle(g)
+    assert o.margins()["mask_edge_mm"] > 1e-4   # no float32/float64 tie at a mask-cell edge
     geo = csx.Geometry(g)
     f = inputs.random_image(g, 100 + seed)
     y = inputs.random_detector(g, 200 + seed)
@@ -112,7 +114,15 @@ def test_recon_step_parity(oracle_mod, beta):
     geo.recon_step(dev(y), fd, beta, J=J)
     ref_f, ref_J = o.recon_step(y, None, f0, beta)
     assert_parity(host(fd), ref_f, what="recon_step f")
-    assert abs(J.item() - ref_J) <= 1e-7 * abs(ref_J)
+    z = o.forward(f0)
+    assert abs(J.item() - ref_J) <= objective_tolerance(y, z, 1e-5) + 1e-12 * abs(ref_J)
+    # sharper: the float64 objective arithmetic is exact up to the float32 z it
+    # is given -- J_gpu - J_oracle equals the first-order effect of the
+    # measured z difference, sum (1 - y/z) dz
+    zg = host(geo.forward(dev(f0)))
+    dz = zg - z
+    pred = float(np.sum(np.where(z > 0, 1.0 - y / np.where(z > 0, z, 1.0), 0.0) * dz))
+    assert abs((J.item() - ref_J) - pred) <= 1e-3 * abs(J.item() - ref_J) + 1e-9 * abs(ref_J)
 
 
 def test_recon_matches_oracle_iterations(oracle_mod):
@@ -125,7 +135,9 @@ def test_recon_matches_oracle_iterations(oracle_mod):
     ref_f, ref_J = o.recon(y, None, f0, w.n_iter, w.beta)
     e = rel_l2(host(fd), ref_f)
     assert e <= 1e-4, e
-    np.testing.assert_allclose(Jg, ref_J, rtol=1e-7)
+    # iterates may drift apart to 1e-4 over the run: bound J with that level
+    z = o.forward(ref_f)
+    assert np.max(np.abs(Jg - ref_J)) <= objective_tolerance(y, z, 1e-4) + 1e-12 * abs(ref_J[0])
     assert np.all(np.diff(Jg) <= 1e-7 * np.abs(Jg[1:]))
 
 
@@ -144,7 +156,7 @@ def test_recon_resume_equals_continuous():
 
 
 def test_zero_mean_with_counts_is_an_error():
-    g = ragged_geometry(7, 6, 6, 8, 8, 16)
+    g = ragged_geometry(7, 6, 6, 8, 8, 16, 402.11)
     g = g.with_(mask=np.zeros_like(g.mask))        # every pair blocked: A f = 0
     geo = csx.Geometry(g)
     fd = torch.ones((g.nz, g.nx, g.nq), dtype=torch.float32, device="cuda")
