@@ -30,7 +30,7 @@ WORKLOAD = "slice128"
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: 3.93e13 lane-ops/s
 OPS_PER_TRIPLE, OPS_PER_OPEN_PAIR, OPS_PER_PAIR = 4.0, 60.0, 10.0
 GOLDEN = os.path.join(ROOT, "tests", "golden")
-SRC = os.path.join(ROOT, "paper_1603_06400_amd", "csrc", "csx.hip")
+SRC = os.path.join(ROOT, "paper_1603_06400_amd", "csrc", "csx_ops.hip")
 
 
 def source_hash() -> str:

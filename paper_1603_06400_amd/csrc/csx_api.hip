@@ -1,0 +1,374 @@
+// csx_api.hip -- C ABI of libcsx: descriptor validation, device tables,
+// operator calls and the EM-type reconstruction loop (Alg. 5).
+#include "csx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+static thread_local std::string g_last_error;
+
+csx_status csx_fail(csx_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+extern "C" const char *csx_last_error(void) { return g_last_error.c_str(); }
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+extern "C" csx_status csx_validate_desc(const csx_geometry_desc *d)
+{
+    if (!d) return csx_fail(CSX_EINVAL, "descriptor is NULL");
+    if (d->nx < 1 || d->nz < 1 || d->nq < 1 || d->ndx < 1 || d->ndy < 1 || d->ne < 1 ||
+        d->mask_nx < 1 || d->mask_ny < 1)
+        return csx_fail(CSX_EGEOM, "all counts must be >= 1");
+    if (!d->q || !d->phi || !d->mask) return csx_fail(CSX_EINVAL, "q, phi and mask must be non-NULL");
+    if (d->ndy % 2 != 0) return csx_fail(CSX_EGEOM, "ndy must be even");
+    if (!(std::isfinite(d->x_min) && std::isfinite(d->x_max) && d->x_min < d->x_max))
+        return csx_fail(CSX_EGEOM, "need x_min < x_max");
+    if (!(finite_pos(d->z_min) && d->z_min < d->z_max && d->z_max < d->mask_z &&
+          d->mask_z < d->det_z && std::isfinite(d->det_z)))
+        return csx_fail(CSX_EGEOM, "need 0 < z_min < z_max < mask_z < det_z");
+    if (!finite_pos(d->det_pitch) || !finite_pos(d->mask_pitch) || !finite_pos(d->hc))
+        return csx_fail(CSX_EGEOM, "pitches and hc must be positive");
+    if (!(std::isfinite(d->e_lo) && std::isfinite(d->e_hi) && d->e_lo < d->e_hi))
+        return csx_fail(CSX_EGEOM, "need e_lo < e_hi");
+    if (!(std::isfinite(d->C) && d->C >= 0.0)) return csx_fail(CSX_EGEOM, "C must be finite and >= 0");
+    if (d->ne > CSX_MAX_NE) return csx_fail(CSX_EGEOM, "ne exceeds the LDS spectrum table (2048)");
+    if (d->table_dtype != CSX_TABLE_F32 && d->table_dtype != CSX_TABLE_BF16)
+        return csx_fail(CSX_EINVAL, "unknown table_dtype");
+    if (d->mask_nx > CSX_MAX_MASK_PERIOD || d->mask_ny > CSX_MAX_MASK_ROWS)
+        return csx_fail(CSX_EGEOM, "mask must have <= 32 columns and <= 4096 rows");
+    const long nvox = (long)d->nx * d->nz, npix = (long)d->ndx * d->ndy;
+    if (nvox * d->nq > (1L << 30) || npix > (1L << 28)) return csx_fail(CSX_EGEOM, "problem too large");
+    if (d->ndx > (1 << 20) || d->ndy > (1 << 20)) return csx_fail(CSX_EGEOM, "detector too large");
+    double qmin = INFINITY, qmax = 0.0;
+    for (int m = 0; m < d->nq; ++m) {
+        if (!finite_pos(d->q[m])) return csx_fail(CSX_EGEOM, "q nodes must be finite and > 0");
+        qmin = std::min(qmin, d->q[m]);
+        qmax = std::max(qmax, d->q[m]);
+    }
+    // bounds the spectrum-bin coordinate of any in-band pair (int range)
+    if (qmax / qmin * d->ne > 1e8) return csx_fail(CSX_EGEOM, "q range times ne too large");
+    for (int k = 0; k < d->ne; ++k)
+        if (!(std::isfinite(d->phi[k]) && d->phi[k] >= 0.0))
+            return csx_fail(CSX_EGEOM, "spectrum must be finite and >= 0");
+    for (long k = 0; k < (long)d->mask_nx * d->mask_ny; ++k)
+        if (d->mask[k] > 1) return csx_fail(CSX_EGEOM, "mask values must be 0 or 1");
+    return CSX_OK;
+}
+
+// float32 -> bfloat16 bits, round to nearest, ties to even
+static uint16_t bf16_rne(float v)
+{
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+template <typename T>
+static csx_status dev_upload(T **dst, const std::vector<T> &src, int64_t &bytes)
+{
+    HIP_TRY(hipMalloc((void **)dst, src.size() * sizeof(T)));
+    HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    bytes += (int64_t)(src.size() * sizeof(T));
+    return CSX_OK;
+}
+
+template <typename T>
+static csx_status dev_alloc(T **dst, size_t n, int64_t &bytes)
+{
+    HIP_TRY(hipMalloc((void **)dst, n * sizeof(T)));
+    bytes += (int64_t)(n * sizeof(T));
+    return CSX_OK;
+}
+
+static void release_events(csx_geometry *h)
+{
+    for (int op = 0; op < 2; ++op) {
+        for (hipEvent_t e : h->ev[op]) (void)hipEventDestroy(e);
+        h->ev[op].clear();
+        h->ev_used[op] = 0;
+    }
+}
+
+static void free_all(csx_geometry *h)
+{
+    void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qb, h->t.qv, h->t.phi32,
+                    h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
+                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->scal, h->jhist, h->flags};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    release_events(h);
+}
+
+#define CSX_TRY(expr)                        \
+    do {                                     \
+        csx_status s_ = (expr);              \
+        if (s_ != CSX_OK) {                  \
+            free_all(h);                     \
+            delete h;                        \
+            return s_;                       \
+        }                                    \
+    } while (0)
+
+extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry **out)
+{
+    if (!out) return csx_fail(CSX_EINVAL, "out is NULL");
+    *out = nullptr;
+    csx_status st = csx_validate_desc(d);
+    if (st != CSX_OK) return st;
+
+    csx_geometry *h = new (std::nothrow) csx_geometry();
+    if (!h) return csx_fail(CSX_ENOMEM, "host allocation failed");
+    h->d = *d;
+    h->d.q = nullptr;
+    h->d.phi = nullptr;
+    h->d.mask = nullptr;
+    h->table_dtype = d->table_dtype;
+
+    KParams &P = h->P;
+    std::memset(&P, 0, sizeof(P));
+    P.nx = d->nx;
+    P.nz = d->nz;
+    P.nvox = d->nx * d->nz;
+    P.ndx = d->ndx;
+    P.ndy = d->ndy;
+    P.npix = d->ndx * d->ndy;
+    P.nq = d->nq;
+    P.ne = d->ne;
+    P.mask_nx = d->mask_nx;
+    P.mask_ny = d->mask_ny;
+    P.lr = (d->x_min == -d->x_max && d->nx % 2 == 0 && d->ndx % 2 == 0) ? 1 : 0;
+    P.n_groups = P.lr ? d->nz * (d->nx / 2) : P.nvox;
+    P.n_cls = d->ndx * (d->ndy / 2);
+    P.n_quad = P.lr ? (d->ndx / 2) * (d->ndy / 2) : d->ndx * (d->ndy / 2);
+    P.qw = d->nq <= 16 ? 16 : (d->nq <= 32 ? 32 : 64);
+    P.qchunks = (d->nq + P.qw - 1) / P.qw;
+    P.det_z = (float)d->det_z;
+    P.det_zd = d->det_z;
+    P.pitch = (float)d->det_pitch;
+    P.pitchd = d->det_pitch;
+    P.hp2 = (float)(0.25 * d->det_pitch * d->det_pitch);
+    P.hc = d->hc;
+    const double dE = (d->e_hi - d->e_lo) / d->ne;
+    double qmin = d->q[0], qmax = d->q[0];
+    for (int m = 1; m < d->nq; ++m) {
+        qmin = std::min(qmin, d->q[m]);
+        qmax = std::max(qmax, d->q[m]);
+    }
+    P.q_min = qmin;
+    P.q_max = qmax;
+    P.band_lo = d->e_lo - 1e-9 * std::fabs(d->e_lo) - 1e-300;
+    P.band_hi = d->e_hi + 1e-9 * std::fabs(d->e_hi);
+    P.half_my = (float)(0.5 * d->mask_ny);
+
+    // per-voxel tables; with the x -> -x mirror the coordinates are mirrored
+    // exactly (x of column nx-1-i is -x of column i)
+    const int nvox = P.nvox;
+    std::vector<float2> vf(nvox), vm(nvox);
+    std::vector<VoxD> vd(nvox);
+    const double dx = (d->x_max - d->x_min) / d->nx, dz = (d->z_max - d->z_min) / d->nz;
+    for (int iz = 0; iz < d->nz; ++iz)
+        for (int ix = 0; ix < d->nx; ++ix) {
+            double x = d->x_min + (ix + 0.5) * dx;
+            if (P.lr && ix >= d->nx / 2) x = -(d->x_min + (d->nx - 1 - ix + 0.5) * dx);
+            const double z = d->z_min + (iz + 0.5) * dz;
+            const double R2 = x * x + z * z;
+            const double R = std::sqrt(R2);
+            const double t = (d->mask_z - z) / (d->det_z - z);
+            const int j = iz * d->nx + ix;
+            vf[j] = make_float2((float)(d->C * z / (R2 * R)), (float)(d->det_z - z));
+            vm[j] = make_float2((float)(t / d->mask_pitch), (float)((1.0 - t) * x / d->mask_pitch));
+            vd[j] = VoxD{x, z, R2, 0.0};
+        }
+    const int nqp = P.qchunks * P.qw;
+    std::vector<double> qa(nqp, 0.0), qb(nqp, -1.0);
+    std::vector<float> qv(nqp, 0.0f);
+    for (int m = 0; m < d->nq; ++m) {
+        qa[m] = d->q[m] / dE;
+        qb[m] = 1.0 - d->e_lo / dE;
+        qv[m] = (float)d->q[m];
+    }
+    std::vector<float> phi32(d->ne + 2, 0.0f);
+    std::vector<uint16_t> phi16(d->ne + 2, 0);
+    for (int k = 0; k < d->ne; ++k) {
+        phi32[k + 1] = (float)d->phi[k];
+        phi16[k + 1] = bf16_rne((float)d->phi[k]);
+    }
+    std::vector<uint32_t> bits(d->mask_ny, 0u);
+    for (int r = 0; r < d->mask_ny; ++r)
+        for (int c = 0; c < d->mask_nx; ++c)
+            if (d->mask[(size_t)r * d->mask_nx + c]) bits[r] |= 1u << c;
+
+    int64_t &B = h->bytes;
+    CSX_TRY(dev_upload(&h->t.vf, vf, B));
+    CSX_TRY(dev_upload(&h->t.vm, vm, B));
+    CSX_TRY(dev_upload(&h->t.vd, vd, B));
+    CSX_TRY(dev_upload(&h->t.qa, qa, B));
+    CSX_TRY(dev_upload(&h->t.qb, qb, B));
+    CSX_TRY(dev_upload(&h->t.qv, qv, B));
+    CSX_TRY(dev_upload(&h->t.phi32, phi32, B));
+    CSX_TRY(dev_upload(&h->t.phi16, phi16, B));
+    CSX_TRY(dev_upload(&h->t.maskbits, bits, B));
+
+    csx_choose_launch(h);
+    const size_t nimg = (size_t)P.nvox * P.nq;
+    CSX_TRY(dev_alloc(&h->part, (size_t)h->fwd_splits * P.qchunks * P.npix, B));
+    CSX_TRY(dev_alloc(&h->gws, P.npix, B));
+    CSX_TRY(dev_alloc(&h->rho, P.npix, B));
+    CSX_TRY(dev_alloc(&h->ones, P.npix, B));
+    CSX_TRY(dev_alloc(&h->b1, nimg, B));
+    CSX_TRY(dev_alloc(&h->b2, nimg, B));
+    CSX_TRY(dev_alloc(&h->ftmp, nimg, B));
+    h->nbL = (P.npix + 255) / 256;
+    h->nbR = (int)((nimg + 255) / 256);
+    CSX_TRY(dev_alloc(&h->partL, h->nbL, B));
+    CSX_TRY(dev_alloc(&h->partR, h->nbR, B));
+    CSX_TRY(dev_alloc(&h->partF, h->nbL, B));
+    CSX_TRY(dev_alloc(&h->scal, 8, B));
+    CSX_TRY(dev_alloc(&h->flags, 1, B));
+    CSX_TRY(csx_launch_fill(h->ones, P.npix, 1.0f, nullptr));
+    CSX_TRY(csx_launch_clear_flags(h, nullptr));
+    {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            free_all(h);
+            delete h;
+            return csx_fail(CSX_EHIP, std::string("init: ") + hipGetErrorString(e));
+        }
+    }
+    *out = h;
+    return CSX_OK;
+}
+
+extern "C" void csx_free_geometry(csx_geometry *h)
+{
+    if (!h) return;
+    free_all(h);
+    delete h;
+}
+
+extern "C" csx_status csx_get_info(const csx_geometry *h, csx_info *out)
+{
+    if (!h || !out) return csx_fail(CSX_EINVAL, "NULL argument");
+    out->nvox = h->P.nvox;
+    out->npix = h->P.npix;
+    out->nq = h->P.nq;
+    out->symmetric_lr = h->P.lr;
+    out->table_dtype = h->table_dtype;
+    out->workspace_bytes = h->bytes;
+    return CSX_OK;
+}
+
+extern "C" csx_status csx_timing_enable(csx_geometry *h, int on)
+{
+    if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
+    HIP_TRY(hipDeviceSynchronize());
+    h->ev_used[0] = h->ev_used[1] = 0;
+    h->timing = on != 0;
+    return CSX_OK;
+}
+
+extern "C" csx_status csx_timing_read(csx_geometry *h, double ms[2], int n[2])
+{
+    if (!h || !ms || !n) return csx_fail(CSX_EINVAL, "NULL argument");
+    for (int op = 0; op < 2; ++op) {
+        ms[op] = 0.0;
+        n[op] = h->ev_used[op] / 2;
+        for (int k = 0; k + 1 < h->ev_used[op]; k += 2) {
+            HIP_TRY(hipEventSynchronize(h->ev[op][k + 1]));
+            float t = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t, h->ev[op][k], h->ev[op][k + 1]));
+            ms[op] += t;
+        }
+    }
+    return CSX_OK;
+}
+
+extern "C" csx_status csx_forward(csx_geometry *h, const float *f, float *g, void *stream)
+{
+    if (!h || !f || !g) return csx_fail(CSX_EINVAL, "NULL argument");
+    return csx_launch_forward(h, f, g, (hipStream_t)stream);
+}
+
+extern "C" csx_status csx_backproject(csx_geometry *h, const float *y, float *b, void *stream)
+{
+    if (!h || !y || !b) return csx_fail(CSX_EINVAL, "NULL argument");
+    return csx_launch_adjoint(h, y, b, (hipStream_t)stream);
+}
+
+static csx_status ensure_b1(csx_geometry *h, hipStream_t s)
+{
+    if (h->have_b1) return CSX_OK;
+    csx_status st = csx_launch_adjoint(h, h->ones, h->b1, s);
+    if (st != CSX_OK) return st;
+    h->have_b1 = true;
+    return CSX_OK;
+}
+
+#define ST_TRY(expr)                 \
+    do {                             \
+        csx_status s_ = (expr);      \
+        if (s_ != CSX_OK) return s_; \
+    } while (0)
+
+static csx_status step_impl(csx_geometry *h, const float *y, const float *r, float *f, double beta,
+                            double *J, hipStream_t s)
+{
+    ST_TRY(ensure_b1(h, s));
+    ST_TRY(csx_launch_forward(h, f, h->gws, s));                // z = A f^t (+ r below)
+    ST_TRY(csx_launch_ratio(h, y, r, true, s));                 // rho = y / z, data-fit partials
+    ST_TRY(csx_launch_adjoint(h, h->rho, h->b2, s));            // b2 = A^T rho
+    ST_TRY(csx_launch_update(h, f, beta, true, s));             // f^{t+1} into ftmp, R(f^t) partials
+    if (J) ST_TRY(csx_launch_objective(h, beta, J, s));         // J(f^t)
+    return csx_launch_copy(h->ftmp, f, h->P.nvox * h->P.nq, s);
+}
+
+extern "C" csx_status csx_recon_step(csx_geometry *h, const float *y, const float *r, float *f,
+                                     double beta, double *J_out, void *stream)
+{
+    if (!h || !y || !f) return csx_fail(CSX_EINVAL, "NULL argument");
+    if (!(std::isfinite(beta) && beta >= 0.0)) return csx_fail(CSX_EINVAL, "beta must be finite and >= 0");
+    return step_impl(h, y, r, f, beta, J_out, (hipStream_t)stream);
+}
+
+extern "C" csx_status csx_recon(csx_geometry *h, const float *y, const float *r, float *f,
+                                int init_uniform, int n_iter, double beta, double *J_hist,
+                                void *stream)
+{
+    if (!h || !y || !f) return csx_fail(CSX_EINVAL, "NULL argument");
+    if (n_iter < 0) return csx_fail(CSX_EINVAL, "n_iter must be >= 0");
+    if (!(std::isfinite(beta) && beta >= 0.0)) return csx_fail(CSX_EINVAL, "beta must be finite and >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (h->jhist_cap < n_iter + 1) {
+        if (h->jhist) HIP_TRY(hipFree(h->jhist));
+        h->jhist = nullptr;
+        h->jhist_cap = 0;
+        HIP_TRY(hipMalloc((void **)&h->jhist, sizeof(double) * (n_iter + 1)));
+        h->jhist_cap = n_iter + 1;
+    }
+    ST_TRY(csx_launch_clear_flags(h, s));
+    ST_TRY(ensure_b1(h, s));
+    if (init_uniform) ST_TRY(csx_launch_uniform_start(h, y, f, s));
+    for (int t = 0; t < n_iter; ++t) ST_TRY(step_impl(h, y, r, f, beta, h->jhist + t, s));
+    // J at the final iterate
+    ST_TRY(csx_launch_forward(h, f, h->gws, s));
+    ST_TRY(csx_launch_ratio(h, y, r, false, s));
+    ST_TRY(csx_launch_update(h, f, beta, false, s));
+    ST_TRY(csx_launch_objective(h, beta, h->jhist + n_iter, s));
+    int flags = 0;
+    HIP_TRY(hipMemcpyAsync(&flags, h->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (J_hist)
+        HIP_TRY(hipMemcpyAsync(J_hist, h->jhist, sizeof(double) * (n_iter + 1),
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (flags & 2) return csx_fail(CSX_EINVAL, "y holds negative or NaN counts");
+    if (flags & 1) return csx_fail(CSX_ENUMERIC, "y_i > 0 where the model mean is 0");
+    return CSX_OK;
+}

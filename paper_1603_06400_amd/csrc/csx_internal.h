@@ -1,0 +1,105 @@
+// csx_internal.h -- shared definitions of the HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/csx.h"
+
+#define CSX_MAX_NE 2048
+#define CSX_MAX_MASK_ROWS 8192
+#define CSX_MAX_MASK_PERIOD 32
+
+csx_status csx_fail(csx_status s, const std::string &msg);
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return csx_fail(CSX_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Per-launch constants of the operator kernels.
+struct KParams {
+    int nvox, npix, nx, nz, nq, ndx, ndy, ne, mask_nx, mask_ny;
+    int lr;              // 1: x -> -x mirror exploited (centred grids, nx and ndx even)
+    int n_groups;        // voxel groups: pairs (j, mirror j) with LR, else single voxels
+    int n_cls;           // pixel classes of the adjoint: ndx * ndy/2 (columns x upper rows)
+    int n_quad;          // forward output groups: (ndx/2)*(ndy/2) with LR, else ndx*(ndy/2)
+    int qw;              // q lanes per class (64, 32 or 16); 64/qw classes share a wave instruction
+    int qchunks;         // ceil(nq / qw)
+    float det_z, pitch, hp2;
+    double hc, det_zd, pitchd;
+    double band_lo, band_hi;    // class in band iff kappa q_max >= band_lo and kappa q_min < band_hi
+    double q_min, q_max;
+    float half_my;
+};
+
+// Per-voxel records.  vf: {C*Gso, det_z - z} (float32); vm: {t/pm,
+// (1-t) x/pm} with t = (mask_z - z)/(det_z - z); vd: {x, z, x^2+z^2} (float64).
+struct VoxD {
+    double x, z, R2, pad;
+};
+
+struct DevTables {
+    float2 *vf = nullptr;
+    float2 *vm = nullptr;
+    VoxD *vd = nullptr;
+    double *qa = nullptr;      // [qchunks*qw] q_m/dE (0 beyond nq)
+    double *qb = nullptr;      // [qchunks*qw] 1 - e_lo/dE (-1 beyond nq: never in band)
+    float *qv = nullptr;       // [qchunks*qw] q_m (0 beyond nq)
+    float *phi32 = nullptr;    // [ne+2] zero-padded spectrum, float32
+    uint16_t *phi16 = nullptr; // [ne+2] zero-padded spectrum, bfloat16 bits
+    uint32_t *maskbits = nullptr; // [mask_ny] bit c of row r = cell (c, r)
+};
+
+struct csx_geometry {
+    csx_geometry_desc d;       // copy (array pointers not kept)
+    KParams P;
+    DevTables t;
+    int table_dtype = CSX_TABLE_F32;
+    // launch shape
+    int fwd_wpb = 8, fwd_splits = 1, adj_wpb = 4;
+    // workspace
+    float *part = nullptr;     // forward partials [fwd_splits*qchunks][npix]
+    float *gws = nullptr;      // [npix] model mean
+    float *rho = nullptr;      // [npix] y / z
+    float *ones = nullptr;     // [npix] 1
+    float *b1 = nullptr;       // [nvox*nq] sensitivity
+    float *b2 = nullptr;       // [nvox*nq]
+    float *ftmp = nullptr;     // [nvox*nq]
+    double *partL = nullptr;   // per-block data-fit partials
+    double *partR = nullptr;   // per-block penalty partials
+    double *scal = nullptr;    // [8] scalars
+    double *jhist = nullptr;   // device J history (grown on demand)
+    int jhist_cap = 0;
+    int *partF = nullptr;      // per-block flags of the data term
+    int *flags = nullptr;      // flags of the last objective: bit 0: y_i > 0 with zero
+                               // mean; bit 1: y_i < 0 or NaN
+    int nbL = 0, nbR = 0;
+    bool have_b1 = false;
+    int64_t bytes = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev[2];
+    int ev_used[2] = {0, 0};
+};
+
+// operator launchers (csx_ops.hip)
+csx_status csx_launch_forward(csx_geometry *h, const float *f, float *g, hipStream_t s);
+csx_status csx_launch_adjoint(csx_geometry *h, const float *rho, float *b, hipStream_t s);
+void csx_choose_launch(csx_geometry *h);
+hipEvent_t csx_timing_event(csx_geometry *h, int op);
+
+// solver pieces (csx_solver.hip)
+csx_status csx_launch_ratio(csx_geometry *h, const float *y, const float *r, bool want_rho,
+                            hipStream_t s);
+csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool do_update,
+                             hipStream_t s);
+csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, hipStream_t s);
+csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, hipStream_t s);
+csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s);
+csx_status csx_launch_fill(float *dst, int n, float v, hipStream_t s);
+csx_status csx_launch_clear_flags(csx_geometry *h, hipStream_t s);

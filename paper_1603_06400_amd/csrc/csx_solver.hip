@@ -1,0 +1,239 @@
+// csx_solver.hip -- the Poisson data term, the separable-surrogate update
+// and the float64 objective of the EM-type algorithm (Alg. 5; Sec. V; App. B).
+#include "csx_internal.h"
+
+#include <cmath>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// K3 Poisson ratio + data-fit partials (float64):
+//   z = g + r, rho = y/z (0 where y = 0), L_i = z - y ln z + ln y!
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum_d(double v, double *s_red)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) s_red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += s_red[k];
+    }
+    return t;
+}
+
+__global__ void __launch_bounds__(256) k_ratio(int n, const float *__restrict__ g,
+                                               const float *__restrict__ y,
+                                               const float *__restrict__ r,
+                                               float *__restrict__ rho, double *__restrict__ partL,
+                                               int *__restrict__ partF, int want_rho)
+{
+    __shared__ double s_red[4];
+    __shared__ int s_flag;
+    if (threadIdx.x == 0) s_flag = 0;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double L = 0.0;
+    int flag = 0;
+    if (i < n) {
+        const float z = g[i] + (r ? r[i] : 0.0f);
+        const float yi = y[i];
+        float q = 0.0f;
+        if (!(yi >= 0.0f)) {
+            flag = 2;
+        } else if (yi > 0.0f) {
+            if (z > 0.0f) {
+                q = yi / z;
+                L = (double)z - (double)yi * log((double)z) + lgamma((double)yi + 1.0);
+            } else {
+                flag = 1;
+                L = INFINITY;
+            }
+        } else {
+            L = (double)z;
+        }
+        if (want_rho) rho[i] = q;
+    }
+    if (flag) atomicOr(&s_flag, flag);
+    const double t = block_sum_d(L, s_red);
+    if (threadIdx.x == 0) {
+        partL[blockIdx.x] = t;
+        partF[blockIdx.x] = s_flag;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4 separable-surrogate update (App. B, eq. f_update) for psi(t) = t^2/2,
+// 4 in-slice neighbours at the same q, unit weights; evaluated in float64:
+//   b3 + b4 = 4 |N_j|, b5 + b6 = 2 sum_k (fhat_j - fhat_k)
+//   chi1 = beta (b3+b4), chi2 = b1 + beta(-fhat (b3+b4) + b5 + b6), chi3 = fhat b2
+//   f = 2 chi3 / (chi2 + sqrt(chi2^2 + 4 chi1 chi3))       if chi2 > 0
+//     = (-chi2 + sqrt(chi2^2 + 4 chi1 chi3)) / (2 chi1)    if chi2 <= 0, chi1 > 0
+//     = fhat                                               otherwise (unseen voxel, beta = 0)
+// The first form is Lemma 1's root multiplied through by its conjugate.
+// Also accumulates R(fhat) = sum_j sum_k (fhat_j - fhat_k)^2 / 2 per block.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const float *__restrict__ fh,
+                                                const float *__restrict__ b1,
+                                                const float *__restrict__ b2, double beta,
+                                                float *__restrict__ fout,
+                                                double *__restrict__ partR, int do_update)
+{
+    __shared__ double s_red[4];
+    const int n = nx * nz * nq;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    double R = 0.0;
+    if (e < n) {
+        const int m = e % nq;
+        const int j = e / nq;
+        const int ix = j % nx, iz = j / nx;
+        const double fj = fh[e];
+        double s = 0.0, rr = 0.0;
+        int cnt = 0;
+        if (ix > 0) { const double d = fj - fh[e - nq]; s += d; rr += d * d; ++cnt; }
+        if (ix < nx - 1) { const double d = fj - fh[e + nq]; s += d; rr += d * d; ++cnt; }
+        if (iz > 0) { const double d = fj - fh[e - (size_t)nx * nq]; s += d; rr += d * d; ++cnt; }
+        if (iz < nz - 1) { const double d = fj - fh[e + (size_t)nx * nq]; s += d; rr += d * d; ++cnt; }
+        R = 0.5 * rr;
+        if (do_update) {
+            const double b34 = 4.0 * cnt;
+            const double chi1 = beta * b34;
+            const double chi2 = (double)b1[e] + beta * (-fj * b34 + 2.0 * s);
+            const double chi3 = fj * (double)b2[e];
+            double out;
+            const double disc = sqrt(chi2 * chi2 + 4.0 * chi1 * chi3);
+            if (chi2 > 0.0) out = 2.0 * chi3 / (chi2 + disc);
+            else if (chi1 > 0.0) out = (-chi2 + disc) / (2.0 * chi1);
+            else out = fj;
+            fout[e] = (float)out;
+        }
+        (void)m;
+    }
+    const double t = block_sum_d(R, s_red);
+    if (threadIdx.x == 0) partR[blockIdx.x] = t;
+}
+
+// K5: J = sum partL + beta * sum partR in a fixed order, one block; the
+// per-block flags of K3 are combined into *flags (J = +inf when some y_i > 0
+// met a zero mean).
+__global__ void __launch_bounds__(256) k_objective(const double *__restrict__ partL, int nL,
+                                                   const double *__restrict__ partR, int nR,
+                                                   const int *__restrict__ partF, double beta,
+                                                   int *__restrict__ flags, double *__restrict__ J)
+{
+    __shared__ double s_red[4];
+    __shared__ int s_flag;
+    if (threadIdx.x == 0) s_flag = 0;
+    __syncthreads();
+    double a = 0.0, b = 0.0;
+    int fl = 0;
+    for (int k = threadIdx.x; k < nL; k += blockDim.x) {
+        a += partL[k];
+        fl |= partF[k];
+    }
+    for (int k = threadIdx.x; k < nR; k += blockDim.x) b += partR[k];
+    if (fl) atomicOr(&s_flag, fl);
+    const double ta = block_sum_d(a, s_red);
+    __syncthreads();
+    const double tb = block_sum_d(b, s_red);
+    if (threadIdx.x == 0) {
+        *flags = s_flag;
+        *J = (s_flag & 1) ? INFINITY : ta + beta * tb;
+    }
+}
+
+// sums for the uniform start: scal[0] = sum y, scal[1] = sum b1
+__global__ void __launch_bounds__(256) k_sum2(const float *__restrict__ x, int nx_,
+                                              const float *__restrict__ y, int ny_,
+                                              double *__restrict__ out)
+{
+    __shared__ double s_red[4];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nx_; k += blockDim.x) a += x[k];
+    for (int k = threadIdx.x; k < ny_; k += blockDim.x) b += y[k];
+    const double ta = block_sum_d(a, s_red);
+    __syncthreads();
+    const double tb = block_sum_d(b, s_red);
+    if (threadIdx.x == 0) { out[0] = ta; out[1] = tb; }
+}
+
+__global__ void k_fill_ratio(float *__restrict__ f, int n, const double *__restrict__ scal)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) f[e] = (float)(scal[1] > 0.0 ? scal[0] / scal[1] : 0.0);
+}
+
+__global__ void k_fill(float *__restrict__ p, int n, float v)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
+__global__ void k_copy(const float *__restrict__ s, float *__restrict__ d, int n)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) d[e] = s[e];
+}
+
+__global__ void k_clear_int(int *p) { *p = 0; }
+
+}  // namespace
+
+csx_status csx_launch_ratio(csx_geometry *h, const float *y, const float *r, bool want_rho,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ratio, dim3(h->nbL), dim3(256), 0, s, h->P.npix, h->gws, y, r, h->rho,
+                       h->partL, h->partF, want_rho ? 1 : 0);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool do_update,
+                             hipStream_t s)
+{
+    const KParams &P = h->P;
+    hipLaunchKernelGGL(k_update, dim3(h->nbR), dim3(256), 0, s, P.nx, P.nz, P.nq, f, h->b1, h->b2,
+                       beta, h->ftmp, h->partR, do_update ? 1 : 0);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, s, h->partL, h->nbL, h->partR, h->nbR,
+                       h->partF, beta, h->flags, J);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, hipStream_t s)
+{
+    const int n = h->P.nvox * h->P.nq;
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, y, h->P.npix, h->b1, n, h->scal);
+    hipLaunchKernelGGL(k_fill_ratio, dim3((n + 255) / 256), dim3(256), 0, s, f, n, h->scal);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_fill(float *dst, int n, float v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, dst, n, v);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_clear_flags(csx_geometry *h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(1), 0, s, h->flags);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}

@@ -54,8 +54,12 @@ def test_validation_accepts_workloads():
         csx.validate(inputs.workload(name).geom, csx.TABLE_BF16)
 
 
-def test_bitmask_form_needs_narrow_mask():
-    g = good().with_(mask=np.ones((10, 40), np.uint8))
-    csx.validate(g)
-    with pytest.raises(csx.CsxError):
-        csx.validate(g, csx.TABLE_BF16)
+def test_mask_limits():
+    """The mask is held in LDS as one 32-bit word per row: period <= 32 cells,
+    <= 4096 rows."""
+    csx.validate(good().with_(mask=np.ones((10, 32), np.uint8)))
+    for bad in (np.ones((10, 33), np.uint8), np.ones((4097, 16), np.uint8)):
+        for td in (csx.TABLE_F32, csx.TABLE_BF16):
+            with pytest.raises(csx.CsxError) as ei:
+                csx.validate(good().with_(mask=bad), td)
+            assert ei.value.code == csx.CSX_EGEOM

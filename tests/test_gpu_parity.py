@@ -35,6 +35,15 @@ RAGGED = [
     (5, 3, 70, 31, 22, 17, 401.9),      # tall slice, ragged everything
 ]
 
+# centred voxel grids with even nx and ndx: the x -> -x mirror path
+SYMMETRIC = [
+    (11, 8, 5, 10, 6, 20, 404.77),      # two classes per wave instruction (nq <= 32)
+    (12, 12, 9, 14, 12, 12, 402.57),    # four classes per wave instruction (nq <= 16)
+    (13, 34, 7, 22, 8, 70, 403.93),     # two q chunks, voxel pairs beyond one batch
+    (14, 6, 40, 6, 30, 64, 402.57),     # exactly one q chunk, tall slice
+    (15, 16, 16, 16, 16, 8, 404.13),    # 8 q nodes
+]
+
 
 @pytest.mark.parametrize("case", RAGGED, ids=[f"r{c[0]}" for c in RAGGED])
 def test_forward_adjoint_ragged(oracle_mod, case):
@@ -44,8 +53,23 @@ def test_forward_adjoint_ragged(oracle_mod, case):
     o = oracle_mod.Oracle(g)
     assert o.margins()["mask_edge_mm"] > 1e-4   # no float32/float64 tie at a mask-cell edge
     geo = csx.Geometry(g)
+    assert geo.info()["symmetric_lr"] == 0
     f = inputs.random_image(g, 100 + seed)
     y = inputs.random_detector(g, 200 + seed)
+    assert_parity(host(geo.forward(dev(f))), o.forward(f), what="forward")
+    assert_parity(host(geo.backproject(dev(y))), o.adjoint(y), what="adjoint")
+
+
+@pytest.mark.parametrize("case", SYMMETRIC, ids=[f"s{c[0]}" for c in SYMMETRIC])
+def test_forward_adjoint_mirror_path(oracle_mod, case):
+    print(f"[symmetric {case}]", flush=True)
+    g = ragged_geometry(*case, x=(-40.0, 40.0))
+    o = oracle_mod.Oracle(g)
+    assert o.margins()["mask_edge_mm"] > 1e-4
+    geo = csx.Geometry(g)
+    assert geo.info()["symmetric_lr"] == 1
+    f = inputs.random_image(g, 300 + case[0])
+    y = inputs.random_detector(g, 400 + case[0])
     assert_parity(host(geo.forward(dev(f))), o.forward(f), what="forward")
     assert_parity(host(geo.backproject(dev(y))), o.adjoint(y), what="adjoint")
 
