@@ -10,7 +10,7 @@
 #include "../../include/csx.h"
 
 #define CSX_MAX_NE 2048
-#define CSX_MAX_MASK_ROWS 8192
+#define CSX_MAX_MASK_ROWS 4096
 #define CSX_MAX_MASK_PERIOD 32
 
 csx_status csx_fail(csx_status s, const std::string &msg);
