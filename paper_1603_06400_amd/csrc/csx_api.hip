@@ -99,9 +99,9 @@ static void release_events(csx_geometry *h)
 
 static void free_all(csx_geometry *h)
 {
-    void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qb, h->t.qv, h->t.phi32,
+    void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qblk, h->t.qv, h->t.phi32,
                     h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
-                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->scal, h->jhist, h->flags};
+                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     release_events(h);
@@ -188,12 +188,23 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
             vd[j] = VoxD{x, z, R2, 0.0};
         }
     const int nqp = P.qchunks * P.qw;
-    std::vector<double> qa(nqp, 0.0), qb(nqp, -1.0);
+    P.b0 = 1.0 - d->e_lo / dE;
+    std::vector<double> qa(nqp, 0.0);
     std::vector<float> qv(nqp, 0.0f);
     for (int m = 0; m < d->nq; ++m) {
         qa[m] = d->q[m] / dE;
-        qb[m] = 1.0 - d->e_lo / dE;
         qv[m] = (float)d->q[m];
+    }
+    // q range of each block of 8 nodes (padding blocks never in band)
+    std::vector<double2> qblk(nqp / 8);
+    for (int bk = 0; bk < nqp / 8; ++bk) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int m = bk * 8; m < bk * 8 + 8; ++m)
+            if (m < d->nq) {
+                lo = std::min(lo, d->q[m]);
+                hi = std::max(hi, d->q[m]);
+            }
+        qblk[bk] = make_double2(lo, hi);
     }
     std::vector<float> phi32(d->ne + 2, 0.0f);
     std::vector<uint16_t> phi16(d->ne + 2, 0);
@@ -211,7 +222,7 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     CSX_TRY(dev_upload(&h->t.vm, vm, B));
     CSX_TRY(dev_upload(&h->t.vd, vd, B));
     CSX_TRY(dev_upload(&h->t.qa, qa, B));
-    CSX_TRY(dev_upload(&h->t.qb, qb, B));
+    CSX_TRY(dev_upload(&h->t.qblk, qblk, B));
     CSX_TRY(dev_upload(&h->t.qv, qv, B));
     CSX_TRY(dev_upload(&h->t.phi32, phi32, B));
     CSX_TRY(dev_upload(&h->t.phi16, phi16, B));
@@ -231,6 +242,7 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     CSX_TRY(dev_alloc(&h->partL, h->nbL, B));
     CSX_TRY(dev_alloc(&h->partR, h->nbR, B));
     CSX_TRY(dev_alloc(&h->partF, h->nbL, B));
+    CSX_TRY(dev_alloc(&h->partS, 2 * CSX_SUM_BLOCKS, B));
     CSX_TRY(dev_alloc(&h->scal, 8, B));
     CSX_TRY(dev_alloc(&h->flags, 1, B));
     CSX_TRY(csx_launch_fill(h->ones, P.npix, 1.0f, nullptr));

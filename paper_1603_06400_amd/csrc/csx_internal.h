@@ -12,6 +12,7 @@
 #define CSX_MAX_NE 2048
 #define CSX_MAX_MASK_ROWS 4096
 #define CSX_MAX_MASK_PERIOD 32
+#define CSX_SUM_BLOCKS 256
 
 csx_status csx_fail(csx_status s, const std::string &msg);
 
@@ -34,6 +35,7 @@ struct KParams {
     float det_z, pitch, hp2;
     double hc, det_zd, pitchd;
     double band_lo, band_hi;    // class in band iff kappa q_max >= band_lo and kappa q_min < band_hi
+    double b0;                  // 1 - e_lo/dE: table index = floor(kappa q/dE + b0)
     double q_min, q_max;
     float half_my;
 };
@@ -49,7 +51,7 @@ struct DevTables {
     float2 *vm = nullptr;
     VoxD *vd = nullptr;
     double *qa = nullptr;      // [qchunks*qw] q_m/dE (0 beyond nq)
-    double *qb = nullptr;      // [qchunks*qw] 1 - e_lo/dE (-1 beyond nq: never in band)
+    double2 *qblk = nullptr;   // [qchunks*qw/8] {min q, max q} of each block of 8 nodes
     float *qv = nullptr;       // [qchunks*qw] q_m (0 beyond nq)
     float *phi32 = nullptr;    // [ne+2] zero-padded spectrum, float32
     uint16_t *phi16 = nullptr; // [ne+2] zero-padded spectrum, bfloat16 bits
@@ -73,6 +75,7 @@ struct csx_geometry {
     float *ftmp = nullptr;     // [nvox*nq]
     double *partL = nullptr;   // per-block data-fit partials
     double *partR = nullptr;   // per-block penalty partials
+    double *partS = nullptr;   // [2 * CSX_SUM_BLOCKS] partial sums of the uniform start
     double *scal = nullptr;    // [8] scalars
     double *jhist = nullptr;   // device J history (grown on demand)
     int jhist_cap = 0;

@@ -7,33 +7,36 @@
 //   A = C Gso God dtheta (1 + cos^2 theta) cos(theta/2) / sin^2(theta/2)
 //
 // Work decomposition (wave64):
-//  * lanes = q.  The per-q inner step (the paper's W(r, theta) = sum_q S f) is
-//    one FP64 FMA for the Bragg bin coordinate, an integer clamp, one gather
-//    from the spectrum table in LDS and one or two FP32 FMAs per lane.
 //  * a "class" is a set of pairs that share every factor except the mask
 //    transmission T: the pixel rows y' and -y' (up-down mirror, Sec. III-A)
 //    and, when the voxel grid and the detector are centred with even sizes,
 //    the voxel / pixel columns x and -x (left-right mirror).  One class is
 //    4 pairs (2 without the left-right mirror); its four mask cells come from a
 //    single crossing point, mirrored with integer arithmetic.
-//  * classes are evaluated one per lane, 64 at a time; the wave compacts the
-//    classes with an open cell and an in-band Bragg energy into an LDS list
-//    (ballot + mbcnt) and then walks the list with 16-byte broadcast reads,
-//    64/qw classes per wave instruction when nq <= 32.
+//  * lane = class.  Each lane evaluates its class's factors once and keeps
+//    kappa and the pair weights in its own registers; the q loop then runs
+//    inside the lane (fully unrolled over a chunk of <= 64 q), so no lane ever
+//    waits on a value another lane produced.  The per-q step is one FP64 FMA
+//    for the Bragg bin coordinate, an unsigned clamp, a gather from the
+//    spectrum table in LDS and FP32 FMAs; q/dE comes from scalar loads.
+//  * blocks of 8 q nodes are skipped, uniformly for the wave, when no lane's
+//    Bragg energies kappa q can reach the spectrum band there.
 //  * the spectral bin of a triple is decided in float64 (kappa in float64
 //    from float32 seeds refined by one Newton step each; the bin coordinate
 //    q/dE * kappa + 1 - e_lo/dE by one FP64 FMA): the same precision as the
 //    float64 definition, so bin decisions agree except at float64 ties.
-//  * forward: output-stationary per group of mirror pixels, voxels staged in
-//    LDS per block, voxel range split across blocks with a fixed-order sum of
-//    the partial images (no atomics, bitwise reproducible).
-//  * adjoint: output-stationary per (voxel, mirror voxel) pair, no atomics.
+//  * adjoint: one wave per voxel (and its x-mirror) walks the pixel classes 64
+//    at a time, accumulating per-lane partial images acc[q]; one butterfly
+//    transpose-reduction per wave sums them over lanes (no atomics).
+//  * forward: one wave per group of mirror pixels; one lane per voxel (pair)
+//    evaluates both mirror classes and accumulates the paper's W(r, theta) =
+//    sum_q S f over the q chunk, reading q f from a q-major LDS tile shared by
+//    the block; the voxel range is split across blocks and the partial images
+//    are summed in a fixed order (bitwise reproducible).
 #include "csx_internal.h"
 
 namespace {
 
-constexpr int UNROLL = 4;
-constexpr int LIST_CAP = 80;   // 64 classes + padding to a multiple of slots * UNROLL
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h)
 {
@@ -41,7 +44,7 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h)
 }
 
 template <int TD>
-__device__ __forceinline__ float spec(const float *s_phi, const uint16_t *s_phi16, int k)
+__device__ __forceinline__ float spec(const float *s_phi, const uint16_t *s_phi16, uint32_t k)
 {
     if (TD == CSX_TABLE_BF16) return bf16_to_f32(s_phi16[k]);
     return s_phi[k];
@@ -119,12 +122,14 @@ __device__ __forceinline__ bool in_band(const KParams &P, double kappa)
     return kappa * P.q_max >= P.band_lo && kappa * P.q_min < P.band_hi;
 }
 
-// Spectrum-table index of one triple: 1 + bin, 0 below the band, ne + 1 above.
-__device__ __forceinline__ int spec_index(const KParams &P, double kappa, double qa, double qb)
+// Spectrum-table index of one triple: 1 + bin inside the band; outside it the
+// index lands on one of the two zero pads (0 or ne + 1): a negative bin
+// coordinate wraps to a large unsigned value and is clamped to ne + 1.
+__device__ __forceinline__ uint32_t spec_index(double kappa, double qa, double b0, uint32_t top)
 {
-    const double u = fma(kappa, qa, qb);
-    const int k = (int)u;
-    return min(max(k, 0), P.ne + 1);
+    const double u = fma(kappa, qa, b0);
+    const uint32_t k = (uint32_t)(int)u;
+    return min(k, top);
 }
 
 template <int TD>
@@ -141,7 +146,7 @@ __device__ __forceinline__ void stage_tables(const KParams &P, const DevTables &
 }
 
 struct Lds {
-    int phi, mask, list, tile, total;
+    int phi, mask, tile, total;
 };
 
 // Mask cells of one crossing: columns of the pixel (col_a) and of its x-mirror
@@ -169,23 +174,56 @@ __device__ __forceinline__ float bitf(uint32_t row, int col)
     return (float)((row >> col) & 1u);
 }
 
+// Sum of v[0..N) over the 64 lanes of the wave, butterfly style: at each
+// distance d the lanes with bit d set keep the upper half of their values and
+// send the lower half to their partner (and vice versa), so after six steps
+// lane l holds the total for index l >> (6 - log2 N).
+template <int N, int D>
+struct WaveTransposeSum {
+    static __device__ __forceinline__ void run(float *v, int lane)
+    {
+        if constexpr (D == 0) {
+            return;
+        } else if constexpr (N > 1) {
+            constexpr int H = N / 2;
+            const bool up = (lane & D) != 0;
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                const float send = up ? v[i] : v[H + i];
+                const float keep = up ? v[H + i] : v[i];
+                v[i] = keep + __shfl_xor(send, D, 64);
+            }
+            WaveTransposeSum<H, D / 2>::run(v, lane);
+        } else {
+            v[0] += __shfl_xor(v[0], D, 64);
+            WaveTransposeSum<1, D / 2>::run(v, lane);
+        }
+    }
+};
+
+template <int QW>
+__device__ __forceinline__ int transposed_index(int lane)
+{
+    return QW == 64 ? lane : (QW == 32 ? (lane >> 1) : (lane >> 2));
+}
+
 // ---------------------------------------------------------------------------
-// adjoint: one wave per voxel group (voxel j, and its mirror j2 with LR) and q
-// chunk; walks all pixel classes (a, b_up), b_up in the upper half.
+// adjoint: one wave per voxel group (voxel j, and its mirror j2 with LR) and
+// q chunk; lanes = pixel classes (a, b_up), b_up in the upper half, 64 per batch.
 // ---------------------------------------------------------------------------
-template <int TD, int LR, int SLOTS>
+template <int TD, int LR, int QW>
 __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
+                                                 const double *__restrict__ qa,
+                                                 const double2 *__restrict__ qblk,
                                                  const float *__restrict__ rho,
                                                  float *__restrict__ b)
 {
-    constexpr int QW = 64 / SLOTS;
-    constexpr int STEP = SLOTS * UNROLL;
+    constexpr int NB = QW / 8;
     extern __shared__ __align__(16) unsigned char lds[];
     float *s_phi = (float *)(lds + L.phi);
     uint16_t *s_phi16 = (uint16_t *)(lds + L.phi);
     uint32_t *s_bits = (uint32_t *)(lds + L.mask);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    float4 *s_list = (float4 *)(lds + L.list) + wv * LIST_CAP;
 
     stage_tables<TD>(P, T, s_phi, s_phi16, s_bits);
     __syncthreads();
@@ -205,11 +243,38 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
     const VoxD vd = T.vd[j];
     const float2 vf = T.vf[j];
     const float2 vm = T.vm[j];
-    const int slot = lane / QW, ml = lane % QW;
-    const int mq = blockIdx.y * QW + ml;
-    const double qa = T.qa[mq], qb = T.qb[mq];
+    const int m0 = blockIdx.y * QW;
+    const double *qa_c = qa + m0;
+    const double2 *qb_c = qblk + blockIdx.y * NB;
+    const double b0 = P.b0;
+    const uint32_t top = (uint32_t)(P.ne + 1);
 
-    float acc0 = 0.0f, acc1 = 0.0f;
+    float acc0[QW], acc1[QW];
+#pragma unroll
+    for (int m = 0; m < QW; ++m) {
+        acc0[m] = 0.0f;
+        acc1[m] = 0.0f;
+    }
+
+    // detector values of the lane's class, prefetched one batch ahead
+    float r_u = 0.0f, r_d = 0.0f, r_bu = 0.0f, r_bd = 0.0f;
+    auto load_rho = [&](int pb) {
+        const int p = pb + lane;
+        if (p < P.n_cls) {
+            const int a = p % P.ndx;
+            const int bu = P.ndy / 2 + p / P.ndx;
+            const int bd = P.ndy - 1 - bu;
+            r_u = rho[bu * P.ndx + a];
+            r_d = rho[bd * P.ndx + a];
+            if (LR) {
+                const int ab = P.ndx - 1 - a;
+                r_bu = rho[bu * P.ndx + ab];
+                r_bd = rho[bd * P.ndx + ab];
+            }
+        }
+    };
+    load_rho(0);
+
     for (int pb = 0; pb < P.n_cls; pb += 64) {
         const int p = pb + lane;
         double kap = 0.0;
@@ -218,92 +283,84 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
         if (p < P.n_cls) {
             const int a = p % P.ndx;
             const int bu = P.ndy / 2 + p / P.ndx;
-            const int bd = P.ndy - 1 - bu;
             const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
             const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
             const Cells c = mask_cells(P, vm, xp, yp);
             float w0 = 0.0f, w1 = 0.0f;
             if (c.in_rows) {
                 const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
-                w0 = bitf(ru, c.col_a) * rho[bu * P.ndx + a] + bitf(rd, c.col_a) * rho[bd * P.ndx + a];
-                if (LR) {
-                    const int ab = P.ndx - 1 - a;
-                    w1 = bitf(ru, c.col_b) * rho[bu * P.ndx + ab] +
-                         bitf(rd, c.col_b) * rho[bd * P.ndx + ab];
-                }
+                w0 = bitf(ru, c.col_a) * r_u + bitf(rd, c.col_a) * r_d;
+                if (LR) w1 = bitf(ru, c.col_b) * r_bu + bitf(rd, c.col_b) * r_bd;
             }
             if (w0 != 0.0f || w1 != 0.0f) {
+                double k;
                 float A;
-                pair_factors(P, vd, vf, (double)xp, (double)yp, kap, A);
-                if (in_band(P, kap)) {
+                pair_factors(P, vd, vf, (double)xp, (double)yp, k, A);
+                if (in_band(P, k)) {
                     c0 = A * w0;
                     c1 = A * w1;
                     act = c0 != 0.0f || c1 != 0.0f;
+                    if (act) kap = k;
                 }
             }
         }
-        const uint64_t bal = __ballot(act);
-        const int nact = __popcll(bal);
-        const int idx = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        if (act) s_list[idx] = make_float4(dlo(kap), dhi(kap), c0, c1);
-        const int npad = (nact + STEP - 1) / STEP * STEP;
-        if (lane < npad - nact) s_list[nact + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        __builtin_amdgcn_wave_barrier();
-        for (int i = 0; i < npad; i += STEP) {
+        if (pb + 64 < P.n_cls) load_rho(pb + 64);
+        if (__ballot(act) == 0) continue;
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const float4 e = s_list[i + u * SLOTS + slot];
-                const int k = spec_index(P, as_double(e.x, e.y), qa, qb);
-                const float ph = spec<TD>(s_phi, s_phi16, k);
-                acc0 = fmaf(e.z, ph, acc0);
-                if (LR) acc1 = fmaf(e.w, ph, acc1);
+        for (int blk = 0; blk < NB; ++blk) {
+            const double2 qr = qb_c[blk];
+            const bool need = act && kap * qr.y >= P.band_lo && kap * qr.x < P.band_hi;
+            if (__ballot(need) == 0) continue;
+#pragma unroll
+            for (int mm = 0; mm < 8; ++mm) {
+                const int m = blk * 8 + mm;
+                const float ph = spec<TD>(s_phi, s_phi16, spec_index(kap, qa_c[m], b0, top));
+                acc0[m] = fmaf(c0, ph, acc0[m]);
+                if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
             }
         }
-        __builtin_amdgcn_wave_barrier();
     }
-    if (SLOTS >= 2) {
-        acc0 += __shfl_xor(acc0, 32, 64);
-        acc1 += __shfl_xor(acc1, 32, 64);
-    }
-    if (SLOTS >= 4) {
-        acc0 += __shfl_xor(acc0, 16, 64);
-        acc1 += __shfl_xor(acc1, 16, 64);
-    }
-    const int m = blockIdx.y * QW + ml;
-    if (slot == 0 && m < P.nq) {
-        const float qm = T.qv[mq];
-        b[(size_t)j * P.nq + m] = acc0 * qm;
-        if (LR) b[(size_t)j2 * P.nq + m] = acc1 * qm;
+    WaveTransposeSum<QW, 32>::run(acc0, lane);
+    if (LR) WaveTransposeSum<QW, 32>::run(acc1, lane);
+    const int mi = transposed_index<QW>(lane);
+    const int m = m0 + mi;
+    const bool writer = (lane & ((64 / QW) - 1)) == 0;
+    if (writer && m < P.nq) {
+        const float qm = T.qv[m];
+        b[(size_t)j * P.nq + m] = acc0[0] * qm;
+        if (LR) b[(size_t)j2 * P.nq + m] = acc1[0] * qm;
     }
 }
 
 // ---------------------------------------------------------------------------
 // forward: one wave per output group (the four mirror pixels (+-x', +-y') with
-// LR, else the two pixels (x', +-y')) and q chunk; the block's waves share a
-// 64-voxel tile of f in LDS; blockIdx.y splits the voxel groups.
-// List entry (32 B): {kappa lo, kappa hi, k0, k1}, {k2, k3, row0 offset, row1 offset}:
-// outputs O0, O1 take k0, k1 times Phi f[row0]; O2, O3 take k2, k3 times Phi f[row1].
+// LR, else the two pixels (x', +-y')) and q chunk; lane = voxel group (64 per
+// batch) evaluating both mirror classes; the block's 8 waves share a q-major
+// tile of q f for the batch's voxels; blockIdx.y splits the voxel groups.
 // ---------------------------------------------------------------------------
-template <int TD, int LR, int SLOTS>
+template <int TD, int LR, int QW>
 __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
+                                                 const double *__restrict__ qa,
+                                                 const double2 *__restrict__ qblk,
                                                  const float *__restrict__ f,
                                                  float *__restrict__ part, int groups_per_split)
 {
-    constexpr int QW = 64 / SLOTS;
-    constexpr int STEP = SLOTS * UNROLL;
-    constexpr int GB = LR ? 32 : 64;       // voxel groups per batch (64 voxels, 64 classes)
+    constexpr int NB = QW / 8;
+    constexpr int RPG = LR ? 2 : 1;             // voxel rows per group
+    constexpr int ROWS = 64 * RPG;              // tile rows per batch
+    constexpr int TS = ROWS + 2;                // tile stride per q (floats), keeps 8-byte alignment
+    constexpr int RSTEP = 512 / QW;             // rows staged per pass
+    constexpr int NPASS = ROWS / RSTEP;
     extern __shared__ __align__(16) unsigned char lds[];
     float *s_phi = (float *)(lds + L.phi);
     uint16_t *s_phi16 = (uint16_t *)(lds + L.phi);
     uint32_t *s_bits = (uint32_t *)(lds + L.mask);
     float *s_tile = (float *)(lds + L.tile);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    float4 *s_list = (float4 *)(lds + L.list) + wv * (2 * LIST_CAP);
 
     stage_tables<TD>(P, T, s_phi, s_phi16, s_bits);
 
-    const int quad = blockIdx.x * (blockDim.x >> 6) + wv;
+    const int quad = blockIdx.x * 8 + wv;       // 8 waves per block
     const bool wave_on = quad < P.n_quad;
     const int qq = wave_on ? quad : 0;
     int a, bu;
@@ -317,58 +374,87 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
     }
     const float xpa = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
     const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
-    const int slot = lane / QW, ml = lane % QW;
     const int qc = blockIdx.z;
-    const int mq = qc * QW + ml;
-    const double qa = T.qa[mq], qb = T.qb[mq];
+    const int m0 = qc * QW;
+    const double *qa_c = qa + m0;
+    const double2 *qb_c = qblk + qc * NB;
+    const double b0 = P.b0;
+    const uint32_t top = (uint32_t)(P.ne + 1);
     const int g0 = blockIdx.y * groups_per_split;
     const int g1 = min(P.n_groups, g0 + groups_per_split);
 
-    float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
-    for (int gb = g0; gb < g1; gb += GB) {
-        __syncthreads();
-        // stage 64 voxel rows x QW q of f; with LR row 2k = left voxel of group
-        // gb+k and row 2k+1 its mirror
-        for (int idx = threadIdx.x; idx < 64 * QW; idx += blockDim.x) {
-            const int r = idx / QW, mm = idx % QW;
-            int vox = -1;
-            if (LR) {
-                const int gg = gb + (r >> 1);
-                if (gg < g1) {
+    // staging of q f: thread t loads q index t % QW of rows t / QW + k * RSTEP
+    // (coalesced along q) for the next batch while the current one runs
+    const int sm = threadIdx.x % QW;
+    const int sr = threadIdx.x / QW;
+    const float qs = (m0 + sm < P.nq) ? T.qv[m0 + sm] : 0.0f;
+    float pre[NPASS];
+    auto stage_load = [&](int gb) {
+#pragma unroll
+        for (int k = 0; k < NPASS; ++k) {
+            const int r = sr + k * RSTEP;
+            const int gg = gb + r / RPG;
+            float v = 0.0f;
+            if (gg < g1 && m0 + sm < P.nq) {
+                int vox;
+                if (LR) {
                     const int half = P.nx / 2;
                     const int iz = gg / half, ix = gg % half;
                     vox = iz * P.nx + ((r & 1) ? (P.nx - 1 - ix) : ix);
+                } else {
+                    vox = gg;
                 }
-            } else {
-                const int gg = gb + r;
-                if (gg < g1) vox = gg;
+                v = qs * f[(size_t)vox * P.nq + m0 + sm];
             }
-            const int m = qc * QW + mm;
-            s_tile[idx] = (vox >= 0 && m < P.nq) ? f[(size_t)vox * P.nq + m] : 0.0f;
+            pre[k] = v;
         }
+    };
+    // voxel records of the lane's group, prefetched one batch ahead
+    VoxD nvd = {0.0, 1.0, 1.0, 0.0};
+    float2 nvf = {0.0f, 0.0f}, nvm = {0.0f, 0.0f};
+    auto load_vox = [&](int gb) {
+        const int g = gb + lane;
+        if (g < g1) {
+            int j;
+            if (LR) {
+                const int half = P.nx / 2;
+                j = (g / half) * P.nx + g % half;
+            } else {
+                j = g;
+            }
+            nvd = T.vd[j];
+            nvf = T.vf[j];
+            nvm = T.vm[j];
+        }
+    };
+    if (g0 < g1) {
+        stage_load(g0);
+        load_vox(g0);
+    }
+
+    float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
+    for (int gb = g0; gb < g1; gb += 64) {
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPASS; ++k) s_tile[sm * TS + sr + k * RSTEP] = pre[k];
+        __syncthreads();
+        const VoxD vd = nvd;
+        const float2 vf = nvf, vm = nvm;
+        if (gb + 64 < g1) {
+            stage_load(gb + 64);
+            load_vox(gb + 64);
+        }
         if (!wave_on) continue;
 
-        // one class per lane
-        double kap = 0.0;
-        float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f, k3 = 0.0f;
-        int r0 = 0, r1 = 0;
-        bool act = false;
-        {
-            const int gg = LR ? (lane >> 1) : lane;
-            const int g = gb + gg;
-            if (g < g1) {
-                const int G = LR ? (lane & 1) : 0;   // 0: pixel column a, 1: mirror column
-                int j;
-                if (LR) {
-                    const int half = P.nx / 2;
-                    j = (g / half) * P.nx + g % half;
-                } else {
-                    j = g;
-                }
-                const float xp = G ? -xpa : xpa;
-                const float2 vm = T.vm[j];
-                const Cells c = mask_cells(P, vm, xp, yp);
+        // the lane's two classes: pixel column a (class 1) and its mirror (class 2)
+        const bool valid = gb + lane < g1;
+        double k1 = 0.0, k2 = 0.0;
+        float c10 = 0.0f, c11 = 0.0f, c12 = 0.0f, c13 = 0.0f;
+        float c20 = 0.0f, c21 = 0.0f, c22 = 0.0f, c23 = 0.0f;
+        bool act1 = false, act2 = false;
+        if (valid) {
+            {
+                const Cells c = mask_cells(P, vm, xpa, yp);
                 float tau = 0.0f, tad = 0.0f, tbu = 0.0f, tbd = 0.0f;
                 if (c.in_rows) {
                     const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
@@ -380,79 +466,96 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
                     }
                 }
                 if (tau + tad + tbu + tbd != 0.0f) {
+                    double k;
                     float A;
-                    pair_factors(P, T.vd[j], T.vf[j], (double)xp, (double)yp, kap, A);
-                    if (in_band(P, kap)) {
-                        act = true;
-                        const int rowA = LR ? 2 * gg : gg, rowB = 2 * gg + 1;
-                        if (G == 0) {
-                            k0 = A * tau; k1 = A * tad; k2 = A * tbu; k3 = A * tbd;
-                            r0 = rowA; r1 = rowB;
-                        } else {
-                            k0 = A * tbu; k1 = A * tbd; k2 = A * tau; k3 = A * tad;
-                            r0 = rowB; r1 = rowA;
-                        }
-                        if (!LR) r1 = r0;
+                    pair_factors(P, vd, vf, (double)xpa, (double)yp, k, A);
+                    if (in_band(P, k)) {
+                        act1 = true;
+                        k1 = k;
+                        // O0, O1 <- voxel j (column a); O2, O3 <- mirror voxel (column -a)
+                        c10 = A * tau; c11 = A * tad; c12 = A * tbu; c13 = A * tbd;
+                    }
+                }
+            }
+            if (LR) {
+                const Cells c = mask_cells(P, vm, -xpa, yp);
+                float tau = 0.0f, tad = 0.0f, tbu = 0.0f, tbd = 0.0f;
+                if (c.in_rows) {
+                    const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
+                    tau = bitf(ru, c.col_a);
+                    tad = bitf(rd, c.col_a);
+                    tbu = bitf(ru, c.col_b);
+                    tbd = bitf(rd, c.col_b);
+                }
+                if (tau + tad + tbu + tbd != 0.0f) {
+                    double k;
+                    float A;
+                    pair_factors(P, vd, vf, -(double)xpa, (double)yp, k, A);
+                    if (in_band(P, k)) {
+                        act2 = true;
+                        k2 = k;
+                        // O0, O1 <- mirror voxel (column a); O2, O3 <- voxel j (column -a)
+                        c20 = A * tbu; c21 = A * tbd; c22 = A * tau; c23 = A * tad;
                     }
                 }
             }
         }
-        const uint64_t bal = __ballot(act);
-        const int nact = __popcll(bal);
-        const int idx = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        if (act) {
-            s_list[2 * idx] = make_float4(dlo(kap), dhi(kap), k0, k1);
-            s_list[2 * idx + 1] = make_float4(k2, k3, __int_as_float(r0 * QW * 4), __int_as_float(r1 * QW * 4));
-        }
-        const int npad = (nact + STEP - 1) / STEP * STEP;
-        if (lane < npad - nact) {
-            s_list[2 * (nact + lane)] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            s_list[2 * (nact + lane) + 1] = make_float4(0.0f, 0.0f, __int_as_float(0), __int_as_float(0));
-        }
-        __builtin_amdgcn_wave_barrier();
-        const unsigned char *tile_lane = (const unsigned char *)s_tile + ml * 4;
-        for (int i = 0; i < npad; i += STEP) {
+        if (__ballot(act1 || act2) == 0) continue;
+        float w1a = 0.0f, w1b = 0.0f, w2a = 0.0f, w2b = 0.0f;
+        const float *trow = s_tile + lane * RPG;
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const int e = i + u * SLOTS + slot;
-                const float4 e0 = s_list[2 * e];
-                const float4 e1 = s_list[2 * e + 1];
-                const int k = spec_index(P, as_double(e0.x, e0.y), qa, qb);
-                const float ph = spec<TD>(s_phi, s_phi16, k);
-                const float w0 = ph * *(const float *)(tile_lane + __float_as_int(e1.z));
-                o0 = fmaf(e0.z, w0, o0);
-                o1 = fmaf(e0.w, w0, o1);
+        for (int blk = 0; blk < NB; ++blk) {
+            const double2 qr = qb_c[blk];
+            const bool need = (act1 && k1 * qr.y >= P.band_lo && k1 * qr.x < P.band_hi) ||
+                              (act2 && k2 * qr.y >= P.band_lo && k2 * qr.x < P.band_hi);
+            if (__ballot(need) == 0) continue;
+#pragma unroll
+            for (int mm = 0; mm < 8; ++mm) {
+                const int m = blk * 8 + mm;
+                const double am = qa_c[m];
+                const float p1 = spec<TD>(s_phi, s_phi16, spec_index(k1, am, b0, top));
                 if (LR) {
-                    const float w1 = ph * *(const float *)(tile_lane + __float_as_int(e1.w));
-                    o2 = fmaf(e1.x, w1, o2);
-                    o3 = fmaf(e1.y, w1, o3);
+                    const float p2 = spec<TD>(s_phi, s_phi16, spec_index(k2, am, b0, top));
+                    const float2 fv = *(const float2 *)(trow + m * TS);
+                    w1a = fmaf(p1, fv.x, w1a);
+                    w1b = fmaf(p1, fv.y, w1b);
+                    w2a = fmaf(p2, fv.x, w2a);
+                    w2b = fmaf(p2, fv.y, w2b);
+                } else {
+                    w1a = fmaf(p1, trow[m * TS], w1a);
                 }
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        o0 = fmaf(c10, w1a, o0);
+        o1 = fmaf(c11, w1a, o1);
+        if (LR) {
+            o2 = fmaf(c12, w1b, o2);
+            o3 = fmaf(c13, w1b, o3);
+            o0 = fmaf(c20, w2b, o0);
+            o1 = fmaf(c21, w2b, o1);
+            o2 = fmaf(c22, w2a, o2);
+            o3 = fmaf(c23, w2a, o3);
+        }
     }
     if (!wave_on) return;
-    const float qm = T.qv[mq];
-    float v0 = o0 * qm, v1 = o1 * qm, v2 = o2 * qm, v3 = o3 * qm;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        v0 += __shfl_xor(v0, off, 64);
-        v1 += __shfl_xor(v1, off, 64);
+        o0 += __shfl_xor(o0, off, 64);
+        o1 += __shfl_xor(o1, off, 64);
         if (LR) {
-            v2 += __shfl_xor(v2, off, 64);
-            v3 += __shfl_xor(v3, off, 64);
+            o2 += __shfl_xor(o2, off, 64);
+            o3 += __shfl_xor(o3, off, 64);
         }
     }
     if (lane == 0) {
         float *dst = part + (size_t)(blockIdx.y * gridDim.z + qc) * P.npix;
         const int bd = P.ndy - 1 - bu;
-        dst[bu * P.ndx + a] = v0;
-        dst[bd * P.ndx + a] = v1;
+        dst[bu * P.ndx + a] = o0;
+        dst[bd * P.ndx + a] = o1;
         if (LR) {
             const int ab = P.ndx - 1 - a;
-            dst[bu * P.ndx + ab] = v2;
-            dst[bd * P.ndx + ab] = v3;
+            dst[bu * P.ndx + ab] = o2;
+            dst[bd * P.ndx + ab] = o3;
         }
     }
 }
@@ -468,7 +571,7 @@ __global__ void __launch_bounds__(256) k_sum_parts(const float *__restrict__ par
     g[i] = s;
 }
 
-Lds lds_layout(const KParams &P, int td, int wpb, bool forward)
+Lds lds_layout(const KParams &P, int td, bool forward)
 {
     auto al = [](int v) { return (v + 15) & ~15; };
     Lds L;
@@ -477,36 +580,36 @@ Lds lds_layout(const KParams &P, int td, int wpb, bool forward)
     off += al((P.ne + 2) * (td == CSX_TABLE_BF16 ? 2 : 4));
     L.mask = off;
     off += al(P.mask_ny * 4);
-    L.list = off;
-    off += wpb * LIST_CAP * (forward ? 32 : 16);
     L.tile = off;
-    if (forward) off += 64 * P.qw * 4;
+    if (forward) off += P.qw * (64 * (P.lr ? 2 : 1) + 2) * 4;
     L.total = off;
     return L;
 }
 
-template <int TD, int LR, int SLOTS>
+template <int TD, int LR, int QW>
 void launch_fwd_t(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
                   const float *f, int gps)
 {
-    hipLaunchKernelGGL((k_forward<TD, LR, SLOTS>), grid, block, L.total, s, h->P, h->t, L, f, h->part, gps);
+    hipLaunchKernelGGL((k_forward<TD, LR, QW>), grid, block, L.total, s, h->P, h->t, L, h->t.qa,
+                       h->t.qblk, f, h->part, gps);
 }
 
-template <int TD, int LR, int SLOTS>
+template <int TD, int LR, int QW>
 void launch_adj_t(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
                   const float *rho, float *b)
 {
-    hipLaunchKernelGGL((k_adjoint<TD, LR, SLOTS>), grid, block, L.total, s, h->P, h->t, L, rho, b);
+    hipLaunchKernelGGL((k_adjoint<TD, LR, QW>), grid, block, L.total, s, h->P, h->t, L, h->t.qa,
+                       h->t.qblk, rho, b);
 }
 
 template <int TD, int LR>
 void dispatch_fwd(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
                   const float *f, int gps)
 {
-    switch (64 / h->P.qw) {
-    case 4: launch_fwd_t<TD, LR, 4>(h, L, grid, block, s, f, gps); break;
-    case 2: launch_fwd_t<TD, LR, 2>(h, L, grid, block, s, f, gps); break;
-    default: launch_fwd_t<TD, LR, 1>(h, L, grid, block, s, f, gps); break;
+    switch (h->P.qw) {
+    case 16: launch_fwd_t<TD, LR, 16>(h, L, grid, block, s, f, gps); break;
+    case 32: launch_fwd_t<TD, LR, 32>(h, L, grid, block, s, f, gps); break;
+    default: launch_fwd_t<TD, LR, 64>(h, L, grid, block, s, f, gps); break;
     }
 }
 
@@ -514,10 +617,10 @@ template <int TD, int LR>
 void dispatch_adj(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
                   const float *rho, float *b)
 {
-    switch (64 / h->P.qw) {
-    case 4: launch_adj_t<TD, LR, 4>(h, L, grid, block, s, rho, b); break;
-    case 2: launch_adj_t<TD, LR, 2>(h, L, grid, block, s, rho, b); break;
-    default: launch_adj_t<TD, LR, 1>(h, L, grid, block, s, rho, b); break;
+    switch (h->P.qw) {
+    case 16: launch_adj_t<TD, LR, 16>(h, L, grid, block, s, rho, b); break;
+    case 32: launch_adj_t<TD, LR, 32>(h, L, grid, block, s, rho, b); break;
+    default: launch_adj_t<TD, LR, 64>(h, L, grid, block, s, rho, b); break;
     }
 }
 
@@ -540,7 +643,7 @@ void csx_choose_launch(csx_geometry *h)
     const KParams &P = h->P;
     h->fwd_wpb = 8;
     h->adj_wpb = 4;
-    const int gb = P.lr ? 32 : 64;
+    const int gb = 64;
     const int bx = (P.n_quad + h->fwd_wpb - 1) / h->fwd_wpb;
     // split the voxel groups so that a launch holds >= ~8 waves per SIMD
     const int target_waves = 8 * 4 * 256;
@@ -553,9 +656,9 @@ void csx_choose_launch(csx_geometry *h)
 csx_status csx_launch_forward(csx_geometry *h, const float *f, float *g, hipStream_t s)
 {
     const KParams &P = h->P;
-    const int wpb = h->fwd_wpb;
-    const Lds L = lds_layout(P, h->table_dtype, wpb, true);
-    const int gb = P.lr ? 32 : 64;
+    const int wpb = 8;   // the forward kernel's staging assumes 512 threads
+    const Lds L = lds_layout(P, h->table_dtype, true);
+    const int gb = 64;
     const int splits = h->fwd_splits;
     int gps = (P.n_groups + splits - 1) / splits;
     gps = (gps + gb - 1) / gb * gb;
@@ -584,7 +687,7 @@ csx_status csx_launch_adjoint(csx_geometry *h, const float *rho, float *b, hipSt
 {
     const KParams &P = h->P;
     const int wpb = h->adj_wpb;
-    const Lds L = lds_layout(P, h->table_dtype, wpb, false);
+    const Lds L = lds_layout(P, h->table_dtype, false);
     dim3 grid((P.n_groups + wpb - 1) / wpb, P.qchunks);
     dim3 block(64 * wpb);
     hipEvent_t e0 = csx_timing_event(h, 1), e1 = csx_timing_event(h, 1);

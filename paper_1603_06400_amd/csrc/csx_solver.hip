@@ -144,19 +144,43 @@ __global__ void __launch_bounds__(256) k_objective(const double *__restrict__ pa
     }
 }
 
-// sums for the uniform start: scal[0] = sum y, scal[1] = sum b1
-__global__ void __launch_bounds__(256) k_sum2(const float *__restrict__ x, int nx_,
-                                              const float *__restrict__ y, int ny_,
-                                              double *__restrict__ out)
+// sums for the uniform start: block partials of sum x and sum y over a
+// grid-stride range, then one block adds the partials in a fixed order
+// (out[0] = sum x, out[1] = sum y)
+__global__ void __launch_bounds__(256) k_sum2_part(const float *__restrict__ x, int nx_,
+                                                   const float *__restrict__ y, int ny_,
+                                                   double *__restrict__ part)
 {
     __shared__ double s_red[4];
     double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nx_; k += blockDim.x) a += x[k];
-    for (int k = threadIdx.x; k < ny_; k += blockDim.x) b += y[k];
+    const int stride = gridDim.x * blockDim.x;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nx_; k += stride) a += x[k];
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ny_; k += stride) b += y[k];
     const double ta = block_sum_d(a, s_red);
     __syncthreads();
     const double tb = block_sum_d(b, s_red);
-    if (threadIdx.x == 0) { out[0] = ta; out[1] = tb; }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ta;
+        part[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sum2_final(const double *__restrict__ part, int nb,
+                                                    double *__restrict__ out)
+{
+    __shared__ double s_red[4];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    const double ta = block_sum_d(a, s_red);
+    __syncthreads();
+    const double tb = block_sum_d(b, s_red);
+    if (threadIdx.x == 0) {
+        out[0] = ta;
+        out[1] = tb;
+    }
 }
 
 __global__ void k_fill_ratio(float *__restrict__ f, int n, const double *__restrict__ scal)
@@ -211,7 +235,9 @@ csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, hipStre
 csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, hipStream_t s)
 {
     const int n = h->P.nvox * h->P.nq;
-    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, y, h->P.npix, h->b1, n, h->scal);
+    const int nb = CSX_SUM_BLOCKS;
+    hipLaunchKernelGGL(k_sum2_part, dim3(nb), dim3(256), 0, s, y, h->P.npix, h->b1, n, h->partS);
+    hipLaunchKernelGGL(k_sum2_final, dim3(1), dim3(256), 0, s, h->partS, nb, h->scal);
     hipLaunchKernelGGL(k_fill_ratio, dim3((n + 255) / 256), dim3(256), 0, s, f, n, h->scal);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
