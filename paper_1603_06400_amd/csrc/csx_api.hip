@@ -167,6 +167,7 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     P.band_lo = d->e_lo - 1e-9 * std::fabs(d->e_lo) - 1e-300;
     P.band_hi = d->e_hi + 1e-9 * std::fabs(d->e_hi);
     P.half_my = (float)(0.5 * d->mask_ny);
+    P.inv_mask_nx = (float)(1.0 / d->mask_nx);
 
     // per-voxel tables; with the x -> -x mirror the coordinates are mirrored
     // exactly (x of column nx-1-i is -x of column i)
@@ -187,8 +188,18 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
             vm[j] = make_float2((float)(t / d->mask_pitch), (float)((1.0 - t) * x / d->mask_pitch));
             vd[j] = VoxD{x, z, R2, 0.0};
         }
-    const int nqp = P.qchunks * P.qw;
+    const int nqp = ((d->nq + 63) / 64) * 64;   // padded for any chunk width dividing 64
     P.b0 = 1.0 - d->e_lo / dE;
+    // uniform q grid: q_m = q_0 + m dq to 1e-12 relative (then q/dE = a0 + m da)
+    {
+        const double dq = d->nq > 1 ? (d->q[d->nq - 1] - d->q[0]) / (d->nq - 1) : 0.0;
+        bool uni = d->nq > 1 && dq > 0.0;
+        for (int m = 0; m < d->nq && uni; ++m)
+            uni = std::fabs(d->q[m] - (d->q[0] + m * dq)) <= 1e-12 * qmax;
+        P.qu = uni ? 1 : 0;
+        P.a0 = d->q[0] / dE;
+        P.da = dq / dE;
+    }
     std::vector<double> qa(nqp, 0.0);
     std::vector<float> qv(nqp, 0.0f);
     for (int m = 0; m < d->nq; ++m) {

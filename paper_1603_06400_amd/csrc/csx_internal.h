@@ -36,8 +36,11 @@ struct KParams {
     double hc, det_zd, pitchd;
     double band_lo, band_hi;    // class in band iff kappa q_max >= band_lo and kappa q_min < band_hi
     double b0;                  // 1 - e_lo/dE: table index = floor(kappa q/dE + b0)
+    int qu;                     // 1: uniform q grid q_m = q_0 + m dq
+    double a0, da;              // q_0/dE and dq/dE of a uniform grid
     double q_min, q_max;
     float half_my;
+    float inv_mask_nx;          // 1 / mask_nx
 };
 
 // Per-voxel records.  vf: {C*Gso, det_z - z} (float32); vm: {t/pm,

@@ -156,15 +156,24 @@ struct Cells {
     bool in_rows;
 };
 
+// v mod P for an integer-valued float v (|v| < 2^22): the quotient is taken at
+// v/P + 1/(2P), half a step away from any integer, so the float rounding of
+// 1/P cannot move it across one.
+__device__ __forceinline__ int fmodp(const KParams &P, float v)
+{
+    const float qf = floorf(fmaf(v, P.inv_mask_nx, 0.5f * P.inv_mask_nx));
+    return (int)fmaf(-(float)P.mask_nx, qf, v);
+}
+
 __device__ __forceinline__ Cells mask_cells(const KParams &P, float2 vm, float xp, float yp)
 {
     Cells c;
-    const int cx = (int)floorf(fmaf(vm.x, xp, vm.y));
+    const float cx = floorf(fmaf(vm.x, xp, vm.y));
     const int cy = (int)floorf(fmaf(vm.x, yp, P.half_my));
-    c.col_a = posmod(cx, P.mask_nx);
-    c.col_b = posmod(-cx - 1, P.mask_nx);   // floor(-px) = -floor(px) - 1 off the cell edges
+    c.col_a = fmodp(P, cx);
+    c.col_b = fmodp(P, -cx - 1.0f);          // floor(-px) = -floor(px) - 1 off the cell edges
     c.row_u = cy;
-    c.row_d = P.mask_ny - 1 - cy;           // floor(My - v) = My - 1 - floor(v)
+    c.row_d = P.mask_ny - 1 - cy;            // floor(My - v) = My - 1 - floor(v)
     c.in_rows = cy >= 0 && cy < P.mask_ny;
     return c;
 }
@@ -201,6 +210,35 @@ struct WaveTransposeSum {
     }
 };
 
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Bin coordinate of q node m on a uniform q grid: u_m = u0 + m du with
+// u0 = kappa q_0/dE + 1 - e_lo/dE and du = kappa dq/dE (one FP64 FMA per node).
+// Nodes whose energy can be in band satisfy 1 <= u_m < ne + 1; the returned
+// range [lo, hi] (chunk-local, widened by one node each side) contains them.
+__device__ __forceinline__ void band_range(const KParams &P, double u0, double du, int m0, int qw,
+                                           int &lo, int &hi)
+{
+    const float fu0 = (float)u0, fdu = (float)du;
+    const float a = (1.0f - fu0) / fdu, b = ((float)P.ne + 1.0f - fu0) / fdu;
+    const float l = fmaxf(floorf(a) - 1.0f - (float)m0, -1.0f);
+    const float h = fminf(floorf(b) + 1.0f - (float)m0, (float)qw);
+    lo = (int)l;
+    hi = (int)h;
+}
+
 template <int QW>
 __device__ __forceinline__ int transposed_index(int lane)
 {
@@ -211,7 +249,7 @@ __device__ __forceinline__ int transposed_index(int lane)
 // adjoint: one wave per voxel group (voxel j, and its mirror j2 with LR) and
 // q chunk; lanes = pixel classes (a, b_up), b_up in the upper half, 64 per batch.
 // ---------------------------------------------------------------------------
-template <int TD, int LR, int QW>
+template <int TD, int LR, int QW, int QU>
 __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
                                                  const double *__restrict__ qa,
                                                  const double2 *__restrict__ qblk,
@@ -256,13 +294,19 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
         acc1[m] = 0.0f;
     }
 
-    // detector values of the lane's class, prefetched one batch ahead
+    // pixel classes in 8 x 8 tiles (columns a, upper rows bu): neighbouring
+    // pixels have close scatter angles, so the q-block skip is tighter
+    const int half_y = P.ndy / 2;
+    const int ntx = (P.ndx + 7) / 8;
+    const int ntiles = ntx * ((half_y + 7) / 8);
+    const int lx = lane & 7, ly = lane >> 3;
+    // detector values of the lane's class, prefetched one tile ahead
     float r_u = 0.0f, r_d = 0.0f, r_bu = 0.0f, r_bd = 0.0f;
-    auto load_rho = [&](int pb) {
-        const int p = pb + lane;
-        if (p < P.n_cls) {
-            const int a = p % P.ndx;
-            const int bu = P.ndy / 2 + p / P.ndx;
+    auto load_rho = [&](int t) {
+        const int a = (t % ntx) * 8 + lx;
+        const int r = (t / ntx) * 8 + ly;
+        if (a < P.ndx && r < half_y) {
+            const int bu = half_y + r;
             const int bd = P.ndy - 1 - bu;
             r_u = rho[bu * P.ndx + a];
             r_d = rho[bd * P.ndx + a];
@@ -275,14 +319,14 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
     };
     load_rho(0);
 
-    for (int pb = 0; pb < P.n_cls; pb += 64) {
-        const int p = pb + lane;
+    for (int t = 0; t < ntiles; ++t) {
+        const int a = (t % ntx) * 8 + lx;
+        const int r = (t / ntx) * 8 + ly;
         double kap = 0.0;
         float c0 = 0.0f, c1 = 0.0f;
         bool act = false;
-        if (p < P.n_cls) {
-            const int a = p % P.ndx;
-            const int bu = P.ndy / 2 + p / P.ndx;
+        if (a < P.ndx && r < half_y) {
+            const int bu = half_y + r;
             const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
             const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
             const Cells c = mask_cells(P, vm, xp, yp);
@@ -304,19 +348,39 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
                 }
             }
         }
-        if (pb + 64 < P.n_cls) load_rho(pb + 64);
+        if (t + 1 < ntiles) load_rho(t + 1);
         if (__ballot(act) == 0) continue;
+        if (QU) {
+            // uniform q grid: u_m = u0 + m du, in-band nodes in the wave's range
+            const double u0 = fma(kap, P.a0 + P.da * m0, b0), du = kap * P.da;
+            int lo = QW, hi = -1;
+            if (act) band_range(P, u0, du, 0, QW, lo, hi);
+            const int wlo = wave_min(lo), whi = wave_max(hi);
 #pragma unroll
-        for (int blk = 0; blk < NB; ++blk) {
-            const double2 qr = qb_c[blk];
-            const bool need = act && kap * qr.y >= P.band_lo && kap * qr.x < P.band_hi;
-            if (__ballot(need) == 0) continue;
+            for (int blk = 0; blk < NB; ++blk) {
+                if (blk * 8 + 7 < wlo || blk * 8 > whi) continue;
 #pragma unroll
-            for (int mm = 0; mm < 8; ++mm) {
-                const int m = blk * 8 + mm;
-                const float ph = spec<TD>(s_phi, s_phi16, spec_index(kap, qa_c[m], b0, top));
-                acc0[m] = fmaf(c0, ph, acc0[m]);
-                if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
+                for (int mm = 0; mm < 8; ++mm) {
+                    const int m = blk * 8 + mm;
+                    const uint32_t kk = min((uint32_t)(int)fma((double)m, du, u0), top);
+                    const float ph = spec<TD>(s_phi, s_phi16, kk);
+                    acc0[m] = fmaf(c0, ph, acc0[m]);
+                    if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int blk = 0; blk < NB; ++blk) {
+                const double2 qr = qb_c[blk];
+                const bool need = act && kap * qr.y >= P.band_lo && kap * qr.x < P.band_hi;
+                if (__ballot(need) == 0) continue;
+#pragma unroll
+                for (int mm = 0; mm < 8; ++mm) {
+                    const int m = blk * 8 + mm;
+                    const float ph = spec<TD>(s_phi, s_phi16, spec_index(kap, qa_c[m], b0, top));
+                    acc0[m] = fmaf(c0, ph, acc0[m]);
+                    if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
+                }
             }
         }
     }
@@ -338,12 +402,12 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
 // batch) evaluating both mirror classes; the block's 8 waves share a q-major
 // tile of q f for the batch's voxels; blockIdx.y splits the voxel groups.
 // ---------------------------------------------------------------------------
-template <int TD, int LR, int QW>
+template <int TD, int LR, int QW, int QU>
 __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
                                                  const double *__restrict__ qa,
                                                  const double2 *__restrict__ qblk,
                                                  const float *__restrict__ f,
-                                                 float *__restrict__ part, int groups_per_split)
+                                                 float *__restrict__ part, int tiles_per_split)
 {
     constexpr int NB = QW / 8;
     constexpr int RPG = LR ? 2 : 1;             // voxel rows per group
@@ -380,74 +444,71 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
     const double2 *qb_c = qblk + qc * NB;
     const double b0 = P.b0;
     const uint32_t top = (uint32_t)(P.ne + 1);
-    const int g0 = blockIdx.y * groups_per_split;
-    const int g1 = min(P.n_groups, g0 + groups_per_split);
+    // voxel groups in 8 x 8 tiles (ix over the group columns, iz); blockIdx.y
+    // takes a contiguous range of tiles
+    const int gw = LR ? P.nx / 2 : P.nx;       // group columns
+    const int ntx = (gw + 7) / 8;
+    const int ntiles = ntx * ((P.nz + 7) / 8);
+    const int t0 = blockIdx.y * tiles_per_split;
+    const int t1 = min(ntiles, t0 + tiles_per_split);
 
-    // staging of q f: thread t loads q index t % QW of rows t / QW + k * RSTEP
-    // (coalesced along q) for the next batch while the current one runs
+    // staging of q f: thread t loads q index t % QW of tile rows t / QW + k * RSTEP
+    // (coalesced along q) for the next tile while the current one runs; tile
+    // row r holds group r / RPG (lane index), voxel j (r even) or its mirror
     const int sm = threadIdx.x % QW;
     const int sr = threadIdx.x / QW;
     const float qs = (m0 + sm < P.nq) ? T.qv[m0 + sm] : 0.0f;
     float pre[NPASS];
-    auto stage_load = [&](int gb) {
+    auto stage_load = [&](int t) {
+        const int tx = t % ntx, ty = t / ntx;
 #pragma unroll
         for (int k = 0; k < NPASS; ++k) {
             const int r = sr + k * RSTEP;
-            const int gg = gb + r / RPG;
+            const int gl = r / RPG;
+            const int ix = tx * 8 + (gl & 7), iz = ty * 8 + (gl >> 3);
             float v = 0.0f;
-            if (gg < g1 && m0 + sm < P.nq) {
-                int vox;
-                if (LR) {
-                    const int half = P.nx / 2;
-                    const int iz = gg / half, ix = gg % half;
-                    vox = iz * P.nx + ((r & 1) ? (P.nx - 1 - ix) : ix);
-                } else {
-                    vox = gg;
-                }
+            if (ix < gw && iz < P.nz && m0 + sm < P.nq) {
+                const int vox = iz * P.nx + ((LR && (r & 1)) ? (P.nx - 1 - ix) : ix);
                 v = qs * f[(size_t)vox * P.nq + m0 + sm];
             }
             pre[k] = v;
         }
     };
-    // voxel records of the lane's group, prefetched one batch ahead
+    // voxel records of the lane's group, prefetched one tile ahead
     VoxD nvd = {0.0, 1.0, 1.0, 0.0};
     float2 nvf = {0.0f, 0.0f}, nvm = {0.0f, 0.0f};
-    auto load_vox = [&](int gb) {
-        const int g = gb + lane;
-        if (g < g1) {
-            int j;
-            if (LR) {
-                const int half = P.nx / 2;
-                j = (g / half) * P.nx + g % half;
-            } else {
-                j = g;
-            }
+    bool nvalid = false;
+    auto load_vox = [&](int t) {
+        const int ix = (t % ntx) * 8 + (lane & 7), iz = (t / ntx) * 8 + (lane >> 3);
+        nvalid = ix < gw && iz < P.nz;
+        if (nvalid) {
+            const int j = iz * P.nx + ix;
             nvd = T.vd[j];
             nvf = T.vf[j];
             nvm = T.vm[j];
         }
     };
-    if (g0 < g1) {
-        stage_load(g0);
-        load_vox(g0);
+    if (t0 < t1) {
+        stage_load(t0);
+        load_vox(t0);
     }
 
     float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
-    for (int gb = g0; gb < g1; gb += 64) {
+    for (int t = t0; t < t1; ++t) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NPASS; ++k) s_tile[sm * TS + sr + k * RSTEP] = pre[k];
         __syncthreads();
         const VoxD vd = nvd;
         const float2 vf = nvf, vm = nvm;
-        if (gb + 64 < g1) {
-            stage_load(gb + 64);
-            load_vox(gb + 64);
+        const bool valid = nvalid;
+        if (t + 1 < t1) {
+            stage_load(t + 1);
+            load_vox(t + 1);
         }
         if (!wave_on) continue;
 
         // the lane's two classes: pixel column a (class 1) and its mirror (class 2)
-        const bool valid = gb + lane < g1;
         double k1 = 0.0, k2 = 0.0;
         float c10 = 0.0f, c11 = 0.0f, c12 = 0.0f, c13 = 0.0f;
         float c20 = 0.0f, c21 = 0.0f, c22 = 0.0f, c23 = 0.0f;
@@ -503,26 +564,60 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
         if (__ballot(act1 || act2) == 0) continue;
         float w1a = 0.0f, w1b = 0.0f, w2a = 0.0f, w2b = 0.0f;
         const float *trow = s_tile + lane * RPG;
+        if (QU) {
+            const double qa0 = P.a0 + P.da * m0;
+            const double u10 = fma(k1, qa0, b0), du1 = k1 * P.da;
+            const double u20 = fma(k2, qa0, b0), du2 = k2 * P.da;
+            int lo = QW, hi = -1;
+            if (act1) band_range(P, u10, du1, 0, QW, lo, hi);
+            if (LR && act2) {
+                int l2, h2;
+                band_range(P, u20, du2, 0, QW, l2, h2);
+                lo = min(lo, l2);
+                hi = max(hi, h2);
+            }
+            const int wlo = wave_min(lo), whi = wave_max(hi);
 #pragma unroll
-        for (int blk = 0; blk < NB; ++blk) {
-            const double2 qr = qb_c[blk];
-            const bool need = (act1 && k1 * qr.y >= P.band_lo && k1 * qr.x < P.band_hi) ||
-                              (act2 && k2 * qr.y >= P.band_lo && k2 * qr.x < P.band_hi);
-            if (__ballot(need) == 0) continue;
+            for (int blk = 0; blk < NB; ++blk) {
+                if (blk * 8 + 7 < wlo || blk * 8 > whi) continue;
 #pragma unroll
-            for (int mm = 0; mm < 8; ++mm) {
-                const int m = blk * 8 + mm;
-                const double am = qa_c[m];
-                const float p1 = spec<TD>(s_phi, s_phi16, spec_index(k1, am, b0, top));
-                if (LR) {
-                    const float p2 = spec<TD>(s_phi, s_phi16, spec_index(k2, am, b0, top));
-                    const float2 fv = *(const float2 *)(trow + m * TS);
-                    w1a = fmaf(p1, fv.x, w1a);
-                    w1b = fmaf(p1, fv.y, w1b);
-                    w2a = fmaf(p2, fv.x, w2a);
-                    w2b = fmaf(p2, fv.y, w2b);
-                } else {
-                    w1a = fmaf(p1, trow[m * TS], w1a);
+                for (int mm = 0; mm < 8; ++mm) {
+                    const int m = blk * 8 + mm;
+                    const float p1 = spec<TD>(s_phi, s_phi16, min((uint32_t)(int)fma((double)m, du1, u10), top));
+                    if (LR) {
+                        const float p2 = spec<TD>(s_phi, s_phi16, min((uint32_t)(int)fma((double)m, du2, u20), top));
+                        const float2 fv = *(const float2 *)(trow + m * TS);
+                        w1a = fmaf(p1, fv.x, w1a);
+                        w1b = fmaf(p1, fv.y, w1b);
+                        w2a = fmaf(p2, fv.x, w2a);
+                        w2b = fmaf(p2, fv.y, w2b);
+                    } else {
+                        w1a = fmaf(p1, trow[m * TS], w1a);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int blk = 0; blk < NB; ++blk) {
+                const double2 qr = qb_c[blk];
+                const bool need = (act1 && k1 * qr.y >= P.band_lo && k1 * qr.x < P.band_hi) ||
+                                  (act2 && k2 * qr.y >= P.band_lo && k2 * qr.x < P.band_hi);
+                if (__ballot(need) == 0) continue;
+#pragma unroll
+                for (int mm = 0; mm < 8; ++mm) {
+                    const int m = blk * 8 + mm;
+                    const double am = qa_c[m];
+                    const float p1 = spec<TD>(s_phi, s_phi16, spec_index(k1, am, b0, top));
+                    if (LR) {
+                        const float p2 = spec<TD>(s_phi, s_phi16, spec_index(k2, am, b0, top));
+                        const float2 fv = *(const float2 *)(trow + m * TS);
+                        w1a = fmaf(p1, fv.x, w1a);
+                        w1b = fmaf(p1, fv.y, w1b);
+                        w2a = fmaf(p2, fv.x, w2a);
+                        w2b = fmaf(p2, fv.y, w2b);
+                    } else {
+                        w1a = fmaf(p1, trow[m * TS], w1a);
+                    }
                 }
             }
         }
@@ -590,16 +685,24 @@ template <int TD, int LR, int QW>
 void launch_fwd_t(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
                   const float *f, int gps)
 {
-    hipLaunchKernelGGL((k_forward<TD, LR, QW>), grid, block, L.total, s, h->P, h->t, L, h->t.qa,
-                       h->t.qblk, f, h->part, gps);
+    if (h->P.qu)
+        hipLaunchKernelGGL((k_forward<TD, LR, QW, 1>), grid, block, L.total, s, h->P, h->t, L,
+                           h->t.qa, h->t.qblk, f, h->part, gps);
+    else
+        hipLaunchKernelGGL((k_forward<TD, LR, QW, 0>), grid, block, L.total, s, h->P, h->t, L,
+                           h->t.qa, h->t.qblk, f, h->part, gps);
 }
 
 template <int TD, int LR, int QW>
 void launch_adj_t(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
                   const float *rho, float *b)
 {
-    hipLaunchKernelGGL((k_adjoint<TD, LR, QW>), grid, block, L.total, s, h->P, h->t, L, h->t.qa,
-                       h->t.qblk, rho, b);
+    if (h->P.qu)
+        hipLaunchKernelGGL((k_adjoint<TD, LR, QW, 1>), grid, block, L.total, s, h->P, h->t, L,
+                           h->t.qa, h->t.qblk, rho, b);
+    else
+        hipLaunchKernelGGL((k_adjoint<TD, LR, QW, 0>), grid, block, L.total, s, h->P, h->t, L,
+                           h->t.qa, h->t.qblk, rho, b);
 }
 
 template <int TD, int LR>
@@ -638,18 +741,22 @@ hipEvent_t csx_timing_event(csx_geometry *h, int op)
     return v[h->ev_used[op]++];
 }
 
+static int fwd_tiles(const KParams &P)
+{
+    const int gw = P.lr ? P.nx / 2 : P.nx;
+    return ((gw + 7) / 8) * ((P.nz + 7) / 8);
+}
+
 void csx_choose_launch(csx_geometry *h)
 {
     const KParams &P = h->P;
     h->fwd_wpb = 8;
     h->adj_wpb = 4;
-    const int gb = 64;
     const int bx = (P.n_quad + h->fwd_wpb - 1) / h->fwd_wpb;
-    // split the voxel groups so that a launch holds >= ~8 waves per SIMD
+    // split the voxel tiles so that a launch holds >= ~8 waves per SIMD
     const int target_waves = 8 * 4 * 256;
     int splits = std::max(1, target_waves / std::max(1, bx * h->fwd_wpb * P.qchunks));
-    const int batches = (P.n_groups + gb - 1) / gb;
-    splits = std::min(splits, std::max(1, batches / 2));
+    splits = std::min(splits, std::max(1, fwd_tiles(P) / 2));
     h->fwd_splits = splits;
 }
 
@@ -658,11 +765,10 @@ csx_status csx_launch_forward(csx_geometry *h, const float *f, float *g, hipStre
     const KParams &P = h->P;
     const int wpb = 8;   // the forward kernel's staging assumes 512 threads
     const Lds L = lds_layout(P, h->table_dtype, true);
-    const int gb = 64;
     const int splits = h->fwd_splits;
-    int gps = (P.n_groups + splits - 1) / splits;
-    gps = (gps + gb - 1) / gb * gb;
-    const int nsplit = (P.n_groups + gps - 1) / gps;
+    const int ntiles = fwd_tiles(P);
+    const int gps = (ntiles + splits - 1) / splits;
+    const int nsplit = (ntiles + gps - 1) / gps;
     dim3 grid((P.n_quad + wpb - 1) / wpb, nsplit, P.qchunks);
     dim3 block(64 * wpb);
     hipEvent_t e0 = csx_timing_event(h, 0), e1 = csx_timing_event(h, 0);

@@ -74,6 +74,25 @@ def test_forward_adjoint_mirror_path(oracle_mod, case):
     assert_parity(host(geo.backproject(dev(y))), o.adjoint(y), what="adjoint")
 
 
+@pytest.mark.parametrize("lr", [True, False])
+@pytest.mark.parametrize("mask_nx", [5, 32])
+def test_nonuniform_q_and_mask_period(oracle_mod, lr, mask_nx):
+    """q nodes off a uniform grid (spectrum bins from the q table) and mask
+    periods other than 16."""
+    rng = np.random.Generator(np.random.PCG64(600 + mask_nx))
+    x = (-40.0, 40.0) if lr else (-37.3, 41.1)
+    g = ragged_geometry(21, 10, 9, 12, 10, 40, 402.57, x=x, mask_nx=mask_nx)
+    g = g.with_(q=np.sort(rng.uniform(0.5, 3.5, 40)))
+    o = oracle_mod.Oracle(g)
+    assert o.margins()["mask_edge_mm"] > 1e-5
+    geo = csx.Geometry(g)
+    assert geo.info()["symmetric_lr"] == int(lr)
+    f = inputs.random_image(g, 31)
+    y = inputs.random_detector(g, 32)
+    assert_parity(host(geo.forward(dev(f))), o.forward(f), what="forward")
+    assert_parity(host(geo.backproject(dev(y))), o.adjoint(y), what="adjoint")
+
+
 @pytest.mark.parametrize("name", ["slice32"])
 def test_workload_operators(oracle_mod, name):
     w, g, f, y = workload_data(name)
