@@ -58,7 +58,7 @@ def stored_traffic(kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(g, f, y, n_pix=4096, n_vox=4096):
+def cpu_baseline(g, f, y, n_pix=12288, n_vox=12288):
     """The FP64 oracle on a bounded sample of the same workload: forward at
     n_pix sampled pixels and adjoint at n_vox sampled voxels."""
     import oracle
