@@ -43,10 +43,12 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h)
     return __uint_as_float(((uint32_t)h) << 16);
 }
 
+// The spectrum table in LDS is always float32: the bfloat16 form stores the
+// table in bfloat16 and widens it while staging (exact), so both forms share
+// one inner loop.
 template <int TD>
-__device__ __forceinline__ float spec(const float *s_phi, const uint16_t *s_phi16, uint32_t k)
+__device__ __forceinline__ float spec(const float *s_phi, const uint16_t *, uint32_t k)
 {
-    if (TD == CSX_TABLE_BF16) return bf16_to_f32(s_phi16[k]);
     return s_phi[k];
 }
 
@@ -138,7 +140,7 @@ __device__ __forceinline__ void stage_tables(const KParams &P, const DevTables &
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     if (TD == CSX_TABLE_BF16) {
-        for (int k = tid; k < P.ne + 2; k += nt) s_phi16[k] = T.phi16[k];
+        for (int k = tid; k < P.ne + 2; k += nt) s_phi[k] = bf16_to_f32(T.phi16[k]);
     } else {
         for (int k = tid; k < P.ne + 2; k += nt) s_phi[k] = T.phi32[k];
     }
@@ -672,7 +674,7 @@ Lds lds_layout(const KParams &P, int td, bool forward)
     Lds L;
     int off = 0;
     L.phi = off;
-    off += al((P.ne + 2) * (td == CSX_TABLE_BF16 ? 2 : 4));
+    off += al((P.ne + 2) * 4);
     L.mask = off;
     off += al(P.mask_ny * 4);
     L.tile = off;

@@ -1,0 +1,75 @@
+"""Precision form: spectrum table in bfloat16 (round to nearest even), mask
+exact in any format, float32 accumulation, float64 reductions and update.
+
+Parity: the GPU form matches the float64 oracle evaluated on the same
+bfloat16-rounded spectrum to rel-L2 <= 1e-5.  Its error against the exact
+float64 oracle is measured and reported for each output and mask open fraction;
+it must equal the table-rounding error of the oracle itself (to 1e-5)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1603_06400_amd import csx, inputs
+
+from .gpu_helpers import assert_parity, rel_l2, workload_data
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def test_bf16_table_slice32_full(oracle_mod):
+    w, g, f, y = workload_data("slice32")
+    phi16 = oracle_mod.bf16_round(g.phi)
+    assert not np.array_equal(phi16, g.phi)
+    o16 = oracle_mod.Oracle(g, phi=phi16)
+    o64 = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g, csx.TABLE_BF16)
+    gg = host(geo.forward(dev(f)))
+    bb = host(geo.backproject(dev(y)))
+    assert_parity(gg, o16.forward(f), what="forward vs bf16-table oracle")
+    assert_parity(bb, o16.adjoint(y), what="adjoint vs bf16-table oracle")
+    ef, eb = rel_l2(gg, o64.forward(f)), rel_l2(bb, o64.adjoint(y))
+    ef16, eb16 = rel_l2(o16.forward(f), o64.forward(f)), rel_l2(o16.adjoint(y), o64.adjoint(y))
+    print(f"slice32 bf16 tables: forward rel-L2 vs FP64 {ef:.3e} (table rounding {ef16:.3e}), "
+          f"adjoint {eb:.3e} ({eb16:.3e})")
+    assert abs(ef - ef16) <= 1e-5 and abs(eb - eb16) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["slice128", "slice128_open1", "slice128_open01"])
+def test_bf16_table_slice128_sampled(oracle_mod, name):
+    w, g, f, y = workload_data(name)
+    phi16 = oracle_mod.bf16_round(g.phi)
+    o16 = oracle_mod.Oracle(g, phi=phi16)
+    o64 = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g, csx.TABLE_BF16)
+    rng = np.random.Generator(np.random.PCG64(91))
+    pix = np.sort(rng.choice(g.npix, 128, replace=False))
+    vox = np.sort(rng.choice(g.nvox, 24, replace=False))
+    gg = host(geo.forward(dev(f))).ravel()[pix]
+    yr = inputs.random_detector(g, 5)
+    bb = host(geo.backproject(dev(yr))).reshape(g.nvox, g.nq)[vox]
+    r16f, r64f = o16.forward_pixels(f, pix), o64.forward_pixels(f, pix)
+    r16b, r64b = o16.adjoint_voxels(yr, vox), o64.adjoint_voxels(yr, vox)
+    if np.any(r16f > 0):
+        assert_parity(gg, r16f, what="forward vs bf16-table oracle")
+    assert_parity(bb, r16b, what="adjoint vs bf16-table oracle")
+    print(f"{name} bf16 tables: forward rel-L2 vs FP64 {rel_l2(gg, r64f):.3e}, "
+          f"adjoint {rel_l2(bb, r64b):.3e}")
+
+
+def test_bf16_recon_objective_in_float64(oracle_mod):
+    """The precision form's reconstruction keeps a monotone float64 objective."""
+    w, g, f, y = workload_data("slice32")
+    geo = csx.Geometry(g, csx.TABLE_BF16)
+    fd = torch.empty((g.nz, g.nx, g.nq), dtype=torch.float32, device="cuda")
+    J = geo.recon(dev(y), fd, 10, w.beta)
+    assert J.dtype == np.float64
+    assert np.all(np.diff(J) <= 1e-7 * np.abs(J[1:]))
