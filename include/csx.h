@@ -141,6 +141,45 @@ csx_status csx_recon_step(csx_geometry *h, const float *y, const float *r, float
 csx_status csx_recon(csx_geometry *h, const float *y, const float *r, float *f,
                      int init_uniform, int n_iter, double beta, double *J_hist, void *stream);
 
+/* Launch shape of a handle's operators; a tuner may change it (results do not
+ * depend on it beyond float32 summation order).
+ *   fwd_splits: the forward's voxel range is split over this many block rows
+ *               (1..64); partial images are summed in a fixed order.
+ *   fwd_qw, adj_qw: q lanes per chunk of the forward / adjoint (16, 32 or 64);
+ *               nq is covered by ceil(nq / qw) chunks. */
+typedef struct {
+    int fwd_splits;
+    int fwd_qw;
+    int adj_qw;
+} csx_launch;
+
+csx_status csx_get_launch(const csx_geometry *h, csx_launch *out);
+/* Validates the shape (CSX_EINVAL) and grows the handle's workspace if needed
+ * (synchronous). */
+csx_status csx_set_launch(csx_geometry *h, const csx_launch *lc);
+
+/* A batch of independent scans reconstructed together (the batched form).
+ * The scans may differ in every size.  Each iteration merges all scans'
+ * forward (and adjoint) work into one launch per kernel variant, largest scans
+ * first, and the whole iteration is captured once in a HIP graph and replayed.
+ * The batch keeps the handles (not owned; they must outlive it, and each may
+ * appear once: the scans use their handles' workspaces) and holds small device
+ * job tables.  csx_batch_create returns CSX_EINVAL for n < 1, a NULL handle or
+ * a repeated handle. */
+typedef struct csx_batch csx_batch;
+
+csx_status csx_batch_create(csx_geometry *const *scans, int n, csx_batch **out);
+void csx_batch_free(csx_batch *b);
+
+/* Alg. 5 for n_iter iterations on every scan k: y[k] (counts), r[k]
+ * (background or NULL; r itself may be NULL), f[k] (in/out image) are device
+ * buffers laid out as for csx_recon.  init_uniform != 0 starts each scan at
+ * its uniform image.  J_hist: NULL or host double[n][n_iter + 1].  Synchronises
+ * `stream`.  Same status conventions as csx_recon (first failing scan). */
+csx_status csx_batch_recon(csx_batch *b, const float *const *y, const float *const *r,
+                           float *const *f, int init_uniform, int n_iter, double beta,
+                           double *J_hist, void *stream);
+
 /* Kernel timing (for measurement): while enabled, every forward and adjoint
  * operator launch on this handle is bracketed by HIP events recorded on the
  * caller's stream.  csx_timing_read synchronises those events and returns the

@@ -145,6 +145,7 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     P.mask_nx = d->mask_nx;
     P.mask_ny = d->mask_ny;
     P.lr = (d->x_min == -d->x_max && d->nx % 2 == 0 && d->ndx % 2 == 0) ? 1 : 0;
+    P.td = d->table_dtype;
     P.n_groups = P.lr ? d->nz * (d->nx / 2) : P.nvox;
     P.n_cls = d->ndx * (d->ndy / 2);
     P.n_quad = P.lr ? (d->ndx / 2) * (d->ndy / 2) : d->ndx * (d->ndy / 2);
@@ -239,9 +240,10 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     CSX_TRY(dev_upload(&h->t.phi16, phi16, B));
     CSX_TRY(dev_upload(&h->t.maskbits, bits, B));
 
-    csx_choose_launch(h);
+    h->lc = csx_default_launch(P);
     const size_t nimg = (size_t)P.nvox * P.nq;
-    CSX_TRY(dev_alloc(&h->part, (size_t)h->fwd_splits * P.qchunks * P.npix, B));
+    h->part_cap = (size_t)csx_forward_shape(h).nparts * P.npix;
+    CSX_TRY(dev_alloc(&h->part, h->part_cap, B));
     CSX_TRY(dev_alloc(&h->gws, P.npix, B));
     CSX_TRY(dev_alloc(&h->rho, P.npix, B));
     CSX_TRY(dev_alloc(&h->ones, P.npix, B));
@@ -289,6 +291,36 @@ extern "C" csx_status csx_get_info(const csx_geometry *h, csx_info *out)
     return CSX_OK;
 }
 
+extern "C" csx_status csx_get_launch(const csx_geometry *h, csx_launch *out)
+{
+    if (!h || !out) return csx_fail(CSX_EINVAL, "NULL argument");
+    *out = h->lc;
+    return CSX_OK;
+}
+
+extern "C" csx_status csx_set_launch(csx_geometry *h, const csx_launch *lc)
+{
+    if (!h || !lc) return csx_fail(CSX_EINVAL, "NULL argument");
+    if (!csx_launch_valid(*lc))
+        return csx_fail(CSX_EINVAL, "launch shape: qw must be 16, 32 or 64 and 1 <= fwd_splits <= 64");
+    const csx_launch old = h->lc;
+    h->lc = *lc;
+    const size_t need = (size_t)csx_forward_shape(h).nparts * h->P.npix;
+    if (need > h->part_cap) {
+        HIP_TRY(hipDeviceSynchronize());
+        float *p = nullptr;
+        if (hipMalloc((void **)&p, need * sizeof(float)) != hipSuccess) {
+            h->lc = old;
+            return csx_fail(CSX_ENOMEM, "forward partials");
+        }
+        HIP_TRY(hipFree(h->part));
+        h->bytes += (int64_t)((need - h->part_cap) * sizeof(float));
+        h->part = p;
+        h->part_cap = need;
+    }
+    return CSX_OK;
+}
+
 extern "C" csx_status csx_timing_enable(csx_geometry *h, int on)
 {
     if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
@@ -326,7 +358,10 @@ extern "C" csx_status csx_backproject(csx_geometry *h, const float *y, float *b,
     return csx_launch_adjoint(h, y, b, (hipStream_t)stream);
 }
 
-static csx_status ensure_b1(csx_geometry *h, hipStream_t s)
+csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s);
+static csx_status ensure_b1(csx_geometry *h, hipStream_t s) { return csx_ensure_b1(h, s); }
+
+csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s)
 {
     if (h->have_b1) return CSX_OK;
     csx_status st = csx_launch_adjoint(h, h->ones, h->b1, s);
@@ -349,7 +384,7 @@ static csx_status step_impl(csx_geometry *h, const float *y, const float *r, flo
     ST_TRY(csx_launch_ratio(h, y, r, true, s));                 // rho = y / z, data-fit partials
     ST_TRY(csx_launch_adjoint(h, h->rho, h->b2, s));            // b2 = A^T rho
     ST_TRY(csx_launch_update(h, f, beta, true, s));             // f^{t+1} into ftmp, R(f^t) partials
-    if (J) ST_TRY(csx_launch_objective(h, beta, J, s));         // J(f^t)
+    if (J) ST_TRY(csx_launch_objective(h, beta, J, nullptr, s)); // J(f^t)
     return csx_launch_copy(h->ftmp, f, h->P.nvox * h->P.nq, s);
 }
 
@@ -384,7 +419,7 @@ extern "C" csx_status csx_recon(csx_geometry *h, const float *y, const float *r,
     ST_TRY(csx_launch_forward(h, f, h->gws, s));
     ST_TRY(csx_launch_ratio(h, y, r, false, s));
     ST_TRY(csx_launch_update(h, f, beta, false, s));
-    ST_TRY(csx_launch_objective(h, beta, h->jhist + n_iter, s));
+    ST_TRY(csx_launch_objective(h, beta, h->jhist + n_iter, nullptr, s));
     int flags = 0;
     HIP_TRY(hipMemcpyAsync(&flags, h->flags, sizeof(int), hipMemcpyDeviceToHost, s));
     if (J_hist)

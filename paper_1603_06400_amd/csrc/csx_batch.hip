@@ -1,0 +1,308 @@
+// csx_batch.hip -- the batched form: many independent scans (each its own
+// geometry handle, any sizes) reconstructed together by Alg. 5.
+//
+// One iteration issues, per kernel variant, a single forward launch and a
+// single adjoint launch that cover every scan's blocks (largest scans first, so
+// the small scans fill the tail), plus the per-scan float64 data-term, update
+// and objective kernels.  The iteration is captured once into a HIP graph on a
+// private stream and replayed n_iter times; the objective kernels index the
+// J history through a device iteration counter, so the replays need no host
+// work.  Nothing in the graph is a memset.
+#include "csx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s);
+
+namespace {
+
+struct Group {
+    int variant = 0;
+    int lds = 0;
+    int nblocks = 0;
+    std::vector<int> scans;        // scan indices, largest first
+    std::vector<CsxJob> jobs;      // host copy of the job table
+    std::vector<int> begin;        // first block of each job
+    CsxJob *jobs_dev = nullptr;
+    int *begin_dev = nullptr;
+};
+
+double scan_cost(const csx_geometry *h)
+{
+    return (double)h->P.nvox * (double)h->P.npix * (double)h->P.nq;
+}
+
+}  // namespace
+
+struct csx_batch {
+    std::vector<csx_geometry *> h;
+    std::vector<Group> fwd, adj;
+    hipStream_t st = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int *iter_dev = nullptr;
+    double *J_dev = nullptr;
+    size_t J_cap = 0;
+};
+
+static void free_groups(std::vector<Group> &gs)
+{
+    for (Group &g : gs) {
+        if (g.jobs_dev) (void)hipFree(g.jobs_dev);
+        if (g.begin_dev) (void)hipFree(g.begin_dev);
+        g.jobs_dev = nullptr;
+        g.begin_dev = nullptr;
+    }
+}
+
+extern "C" void csx_batch_free(csx_batch *b)
+{
+    if (!b) return;
+    free_groups(b->fwd);
+    free_groups(b->adj);
+    if (b->iter_dev) (void)hipFree(b->iter_dev);
+    if (b->J_dev) (void)hipFree(b->J_dev);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->st) (void)hipStreamDestroy(b->st);
+    delete b;
+}
+
+// Groups the scans by kernel variant of one operator and orders each group's
+// scans by decreasing work.
+static void make_groups(const std::vector<csx_geometry *> &hs, bool forward, std::vector<Group> &out)
+{
+    std::vector<int> order(hs.size());
+    for (size_t k = 0; k < hs.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return scan_cost(hs[a]) > scan_cost(hs[b]); });
+    for (int k : order) {
+        const OpShape S = forward ? csx_forward_shape(hs[k]) : csx_adjoint_shape(hs[k]);
+        Group *g = nullptr;
+        for (Group &c : out)
+            if (c.variant == S.variant) g = &c;
+        if (!g) {
+            out.emplace_back();
+            g = &out.back();
+            g->variant = S.variant;
+        }
+        g->scans.push_back(k);
+    }
+}
+
+// Rebuilds the job tables of a group for the given per-scan buffers and
+// uploads them (asynchronously on s).
+static csx_status upload_jobs(Group &g, const std::vector<csx_geometry *> &hs, bool forward,
+                              const std::vector<const float *> &in, const std::vector<float *> &out,
+                              hipStream_t s)
+{
+    g.jobs.clear();
+    g.begin.clear();
+    g.lds = 0;
+    g.nblocks = 0;
+    for (int k : g.scans) {
+        csx_geometry *h = hs[k];
+        const OpShape S = forward ? csx_forward_shape(h) : csx_adjoint_shape(h);
+        CsxJob J;
+        std::memset(&J, 0, sizeof(J));
+        J.P = S.P;
+        J.T = h->t;
+        J.L = S.L;
+        J.in = in[k];
+        J.out = forward ? h->part : out[k];
+        J.gx = (int)S.grid.x;
+        J.gy = (int)S.grid.y;
+        J.gz = (int)S.grid.z;
+        J.tps = S.tps;
+        g.begin.push_back(g.nblocks);
+        g.nblocks += J.gx * J.gy * J.gz;
+        g.lds = std::max(g.lds, S.L.total);
+        g.jobs.push_back(J);
+    }
+    if (!g.jobs_dev) {
+        HIP_TRY(hipMalloc((void **)&g.jobs_dev, sizeof(CsxJob) * g.scans.size()));
+        HIP_TRY(hipMalloc((void **)&g.begin_dev, sizeof(int) * g.scans.size()));
+    }
+    HIP_TRY(hipMemcpyAsync(g.jobs_dev, g.jobs.data(), sizeof(CsxJob) * g.jobs.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(g.begin_dev, g.begin.data(), sizeof(int) * g.begin.size(),
+                           hipMemcpyHostToDevice, s));
+    return CSX_OK;
+}
+
+static csx_status launch_group(const Group &g, bool forward, hipStream_t s)
+{
+    if (forward)
+        return csx_launch_forward_batch(g.jobs_dev, g.begin_dev, (int)g.jobs.size(), g.nblocks,
+                                        g.variant, g.lds, s);
+    return csx_launch_adjoint_batch(g.jobs_dev, g.begin_dev, (int)g.jobs.size(), g.nblocks,
+                                    g.variant, g.lds, s);
+}
+
+#define BT_TRY(expr)                 \
+    do {                             \
+        csx_status s_ = (expr);      \
+        if (s_ != CSX_OK) return s_; \
+    } while (0)
+
+extern "C" csx_status csx_batch_create(csx_geometry *const *scans, int n, csx_batch **out)
+{
+    if (!scans || !out || n < 1) return csx_fail(CSX_EINVAL, "need >= 1 scan and an out pointer");
+    *out = nullptr;
+    for (int k = 0; k < n; ++k) {
+        if (!scans[k]) return csx_fail(CSX_EINVAL, "NULL scan handle");
+        for (int j = 0; j < k; ++j)   // scans own their workspaces: no sharing
+            if (scans[j] == scans[k]) return csx_fail(CSX_EINVAL, "a handle appears twice in the batch");
+    }
+    csx_batch *b = new (std::nothrow) csx_batch();
+    if (!b) return csx_fail(CSX_ENOMEM, "host allocation failed");
+    b->h.assign(scans, scans + n);
+    auto bail = [&](csx_status st) {
+        csx_batch_free(b);
+        return st;
+    };
+    if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc((void **)&b->iter_dev, sizeof(int)) != hipSuccess)
+        return bail(csx_fail(CSX_EHIP, "batch stream / events / counter"));
+    *out = b;
+    return CSX_OK;
+}
+
+// One Alg. 5 iteration of every scan (the body that is captured).
+static csx_status issue_iteration(csx_batch *b, const float *const *y, const float *const *r,
+                                  float *const *f, double beta, size_t jstride, hipStream_t s)
+{
+    const int n = (int)b->h.size();
+    for (const Group &g : b->fwd) BT_TRY(launch_group(g, true, s));
+    for (int k = 0; k < n; ++k) {
+        csx_geometry *h = b->h[k];
+        BT_TRY(csx_launch_sum_parts(h, csx_forward_shape(h).nparts, h->gws, s));
+        BT_TRY(csx_launch_ratio(h, y[k], r ? r[k] : nullptr, true, s));
+    }
+    for (const Group &g : b->adj) BT_TRY(launch_group(g, false, s));
+    for (int k = 0; k < n; ++k) {
+        csx_geometry *h = b->h[k];
+        BT_TRY(csx_launch_update(h, f[k], beta, true, s));
+        BT_TRY(csx_launch_objective(h, beta, b->J_dev + k * jstride, b->iter_dev, s));
+        BT_TRY(csx_launch_copy(h->ftmp, f[k], h->P.nvox * h->P.nq, s));
+    }
+    return csx_launch_iter_incr(b->iter_dev, s);
+}
+
+extern "C" csx_status csx_batch_recon(csx_batch *b, const float *const *y, const float *const *r,
+                                      float *const *f, int init_uniform, int n_iter, double beta,
+                                      double *J_hist, void *stream)
+{
+    if (!b || !y || !f) return csx_fail(CSX_EINVAL, "NULL argument");
+    if (n_iter < 0) return csx_fail(CSX_EINVAL, "n_iter must be >= 0");
+    if (!(std::isfinite(beta) && beta >= 0.0)) return csx_fail(CSX_EINVAL, "beta must be finite and >= 0");
+    const int n = (int)b->h.size();
+    for (int k = 0; k < n; ++k)
+        if (!y[k] || !f[k]) return csx_fail(CSX_EINVAL, "NULL scan buffer");
+    hipStream_t cs = (hipStream_t)stream;
+    hipStream_t s = b->st;
+    // group by the handles' current launch shapes (a tuner may have changed them)
+    HIP_TRY(hipStreamSynchronize(s));
+    free_groups(b->fwd);
+    free_groups(b->adj);
+    b->fwd.clear();
+    b->adj.clear();
+    make_groups(b->h, true, b->fwd);
+    make_groups(b->h, false, b->adj);
+    HIP_TRY(hipEventRecord(b->ev_in, cs));
+    HIP_TRY(hipStreamWaitEvent(s, b->ev_in, 0));
+
+    const size_t jstride = (size_t)n_iter + 1;
+    if (b->J_cap < jstride * n) {
+        if (b->J_dev) HIP_TRY(hipFree(b->J_dev));
+        b->J_dev = nullptr;
+        b->J_cap = 0;
+        HIP_TRY(hipMalloc((void **)&b->J_dev, sizeof(double) * jstride * n));
+        b->J_cap = jstride * n;
+    }
+
+    // sensitivity images of the scans that lack one, batched
+    std::vector<const float *> in(n);
+    std::vector<float *> outp(n);
+    {
+        bool any = false;
+        for (int k = 0; k < n; ++k) any = any || !b->h[k]->have_b1;
+        if (any) {
+            for (int k = 0; k < n; ++k) {
+                in[k] = b->h[k]->ones;
+                outp[k] = b->h[k]->b1;
+            }
+            for (Group &g : b->adj) {
+                BT_TRY(upload_jobs(g, b->h, false, in, outp, s));
+                BT_TRY(launch_group(g, false, s));
+            }
+            for (int k = 0; k < n; ++k) b->h[k]->have_b1 = true;
+            HIP_TRY(hipStreamSynchronize(s));   // the job tables are rebuilt below
+        }
+    }
+    if (init_uniform)
+        for (int k = 0; k < n; ++k) BT_TRY(csx_launch_uniform_start(b->h[k], y[k], f[k], s));
+
+    // job tables of this call's buffers
+    for (int k = 0; k < n; ++k) {
+        in[k] = f[k];
+        outp[k] = nullptr;
+    }
+    for (Group &g : b->fwd) BT_TRY(upload_jobs(g, b->h, true, in, outp, s));
+    for (int k = 0; k < n; ++k) {
+        in[k] = b->h[k]->rho;
+        outp[k] = b->h[k]->b2;
+    }
+    for (Group &g : b->adj) BT_TRY(upload_jobs(g, b->h, false, in, outp, s));
+    const int zero = 0;
+    HIP_TRY(hipMemcpyAsync(b->iter_dev, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+
+    if (n_iter > 0) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        csx_status st = issue_iteration(b, y, r, f, beta, jstride, s);
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (st != CSX_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return csx_fail(CSX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return csx_fail(CSX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        for (int t = 0; t < n_iter && e == hipSuccess; ++t) e = hipGraphLaunch(exec, s);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return csx_fail(CSX_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+    }
+    // objective at the final iterates (the counter now equals n_iter)
+    for (const Group &g : b->fwd) BT_TRY(launch_group(g, true, s));
+    for (int k = 0; k < n; ++k) {
+        csx_geometry *h = b->h[k];
+        BT_TRY(csx_launch_sum_parts(h, csx_forward_shape(h).nparts, h->gws, s));
+        BT_TRY(csx_launch_ratio(h, y[k], r ? r[k] : nullptr, false, s));
+        BT_TRY(csx_launch_update(h, f[k], beta, false, s));
+        BT_TRY(csx_launch_objective(h, beta, b->J_dev + k * jstride, b->iter_dev, s));
+    }
+    std::vector<int> flags(n, 0);
+    for (int k = 0; k < n; ++k)
+        HIP_TRY(hipMemcpyAsync(&flags[k], b->h[k]->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (J_hist)
+        HIP_TRY(hipMemcpyAsync(J_hist, b->J_dev, sizeof(double) * jstride * n,
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipEventRecord(b->ev_out, s));
+    HIP_TRY(hipStreamWaitEvent(cs, b->ev_out, 0));
+    for (int k = 0; k < n; ++k) {
+        if (flags[k] & 2) return csx_fail(CSX_EINVAL, "scan " + std::to_string(k) + ": y holds negative or NaN counts");
+        if (flags[k] & 1) return csx_fail(CSX_ENUMERIC, "scan " + std::to_string(k) + ": y_i > 0 where the model mean is 0");
+    }
+    return CSX_OK;
+}

@@ -27,6 +27,7 @@ csx_status csx_fail(csx_status s, const std::string &msg);
 struct KParams {
     int nvox, npix, nx, nz, nq, ndx, ndy, ne, mask_nx, mask_ny;
     int lr;              // 1: x -> -x mirror exploited (centred grids, nx and ndx even)
+    int td;              // table dtype (CSX_TABLE_F32 / CSX_TABLE_BF16)
     int n_groups;        // voxel groups: pairs (j, mirror j) with LR, else single voxels
     int n_cls;           // pixel classes of the adjoint: ndx * ndy/2 (columns x upper rows)
     int n_quad;          // forward output groups: (ndx/2)*(ndy/2) with LR, else ndx*(ndy/2)
@@ -61,15 +62,42 @@ struct DevTables {
     uint32_t *maskbits = nullptr; // [mask_ny] bit c of row r = cell (c, r)
 };
 
+// LDS layout of an operator launch (byte offsets).
+struct Lds {
+    int phi, mask, tile, total;
+};
+
+// One scan's share of a batched operator launch (device array).
+struct CsxJob {
+    KParams P;
+    DevTables T;
+    Lds L;
+    const float *in;
+    float *out;
+    int gx, gy, gz, tps;
+};
+
+// Launch geometry of one operator for one handle.
+struct OpShape {
+    KParams P;          // with the operator's q chunk width
+    Lds L;
+    dim3 grid, block;
+    int tps;            // forward: voxel tiles per split
+    int nparts;         // forward: partial images (splits x q chunks)
+    int variant;        // kernel template: bit 1 LR, bit 2 uniform q, bits 3+ log2 qw
+};
+
 struct csx_geometry {
     csx_geometry_desc d;       // copy (array pointers not kept)
     KParams P;
     DevTables t;
     int table_dtype = CSX_TABLE_F32;
     // launch shape
-    int fwd_wpb = 8, fwd_splits = 1, adj_wpb = 4;
+    int fwd_wpb = 8, adj_wpb = 4;
+    csx_launch lc;
     // workspace
-    float *part = nullptr;     // forward partials [fwd_splits*qchunks][npix]
+    float *part = nullptr;     // forward partials [part_cap] floats
+    size_t part_cap = 0;
     float *gws = nullptr;      // [npix] model mean
     float *rho = nullptr;      // [npix] y / z
     float *ones = nullptr;     // [npix] 1
@@ -96,7 +124,15 @@ struct csx_geometry {
 // operator launchers (csx_ops.hip)
 csx_status csx_launch_forward(csx_geometry *h, const float *f, float *g, hipStream_t s);
 csx_status csx_launch_adjoint(csx_geometry *h, const float *rho, float *b, hipStream_t s);
-void csx_choose_launch(csx_geometry *h);
+csx_launch csx_default_launch(const KParams &P);
+bool csx_launch_valid(const csx_launch &lc);
+OpShape csx_forward_shape(const csx_geometry *h);
+OpShape csx_adjoint_shape(const csx_geometry *h);
+csx_status csx_launch_forward_batch(const CsxJob *jobs_dev, const int *begin_dev, int njobs,
+                                    int nblocks, int variant, int lds_bytes, hipStream_t s);
+csx_status csx_launch_adjoint_batch(const CsxJob *jobs_dev, const int *begin_dev, int njobs,
+                                    int nblocks, int variant, int lds_bytes, hipStream_t s);
+csx_status csx_launch_sum_parts(csx_geometry *h, int nparts, float *g, hipStream_t s);
 hipEvent_t csx_timing_event(csx_geometry *h, int op);
 
 // solver pieces (csx_solver.hip)
@@ -104,7 +140,9 @@ csx_status csx_launch_ratio(csx_geometry *h, const float *y, const float *r, boo
                             hipStream_t s);
 csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool do_update,
                              hipStream_t s);
-csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, hipStream_t s);
+csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, const int *iter,
+                                hipStream_t s);
+csx_status csx_launch_iter_incr(int *iter, hipStream_t s);
 csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, hipStream_t s);
 csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s);
 csx_status csx_launch_fill(float *dst, int n, float v, hipStream_t s);

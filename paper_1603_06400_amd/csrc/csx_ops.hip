@@ -46,8 +46,7 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h)
 // The spectrum table in LDS is always float32: the bfloat16 form stores the
 // table in bfloat16 and widens it while staging (exact), so both forms share
 // one inner loop.
-template <int TD>
-__device__ __forceinline__ float spec(const float *s_phi, const uint16_t *, uint32_t k)
+__device__ __forceinline__ float spec(const float *s_phi, uint32_t k)
 {
     return s_phi[k];
 }
@@ -134,22 +133,17 @@ __device__ __forceinline__ uint32_t spec_index(double kappa, double qa, double b
     return min(k, top);
 }
 
-template <int TD>
 __device__ __forceinline__ void stage_tables(const KParams &P, const DevTables &T, float *s_phi,
-                                             uint16_t *s_phi16, uint32_t *s_bits)
+                                             uint32_t *s_bits)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    if (TD == CSX_TABLE_BF16) {
+    if (P.td == CSX_TABLE_BF16) {
         for (int k = tid; k < P.ne + 2; k += nt) s_phi[k] = bf16_to_f32(T.phi16[k]);
     } else {
         for (int k = tid; k < P.ne + 2; k += nt) s_phi[k] = T.phi32[k];
     }
     for (int k = tid; k < P.mask_ny; k += nt) s_bits[k] = T.maskbits[k];
 }
-
-struct Lds {
-    int phi, mask, tile, total;
-};
 
 // Mask cells of one crossing: columns of the pixel (col_a) and of its x-mirror
 // seen from the mirror voxel (col_b), rows of y' (row_u) and -y' (row_d).
@@ -251,23 +245,22 @@ __device__ __forceinline__ int transposed_index(int lane)
 // adjoint: one wave per voxel group (voxel j, and its mirror j2 with LR) and
 // q chunk; lanes = pixel classes (a, b_up), b_up in the upper half, 64 per batch.
 // ---------------------------------------------------------------------------
-template <int TD, int LR, int QW, int QU>
-__global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
-                                                 const double *__restrict__ qa,
-                                                 const double2 *__restrict__ qblk,
-                                                 const float *__restrict__ rho,
-                                                 float *__restrict__ b)
+template <int LR, int QW, int QU>
+__device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &T, const Lds &L,
+                                             const double *__restrict__ qa,
+                                             const double2 *__restrict__ qblk,
+                                             const float *__restrict__ rho, float *__restrict__ b,
+                                             int bx, int by)
 {
     constexpr int NB = QW / 8;
     extern __shared__ __align__(16) unsigned char lds[];
     float *s_phi = (float *)(lds + L.phi);
-    uint16_t *s_phi16 = (uint16_t *)(lds + L.phi);
     uint32_t *s_bits = (uint32_t *)(lds + L.mask);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
-    stage_tables<TD>(P, T, s_phi, s_phi16, s_bits);
+    stage_tables(P, T, s_phi, s_bits);
     __syncthreads();
-    const int g = blockIdx.x * (blockDim.x >> 6) + wv;
+    const int g = bx * (blockDim.x >> 6) + wv;
     if (g >= P.n_groups) return;
 
     int j, j2;
@@ -283,9 +276,9 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
     const VoxD vd = T.vd[j];
     const float2 vf = T.vf[j];
     const float2 vm = T.vm[j];
-    const int m0 = blockIdx.y * QW;
+    const int m0 = by * QW;
     const double *qa_c = qa + m0;
-    const double2 *qb_c = qblk + blockIdx.y * NB;
+    const double2 *qb_c = qblk + by * NB;
     const double b0 = P.b0;
     const uint32_t top = (uint32_t)(P.ne + 1);
 
@@ -365,7 +358,7 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
                     const uint32_t kk = min((uint32_t)(int)fma((double)m, du, u0), top);
-                    const float ph = spec<TD>(s_phi, s_phi16, kk);
+                    const float ph = spec(s_phi, kk);
                     acc0[m] = fmaf(c0, ph, acc0[m]);
                     if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
                 }
@@ -379,7 +372,7 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
-                    const float ph = spec<TD>(s_phi, s_phi16, spec_index(kap, qa_c[m], b0, top));
+                    const float ph = spec(s_phi, spec_index(kap, qa_c[m], b0, top));
                     acc0[m] = fmaf(c0, ph, acc0[m]);
                     if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
                 }
@@ -390,6 +383,7 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
     if (LR) WaveTransposeSum<QW, 32>::run(acc1, lane);
     const int mi = transposed_index<QW>(lane);
     const int m = m0 + mi;
+    (void)qb_c;
     const bool writer = (lane & ((64 / QW) - 1)) == 0;
     if (writer && m < P.nq) {
         const float qm = T.qv[m];
@@ -404,12 +398,13 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
 // batch) evaluating both mirror classes; the block's 8 waves share a q-major
 // tile of q f for the batch's voxels; blockIdx.y splits the voxel groups.
 // ---------------------------------------------------------------------------
-template <int TD, int LR, int QW, int QU>
-__global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
-                                                 const double *__restrict__ qa,
-                                                 const double2 *__restrict__ qblk,
-                                                 const float *__restrict__ f,
-                                                 float *__restrict__ part, int tiles_per_split)
+template <int LR, int QW, int QU>
+__device__ __forceinline__ void forward_body(const KParams &P, const DevTables &T, const Lds &L,
+                                             const double *__restrict__ qa,
+                                             const double2 *__restrict__ qblk,
+                                             const float *__restrict__ f,
+                                             float *__restrict__ part, int tiles_per_split,
+                                             int bx, int by, int bz, int gz)
 {
     constexpr int NB = QW / 8;
     constexpr int RPG = LR ? 2 : 1;             // voxel rows per group
@@ -419,14 +414,13 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
     constexpr int NPASS = ROWS / RSTEP;
     extern __shared__ __align__(16) unsigned char lds[];
     float *s_phi = (float *)(lds + L.phi);
-    uint16_t *s_phi16 = (uint16_t *)(lds + L.phi);
     uint32_t *s_bits = (uint32_t *)(lds + L.mask);
     float *s_tile = (float *)(lds + L.tile);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
-    stage_tables<TD>(P, T, s_phi, s_phi16, s_bits);
+    stage_tables(P, T, s_phi, s_bits);
 
-    const int quad = blockIdx.x * 8 + wv;       // 8 waves per block
+    const int quad = bx * 8 + wv;               // 8 waves per block
     const bool wave_on = quad < P.n_quad;
     const int qq = wave_on ? quad : 0;
     int a, bu;
@@ -440,7 +434,7 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
     }
     const float xpa = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
     const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
-    const int qc = blockIdx.z;
+    const int qc = bz;
     const int m0 = qc * QW;
     const double *qa_c = qa + m0;
     const double2 *qb_c = qblk + qc * NB;
@@ -451,7 +445,7 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
     const int gw = LR ? P.nx / 2 : P.nx;       // group columns
     const int ntx = (gw + 7) / 8;
     const int ntiles = ntx * ((P.nz + 7) / 8);
-    const int t0 = blockIdx.y * tiles_per_split;
+    const int t0 = by * tiles_per_split;
     const int t1 = min(ntiles, t0 + tiles_per_split);
 
     // staging of q f: thread t loads q index t % QW of tile rows t / QW + k * RSTEP
@@ -585,9 +579,9 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
-                    const float p1 = spec<TD>(s_phi, s_phi16, min((uint32_t)(int)fma((double)m, du1, u10), top));
+                    const float p1 = spec(s_phi, min((uint32_t)(int)fma((double)m, du1, u10), top));
                     if (LR) {
-                        const float p2 = spec<TD>(s_phi, s_phi16, min((uint32_t)(int)fma((double)m, du2, u20), top));
+                        const float p2 = spec(s_phi, min((uint32_t)(int)fma((double)m, du2, u20), top));
                         const float2 fv = *(const float2 *)(trow + m * TS);
                         w1a = fmaf(p1, fv.x, w1a);
                         w1b = fmaf(p1, fv.y, w1b);
@@ -609,9 +603,9 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
                     const double am = qa_c[m];
-                    const float p1 = spec<TD>(s_phi, s_phi16, spec_index(k1, am, b0, top));
+                    const float p1 = spec(s_phi, spec_index(k1, am, b0, top));
                     if (LR) {
-                        const float p2 = spec<TD>(s_phi, s_phi16, spec_index(k2, am, b0, top));
+                        const float p2 = spec(s_phi, spec_index(k2, am, b0, top));
                         const float2 fv = *(const float2 *)(trow + m * TS);
                         w1a = fmaf(p1, fv.x, w1a);
                         w1b = fmaf(p1, fv.y, w1b);
@@ -645,7 +639,7 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
         }
     }
     if (lane == 0) {
-        float *dst = part + (size_t)(blockIdx.y * gridDim.z + qc) * P.npix;
+        float *dst = part + (size_t)(by * gz + qc) * P.npix;
         const int bd = P.ndy - 1 - bu;
         dst[bu * P.ndx + a] = o0;
         dst[bd * P.ndx + a] = o1;
@@ -655,6 +649,64 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
             dst[bd * P.ndx + ab] = o3;
         }
     }
+}
+
+template <int LR, int QW, int QU>
+__global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
+                                                 const double *__restrict__ qa,
+                                                 const double2 *__restrict__ qblk,
+                                                 const float *__restrict__ rho,
+                                                 float *__restrict__ b)
+{
+    adjoint_body<LR, QW, QU>(P, T, L, qa, qblk, rho, b, blockIdx.x, blockIdx.y);
+}
+
+template <int LR, int QW, int QU>
+__global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
+                                                 const double *__restrict__ qa,
+                                                 const double2 *__restrict__ qblk,
+                                                 const float *__restrict__ f,
+                                                 float *__restrict__ part, int tiles_per_split)
+{
+    forward_body<LR, QW, QU>(P, T, L, qa, qblk, f, part, tiles_per_split, blockIdx.x,
+                                 blockIdx.y, blockIdx.z, gridDim.z);
+}
+
+// Batched launches: the blocks of several scans in one grid.  Block b belongs
+// to the job whose [begin, begin + blocks) range holds it (binary search over
+// the sorted begin offsets); its local index is decoded into that job's grid.
+__device__ __forceinline__ int find_job(const int *__restrict__ begin, int njobs, int b)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int LR, int QW, int QU>
+__global__ void __launch_bounds__(256) k_adjoint_batch(const CsxJob *__restrict__ jobs,
+                                                       const int *__restrict__ begin, int njobs)
+{
+    const int jb = find_job(begin, njobs, blockIdx.x);
+    const CsxJob &J = jobs[jb];
+    const int local = blockIdx.x - begin[jb];
+    adjoint_body<LR, QW, QU>(J.P, J.T, J.L, J.T.qa, J.T.qblk, J.in, J.out, local % J.gx,
+                                 local / J.gx);
+}
+
+template <int LR, int QW, int QU>
+__global__ void __launch_bounds__(512) k_forward_batch(const CsxJob *__restrict__ jobs,
+                                                       const int *__restrict__ begin, int njobs)
+{
+    const int jb = find_job(begin, njobs, blockIdx.x);
+    const CsxJob &J = jobs[jb];
+    const int local = blockIdx.x - begin[jb];
+    const int bx = local % J.gx, by = (local / J.gx) % J.gy, bz = local / (J.gx * J.gy);
+    forward_body<LR, QW, QU>(J.P, J.T, J.L, J.T.qa, J.T.qblk, J.in, J.out, J.tps, bx, by, bz,
+                                 J.gz);
 }
 
 // g_i = sum_p part[p][i] in a fixed order.
@@ -668,7 +720,7 @@ __global__ void __launch_bounds__(256) k_sum_parts(const float *__restrict__ par
     g[i] = s;
 }
 
-Lds lds_layout(const KParams &P, int td, bool forward)
+Lds lds_layout(const KParams &P, bool forward)
 {
     auto al = [](int v) { return (v + 15) & ~15; };
     Lds L;
@@ -683,51 +735,78 @@ Lds lds_layout(const KParams &P, int td, bool forward)
     return L;
 }
 
-template <int TD, int LR, int QW>
-void launch_fwd_t(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
-                  const float *f, int gps)
+int fwd_tiles(const KParams &P)
 {
-    if (h->P.qu)
-        hipLaunchKernelGGL((k_forward<TD, LR, QW, 1>), grid, block, L.total, s, h->P, h->t, L,
-                           h->t.qa, h->t.qblk, f, h->part, gps);
-    else
-        hipLaunchKernelGGL((k_forward<TD, LR, QW, 0>), grid, block, L.total, s, h->P, h->t, L,
-                           h->t.qa, h->t.qblk, f, h->part, gps);
+    const int gw = P.lr ? P.nx / 2 : P.nx;
+    return ((gw + 7) / 8) * ((P.nz + 7) / 8);
 }
 
-template <int TD, int LR, int QW>
-void launch_adj_t(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
-                  const float *rho, float *b)
+int log2i(int v)
 {
-    if (h->P.qu)
-        hipLaunchKernelGGL((k_adjoint<TD, LR, QW, 1>), grid, block, L.total, s, h->P, h->t, L,
-                           h->t.qa, h->t.qblk, rho, b);
-    else
-        hipLaunchKernelGGL((k_adjoint<TD, LR, QW, 0>), grid, block, L.total, s, h->P, h->t, L,
-                           h->t.qa, h->t.qblk, rho, b);
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
 }
 
-template <int TD, int LR>
-void dispatch_fwd(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
-                  const float *f, int gps)
+// Kernel template of a launch: bit 1 LR mirror, bit 2 uniform q, bits 3+
+// log2 of the q chunk width.  (The table dtype only changes table staging.)
+int variant_of(const KParams &P)
 {
-    switch (h->P.qw) {
-    case 16: launch_fwd_t<TD, LR, 16>(h, L, grid, block, s, f, gps); break;
-    case 32: launch_fwd_t<TD, LR, 32>(h, L, grid, block, s, f, gps); break;
-    default: launch_fwd_t<TD, LR, 64>(h, L, grid, block, s, f, gps); break;
+    return (P.lr ? 2 : 0) | (P.qu ? 4 : 0) | (log2i(P.qw) << 3);
+}
+
+// Template dispatch: variant -> kernel instance.
+template <template <int, int, int> class K, typename... A>
+void dispatch(int variant, A &&...a)
+{
+    const int lr = (variant >> 1) & 1, qu = (variant >> 2) & 1;
+    const int qw = 1 << (variant >> 3);
+#define CSX_CASE(LR_, QW_, QU_) \
+    if (lr == LR_ && qw == QW_ && qu == QU_) { K<LR_, QW_, QU_>::run(a...); return; }
+#define CSX_CASES_QW(LR_, QU_) CSX_CASE(LR_, 16, QU_) CSX_CASE(LR_, 32, QU_) CSX_CASE(LR_, 64, QU_)
+    CSX_CASES_QW(0, 0) CSX_CASES_QW(0, 1) CSX_CASES_QW(1, 0) CSX_CASES_QW(1, 1)
+#undef CSX_CASES_QW
+#undef CSX_CASE
+}
+
+template <int LR, int QW, int QU>
+struct RunFwd {
+    static void run(const OpShape &S, const csx_geometry *h, const float *f, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_forward<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t,
+                           S.L, h->t.qa, h->t.qblk, f, h->part, S.tps);
     }
-}
+};
 
-template <int TD, int LR>
-void dispatch_adj(const csx_geometry *h, const Lds &L, dim3 grid, dim3 block, hipStream_t s,
-                  const float *rho, float *b)
-{
-    switch (h->P.qw) {
-    case 16: launch_adj_t<TD, LR, 16>(h, L, grid, block, s, rho, b); break;
-    case 32: launch_adj_t<TD, LR, 32>(h, L, grid, block, s, rho, b); break;
-    default: launch_adj_t<TD, LR, 64>(h, L, grid, block, s, rho, b); break;
+template <int LR, int QW, int QU>
+struct RunAdj {
+    static void run(const OpShape &S, const csx_geometry *h, const float *rho, float *b,
+                    hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_adjoint<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t,
+                           S.L, h->t.qa, h->t.qblk, rho, b);
     }
-}
+};
+
+template <int LR, int QW, int QU>
+struct RunFwdBatch {
+    static void run(const CsxJob *jobs, const int *begin, int njobs, int nblocks, int lds,
+                    hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_forward_batch<LR, QW, QU>), dim3(nblocks), dim3(512), lds, s,
+                           jobs, begin, njobs);
+    }
+};
+
+template <int LR, int QW, int QU>
+struct RunAdjBatch {
+    static void run(const CsxJob *jobs, const int *begin, int njobs, int nblocks, int lds,
+                    hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_adjoint_batch<LR, QW, QU>), dim3(nblocks), dim3(256), lds, s,
+                           jobs, begin, njobs);
+    }
+};
 
 }  // namespace
 
@@ -743,72 +822,105 @@ hipEvent_t csx_timing_event(csx_geometry *h, int op)
     return v[h->ev_used[op]++];
 }
 
-static int fwd_tiles(const KParams &P)
+csx_launch csx_default_launch(const KParams &P)
 {
-    const int gw = P.lr ? P.nx / 2 : P.nx;
-    return ((gw + 7) / 8) * ((P.nz + 7) / 8);
+    csx_launch lc;
+    const int qw = P.nq <= 16 ? 16 : (P.nq <= 32 ? 32 : 64);
+    lc.fwd_qw = qw;
+    lc.adj_qw = qw;
+    const int qchunks = (P.nq + qw - 1) / qw;
+    // split the voxel tiles so that a forward launch holds >= ~8 waves per SIMD
+    const int bx = (P.n_quad + 7) / 8;
+    const int target_waves = 8 * 4 * 256;
+    int splits = std::max(1, target_waves / std::max(1, bx * 8 * qchunks));
+    splits = std::min(splits, std::max(1, fwd_tiles(P) / 2));
+    lc.fwd_splits = std::min(splits, 64);
+    return lc;
 }
 
-void csx_choose_launch(csx_geometry *h)
+bool csx_launch_valid(const csx_launch &lc)
 {
-    const KParams &P = h->P;
-    h->fwd_wpb = 8;
-    h->adj_wpb = 4;
-    const int bx = (P.n_quad + h->fwd_wpb - 1) / h->fwd_wpb;
-    // split the voxel tiles so that a launch holds >= ~8 waves per SIMD
-    const int target_waves = 8 * 4 * 256;
-    int splits = std::max(1, target_waves / std::max(1, bx * h->fwd_wpb * P.qchunks));
-    splits = std::min(splits, std::max(1, fwd_tiles(P) / 2));
-    h->fwd_splits = splits;
+    auto okq = [](int q) { return q == 16 || q == 32 || q == 64; };
+    return okq(lc.fwd_qw) && okq(lc.adj_qw) && lc.fwd_splits >= 1 && lc.fwd_splits <= 64;
+}
+
+OpShape csx_forward_shape(const csx_geometry *h)
+{
+    OpShape S;
+    S.P = h->P;
+    S.P.qw = h->lc.fwd_qw;
+    S.P.qchunks = (S.P.nq + S.P.qw - 1) / S.P.qw;
+    S.L = lds_layout(S.P, true);
+    const int ntiles = fwd_tiles(S.P);
+    const int splits = std::max(1, std::min(h->lc.fwd_splits, ntiles));
+    S.tps = (ntiles + splits - 1) / splits;
+    const int nsplit = (ntiles + S.tps - 1) / S.tps;
+    S.grid = dim3((S.P.n_quad + 7) / 8, nsplit, S.P.qchunks);
+    S.block = dim3(512);
+    S.nparts = nsplit * S.P.qchunks;
+    S.variant = variant_of(S.P);
+    return S;
+}
+
+OpShape csx_adjoint_shape(const csx_geometry *h)
+{
+    OpShape S;
+    S.P = h->P;
+    S.P.qw = h->lc.adj_qw;
+    S.P.qchunks = (S.P.nq + S.P.qw - 1) / S.P.qw;
+    S.L = lds_layout(S.P, false);
+    S.grid = dim3((S.P.n_groups + h->adj_wpb - 1) / h->adj_wpb, S.P.qchunks);
+    S.block = dim3(64 * h->adj_wpb);
+    S.tps = 0;
+    S.nparts = 0;
+    S.variant = variant_of(S.P);
+    return S;
+}
+
+csx_status csx_launch_sum_parts(csx_geometry *h, int nparts, float *g, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_parts, dim3((h->P.npix + 255) / 256), dim3(256), 0, s, h->part,
+                       nparts, h->P.npix, g);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
 }
 
 csx_status csx_launch_forward(csx_geometry *h, const float *f, float *g, hipStream_t s)
 {
-    const KParams &P = h->P;
-    const int wpb = 8;   // the forward kernel's staging assumes 512 threads
-    const Lds L = lds_layout(P, h->table_dtype, true);
-    const int splits = h->fwd_splits;
-    const int ntiles = fwd_tiles(P);
-    const int gps = (ntiles + splits - 1) / splits;
-    const int nsplit = (ntiles + gps - 1) / gps;
-    dim3 grid((P.n_quad + wpb - 1) / wpb, nsplit, P.qchunks);
-    dim3 block(64 * wpb);
+    const OpShape S = csx_forward_shape(h);
     hipEvent_t e0 = csx_timing_event(h, 0), e1 = csx_timing_event(h, 0);
     if (e0) HIP_TRY(hipEventRecord(e0, s));
-    const bool bf = h->table_dtype == CSX_TABLE_BF16;
-    if (P.lr) {
-        if (bf) dispatch_fwd<CSX_TABLE_BF16, 1>(h, L, grid, block, s, f, gps);
-        else dispatch_fwd<CSX_TABLE_F32, 1>(h, L, grid, block, s, f, gps);
-    } else {
-        if (bf) dispatch_fwd<CSX_TABLE_BF16, 0>(h, L, grid, block, s, f, gps);
-        else dispatch_fwd<CSX_TABLE_F32, 0>(h, L, grid, block, s, f, gps);
-    }
+    dispatch<RunFwd>(S.variant, S, h, f, s);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_parts, dim3((P.npix + 255) / 256), dim3(256), 0, s, h->part,
-                       nsplit * P.qchunks, P.npix, g);
-    HIP_TRY(hipGetLastError());
+    csx_status st = csx_launch_sum_parts(h, S.nparts, g, s);
+    if (st != CSX_OK) return st;
     if (e1) HIP_TRY(hipEventRecord(e1, s));
     return CSX_OK;
 }
 
 csx_status csx_launch_adjoint(csx_geometry *h, const float *rho, float *b, hipStream_t s)
 {
-    const KParams &P = h->P;
-    const int wpb = h->adj_wpb;
-    const Lds L = lds_layout(P, h->table_dtype, false);
-    dim3 grid((P.n_groups + wpb - 1) / wpb, P.qchunks);
-    dim3 block(64 * wpb);
+    const OpShape S = csx_adjoint_shape(h);
     hipEvent_t e0 = csx_timing_event(h, 1), e1 = csx_timing_event(h, 1);
     if (e0) HIP_TRY(hipEventRecord(e0, s));
-    const bool bf = h->table_dtype == CSX_TABLE_BF16;
-    if (P.lr) {
-        if (bf) dispatch_adj<CSX_TABLE_BF16, 1>(h, L, grid, block, s, rho, b);
-        else dispatch_adj<CSX_TABLE_F32, 1>(h, L, grid, block, s, rho, b);
-    } else {
-        if (bf) dispatch_adj<CSX_TABLE_BF16, 0>(h, L, grid, block, s, rho, b);
-        else dispatch_adj<CSX_TABLE_F32, 0>(h, L, grid, block, s, rho, b);
-    }
+    dispatch<RunAdj>(S.variant, S, h, rho, b, s);
     HIP_TRY(hipGetLastError());
     if (e1) HIP_TRY(hipEventRecord(e1, s));
+    return CSX_OK;
+}
+
+csx_status csx_launch_forward_batch(const CsxJob *jobs_dev, const int *begin_dev, int njobs,
+                                    int nblocks, int variant, int lds_bytes, hipStream_t s)
+{
+    dispatch<RunFwdBatch>(variant, jobs_dev, begin_dev, njobs, nblocks, lds_bytes, s);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_adjoint_batch(const CsxJob *jobs_dev, const int *begin_dev, int njobs,
+                                    int nblocks, int variant, int lds_bytes, hipStream_t s)
+{
+    dispatch<RunAdjBatch>(variant, jobs_dev, begin_dev, njobs, nblocks, lds_bytes, s);
+    HIP_TRY(hipGetLastError());
     return CSX_OK;
 }

@@ -121,7 +121,8 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
 __global__ void __launch_bounds__(256) k_objective(const double *__restrict__ partL, int nL,
                                                    const double *__restrict__ partR, int nR,
                                                    const int *__restrict__ partF, double beta,
-                                                   int *__restrict__ flags, double *__restrict__ J)
+                                                   int *__restrict__ flags, double *__restrict__ J,
+                                                   const int *__restrict__ iter)
 {
     __shared__ double s_red[4];
     __shared__ int s_flag;
@@ -140,9 +141,11 @@ __global__ void __launch_bounds__(256) k_objective(const double *__restrict__ pa
     const double tb = block_sum_d(b, s_red);
     if (threadIdx.x == 0) {
         *flags = s_flag;
-        *J = (s_flag & 1) ? INFINITY : ta + beta * tb;
+        J[iter ? *iter : 0] = (s_flag & 1) ? INFINITY : ta + beta * tb;
     }
 }
+
+__global__ void k_iter_incr(int *iter) { *iter += 1; }
 
 // sums for the uniform start: block partials of sum x and sum y over a
 // grid-stride range, then one block adds the partials in a fixed order
@@ -224,10 +227,18 @@ csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool 
     return CSX_OK;
 }
 
-csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, hipStream_t s)
+csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, const int *iter,
+                                hipStream_t s)
 {
     hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, s, h->partL, h->nbL, h->partR, h->nbR,
-                       h->partF, beta, h->flags, J);
+                       h->partF, beta, h->flags, J, iter);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_iter_incr(int *iter, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iter_incr, dim3(1), dim3(1), 0, s, iter);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }

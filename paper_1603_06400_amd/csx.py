@@ -45,6 +45,10 @@ class _Desc(ctypes.Structure):
     ]
 
 
+class _Launch(ctypes.Structure):
+    _fields_ = [("fwd_splits", ctypes.c_int), ("fwd_qw", ctypes.c_int), ("adj_qw", ctypes.c_int)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("nvox", ctypes.c_int), ("npix", ctypes.c_int), ("nq", ctypes.c_int),
                 ("symmetric_lr", ctypes.c_int), ("table_dtype", ctypes.c_int),
@@ -53,7 +57,8 @@ class _Info(ctypes.Structure):
 
 EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_get_info",
            "csx_forward", "csx_backproject", "csx_recon_step", "csx_recon",
-           "csx_timing_enable", "csx_timing_read", "csx_last_error"]
+           "csx_get_launch", "csx_set_launch", "csx_batch_create", "csx_batch_free",
+           "csx_batch_recon", "csx_timing_enable", "csx_timing_read", "csx_last_error"]
 
 _lib = None
 
@@ -84,6 +89,18 @@ def lib():
         L.csx_recon.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double), vp]
         L.csx_recon.restype = ctypes.c_int
+        L.csx_get_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
+        L.csx_get_launch.restype = ctypes.c_int
+        L.csx_set_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
+        L.csx_set_launch.restype = ctypes.c_int
+        L.csx_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp)]
+        L.csx_batch_create.restype = ctypes.c_int
+        L.csx_batch_free.argtypes = [vp]
+        L.csx_batch_free.restype = None
+        L.csx_batch_recon.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double), vp]
+        L.csx_batch_recon.restype = ctypes.c_int
         L.csx_timing_enable.argtypes = [vp, ctypes.c_int]
         L.csx_timing_enable.restype = ctypes.c_int
         L.csx_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
@@ -167,6 +184,15 @@ class Geometry:
         _check(lib().csx_get_info(self._h, ctypes.byref(out)))
         return {k: getattr(out, k) for k, _ in _Info._fields_}
 
+    def get_launch(self) -> dict:
+        out = _Launch()
+        _check(lib().csx_get_launch(self._h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in _Launch._fields_}
+
+    def set_launch(self, fwd_splits: int, fwd_qw: int, adj_qw: int) -> None:
+        lc = _Launch(int(fwd_splits), int(fwd_qw), int(adj_qw))
+        _check(lib().csx_set_launch(self._h, ctypes.byref(lc)))
+
     def timing_enable(self, on: bool = True) -> None:
         _check(lib().csx_timing_enable(self._h, int(bool(on))))
 
@@ -214,4 +240,43 @@ class Geometry:
                                _dev(f, self.nvox * self.nq, "f"), int(bool(init_uniform)),
                                int(n_iter), float(beta),
                                hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+        return hist
+
+
+class Batch:
+    """Independent scans reconstructed together (the batched form)."""
+
+    def __init__(self, geoms):
+        self.geoms = list(geoms)
+        arr = (ctypes.c_void_p * len(self.geoms))(*[g._h.value for g in self.geoms])
+        h = ctypes.c_void_p()
+        _check(lib().csx_batch_create(arr, len(self.geoms), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().csx_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def recon(self, ys, fs, n_iter: int, beta: float, rs=None, init_uniform: bool = True) -> np.ndarray:
+        """Alg. 5 on every scan in place; returns J histories [n_scans][n_iter + 1]."""
+        n = len(self.geoms)
+        if len(ys) != n or len(fs) != n or (rs is not None and len(rs) != n):
+            raise ValueError("one y and one f per scan")
+        yp = (ctypes.c_void_p * n)(*[_dev(y, g.npix, "y").value for y, g in zip(ys, self.geoms)])
+        fp = (ctypes.c_void_p * n)(*[_dev(f, g.nvox * g.nq, "f").value for f, g in zip(fs, self.geoms)])
+        rp = None
+        if rs is not None:
+            rp = (ctypes.c_void_p * n)(*[None if r is None else _dev(r, g.npix, "r").value
+                                         for r, g in zip(rs, self.geoms)])
+        hist = np.zeros((n, n_iter + 1), dtype=np.float64)
+        _check(lib().csx_batch_recon(self._h, yp, rp, fp, int(bool(init_uniform)), int(n_iter),
+                                     float(beta), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     _stream()))
         return hist
