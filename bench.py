@@ -8,6 +8,7 @@ nominal voxel*pixel*q evaluations of one forward plus one adjoint
 (2 * 16384 * 16384 * 64 = 3.436e10) per step.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --workload batch64 [--steps K] [--warmup W]
 
 Prints one JSON line.  The roofline entry uses the work model of the direct
 evaluation (4 VALU lane-ops per open in-band triple, 60 per open pair, 10 per
@@ -79,6 +80,94 @@ def cpu_baseline(g, f, y, n_pix=12288, n_vox=12288):
                       f"{t1 - t0:.1f} s + {t2 - t1:.1f} s)"}
 
 
+def bench_batch(args):
+    """The batched form: 64 scans of uneven sizes (N in {48, 64, 96, 128}, nq in
+    {32, 64}), launch shapes from the autotuner, reconstructed together by one
+    replayed iteration graph; timed against the same scans run one after the
+    other through the single-scan entry point.  Counts are Poisson draws around
+    the library's own forward of each phantom, scaled to a maximum mean of 1e4."""
+    import torch
+
+    from paper_1603_06400_amd import autotune, csx, inputs
+
+    beta = 1e-3
+    scans = inputs.batch_scans(64)
+    try:
+        with open(os.path.join(GOLDEN, "batch64_census.json")) as fh:
+            census = json.load(fh)
+    except (OSError, ValueError):
+        census = None
+    torch.cuda.set_device(0)
+    cache = autotune.load_cache(args.tune_cache) if args.tune_cache else {}
+    geos, ys = [], []
+    t_tune = time.perf_counter()
+    for s in scans:
+        f = torch.tensor(inputs.phantom(s.geom, s.phantom_seed, s.n_rect), dtype=torch.float32,
+                         device="cuda")
+        unit = csx.Geometry(s.geom.with_(C=1.0))
+        l1 = unit.forward(f).double().cpu().numpy()
+        unit.close()
+        C = 1e4 / float(l1.max())
+        geo = csx.Geometry(s.geom.with_(C=C))
+        autotune.tuned(geo, cache)
+        geos.append(geo)
+        ys.append(torch.tensor(inputs.poisson_counts(C * l1, s.noise_seed), dtype=torch.float32,
+                               device="cuda"))
+    t_tune = time.perf_counter() - t_tune
+    if args.tune_cache:
+        autotune.save_cache(cache, args.tune_cache)
+    batch = csx.Batch(geos)
+    fb = [g.new_image() for g in geos]
+    fs = [g.new_image() for g in geos]
+    if args.warmup:
+        batch.recon(ys, fb, args.warmup, beta)
+        for g, y, f in zip(geos, ys, fs):
+            g.recon(y, f, args.warmup, beta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Jb = batch.recon(ys, fb, args.steps, beta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Js = [g.recon(y, f, args.steps, beta) for g, y, f in zip(geos, ys, fs)]
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    same = all(torch.equal(a, b) for a, b in zip(fb, fs)) and all(
+        np.array_equal(Jb[k], Js[k]) for k in range(len(geos)))
+
+    steps = max(1, args.steps)
+    nominal = sum(2.0 * g.nvox * g.npix * g.nq for g in (s.geom for s in scans))
+    ms_b = (t1 - t0) * 1e3 / steps
+    ms_s = (t2 - t1) * 1e3 / steps
+    roofline = None
+    if census is not None:
+        ops = 2.0 * sum(algorithmic_ops(c) for c in census)
+        achieved = ops / (ms_b * 1e-3)
+        roofline = {"bound": "alu", "kernel": "whole batched iteration (forward + adjoint + solver)",
+                    "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+                    "frac": achieved / PEAK_LANE_OPS, "traffic": None, "ops_per_step": ops}
+    sizes = {}
+    for s in scans:
+        key = f"{s.geom.nx}^2x{s.geom.nq}q"
+        sizes[key] = sizes.get(key, 0) + 1
+    out = {
+        "metric": "fwd+adjoint voxel*pixel*energy evals/s, 64-scan uneven batch (one Alg. 5 iteration "
+                  "of every scan per step)",
+        "value": nominal / (ms_b * 1e-3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64", "scans": len(scans), "sizes": sizes, "beta": beta,
+                   "nominal_evals_per_step": nominal,
+                   "timed": "csx_batch_recon of all scans (graph capture, uniform start and final "
+                            "objective included) vs csx_recon per scan in turn"},
+        "sequential": {"value": nominal / (ms_s * 1e-3), "ms_per_step": ms_s},
+        "speedup_vs_sequential": ms_s / ms_b,
+        "batched_equals_sequential": bool(same),
+        "autotune_s": t_tune, "autotune_classes": len(cache),
+        "roofline": roofline,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +177,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
                          "reference kernel for scaling HBM byte counters")
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64"],
+                    help="slice128 (default): the single 128^2 x 64q slice; batch64: the batched form")
+    ap.add_argument("--tune-cache", default=None, metavar="PATH",
+                    help="batch64: launch-shape cache file to read and update")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -103,6 +196,10 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(independent scans shard across GPUs without communication).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        bench_batch(args)
+        return
 
     import torch
 

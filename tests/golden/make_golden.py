@@ -6,7 +6,10 @@ integer counts y ~ Poisson(C l1) with the workload's noise seed; and the work
 census of the workload's geometry.  Calls only ``oracle`` and the seeded input
 generators.
 
-    python tests/golden/make_golden.py [slice32 slice128 ...]
+    python tests/golden/make_golden.py [slice32 slice128 ... batch64]
+
+``batch64`` writes only the per-scan work census of the 64-scan uneven batch
+(its counts are drawn at run time).
 """
 import json
 import os
@@ -47,7 +50,24 @@ def census(name: str) -> str:
     return path
 
 
+def batch_census(n_scans: int = 64) -> str:
+    """Per-scan work census of the uneven batch (same fields as census())."""
+    out = []
+    for s in inputs.batch_scans(n_scans):
+        c = {k: float(v) for k, v in oracle.Oracle(s.geom).census().items()}
+        c.update(n=s.geom.nx, nvox=s.geom.nvox, npix=s.geom.npix, nq=s.geom.nq,
+                 phantom_seed=s.phantom_seed)
+        out.append(c)
+    path = os.path.join(HERE, f"batch{n_scans}_census.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=0)
+    return path
+
+
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or ["slice32", "slice128", "slice128_open1", "slice128_open01"]):
+    for n in (sys.argv[1:] or ["slice32", "slice128", "slice128_open1", "slice128_open01", "batch64"]):
+        if n.startswith("batch"):
+            print(batch_census(int(n[5:])))
+            continue
         print(make(n))
         print(census(n))
