@@ -238,3 +238,40 @@ def batch_scans(n_scans: int = 64, seed0: int = 1000,
         g = standard_geometry(n, nq, mask_seed=seed0 + i)
         out.append(BatchScan(g, seed0 + i, 50000 + seed0 + i, n_rect))
     return out
+
+
+# ---- learned warm start: seeded network weights and phantom sets ------------------
+
+WARM_CHANNELS = (64, 32, 32, 32, 64)
+
+
+def cnn_init(seed: int, channels=WARM_CHANNELS, out_bias: float = 0.5413) -> List[dict]:
+    """Initial weights of the 3x3 network: per layer w [9][c_in][c_out] normal
+    with std sqrt(2 / (9 c_in)) (He), the last layer's scaled by 0.1; biases
+    zero except the last layer's (out_bias; 0.5413 ~ log(e - 1) puts the
+    softplus output near 1).  float32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    n = len(channels) - 1
+    for k in range(n):
+        ci, co = channels[k], channels[k + 1]
+        std = np.sqrt(2.0 / (9.0 * ci)) * (0.1 if k == n - 1 else 1.0)
+        w = rng.normal(0.0, std, size=(9, ci, co)).astype(np.float32)
+        b = np.full(co, out_bias if k == n - 1 else 0.0, dtype=np.float32)
+        out.append({"w": w, "b": b})
+    return out
+
+
+@dataclass
+class WarmCase:
+    phantom_seed: int
+    noise_seed: int
+    n_rect: int
+
+
+def warm_cases(split: str, n: int) -> List[WarmCase]:
+    """Phantoms of the learned warm start on the slice128 geometry: 'train'
+    draws phantom seeds from 100000 up, 'eval' (held out) from 900000 up; each
+    has 3 rectangles and its own noise seed."""
+    base = {"train": 100000, "eval": 900000}[split]
+    return [WarmCase(base + i, base + 500000 + i, 3) for i in range(n)]

@@ -1,0 +1,144 @@
+"""Pins of the FP64 network oracle (oracle/cnn.py) against references other
+than itself: scipy's 2-D correlation, shifted identities, central finite
+differences, Adam's closed-form first step and known binary16 values."""
+import numpy as np
+import pytest
+from scipy.signal import correlate2d
+
+from oracle import cnn
+
+
+def rnd(shape, seed, lo=-1.0, hi=1.0):
+    return np.random.Generator(np.random.PCG64(seed)).uniform(lo, hi, size=shape)
+
+
+def test_f16_rounding_known_values():
+    one = 1.0
+    ulp = 2.0 ** -10
+    assert cnn.f16(one + ulp / 2) == one                  # tie -> even
+    assert cnn.f16(one + 3 * ulp / 2) == one + 2 * ulp     # tie -> even (up)
+    assert cnn.f16(one + 0.51 * ulp) == one + ulp
+    assert cnn.f16(65504.0) == 65504.0
+    assert cnn.f16(2.0 ** -24) == 2.0 ** -24               # smallest subnormal
+    assert cnn.f16(2.0 ** -26) == 0.0
+    assert cnn.f16(0.1) == 0.0999755859375
+
+
+def test_conv_matches_scipy_correlate():
+    x = rnd((2, 7, 9, 3), 1)
+    w = rnd((9, 3, 4), 2)
+    b = rnd(4, 3)
+    y = cnn.conv3x3(x, w, b, half=False)
+    for n in range(2):
+        for o in range(4):
+            ref = np.full((7, 9), b[o])
+            for i in range(3):
+                k = w[:, i, o].reshape(3, 3)       # k[dh, dw]
+                ref += correlate2d(x[n, :, :, i], k, mode="same", boundary="fill")
+            np.testing.assert_allclose(y[n, :, :, o], ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("tap", range(9))
+def test_single_tap_identity_is_a_shift(tap):
+    x = rnd((1, 6, 5, 2), 4)
+    w = np.zeros((9, 2, 2))
+    w[tap] = np.eye(2)
+    y = cnn.conv3x3(x, w, half=False)
+    dh, dw = cnn.TAPS[tap]
+    ref = np.zeros_like(x)
+    for h in range(6):
+        for c in range(5):
+            hh, cc = h + dh - 1, c + dw - 1
+            if 0 <= hh < 6 and 0 <= cc < 5:
+                ref[0, h, c] = x[0, hh, cc]
+    np.testing.assert_array_equal(y, ref)
+
+
+def test_relu_and_half_rounding_points():
+    x = rnd((1, 4, 4, 2), 5)
+    w = rnd((9, 2, 3), 6)
+    y16 = cnn.conv3x3(x, w, relu=True, half=True)
+    y = cnn.conv3x3(cnn.f16(x), cnn.f16(w), relu=True, half=False)
+    np.testing.assert_array_equal(y16, y)
+    assert np.all(y16 >= 0) and np.any(y16 == 0)
+
+
+def tiny_net(seed=7, ch=(3, 4, 4, 2)):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [{"w": rng.normal(0, 0.5, (9, ch[k], ch[k + 1])), "b": rng.normal(0, 0.2, ch[k + 1])}
+            for k in range(len(ch) - 1)]
+
+
+def test_backward_matches_finite_differences():
+    params = tiny_net()
+    x = rnd((2, 5, 6, 3), 8, 0.0, 1.0)
+    t = rnd((2, 5, 6, 2), 9, 0.0, 2.0)
+    acts = cnn.forward(params, x, half=False)
+    L, grads = cnn.backward(params, acts, t, half=False)
+    assert L == pytest.approx(cnn.loss(params, x, t, half=False), rel=1e-14)
+    rng = np.random.Generator(np.random.PCG64(10))
+    h = 1e-6
+    for k, lay in enumerate(params):
+        for name in ("w", "b"):
+            arr = lay[name]
+            for flat in rng.choice(arr.size, size=min(12, arr.size), replace=False):
+                idx = np.unravel_index(flat, arr.shape)
+                old = arr[idx]
+                arr[idx] = old + h
+                lp = cnn.loss(params, x, t, half=False)
+                arr[idx] = old - h
+                lm = cnn.loss(params, x, t, half=False)
+                arr[idx] = old
+                fd = (lp - lm) / (2 * h)
+                an = grads[k][name][idx]
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (k, name, idx, fd, an)
+
+
+def test_backward_data_is_adjoint_of_forward():
+    """<conv(x), dy> = <x, conv^T(dy)> for the bias-free convolution."""
+    x = rnd((2, 6, 7, 3), 11)
+    w = rnd((9, 3, 5), 12)
+    dy = rnd((2, 6, 7, 5), 13)
+    lhs = np.sum(cnn.conv3x3(x, w, half=False) * dy)
+    rhs = np.sum(x * cnn.conv3x3_backward_data(dy, w, half=False))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_head_gradient_and_softplus_limits():
+    o = np.array([-800.0, -3.0, 0.0, 2.5, 800.0])
+    assert cnn.softplus(o)[2] == pytest.approx(np.log(2.0), rel=1e-15)
+    assert cnn.softplus(o)[4] == 800.0 and cnn.softplus(o)[0] >= 0.0
+    assert cnn.sigmoid(np.array([0.0]))[0] == 0.5
+    t = np.array([0.1, 0.2, 0.3, 0.4, 0.5])
+    L, d = cnn.head(o[1:4], t[1:4], 1)
+    h = 1e-6
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        fd = (cnn.head(o[1:4] + e, t[1:4], 1)[0] - cnn.head(o[1:4] - e, t[1:4], 1)[0]) / (2 * h)
+        assert d[k] == pytest.approx(fd, rel=1e-7)
+
+
+def test_adam_first_step_closed_form():
+    g = np.array([3.0, -0.5, 1e-3, 0.0])
+    w = np.array([1.0, 2.0, 3.0, 4.0])
+    w1, m, v = cnn.adam(w, np.zeros(4), np.zeros(4), g, 1, lr=0.01, eps=1e-8)
+    np.testing.assert_allclose(w1, w - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-13)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_adam_minimises_a_quadratic():
+    w = np.array([0.0, 10.0])
+    m = v = np.zeros(2)
+    for k in range(1, 3001):
+        w, m, v = cnn.adam(w, m, v, 2 * (w - np.array([3.0, -1.0])), k, lr=0.05)
+    np.testing.assert_allclose(w, [3.0, -1.0], atol=1e-3)
+
+
+def test_warm_input_output():
+    b = np.array([2.0, 0.0, 5.0])
+    b1 = np.array([4.0, 0.0, 1.0])
+    np.testing.assert_allclose(cnn.warm_input(b, b1, 0.5), [1.0, 0.0, 10.0])
+    f0 = cnn.warm_output(np.array([-50.0, 0.0]), 2.0, 1e-3)
+    assert np.all(f0 > 0) and f0[1] == pytest.approx(2.0 * (np.log(2.0) + 1e-3))
