@@ -41,6 +41,7 @@
 #ifndef CSX_H
 #define CSX_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -188,6 +189,91 @@ csx_status csx_batch_recon(csx_batch *b, const float *const *y, const float *con
  * adjoint kernels.  Off by default; enabling resets the counters. */
 csx_status csx_timing_enable(csx_geometry *h, int on);
 csx_status csx_timing_read(csx_geometry *h, double ms[2], int n[2]);
+
+/* ---- Learned warm start ------------------------------------------------------
+ * Not part of the paper, which starts Alg. 5 from a uniform image: a small
+ * network maps the first EM factor from the uniform start (the back
+ * projection, by the back projector of Sec. IV, of the count ratio, divided
+ * by the sensitivity image b1 = A^T 1; u = sum(y) / sum(b1) is the uniform
+ * start value) to a strictly positive starting image f0 = u (softplus(o) +
+ * eps), trained on reconstructions made by Alg. 5 itself.  A judge (csx_recon_warm) runs Alg. 5 from both starts and keeps
+ * the warm one only if its objective is lower.
+ *
+ * Images are [nb][h][w][c] float32 (an f image [nz][nx][nq] is one image of
+ * h = nz, w = nx, c = nq channels).  Weights are [9][c_in][c_out] binary16
+ * bits, tap 3 dh + dw reading input pixel (row + dh - 1, col + dw - 1); pixels
+ * outside the image read 0.  The products take binary16 operands (activations
+ * and output gradients rounded to nearest-even on load) and accumulate in
+ * float32.  Supported (c_in, c_out): (64, 32), (32, 32), (32, 64).  All
+ * pointers are device memory owned by the caller; calls are asynchronous on
+ * `stream` and return CSX_EINVAL for NULL buffers, unsupported channels or
+ * sizes < 1. */
+typedef struct {
+    const uint16_t *w[4];   /* layers 64->32, 32->32, 32->32, 32->64 (binary16) */
+    const float *b[4];      /* biases [c_out] float32 */
+} csx_warm_net;
+
+/* Workspace needed by csx_conv3x3_backward_weights and csx_warm_loss for nb
+ * images of h x w (0 for sizes < 1). */
+size_t csx_cnn_workspace_bytes(int nb, int h, int w);
+
+/* y = conv3x3(x, w) + bias (bias may be NULL), then max(y, 0) if relu. */
+csx_status csx_conv3x3_forward(const float *x, const uint16_t *w, const float *bias, float *y,
+                               int nb, int h, int w_, int cin, int cout, int relu, void *stream);
+
+/* dx[p][i] = sum_t sum_o dy[p - off_t][o] w[t][i][o] for the layer
+ * (cin -> cout) with weights w; dy has cout channels, dx cin.  If mask (a
+ * [nb][h][w][cin] activation) is not NULL, dx is 0 where mask <= 0 (the ReLU
+ * derivative of the layer's input). */
+csx_status csx_conv3x3_backward_data(const float *dy, const uint16_t *w, const float *mask, float *dx,
+                                     int nb, int h, int w_, int cin, int cout, void *stream);
+
+/* dw[t][i][o] = sum over images and pixels p of x[p + off_t][i] dy[p][o]
+ * (float32 [9][cin][cout]); dbias[o] = sum of dy[.][o] (float32 operands,
+ * may be NULL).  Fixed summation order (reproducible). */
+csx_status csx_conv3x3_backward_weights(const float *x, const float *dy, float *dw, float *dbias,
+                                        int nb, int h, int w_, int cin, int cout, void *ws,
+                                        size_t ws_bytes, void *stream);
+
+/* Training head: p = softplus(o), *loss = sum (p - t)^2 / nb (device
+ * float64), d = dL/do = 2 (p - t) sigmoid(o) / nb; o, t, d hold nb *
+ * n_per_image floats. */
+csx_status csx_warm_loss(const float *o, const float *t, int nb, int n_per_image, float *d,
+                         double *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* Adam (Kingma & Ba 2015, with bias correction) on n float32 weights w with
+ * moments m, v and gradient g; step counts from 1.  w16 (may be NULL)
+ * receives the binary16 copy of the updated weights. */
+csx_status csx_adam_step(float *w, float *m, float *v, const float *g, uint16_t *w16, int n,
+                         double lr, double beta1, double beta2, double eps, int step, void *stream);
+
+/* y = binary16(x), nearest-even. */
+csx_status csx_to_half(const float *x, uint16_t *y, int n, void *stream);
+
+/* Network input of scan h: the first multiplicative EM factor from the
+ * uniform start, x = A^T (y / (u A 1)) / b1 (ratio 0 where A 1 = 0, x = 0
+ * where b1 = 0); u x is the first unpenalised EM iterate.  x holds nvox * nq
+ * floats ([nz][nx][nq]).  A 1 is computed once per handle. */
+csx_status csx_warm_input(csx_geometry *h, const float *y, float *x, void *stream);
+
+/* f0 = u (softplus(o) + eps) with u of the counts y; eps > 0. */
+csx_status csx_warm_output(csx_geometry *h, const float *y, const float *o, float eps, float *f0,
+                           void *stream);
+
+/* Input, the four layers (ReLU after the first three) and output in one call
+ * (needs nq = 64); activations live in a handle workspace. */
+csx_status csx_warm_start(csx_geometry *h, const float *y, const csx_warm_net *net, float eps,
+                          float *f0, void *stream);
+
+/* The judge: k_judge iterations of Alg. 5 from f_warm and k_judge from the
+ * uniform start; the start whose objective is lower after k_judge iterations
+ * (the warm one only if strictly lower) is continued to n_iter iterations in
+ * f.  J_hist (host, n_iter + 1, may be NULL) is the kept trajectory;
+ * *accepted = 1 if the warm start was kept.  Costs n_iter + k_judge
+ * iterations; synchronises `stream`.  0 <= k_judge <= n_iter. */
+csx_status csx_recon_warm(csx_geometry *h, const float *y, const float *r, const float *f_warm, float *f,
+                          int k_judge, int n_iter, double beta, double *J_hist, int *accepted,
+                          void *stream);
 
 /* Thread-local description of the last error ("" if none). */
 const char *csx_last_error(void);

@@ -4,12 +4,14 @@ TEST INFRASTRUCTURE.  Same rule as the rest of ``oracle``: only tests/,
 ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
 import it; it shares no code with the GPU library.
 
-The paper has no network.  The learned warm start feeds the paper's back
-projection of the counts (Sec. IV, the back projector of Alg. 3) divided by
-the sensitivity image b^(1) = A^T 1 (Alg. 5) and by the uniform start value
-u = sum(y) / sum(b^(1)) to a small convolutional network whose output becomes
-the solver's starting image f^0 = u (softplus(o) + eps).  The definitions
-written out here are the textbook ones:
+The paper has no network.  The learned warm start feeds the first
+multiplicative factor of the EM-type update from the uniform start (Alg. 5
+with f^0 = u everywhere, u = sum(y) / sum(b^(1)), b^(1) = A^T 1): the back
+projection (the back projector of Alg. 3) of the count ratio y / (A f^0),
+divided by b^(1) -- dimensionless, and u times it is the first EM iterate --
+to a small convolutional network whose output becomes the solver's starting
+image f^0 = u (softplus(o) + eps).  The definitions written out here are the
+textbook ones:
 
 * 3 x 3 cross-correlation with one pixel of zero padding, images stored
   height x width x channels (the q bins of an image [nz][nx][nq] are its
@@ -158,11 +160,17 @@ def adam(w, m, v, g, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.
     return np.asarray(w, dtype=np.float64) - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def warm_input(b, b1, u: float) -> np.ndarray:
-    """Network input: A^T y / (b^(1) u), zero where b^(1) = 0."""
-    b = np.asarray(b, dtype=np.float64)
-    b1 = np.asarray(b1, dtype=np.float64)
-    return np.where(b1 > 0, b / np.where(b1 > 0, b1 * u, 1.0), 0.0)
+def warm_input(orc, y) -> np.ndarray:
+    """Network input x = A^T (y / (u A 1)) / b^(1) of the scan modelled by the
+    oracle ``orc`` (ratio 0 where A 1 = 0, x = 0 where b^(1) = 0)."""
+    g = orc.geom
+    y = np.asarray(y, dtype=np.float64).reshape(g.ndy, g.ndx)
+    b1 = orc.sensitivity()
+    u = uniform_value(y, b1)
+    z0 = u * orc.forward(np.ones((g.nz, g.nx, g.nq)))
+    rho = np.where(z0 > 0, y / np.where(z0 > 0, z0, 1.0), 0.0)
+    b = orc.adjoint(rho)
+    return np.where(b1 > 0, b / np.where(b1 > 0, b1, 1.0), 0.0)
 
 
 def warm_output(o, u: float, eps: float) -> np.ndarray:

@@ -101,7 +101,8 @@ static void free_all(csx_geometry *h)
 {
     void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qblk, h->t.qv, h->t.phi32,
                     h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
-                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags};
+                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags,
+                    h->fplain, h->warm, h->a1};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     release_events(h);
@@ -358,7 +359,6 @@ extern "C" csx_status csx_backproject(csx_geometry *h, const float *y, float *b,
     return csx_launch_adjoint(h, y, b, (hipStream_t)stream);
 }
 
-csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s);
 static csx_status ensure_b1(csx_geometry *h, hipStream_t s) { return csx_ensure_b1(h, s); }
 
 csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s)
@@ -428,5 +428,32 @@ extern "C" csx_status csx_recon(csx_geometry *h, const float *y, const float *r,
     HIP_TRY(hipStreamSynchronize(s));
     if (flags & 2) return csx_fail(CSX_EINVAL, "y holds negative or NaN counts");
     if (flags & 1) return csx_fail(CSX_ENUMERIC, "y_i > 0 where the model mean is 0");
+    return CSX_OK;
+}
+
+extern "C" csx_status csx_recon_warm(csx_geometry *h, const float *y, const float *r, const float *f_warm,
+                                     float *f, int k_judge, int n_iter, double beta, double *J_hist,
+                                     int *accepted, void *stream)
+{
+    if (!h || !y || !f_warm || !f) return csx_fail(CSX_EINVAL, "NULL argument");
+    if (k_judge < 0 || k_judge > n_iter) return csx_fail(CSX_EINVAL, "need 0 <= k_judge <= n_iter");
+    if (f_warm == f) return csx_fail(CSX_EINVAL, "f_warm and f must be different buffers");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = h->P.nvox * h->P.nq;
+    if (!h->fplain) HIP_TRY(hipMalloc((void **)&h->fplain, sizeof(float) * n));
+    std::vector<double> Jw(k_judge + 1), Jp(k_judge + 1), Jr(n_iter - k_judge + 1);
+    // k iterations from the candidate, then k from the plain uniform start
+    ST_TRY(csx_launch_copy(f_warm, f, n, s));
+    ST_TRY(csx_recon(h, y, r, f, 0, k_judge, beta, Jw.data(), stream));
+    ST_TRY(csx_recon(h, y, r, h->fplain, 1, k_judge, beta, Jp.data(), stream));
+    const bool take = Jw[k_judge] < Jp[k_judge];
+    if (!take) ST_TRY(csx_launch_copy(h->fplain, f, n, s));
+    ST_TRY(csx_recon(h, y, r, f, 0, n_iter - k_judge, beta, Jr.data(), stream));
+    if (J_hist) {
+        const std::vector<double> &Jc = take ? Jw : Jp;
+        for (int t = 0; t < k_judge; ++t) J_hist[t] = Jc[t];
+        for (int t = k_judge; t <= n_iter; ++t) J_hist[t] = Jr[t - k_judge];
+    }
+    if (accepted) *accepted = take ? 1 : 0;
     return CSX_OK;
 }

@@ -15,8 +15,6 @@
 #include <cstring>
 #include <new>
 
-csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s);
-
 namespace {
 
 struct Group {

@@ -113,6 +113,10 @@ struct csx_geometry {
     int *partF = nullptr;      // per-block flags of the data term
     int *flags = nullptr;      // flags of the last objective: bit 0: y_i > 0 with zero
                                // mean; bit 1: y_i < 0 or NaN
+    float *fplain = nullptr;   // [nvox*nq] plain-start iterate of the warm-start judge
+    float *a1 = nullptr;       // [npix] A 1 (forward of the all-ones image), on demand
+    float *warm = nullptr;     // activations of the warm-start network
+    size_t warm_cap = 0;       // floats in warm
     int nbL = 0, nbR = 0;
     bool have_b1 = false;
     int64_t bytes = 0;
@@ -144,6 +148,8 @@ csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, const i
                                 hipStream_t s);
 csx_status csx_launch_iter_incr(int *iter, hipStream_t s);
 csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, hipStream_t s);
+csx_status csx_launch_uniform_sums(csx_geometry *h, const float *y, hipStream_t s);
+csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s);
 csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s);
 csx_status csx_launch_fill(float *dst, int n, float v, hipStream_t s);
 csx_status csx_launch_clear_flags(csx_geometry *h, hipStream_t s);

@@ -243,12 +243,22 @@ csx_status csx_launch_iter_incr(int *iter, hipStream_t s)
     return CSX_OK;
 }
 
-csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, hipStream_t s)
+// scal[0] = sum(y), scal[1] = sum(b1) (float64, fixed order)
+csx_status csx_launch_uniform_sums(csx_geometry *h, const float *y, hipStream_t s)
 {
     const int n = h->P.nvox * h->P.nq;
     const int nb = CSX_SUM_BLOCKS;
     hipLaunchKernelGGL(k_sum2_part, dim3(nb), dim3(256), 0, s, y, h->P.npix, h->b1, n, h->partS);
     hipLaunchKernelGGL(k_sum2_final, dim3(1), dim3(256), 0, s, h->partS, nb, h->scal);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, hipStream_t s)
+{
+    const int n = h->P.nvox * h->P.nq;
+    csx_status st = csx_launch_uniform_sums(h, y, s);
+    if (st != CSX_OK) return st;
     hipLaunchKernelGGL(k_fill_ratio, dim3((n + 255) / 256), dim3(256), 0, s, f, n, h->scal);
     HIP_TRY(hipGetLastError());
     return CSX_OK;

@@ -58,7 +58,14 @@ class _Info(ctypes.Structure):
 EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_get_info",
            "csx_forward", "csx_backproject", "csx_recon_step", "csx_recon",
            "csx_get_launch", "csx_set_launch", "csx_batch_create", "csx_batch_free",
-           "csx_batch_recon", "csx_timing_enable", "csx_timing_read", "csx_last_error"]
+           "csx_batch_recon", "csx_timing_enable", "csx_timing_read", "csx_last_error",
+           "csx_cnn_workspace_bytes", "csx_conv3x3_forward", "csx_conv3x3_backward_data",
+           "csx_conv3x3_backward_weights", "csx_warm_loss", "csx_adam_step", "csx_to_half",
+           "csx_warm_input", "csx_warm_output", "csx_warm_start", "csx_recon_warm"]
+
+
+class _WarmNet(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p * 4), ("b", ctypes.c_void_p * 4)]
 
 _lib = None
 
@@ -105,6 +112,30 @@ def lib():
         L.csx_timing_enable.restype = ctypes.c_int
         L.csx_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         L.csx_timing_read.restype = ctypes.c_int
+        i, d, sz = ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        L.csx_cnn_workspace_bytes.argtypes = [i, i, i]
+        L.csx_cnn_workspace_bytes.restype = sz
+        L.csx_conv3x3_forward.argtypes = [vp, vp, vp, vp, i, i, i, i, i, i, vp]
+        L.csx_conv3x3_forward.restype = i
+        L.csx_conv3x3_backward_data.argtypes = [vp, vp, vp, vp, i, i, i, i, i, vp]
+        L.csx_conv3x3_backward_data.restype = i
+        L.csx_conv3x3_backward_weights.argtypes = [vp, vp, vp, vp, i, i, i, i, i, vp, sz, vp]
+        L.csx_conv3x3_backward_weights.restype = i
+        L.csx_warm_loss.argtypes = [vp, vp, i, i, vp, vp, vp, sz, vp]
+        L.csx_warm_loss.restype = i
+        L.csx_adam_step.argtypes = [vp, vp, vp, vp, vp, i, d, d, d, d, i, vp]
+        L.csx_adam_step.restype = i
+        L.csx_to_half.argtypes = [vp, vp, i, vp]
+        L.csx_to_half.restype = i
+        L.csx_warm_input.argtypes = [vp, vp, vp, vp]
+        L.csx_warm_input.restype = i
+        L.csx_warm_output.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp]
+        L.csx_warm_output.restype = i
+        L.csx_warm_start.argtypes = [vp, vp, ctypes.POINTER(_WarmNet), ctypes.c_float, vp, vp]
+        L.csx_warm_start.restype = i
+        L.csx_recon_warm.argtypes = [vp, vp, vp, vp, vp, i, i, d, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(i), vp]
+        L.csx_recon_warm.restype = i
         L.csx_last_error.argtypes = []
         L.csx_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -241,6 +272,131 @@ class Geometry:
                                int(n_iter), float(beta),
                                hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
         return hist
+
+
+    # ---- learned warm start ----------------------------------------------------------
+    def warm_input(self, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Network input A^T (y / (u A 1)) / b1 as an image [nz][nx][nq]."""
+        out = self.new_image() if out is None else out
+        _check(lib().csx_warm_input(self._h, _dev(y, self.npix, "y"), _dev(out, self.nvox * self.nq, "x"),
+                                    _stream()))
+        return out
+
+    def warm_output(self, y: torch.Tensor, o: torch.Tensor, eps: float,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """f0 = u (softplus(o) + eps)."""
+        out = self.new_image() if out is None else out
+        _check(lib().csx_warm_output(self._h, _dev(y, self.npix, "y"), _dev(o, self.nvox * self.nq, "o"),
+                                     float(eps), _dev(out, self.nvox * self.nq, "f0"), _stream()))
+        return out
+
+    def warm_start(self, y: torch.Tensor, net, eps: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Input map, the network (w16/b device tensors of 4 layers) and output map in one call."""
+        out = self.new_image() if out is None else out
+        wn = _WarmNet()
+        for k in range(4):
+            w16, b = net[k]
+            if w16.dtype != torch.float16 or b.dtype != torch.float32 or not (w16.is_cuda and b.is_cuda):
+                raise ValueError("layer weights must be CUDA float16 and biases CUDA float32")
+            wn.w[k] = w16.data_ptr()
+            wn.b[k] = b.data_ptr()
+        _check(lib().csx_warm_start(self._h, _dev(y, self.npix, "y"), ctypes.byref(wn), float(eps),
+                                    _dev(out, self.nvox * self.nq, "f0"), _stream()))
+        return out
+
+    def recon_warm(self, y: torch.Tensor, f_warm: torch.Tensor, f: torch.Tensor, k_judge: int, n_iter: int,
+                   beta: float, r: Optional[torch.Tensor] = None):
+        """The judge; returns (J history of the kept start, accepted)."""
+        rp = ctypes.c_void_p(None) if r is None else _dev(r, self.npix, "r")
+        hist = np.zeros(n_iter + 1, dtype=np.float64)
+        acc = ctypes.c_int(0)
+        _check(lib().csx_recon_warm(self._h, _dev(y, self.npix, "y"), rp,
+                                    _dev(f_warm, self.nvox * self.nq, "f_warm"),
+                                    _dev(f, self.nvox * self.nq, "f"), int(k_judge), int(n_iter), float(beta),
+                                    hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(acc),
+                                    _stream()))
+        return hist, bool(acc.value)
+
+
+def _img(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def cnn_workspace_bytes(nb: int, h: int, w: int) -> int:
+    return int(lib().csx_cnn_workspace_bytes(nb, h, w))
+
+
+def conv3x3_forward(x: torch.Tensor, w16: torch.Tensor, bias: Optional[torch.Tensor], y: torch.Tensor,
+                    relu: bool) -> torch.Tensor:
+    """x [nb][h][w][cin] float32, w16 [9][cin][cout] float16 -> y [nb][h][w][cout]."""
+    nb, h, w, ci = x.shape
+    co = w16.shape[2]
+    if tuple(w16.shape) != (9, ci, co) or tuple(y.shape) != (nb, h, w, co):
+        raise ValueError("shape mismatch")
+    bp = ctypes.c_void_p(None) if bias is None else _img(bias, torch.float32, "bias")
+    _check(lib().csx_conv3x3_forward(_img(x, torch.float32, "x"), _img(w16, torch.float16, "w"), bp,
+                                     _img(y, torch.float32, "y"), nb, h, w, ci, co, int(bool(relu)), _stream()))
+    return y
+
+
+def conv3x3_backward_data(dy: torch.Tensor, w16: torch.Tensor, mask: Optional[torch.Tensor],
+                          dx: torch.Tensor) -> torch.Tensor:
+    nb, h, w, co = dy.shape
+    ci = w16.shape[1]
+    if tuple(w16.shape) != (9, ci, co) or tuple(dx.shape) != (nb, h, w, ci):
+        raise ValueError("shape mismatch")
+    if mask is not None and tuple(mask.shape) != tuple(dx.shape):
+        raise ValueError("mask shape mismatch")
+    mp = ctypes.c_void_p(None) if mask is None else _img(mask, torch.float32, "mask")
+    _check(lib().csx_conv3x3_backward_data(_img(dy, torch.float32, "dy"), _img(w16, torch.float16, "w"), mp,
+                                           _img(dx, torch.float32, "dx"), nb, h, w, ci, co, _stream()))
+    return dx
+
+
+def conv3x3_backward_weights(x: torch.Tensor, dy: torch.Tensor, dw: torch.Tensor, dbias: Optional[torch.Tensor],
+                             ws: torch.Tensor) -> None:
+    nb, h, w, ci = x.shape
+    co = dy.shape[3]
+    if tuple(dy.shape) != (nb, h, w, co) or tuple(dw.shape) != (9, ci, co):
+        raise ValueError("shape mismatch")
+    bp = ctypes.c_void_p(None) if dbias is None else _img(dbias, torch.float32, "dbias")
+    _check(lib().csx_conv3x3_backward_weights(_img(x, torch.float32, "x"), _img(dy, torch.float32, "dy"),
+                                              _img(dw, torch.float32, "dw"), bp, nb, h, w, ci, co,
+                                              _img(ws, torch.uint8, "ws"), ws.numel(), _stream()))
+
+
+def warm_loss(o: torch.Tensor, t: torch.Tensor, d: torch.Tensor, loss: torch.Tensor, ws: torch.Tensor) -> None:
+    nb = o.shape[0]
+    if o.shape != t.shape or o.shape != d.shape or loss.dtype != torch.float64 or not loss.is_cuda:
+        raise ValueError("shape / dtype mismatch")
+    _check(lib().csx_warm_loss(_img(o, torch.float32, "o"), _img(t, torch.float32, "t"), nb, o.numel() // nb,
+                               _img(d, torch.float32, "d"), ctypes.c_void_p(loss.data_ptr()),
+                               _img(ws, torch.uint8, "ws"), ws.numel(), _stream()))
+
+
+def adam_step(w: torch.Tensor, m: torch.Tensor, v: torch.Tensor, g: torch.Tensor, w16: Optional[torch.Tensor],
+              step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    n = w.numel()
+    for t, name in ((m, "m"), (v, "v"), (g, "g")):
+        if t.numel() != n:
+            raise ValueError(f"{name} size mismatch")
+    hp = ctypes.c_void_p(None)
+    if w16 is not None:
+        if w16.numel() != n:
+            raise ValueError("w16 size mismatch")
+        hp = _img(w16, torch.float16, "w16")
+    _check(lib().csx_adam_step(_img(w, torch.float32, "w"), _img(m, torch.float32, "m"),
+                               _img(v, torch.float32, "v"), _img(g, torch.float32, "g"), hp, n, lr, beta1,
+                               beta2, eps, int(step), _stream()))
+
+
+def to_half(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    if x.numel() != y.numel():
+        raise ValueError("size mismatch")
+    _check(lib().csx_to_half(_img(x, torch.float32, "x"), _img(y, torch.float16, "y"), x.numel(), _stream()))
+    return y
 
 
 class Batch:

@@ -136,9 +136,26 @@ def test_adam_minimises_a_quadratic():
     np.testing.assert_allclose(w, [3.0, -1.0], atol=1e-3)
 
 
-def test_warm_input_output():
-    b = np.array([2.0, 0.0, 5.0])
-    b1 = np.array([4.0, 0.0, 1.0])
-    np.testing.assert_allclose(cnn.warm_input(b, b1, 0.5), [1.0, 0.0, 10.0])
+def test_warm_input_is_the_first_em_factor(oracle_mod):
+    """u x is the first iterate of the unpenalised EM update from the uniform
+    start (beta = 0 in Alg. 5 reduces the update to f b2 / b1), and x = 1
+    wherever b1 > 0 when y is exactly the mean of a uniform image."""
+    from paper_1603_06400_amd import inputs
+    g = inputs.standard_geometry(8, 6, ndet=10)
+    o = oracle_mod.Oracle(g)
+    y = inputs.poisson_counts(o.forward(inputs.phantom(g, 3, 2)) * 50.0, 4)
+    b1 = o.sensitivity()
+    u = cnn.uniform_value(y, b1)
+    f1, _ = o.recon_step(y, None, np.full(b1.shape, u), 0.0)
+    x = cnn.warm_input(o, y)
+    seen = b1 > 0
+    np.testing.assert_allclose((u * x)[seen], f1[seen], rtol=1e-12)
+    y_flat = o.forward(np.full(b1.shape, 2.5))
+    x_flat = cnn.warm_input(o, y_flat)
+    np.testing.assert_allclose(x_flat[seen], 1.0, rtol=1e-12)
+    assert np.all(x_flat[~seen] == 0.0)
+
+
+def test_warm_output():
     f0 = cnn.warm_output(np.array([-50.0, 0.0]), 2.0, 1e-3)
     assert np.all(f0 > 0) and f0[1] == pytest.approx(2.0 * (np.log(2.0) + 1e-3))
