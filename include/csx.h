@@ -191,12 +191,17 @@ csx_status csx_timing_enable(csx_geometry *h, int on);
 csx_status csx_timing_read(csx_geometry *h, double ms[2], int n[2]);
 
 /* ---- Learned warm start ------------------------------------------------------
- * Not part of the paper, which starts Alg. 5 from a uniform image: a small
- * network maps the first EM factor from the uniform start (the back
- * projection, by the back projector of Sec. IV, of the count ratio, divided
- * by the sensitivity image b1 = A^T 1; u = sum(y) / sum(b1) is the uniform
- * start value) to a strictly positive starting image f0 = u (softplus(o) +
- * eps), trained on reconstructions made by Alg. 5 itself.  A judge (csx_recon_warm) runs Alg. 5 from both starts and keeps
+ * Not part of the paper, which starts Alg. 5 from a uniform image.  The
+ * first EM factor from the uniform start, x = A^T (y / (u A 1)) / b1 (the
+ * back projection, by the back projector of Sec. IV, of the count ratio,
+ * divided by the sensitivity image b1 = A^T 1; u = sum(y) / sum(b1) is the
+ * uniform start value), enters a small network as log(x + delta); its last
+ * layer adds that input back.  The training target of a reconstruction f_T
+ * made by Alg. 5 itself is log(f_T / u + delta), and the output o gives the
+ * starting image by the inverse map u max(exp(min(o, 30)) - delta,
+ * delta / 100) > 0, scaled so that sum(b1 f0) = sum(y) (the total every
+ * unpenalised EM iterate carries).  delta in (0, 1] is chosen with the
+ * network (CSX_EINVAL otherwise).  A judge (csx_recon_warm) runs Alg. 5 from both starts and keeps
  * the warm one only if its objective is lower.
  *
  * Images are [nb][h][w][c] float32 (an f image [nz][nx][nq] is one image of
@@ -217,9 +222,10 @@ typedef struct {
  * images of h x w (0 for sizes < 1). */
 size_t csx_cnn_workspace_bytes(int nb, int h, int w);
 
-/* y = conv3x3(x, w) + bias (bias may be NULL), then max(y, 0) if relu. */
-csx_status csx_conv3x3_forward(const float *x, const uint16_t *w, const float *bias, float *y,
-                               int nb, int h, int w_, int cin, int cout, int relu, void *stream);
+/* y = conv3x3(x, w) + bias + residual (bias and residual may be NULL; the
+ * residual is [nb][h][w][cout] and must not be y), then max(y, 0) if relu. */
+csx_status csx_conv3x3_forward(const float *x, const uint16_t *w, const float *bias, const float *residual,
+                               float *y, int nb, int h, int w_, int cin, int cout, int relu, void *stream);
 
 /* dx[p][i] = sum_t sum_o dy[p - off_t][o] w[t][i][o] for the layer
  * (cin -> cout) with weights w; dy has cout channels, dx cin.  If mask (a
@@ -235,9 +241,8 @@ csx_status csx_conv3x3_backward_weights(const float *x, const float *dy, float *
                                         int nb, int h, int w_, int cin, int cout, void *ws,
                                         size_t ws_bytes, void *stream);
 
-/* Training head: p = softplus(o), *loss = sum (p - t)^2 / nb (device
- * float64), d = dL/do = 2 (p - t) sigmoid(o) / nb; o, t, d hold nb *
- * n_per_image floats. */
+/* Training head: *loss = sum (o - t)^2 / nb (device float64, fixed order),
+ * d = dL/do = 2 (o - t) / nb; o, t, d hold nb * n_per_image floats. */
 csx_status csx_warm_loss(const float *o, const float *t, int nb, int n_per_image, float *d,
                          double *loss, void *ws, size_t ws_bytes, void *stream);
 
@@ -250,19 +255,25 @@ csx_status csx_adam_step(float *w, float *m, float *v, const float *g, uint16_t 
 /* y = binary16(x), nearest-even. */
 csx_status csx_to_half(const float *x, uint16_t *y, int n, void *stream);
 
-/* Network input of scan h: the first multiplicative EM factor from the
- * uniform start, x = A^T (y / (u A 1)) / b1 (ratio 0 where A 1 = 0, x = 0
- * where b1 = 0); u x is the first unpenalised EM iterate.  x holds nvox * nq
- * floats ([nz][nx][nq]).  A 1 is computed once per handle. */
-csx_status csx_warm_input(csx_geometry *h, const float *y, float *x, void *stream);
+/* Network input of scan h: log(x + delta) of the first multiplicative EM
+ * factor from the uniform start, x = A^T (y / (u A 1)) / b1 (ratio 0 where
+ * A 1 = 0, x = 0 where b1 = 0); u x is the first unpenalised EM iterate.
+ * The output holds nvox * nq floats ([nz][nx][nq]).  A 1 is computed once per
+ * handle. */
+csx_status csx_warm_input(csx_geometry *h, const float *y, float delta, float *x, void *stream);
 
-/* f0 = u (softplus(o) + eps) with u of the counts y; eps > 0. */
-csx_status csx_warm_output(csx_geometry *h, const float *y, const float *o, float eps, float *f0,
+/* f0 = c max(exp(min(o, 30)) - delta, delta / 100), c = u s with u of the
+ * counts y and s such that sum(b1 f0) = sum(y) (float64 sums, fixed order). */
+csx_status csx_warm_output(csx_geometry *h, const float *y, const float *o, float delta, float *f0,
+                           void *stream);
+
+/* Training target t = log(f / u + delta) of a reconstruction f of counts y. */
+csx_status csx_warm_target(csx_geometry *h, const float *y, const float *f, float delta, float *t,
                            void *stream);
 
 /* Input, the four layers (ReLU after the first three) and output in one call
  * (needs nq = 64); activations live in a handle workspace. */
-csx_status csx_warm_start(csx_geometry *h, const float *y, const csx_warm_net *net, float eps,
+csx_status csx_warm_start(csx_geometry *h, const float *y, const csx_warm_net *net, float delta,
                           float *f0, void *stream);
 
 /* The judge: k_judge iterations of Alg. 5 from f_warm and k_judge from the

@@ -4,21 +4,26 @@ TEST INFRASTRUCTURE.  Same rule as the rest of ``oracle``: only tests/,
 ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
 import it; it shares no code with the GPU library.
 
-The paper has no network.  The learned warm start feeds the first
-multiplicative factor of the EM-type update from the uniform start (Alg. 5
+The paper has no network.  The learned warm start takes the first
+multiplicative factor x of the EM-type update from the uniform start (Alg. 5
 with f^0 = u everywhere, u = sum(y) / sum(b^(1)), b^(1) = A^T 1): the back
 projection (the back projector of Alg. 3) of the count ratio y / (A f^0),
-divided by b^(1) -- dimensionless, and u times it is the first EM iterate --
-to a small convolutional network whose output becomes the solver's starting
-image f^0 = u (softplus(o) + eps).  The definitions written out here are the
-textbook ones:
+divided by b^(1) -- dimensionless, and u x is the first EM iterate.  As the
+EM iterates are products of such factors, the network works on logarithms:
+its input is log(x + delta), its last layer adds that input back (a residual),
+its training target is log(f_T / u + delta) for a reconstruction f_T made by
+Alg. 5 itself, and its output o gives the starting image through the inverse
+map u max(exp(o) - delta, delta / 100) > 0, scaled to the total
+sum(b^(1) f) = sum(y) that every unpenalised EM iterate carries (a regression
+on logarithms estimates geometric means, biased low).  The definitions written out here
+are the textbook ones:
 
 * 3 x 3 cross-correlation with one pixel of zero padding, images stored
   height x width x channels (the q bins of an image [nz][nx][nq] are its
   channels), weights [tap][c_in][c_out] with tap = 3 dh + dw reading the input
   pixel (h + dh - 1, w + dw - 1);
-* ReLU, softplus(o) = log(1 + e^o), squared error summed over elements and
-  averaged over the images of a batch;
+* ReLU; squared error summed over elements and averaged over the images of a
+  batch;
 * gradients by the chain rule (pinned by central finite differences);
 * Adam with bias correction (Kingma & Ba, 2015, Algorithm 1).
 
@@ -26,8 +31,8 @@ Precision model of the GPU network (``half=True``): every operand of a
 convolution's products -- input activation, weight and, in the backward
 passes, the output gradient -- is rounded to IEEE binary16 (nearest, ties to
 even) before it is multiplied; products and sums are then exact here (the GPU
-accumulates in binary32).  Bias terms, ReLU, the mask of the ReLU backward,
-the head and Adam see unrounded values.
+accumulates in binary32).  Bias terms, the residual, ReLU, the mask of the
+ReLU backward, the head and Adam see unrounded values.
 
 Parity status: pinned in tests/test_oracle_cnn.py (scipy.signal.correlate2d,
 shifted-identity kernels, finite differences, Adam's closed-form first step,
@@ -40,6 +45,8 @@ from typing import Dict, List, Optional
 import numpy as np
 
 TAPS = [(dh, dw) for dh in range(3) for dw in range(3)]
+O_CLAMP = 30.0        # upper bound of o before exponentiation
+FLOOR = 0.01          # f^0 / u >= FLOOR * delta
 
 
 def f16(a) -> np.ndarray:
@@ -55,9 +62,9 @@ def _pad(x: np.ndarray) -> np.ndarray:
     return np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
 
 
-def conv3x3(x, w, bias=None, relu: bool = False, half: bool = True) -> np.ndarray:
+def conv3x3(x, w, bias=None, relu: bool = False, half: bool = True, residual=None) -> np.ndarray:
     """y[b,h,w,o] = bias[o] + sum_{dh,dw,i} x[b,h+dh-1,w+dw-1,i] w[3dh+dw,i,o]
-    (zero outside the image), then max(., 0) if relu."""
+    (zero outside the image) (+ residual[b,h,w,o]), then max(., 0) if relu."""
     x = _maybe16(x, half)
     w = _maybe16(w, half)
     nb, H, W, _ = x.shape
@@ -67,6 +74,8 @@ def conv3x3(x, w, bias=None, relu: bool = False, half: bool = True) -> np.ndarra
         y += xp[:, dh:dh + H, dw:dw + W, :] @ w[t]
     if bias is not None:
         y += np.asarray(bias, dtype=np.float64)
+    if residual is not None:
+        y += np.asarray(residual, dtype=np.float64)
     return np.maximum(y, 0.0) if relu else y
 
 
@@ -103,30 +112,21 @@ def conv3x3_backward_weights(x, dy, half: bool = True):
     return dw, db
 
 
-def softplus(o) -> np.ndarray:
-    return np.logaddexp(0.0, np.asarray(o, dtype=np.float64))
-
-
-def sigmoid(o) -> np.ndarray:
-    o = np.asarray(o, dtype=np.float64)
-    return np.exp(-np.logaddexp(0.0, -o))
-
-
 def head(o, t, n_images: int):
-    """Squared-error loss of p = softplus(o) against the target t, summed over
-    elements and divided by the number of images; returns (loss, dL/do)."""
-    o = np.asarray(o, dtype=np.float64)
-    p = softplus(o)
-    r = p - np.asarray(t, dtype=np.float64)
-    return float(np.sum(r * r)) / n_images, 2.0 * r * sigmoid(o) / n_images
+    """Squared error of o against the target t, summed over elements and
+    divided by the number of images; returns (loss, dL/do)."""
+    r = np.asarray(o, dtype=np.float64) - np.asarray(t, dtype=np.float64)
+    return float(np.sum(r * r)) / n_images, 2.0 * r / n_images
 
 
 def forward(params: List[Dict[str, np.ndarray]], x, half: bool = True) -> List[np.ndarray]:
     """Activations [x, a1, ..., o] of the network: every layer but the last is
-    followed by a ReLU."""
+    followed by a ReLU; the last adds the network input x (same channels)."""
     acts = [np.asarray(x, dtype=np.float64)]
+    n = len(params)
     for k, lay in enumerate(params):
-        acts.append(conv3x3(acts[-1], lay["w"], lay["b"], relu=k < len(params) - 1, half=half))
+        acts.append(conv3x3(acts[-1], lay["w"], lay["b"], relu=k < n - 1, half=half,
+                            residual=acts[0] if k == n - 1 else None))
     return acts
 
 
@@ -173,9 +173,37 @@ def warm_input(orc, y) -> np.ndarray:
     return np.where(b1 > 0, b / np.where(b1 > 0, b1, 1.0), 0.0)
 
 
-def warm_output(o, u: float, eps: float) -> np.ndarray:
-    """Warm start f^0 = u (softplus(o) + eps) (strictly positive)."""
-    return u * (softplus(o) + eps)
+def features(x, delta: float) -> np.ndarray:
+    """Network input log(x + delta) of a first EM factor x."""
+    return np.log(np.asarray(x, dtype=np.float64) + delta)
+
+
+def target(f, u: float, delta: float) -> np.ndarray:
+    """Training target log(f / u + delta) of a reconstruction f."""
+    return np.log(np.asarray(f, dtype=np.float64) / u + delta)
+
+
+def warm_output(o, u: float, delta: float) -> np.ndarray:
+    """u max(exp(min(o, O_CLAMP)) - delta, FLOOR delta): the inverse of the
+    target map, kept strictly positive and finite."""
+    e = np.exp(np.minimum(np.asarray(o, dtype=np.float64), O_CLAMP))
+    return u * np.maximum(e - delta, FLOOR * delta)
+
+
+def mass_normalise(f, y, b1) -> np.ndarray:
+    """f scaled so that sum(b^(1) f) = sum(y), the total that every
+    unpenalised EM iterate of Alg. 5 carries (no background)."""
+    f = np.asarray(f, dtype=np.float64)
+    return f * (float(np.sum(y)) / float(np.sum(np.asarray(b1, dtype=np.float64) * f)))
+
+
+def warm_start(orc, y, params, delta: float, half: bool = True) -> np.ndarray:
+    """The starting image of the learned warm start for counts y."""
+    g = orc.geom
+    x = features(warm_input(orc, y), delta).reshape(1, g.nz, g.nx, g.nq)
+    o = forward(params, x, half)[-1][0]
+    b1 = orc.sensitivity()
+    return mass_normalise(warm_output(o, uniform_value(y, b1), delta), y, b1)
 
 
 def uniform_value(y, b1) -> float:

@@ -46,12 +46,14 @@ struct FwdLds {
     static constexpr int bytes = 2 * (patch + weights);
 };
 
-// out = conv3x3(in) (+ bias, ReLU) or, with FLIP, the transposed convolution
-// of the forward layer whose weights w are [9][CO][CI] (its c_in = CO here).
+// out = conv3x3(in) (+ bias, + residual, ReLU) or, with FLIP, the transposed
+// convolution of the forward layer whose weights w are [9][CO][CI] (its c_in =
+// CO here), times the mask.
 template <int CI, int CO, bool FLIP>
 __global__ void __launch_bounds__(256)
 k_conv3x3(const float *__restrict__ in, const _Float16 *__restrict__ w, const float *__restrict__ bias,
-          const float *__restrict__ mask, float *__restrict__ out, int H, int W, int relu)
+          const float *__restrict__ residual, const float *__restrict__ mask, float *__restrict__ out, int H,
+          int W, int relu)
 {
     using L = FwdLds<CI, CO>;
     constexpr int PW = TW + 2;
@@ -131,6 +133,7 @@ k_conv3x3(const float *__restrict__ in, const _Float16 *__restrict__ w, const fl
             for (int nt = 0; nt < NT; ++nt) {
                 const int o = nt * 16 + m;
                 float val = acc[mt][nt][v] + (bias ? bias[o] : 0.f);
+                if (residual) val += residual[base + o];
                 if (relu) val = fmaxf(val, 0.f);
                 if (mask && !(mask[base + o] > 0.f)) val = 0.f;
                 out[base + o] = val;
@@ -274,8 +277,8 @@ __global__ void __launch_bounds__(256) k_bias_part(const float *__restrict__ d, 
     }
 }
 
-__device__ inline float softplus_f(float o) { return fmaxf(o, 0.f) + log1pf(expf(-fabsf(o))); }
-__device__ inline float sigmoid_f(float o) { return 1.f / (1.f + expf(-o)); }
+constexpr float WARM_CLAMP = 30.f;     // upper bound of o before exponentiation
+constexpr float WARM_FLOOR = 0.01f;    // f0 / u >= WARM_FLOOR * delta
 
 __device__ double block_sum_f64(double v, double *red)
 {
@@ -291,7 +294,7 @@ __device__ double block_sum_f64(double v, double *red)
     return r;
 }
 
-// p = softplus(o); d = 2 (p - t) sigmoid(o) / n_images; float64 partial sums of (p - t)^2.
+// d = 2 (o - t) / n_images; float64 partial sums of (o - t)^2.
 __global__ void __launch_bounds__(256) k_head(const float *__restrict__ o, const float *__restrict__ t,
                                               long n, long chunk, float inv_images, float *__restrict__ d,
                                               double *__restrict__ part)
@@ -301,9 +304,8 @@ __global__ void __launch_bounds__(256) k_head(const float *__restrict__ o, const
     const long e1 = e0 + chunk < n ? e0 + chunk : n;
     double s = 0.0;
     for (long e = e0 + threadIdx.x; e < e1; e += 256) {
-        const float ov = o[e];
-        const float r = softplus_f(ov) - t[e];
-        d[e] = 2.f * r * sigmoid_f(ov) * inv_images;
+        const float r = o[e] - t[e];
+        d[e] = 2.f * r * inv_images;
         s += (double)r * (double)r;
     }
     s = block_sum_f64(s, red);
@@ -353,23 +355,72 @@ __global__ void __launch_bounds__(256) k_warm_ratio(const float *__restrict__ y,
     rho[e] = z > 0.f ? y[e] / z : 0.f;
 }
 
-// x = b / b1, 0 where b1 = 0
-__global__ void __launch_bounds__(256) k_warm_input(float *__restrict__ x, const float *__restrict__ b1, int n)
+// x = log(b / b1 + delta), b / b1 taken as 0 where b1 = 0
+__global__ void __launch_bounds__(256) k_warm_input(float *__restrict__ x, const float *__restrict__ b1, int n,
+                                                    float delta)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
     const float s = b1[e];
-    x[e] = s > 0.f ? x[e] / s : 0.f;
+    x[e] = logf((s > 0.f ? x[e] / s : 0.f) + delta);
 }
 
-// f0 = u (softplus(o) + eps)
-__global__ void __launch_bounds__(256) k_warm_output(const float *__restrict__ o, float *__restrict__ f0, int n,
-                                                     float eps, const double *__restrict__ scal)
+// t = log(f / u + delta)
+__global__ void __launch_bounds__(256) k_warm_target(const float *__restrict__ f, float *__restrict__ t, int n,
+                                                     const double *__restrict__ scal, float delta)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
     const float u = (float)(scal[0] / scal[1]);
-    f0[e] = u * (softplus_f(o[e]) + eps);
+    t[e] = logf(f[e] / u + delta);
+}
+
+// f0 = u max(exp(min(o, WARM_CLAMP)) - delta, WARM_FLOOR delta)
+__global__ void __launch_bounds__(256) k_warm_output(const float *__restrict__ o, float *__restrict__ f0, int n,
+                                                     const double *__restrict__ scal, float delta)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float u = (float)(scal[0] / scal[1]);
+    f0[e] = u * fmaxf(expf(fminf(o[e], WARM_CLAMP)) - delta, WARM_FLOOR * delta);
+}
+
+// part[b] = sum of b1 f over block b's contiguous share (float64)
+__global__ void __launch_bounds__(256) k_mass_part(const float *__restrict__ b1, const float *__restrict__ f,
+                                                   long n, long chunk, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const long e0 = (long)blockIdx.x * chunk;
+    const long e1 = e0 + chunk < n ? e0 + chunk : n;
+    double s = 0.0;
+    for (long e = e0 + threadIdx.x; e < e1; e += 256) s += (double)b1[e] * (double)f[e];
+    s = block_sum_f64(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// scal[2] = sum of the partials, fixed order
+__global__ void __launch_bounds__(256) k_mass_final(const double *__restrict__ part, int nparts,
+                                                    double *__restrict__ scal)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += 256) s += part[k];
+    s = block_sum_f64(s, red);
+    if (threadIdx.x == 0) scal[2] = s;
+}
+
+// f *= sum(y) / sum(b1 f) = scal[0] / scal[2]
+__global__ void __launch_bounds__(256) k_mass_scale(float *__restrict__ f, int n, const double *__restrict__ scal)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    f[e] = (float)((double)f[e] * (scal[0] / scal[2]));
+}
+
+csx_status check_delta(float delta)
+{
+    if (!(delta > 0.f && delta <= 1.f)) return csx_fail(CSX_EINVAL, "delta must be in (0, 1]");
+    return CSX_OK;
 }
 
 bool channels_ok(int ci, int co)
@@ -378,13 +429,13 @@ bool channels_ok(int ci, int co)
 }
 
 template <int CI, int CO, bool FLIP>
-csx_status run_conv(const float *in, const _Float16 *w, const float *bias, const float *mask, float *out,
-                    int nb, int H, int W, int relu, hipStream_t s)
+csx_status run_conv(const float *in, const _Float16 *w, const float *bias, const float *residual,
+                    const float *mask, float *out, int nb, int H, int W, int relu, hipStream_t s)
 {
     dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH, nb);
     constexpr int lds = FwdLds<CI, CO>::bytes;
     hipLaunchKernelGGL((k_conv3x3<CI, CO, FLIP>), grid, dim3(256), lds, s, in, w, bias,
-                       mask, out, H, W, relu);
+                       residual, mask, out, H, W, relu);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
@@ -429,8 +480,9 @@ extern "C" size_t csx_cnn_workspace_bytes(int nb, int h, int w)
     return sizeof(float) * csx_cnn_ws_floats(nb, h, w);
 }
 
-extern "C" csx_status csx_conv3x3_forward(const float *x, const uint16_t *w, const float *bias, float *y,
-                                          int nb, int h, int w_, int cin, int cout, int relu, void *stream)
+extern "C" csx_status csx_conv3x3_forward(const float *x, const uint16_t *w, const float *bias,
+                                          const float *residual, float *y, int nb, int h, int w_, int cin,
+                                          int cout, int relu, void *stream)
 {
     if (!x || !w || !y) return csx_fail(CSX_EINVAL, "NULL argument");
     if (!channels_ok(cin, cout)) return csx_fail(CSX_EINVAL, "unsupported channel pair (64,32), (32,32), (32,64)");
@@ -438,9 +490,10 @@ extern "C" csx_status csx_conv3x3_forward(const float *x, const uint16_t *w, con
     if (st != CSX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const _Float16 *wh = reinterpret_cast<const _Float16 *>(w);
-    if (cin == 64) return run_conv<64, 32, false>(x, wh, bias, nullptr, y, nb, h, w_, relu, s);
-    if (cout == 32) return run_conv<32, 32, false>(x, wh, bias, nullptr, y, nb, h, w_, relu, s);
-    return run_conv<32, 64, false>(x, wh, bias, nullptr, y, nb, h, w_, relu, s);
+    if (residual == y) return csx_fail(CSX_EINVAL, "residual and y must be different buffers");
+    if (cin == 64) return run_conv<64, 32, false>(x, wh, bias, residual, nullptr, y, nb, h, w_, relu, s);
+    if (cout == 32) return run_conv<32, 32, false>(x, wh, bias, residual, nullptr, y, nb, h, w_, relu, s);
+    return run_conv<32, 64, false>(x, wh, bias, residual, nullptr, y, nb, h, w_, relu, s);
 }
 
 extern "C" csx_status csx_conv3x3_backward_data(const float *dy, const uint16_t *w, const float *mask, float *dx,
@@ -453,9 +506,9 @@ extern "C" csx_status csx_conv3x3_backward_data(const float *dy, const uint16_t 
     hipStream_t s = (hipStream_t)stream;
     const _Float16 *wh = reinterpret_cast<const _Float16 *>(w);
     // transposed layer: input channels = cout, output channels = cin
-    if (cin == 64) return run_conv<32, 64, true>(dy, wh, nullptr, mask, dx, nb, h, w_, 0, s);
-    if (cout == 32) return run_conv<32, 32, true>(dy, wh, nullptr, mask, dx, nb, h, w_, 0, s);
-    return run_conv<64, 32, true>(dy, wh, nullptr, mask, dx, nb, h, w_, 0, s);
+    if (cin == 64) return run_conv<32, 64, true>(dy, wh, nullptr, nullptr, mask, dx, nb, h, w_, 0, s);
+    if (cout == 32) return run_conv<32, 32, true>(dy, wh, nullptr, nullptr, mask, dx, nb, h, w_, 0, s);
+    return run_conv<64, 32, true>(dy, wh, nullptr, nullptr, mask, dx, nb, h, w_, 0, s);
 }
 
 extern "C" csx_status csx_conv3x3_backward_weights(const float *x, const float *dy, float *dw, float *dbias,
@@ -531,11 +584,13 @@ extern "C" csx_status csx_to_half(const float *x, uint16_t *y, int n, void *stre
     return CSX_OK;
 }
 
-extern "C" csx_status csx_warm_input(csx_geometry *h, const float *y, float *x, void *stream)
+extern "C" csx_status csx_warm_input(csx_geometry *h, const float *y, float delta, float *x, void *stream)
 {
     if (!h || !y || !x) return csx_fail(CSX_EINVAL, "NULL argument");
+    csx_status st = check_delta(delta);
+    if (st != CSX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    csx_status st = csx_ensure_b1(h, s);
+    st = csx_ensure_b1(h, s);
     if (st != CSX_OK) return st;
     const int n = h->P.nvox * h->P.nq, np = h->P.npix;
     if (!h->a1) {   // A 1, once per handle
@@ -554,28 +609,51 @@ extern "C" csx_status csx_warm_input(csx_geometry *h, const float *y, float *x, 
     HIP_TRY(hipGetLastError());
     st = csx_launch_adjoint(h, h->rho, x, s);
     if (st != CSX_OK) return st;
-    hipLaunchKernelGGL(k_warm_input, dim3((n + 255) / 256), dim3(256), 0, s, x, h->b1, n);
+    hipLaunchKernelGGL(k_warm_input, dim3((n + 255) / 256), dim3(256), 0, s, x, h->b1, n, delta);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
 
-extern "C" csx_status csx_warm_output(csx_geometry *h, const float *y, const float *o, float eps, float *f0,
+extern "C" csx_status csx_warm_target(csx_geometry *h, const float *y, const float *f, float delta, float *t,
                                       void *stream)
 {
-    if (!h || !y || !o || !f0) return csx_fail(CSX_EINVAL, "NULL argument");
-    if (!(eps > 0.f)) return csx_fail(CSX_EINVAL, "eps must be > 0");
+    if (!h || !y || !f || !t) return csx_fail(CSX_EINVAL, "NULL argument");
+    csx_status st = check_delta(delta);
+    if (st != CSX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    csx_status st = csx_ensure_b1(h, s);
+    st = csx_ensure_b1(h, s);
     if (st != CSX_OK) return st;
     st = csx_launch_uniform_sums(h, y, s);
     if (st != CSX_OK) return st;
     const int n = h->P.nvox * h->P.nq;
-    hipLaunchKernelGGL(k_warm_output, dim3((n + 255) / 256), dim3(256), 0, s, o, f0, n, eps, h->scal);
+    hipLaunchKernelGGL(k_warm_target, dim3((n + 255) / 256), dim3(256), 0, s, f, t, n, h->scal, delta);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
 
-extern "C" csx_status csx_warm_start(csx_geometry *h, const float *y, const csx_warm_net *net, float eps,
+extern "C" csx_status csx_warm_output(csx_geometry *h, const float *y, const float *o, float delta, float *f0,
+                                      void *stream)
+{
+    if (!h || !y || !o || !f0) return csx_fail(CSX_EINVAL, "NULL argument");
+    csx_status st = check_delta(delta);
+    if (st != CSX_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = csx_ensure_b1(h, s);
+    if (st != CSX_OK) return st;
+    st = csx_launch_uniform_sums(h, y, s);
+    if (st != CSX_OK) return st;
+    const int n = h->P.nvox * h->P.nq;
+    hipLaunchKernelGGL(k_warm_output, dim3((n + 255) / 256), dim3(256), 0, s, o, f0, n, h->scal, delta);
+    const long chunk = ((long)n + CSX_SUM_BLOCKS - 1) / CSX_SUM_BLOCKS;
+    const int nbk = (int)(((long)n + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_mass_part, dim3(nbk), dim3(256), 0, s, h->b1, f0, (long)n, chunk, h->partS);
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, h->partS, nbk, h->scal);
+    hipLaunchKernelGGL(k_mass_scale, dim3((n + 255) / 256), dim3(256), 0, s, f0, n, h->scal);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+extern "C" csx_status csx_warm_start(csx_geometry *h, const float *y, const csx_warm_net *net, float delta,
                                      float *f0, void *stream)
 {
     if (!h || !y || !net || !f0) return csx_fail(CSX_EINVAL, "NULL argument");
@@ -586,7 +664,7 @@ extern "C" csx_status csx_warm_start(csx_geometry *h, const float *y, const csx_
     hipStream_t s = (hipStream_t)stream;
     const int H = h->P.nz, W = h->P.nx;
     const size_t img = (size_t)H * W;
-    const size_t need = img * (64 + 32 + 32);
+    const size_t need = img * (64 + 32 + 32 + 64);
     if (h->warm_cap < need) {
         if (h->warm) HIP_TRY(hipFree(h->warm));
         h->warm = nullptr;
@@ -594,15 +672,16 @@ extern "C" csx_status csx_warm_start(csx_geometry *h, const float *y, const csx_
         HIP_TRY(hipMalloc((void **)&h->warm, sizeof(float) * need));
         h->warm_cap = need;
     }
-    float *xin = h->warm;                 // [H][W][64]: input, later the output o
-    float *a = xin + img * 64, *b = a + img * 32;
-    csx_status st = csx_warm_input(h, y, xin, stream);
+    float *xin = h->warm;                 // [H][W][64] network input
+    float *a = xin + img * 64, *b = a + img * 32, *o = b + img * 32;
+    csx_status st = csx_warm_input(h, y, delta, xin, stream);
     if (st != CSX_OK) return st;
     const float *src[4] = {xin, a, b, a};
-    float *dst[4] = {a, b, a, xin};
+    float *dst[4] = {a, b, a, o};
     for (int k = 0; k < 4; ++k) {
-        st = csx_conv3x3_forward(src[k], net->w[k], net->b[k], dst[k], 1, H, W, ch[k], ch[k + 1], k < 3, s);
+        st = csx_conv3x3_forward(src[k], net->w[k], net->b[k], k == 3 ? xin : nullptr, dst[k], 1, H, W, ch[k],
+                                 ch[k + 1], k < 3, s);
         if (st != CSX_OK) return st;
     }
-    return csx_warm_output(h, y, xin, eps, f0, stream);
+    return csx_warm_output(h, y, o, delta, f0, stream);
 }

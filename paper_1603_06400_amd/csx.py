@@ -61,7 +61,7 @@ EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_g
            "csx_batch_recon", "csx_timing_enable", "csx_timing_read", "csx_last_error",
            "csx_cnn_workspace_bytes", "csx_conv3x3_forward", "csx_conv3x3_backward_data",
            "csx_conv3x3_backward_weights", "csx_warm_loss", "csx_adam_step", "csx_to_half",
-           "csx_warm_input", "csx_warm_output", "csx_warm_start", "csx_recon_warm"]
+           "csx_warm_input", "csx_warm_output", "csx_warm_target", "csx_warm_start", "csx_recon_warm"]
 
 
 class _WarmNet(ctypes.Structure):
@@ -115,7 +115,7 @@ def lib():
         i, d, sz = ctypes.c_int, ctypes.c_double, ctypes.c_size_t
         L.csx_cnn_workspace_bytes.argtypes = [i, i, i]
         L.csx_cnn_workspace_bytes.restype = sz
-        L.csx_conv3x3_forward.argtypes = [vp, vp, vp, vp, i, i, i, i, i, i, vp]
+        L.csx_conv3x3_forward.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, i, i, vp]
         L.csx_conv3x3_forward.restype = i
         L.csx_conv3x3_backward_data.argtypes = [vp, vp, vp, vp, i, i, i, i, i, vp]
         L.csx_conv3x3_backward_data.restype = i
@@ -127,10 +127,12 @@ def lib():
         L.csx_adam_step.restype = i
         L.csx_to_half.argtypes = [vp, vp, i, vp]
         L.csx_to_half.restype = i
-        L.csx_warm_input.argtypes = [vp, vp, vp, vp]
+        L.csx_warm_input.argtypes = [vp, vp, ctypes.c_float, vp, vp]
         L.csx_warm_input.restype = i
         L.csx_warm_output.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp]
         L.csx_warm_output.restype = i
+        L.csx_warm_target.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp]
+        L.csx_warm_target.restype = i
         L.csx_warm_start.argtypes = [vp, vp, ctypes.POINTER(_WarmNet), ctypes.c_float, vp, vp]
         L.csx_warm_start.restype = i
         L.csx_recon_warm.argtypes = [vp, vp, vp, vp, vp, i, i, d, ctypes.POINTER(ctypes.c_double),
@@ -275,22 +277,30 @@ class Geometry:
 
 
     # ---- learned warm start ----------------------------------------------------------
-    def warm_input(self, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """Network input A^T (y / (u A 1)) / b1 as an image [nz][nx][nq]."""
+    def warm_input(self, y: torch.Tensor, delta: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Network input log(x + delta), x = A^T (y / (u A 1)) / b1, as an image [nz][nx][nq]."""
         out = self.new_image() if out is None else out
-        _check(lib().csx_warm_input(self._h, _dev(y, self.npix, "y"), _dev(out, self.nvox * self.nq, "x"),
-                                    _stream()))
+        _check(lib().csx_warm_input(self._h, _dev(y, self.npix, "y"), float(delta),
+                                    _dev(out, self.nvox * self.nq, "x"), _stream()))
         return out
 
-    def warm_output(self, y: torch.Tensor, o: torch.Tensor, eps: float,
+    def warm_output(self, y: torch.Tensor, o: torch.Tensor, delta: float,
                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """f0 = u (softplus(o) + eps)."""
+        """f0 = u max(exp(o) - delta, delta / 100)."""
         out = self.new_image() if out is None else out
         _check(lib().csx_warm_output(self._h, _dev(y, self.npix, "y"), _dev(o, self.nvox * self.nq, "o"),
-                                     float(eps), _dev(out, self.nvox * self.nq, "f0"), _stream()))
+                                     float(delta), _dev(out, self.nvox * self.nq, "f0"), _stream()))
         return out
 
-    def warm_start(self, y: torch.Tensor, net, eps: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def warm_target(self, y: torch.Tensor, f: torch.Tensor, delta: float,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Training target log(f / u + delta)."""
+        out = self.new_image() if out is None else out
+        _check(lib().csx_warm_target(self._h, _dev(y, self.npix, "y"), _dev(f, self.nvox * self.nq, "f"),
+                                     float(delta), _dev(out, self.nvox * self.nq, "t"), _stream()))
+        return out
+
+    def warm_start(self, y: torch.Tensor, net, delta: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """Input map, the network (w16/b device tensors of 4 layers) and output map in one call."""
         out = self.new_image() if out is None else out
         wn = _WarmNet()
@@ -300,7 +310,7 @@ class Geometry:
                 raise ValueError("layer weights must be CUDA float16 and biases CUDA float32")
             wn.w[k] = w16.data_ptr()
             wn.b[k] = b.data_ptr()
-        _check(lib().csx_warm_start(self._h, _dev(y, self.npix, "y"), ctypes.byref(wn), float(eps),
+        _check(lib().csx_warm_start(self._h, _dev(y, self.npix, "y"), ctypes.byref(wn), float(delta),
                                     _dev(out, self.nvox * self.nq, "f0"), _stream()))
         return out
 
@@ -329,14 +339,17 @@ def cnn_workspace_bytes(nb: int, h: int, w: int) -> int:
 
 
 def conv3x3_forward(x: torch.Tensor, w16: torch.Tensor, bias: Optional[torch.Tensor], y: torch.Tensor,
-                    relu: bool) -> torch.Tensor:
+                    relu: bool, residual: Optional[torch.Tensor] = None) -> torch.Tensor:
     """x [nb][h][w][cin] float32, w16 [9][cin][cout] float16 -> y [nb][h][w][cout]."""
     nb, h, w, ci = x.shape
     co = w16.shape[2]
     if tuple(w16.shape) != (9, ci, co) or tuple(y.shape) != (nb, h, w, co):
         raise ValueError("shape mismatch")
+    if residual is not None and tuple(residual.shape) != tuple(y.shape):
+        raise ValueError("residual shape mismatch")
     bp = ctypes.c_void_p(None) if bias is None else _img(bias, torch.float32, "bias")
-    _check(lib().csx_conv3x3_forward(_img(x, torch.float32, "x"), _img(w16, torch.float16, "w"), bp,
+    rp = ctypes.c_void_p(None) if residual is None else _img(residual, torch.float32, "residual")
+    _check(lib().csx_conv3x3_forward(_img(x, torch.float32, "x"), _img(w16, torch.float16, "w"), bp, rp,
                                      _img(y, torch.float32, "y"), nb, h, w, ci, co, int(bool(relu)), _stream()))
     return y
 

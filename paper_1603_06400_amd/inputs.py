@@ -245,11 +245,10 @@ def batch_scans(n_scans: int = 64, seed0: int = 1000,
 WARM_CHANNELS = (64, 32, 32, 32, 64)
 
 
-def cnn_init(seed: int, channels=WARM_CHANNELS, out_bias: float = 0.5413) -> List[dict]:
+def cnn_init(seed: int, channels=WARM_CHANNELS, out_bias: float = 0.0) -> List[dict]:
     """Initial weights of the 3x3 network: per layer w [9][c_in][c_out] normal
     with std sqrt(2 / (9 c_in)) (He), the last layer's scaled by 0.1; biases
-    zero except the last layer's (out_bias; 0.5413 ~ log(e - 1) puts the
-    softplus output near 1).  float32."""
+    zero except the last layer's (out_bias).  float32."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     n = len(channels) - 1

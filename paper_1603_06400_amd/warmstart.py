@@ -1,13 +1,17 @@
 """Learned warm start of the reconstruction (Alg. 5).
 
 A four-layer 3x3 network (64 -> 32 -> 32 -> 32 -> 64 channels, ReLU after the
-first three; the q bins of an image are its channels) maps the first EM factor
-from the uniform start, x = A^T (y / (u A 1)) / b1, to a strictly positive
-starting image f0 = u (softplus(o) + eps), where b1 = A^T 1 is the sensitivity
-image and u = sum(y) / sum(b1) the value of the plain uniform start (u x is
-the first unpenalised EM iterate).  It is
-trained with Adam on pairs (x, f_T / u) where f_T is the reconstruction that
-Alg. 5 itself reaches after T iterations from the uniform start.  At use, the
+first three, the last adding its input back; the q bins of an image are its
+channels) works on logarithms: it maps log(x + delta) of the first EM factor
+from the uniform start, x = A^T (y / (u A 1)) / b1, to an estimate o of
+log(f_T / u + delta); b1 = A^T 1 is the sensitivity image and u = sum(y) /
+sum(b1) the value of the plain uniform start (u x is the first unpenalised EM
+iterate).  EM iterates are products of such factors, hence the log domain.
+The starting image is the inverse map u max(exp(o) - delta, delta / 100),
+strictly positive, scaled so that sum(b1 f0) = sum(y) (the total of every
+unpenalised EM iterate; a regression on logarithms is biased low).  It is trained with Adam on pairs (log(x + delta),
+log(f_T / u + delta)) where f_T is the reconstruction that Alg. 5 itself
+reaches after T iterations from the uniform start.  At use, the
 judge (csx_recon_warm) runs k iterations from both starts and keeps the warm
 one only if its penalised objective is lower; otherwise it falls back.
 
@@ -31,7 +35,6 @@ import torch
 
 from . import csx, inputs
 
-EPS = 1e-3
 CHANNELS = inputs.WARM_CHANNELS
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warm_slice128.npz")
 
@@ -40,8 +43,9 @@ class WarmNet:
     """Device parameters of the network (float32 master weights, binary16
     copies used by the convolutions, Adam moments, gradients)."""
 
-    def __init__(self, params: Sequence[dict]):
+    def __init__(self, params: Sequence[dict], delta: float = 0.1):
         dev = "cuda"
+        self.delta = float(delta)
         self.w32 = [torch.tensor(np.asarray(p["w"], np.float32), device=dev).contiguous() for p in params]
         self.b = [torch.tensor(np.asarray(p["b"], np.float32), device=dev).contiguous() for p in params]
         self.w16 = [torch.empty(w.shape, dtype=torch.float16, device=dev) for w in self.w32]
@@ -56,18 +60,18 @@ class WarmNet:
         self.step_count = 0
 
     @classmethod
-    def init(cls, seed: int) -> "WarmNet":
-        return cls(inputs.cnn_init(seed))
+    def init(cls, seed: int, delta: float = 0.1) -> "WarmNet":
+        return cls(inputs.cnn_init(seed), delta)
 
     @classmethod
     def load(cls, path: str = WEIGHTS) -> "WarmNet":
         with np.load(path, allow_pickle=False) as z:
             n = int(z["n_layers"])
-            return cls([{"w": z[f"w{k}"], "b": z[f"b{k}"]} for k in range(n)])
+            return cls([{"w": z[f"w{k}"], "b": z[f"b{k}"]} for k in range(n)], float(z["delta"]))
 
     def save(self, path: str, meta: Optional[dict] = None) -> None:
         os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
-        arrs = {"n_layers": np.int64(len(self.w32))}
+        arrs = {"n_layers": np.int64(len(self.w32)), "delta": np.float64(self.delta)}
         for k, (w, b) in enumerate(zip(self.w32, self.b)):
             arrs[f"w{k}"] = w.cpu().numpy()
             arrs[f"b{k}"] = b.cpu().numpy()
@@ -96,7 +100,8 @@ class Trainer:
         src = x
         n = len(self.acts)
         for k in range(n):
-            csx.conv3x3_forward(src, self.net.w16[k], self.net.b[k], self.acts[k], relu=k < n - 1)
+            csx.conv3x3_forward(src, self.net.w16[k], self.net.b[k], self.acts[k], relu=k < n - 1,
+                                residual=x if k == n - 1 else None)
             src = self.acts[k]
         return self.acts[-1]
 
@@ -130,24 +135,19 @@ def counts(geo: "csx.Geometry", f_true: np.ndarray, noise_seed: int) -> torch.Te
     return torch.tensor(inputs.poisson_counts(g, noise_seed), dtype=torch.float32, device="cuda")
 
 
-def uniform_value(geo: "csx.Geometry", y: torch.Tensor, b1: torch.Tensor) -> float:
-    return float(y.double().sum()) / float(b1.double().sum())
-
-
-def make_pairs(geo, cases, n_iter: int, beta: float, log=None):
-    """Network inputs and targets f_T / u of the given cases ([n][nz][nx][nq] each)."""
+def make_pairs(geo, cases, n_iter: int, beta: float, delta: float, log=None):
+    """Network inputs and targets of the given cases ([n][nz][nx][nq] each)."""
     g = geo.geom
     n = len(cases)
     X = torch.empty((n, g.nz, g.nx, g.nq), device="cuda")
     T = torch.empty_like(X)
-    b1 = geo.backproject(torch.ones(geo.detector_shape, device="cuda"))
     f = geo.new_image()
     t0 = time.perf_counter()
     for i, c in enumerate(cases):
         y = counts(geo, inputs.phantom(g, c.phantom_seed, c.n_rect), c.noise_seed)
-        geo.warm_input(y, X[i])
+        geo.warm_input(y, delta, X[i])
         geo.recon(y, f, n_iter, beta)
-        T[i].copy_(f).div_(uniform_value(geo, y, b1))
+        geo.warm_target(y, f, delta, T[i])
         if log and (i + 1) % 100 == 0:
             log(f"pairs {i + 1}/{n} ({time.perf_counter() - t0:.0f} s)")
     torch.cuda.synchronize()
@@ -196,7 +196,7 @@ def evaluate(geo, net: WarmNet, cases, n_iter: int, beta: float, k_judge: int, r
         Jp = geo.recon(y, f, n_iter, beta)
         target = Jp[-1] + rel * abs(Jp[-1])
         n_p = first_reaching(Jp, target)
-        geo.warm_start(y, net.layers(), EPS, f0)
+        geo.warm_start(y, net.layers(), net.delta, f0)
         Jw, acc = geo.recon_warm(y, f0, f, k_judge, n_iter, beta)
         n_w = first_reaching(Jw, target)
         # wall time to the target: plain start vs network + judge + the kept run
@@ -206,14 +206,14 @@ def evaluate(geo, net: WarmNet, cases, n_iter: int, beta: float, k_judge: int, r
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         n_run = max(k_judge, n_w if n_w is not None else n_iter)
-        geo.warm_start(y, net.layers(), EPS, f0)
+        geo.warm_start(y, net.layers(), net.delta, f0)
         geo.recon_warm(y, f0, f, k_judge, n_run, beta)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         out.append({"case": c.phantom_seed, "J_plain_T": float(Jp[-1]), "J_warm_0": float(Jw[0]),
                     "J_plain_0": float(Jp[0]), "accepted": acc, "iters_plain": n_p, "iters_warm": n_w,
                     "ms_plain": (t1 - t0) * 1e3, "ms_warm": (t2 - t1) * 1e3,
-                    "J_warm_T": float(Jw[-1])})
+                    "J_warm_T": float(Jw[-1]), "J_plain": Jp.tolist(), "J_warm": Jw.tolist()})
         if log and (i + 1) % 20 == 0:
             log(f"eval {i + 1}/{len(cases)}")
     return out
@@ -246,11 +246,13 @@ def main(argv=None):
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-eval", type=int, default=200)
     ap.add_argument("--iters", type=int, default=50)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--k-judge", type=int, default=2)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--delta", type=float, default=0.1)
+    ap.add_argument("--weights", default=None, help="evaluate this trained network instead of training")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
 
@@ -261,18 +263,24 @@ def main(argv=None):
     torch.cuda.set_device(0)
     w, g = calibrated_geometry()
     geo = csx.Geometry(g)
-    t0 = time.perf_counter()
-    X, T = make_pairs(geo, inputs.warm_cases("train", args.n_train), args.iters, w.beta, log)
-    t_pairs = time.perf_counter() - t0
-    net = WarmNet.init(args.seed)
-    t0 = time.perf_counter()
-    hist = train(net, X, T, args.epochs, args.batch, args.lr, seed=args.seed, log=log)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    del X, T
-    meta = {"n_train": args.n_train, "iters": args.iters, "epochs": args.epochs, "batch": args.batch,
-            "lr": args.lr, "seed": args.seed, "loss": hist, "eps": EPS, "beta": w.beta}
-    net.save(os.path.join(args.out, "warm_slice128.npz"), meta)
+    if args.weights:
+        net = WarmNet.load(args.weights)
+        with np.load(args.weights, allow_pickle=False) as z:
+            meta = json.loads(str(z["meta"]))
+        t_pairs = t_train = 0.0
+    else:
+        t0 = time.perf_counter()
+        X, T = make_pairs(geo, inputs.warm_cases("train", args.n_train), args.iters, w.beta, args.delta, log)
+        t_pairs = time.perf_counter() - t0
+        net = WarmNet.init(args.seed, args.delta)
+        t0 = time.perf_counter()
+        hist = train(net, X, T, args.epochs, args.batch, args.lr, seed=args.seed, log=log)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        del X, T
+        meta = {"n_train": args.n_train, "iters": args.iters, "epochs": args.epochs, "batch": args.batch,
+                "lr": args.lr, "seed": args.seed, "loss": hist, "beta": w.beta, "delta": args.delta}
+        net.save(os.path.join(args.out, "warm_slice128.npz"), meta)
     rows = evaluate(geo, net, inputs.warm_cases("eval", args.n_eval), args.iters, w.beta, args.k_judge, log=log)
     summ = summarize(rows)
     summ.update(seconds_pairs=t_pairs, seconds_train=t_train, k_judge=args.k_judge, rel=1e-3)

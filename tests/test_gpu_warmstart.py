@@ -55,17 +55,19 @@ def check_bound(got, ref, absref, K, what):
 
 
 @pytest.mark.parametrize("ci,co", PAIRS)
-@pytest.mark.parametrize("relu", [False, True])
-def test_conv_forward(ci, co, relu):
+@pytest.mark.parametrize("relu,res", [(False, False), (True, False), (False, True)])
+def test_conv_forward(ci, co, relu, res):
     nb, H, W = 2, 19, 37                     # ragged against the 8 x 16 tiles
     x = rnd((nb, H, W, ci), 1 + ci + co)
     w, w_d = half_w((9, ci, co), 2 + ci)
     b = rnd(co, 3)
+    r = rnd((nb, H, W, co), 4) if res else None
     y = torch.empty((nb, H, W, co), device="cuda")
-    csx.conv3x3_forward(dev(x), w_d, dev(b), y, relu)
-    ref = cnn.conv3x3(x, w.astype(np.float64), b, relu=relu, half=True)
-    absref = cnn.conv3x3(np.abs(x), np.abs(w.astype(np.float64)), np.abs(b), half=True)
-    check_bound(host(y), ref, absref, 9 * ci + 1, f"forward {ci}->{co}")
+    csx.conv3x3_forward(dev(x), w_d, dev(b), y, relu, None if r is None else dev(r))
+    ref = cnn.conv3x3(x, w.astype(np.float64), b, relu=relu, half=True, residual=r)
+    absref = cnn.conv3x3(np.abs(x), np.abs(w.astype(np.float64)), np.abs(b), half=True,
+                         residual=None if r is None else np.abs(r))
+    check_bound(host(y), ref, absref, 9 * ci + 2, f"forward {ci}->{co}")
 
 
 @pytest.mark.parametrize("ci,co", PAIRS)
@@ -113,7 +115,7 @@ def test_workspace_too_small_is_rejected():
 def test_loss_head_and_adam():
     nb, n = 3, 5000
     o = rnd((nb, n), 11, -4.0, 4.0)
-    t = rnd((nb, n), 12, 0.0, 3.0)
+    t = rnd((nb, n), 12, -3.0, 3.0)
     d = torch.empty((nb, n), device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
@@ -145,8 +147,8 @@ def net_params(seed):
 def test_training_step_gradients_match_oracle():
     nb, H, W = 2, 12, 20
     params = net_params(3)
-    x = rnd((nb, H, W, 64), 21, 0.0, 2.0)
-    t = rnd((nb, H, W, 64), 22, 0.0, 1.5)
+    x = rnd((nb, H, W, 64), 21, -2.0, 2.0)
+    t = rnd((nb, H, W, 64), 22, -1.5, 1.5)
     net = warmstart.WarmNet(params)
     tr = warmstart.Trainer(net, nb, H, W)
     tr.forward(dev(x))
@@ -163,7 +165,7 @@ def test_training_step_gradients_match_oracle():
 def test_training_is_deterministic_and_reduces_the_loss():
     nb, H, W = 2, 16, 16
     x = rnd((4, H, W, 64), 31, 0.0, 2.0)
-    t = 0.5 * x + 0.25                       # learnable: the FP64 recursion drops the loss ~30 %
+    t = 0.5 * x + 0.25                       # learnable: the FP64 recursion drops the loss
     X, T = dev(x), dev(t)
     runs = []
     for _ in range(2):
@@ -188,18 +190,30 @@ def test_warm_input_and_start_match_oracle(oracle_mod):
     y = inputs.poisson_counts(o.forward(f) * (1e3 / o.forward(f).max()), 42)
     geo = csx.Geometry(g)
     yd = dev(y)
-    x = geo.warm_input(yd)
-    xref = cnn.warm_input(o, y)
+    d = 0.05
+    x = geo.warm_input(yd, d)
+    xref = cnn.features(cnn.warm_input(o, y), d)
     assert rel_l2(host(x), xref) <= 1e-5
     params = net_params(5)
-    net = warmstart.WarmNet(params)
-    f0 = geo.warm_start(yd, net.layers(), warmstart.EPS)
+    net = warmstart.WarmNet(params, d)
+    f0 = geo.warm_start(yd, net.layers(), d)
     acts = cnn.forward([{"w": p["w"].astype(np.float64), "b": p["b"]} for p in params],
                        xref.reshape(1, g.nz, g.nx, g.nq), half=True)
-    u = cnn.uniform_value(y, o.sensitivity())
-    ref = cnn.warm_output(acts[-1][0], u, warmstart.EPS)
+    b1 = o.sensitivity()
+    u = cnn.uniform_value(y, b1)
+    ref = cnn.mass_normalise(cnn.warm_output(acts[-1][0], u, d), y, b1)
     assert rel_l2(host(f0), ref) <= E2E
+    np.testing.assert_allclose(ref, cnn.warm_start(o, y, [{"w": p["w"].astype(np.float64), "b": p["b"]}
+                                                          for p in params], d), rtol=1e-12)
+    assert abs(float(np.sum(b1 * host(f0))) / float(np.sum(y)) - 1.0) <= 1e-5
     assert float(f0.min()) > 0.0
+    # training target of an image
+    fr = inputs.random_image(g, 43, 0.0, 5.0)
+    t = geo.warm_target(yd, dev(fr), d)
+    assert rel_l2(host(t), cnn.target(fr, u, d)) <= 1e-6
+    with pytest.raises(csx.CsxError) as ei:
+        geo.warm_input(yd, 0.0)
+    assert ei.value.code == csx.CSX_EINVAL
 
 
 def judge_case():

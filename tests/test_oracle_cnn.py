@@ -63,7 +63,7 @@ def test_relu_and_half_rounding_points():
     assert np.all(y16 >= 0) and np.any(y16 == 0)
 
 
-def tiny_net(seed=7, ch=(3, 4, 4, 2)):
+def tiny_net(seed=7, ch=(3, 4, 4, 3)):
     rng = np.random.Generator(np.random.PCG64(seed))
     return [{"w": rng.normal(0, 0.5, (9, ch[k], ch[k + 1])), "b": rng.normal(0, 0.2, ch[k + 1])}
             for k in range(len(ch) - 1)]
@@ -72,7 +72,7 @@ def tiny_net(seed=7, ch=(3, 4, 4, 2)):
 def test_backward_matches_finite_differences():
     params = tiny_net()
     x = rnd((2, 5, 6, 3), 8, 0.0, 1.0)
-    t = rnd((2, 5, 6, 2), 9, 0.0, 2.0)
+    t = rnd((2, 5, 6, 3), 9, 0.0, 2.0)
     acts = cnn.forward(params, x, half=False)
     L, grads = cnn.backward(params, acts, t, half=False)
     assert L == pytest.approx(cnn.loss(params, x, t, half=False), rel=1e-14)
@@ -104,19 +104,24 @@ def test_backward_data_is_adjoint_of_forward():
     assert lhs == pytest.approx(rhs, rel=1e-12)
 
 
-def test_head_gradient_and_softplus_limits():
-    o = np.array([-800.0, -3.0, 0.0, 2.5, 800.0])
-    assert cnn.softplus(o)[2] == pytest.approx(np.log(2.0), rel=1e-15)
-    assert cnn.softplus(o)[4] == 800.0 and cnn.softplus(o)[0] >= 0.0
-    assert cnn.sigmoid(np.array([0.0]))[0] == 0.5
-    t = np.array([0.1, 0.2, 0.3, 0.4, 0.5])
-    L, d = cnn.head(o[1:4], t[1:4], 1)
+def test_head_gradient():
+    o = np.array([-3.0, 0.0, 2.5])
+    t = np.array([0.1, 0.2, 0.3])
+    L, d = cnn.head(o, t, 2)
+    assert L == pytest.approx((3.1 ** 2 + 0.2 ** 2 + 2.2 ** 2) / 2, rel=1e-15)
     h = 1e-6
     for k in range(3):
         e = np.zeros(3)
         e[k] = h
-        fd = (cnn.head(o[1:4] + e, t[1:4], 1)[0] - cnn.head(o[1:4] - e, t[1:4], 1)[0]) / (2 * h)
+        fd = (cnn.head(o + e, t, 2)[0] - cnn.head(o - e, t, 2)[0]) / (2 * h)
         assert d[k] == pytest.approx(fd, rel=1e-7)
+
+
+def test_last_layer_adds_the_input():
+    """With zero weights and biases the network is the identity map."""
+    p = [{"w": np.zeros((9, c0, c1)), "b": np.zeros(c1)} for c0, c1 in [(3, 4), (4, 4), (4, 3)]]
+    x = rnd((1, 4, 5, 3), 14)
+    np.testing.assert_array_equal(cnn.forward(p, x, half=False)[-1], x)
 
 
 def test_adam_first_step_closed_form():
@@ -156,6 +161,31 @@ def test_warm_input_is_the_first_em_factor(oracle_mod):
     assert np.all(x_flat[~seen] == 0.0)
 
 
-def test_warm_output():
-    f0 = cnn.warm_output(np.array([-50.0, 0.0]), 2.0, 1e-3)
-    assert np.all(f0 > 0) and f0[1] == pytest.approx(2.0 * (np.log(2.0) + 1e-3))
+def test_feature_target_output_maps():
+    d = 0.05
+    f0 = cnn.warm_output(np.array([-50.0, 0.0, 1.0, 500.0]), 2.0, d)
+    assert np.all(f0 > 0) and np.all(np.isfinite(f0))
+    assert f0[0] == pytest.approx(2.0 * 0.01 * d, rel=1e-15)
+    assert f0[1] == pytest.approx(2.0 * (1.0 - d), rel=1e-15)
+    assert f0[3] == pytest.approx(2.0 * (np.exp(30.0) - d), rel=1e-15)
+    # the output map inverts the target map above the floor
+    f = np.array([0.001, 0.5, 7.0])
+    np.testing.assert_allclose(cnn.warm_output(cnn.target(f, 2.0, d), 2.0, d), f, rtol=1e-12)
+    assert cnn.features(np.array([0.0]), d)[0] == pytest.approx(np.log(d))
+
+
+def test_mass_normalise_matches_the_em_invariant(oracle_mod):
+    """One unpenalised EM step (Alg. 5, beta = 0, no background) from any
+    positive image lands on sum(b1 f) = sum(y); the normalised start carries
+    the same total."""
+    from paper_1603_06400_amd import inputs
+    g = inputs.standard_geometry(8, 6, ndet=10)
+    o = oracle_mod.Oracle(g)
+    y = inputs.poisson_counts(o.forward(inputs.phantom(g, 5, 2)) * 80.0, 6)
+    b1 = o.sensitivity()
+    f = inputs.random_image(g, 7, 0.1, 3.0)
+    f1, _ = o.recon_step(y, None, f, 0.0)
+    fn = cnn.mass_normalise(f, y, b1)
+    assert np.sum(b1 * fn) == pytest.approx(np.sum(b1 * f1), rel=1e-12)
+    assert np.sum(b1 * fn) == pytest.approx(np.sum(y), rel=1e-12)
+    np.testing.assert_allclose(fn / f, fn.flat[0] / f.flat[0], rtol=1e-13)
