@@ -246,9 +246,9 @@ def main(argv=None):
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-eval", type=int, default=200)
     ap.add_argument("--iters", type=int, default=50)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--k-judge", type=int, default=2)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--delta", type=float, default=0.1)
