@@ -31,6 +31,7 @@ constexpr int TW = 16;            // forward tile columns (one MFMA M block)
 constexpr int GT = 16;            // weight-gradient pixel tile side
 constexpr int WG_BLOCKS = 256;    // weight-gradient partial count (max)
 constexpr int RED_BLOCKS = 256;   // loss / bias partial count
+constexpr int WG_GROUP = 16;      // weight-gradient partials summed per first-stage group
 
 __device__ inline f4 mfma16(h4 a, h4 b, f4 c)
 {
@@ -243,15 +244,18 @@ k_conv3x3_wgrad(const float *__restrict__ in, const float *__restrict__ dout, fl
     }
 }
 
-// out[e] = sum_k part[k * n + e], k ascending.
-__global__ void __launch_bounds__(256) k_sum_partials(const float *__restrict__ part, int nparts, int n,
+// out[g * n + e] = sum of part[k * n + e] over k in [g * per, min((g + 1) * per, nparts)),
+// k ascending; g = blockIdx.y.  With gridDim.y = 1 and per = nparts it is the plain sum.
+__global__ void __launch_bounds__(256) k_sum_partials(const float *__restrict__ part, int nparts, int n, int per,
                                                       float *__restrict__ out)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
+    const int k0 = blockIdx.y * per;
+    const int k1 = k0 + per < nparts ? k0 + per : nparts;
     float s = 0.f;
-    for (int k = 0; k < nparts; ++k) s += part[(size_t)k * n + e];
-    out[e] = s;
+    for (int k = k0; k < k1; ++k) s += part[(size_t)k * n + e];
+    out[(size_t)blockIdx.y * n + e] = s;
 }
 
 // Bias gradient partials: block b sums pixels [b*chunk, (b+1)*chunk) of every
@@ -466,12 +470,16 @@ csx_status check_dims(int nb, int H, int W)
 
 }  // namespace
 
+// Workspace layout (floats): weight partials [nblk][9*64*32], bias partials
+// [RED_BLOCKS][64], first-stage group sums [WG_BLOCKS/WG_GROUP][9*64*32]; the
+// loss head uses the front as [RED_BLOCKS] doubles.
 size_t csx_cnn_ws_floats(int nb, int H, int W)
 {
     const size_t wg = (size_t)wgrad_blocks(nb, H, W) * 9 * 64 * 32;
     const size_t bias = (size_t)RED_BLOCKS * 64;
+    const size_t groups = (size_t)((WG_BLOCKS + WG_GROUP - 1) / WG_GROUP) * 9 * 64 * 32;
     const size_t head = 2 * RED_BLOCKS;                     // doubles
-    return wg + bias + head + 64;
+    return (wg + bias + groups > head ? wg + bias + groups : head) + 64;
 }
 
 extern "C" size_t csx_cnn_workspace_bytes(int nb, int h, int w)
@@ -527,8 +535,13 @@ extern "C" csx_status csx_conv3x3_backward_weights(const float *x, const float *
     else if (cout == 32) st = run_wgrad<32, 32>(x, dy, part, nblk, nb, h, w_, s);
     else st = run_wgrad<32, 64>(x, dy, part, nblk, nb, h, w_, s);
     if (st != CSX_OK) return st;
+    // two fixed-order stages: groups of WG_GROUP partials, then the group sums
     const int n = 9 * cin * cout;
-    hipLaunchKernelGGL(k_sum_partials, dim3((n + 255) / 256), dim3(256), 0, s, part, nblk, n, dw);
+    const int ngrp = (nblk + WG_GROUP - 1) / WG_GROUP;
+    float *gsum = part + (size_t)nblk * 9 * 64 * 32 + (size_t)RED_BLOCKS * 64;
+    hipLaunchKernelGGL(k_sum_partials, dim3((n + 255) / 256, ngrp), dim3(256), 0, s, part, nblk, n, WG_GROUP,
+                       gsum);
+    hipLaunchKernelGGL(k_sum_partials, dim3((n + 255) / 256, 1), dim3(256), 0, s, gsum, ngrp, n, ngrp, dw);
     HIP_TRY(hipGetLastError());
     if (dbias) {
         const long npix = (long)nb * h * w_;
@@ -536,7 +549,7 @@ extern "C" csx_status csx_conv3x3_backward_weights(const float *x, const float *
         const int nbb = (int)((npix + chunk - 1) / chunk);
         float *bpart = part + (size_t)nblk * 9 * 64 * 32;   // after the weight partials
         hipLaunchKernelGGL(k_bias_part, dim3(nbb), dim3(256), 0, s, dy, npix, cout, chunk, bpart);
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, bpart, nbb, cout, dbias);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1, 1), dim3(256), 0, s, bpart, nbb, cout, nbb, dbias);
         HIP_TRY(hipGetLastError());
     }
     return CSX_OK;
