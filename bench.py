@@ -9,6 +9,7 @@ nominal voxel*pixel*q evaluations of one forward plus one adjoint
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --workload batch64 [--steps K] [--warmup W]
+    python bench.py --workload warm [--tto-cases N]
 
 Prints one JSON line.  The roofline entry uses the work model of the direct
 evaluation (4 VALU lane-ops per open in-band triple, 60 per open pair, 10 per
@@ -168,6 +169,24 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def time_to_objective(n_cases: int, batched: bool = False, log=None) -> dict:
+    """Time for the plain solver and for the judged learned warm start to
+    reach J_plain(50) (1 + 1e-3) on held-out phantoms of the 128^2 x 64q slice
+    (network and judge included); with batched, the warm path also runs
+    batched over the cases."""
+    from paper_1603_06400_amd import csx, inputs, warmstart
+    w, g = warmstart.calibrated_geometry()
+    net = warmstart.WarmNet.load()
+    cases = inputs.warm_cases("eval", n_cases)
+    geo = csx.Geometry(g)
+    rows = warmstart.evaluate(geo, net, cases, w.n_iter, w.beta, k_judge=2, log=log)
+    out = warmstart.summarize(rows)
+    out["target"] = "J <= J_plain(50) (1 + 1e-3), held-out phantoms"
+    if batched:
+        out["batched"] = warmstart.evaluate_batched(g, net, cases, w.n_iter, w.beta, k_judge=2, log=log)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,8 +196,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
                          "reference kernel for scaling HBM byte counters")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64"],
-                    help="slice128 (default): the single 128^2 x 64q slice; batch64: the batched form")
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64", "warm"],
+                    help="slice128 (default): the single 128^2 x 64q slice; batch64: the batched form; "
+                         "warm: time to the plain objective with the learned warm start")
+    ap.add_argument("--tto-cases", type=int, default=4,
+                    help="held-out phantoms for the time-to-objective entry (0: skip; warm workload: 200)")
     ap.add_argument("--tune-cache", default=None, metavar="PATH",
                     help="batch64: launch-shape cache file to read and update")
     args = ap.parse_args()
@@ -199,6 +221,16 @@ def main():
 
     if args.workload == "batch64":
         bench_batch(args)
+        return
+    if args.workload == "warm":
+        import torch
+        torch.cuda.set_device(0)
+        n = args.tto_cases if args.tto_cases != 4 else 200
+        tto = time_to_objective(n, batched=True, log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps({"metric": "time to the plain solver's objective (1e-3 relative), 128^2 x 64q slice",
+                          "value": tto["speedup_mean_time"], "unit": "x (plain time / warm time)",
+                          "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+                          "config": {"workload": "warm", "cases": n}, "time_to_objective": tto}))
         return
 
     import torch
@@ -261,6 +293,11 @@ def main():
         "roofline": roofline,
         "objective_first_last": [float(Jh[0]), float(Jh[-1])] if args.steps else None,
     }
+    if args.tto_cases > 0:
+        tto = time_to_objective(args.tto_cases)
+        out["time_to_objective"] = {k: tto[k] for k in ("cases", "target", "ms_plain_mean", "ms_warm_mean",
+                                                         "speedup_mean_time", "iters_plain_mean",
+                                                         "iters_warm_mean", "accept_rate")}
     if not args.no_cpu_baseline:
         f_true = inputs.phantom(w.geom, w.phantom_seed, w.n_rect)
         out["cpu_baseline"] = cpu_baseline(g, f_true, y)

@@ -181,6 +181,16 @@ csx_status csx_batch_recon(csx_batch *b, const float *const *y, const float *con
                            float *const *f, int init_uniform, int n_iter, double beta,
                            double *J_hist, void *stream);
 
+/* As csx_batch_recon with an iteration count per scan: n_iter[k] >= 0
+ * iterations for scan k.  The run goes in stages between consecutive distinct
+ * counts; a scan leaves the merged launches once it has run its count, so the
+ * scans' results are still bitwise those of csx_recon.  J_hist (NULL or host
+ * double[n][J_stride], J_stride >= max(n_iter) + 1): row k receives
+ * J(f^0..f^n_iter[k]); its later entries are not written. */
+csx_status csx_batch_recon_n(csx_batch *b, const float *const *y, const float *const *r,
+                             float *const *f, int init_uniform, const int *n_iter, double beta,
+                             double *J_hist, int J_stride, void *stream);
+
 /* Kernel timing (for measurement): while enabled, every forward and adjoint
  * operator launch on this handle is bracketed by HIP events recorded on the
  * caller's stream.  csx_timing_read synchronises those events and returns the

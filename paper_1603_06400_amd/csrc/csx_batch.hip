@@ -2,12 +2,14 @@
 // geometry handle, any sizes) reconstructed together by Alg. 5.
 //
 // One iteration issues, per kernel variant, a single forward launch and a
-// single adjoint launch that cover every scan's blocks (largest scans first, so
-// the small scans fill the tail), plus the per-scan float64 data-term, update
-// and objective kernels.  The iteration is captured once into a HIP graph on a
-// private stream and replayed n_iter times; the objective kernels index the
+// single adjoint launch that cover every active scan's blocks (largest scans
+// first, so the small scans fill the tail), plus the per-scan float64
+// data-term, update and objective kernels.  The iteration is captured into a
+// HIP graph on a private stream and replayed; the objective kernels index the
 // J history through a device iteration counter, so the replays need no host
-// work.  Nothing in the graph is a memset.
+// work.  Scans may have their own iteration counts: the run goes in stages
+// between consecutive distinct counts, each with its own graph over the scans
+// still running.  Nothing in a graph is a memset.
 #include "csx_internal.h"
 
 #include <algorithm>
@@ -68,12 +70,12 @@ extern "C" void csx_batch_free(csx_batch *b)
     delete b;
 }
 
-// Groups the scans by kernel variant of one operator and orders each group's
-// scans by decreasing work.
-static void make_groups(const std::vector<csx_geometry *> &hs, bool forward, std::vector<Group> &out)
+// Groups the active scans by kernel variant of one operator and orders each
+// group's scans by decreasing work.
+static void make_groups(const std::vector<csx_geometry *> &hs, const std::vector<int> &active, bool forward,
+                        std::vector<Group> &out)
 {
-    std::vector<int> order(hs.size());
-    for (size_t k = 0; k < hs.size(); ++k) order[k] = (int)k;
+    std::vector<int> order(active);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return scan_cost(hs[a]) > scan_cost(hs[b]); });
     for (int k : order) {
@@ -170,19 +172,19 @@ extern "C" csx_status csx_batch_create(csx_geometry *const *scans, int n, csx_ba
     return CSX_OK;
 }
 
-// One Alg. 5 iteration of every scan (the body that is captured).
-static csx_status issue_iteration(csx_batch *b, const float *const *y, const float *const *r,
-                                  float *const *f, double beta, size_t jstride, hipStream_t s)
+// One Alg. 5 iteration of the active scans (the body that is captured).
+static csx_status issue_iteration(csx_batch *b, const std::vector<int> &active, const float *const *y,
+                                  const float *const *r, float *const *f, double beta, size_t jstride,
+                                  hipStream_t s)
 {
-    const int n = (int)b->h.size();
     for (const Group &g : b->fwd) BT_TRY(launch_group(g, true, s));
-    for (int k = 0; k < n; ++k) {
+    for (int k : active) {
         csx_geometry *h = b->h[k];
         BT_TRY(csx_launch_sum_parts(h, csx_forward_shape(h).nparts, h->gws, s));
         BT_TRY(csx_launch_ratio(h, y[k], r ? r[k] : nullptr, true, s));
     }
     for (const Group &g : b->adj) BT_TRY(launch_group(g, false, s));
-    for (int k = 0; k < n; ++k) {
+    for (int k : active) {
         csx_geometry *h = b->h[k];
         BT_TRY(csx_launch_update(h, f[k], beta, true, s));
         BT_TRY(csx_launch_objective(h, beta, b->J_dev + k * jstride, b->iter_dev, s));
@@ -191,30 +193,88 @@ static csx_status issue_iteration(csx_batch *b, const float *const *y, const flo
     return csx_launch_iter_incr(b->iter_dev, s);
 }
 
-extern "C" csx_status csx_batch_recon(csx_batch *b, const float *const *y, const float *const *r,
-                                      float *const *f, int init_uniform, int n_iter, double beta,
-                                      double *J_hist, void *stream)
+// J at scan k's current iterate, stored at its iteration counter (single-scan
+// launches: the same kernels and shapes as the batched ones).
+static csx_status final_objective(csx_batch *b, int k, const float *y, const float *r, float *f, double beta,
+                                  size_t jstride, hipStream_t s)
 {
-    if (!b || !y || !f) return csx_fail(CSX_EINVAL, "NULL argument");
-    if (n_iter < 0) return csx_fail(CSX_EINVAL, "n_iter must be >= 0");
-    if (!(std::isfinite(beta) && beta >= 0.0)) return csx_fail(CSX_EINVAL, "beta must be finite and >= 0");
-    const int n = (int)b->h.size();
-    for (int k = 0; k < n; ++k)
-        if (!y[k] || !f[k]) return csx_fail(CSX_EINVAL, "NULL scan buffer");
-    hipStream_t cs = (hipStream_t)stream;
-    hipStream_t s = b->st;
-    // group by the handles' current launch shapes (a tuner may have changed them)
-    HIP_TRY(hipStreamSynchronize(s));
+    csx_geometry *h = b->h[k];
+    BT_TRY(csx_launch_forward(h, f, h->gws, s));
+    BT_TRY(csx_launch_ratio(h, y, r, false, s));
+    BT_TRY(csx_launch_update(h, f, beta, false, s));
+    return csx_launch_objective(h, beta, b->J_dev + k * jstride, b->iter_dev, s);
+}
+
+// Replaces the groups by those of the active scans and uploads their job
+// tables for this call's buffers (the stream is idle when this runs).
+static csx_status regroup(csx_batch *b, const std::vector<int> &active, const float *const *f, hipStream_t s)
+{
     free_groups(b->fwd);
     free_groups(b->adj);
     b->fwd.clear();
     b->adj.clear();
-    make_groups(b->h, true, b->fwd);
-    make_groups(b->h, false, b->adj);
+    make_groups(b->h, active, true, b->fwd);
+    make_groups(b->h, active, false, b->adj);
+    const int n = (int)b->h.size();
+    std::vector<const float *> in(n);
+    std::vector<float *> outp(n, nullptr);
+    for (int k = 0; k < n; ++k) in[k] = f[k];
+    for (Group &g : b->fwd) BT_TRY(upload_jobs(g, b->h, true, in, outp, s));
+    for (int k = 0; k < n; ++k) {
+        in[k] = b->h[k]->rho;
+        outp[k] = b->h[k]->b2;
+    }
+    for (Group &g : b->adj) BT_TRY(upload_jobs(g, b->h, false, in, outp, s));
+    return CSX_OK;
+}
+
+static csx_status replay(csx_batch *b, const std::vector<int> &active, const float *const *y,
+                         const float *const *r, float *const *f, double beta, size_t jstride, int steps,
+                         hipStream_t s)
+{
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    csx_status st = issue_iteration(b, active, y, r, f, beta, jstride, s);
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st != CSX_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return csx_fail(CSX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return csx_fail(CSX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    for (int t = 0; t < steps && e == hipSuccess; ++t) e = hipGraphLaunch(exec, s);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return csx_fail(CSX_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+    return CSX_OK;
+}
+
+extern "C" csx_status csx_batch_recon_n(csx_batch *b, const float *const *y, const float *const *r,
+                                        float *const *f, int init_uniform, const int *n_iter, double beta,
+                                        double *J_hist, int J_stride, void *stream)
+{
+    if (!b || !y || !f || !n_iter) return csx_fail(CSX_EINVAL, "NULL argument");
+    if (!(std::isfinite(beta) && beta >= 0.0)) return csx_fail(CSX_EINVAL, "beta must be finite and >= 0");
+    const int n = (int)b->h.size();
+    int n_max = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!y[k] || !f[k]) return csx_fail(CSX_EINVAL, "NULL scan buffer");
+        if (n_iter[k] < 0) return csx_fail(CSX_EINVAL, "n_iter must be >= 0");
+        n_max = std::max(n_max, n_iter[k]);
+    }
+    if (J_hist && J_stride < n_max + 1) return csx_fail(CSX_EINVAL, "J_stride must be >= max(n_iter) + 1");
+    hipStream_t cs = (hipStream_t)stream;
+    hipStream_t s = b->st;
+    HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipEventRecord(b->ev_in, cs));
     HIP_TRY(hipStreamWaitEvent(s, b->ev_in, 0));
 
-    const size_t jstride = (size_t)n_iter + 1;
+    const size_t jstride = (size_t)n_max + 1;
     if (b->J_cap < jstride * n) {
         if (b->J_dev) HIP_TRY(hipFree(b->J_dev));
         b->J_dev = nullptr;
@@ -222,85 +282,78 @@ extern "C" csx_status csx_batch_recon(csx_batch *b, const float *const *y, const
         HIP_TRY(hipMalloc((void **)&b->J_dev, sizeof(double) * jstride * n));
         b->J_cap = jstride * n;
     }
+    std::vector<int> all(n);
+    for (int k = 0; k < n; ++k) all[k] = k;
 
     // sensitivity images of the scans that lack one, batched
-    std::vector<const float *> in(n);
-    std::vector<float *> outp(n);
-    {
-        bool any = false;
-        for (int k = 0; k < n; ++k) any = any || !b->h[k]->have_b1;
-        if (any) {
-            for (int k = 0; k < n; ++k) {
-                in[k] = b->h[k]->ones;
-                outp[k] = b->h[k]->b1;
-            }
-            for (Group &g : b->adj) {
-                BT_TRY(upload_jobs(g, b->h, false, in, outp, s));
-                BT_TRY(launch_group(g, false, s));
-            }
-            for (int k = 0; k < n; ++k) b->h[k]->have_b1 = true;
-            HIP_TRY(hipStreamSynchronize(s));   // the job tables are rebuilt below
+    std::vector<int> need;
+    for (int k = 0; k < n; ++k)
+        if (!b->h[k]->have_b1) need.push_back(k);
+    if (!need.empty()) {
+        free_groups(b->adj);
+        b->adj.clear();
+        make_groups(b->h, need, false, b->adj);
+        std::vector<const float *> in(n);
+        std::vector<float *> outp(n);
+        for (int k = 0; k < n; ++k) {
+            in[k] = b->h[k]->ones;
+            outp[k] = b->h[k]->b1;
         }
+        for (Group &g : b->adj) {
+            BT_TRY(upload_jobs(g, b->h, false, in, outp, s));
+            BT_TRY(launch_group(g, false, s));
+        }
+        for (int k : need) b->h[k]->have_b1 = true;
+        HIP_TRY(hipStreamSynchronize(s));   // the job tables are rebuilt below
     }
     if (init_uniform)
         for (int k = 0; k < n; ++k) BT_TRY(csx_launch_uniform_start(b->h[k], y[k], f[k], s));
-
-    // job tables of this call's buffers
-    for (int k = 0; k < n; ++k) {
-        in[k] = f[k];
-        outp[k] = nullptr;
-    }
-    for (Group &g : b->fwd) BT_TRY(upload_jobs(g, b->h, true, in, outp, s));
-    for (int k = 0; k < n; ++k) {
-        in[k] = b->h[k]->rho;
-        outp[k] = b->h[k]->b2;
-    }
-    for (Group &g : b->adj) BT_TRY(upload_jobs(g, b->h, false, in, outp, s));
     const int zero = 0;
     HIP_TRY(hipMemcpyAsync(b->iter_dev, &zero, sizeof(int), hipMemcpyHostToDevice, s));
 
-    if (n_iter > 0) {
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        csx_status st = issue_iteration(b, y, r, f, beta, jstride, s);
-        hipError_t e = hipStreamEndCapture(s, &graph);
-        if (st != CSX_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return st;
+    // stages between consecutive distinct iteration counts; a scan leaves the
+    // merged launches once it has run its own count
+    std::vector<int> counts(n_iter, n_iter + n);
+    std::sort(counts.begin(), counts.end());
+    counts.erase(std::unique(counts.begin(), counts.end()), counts.end());
+    int done = 0;
+    for (int c : counts) {
+        if (c > done) {
+            std::vector<int> active;
+            for (int k = 0; k < n; ++k)
+                if (n_iter[k] >= c) active.push_back(k);
+            HIP_TRY(hipStreamSynchronize(s));   // the previous job tables may still be read
+            BT_TRY(regroup(b, active, f, s));
+            BT_TRY(replay(b, active, y, r, f, beta, jstride, c - done, s));
+            done = c;
         }
-        if (e != hipSuccess) return csx_fail(CSX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return csx_fail(CSX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-        }
-        for (int t = 0; t < n_iter && e == hipSuccess; ++t) e = hipGraphLaunch(exec, s);
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) return csx_fail(CSX_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
-    }
-    // objective at the final iterates (the counter now equals n_iter)
-    for (const Group &g : b->fwd) BT_TRY(launch_group(g, true, s));
-    for (int k = 0; k < n; ++k) {
-        csx_geometry *h = b->h[k];
-        BT_TRY(csx_launch_sum_parts(h, csx_forward_shape(h).nparts, h->gws, s));
-        BT_TRY(csx_launch_ratio(h, y[k], r ? r[k] : nullptr, false, s));
-        BT_TRY(csx_launch_update(h, f[k], beta, false, s));
-        BT_TRY(csx_launch_objective(h, beta, b->J_dev + k * jstride, b->iter_dev, s));
+        for (int k = 0; k < n; ++k)
+            if (n_iter[k] == c) BT_TRY(final_objective(b, k, y[k], r ? r[k] : nullptr, f[k], beta, jstride, s));
     }
     std::vector<int> flags(n, 0);
     for (int k = 0; k < n; ++k)
         HIP_TRY(hipMemcpyAsync(&flags[k], b->h[k]->flags, sizeof(int), hipMemcpyDeviceToHost, s));
-    if (J_hist)
-        HIP_TRY(hipMemcpyAsync(J_hist, b->J_dev, sizeof(double) * jstride * n,
-                               hipMemcpyDeviceToHost, s));
+    std::vector<double> Jh(jstride * n);
+    HIP_TRY(hipMemcpyAsync(Jh.data(), b->J_dev, sizeof(double) * jstride * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipEventRecord(b->ev_out, s));
     HIP_TRY(hipStreamWaitEvent(cs, b->ev_out, 0));
+    if (J_hist)
+        for (int k = 0; k < n; ++k)
+            for (int t = 0; t <= n_iter[k]; ++t) J_hist[(size_t)k * J_stride + t] = Jh[(size_t)k * jstride + t];
     for (int k = 0; k < n; ++k) {
         if (flags[k] & 2) return csx_fail(CSX_EINVAL, "scan " + std::to_string(k) + ": y holds negative or NaN counts");
         if (flags[k] & 1) return csx_fail(CSX_ENUMERIC, "scan " + std::to_string(k) + ": y_i > 0 where the model mean is 0");
     }
     return CSX_OK;
+}
+
+extern "C" csx_status csx_batch_recon(csx_batch *b, const float *const *y, const float *const *r,
+                                      float *const *f, int init_uniform, int n_iter, double beta,
+                                      double *J_hist, void *stream)
+{
+    if (!b) return csx_fail(CSX_EINVAL, "NULL argument");
+    if (n_iter < 0) return csx_fail(CSX_EINVAL, "n_iter must be >= 0");
+    std::vector<int> counts(b->h.size(), n_iter);
+    return csx_batch_recon_n(b, y, r, f, init_uniform, counts.data(), beta, J_hist, n_iter + 1, stream);
 }

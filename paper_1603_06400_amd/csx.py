@@ -58,7 +58,7 @@ class _Info(ctypes.Structure):
 EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_get_info",
            "csx_forward", "csx_backproject", "csx_recon_step", "csx_recon",
            "csx_get_launch", "csx_set_launch", "csx_batch_create", "csx_batch_free",
-           "csx_batch_recon", "csx_timing_enable", "csx_timing_read", "csx_last_error",
+           "csx_batch_recon", "csx_batch_recon_n", "csx_timing_enable", "csx_timing_read", "csx_last_error",
            "csx_cnn_workspace_bytes", "csx_conv3x3_forward", "csx_conv3x3_backward_data",
            "csx_conv3x3_backward_weights", "csx_warm_loss", "csx_adam_step", "csx_to_half",
            "csx_warm_input", "csx_warm_output", "csx_warm_target", "csx_warm_start", "csx_recon_warm"]
@@ -108,6 +108,10 @@ def lib():
                                       ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.POINTER(ctypes.c_double), vp]
         L.csx_batch_recon.restype = ctypes.c_int
+        L.csx_batch_recon_n.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int, vp]
+        L.csx_batch_recon_n.restype = ctypes.c_int
         L.csx_timing_enable.argtypes = [vp, ctypes.c_int]
         L.csx_timing_enable.restype = ctypes.c_int
         L.csx_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
@@ -433,8 +437,10 @@ class Batch:
         except Exception:
             pass
 
-    def recon(self, ys, fs, n_iter: int, beta: float, rs=None, init_uniform: bool = True) -> np.ndarray:
-        """Alg. 5 on every scan in place; returns J histories [n_scans][n_iter + 1]."""
+    def recon(self, ys, fs, n_iter, beta: float, rs=None, init_uniform: bool = True) -> np.ndarray:
+        """Alg. 5 on every scan in place; returns J histories [n_scans][max(n_iter) + 1].
+        n_iter is one count for all scans or a sequence of per-scan counts (then
+        row k holds J(f^0..f^n_k) followed by NaN)."""
         n = len(self.geoms)
         if len(ys) != n or len(fs) != n or (rs is not None and len(rs) != n):
             raise ValueError("one y and one f per scan")
@@ -444,8 +450,19 @@ class Batch:
         if rs is not None:
             rp = (ctypes.c_void_p * n)(*[None if r is None else _dev(r, g.npix, "r").value
                                          for r, g in zip(rs, self.geoms)])
-        hist = np.zeros((n, n_iter + 1), dtype=np.float64)
-        _check(lib().csx_batch_recon(self._h, yp, rp, fp, int(bool(init_uniform)), int(n_iter),
-                                     float(beta), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                     _stream()))
+        if np.ndim(n_iter) == 0:
+            hist = np.zeros((n, int(n_iter) + 1), dtype=np.float64)
+            _check(lib().csx_batch_recon(self._h, yp, rp, fp, int(bool(init_uniform)), int(n_iter),
+                                         float(beta), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         _stream()))
+            return hist
+        counts = [int(c) for c in n_iter]
+        if len(counts) != n:
+            raise ValueError("one iteration count per scan")
+        stride = max(counts) + 1
+        hist = np.full((n, stride), np.nan, dtype=np.float64)
+        cp = (ctypes.c_int * n)(*counts)
+        _check(lib().csx_batch_recon_n(self._h, yp, rp, fp, int(bool(init_uniform)), cp, float(beta),
+                                       hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), stride,
+                                       _stream()))
         return hist

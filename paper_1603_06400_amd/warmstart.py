@@ -219,6 +219,73 @@ def evaluate(geo, net: WarmNet, cases, n_iter: int, beta: float, k_judge: int, r
     return out
 
 
+def evaluate_batched(g, net: WarmNet, cases, n_iter: int, beta: float, k_judge: int, chunk: int = 25,
+                     rel: float = 1e-3, log=None) -> dict:
+    """Wall time to bring every case to J_plain(n_iter) (1 + rel): the plain
+    solver run case after case (each for the iterations it needs) against the
+    warm path batched over `chunk` scans at a time (network per scan, the judge
+    as two batched k-iteration runs, then one batched continuation in which
+    each scan runs the iterations it needs)."""
+    geos = [csx.Geometry(g) for _ in range(min(chunk, len(cases)))]
+    batch = csx.Batch(geos)
+    t_plain = t_warm = 0.0
+    accepted = 0
+    iters_plain, iters_warm = [], []
+    for c0 in range(0, len(cases), chunk):
+        cs = cases[c0:c0 + chunk]
+        if len(cs) < len(geos):
+            geos_c = geos[:len(cs)]
+            batch_c = csx.Batch(geos_c)
+        else:
+            geos_c, batch_c = geos, batch
+        ys = [counts(geo, inputs.phantom(g, c.phantom_seed, c.n_rect), c.noise_seed) for geo, c in zip(geos_c, cs)]
+        fp = [geo.new_image() for geo in geos_c]
+        Jp = batch_c.recon(ys, fp, n_iter, beta)                       # untimed: the targets
+        targets = Jp[:, -1] + rel * np.abs(Jp[:, -1])
+        n_p = [first_reaching(Jp[i], targets[i]) for i in range(len(cs))]
+        iters_plain += n_p
+        # plain, one scan after the other, each for the iterations it needs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for geo, y, f, n in zip(geos_c, ys, fp, n_p):
+            geo.recon(y, f, n, beta)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        # warm + batched: first find the iterations needed (untimed), then time the run
+        fw = [geo.new_image() for geo in geos_c]
+        fu = [geo.new_image() for geo in geos_c]
+
+        def warm_run(n_cont):
+            for geo, y, f in zip(geos_c, ys, fw):
+                geo.warm_start(y, net.layers(), net.delta, f)
+            Jw = batch_c.recon(ys, fw, k_judge, beta, init_uniform=False)
+            Ju = batch_c.recon(ys, fu, k_judge, beta, init_uniform=True)
+            take = Jw[:, -1] < Ju[:, -1]
+            for i in range(len(cs)):
+                if not take[i]:
+                    fw[i].copy_(fu[i])
+            Jc = batch_c.recon(ys, fw, n_cont, beta, init_uniform=False)
+            J = np.concatenate([np.where(take[:, None], Jw, Ju)[:, :k_judge], Jc], axis=1)
+            return J, take
+
+        J, take = warm_run(n_iter - k_judge)
+        n_w = [first_reaching(J[i], targets[i]) for i in range(len(cs))]
+        n_w = [n_iter if n is None else n for n in n_w]
+        iters_warm += n_w
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        warm_run([max(0, n - k_judge) for n in n_w])
+        torch.cuda.synchronize()
+        t_warm += time.perf_counter() - t0
+        accepted += int(np.sum(take))
+        if log:
+            log(f"batched eval {c0 + len(cs)}/{len(cases)}")
+    return {"cases": len(cases), "chunk": chunk, "k_judge": k_judge, "rel": rel,
+            "total_s_plain_sequential": t_plain, "total_s_warm_batched": t_warm,
+            "speedup_total": t_plain / t_warm, "accept_rate": accepted / len(cases),
+            "iters_plain_mean": float(np.mean(iters_plain)), "iters_warm_mean": float(np.mean(iters_warm))}
+
+
 def summarize(rows) -> dict:
     mp = np.array([r["ms_plain"] for r in rows])
     mw = np.array([r["ms_warm"] for r in rows])
@@ -226,6 +293,8 @@ def summarize(rows) -> dict:
     iw = np.array([np.nan if r["iters_warm"] is None else r["iters_warm"] for r in rows], dtype=float)
     return {"cases": len(rows), "accept_rate": float(np.mean([r["accepted"] for r in rows])),
             "ms_plain_mean": float(mp.mean()), "ms_warm_mean": float(mw.mean()),
+            "ms_plain_median": float(np.median(mp)), "ms_warm_median": float(np.median(mw)),
+            "s_plain_total": float(mp.sum() / 1e3), "s_warm_total": float(mw.sum() / 1e3),
             "speedup_mean_time": float(mp.mean() / mw.mean()),
             "iters_plain_mean": float(np.nanmean(ip)), "iters_warm_mean": float(np.nanmean(iw)),
             "warm_reached_target": int(np.sum(~np.isnan(iw))),

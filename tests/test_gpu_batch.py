@@ -67,6 +67,31 @@ def test_batch_equals_sequential():
         np.testing.assert_array_equal(J_seq[k], J_bat[k])
 
 
+def test_batch_per_scan_counts_equal_sequential():
+    """Scans with their own iteration counts (including 0 and repeated counts)
+    leave the merged launches when done; each equals its csx_recon run."""
+    scans = mixed_scans()
+    counts = [3, 0, 5, 3, 1, 6]
+    geos = [csx.Geometry(g) for g, _ in scans]
+    ys = [dev(counts_for(geo, f, 60 + k)) for k, (geo, (_, f)) in enumerate(zip(geos, scans))]
+    f_seq, J_seq = [], []
+    for geo, y, n in zip(geos, ys, counts):
+        f = geo.new_image()
+        J_seq.append(geo.recon(y, f, n, 1e-3))
+        f_seq.append(f)
+    geos2 = [csx.Geometry(g) for g, _ in scans]
+    for a, b in zip(geos, geos2):
+        lc = a.get_launch()
+        b.set_launch(lc["fwd_splits"], lc["fwd_qw"], lc["adj_qw"])
+    f_bat = [g.new_image() for g in geos2]
+    J_bat = csx.Batch(geos2).recon(ys, f_bat, counts, 1e-3)
+    assert J_bat.shape == (len(scans), max(counts) + 1)
+    for k, n in enumerate(counts):
+        assert torch.equal(f_seq[k], f_bat[k]), k
+        np.testing.assert_array_equal(J_seq[k], J_bat[k, :n + 1])
+        assert np.all(np.isnan(J_bat[k, n + 1:]))
+
+
 def test_batch_resume_equals_continuous():
     scans = mixed_scans()[:4]
     geos = [csx.Geometry(g) for g, _ in scans]
