@@ -16,15 +16,18 @@
 //  * lane = class.  Each lane evaluates its class's factors once and keeps
 //    kappa and the pair weights in its own registers; the q loop then runs
 //    inside the lane (fully unrolled over a chunk of <= 64 q), so no lane ever
-//    waits on a value another lane produced.  The per-q step is one FP64 FMA
-//    for the Bragg bin coordinate, an unsigned clamp, a gather from the
-//    spectrum table in LDS and FP32 FMAs; q/dE comes from scalar loads.
+//    waits on a value another lane produced.  The per-q step is one FP64 add
+//    for the Bragg bin coordinate (an FMA anchors it at every 8th node), an
+//    unsigned clamp, a gather from the spectrum table in LDS and FP32 FMAs;
+//    on a non-uniform q grid q/dE comes from scalar loads.
 //  * blocks of 8 q nodes are skipped, uniformly for the wave, when no lane's
 //    Bragg energies kappa q can reach the spectrum band there.
 //  * the spectral bin of a triple is decided in float64 (kappa in float64
 //    from float32 seeds refined by one Newton step each; the bin coordinate
-//    q/dE * kappa + 1 - e_lo/dE by one FP64 FMA): the same precision as the
-//    float64 definition, so bin decisions agree except at float64 ties.
+//    q/dE * kappa + 1 - e_lo/dE by FP64 FMA, or on a uniform grid by an FMA
+//    at every 8th node and FP64 adds between, within 8 ulp): float64
+//    precision, so bin decisions agree with the float64 definition except
+//    within ~1e-13 of a bin edge.
 //  * adjoint: one wave per voxel (and its x-mirror) walks the pixel classes 64
 //    at a time, accumulating per-lane partial images acc[q]; one butterfly
 //    transpose-reduction per wave sums them over lanes (no atomics).
@@ -221,7 +224,8 @@ __device__ __forceinline__ int wave_max(int v)
 }
 
 // Bin coordinate of q node m on a uniform q grid: u_m = u0 + m du with
-// u0 = kappa q_0/dE + 1 - e_lo/dE and du = kappa dq/dE (one FP64 FMA per node).
+// u0 = kappa q_0/dE + 1 - e_lo/dE and du = kappa dq/dE (an FP64 FMA at nodes
+// 0, 8, 16, ..., one FP64 add per node between).
 // Nodes whose energy can be in band satisfy 1 <= u_m < ne + 1; the returned
 // range [lo, hi] (chunk-local, widened by one node each side) contains them.
 __device__ __forceinline__ void band_range(const KParams &P, double u0, double du, int m0, int qw,
@@ -354,10 +358,13 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
 #pragma unroll
             for (int blk = 0; blk < NB; ++blk) {
                 if (blk * 8 + 7 < wlo || blk * 8 > whi) continue;
+                // anchored by an FMA at each 8-node block, then one add per node
+                double u = fma((double)(blk * 8), du, u0);
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
-                    const uint32_t kk = min((uint32_t)(int)fma((double)m, du, u0), top);
+                    const uint32_t kk = min((uint32_t)(int)u, top);
+                    u += du;
                     const float ph = spec(s_phi, kk);
                     acc0[m] = fmaf(c0, ph, acc0[m]);
                     if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
@@ -576,12 +583,16 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
 #pragma unroll
             for (int blk = 0; blk < NB; ++blk) {
                 if (blk * 8 + 7 < wlo || blk * 8 > whi) continue;
+                // anchored by an FMA at each 8-node block, then one add per node
+                double ua = fma((double)(blk * 8), du1, u10), ub = fma((double)(blk * 8), du2, u20);
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
-                    const float p1 = spec(s_phi, min((uint32_t)(int)fma((double)m, du1, u10), top));
+                    const float p1 = spec(s_phi, min((uint32_t)(int)ua, top));
+                    ua += du1;
                     if (LR) {
-                        const float p2 = spec(s_phi, min((uint32_t)(int)fma((double)m, du2, u20), top));
+                        const float p2 = spec(s_phi, min((uint32_t)(int)ub, top));
+                        ub += du2;
                         const float2 fv = *(const float2 *)(trow + m * TS);
                         w1a = fmaf(p1, fv.x, w1a);
                         w1b = fmaf(p1, fv.y, w1b);
