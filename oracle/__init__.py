@@ -15,6 +15,8 @@ Layers, each following the paper (Odinaka et al., arXiv:1603.06400):
 * ``surrogate_coefficients`` / ``lemma_minimizer`` / ``recon_step`` /
   ``recon`` -- the separable-surrogate EM-type update of Sec. VI, Alg. 5 and
   App. B-C (eqs. grad_sep_obj, f_update, Lemma 1).
+* ``os_partition`` / ``recon_os`` -- the ordered-subsets variant, Alg. 6,
+  with the symmetry-preserving partition of Sec. VI.
 
 Parity status: every function here is pinned by tests in tests/test_oracle_*.py
 (closed forms, brute force, invariants); the absolute normalisation C has no
@@ -213,6 +215,35 @@ class Oracle:
                                         self.forward(f) + rr, f, beta))
         return f, np.array(hist)
 
+    def recon_os(self, y, r, f0, n_iter, beta, subsets):
+        """Alg. 6 (ordered subsets): n_iter outer iterations from f0, each a
+        sweep over the pixel subsets in the given order.  Sub-step p uses the
+        subset's data only: z_p = A_p f + r_p, b^(1)_p = A_p^T 1, b^(2)_p =
+        A_p^T (y_p / z_p), and the update of eq. f_update with b^(1)_p,
+        b^(2)_p and penalty weight beta / P (one penalty per sweep, like the
+        data term).  Returns (f_T, [J(f^0), ..., J(f^T)]) with the full
+        objective J."""
+        g = self.geom
+        y = np.asarray(y, dtype=np.float64).reshape(-1)
+        rr = np.zeros(g.npix) if r is None else np.asarray(r, dtype=np.float64).reshape(-1)
+        P = len(subsets)
+        b1 = []
+        for pix in subsets:
+            ind = np.zeros(g.npix)
+            ind[pix] = 1.0
+            b1.append(self.adjoint(ind.reshape(g.ndy, g.ndx)))
+        f = np.asarray(f0, dtype=np.float64).reshape(g.nz, g.nx, g.nq).copy()
+        hist = [self.objective(y, r, f, beta)]
+        for _ in range(n_iter):
+            for p, pix in enumerate(subsets):
+                z = self.forward_pixels(f, pix) + rr[pix]
+                rho = np.zeros(g.npix)
+                rho[pix] = poisson_ratio(y[pix], z)
+                b2 = self.adjoint(rho.reshape(g.ndy, g.ndx))
+                f = em_update(f, b1[p], b2, beta / P)
+            hist.append(self.objective(y, r, f, beta))
+        return f, np.array(hist)
+
     def objective(self, y, r, f, beta) -> float:
         g = self.geom
         y = np.asarray(y, dtype=np.float64).reshape(g.ndy, g.ndx)
@@ -325,6 +356,28 @@ def em_update(fhat, b1, b2, beta):
     out = lemma_minimizer(chi1, chi2, chi3)
     stuck = (chi1 <= 0) & (chi2 <= 0)
     return np.where(stuck, fhat, out)
+
+
+def os_partition(ndy: int, ndx: int, rho_z: int, rho_y: int):
+    """The symmetry-preserving detector partition of Sec. VI (ordered subsets):
+    a subset is one vertical class and one horizontal class.  Vertical class
+    rz (0 <= rz < rho_z) holds rows rz, rz + rho_z, ... of one half of the
+    detector (ndy / 2 rows) and their up-down mirrors ndy - 1 - row;
+    horizontal class cy (0 <= cy < rho_y / 2) holds columns cy, cy + rho_y,
+    ... and their left-right mirrors ndx - 1 - column.  Subset p = rz
+    (rho_y / 2) + cy (the sweep order, which the paper leaves open); each is
+    returned as sorted pixel indices row * ndx + column."""
+    if ndy % 2 or (ndy // 2) % rho_z or ndx % rho_y or rho_y % 2:
+        raise ValueError("need rho_z | ndy/2, rho_y | ndx and rho_y even")
+    out = []
+    for rz in range(rho_z):
+        rows = list(range(rz, ndy // 2, rho_z))
+        rows = sorted(set(rows + [ndy - 1 - r for r in rows]))
+        for cy in range(rho_y // 2):
+            cols = list(range(cy, ndx, rho_y))
+            cols = sorted(set(cols + [ndx - 1 - c for c in cols]))
+            out.append(np.array(sorted(r * ndx + c for r in rows for c in cols), dtype=np.int64))
+    return out
 
 
 def bf16_round(x: np.ndarray) -> np.ndarray:
