@@ -142,6 +142,23 @@ csx_status csx_recon_step(csx_geometry *h, const float *y, const float *r, float
 csx_status csx_recon(csx_geometry *h, const float *y, const float *r, float *f,
                      int init_uniform, int n_iter, double beta, double *J_hist, void *stream);
 
+/* Alg. 6, ordered subsets: n_iter sweeps over the detector subsets of the
+ * symmetry-preserving partition of Sec. VI.  Vertical class rz (0 <= rz <
+ * rho_z) holds rows rz, rz + rho_z, ... of one half of the detector and their
+ * up-down mirrors; horizontal class cy (0 <= cy < rho_y / 2) holds columns cy,
+ * cy + rho_y, ... and their left-right mirrors; subset p = rz (rho_y / 2) + cy
+ * is swept in increasing p (the paper leaves the order open).  Needs
+ * rho_z | ndy / 2, rho_y | ndx and rho_y even (else CSX_EINVAL); the paper's
+ * choice is rho_z = 8, rho_y = 16 (64 subsets).  Each sub-step uses the
+ * subset's data only (forward and back projection restricted to its pixels,
+ * b1_p = A_p^T 1) and the update of App. B with penalty weight beta / P.
+ * Buffers and init_uniform as for csx_recon; J_hist (host, n_iter + 1, may be
+ * NULL) receives the full objective J before the first and after every sweep.
+ * The partition's lists and the P sensitivity images (P * nvox * nq floats)
+ * are built on the first call and kept by the handle.  Synchronises `stream`. */
+csx_status csx_recon_os(csx_geometry *h, const float *y, const float *r, float *f, int init_uniform,
+                        int n_iter, int rho_z, int rho_y, double beta, double *J_hist, void *stream);
+
 /* Launch shape of a handle's operators; a tuner may change it (results do not
  * depend on it beyond float32 summation order).
  *   fwd_splits: the forward's voxel range is split over this many block rows

@@ -42,6 +42,12 @@ struct KParams {
     double q_min, q_max;
     float half_my;
     float inv_mask_nx;          // 1 / mask_nx
+    // pixel subsets (ordered subsets): when set, the forward's waves take
+    // their pixel quads from quad_list[0 .. n_quad) and the adjoint's lanes
+    // their pixel classes from cls_list[0 .. n_cls) (class = row r * ndx +
+    // column a, pixel row ndy/2 + r); otherwise all quads and classes
+    const int *quad_list = nullptr;
+    const int *cls_list = nullptr;
 };
 
 // Per-voxel records.  vf: {C*Gso, det_z - z} (float32); vm: {t/pm,
@@ -113,6 +119,7 @@ struct csx_geometry {
     int *partF = nullptr;      // per-block flags of the data term
     int *flags = nullptr;      // flags of the last objective: bit 0: y_i > 0 with zero
                                // mean; bit 1: y_i < 0 or NaN
+    void *os = nullptr;        // ordered-subsets state (csx_os.hip), on demand
     float *fplain = nullptr;   // [nvox*nq] plain-start iterate of the warm-start judge
     float *a1 = nullptr;       // [npix] A 1 (forward of the all-ones image), on demand
     float *warm = nullptr;     // activations of the warm-start network
@@ -137,6 +144,13 @@ csx_status csx_launch_forward_batch(const CsxJob *jobs_dev, const int *begin_dev
 csx_status csx_launch_adjoint_batch(const CsxJob *jobs_dev, const int *begin_dev, int njobs,
                                     int nblocks, int variant, int lds_bytes, hipStream_t s);
 csx_status csx_launch_sum_parts(csx_geometry *h, int nparts, float *g, hipStream_t s);
+// subset operators: forward at the quads of a list (with its own split count),
+// adjoint over the classes of a list
+OpShape csx_forward_shape_list(const csx_geometry *h, const int *quads, int n_quads, int splits);
+csx_status csx_launch_forward_list(csx_geometry *h, const float *f, const int *quads, int n_quads, int splits,
+                                   float *g, hipStream_t s);
+csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
+                                   hipStream_t s);
 hipEvent_t csx_timing_event(csx_geometry *h, int op);
 
 // solver pieces (csx_solver.hip)
@@ -144,12 +158,17 @@ csx_status csx_launch_ratio(csx_geometry *h, const float *y, const float *r, boo
                             hipStream_t s);
 csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool do_update,
                              hipStream_t s);
+csx_status csx_launch_update_ex(csx_geometry *h, const float *f, const float *b1, const float *b2,
+                                double beta, float *fout, hipStream_t s);
+csx_status csx_launch_ratio_subset(csx_geometry *h, const int *pix, int n, const float *y, const float *r,
+                                   const float *g, float *rho, hipStream_t s);
 csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, const int *iter,
                                 hipStream_t s);
 csx_status csx_launch_iter_incr(int *iter, hipStream_t s);
 csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, hipStream_t s);
 csx_status csx_launch_uniform_sums(csx_geometry *h, const float *y, hipStream_t s);
 csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s);
+void csx_os_free(csx_geometry *h);
 csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s);
 csx_status csx_launch_fill(float *dst, int n, float v, hipStream_t s);
 csx_status csx_launch_clear_flags(csx_geometry *h, hipStream_t s);

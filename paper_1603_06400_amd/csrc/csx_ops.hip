@@ -297,14 +297,28 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
     // pixels have close scatter angles, so the q-block skip is tighter
     const int half_y = P.ndy / 2;
     const int ntx = (P.ndx + 7) / 8;
-    const int ntiles = ntx * ((half_y + 7) / 8);
+    const int ntiles = P.cls_list ? (P.n_cls + 63) / 64 : ntx * ((half_y + 7) / 8);
     const int lx = lane & 7, ly = lane >> 3;
+    // class (column a, upper row r) of the lane in tile t: an 8 x 8 tile of
+    // the detector, or 64 consecutive entries of the class list
+    auto class_of = [&](int t, int &a, int &r) -> bool {
+        if (P.cls_list) {
+            const int e = t * 64 + lane;
+            if (e >= P.n_cls) return false;
+            const int c = P.cls_list[e];
+            a = c % P.ndx;
+            r = c / P.ndx;
+            return true;
+        }
+        a = (t % ntx) * 8 + lx;
+        r = (t / ntx) * 8 + ly;
+        return a < P.ndx && r < half_y;
+    };
     // detector values of the lane's class, prefetched one tile ahead
     float r_u = 0.0f, r_d = 0.0f, r_bu = 0.0f, r_bd = 0.0f;
     auto load_rho = [&](int t) {
-        const int a = (t % ntx) * 8 + lx;
-        const int r = (t / ntx) * 8 + ly;
-        if (a < P.ndx && r < half_y) {
+        int a, r;
+        if (class_of(t, a, r)) {
             const int bu = half_y + r;
             const int bd = P.ndy - 1 - bu;
             r_u = rho[bu * P.ndx + a];
@@ -319,12 +333,12 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
     load_rho(0);
 
     for (int t = 0; t < ntiles; ++t) {
-        const int a = (t % ntx) * 8 + lx;
-        const int r = (t / ntx) * 8 + ly;
+        int a = 0, r = 0;
+        const bool has = class_of(t, a, r);
         double kap = 0.0;
         float c0 = 0.0f, c1 = 0.0f;
         bool act = false;
-        if (a < P.ndx && r < half_y) {
+        if (has) {
             const int bu = half_y + r;
             const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
             const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
@@ -429,7 +443,7 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
 
     const int quad = bx * 8 + wv;               // 8 waves per block
     const bool wave_on = quad < P.n_quad;
-    const int qq = wave_on ? quad : 0;
+    const int qq = wave_on ? (P.quad_list ? P.quad_list[quad] : quad) : 0;
     int a, bu;
     if (LR) {
         const int hx = P.ndx / 2;
@@ -917,6 +931,41 @@ csx_status csx_launch_adjoint(csx_geometry *h, const float *rho, float *b, hipSt
     dispatch<RunAdj>(S.variant, S, h, rho, b, s);
     HIP_TRY(hipGetLastError());
     if (e1) HIP_TRY(hipEventRecord(e1, s));
+    return CSX_OK;
+}
+
+OpShape csx_forward_shape_list(const csx_geometry *h, const int *quads, int n_quads, int splits)
+{
+    OpShape S = csx_forward_shape(h);
+    S.P.quad_list = quads;
+    S.P.n_quad = n_quads;
+    const int ntiles = fwd_tiles(S.P);
+    const int sp = std::max(1, std::min(splits, ntiles));
+    S.tps = (ntiles + sp - 1) / sp;
+    const int nsplit = (ntiles + S.tps - 1) / S.tps;
+    S.grid = dim3((n_quads + 7) / 8, nsplit, S.P.qchunks);
+    S.nparts = nsplit * S.P.qchunks;
+    return S;
+}
+
+csx_status csx_launch_forward_list(csx_geometry *h, const float *f, const int *quads, int n_quads, int splits,
+                                   float *g, hipStream_t s)
+{
+    const OpShape S = csx_forward_shape_list(h, quads, n_quads, splits);
+    if ((size_t)S.nparts * h->P.npix > h->part_cap) return csx_fail(CSX_EINVAL, "forward partials too small");
+    dispatch<RunFwd>(S.variant, S, h, f, s);
+    HIP_TRY(hipGetLastError());
+    return csx_launch_sum_parts(h, S.nparts, g, s);
+}
+
+csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
+                                   hipStream_t s)
+{
+    OpShape S = csx_adjoint_shape(h);
+    S.P.cls_list = cls;
+    S.P.n_cls = n_cls;
+    dispatch<RunAdj>(S.variant, S, h, rho, b, s);
+    HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
 

@@ -56,7 +56,7 @@ class _Info(ctypes.Structure):
 
 
 EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_get_info",
-           "csx_forward", "csx_backproject", "csx_recon_step", "csx_recon",
+           "csx_forward", "csx_backproject", "csx_recon_step", "csx_recon", "csx_recon_os",
            "csx_get_launch", "csx_set_launch", "csx_batch_create", "csx_batch_free",
            "csx_batch_recon", "csx_batch_recon_n", "csx_timing_enable", "csx_timing_read", "csx_last_error",
            "csx_cnn_workspace_bytes", "csx_conv3x3_forward", "csx_conv3x3_backward_data",
@@ -96,6 +96,9 @@ def lib():
         L.csx_recon.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double), vp]
         L.csx_recon.restype = ctypes.c_int
+        L.csx_recon_os.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+        L.csx_recon_os.restype = ctypes.c_int
         L.csx_get_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
         L.csx_get_launch.restype = ctypes.c_int
         L.csx_set_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
@@ -279,6 +282,16 @@ class Geometry:
                                hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
         return hist
 
+
+    def recon_os(self, y: torch.Tensor, f: torch.Tensor, n_iter: int, beta: float, rho_z: int = 8,
+                 rho_y: int = 16, r: Optional[torch.Tensor] = None, init_uniform: bool = True) -> np.ndarray:
+        """Alg. 6 (ordered subsets) for n_iter sweeps in place on f; returns J(f^0..f^n) (float64)."""
+        rp = ctypes.c_void_p(None) if r is None else _dev(r, self.npix, "r")
+        hist = np.zeros(n_iter + 1, dtype=np.float64)
+        _check(lib().csx_recon_os(self._h, _dev(y, self.npix, "y"), rp, _dev(f, self.nvox * self.nq, "f"),
+                                  int(bool(init_uniform)), int(n_iter), int(rho_z), int(rho_y), float(beta),
+                                  hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+        return hist
 
     # ---- learned warm start ----------------------------------------------------------
     def warm_input(self, y: torch.Tensor, delta: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
