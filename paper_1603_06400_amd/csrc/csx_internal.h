@@ -144,11 +144,13 @@ csx_status csx_launch_forward_batch(const CsxJob *jobs_dev, const int *begin_dev
 csx_status csx_launch_adjoint_batch(const CsxJob *jobs_dev, const int *begin_dev, int njobs,
                                     int nblocks, int variant, int lds_bytes, hipStream_t s);
 csx_status csx_launch_sum_parts(csx_geometry *h, int nparts, float *g, hipStream_t s);
-// subset operators: forward at the quads of a list (with its own split count),
-// adjoint over the classes of a list
+// subset operators: forward at the quads of a list (with its own split count)
+// finished by the count ratio rho = y / (A f + r) at the subset's pixels, and
+// the adjoint over the classes of a list
 OpShape csx_forward_shape_list(const csx_geometry *h, const int *quads, int n_quads, int splits);
 csx_status csx_launch_forward_list(csx_geometry *h, const float *f, const int *quads, int n_quads, int splits,
-                                   float *g, hipStream_t s);
+                                   const int *pix, int n_pix, const float *y, const float *r, float *rho,
+                                   hipStream_t s);
 csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
                                    hipStream_t s);
 hipEvent_t csx_timing_event(csx_geometry *h, int op);
@@ -160,8 +162,6 @@ csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool 
                              hipStream_t s);
 csx_status csx_launch_update_ex(csx_geometry *h, const float *f, const float *b1, const float *b2,
                                 double beta, float *fout, hipStream_t s);
-csx_status csx_launch_ratio_subset(csx_geometry *h, const int *pix, int n, const float *y, const float *r,
-                                   const float *g, float *rho, hipStream_t s);
 csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, const int *iter,
                                 hipStream_t s);
 csx_status csx_launch_iter_incr(int *iter, hipStream_t s);

@@ -745,6 +745,26 @@ __global__ void __launch_bounds__(256) k_sum_parts(const float *__restrict__ par
     g[i] = s;
 }
 
+// Subset forward, finished: at the listed pixels z = sum of the partial
+// images (+ r) and rho = y / z (0 where y = 0 or z <= 0).  One wave per pixel:
+// lane k adds partials k, k + 64, ..., then a fixed butterfly adds the lanes.
+__global__ void __launch_bounds__(64) k_sum_ratio_list(const float *__restrict__ part, int nparts, int npix,
+                                                      const int *__restrict__ pix, const float *__restrict__ y,
+                                                      const float *__restrict__ r, float *__restrict__ rho)
+{
+    const int i = pix[blockIdx.x];
+    const int lane = threadIdx.x;
+    float s = 0.0f;
+    for (int p = lane; p < nparts; p += 64) s += part[(size_t)p * npix + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        const float z = s + (r ? r[i] : 0.0f);
+        const float yi = y[i];
+        rho[i] = (yi > 0.0f && z > 0.0f) ? yi / z : 0.0f;
+    }
+}
+
 Lds lds_layout(const KParams &P, bool forward)
 {
     auto al = [](int v) { return (v + 15) & ~15; };
@@ -949,13 +969,16 @@ OpShape csx_forward_shape_list(const csx_geometry *h, const int *quads, int n_qu
 }
 
 csx_status csx_launch_forward_list(csx_geometry *h, const float *f, const int *quads, int n_quads, int splits,
-                                   float *g, hipStream_t s)
+                                   const int *pix, int n_pix, const float *y, const float *r, float *rho,
+                                   hipStream_t s)
 {
     const OpShape S = csx_forward_shape_list(h, quads, n_quads, splits);
     if ((size_t)S.nparts * h->P.npix > h->part_cap) return csx_fail(CSX_EINVAL, "forward partials too small");
     dispatch<RunFwd>(S.variant, S, h, f, s);
+    hipLaunchKernelGGL(k_sum_ratio_list, dim3(n_pix), dim3(64), 0, s, h->part, S.nparts, h->P.npix, pix, y, r,
+                       rho);
     HIP_TRY(hipGetLastError());
-    return csx_launch_sum_parts(h, S.nparts, g, s);
+    return CSX_OK;
 }
 
 csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,

@@ -6,8 +6,9 @@
 // ... and their left-right mirrors); subset p = rz (rho_y / 2) + cy is the
 // sweep order.  Every subset is closed under both mirrors, so the operators
 // run on it unchanged: the forward's waves take the subset's pixel quads from
-// a list, the adjoint's lanes the subset's pixel classes.  A sub-step is
-// z_p = A_p f + r_p, rho_p = y_p / z_p, b2 = A_p^T rho_p and the closed-form
+// a list (its partial images are summed, and the count ratio formed, at the
+// subset's pixels only), the adjoint's lanes the subset's pixel classes.  A
+// sub-step is z_p = A_p f + r_p, rho_p = y_p / z_p, b2 = A_p^T rho_p and the closed-form
 // update of App. B with b1_p = A_p^T 1 (computed once per partition) and
 // penalty weight beta / P, so that one sweep applies the penalty once, like
 // the data term.  The sweep alternates the image between the caller's buffer
@@ -113,17 +114,6 @@ csx_status build(csx_geometry *h, int rho_z, int rho_y, hipStream_t s, OsState *
         return fail(e);
     if ((e = hipMemcpyAsync(o->pix, pix.data(), sizeof(int) * pix.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
         return fail(e);
-    // forward partials of the subset launches
-    const OpShape S = csx_forward_shape_list(h, o->quads, o->n_quads, o->splits);
-    const size_t need = (size_t)S.nparts * P.npix;
-    if (need > h->part_cap) {
-        if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
-        float *np = nullptr;
-        if ((e = hipMalloc((void **)&np, sizeof(float) * need)) != hipSuccess) return fail(e);
-        (void)hipFree(h->part);
-        h->part = np;
-        h->part_cap = need;
-    }
     for (int p = 0; p < o->n_sub; ++p) {
         csx_status st = csx_launch_adjoint_list(h, h->ones, o->cls + (size_t)p * o->n_cls, o->n_cls,
                                                 o->b1 + (size_t)p * img, s);
@@ -133,6 +123,22 @@ csx_status build(csx_geometry *h, int rho_z, int rho_y, hipStream_t s, OsState *
         }
     }
     *out = o;
+    return CSX_OK;
+}
+
+// Grows the handle's forward partials to what the subset launches need with
+// the handle's current launch shape (the stream is synchronised first).
+csx_status ensure_parts(csx_geometry *h, const OsState *o, hipStream_t s)
+{
+    const OpShape S = csx_forward_shape_list(h, o->quads, o->n_quads, o->splits);
+    const size_t need = (size_t)S.nparts * h->P.npix;
+    if (need <= h->part_cap) return CSX_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    float *np = nullptr;
+    HIP_TRY(hipMalloc((void **)&np, sizeof(float) * need));
+    (void)hipFree(h->part);
+    h->part = np;
+    h->part_cap = need;
     return CSX_OK;
 }
 
@@ -170,6 +176,7 @@ extern "C" csx_status csx_recon_os(csx_geometry *h, const float *y, const float 
         OS_TRY(build(h, rho_z, rho_y, s, &o));
         h->os = o;
     }
+    OS_TRY(ensure_parts(h, o, s));
     if (init_uniform) OS_TRY(csx_launch_uniform_start(h, y, f, s));
     const size_t img = (size_t)P.nvox * P.nq;
     auto objective = [&](const float *fc, int t) -> csx_status {
@@ -184,8 +191,7 @@ extern "C" csx_status csx_recon_os(csx_geometry *h, const float *y, const float 
         float *cur = f, *nxt = h->ftmp;
         for (int p = 0; p < o->n_sub; ++p) {
             OS_TRY(csx_launch_forward_list(h, cur, o->quads + (size_t)p * o->n_quads, o->n_quads, o->splits,
-                                           h->gws, s));
-            OS_TRY(csx_launch_ratio_subset(h, o->pix + (size_t)p * o->n_pix, o->n_pix, y, r, h->gws, h->rho, s));
+                                           o->pix + (size_t)p * o->n_pix, o->n_pix, y, r, h->rho, s));
             OS_TRY(csx_launch_adjoint_list(h, h->rho, o->cls + (size_t)p * o->n_cls, o->n_cls, h->b2, s));
             OS_TRY(csx_launch_update_ex(h, cur, o->b1 + (size_t)p * img, h->b2, bp, nxt, s));
             std::swap(cur, nxt);

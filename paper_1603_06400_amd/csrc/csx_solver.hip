@@ -75,21 +75,6 @@ __global__ void __launch_bounds__(256) k_ratio(int n, const float *__restrict__ 
 // The first form is Lemma 1's root multiplied through by its conjugate.
 // Also accumulates R(fhat) = sum_j sum_k (fhat_j - fhat_k)^2 / 2 per block.
 // ---------------------------------------------------------------------------
-// rho_i = y_i / (g_i + r_i) at the listed pixels (0 where y_i = 0 or the
-// model mean is not positive; the full objective reports the latter)
-__global__ void __launch_bounds__(256) k_ratio_subset(const int *__restrict__ pix, int n,
-                                                      const float *__restrict__ y,
-                                                      const float *__restrict__ r,
-                                                      const float *__restrict__ g, float *__restrict__ rho)
-{
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= n) return;
-    const int i = pix[e];
-    const float z = g[i] + (r ? r[i] : 0.0f);
-    const float yi = y[i];
-    rho[i] = (yi > 0.0f && z > 0.0f) ? yi / z : 0.0f;
-}
-
 __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const float *__restrict__ fh,
                                                 const float *__restrict__ b1,
                                                 const float *__restrict__ b2, double beta,
@@ -248,14 +233,6 @@ csx_status csx_launch_update_ex(csx_geometry *h, const float *f, const float *b1
     const KParams &P = h->P;
     hipLaunchKernelGGL(k_update, dim3(h->nbR), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout,
                        h->partR, 1);
-    HIP_TRY(hipGetLastError());
-    return CSX_OK;
-}
-
-csx_status csx_launch_ratio_subset(csx_geometry *h, const int *pix, int n, const float *y, const float *r,
-                                   const float *g, float *rho, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_ratio_subset, dim3((n + 255) / 256), dim3(256), 0, s, pix, n, y, r, g, rho);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }

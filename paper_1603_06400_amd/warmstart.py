@@ -184,9 +184,12 @@ def first_reaching(J: np.ndarray, target: float) -> Optional[int]:
     return int(k[0]) if k.size else None
 
 
-def evaluate(geo, net: WarmNet, cases, n_iter: int, beta: float, k_judge: int, rel: float = 1e-3, log=None):
+def evaluate(geo, net: WarmNet, cases, n_iter: int, beta: float, k_judge: int, rel: float = 1e-3, log=None,
+             os_partition=None, os_max_sweeps: int = 10):
     """Per held-out case: iterations and wall time for the plain start and for
-    the judged warm start to reach J_plain(T) (1 + rel)."""
+    the judged warm start to reach J_plain(T) (1 + rel); with os_partition =
+    (rho_z, rho_y) also the sweeps and wall time of ordered subsets (Alg. 6)
+    from the uniform start."""
     g = geo.geom
     f = geo.new_image()
     f0 = geo.new_image()
@@ -210,10 +213,22 @@ def evaluate(geo, net: WarmNet, cases, n_iter: int, beta: float, k_judge: int, r
         geo.recon_warm(y, f0, f, k_judge, n_run, beta)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out.append({"case": c.phantom_seed, "J_plain_T": float(Jp[-1]), "J_warm_0": float(Jw[0]),
-                    "J_plain_0": float(Jp[0]), "accepted": acc, "iters_plain": n_p, "iters_warm": n_w,
-                    "ms_plain": (t1 - t0) * 1e3, "ms_warm": (t2 - t1) * 1e3,
-                    "J_warm_T": float(Jw[-1]), "J_plain": Jp.tolist(), "J_warm": Jw.tolist()})
+        row = {"case": c.phantom_seed, "J_plain_T": float(Jp[-1]), "J_warm_0": float(Jw[0]),
+               "J_plain_0": float(Jp[0]), "accepted": acc, "iters_plain": n_p, "iters_warm": n_w,
+               "ms_plain": (t1 - t0) * 1e3, "ms_warm": (t2 - t1) * 1e3,
+               "J_warm_T": float(Jw[-1]), "J_plain": Jp.tolist(), "J_warm": Jw.tolist()}
+        if os_partition is not None:
+            rz, ry = os_partition
+            Jo = geo.recon_os(y, f, os_max_sweeps, beta, rz, ry)
+            n_o = first_reaching(Jo, target)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if n_o is not None:
+                geo.recon_os(y, f, n_o, beta, rz, ry)
+            torch.cuda.synchronize()
+            row.update(sweeps_os=n_o, ms_os=(time.perf_counter() - t3) * 1e3 if n_o is not None else None,
+                       J_os=Jo.tolist())
+        out.append(row)
         if log and (i + 1) % 20 == 0:
             log(f"eval {i + 1}/{len(cases)}")
     return out
@@ -291,7 +306,16 @@ def summarize(rows) -> dict:
     mw = np.array([r["ms_warm"] for r in rows])
     ip = np.array([r["iters_plain"] for r in rows], dtype=float)
     iw = np.array([np.nan if r["iters_warm"] is None else r["iters_warm"] for r in rows], dtype=float)
-    return {"cases": len(rows), "accept_rate": float(np.mean([r["accepted"] for r in rows])),
+    extra = {}
+    if rows and "sweeps_os" in rows[0]:
+        ok = [r for r in rows if r["sweeps_os"] is not None]
+        mo = np.array([r["ms_os"] for r in ok])
+        extra = {"os_reached_target": len(ok),
+                 "os_sweeps_mean": float(np.mean([r["sweeps_os"] for r in ok])) if ok else None,
+                 "ms_os_mean": float(mo.mean()) if ok else None,
+                 "ms_os_median": float(np.median(mo)) if ok else None,
+                 "speedup_os_mean_time": float(np.mean([r["ms_plain"] for r in ok]) / mo.mean()) if ok else None}
+    return {**extra, "cases": len(rows), "accept_rate": float(np.mean([r["accepted"] for r in rows])),
             "ms_plain_mean": float(mp.mean()), "ms_warm_mean": float(mw.mean()),
             "ms_plain_median": float(np.median(mp)), "ms_warm_median": float(np.median(mw)),
             "s_plain_total": float(mp.sum() / 1e3), "s_warm_total": float(mw.sum() / 1e3),

@@ -74,3 +74,17 @@ def test_os_argument_errors():
         with pytest.raises(csx.CsxError) as ei:
             geo.recon_os(dev(y), fd, 1, w.beta, rz, ry)
         assert ei.value.code == csx.CSX_EINVAL
+
+
+def test_os_after_a_launch_shape_change(oracle_mod):
+    """The subset launches follow the handle's launch shape; a change after the
+    partition was built (more forward partials) still gives the same sweep."""
+    w, g, f, y = workload_data("slice32")
+    geo = csx.Geometry(g)
+    fa, fb = geo.new_image(), geo.new_image()
+    Ja = geo.recon_os(dev(y), fa, 1, w.beta, 8, 16)
+    lc = geo.get_launch()
+    geo.set_launch(lc["fwd_splits"], 16, 16)
+    Jb = geo.recon_os(dev(y), fb, 1, w.beta, 8, 16)
+    assert rel_l2(host(fb), host(fa)) <= 1e-6
+    np.testing.assert_allclose(Jb, Ja, rtol=1e-7)
