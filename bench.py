@@ -10,6 +10,7 @@ nominal voxel*pixel*q evaluations of one forward plus one adjoint
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --workload batch64 [--steps K] [--warmup W]
     python bench.py --workload warm [--tto-cases N]
+    python bench.py --workload os [--steps K]
 
 Prints one JSON line.  The roofline entry uses the work model of the direct
 evaluation (4 VALU lane-ops per open in-band triple, 60 per open pair, 10 per
@@ -169,6 +170,40 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_os(args):
+    """Ordered subsets (Alg. 6) with the paper's 64-subset partition on the
+    128^2 x 64q slice and its stored counts: a step is one sweep over all
+    subsets plus the full objective.  Nominal evals per sweep: one forward and
+    one adjoint over all pixels (the subsets cover the detector once) plus the
+    objective's forward."""
+    import torch
+
+    from paper_1603_06400_amd import csx, inputs
+
+    w = inputs.workload(WORKLOAD)
+    z = np.load(os.path.join(GOLDEN, f"{WORKLOAD}_counts.npz"))
+    g = w.geom.with_(C=float(z["C"]))
+    torch.cuda.set_device(0)
+    geo = csx.Geometry(g)
+    y = torch.tensor(z["y"], dtype=torch.float32, device="cuda")
+    f = geo.new_image()
+    geo.recon_os(y, f, max(1, args.warmup), w.beta, 8, 16)          # builds the partition
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = geo.recon_os(y, f, args.steps, w.beta, 8, 16, init_uniform=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / max(1, args.steps)
+    nominal = 3.0 * g.nvox * g.npix * g.nq
+    print(json.dumps({"metric": "ordered-subsets sweeps, 128^2 x 64q, 64 subsets (voxel*pixel*energy evals/s)",
+                      "value": nominal / (ms * 1e-3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "slice128_os64", "rho_z": 8, "rho_y": 16, "beta": w.beta,
+                                 "nominal_evals_per_step": nominal},
+                      "objective": [float(v) for v in J]}))
+
+
 def time_to_objective(n_cases: int, batched: bool = False, log=None) -> dict:
     """Time for the plain solver, for the judged learned warm start (network
     and judge included) and for ordered subsets (Alg. 6, 64 subsets) to reach
@@ -198,9 +233,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
                          "reference kernel for scaling HBM byte counters")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64", "warm"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64", "warm", "os"],
                     help="slice128 (default): the single 128^2 x 64q slice; batch64: the batched form; "
-                         "warm: time to the plain objective with the learned warm start")
+                         "warm: time to the plain objective with the learned warm start; os: sweeps of "
+                         "ordered subsets (Alg. 6, 64 subsets) on the slice")
     ap.add_argument("--tto-cases", type=int, default=4,
                     help="held-out phantoms for the time-to-objective entry (0: skip; warm workload: 200)")
     ap.add_argument("--tune-cache", default=None, metavar="PATH",
@@ -223,6 +259,9 @@ def main():
 
     if args.workload == "batch64":
         bench_batch(args)
+        return
+    if args.workload == "os":
+        bench_os(args)
         return
     if args.workload == "warm":
         import torch
