@@ -11,7 +11,8 @@ Layers, each following the paper (Odinaka et al., arXiv:1603.06400):
   evaluated per triple in double precision by ``csx_oracle.c`` (Alg. 1 and
   Alg. 3 without any optimisation).
 * ``objective`` -- J(f) = L(f) + beta R(f) of Sec. V (eqs. overall_objective,
-  standard_EPR) with the quadratic potential psi(t) = t^2/2.
+  standard_EPR) with the quadratic potential psi(t) = t^2/2 or Huber's
+  edge-preserving potential (``potential``).
 * ``surrogate_coefficients`` / ``lemma_minimizer`` / ``recon_step`` /
   ``recon`` -- the separable-surrogate EM-type update of Sec. VI, Alg. 5 and
   App. B-C (eqs. grad_sep_obj, f_update, Lemma 1).
@@ -188,7 +189,7 @@ class Oracle:
         g = self.geom
         return self.adjoint(np.ones((g.ndy, g.ndx)))
 
-    def recon_step(self, y, r, fhat, beta, b1=None):
+    def recon_step(self, y, r, fhat, beta, b1=None, psi=None):
         """One iteration of Alg. 5 from fhat; returns (f_next, J(fhat))."""
         g = self.geom
         y = np.asarray(y, dtype=np.float64).reshape(g.ndy, g.ndx)
@@ -197,22 +198,22 @@ class Oracle:
         if b1 is None:
             b1 = self.sensitivity()
         z = self.forward(fhat) + r
-        J = objective_from_mean(y, z, fhat, beta)
+        J = objective_from_mean(y, z, fhat, beta, psi)
         b2 = self.adjoint(poisson_ratio(y, z))
-        return em_update(fhat, b1, b2, beta), J
+        return em_update(fhat, b1, b2, beta, psi), J
 
-    def recon(self, y, r, f0, n_iter, beta):
+    def recon(self, y, r, f0, n_iter, beta, psi=None):
         """Alg. 5: n_iter iterations from f0; returns (f_T, [J(f^0), ..., J(f^T)])."""
         b1 = self.sensitivity()
         f = np.asarray(f0, dtype=np.float64).copy()
         hist = []
         for _ in range(n_iter):
-            f, J = self.recon_step(y, r, f, beta, b1=b1)
+            f, J = self.recon_step(y, r, f, beta, b1=b1, psi=psi)
             hist.append(J)
         g = self.geom
         rr = np.zeros((g.ndy, g.ndx)) if r is None else np.asarray(r, dtype=np.float64).reshape(g.ndy, g.ndx)
         hist.append(objective_from_mean(np.asarray(y, dtype=np.float64).reshape(g.ndy, g.ndx),
-                                        self.forward(f) + rr, f, beta))
+                                        self.forward(f) + rr, f, beta, psi))
         return f, np.array(hist)
 
     def recon_os(self, y, r, f0, n_iter, beta, subsets):
@@ -244,11 +245,11 @@ class Oracle:
             hist.append(self.objective(y, r, f, beta))
         return f, np.array(hist)
 
-    def objective(self, y, r, f, beta) -> float:
+    def objective(self, y, r, f, beta, psi=None) -> float:
         g = self.geom
         y = np.asarray(y, dtype=np.float64).reshape(g.ndy, g.ndx)
         r = np.zeros_like(y) if r is None else np.asarray(r, dtype=np.float64).reshape(y.shape)
-        return objective_from_mean(y, self.forward(f) + r, f, beta)
+        return objective_from_mean(y, self.forward(f) + r, f, beta, psi)
 
 
 # ---- pieces of the objective and the update ----------------------------------------------
@@ -277,11 +278,42 @@ def neighbour_diffs(f: np.ndarray):
     return d, cnt
 
 
-def penalty(f: np.ndarray) -> float:
-    """R(f) = sum_j sum_{k in N_j} w_jk psi(f_j - f_k), psi(t) = t^2/2, w = 1
-    (Sec. V eq. standard_EPR; every neighbour pair appears once from each side)."""
+def neighbour_exists(f: np.ndarray) -> np.ndarray:
+    """[4][nz][nx] masks of the neighbours used by neighbour_diffs."""
+    nz, nx = np.asarray(f).shape[0], np.asarray(f).shape[1]
+    e = np.zeros((4, nz, nx), dtype=bool)
+    e[0, :, 1:] = True
+    e[1, :, :-1] = True
+    e[2, 1:] = True
+    e[3, :-1] = True
+    return e
+
+
+def potential(psi):
+    """(psi, psi', omega = psi'(t)/t) of a potential (Sec. V, App. B).
+    psi None or ("quadratic",): t^2/2.  ("huber", delta): Huber's potential,
+    t^2/2 for |t| <= delta and delta |t| - delta^2/2 beyond, so psi' = t or
+    delta sign(t) and omega = 1 or delta/|t| (omega(0) = 1)."""
+    if psi is None or psi[0] == "quadratic":
+        return (lambda t: 0.5 * t * t, lambda t: t, lambda t: np.ones_like(t))
+    if psi[0] == "huber":
+        dl = float(psi[1])
+        inner = lambda t: np.abs(t) <= dl
+        return (lambda t: np.where(inner(t), 0.5 * t * t, dl * np.abs(t) - 0.5 * dl * dl),
+                lambda t: np.where(inner(t), t, dl * np.sign(t)),
+                lambda t: np.where(inner(t), 1.0, dl / np.where(inner(t), 1.0, np.abs(t))))
+    raise ValueError(f"unknown potential {psi!r}")
+
+
+def penalty(f: np.ndarray, psi=None) -> float:
+    """R(f) = sum_j sum_{k in N_j} w_jk psi(f_j - f_k) with w = 1 (Sec. V eq.
+    standard_EPR; every neighbour pair appears once from each side)."""
     d, _ = neighbour_diffs(f)
-    return float(np.sum(0.5 * d * d))
+    e = neighbour_exists(f)
+    p, _, _ = potential(psi)
+    f = np.asarray(f)
+    mask = e if f.ndim == 2 else e[..., None] * np.ones(f.shape[2:], dtype=bool)
+    return float(np.sum(np.where(mask, p(d), 0.0)))
 
 
 def poisson_ratio(y: np.ndarray, z: np.ndarray) -> np.ndarray:
@@ -304,19 +336,22 @@ def data_fit(y: np.ndarray, z: np.ndarray) -> float:
     return float(np.sum(z - ylog + gammaln(y + 1.0)))
 
 
-def objective_from_mean(y, z, f, beta) -> float:
+def objective_from_mean(y, z, f, beta, psi=None) -> float:
     """J(f) = L(f) + beta R(f) (Sec. V eq. overall_objective)."""
-    return data_fit(y, z) + beta * penalty(f)
+    return data_fit(y, z) + beta * penalty(f, psi)
 
 
-def surrogate_coefficients(fhat, b1, b2, beta):
-    """b^(3)..b^(6) and chi^(1..3) of App. B for the quadratic potential
-    (psi'(t) = t, omega = psi'(t)/t = 1) with symmetric 4-neighbourhoods and w = 1."""
+def surrogate_coefficients(fhat, b1, b2, beta, psi=None):
+    """b^(3)..b^(6) and chi^(1..3) of App. B with symmetric 4-neighbourhoods
+    and w = 1: b3 = b4 = 2 sum_k omega(fhat_j - fhat_k), b5 = b6 = sum_k
+    psi'(fhat_j - fhat_k)."""
     fhat = np.asarray(fhat, dtype=np.float64)
     d, cnt = neighbour_diffs(fhat)
-    b3 = 2.0 * cnt[:, :, None] * np.ones_like(fhat)   # 2 sum_k w omega
-    b4 = b3.copy()                                     # same set for a symmetric N
-    b5 = d.sum(axis=0)                                 # sum_k w psi'(fhat_j - fhat_k)
+    e = neighbour_exists(fhat)[..., None]
+    _, dp, om = potential(psi)
+    b3 = 2.0 * np.sum(np.where(e, om(d), 0.0), axis=0)   # 2 sum_k w omega
+    b4 = b3.copy()                                        # same set for a symmetric N
+    b5 = np.sum(np.where(e, dp(d), 0.0), axis=0)         # sum_k w psi'(fhat_j - fhat_k)
     b6 = b5.copy()
     chi1 = beta * (b3 + b4)
     chi2 = b1 + beta * (-fhat * (b3 + b4) + b5 + b6)
@@ -346,13 +381,13 @@ def lemma_minimizer(a, b, c):
     return out
 
 
-def em_update(fhat, b1, b2, beta):
+def em_update(fhat, b1, b2, beta, psi=None):
     """f^{t+1} from eq. f_update (App. B) via Lemma 1.
 
     Lemma 1's unbounded case (chi1 = 0, chi2 <= 0) needs beta = 0 and a voxel
     that no pixel sees (b^(1)_j = 0); such a voxel keeps its previous value."""
     fhat = np.asarray(fhat, dtype=np.float64)
-    chi1, chi2, chi3 = surrogate_coefficients(fhat, b1, b2, beta)
+    chi1, chi2, chi3 = surrogate_coefficients(fhat, b1, b2, beta, psi)
     out = lemma_minimizer(chi1, chi2, chi3)
     stuck = (chi1 <= 0) & (chi2 <= 0)
     return np.where(stuck, fhat, out)
