@@ -142,6 +142,18 @@ csx_status csx_recon_step(csx_geometry *h, const float *y, const float *r, float
 csx_status csx_recon(csx_geometry *h, const float *y, const float *r, float *f,
                      int init_uniform, int n_iter, double beta, double *J_hist, void *stream);
 
+/* Penalty potential psi of R(f) = sum_j sum_{k in N_j} psi(f_j - f_k) (Sec. V
+ * eq. standard_EPR; 4 in-slice neighbours at the same q, w = 1).  Quadratic
+ * psi(t) = t^2/2 by default; CSX_PSI_HUBER: Huber's edge-preserving potential
+ * with scale delta > 0 (t^2/2 for |t| <= delta, delta |t| - delta^2/2
+ * beyond), whose separable surrogate (App. B) uses psi'(t) and the curvature
+ * omega(t) = psi'(t)/t.  Applies to every later csx_recon_step, csx_recon,
+ * csx_recon_os and batched call on the handle and to their objectives.
+ * CSX_EINVAL for an unknown kind or a bad delta. */
+#define CSX_PSI_QUADRATIC 0
+#define CSX_PSI_HUBER 1
+csx_status csx_set_penalty(csx_geometry *h, int kind, double delta);
+
 /* Alg. 6, ordered subsets: n_iter sweeps over the detector subsets of the
  * symmetry-preserving partition of Sec. VI.  Vertical class rz (0 <= rz <
  * rho_z) holds rows rz, rz + rho_z, ... of one half of the detector and their

@@ -458,3 +458,18 @@ extern "C" csx_status csx_recon_warm(csx_geometry *h, const float *y, const floa
     if (accepted) *accepted = take ? 1 : 0;
     return CSX_OK;
 }
+
+extern "C" csx_status csx_set_penalty(csx_geometry *h, int kind, double delta)
+{
+    if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
+    if (kind == CSX_PSI_QUADRATIC) {
+        h->psi_delta = 0.0;
+        return CSX_OK;
+    }
+    if (kind == CSX_PSI_HUBER) {
+        if (!(std::isfinite(delta) && delta > 0.0)) return csx_fail(CSX_EINVAL, "Huber scale must be finite and > 0");
+        h->psi_delta = delta;
+        return CSX_OK;
+    }
+    return csx_fail(CSX_EINVAL, "unknown penalty potential");
+}

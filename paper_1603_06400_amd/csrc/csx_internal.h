@@ -119,6 +119,7 @@ struct csx_geometry {
     int *partF = nullptr;      // per-block flags of the data term
     int *flags = nullptr;      // flags of the last objective: bit 0: y_i > 0 with zero
                                // mean; bit 1: y_i < 0 or NaN
+    double psi_delta = 0.0;    // penalty potential: 0 quadratic, > 0 Huber scale
     void *os = nullptr;        // ordered-subsets state (csx_os.hip), on demand
     float *fplain = nullptr;   // [nvox*nq] plain-start iterate of the warm-start judge
     float *a1 = nullptr;       // [npix] A 1 (forward of the all-ones image), on demand

@@ -75,11 +75,28 @@ __global__ void __launch_bounds__(256) k_ratio(int n, const float *__restrict__ 
 // The first form is Lemma 1's root multiplied through by its conjugate.
 // Also accumulates R(fhat) = sum_j sum_k (fhat_j - fhat_k)^2 / 2 per block.
 // ---------------------------------------------------------------------------
+// Potential psi of the penalty at a neighbour difference d: adds psi(d) to R,
+// psi'(d) to s and omega(d) = psi'(d)/d to w.  delta <= 0: quadratic t^2/2;
+// delta > 0: Huber's potential (t^2/2 inside |t| <= delta, linear outside).
+__device__ __forceinline__ void potential(double d, double delta, double &R, double &s, double &w)
+{
+    const double ad = fabs(d);
+    if (delta <= 0.0 || ad <= delta) {
+        R += 0.5 * d * d;
+        s += d;
+        w += 1.0;
+    } else {
+        R += delta * ad - 0.5 * delta * delta;
+        s += d > 0.0 ? delta : -delta;
+        w += delta / ad;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const float *__restrict__ fh,
                                                 const float *__restrict__ b1,
                                                 const float *__restrict__ b2, double beta,
                                                 float *__restrict__ fout,
-                                                double *__restrict__ partR, int do_update)
+                                                double *__restrict__ partR, int do_update, double delta)
 {
     __shared__ double s_red[4];
     const int n = nx * nz * nq;
@@ -90,15 +107,14 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
         const int j = e / nq;
         const int ix = j % nx, iz = j / nx;
         const double fj = fh[e];
-        double s = 0.0, rr = 0.0;
-        int cnt = 0;
-        if (ix > 0) { const double d = fj - fh[e - nq]; s += d; rr += d * d; ++cnt; }
-        if (ix < nx - 1) { const double d = fj - fh[e + nq]; s += d; rr += d * d; ++cnt; }
-        if (iz > 0) { const double d = fj - fh[e - (size_t)nx * nq]; s += d; rr += d * d; ++cnt; }
-        if (iz < nz - 1) { const double d = fj - fh[e + (size_t)nx * nq]; s += d; rr += d * d; ++cnt; }
-        R = 0.5 * rr;
+        double s = 0.0, w = 0.0;
+        if (ix > 0) potential(fj - fh[e - nq], delta, R, s, w);
+        if (ix < nx - 1) potential(fj - fh[e + nq], delta, R, s, w);
+        if (iz > 0) potential(fj - fh[e - (size_t)nx * nq], delta, R, s, w);
+        if (iz < nz - 1) potential(fj - fh[e + (size_t)nx * nq], delta, R, s, w);
         if (do_update) {
-            const double b34 = 4.0 * cnt;
+            // b3 + b4 = 4 sum omega, b5 + b6 = 2 sum psi' (symmetric neighbourhood, w_jk = 1)
+            const double b34 = 4.0 * w;
             const double chi1 = beta * b34;
             const double chi2 = (double)b1[e] + beta * (-fj * b34 + 2.0 * s);
             const double chi3 = fj * (double)b2[e];
@@ -222,7 +238,7 @@ csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool 
 {
     const KParams &P = h->P;
     hipLaunchKernelGGL(k_update, dim3(h->nbR), dim3(256), 0, s, P.nx, P.nz, P.nq, f, h->b1, h->b2,
-                       beta, h->ftmp, h->partR, do_update ? 1 : 0);
+                       beta, h->ftmp, h->partR, do_update ? 1 : 0, h->psi_delta);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
@@ -232,7 +248,7 @@ csx_status csx_launch_update_ex(csx_geometry *h, const float *f, const float *b1
 {
     const KParams &P = h->P;
     hipLaunchKernelGGL(k_update, dim3(h->nbR), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout,
-                       h->partR, 1);
+                       h->partR, 1, h->psi_delta);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }

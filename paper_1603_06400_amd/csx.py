@@ -17,6 +17,7 @@ from .build import LIB
 
 CSX_OK, CSX_EINVAL, CSX_EGEOM, CSX_EHIP, CSX_ENOMEM, CSX_ENUMERIC = 0, -1, -2, -3, -4, -5
 TABLE_F32, TABLE_BF16 = 0, 1
+PSI_QUADRATIC, PSI_HUBER = 0, 1
 _NAMES = {CSX_EINVAL: "EINVAL", CSX_EGEOM: "EGEOM", CSX_EHIP: "EHIP", CSX_ENOMEM: "ENOMEM",
           CSX_ENUMERIC: "ENUMERIC"}
 
@@ -56,7 +57,7 @@ class _Info(ctypes.Structure):
 
 
 EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_get_info",
-           "csx_forward", "csx_backproject", "csx_recon_step", "csx_recon", "csx_recon_os",
+           "csx_forward", "csx_backproject", "csx_recon_step", "csx_recon", "csx_recon_os", "csx_set_penalty",
            "csx_get_launch", "csx_set_launch", "csx_batch_create", "csx_batch_free",
            "csx_batch_recon", "csx_batch_recon_n", "csx_timing_enable", "csx_timing_read", "csx_last_error",
            "csx_cnn_workspace_bytes", "csx_conv3x3_forward", "csx_conv3x3_backward_data",
@@ -99,6 +100,8 @@ def lib():
         L.csx_recon_os.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
         L.csx_recon_os.restype = ctypes.c_int
+        L.csx_set_penalty.argtypes = [vp, ctypes.c_int, ctypes.c_double]
+        L.csx_set_penalty.restype = ctypes.c_int
         L.csx_get_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
         L.csx_get_launch.restype = ctypes.c_int
         L.csx_set_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
@@ -282,6 +285,13 @@ class Geometry:
                                hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
         return hist
 
+
+    def set_penalty(self, kind: str = "quadratic", delta: float = 0.0) -> None:
+        """Penalty potential: "quadratic" (t^2/2) or "huber" with scale delta."""
+        code = {"quadratic": PSI_QUADRATIC, "huber": PSI_HUBER}.get(kind)
+        if code is None:
+            raise ValueError(f"unknown potential {kind!r}")
+        _check(lib().csx_set_penalty(self._h, code, float(delta)))
 
     def recon_os(self, y: torch.Tensor, f: torch.Tensor, n_iter: int, beta: float, rho_z: int = 8,
                  rho_y: int = 16, r: Optional[torch.Tensor] = None, init_uniform: bool = True) -> np.ndarray:
