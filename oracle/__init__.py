@@ -18,6 +18,9 @@ Layers, each following the paper (Odinaka et al., arXiv:1603.06400):
   App. B-C (eqs. grad_sep_obj, f_update, Lemma 1).
 * ``os_partition`` / ``recon_os`` -- the ordered-subsets variant, Alg. 6,
   with the symmetry-preserving partition of Sec. VI.
+* ``forward_sai`` / ``adjoint_sai`` -- scatter-angle interpolation (Sec.
+  III-B, the precompute and interpolate lines of Alg. 2 / Alg. 4): W(r,
+  theta) of eq. q_integral on a uniform angle table, interpolated per pair.
 
 Parity status: every function here is pinned by tests in tests/test_oracle_*.py
 (closed forms, brute force, invariants); the absolute normalisation C has no
@@ -76,6 +79,10 @@ def _load():
         lib.orc_dense.argtypes = [gp, dp]
         lib.orc_census.argtypes = [gp, dp]
         lib.orc_margins.argtypes = [gp, dp]
+        lib.orc_forward_sai.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
+        lib.orc_adjoint_sai.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
+        lib.orc_max_angle.argtypes = [gp]
+        lib.orc_max_angle.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -171,6 +178,31 @@ class Oracle:
         H = np.zeros((g.npix, g.nvox * g.nq))
         self._lib.orc_dense(ctypes.byref(self._s), _dptr(H))
         return H
+
+    # ---- scatter-angle interpolation (Sec. III-B) --------------------------------
+    def max_angle(self) -> float:
+        """Largest scatter angle over all voxel-pixel pairs (rad)."""
+        return float(self._lib.orc_max_angle(ctypes.byref(self._s)))
+
+    def forward_sai(self, f: np.ndarray, nt: int, theta_max: float, interp: int = 1) -> np.ndarray:
+        """g with W(r, theta) interpolated from nt uniform angles on [0, theta_max]
+        (nearest node for interp = 0, linear for interp = 1); the geometric angle
+        factor stays exact per pair."""
+        g = self.geom
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(g.nz, g.nx, g.nq)
+        out = np.zeros((g.ndy, g.ndx))
+        self._lib.orc_forward_sai(ctypes.byref(self._s), int(nt), int(interp), float(theta_max), _dptr(f),
+                                  _dptr(out))
+        return out
+
+    def adjoint_sai(self, y: np.ndarray, nt: int, theta_max: float, interp: int = 1) -> np.ndarray:
+        """The transpose of forward_sai."""
+        g = self.geom
+        y = np.ascontiguousarray(y, dtype=np.float64).reshape(g.ndy, g.ndx)
+        out = np.zeros((g.nz, g.nx, g.nq))
+        self._lib.orc_adjoint_sai(ctypes.byref(self._s), int(nt), int(interp), float(theta_max), _dptr(y),
+                                  _dptr(out))
+        return out
 
     def census(self) -> dict:
         out = np.zeros(4)

@@ -247,6 +247,126 @@ void orc_adjoint_voxels(const orc_geom *g, const double *y, const int *vox, int 
     for (int k = 0; k < n; ++k) adjoint_one(g, y, vox[k], out + (long)k * g->nq);
 }
 
+/* ---- scatter-angle interpolation (Sec. III-B) -------------------------------------
+ * The spectral part of S(theta, q), q Phi(hc q / sin(theta/2)), is tabulated
+ * at nt uniformly spaced angles theta_t = t * theta_max / (nt - 1) (0 at
+ * theta = 0); W(r, theta) of eq. q_integral is evaluated at the table's
+ * angles and interpolated to a pair's angle, nearest node (interp = 0, the
+ * paper's choice) or linear (interp = 1).  The geometric angle factor
+ * (1 + cos^2 theta) cos(theta/2) / sin^2(theta/2) stays exact per pair. */
+typedef struct {
+    int nt, interp;
+    double theta_max;
+} orc_sai;
+
+static double sai_table(const orc_geom *g, const orc_sai *a, int t, double q)
+{
+    double th = t * a->theta_max / (a->nt - 1);
+    double sh = sin(0.5 * th);
+    if (sh <= 0.0) return 0.0;
+    return q * spectrum(g, g->hc * q / sh);
+}
+
+/* interpolation weights of a pair's angle: nodes t0, t0 + 1 with weights w0, w1 */
+static void sai_weights(const orc_sai *a, const orc_pair *p, int *t0, double *w0, double *w1)
+{
+    double th = 2.0 * atan2(p->sin_half, p->cos_half);
+    double u = th * (a->nt - 1) / a->theta_max;
+    if (a->interp == 0) {
+        double k = floor(u + 0.5);
+        if (k > a->nt - 1) k = a->nt - 1;
+        *t0 = (int)k;
+        *w0 = 1.0;
+        *w1 = 0.0;
+        return;
+    }
+    double k = floor(u);
+    if (k > a->nt - 2) k = a->nt - 2;
+    double fr = u - k;
+    if (fr > 1.0) fr = 1.0;
+    *t0 = (int)k;
+    *w0 = 1.0 - fr;
+    *w1 = fr;
+}
+
+/* the pair's weight without the spectrum: C Gso God T dtheta (1 + cos^2) cos(th/2) / sin^2(th/2) */
+static double sai_pair_weight(const orc_geom *g, const orc_pair *p)
+{
+    double c2 = p->theta_cos * p->theta_cos;
+    return g->C * p->Gso * p->God * p->T * p->dtheta * (1.0 + c2) * p->cos_half / (p->sin_half * p->sin_half);
+}
+
+void orc_forward_sai(const orc_geom *g, int nt, int interp, double theta_max, const double *f, double *out)
+{
+    orc_sai a = {nt, interp, theta_max};
+    int npix = g->ndx * g->ndy, nvox = g->nx * g->nz;
+    double *W = (double *)malloc(sizeof(double) * (size_t)nvox * nt);
+#pragma omp parallel for
+    for (int j = 0; j < nvox; ++j)
+        for (int t = 0; t < nt; ++t) {
+            double acc = 0.0;
+            for (int m = 0; m < g->nq; ++m) acc += sai_table(g, &a, t, g->q[m]) * f[(long)j * g->nq + m];
+            W[(long)j * nt + t] = acc;
+        }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < npix; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < nvox; ++j) {
+            orc_pair p;
+            pair_factors(g, j, i, &p);
+            int t0;
+            double w0, w1;
+            sai_weights(&a, &p, &t0, &w0, &w1);
+            double Wi = w0 * W[(long)j * nt + t0] + (w1 != 0.0 ? w1 * W[(long)j * nt + t0 + 1] : 0.0);
+            acc += sai_pair_weight(g, &p) * Wi;
+        }
+        out[i] = acc;
+    }
+    free(W);
+}
+
+void orc_adjoint_sai(const orc_geom *g, int nt, int interp, double theta_max, const double *y, double *out)
+{
+    orc_sai a = {nt, interp, theta_max};
+    int npix = g->ndx * g->ndy, nvox = g->nx * g->nz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < nvox; ++j) {
+        double *V = (double *)calloc((size_t)nt, sizeof(double));
+        for (int i = 0; i < npix; ++i) {
+            orc_pair p;
+            pair_factors(g, j, i, &p);
+            int t0;
+            double w0, w1;
+            sai_weights(&a, &p, &t0, &w0, &w1);
+            double c = sai_pair_weight(g, &p) * y[i];
+            V[t0] += w0 * c;
+            if (w1 != 0.0) V[t0 + 1] += w1 * c;
+        }
+        for (int m = 0; m < g->nq; ++m) {
+            double acc = 0.0;
+            for (int t = 0; t < nt; ++t) acc += V[t] * sai_table(g, &a, t, g->q[m]);
+            out[(long)j * g->nq + m] = acc;
+        }
+        free(V);
+    }
+}
+
+/* Largest scatter angle over all voxel-pixel pairs. */
+double orc_max_angle(const orc_geom *g)
+{
+    int npix = g->ndx * g->ndy, nvox = g->nx * g->nz;
+    double best = 0.0;
+#pragma omp parallel for reduction(max : best)
+    for (int j = 0; j < nvox; ++j)
+        for (int i = 0; i < npix; ++i) {
+            orc_pair p;
+            pair_factors(g, j, i, &p);
+            double th = 2.0 * atan2(p.sin_half, p.cos_half);
+            if (th > best) best = th;
+        }
+    return best;
+}
+
 /* Dense system matrix H[i][j*nq + m] for tiny problems. */
 void orc_dense(const orc_geom *g, double *H)
 {
