@@ -171,6 +171,48 @@ csx_status csx_set_penalty(csx_geometry *h, int kind, double delta);
 csx_status csx_recon_os(csx_geometry *h, const float *y, const float *r, float *f, int init_uniform,
                         int n_iter, int rho_z, int rho_y, double beta, double *J_hist, void *stream);
 
+/* Scatter-angle interpolation (Sec. III-B; the precomputation and the
+ * interpolated reads of Alg. 2 and Alg. 4).  The spectral part of S,
+ * s(theta, q) = q Phi(hc q / sin(theta/2)), is tabulated at nt angles
+ * theta_t = t theta_max / (nt - 1), t = 0 .. nt-1 (s = 0 at theta = 0), in
+ * float32; the geometric factor (1 + cos^2 theta) cos(theta/2) / sin^2(theta/2)
+ * stays exact per pair.  interp: 0 takes the nearest node (the paper's
+ * choice), 1 interpolates linearly between the two nodes around the pair's
+ * angle; angles beyond theta_max take the last node's value.  theta_max = 0 takes the
+ * largest scatter angle of the geometry (plus 1e-7 relative).
+ * nt: 2 .. CSX_SAI_MAX_NODES; theta_max: 0 or in (0, pi]; else CSX_EINVAL.
+ * Builds the table on the host in float64 and keeps it, with two
+ * [nvox][nt] float32 work arrays, on the handle; a later call replaces it.
+ * Synchronous. */
+#define CSX_SAI_MAX_NODES 1024
+csx_status csx_sai_config(csx_geometry *h, int nt, int interp, double theta_max);
+
+/* The configuration in force (CSX_EINVAL before csx_sai_config); any output
+ * pointer may be NULL. */
+csx_status csx_sai_info(const csx_geometry *h, int *nt, int *interp, double *theta_max);
+
+/* Forward with interpolated angles: W = f s^T ([nvox][nq] x [nq][nt], on the
+ * matrix cores), then g_i = sum_j A_ij T_ij W_j(theta_ij) with W_j read at the
+ * interpolation nodes of the pair's angle.  Buffers as for csx_forward.
+ * CSX_EINVAL before csx_sai_config.  Asynchronous on `stream`. */
+csx_status csx_forward_sai(csx_geometry *h, const float *f, float *g, void *stream);
+
+/* The exact transpose of csx_forward_sai: V_jt = sum_i A_ij T_ij y_i w_t(theta_ij)
+ * (w_t: the pair's interpolation weight of node t), then b = V s
+ * ([nvox][nt] x [nt][nq]).  Buffers as for csx_backproject.  Asynchronous. */
+csx_status csx_backproject_sai(csx_geometry *h, const float *y, float *b, void *stream);
+
+/* Operators of the solver: bit CSX_OP_FORWARD_SAI makes csx_recon_step,
+ * csx_recon and csx_recon_warm use csx_forward_sai for A f (objectives
+ * included), bit CSX_OP_ADJOINT_SAI makes them use csx_backproject_sai for
+ * A^T rho and for the sensitivity A^T 1 (recomputed after a change).  With one
+ * bit only, the adjoint is not the transpose of the forward and J need not
+ * decrease.  ops != 0 needs csx_sai_config first; csx_recon_os and batches
+ * return CSX_EINVAL while ops != 0.  Default 0 (exact operators). */
+#define CSX_OP_FORWARD_SAI 1
+#define CSX_OP_ADJOINT_SAI 2
+csx_status csx_set_operator(csx_geometry *h, int ops);
+
 /* Launch shape of a handle's operators; a tuner may change it (results do not
  * depend on it beyond float32 summation order).
  *   fwd_splits: the forward's voxel range is split over this many block rows

@@ -100,6 +100,7 @@ static void release_events(csx_geometry *h)
 static void free_all(csx_geometry *h)
 {
     csx_os_free(h);
+    csx_sai_free(h);
     void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qblk, h->t.qv, h->t.phi32,
                     h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
                     h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags,
@@ -129,6 +130,8 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     csx_geometry *h = new (std::nothrow) csx_geometry();
     if (!h) return csx_fail(CSX_ENOMEM, "host allocation failed");
     h->d = *d;
+    h->q_host.assign(d->q, d->q + d->nq);
+    h->phi_host.assign(d->phi, d->phi + d->ne);
     h->d.q = nullptr;
     h->d.phi = nullptr;
     h->d.mask = nullptr;
@@ -362,10 +365,22 @@ extern "C" csx_status csx_backproject(csx_geometry *h, const float *y, float *b,
 
 static csx_status ensure_b1(csx_geometry *h, hipStream_t s) { return csx_ensure_b1(h, s); }
 
+// the solver's operators: exact, or interpolated in angle (csx_set_operator)
+static csx_status solver_forward(csx_geometry *h, const float *f, float *g, hipStream_t s)
+{
+    return (h->op_sai & CSX_OP_FORWARD_SAI) ? csx_launch_forward_sai(h, f, g, s) : csx_launch_forward(h, f, g, s);
+}
+
+static csx_status solver_adjoint(csx_geometry *h, const float *rho, float *b, hipStream_t s)
+{
+    return (h->op_sai & CSX_OP_ADJOINT_SAI) ? csx_launch_adjoint_sai(h, rho, b, s)
+                                            : csx_launch_adjoint(h, rho, b, s);
+}
+
 csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s)
 {
     if (h->have_b1) return CSX_OK;
-    csx_status st = csx_launch_adjoint(h, h->ones, h->b1, s);
+    csx_status st = solver_adjoint(h, h->ones, h->b1, s);
     if (st != CSX_OK) return st;
     h->have_b1 = true;
     return CSX_OK;
@@ -381,9 +396,9 @@ static csx_status step_impl(csx_geometry *h, const float *y, const float *r, flo
                             double *J, hipStream_t s)
 {
     ST_TRY(ensure_b1(h, s));
-    ST_TRY(csx_launch_forward(h, f, h->gws, s));                // z = A f^t (+ r below)
+    ST_TRY(solver_forward(h, f, h->gws, s));                    // z = A f^t (+ r below)
     ST_TRY(csx_launch_ratio(h, y, r, true, s));                 // rho = y / z, data-fit partials
-    ST_TRY(csx_launch_adjoint(h, h->rho, h->b2, s));            // b2 = A^T rho
+    ST_TRY(solver_adjoint(h, h->rho, h->b2, s));                // b2 = A^T rho
     ST_TRY(csx_launch_update(h, f, beta, true, s));             // f^{t+1} into ftmp, R(f^t) partials
     if (J) ST_TRY(csx_launch_objective(h, beta, J, nullptr, s)); // J(f^t)
     return csx_launch_copy(h->ftmp, f, h->P.nvox * h->P.nq, s);
@@ -417,7 +432,7 @@ extern "C" csx_status csx_recon(csx_geometry *h, const float *y, const float *r,
     if (init_uniform) ST_TRY(csx_launch_uniform_start(h, y, f, s));
     for (int t = 0; t < n_iter; ++t) ST_TRY(step_impl(h, y, r, f, beta, h->jhist + t, s));
     // J at the final iterate
-    ST_TRY(csx_launch_forward(h, f, h->gws, s));
+    ST_TRY(solver_forward(h, f, h->gws, s));
     ST_TRY(csx_launch_ratio(h, y, r, false, s));
     ST_TRY(csx_launch_update(h, f, beta, false, s));
     ST_TRY(csx_launch_objective(h, beta, h->jhist + n_iter, nullptr, s));

@@ -264,6 +264,7 @@ extern "C" csx_status csx_batch_recon_n(csx_batch *b, const float *const *y, con
     int n_max = 0;
     for (int k = 0; k < n; ++k) {
         if (!y[k] || !f[k]) return csx_fail(CSX_EINVAL, "NULL scan buffer");
+        if (b->h[k]->op_sai) return csx_fail(CSX_EINVAL, "batches use the exact operators (csx_set_operator(h, 0))");
         if (n_iter[k] < 0) return csx_fail(CSX_EINVAL, "n_iter must be >= 0");
         n_max = std::max(n_max, n_iter[k]);
     }

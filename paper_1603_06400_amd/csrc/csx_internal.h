@@ -125,6 +125,9 @@ struct csx_geometry {
     float *a1 = nullptr;       // [npix] A 1 (forward of the all-ones image), on demand
     float *warm = nullptr;     // activations of the warm-start network
     size_t warm_cap = 0;       // floats in warm
+    void *sai = nullptr;       // scatter-angle-interpolation tables (csx_sai.hip), on demand
+    int op_sai = 0;            // solver operators: bit 0 forward, bit 1 adjoint interpolated
+    std::vector<double> q_host, phi_host;   // the descriptor's q nodes and spectrum
     int nbL = 0, nbR = 0;
     bool have_b1 = false;
     int64_t bytes = 0;
@@ -170,6 +173,10 @@ csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, h
 csx_status csx_launch_uniform_sums(csx_geometry *h, const float *y, hipStream_t s);
 csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s);
 void csx_os_free(csx_geometry *h);
+// scatter-angle interpolation (csx_sai.hip)
+void csx_sai_free(csx_geometry *h);
+csx_status csx_launch_forward_sai(csx_geometry *h, const float *f, float *g, hipStream_t s);
+csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, hipStream_t s);
 csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s);
 csx_status csx_launch_fill(float *dst, int n, float v, hipStream_t s);
 csx_status csx_launch_clear_flags(csx_geometry *h, hipStream_t s);

@@ -38,212 +38,9 @@
 //    are summed in a fixed order (bitwise reproducible).
 #include "csx_internal.h"
 
+#include "csx_device.h"
+
 namespace {
-
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t h)
-{
-    return __uint_as_float(((uint32_t)h) << 16);
-}
-
-// The spectrum table in LDS is always float32: the bfloat16 form stores the
-// table in bfloat16 and widens it while staging (exact), so both forms share
-// one inner loop.
-__device__ __forceinline__ float spec(const float *s_phi, uint32_t k)
-{
-    return s_phi[k];
-}
-
-__device__ __forceinline__ double as_double(float lo, float hi)
-{
-    const uint64_t u = ((uint64_t)__float_as_uint(hi) << 32) | (uint64_t)__float_as_uint(lo);
-    return __longlong_as_double((long long)u);
-}
-
-__device__ __forceinline__ float dlo(double v)
-{
-    return __uint_as_float((uint32_t)((uint64_t)__double_as_longlong(v)));
-}
-
-__device__ __forceinline__ float dhi(double v)
-{
-    return __uint_as_float((uint32_t)((uint64_t)__double_as_longlong(v) >> 32));
-}
-
-__device__ __forceinline__ int posmod(int v, int p)
-{
-    int r = v % p;
-    return r + (r < 0 ? p : 0);
-}
-
-// Pair factors of voxel (vd, vf) and pixel (xp, yp, det_z).
-//   theta: sin^2(theta/2) = |r x r'|^2 / (2 |r||s| (|r||s| + r.s))  (no cancellation)
-//   kappa = hc / sin(theta/2) in float64; A in float32.
-//   dtheta = angle between s - (pitch/2) y^ and s + (pitch/2) y^
-//          = atan(pitch |s_xz| / (|s|^2 - pitch^2/4)).
-__device__ __forceinline__ void pair_factors(const KParams &P, const VoxD &vd, float2 vf,
-                                             double xp, double yp, double &kappa, float &A)
-{
-    const double x = vd.x, z = vd.z, R2 = vd.R2;
-    const double sx = xp - x, sz = P.det_zd - z;
-    const double h2 = sx * sx + sz * sz;
-    const double s2 = h2 + yp * yp;
-    const double dot = x * sx + z * sz;
-    const double cy = z * xp - x * P.det_zd;
-    const double cross2 = yp * yp * R2 + cy * cy;
-    const double Rs2 = R2 * s2;
-    const float rs0 = __builtin_amdgcn_sqrtf((float)Rs2);
-    const double Rs = (double)rs0 + (Rs2 - (double)rs0 * (double)rs0) * (double)(0.5f * __builtin_amdgcn_rcpf(rs0));
-    const double den = 2.0 * Rs * (Rs + dot);
-    const float r0 = __builtin_amdgcn_rcpf((float)cross2);
-    const double inv = (double)r0 * (2.0 - cross2 * (double)r0);
-    const double K2 = den * inv;   // 1 / sin^2(theta/2)
-    const float k0 = __builtin_amdgcn_sqrtf((float)K2);
-    const double k = (double)k0 + (K2 - (double)k0 * (double)k0) * (double)(0.5f * __builtin_amdgcn_rcpf(k0));
-    kappa = P.hc * k;
-
-    const float s2f = (float)s2;
-    const float inv_s = __builtin_amdgcn_rsqf(s2f);
-    const float God = vf.y * inv_s * inv_s * inv_s;
-    const float cos_t = (float)dot * __builtin_amdgcn_rcpf((float)Rs);
-    const float cos_h = __builtin_amdgcn_sqrtf(0.5f * (1.0f + cos_t));
-    const float num = P.pitch * __builtin_amdgcn_sqrtf((float)h2);
-    const float dnm = s2f - P.hp2;
-    const float tq = num * __builtin_amdgcn_rcpf(dnm);
-    float dth;
-    if (dnm > 0.0f && tq < 0.05f) {
-        // atan(t) = t - t^3/3 + t^5/5 - ...; the dropped terms are < 3e-9 relative
-        const float t2 = tq * tq;
-        dth = tq * fmaf(t2, fmaf(t2, 0.2f, -1.0f / 3.0f), 1.0f);
-    } else {
-        dth = atan2f(num, dnm);
-    }
-    A = vf.x * God * dth * fmaf(cos_t, cos_t, 1.0f) * cos_h * (float)K2;
-}
-
-__device__ __forceinline__ bool in_band(const KParams &P, double kappa)
-{
-    return kappa * P.q_max >= P.band_lo && kappa * P.q_min < P.band_hi;
-}
-
-// Spectrum-table index of one triple: 1 + bin inside the band; outside it the
-// index lands on one of the two zero pads (0 or ne + 1): a negative bin
-// coordinate wraps to a large unsigned value and is clamped to ne + 1.
-__device__ __forceinline__ uint32_t spec_index(double kappa, double qa, double b0, uint32_t top)
-{
-    const double u = fma(kappa, qa, b0);
-    const uint32_t k = (uint32_t)(int)u;
-    return min(k, top);
-}
-
-__device__ __forceinline__ void stage_tables(const KParams &P, const DevTables &T, float *s_phi,
-                                             uint32_t *s_bits)
-{
-    const int tid = threadIdx.x, nt = blockDim.x;
-    if (P.td == CSX_TABLE_BF16) {
-        for (int k = tid; k < P.ne + 2; k += nt) s_phi[k] = bf16_to_f32(T.phi16[k]);
-    } else {
-        for (int k = tid; k < P.ne + 2; k += nt) s_phi[k] = T.phi32[k];
-    }
-    for (int k = tid; k < P.mask_ny; k += nt) s_bits[k] = T.maskbits[k];
-}
-
-// Mask cells of one crossing: columns of the pixel (col_a) and of its x-mirror
-// seen from the mirror voxel (col_b), rows of y' (row_u) and -y' (row_d).
-struct Cells {
-    int col_a, col_b, row_u, row_d;
-    bool in_rows;
-};
-
-// v mod P for an integer-valued float v (|v| < 2^22): the quotient is taken at
-// v/P + 1/(2P), half a step away from any integer, so the float rounding of
-// 1/P cannot move it across one.
-__device__ __forceinline__ int fmodp(const KParams &P, float v)
-{
-    const float qf = floorf(fmaf(v, P.inv_mask_nx, 0.5f * P.inv_mask_nx));
-    return (int)fmaf(-(float)P.mask_nx, qf, v);
-}
-
-__device__ __forceinline__ Cells mask_cells(const KParams &P, float2 vm, float xp, float yp)
-{
-    Cells c;
-    const float cx = floorf(fmaf(vm.x, xp, vm.y));
-    const int cy = (int)floorf(fmaf(vm.x, yp, P.half_my));
-    c.col_a = fmodp(P, cx);
-    c.col_b = fmodp(P, -cx - 1.0f);          // floor(-px) = -floor(px) - 1 off the cell edges
-    c.row_u = cy;
-    c.row_d = P.mask_ny - 1 - cy;            // floor(My - v) = My - 1 - floor(v)
-    c.in_rows = cy >= 0 && cy < P.mask_ny;
-    return c;
-}
-
-__device__ __forceinline__ float bitf(uint32_t row, int col)
-{
-    return (float)((row >> col) & 1u);
-}
-
-// Sum of v[0..N) over the 64 lanes of the wave, butterfly style: at each
-// distance d the lanes with bit d set keep the upper half of their values and
-// send the lower half to their partner (and vice versa), so after six steps
-// lane l holds the total for index l >> (6 - log2 N).
-template <int N, int D>
-struct WaveTransposeSum {
-    static __device__ __forceinline__ void run(float *v, int lane)
-    {
-        if constexpr (D == 0) {
-            return;
-        } else if constexpr (N > 1) {
-            constexpr int H = N / 2;
-            const bool up = (lane & D) != 0;
-#pragma unroll
-            for (int i = 0; i < H; ++i) {
-                const float send = up ? v[i] : v[H + i];
-                const float keep = up ? v[H + i] : v[i];
-                v[i] = keep + __shfl_xor(send, D, 64);
-            }
-            WaveTransposeSum<H, D / 2>::run(v, lane);
-        } else {
-            v[0] += __shfl_xor(v[0], D, 64);
-            WaveTransposeSum<1, D / 2>::run(v, lane);
-        }
-    }
-};
-
-__device__ __forceinline__ int wave_min(int v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-__device__ __forceinline__ int wave_max(int v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-// Bin coordinate of q node m on a uniform q grid: u_m = u0 + m du with
-// u0 = kappa q_0/dE + 1 - e_lo/dE and du = kappa dq/dE (an FP64 FMA at nodes
-// 0, 8, 16, ..., one FP64 add per node between).
-// Nodes whose energy can be in band satisfy 1 <= u_m < ne + 1; the returned
-// range [lo, hi] (chunk-local, widened by one node each side) contains them.
-__device__ __forceinline__ void band_range(const KParams &P, double u0, double du, int m0, int qw,
-                                           int &lo, int &hi)
-{
-    const float fu0 = (float)u0, fdu = (float)du;
-    const float a = (1.0f - fu0) / fdu, b = ((float)P.ne + 1.0f - fu0) / fdu;
-    const float l = fmaxf(floorf(a) - 1.0f - (float)m0, -1.0f);
-    const float h = fminf(floorf(b) + 1.0f - (float)m0, (float)qw);
-    lo = (int)l;
-    hi = (int)h;
-}
-
-template <int QW>
-__device__ __forceinline__ int transposed_index(int lane)
-{
-    return QW == 64 ? lane : (QW == 32 ? (lane >> 1) : (lane >> 2));
-}
 
 // ---------------------------------------------------------------------------
 // adjoint: one wave per voxel group (voxel j, and its mirror j2 with LR) and

@@ -156,6 +156,7 @@ extern "C" csx_status csx_recon_os(csx_geometry *h, const float *y, const float 
     if (!h || !y || !f) return csx_fail(CSX_EINVAL, "NULL argument");
     if (n_iter < 0) return csx_fail(CSX_EINVAL, "n_iter must be >= 0");
     if (!(std::isfinite(beta) && beta >= 0.0)) return csx_fail(CSX_EINVAL, "beta must be finite and >= 0");
+    if (h->op_sai) return csx_fail(CSX_EINVAL, "ordered subsets use the exact operators (csx_set_operator(h, 0))");
     const KParams &P = h->P;
     if (rho_z < 1 || rho_y < 2 || rho_y % 2 || (P.ndy / 2) % rho_z || P.ndx % rho_y)
         return csx_fail(CSX_EINVAL, "partition needs rho_z | ndy/2, rho_y | ndx and rho_y even");

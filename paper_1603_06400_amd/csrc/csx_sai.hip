@@ -1,0 +1,532 @@
+// csx_sai.hip -- scatter-angle interpolation (Sec. III-B, the precompute and
+// interpolate lines of Alg. 2 and Alg. 4).
+//
+// The spectral part of S(theta, q), s(theta, q) = q Phi(hc q / sin(theta/2)),
+// is tabulated at nt uniformly spaced angles theta_t = t theta_max / (nt - 1)
+// (float32, [nt][nq] and its transpose).  The geometric angle factor
+// (1 + cos^2 theta) cos(theta/2) / sin^2(theta/2) stays exact in the pair
+// weight A, as in the exact operators.
+//
+//   forward   W = f s^T, a dense [nvox x nq] x [nq x nt] product on the matrix
+//             cores (v_mfma_f32_16x16x4_f32); then per pair one interpolated
+//             read of W(theta_ij, j) replaces the q loop of the exact forward.
+//   adjoint   per voxel, V(j, t) = sum_i A_ij T_ij rho_i w_t(theta_ij) (the
+//             interpolation weights) collected in a per-wave LDS histogram,
+//             then b = V s, a dense [nvox x nt] x [nt x nq] product.
+//
+// The histogram adds are LDS atomics into memory that only the adding wave
+// touches; the lanes of one instruction are applied in a fixed order, so runs
+// are reproducible bit for bit (tested).  Interpolation: nearest node (the
+// paper's choice) or linear.
+#include "csx_device.h"
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+struct SaiState {
+    int nt = 0, interp = 1;
+    double theta_max = 0.0;
+    float inv_dth = 0.0f;          // (nt - 1) / theta_max
+    float *S = nullptr;            // [nt][nq] spectral part
+    float *St = nullptr;           // [nq][nt]
+    float *W = nullptr;            // [nvox][nt]
+    float *V = nullptr;            // [nvox][nt]
+    double *smid = nullptr;        // [nt - 1] sin(half the midpoint angle) / hc
+};
+
+void release(SaiState *s)
+{
+    if (!s) return;
+    void *ptrs[] = {s->S, s->St, s->W, s->V, s->smid};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete s;
+}
+
+// C[M][N] = sum_k A[m][k] B[n][k]: 64 x 64 tiles, 4 waves of 16 rows, K in
+// steps of 32 staged in LDS.  Lane l of v_mfma_f32_16x16x4_f32 holds A[l%16][l/16]
+// and B[l/16][l%16] of its 16 x 4 / 4 x 16 operands; D[4 (l/16) + v][l%16].
+__global__ void __launch_bounds__(256) k_gemm_nt(const float *__restrict__ A, int lda, const float *__restrict__ B,
+                                                 int ldb, float *__restrict__ C, int ldc, int M, int N, int K)
+{
+    __shared__ float sA[64][33];
+    __shared__ float sB[64][33];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    f4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        for (int e = tid; e < 64 * 32; e += 256) {
+            const int r = e >> 5, c = e & 31;
+            const int gk = k0 + c;
+            const int gm = m0 + r, gn = n0 + r;
+            sA[r][c] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.f;
+            sB[r][c] = (gn < N && gk < K) ? B[(size_t)gn * ldb + gk] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 4) {
+            const float a = sA[wave * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float b = sB[t * 16 + (lane & 15)][kk + (lane >> 4)];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = m0 + wave * 16 + 4 * (lane >> 4) + v;
+            const int col = n0 + t * 16 + (lane & 15);
+            if (row < M && col < N) C[(size_t)row * ldc + col] = acc[t][v];
+        }
+}
+
+__device__ __forceinline__ void stage_mask(const KParams &P, const DevTables &T, uint32_t *s_bits)
+{
+    for (int k = threadIdx.x; k < P.mask_ny; k += blockDim.x) s_bits[k] = T.maskbits[k];
+}
+
+// Interpolation node(s) of an angle: u = theta (nt - 1) / theta_max, from
+// float32 arithmetic (error below 2e-4 spacings).  The nearest-node rule
+// settles angles within 2e-3 spacings of a midpoint exactly: theta is past
+// midpoint k iff sin(theta/2) >= sin(theta_k+1/2 / 2), i.e. iff
+// smid[k] kappa <= 1 with smid[k] = sin(theta_k+1/2 / 2) / hc, in float64.
+template <int INTERP>
+__device__ __forceinline__ void nodes(float u, double kappa, const double *__restrict__ smid, int nt, int &t0,
+                                      float &w0, float &w1)
+{
+    if (INTERP == 0) {
+        t0 = min((int)(u + 0.5f), nt - 1);
+        if (fabsf(u - floorf(u) - 0.5f) < 2e-3f) {
+            const int k = min((int)u, nt - 2);   // the midpoint between nodes k and k + 1
+            t0 = smid[k] * kappa <= 1.0 ? k + 1 : k;
+        }
+        w0 = 1.0f;
+        w1 = 0.0f;
+    } else {
+        t0 = min((int)u, nt - 2);
+        const float fr = fminf(u - (float)t0, 1.0f);
+        w0 = 1.0f - fr;
+        w1 = fr;
+    }
+}
+
+__device__ __forceinline__ float angle_of(const KParams &P, double kappa)
+{
+    const float sh = fminf((float)P.hc * __builtin_amdgcn_rcpf((float)kappa), 1.0f);   // sin(theta/2)
+    return 2.0f * asinf(sh);
+}
+
+template <int INTERP>
+__device__ __forceinline__ float interp_w(const float *__restrict__ Wrow, int t0, float w0, float w1)
+{
+    return INTERP == 0 ? Wrow[t0] : fmaf(w0, Wrow[t0], w1 * Wrow[t0 + 1]);
+}
+
+// Forward pairs: one wave per pixel quad (as the exact forward), lanes = voxel
+// groups in 8 x 8 tiles over the block row's tile range; partial images per
+// block row.
+template <int LR, int INTERP>
+__global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds L, const float *__restrict__ W,
+                                                     const double *__restrict__ smid, int nt, float inv_dth,
+                                                     float *__restrict__ part,
+                                                     int tiles_per_split)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint32_t *s_bits = (uint32_t *)(lds + L.mask);
+    stage_mask(P, T, s_bits);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int quad = blockIdx.x * 8 + wv;
+    if (quad >= P.n_quad) return;
+    int a, bu;
+    if (LR) {
+        const int hx = P.ndx / 2;
+        a = hx + quad % hx;
+        bu = P.ndy / 2 + quad / hx;
+    } else {
+        a = quad % P.ndx;
+        bu = P.ndy / 2 + quad / P.ndx;
+    }
+    const float xpa = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
+    const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
+    const int gw = LR ? P.nx / 2 : P.nx;
+    const int ntx = (gw + 7) / 8;
+    const int ntiles = ntx * ((P.nz + 7) / 8);
+    const int t0 = blockIdx.y * tiles_per_split;
+    const int t1 = min(ntiles, t0 + tiles_per_split);
+    float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
+    for (int t = t0; t < t1; ++t) {
+        const int ix = (t % ntx) * 8 + (lane & 7), iz = (t / ntx) * 8 + (lane >> 3);
+        if (ix >= gw || iz >= P.nz) continue;
+        const int j = iz * P.nx + ix;
+        const int jm = LR ? iz * P.nx + (P.nx - 1 - ix) : j;
+        const VoxD vd = T.vd[j];
+        const float2 vf = T.vf[j], vm = T.vm[j];
+        const float *Wj = W + (size_t)j * nt;
+        const float *Wm = W + (size_t)jm * nt;
+        {
+            const Cells c = mask_cells(P, vm, xpa, yp);
+            float tau = 0.0f, tad = 0.0f, tbu = 0.0f, tbd = 0.0f;
+            if (c.in_rows) {
+                const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
+                tau = bitf(ru, c.col_a);
+                tad = bitf(rd, c.col_a);
+                if (LR) {
+                    tbu = bitf(ru, c.col_b);
+                    tbd = bitf(rd, c.col_b);
+                }
+            }
+            if (tau + tad + tbu + tbd != 0.0f) {
+                double k;
+                float A;
+                pair_factors(P, vd, vf, (double)xpa, (double)yp, k, A);
+                int n0;
+                float w0, w1;
+                nodes<INTERP>(angle_of(P, k) * inv_dth, k, smid, nt, n0, w0, w1);
+                const float wa = interp_w<INTERP>(Wj, n0, w0, w1);
+                o0 = fmaf(A * tau, wa, o0);
+                o1 = fmaf(A * tad, wa, o1);
+                if (LR) {
+                    const float wb = interp_w<INTERP>(Wm, n0, w0, w1);
+                    o2 = fmaf(A * tbu, wb, o2);
+                    o3 = fmaf(A * tbd, wb, o3);
+                }
+            }
+        }
+        if (LR) {
+            const Cells c = mask_cells(P, vm, -xpa, yp);
+            float tau = 0.0f, tad = 0.0f, tbu = 0.0f, tbd = 0.0f;
+            if (c.in_rows) {
+                const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
+                tau = bitf(ru, c.col_a);
+                tad = bitf(rd, c.col_a);
+                tbu = bitf(ru, c.col_b);
+                tbd = bitf(rd, c.col_b);
+            }
+            if (tau + tad + tbu + tbd != 0.0f) {
+                double k;
+                float A;
+                pair_factors(P, vd, vf, -(double)xpa, (double)yp, k, A);
+                int n0;
+                float w0, w1;
+                nodes<INTERP>(angle_of(P, k) * inv_dth, k, smid, nt, n0, w0, w1);
+                const float wa = interp_w<INTERP>(Wj, n0, w0, w1);
+                const float wb = interp_w<INTERP>(Wm, n0, w0, w1);
+                // pixel (-a) seen from voxel j is pixel (a) seen from the mirror voxel
+                o0 = fmaf(A * tbu, wb, o0);
+                o1 = fmaf(A * tbd, wb, o1);
+                o2 = fmaf(A * tau, wa, o2);
+                o3 = fmaf(A * tad, wa, o3);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        o0 += __shfl_xor(o0, off, 64);
+        o1 += __shfl_xor(o1, off, 64);
+        if (LR) {
+            o2 += __shfl_xor(o2, off, 64);
+            o3 += __shfl_xor(o3, off, 64);
+        }
+    }
+    if (lane == 0) {
+        float *dst = part + (size_t)blockIdx.y * P.npix;
+        const int bd = P.ndy - 1 - bu;
+        dst[bu * P.ndx + a] = o0;
+        dst[bd * P.ndx + a] = o1;
+        if (LR) {
+            const int ab = P.ndx - 1 - a;
+            dst[bu * P.ndx + ab] = o2;
+            dst[bd * P.ndx + ab] = o3;
+        }
+    }
+}
+
+// Adjoint pairs: one wave per voxel group (voxel j, and its mirror with LR),
+// lanes = pixel classes in 8 x 8 tiles; the weighted ratios go to the wave's
+// two angle histograms in LDS, which are then written to V.
+template <int LR, int INTERP>
+__global__ void __launch_bounds__(256) k_adjoint_sai(KParams P, DevTables T, Lds L, const float *__restrict__ rho,
+                                                     float *__restrict__ V, const double *__restrict__ smid, int nt,
+                                                     float inv_dth)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint32_t *s_bits = (uint32_t *)(lds + L.mask);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float *h0 = (float *)(lds + L.tile) + (size_t)wv * 2 * nt;
+    float *h1 = h0 + nt;
+    stage_mask(P, T, s_bits);
+    for (int k = lane; k < 2 * nt; k += 64) h0[k] = 0.0f;
+    __syncthreads();
+    const int g = blockIdx.x * 4 + wv;
+    if (g >= P.n_groups) return;
+    int j, j2;
+    if (LR) {
+        const int half = P.nx / 2;
+        const int iz = g / half, ix = g % half;
+        j = iz * P.nx + ix;
+        j2 = iz * P.nx + (P.nx - 1 - ix);
+    } else {
+        j = g;
+        j2 = g;
+    }
+    const VoxD vd = T.vd[j];
+    const float2 vf = T.vf[j], vm = T.vm[j];
+    const int half_y = P.ndy / 2;
+    const int ntx = (P.ndx + 7) / 8;
+    const int ntiles = ntx * ((half_y + 7) / 8);
+    for (int t = 0; t < ntiles; ++t) {
+        const int a = (t % ntx) * 8 + (lane & 7);
+        const int r = (t / ntx) * 8 + (lane >> 3);
+        if (a >= P.ndx || r >= half_y) continue;
+        const int bu = half_y + r, bd = P.ndy - 1 - bu;
+        const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
+        const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
+        const Cells c = mask_cells(P, vm, xp, yp);
+        if (!c.in_rows) continue;
+        const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
+        const float w0 = bitf(ru, c.col_a) * rho[bu * P.ndx + a] + bitf(rd, c.col_a) * rho[bd * P.ndx + a];
+        float w1 = 0.0f;
+        if (LR) {
+            const int ab = P.ndx - 1 - a;
+            w1 = bitf(ru, c.col_b) * rho[bu * P.ndx + ab] + bitf(rd, c.col_b) * rho[bd * P.ndx + ab];
+        }
+        if (w0 == 0.0f && w1 == 0.0f) continue;
+        double k;
+        float A;
+        pair_factors(P, vd, vf, (double)xp, (double)yp, k, A);
+        int n0;
+        float u0, u1;
+        nodes<INTERP>(angle_of(P, k) * inv_dth, k, smid, nt, n0, u0, u1);
+        const float c0 = A * w0, c1 = A * w1;
+        atomicAdd(&h0[n0], c0 * u0);
+        if (INTERP) atomicAdd(&h0[n0 + 1], c0 * u1);
+        if (LR) {
+            atomicAdd(&h1[n0], c1 * u0);
+            if (INTERP) atomicAdd(&h1[n0 + 1], c1 * u1);
+        }
+    }
+    float *vj = V + (size_t)j * nt;
+    for (int k = lane; k < nt; k += 64) vj[k] = h0[k];
+    if (LR) {
+        float *v2 = V + (size_t)j2 * nt;
+        for (int k = lane; k < nt; k += 64) v2[k] = h1[k];
+    }
+}
+
+int al16(int v) { return (v + 15) & ~15; }
+
+Lds sai_lds(const KParams &P, int hist_floats)
+{
+    Lds L;
+    int off = 0;
+    L.phi = 0;
+    L.mask = off;
+    off += al16(P.mask_ny * 4);
+    L.tile = off;
+    off += hist_floats * 4;
+    L.total = off;
+    return L;
+}
+
+csx_status gemm_nt(const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M, int N, int K,
+                   hipStream_t s)
+{
+    dim3 grid((M + 63) / 64, (N + 63) / 64);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+// Largest scatter angle over the voxels and the detector's edge pixels (the
+// angle seen from a voxel has no interior maximum on the detector plane).
+double max_angle(const csx_geometry *h)
+{
+    const csx_geometry_desc &d = h->d;
+    const double dx = (d.x_max - d.x_min) / d.nx, dz = (d.z_max - d.z_min) / d.nz;
+    double best = 0.0;
+    for (int iz = 0; iz < d.nz; ++iz)
+        for (int ix = 0; ix < d.nx; ++ix) {
+            const double x = d.x_min + (ix + 0.5) * dx, z = d.z_min + (iz + 0.5) * dz;
+            for (int b = 0; b < d.ndy; ++b)
+                for (int a = 0; a < d.ndx; ++a) {
+                    if (b != 0 && b != d.ndy - 1 && a != 0 && a != d.ndx - 1) continue;
+                    const double xp = (a - d.ndx / 2.0 + 0.5) * d.det_pitch;
+                    const double yp = (b - d.ndy / 2.0 + 0.5) * d.det_pitch;
+                    const double sx = xp - x, sy = yp, sz = d.det_z - z;
+                    const double cx = -z * sy, cy = z * sx - x * sz, cz = x * sy;
+                    const double cr = std::sqrt(cx * cx + cy * cy + cz * cz), dt = x * sx + z * sz;
+                    best = std::max(best, std::atan2(cr, dt));
+                }
+        }
+    return best;
+}
+
+SaiState *state(const csx_geometry *h) { return static_cast<SaiState *>(h->sai); }
+
+}  // namespace
+
+void csx_sai_free(csx_geometry *h)
+{
+    release(state(h));
+    h->sai = nullptr;
+}
+
+extern "C" csx_status csx_sai_config(csx_geometry *h, int nt, int interp, double theta_max)
+{
+    if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
+    if (nt < 2 || nt > CSX_SAI_MAX_NODES) return csx_fail(CSX_EINVAL, "nt must be in [2, 1024]");
+    if (interp != 0 && interp != 1) return csx_fail(CSX_EINVAL, "interp must be 0 (nearest) or 1 (linear)");
+    if (!(std::isfinite(theta_max) && theta_max >= 0.0) || theta_max > M_PI)
+        return csx_fail(CSX_EINVAL, "theta_max must be in [0, pi] (0: the largest pair angle)");
+    const csx_geometry_desc &d = h->d;
+    const int nq = h->P.nq, nvox = h->P.nvox;
+    double tm = theta_max > 0.0 ? theta_max : max_angle(h) * (1.0 + 1e-7);
+    // spectral part of S at the table's angles, float64 then float32
+    std::vector<float> S((size_t)nt * nq), St((size_t)nq * nt);
+    const double de = (d.e_hi - d.e_lo) / d.ne;
+    const std::vector<double> &phi = h->phi_host;
+    for (int t = 0; t < nt; ++t) {
+        const double sh = std::sin(0.5 * t * tm / (nt - 1));
+        for (int m = 0; m < nq; ++m) {
+            double v = 0.0;
+            if (sh > 0.0) {
+                const double q = h->q_host[m];
+                const double kb = std::floor((d.hc * q / sh - d.e_lo) / de);
+                if (kb >= 0.0 && kb < d.ne) v = q * phi[(int)kb];
+            }
+            S[(size_t)t * nq + m] = (float)v;
+            St[(size_t)m * nt + t] = (float)v;
+        }
+    }
+    std::vector<double> smid(nt - 1);
+    for (int k = 0; k < nt - 1; ++k) smid[k] = std::sin(0.5 * (k + 0.5) * tm / (nt - 1)) / d.hc;
+    SaiState *s = new (std::nothrow) SaiState();
+    if (!s) return csx_fail(CSX_ENOMEM, "host allocation failed");
+    s->nt = nt;
+    s->interp = interp;
+    s->theta_max = tm;
+    s->inv_dth = (float)((nt - 1) / tm);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc((void **)&s->S, sizeof(float) * S.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&s->St, sizeof(float) * St.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&s->W, sizeof(float) * (size_t)nvox * nt);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->V, sizeof(float) * (size_t)nvox * nt);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->smid, sizeof(double) * smid.size());
+    if (e == hipSuccess) e = hipMemcpy(s->smid, smid.data(), sizeof(double) * smid.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->S, S.data(), sizeof(float) * S.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->St, St.data(), sizeof(float) * St.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        release(s);
+        return csx_fail(CSX_EHIP, std::string("scatter-angle tables: ") + hipGetErrorString(e));
+    }
+    (void)hipDeviceSynchronize();
+    csx_sai_free(h);
+    h->sai = s;
+    if (h->op_sai & CSX_OP_ADJOINT_SAI) h->have_b1 = false;   // new table, new sensitivity
+    return CSX_OK;
+}
+
+extern "C" csx_status csx_sai_info(const csx_geometry *h, int *nt, int *interp, double *theta_max)
+{
+    if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
+    const SaiState *s = state(h);
+    if (!s) return csx_fail(CSX_EINVAL, "scatter-angle interpolation not configured");
+    if (nt) *nt = s->nt;
+    if (interp) *interp = s->interp;
+    if (theta_max) *theta_max = s->theta_max;
+    return CSX_OK;
+}
+
+csx_status csx_launch_forward_sai(csx_geometry *h, const float *f, float *g, hipStream_t st)
+{
+    SaiState *s = state(h);
+    if (!s) return csx_fail(CSX_EINVAL, "scatter-angle interpolation not configured");
+    const KParams &P = h->P;
+    csx_status r = gemm_nt(f, P.nq, s->S, P.nq, s->W, s->nt, P.nvox, s->nt, P.nq, st);
+    if (r != CSX_OK) return r;
+    const int gw = P.lr ? P.nx / 2 : P.nx;
+    const int ntiles = ((gw + 7) / 8) * ((P.nz + 7) / 8);
+    const int splits = std::max(1, std::min(h->lc.fwd_splits, ntiles));
+    const int tps = (ntiles + splits - 1) / splits;
+    const int nsplit = (ntiles + tps - 1) / tps;
+    if ((size_t)nsplit * P.npix > h->part_cap) return csx_fail(CSX_EINVAL, "forward partials too small");
+    const Lds L = sai_lds(P, 0);
+    dim3 grid((P.n_quad + 7) / 8, nsplit);
+    if (P.lr) {
+        if (s->interp)
+            hipLaunchKernelGGL((k_forward_sai<1, 1>), grid, dim3(512), L.total, st, P, h->t, L, s->W, s->smid, s->nt,
+                               s->inv_dth, h->part, tps);
+        else
+            hipLaunchKernelGGL((k_forward_sai<1, 0>), grid, dim3(512), L.total, st, P, h->t, L, s->W, s->smid, s->nt,
+                               s->inv_dth, h->part, tps);
+    } else {
+        if (s->interp)
+            hipLaunchKernelGGL((k_forward_sai<0, 1>), grid, dim3(512), L.total, st, P, h->t, L, s->W, s->smid, s->nt,
+                               s->inv_dth, h->part, tps);
+        else
+            hipLaunchKernelGGL((k_forward_sai<0, 0>), grid, dim3(512), L.total, st, P, h->t, L, s->W, s->smid, s->nt,
+                               s->inv_dth, h->part, tps);
+    }
+    HIP_TRY(hipGetLastError());
+    return csx_launch_sum_parts(h, nsplit, g, st);
+}
+
+csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, hipStream_t st)
+{
+    SaiState *s = state(h);
+    if (!s) return csx_fail(CSX_EINVAL, "scatter-angle interpolation not configured");
+    const KParams &P = h->P;
+    const Lds L = sai_lds(P, 4 * 2 * s->nt);
+    dim3 grid((P.n_groups + 3) / 4);
+    if (P.lr) {
+        if (s->interp)
+            hipLaunchKernelGGL((k_adjoint_sai<1, 1>), grid, dim3(256), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
+                               s->inv_dth);
+        else
+            hipLaunchKernelGGL((k_adjoint_sai<1, 0>), grid, dim3(256), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
+                               s->inv_dth);
+    } else {
+        if (s->interp)
+            hipLaunchKernelGGL((k_adjoint_sai<0, 1>), grid, dim3(256), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
+                               s->inv_dth);
+        else
+            hipLaunchKernelGGL((k_adjoint_sai<0, 0>), grid, dim3(256), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
+                               s->inv_dth);
+    }
+    HIP_TRY(hipGetLastError());
+    return gemm_nt(s->V, s->nt, s->St, s->nt, b, P.nq, P.nvox, P.nq, s->nt, st);
+}
+
+extern "C" csx_status csx_forward_sai(csx_geometry *h, const float *f, float *g, void *stream)
+{
+    if (!h || !f || !g) return csx_fail(CSX_EINVAL, "NULL argument");
+    return csx_launch_forward_sai(h, f, g, (hipStream_t)stream);
+}
+
+extern "C" csx_status csx_backproject_sai(csx_geometry *h, const float *y, float *b, void *stream)
+{
+    if (!h || !y || !b) return csx_fail(CSX_EINVAL, "NULL argument");
+    return csx_launch_adjoint_sai(h, y, b, (hipStream_t)stream);
+}
+
+extern "C" csx_status csx_set_operator(csx_geometry *h, int ops)
+{
+    if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
+    if (ops & ~(CSX_OP_FORWARD_SAI | CSX_OP_ADJOINT_SAI)) return csx_fail(CSX_EINVAL, "unknown operator bits");
+    if (ops && !state(h)) return csx_fail(CSX_EINVAL, "scatter-angle interpolation not configured");
+    if ((ops ^ h->op_sai) & CSX_OP_ADJOINT_SAI) h->have_b1 = false;   // the sensitivity A^T 1 changes
+    h->op_sai = ops;
+    return CSX_OK;
+}

@@ -18,6 +18,8 @@ from .build import LIB
 CSX_OK, CSX_EINVAL, CSX_EGEOM, CSX_EHIP, CSX_ENOMEM, CSX_ENUMERIC = 0, -1, -2, -3, -4, -5
 TABLE_F32, TABLE_BF16 = 0, 1
 PSI_QUADRATIC, PSI_HUBER = 0, 1
+OP_FORWARD_SAI, OP_ADJOINT_SAI = 1, 2
+SAI_MAX_NODES = 1024
 _NAMES = {CSX_EINVAL: "EINVAL", CSX_EGEOM: "EGEOM", CSX_EHIP: "EHIP", CSX_ENOMEM: "ENOMEM",
           CSX_ENUMERIC: "ENUMERIC"}
 
@@ -62,7 +64,8 @@ EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_g
            "csx_batch_recon", "csx_batch_recon_n", "csx_timing_enable", "csx_timing_read", "csx_last_error",
            "csx_cnn_workspace_bytes", "csx_conv3x3_forward", "csx_conv3x3_backward_data",
            "csx_conv3x3_backward_weights", "csx_warm_loss", "csx_adam_step", "csx_to_half",
-           "csx_warm_input", "csx_warm_output", "csx_warm_target", "csx_warm_start", "csx_recon_warm"]
+           "csx_warm_input", "csx_warm_output", "csx_warm_target", "csx_warm_start", "csx_recon_warm",
+           "csx_sai_config", "csx_sai_info", "csx_forward_sai", "csx_backproject_sai", "csx_set_operator"]
 
 
 class _WarmNet(ctypes.Structure):
@@ -102,6 +105,17 @@ def lib():
         L.csx_recon_os.restype = ctypes.c_int
         L.csx_set_penalty.argtypes = [vp, ctypes.c_int, ctypes.c_double]
         L.csx_set_penalty.restype = ctypes.c_int
+        L.csx_sai_config.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.csx_sai_config.restype = ctypes.c_int
+        L.csx_sai_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_double)]
+        L.csx_sai_info.restype = ctypes.c_int
+        L.csx_forward_sai.argtypes = [vp, vp, vp, vp]
+        L.csx_forward_sai.restype = ctypes.c_int
+        L.csx_backproject_sai.argtypes = [vp, vp, vp, vp]
+        L.csx_backproject_sai.restype = ctypes.c_int
+        L.csx_set_operator.argtypes = [vp, ctypes.c_int]
+        L.csx_set_operator.restype = ctypes.c_int
         L.csx_get_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
         L.csx_get_launch.restype = ctypes.c_int
         L.csx_set_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
@@ -292,6 +306,36 @@ class Geometry:
         if code is None:
             raise ValueError(f"unknown potential {kind!r}")
         _check(lib().csx_set_penalty(self._h, code, float(delta)))
+
+    def sai_config(self, nt: int, interp: str = "linear", theta_max: float = 0.0) -> None:
+        """Scatter-angle interpolation table of nt angles on [0, theta_max]
+        (0: the geometry's largest angle); interp "nearest" or "linear"."""
+        code = {"nearest": 0, "linear": 1}.get(interp)
+        if code is None:
+            raise ValueError(f"unknown interpolation {interp!r}")
+        _check(lib().csx_sai_config(self._h, int(nt), code, float(theta_max)))
+
+    def sai_info(self) -> dict:
+        nt, it, tm = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().csx_sai_info(self._h, ctypes.byref(nt), ctypes.byref(it), ctypes.byref(tm)))
+        return {"nt": nt.value, "interp": ("nearest", "linear")[it.value], "theta_max": tm.value}
+
+    def forward_sai(self, f: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.new_detector() if out is None else out
+        _check(lib().csx_forward_sai(self._h, _dev(f, self.nvox * self.nq, "f"),
+                                     _dev(out, self.npix, "g"), _stream()))
+        return out
+
+    def backproject_sai(self, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.new_image() if out is None else out
+        _check(lib().csx_backproject_sai(self._h, _dev(y, self.npix, "y"),
+                                         _dev(out, self.nvox * self.nq, "b"), _stream()))
+        return out
+
+    def set_operator(self, forward_sai: bool = False, adjoint_sai: bool = False) -> None:
+        """Operators of recon_step / recon / recon_warm: exact, or interpolated in angle."""
+        ops = (OP_FORWARD_SAI if forward_sai else 0) | (OP_ADJOINT_SAI if adjoint_sai else 0)
+        _check(lib().csx_set_operator(self._h, ops))
 
     def recon_os(self, y: torch.Tensor, f: torch.Tensor, n_iter: int, beta: float, rho_z: int = 8,
                  rho_y: int = 16, r: Optional[torch.Tensor] = None, init_uniform: bool = True) -> np.ndarray:
