@@ -11,6 +11,7 @@ nominal voxel*pixel*q evaluations of one forward plus one adjoint
     python bench.py --workload batch64 [--steps K] [--warmup W]
     python bench.py --workload warm [--tto-cases N]
     python bench.py --workload os [--steps K]
+    python bench.py --workload sai [--steps K] [--sai-interp linear|nearest]
 
 Prints one JSON line.  The roofline entry uses the work model of the direct
 evaluation (4 VALU lane-ops per open in-band triple, 60 per open pair, 10 per
@@ -204,6 +205,98 @@ def bench_os(args):
                       "objective": [float(v) for v in J]}))
 
 
+def bench_sai(args):
+    """Scatter-angle interpolation (Sec. III-B) on the 128^2 x 64q slice: a
+    step is one Alg. 5 iteration with both operators interpolated (N_theta =
+    250, the paper's table size; linear nodes by default).  Also reported: the
+    event-timed operators beside the exact ones, the operators' NRMSE against
+    the exact ones (the paper's Table 1 measure: forward on the phantom,
+    adjoint on its noiseless data) over table sizes and both node rules, and
+    the reconstruction after 50 iterations against the exact operators'."""
+    import torch
+
+    from paper_1603_06400_amd import csx, inputs
+
+    w = inputs.workload(WORKLOAD)
+    z = np.load(os.path.join(GOLDEN, f"{WORKLOAD}_counts.npz"))
+    g = w.geom.with_(C=float(z["C"]))
+    torch.cuda.set_device(0)
+    geo = csx.Geometry(g)
+    f_true = torch.tensor(inputs.phantom(w.geom, w.phantom_seed, w.n_rect), dtype=torch.float32, device="cuda")
+    y = torch.tensor(z["y"], dtype=torch.float32, device="cuda")
+
+    def nrmse(a, b):
+        return float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
+
+    g_ex = geo.forward(f_true)
+    b_ex = geo.backproject(g_ex.clone())
+    accuracy = []
+    for interp in ("nearest", "linear"):
+        for nt in (64, 250, 1000, 2000, csx.SAI_MAX_NODES):
+            geo.sai_config(nt, interp)
+            accuracy.append({"nt": nt, "interp": interp,
+                             "forward_nrmse": nrmse(geo.forward_sai(f_true), g_ex),
+                             "adjoint_nrmse": nrmse(geo.backproject_sai(g_ex), b_ex)})
+    nt, interp = 250, args.sai_interp
+    geo.sai_config(nt, interp)
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    gbuf, bbuf = geo.new_detector(), geo.new_image()
+    ops = {"forward_sai_ms": timed(lambda: geo.forward_sai(f_true, gbuf), 20),
+           "adjoint_sai_ms": timed(lambda: geo.backproject_sai(y, bbuf), 20),
+           "forward_exact_ms": timed(lambda: geo.forward(f_true, gbuf), 20),
+           "adjoint_exact_ms": timed(lambda: geo.backproject(y, bbuf), 20)}
+
+    # Alg. 5 steps with both operators interpolated
+    geo.set_operator(forward_sai=True, adjoint_sai=True)
+    f_d = geo.new_image()
+    J = torch.zeros(max(1, args.steps), dtype=torch.float64, device="cuda")
+    geo.recon(y, f_d, 0, w.beta, init_uniform=True)
+    for _ in range(args.warmup):
+        geo.recon_step(y, f_d, w.beta, J=J[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        geo.recon_step(y, f_d, w.beta, J=J[k:k + 1])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / max(1, args.steps)
+    # reconstructions: 50 iterations with interpolated and with exact operators
+    f_sai = geo.new_image()
+    geo.recon(y, f_sai, w.n_iter, w.beta)
+    geo.set_operator()
+    f_ex = geo.new_image()
+    J_ex = geo.recon(y, f_ex, w.n_iter, w.beta)
+    t2 = time.perf_counter()
+    geo.recon(y, f_ex, w.n_iter, w.beta)
+    torch.cuda.synchronize()
+    ms_exact_step = (time.perf_counter() - t2) * 1e3 / w.n_iter
+    nominal = 2.0 * g.nvox * g.npix * g.nq
+    print(json.dumps({
+        "metric": "fwd+adjoint voxel*pixel*energy evals/s at 128^2 x 64q, Alg. 5 with interpolated scatter "
+                  "angles (N_theta = 250; nominal evals counted as if exact)",
+        "value": nominal / (ms * 1e-3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "slice128_sai", "nt": nt, "interp": interp, "theta_max": geo.sai_info()["theta_max"],
+                   "beta": w.beta, "nominal_evals_per_step": nominal},
+        "operators": ops, "ms_per_exact_step": ms_exact_step, "speedup_step": ms_exact_step / ms,
+        "accuracy": accuracy,
+        "recon_nrmse_vs_exact": nrmse(f_sai, f_ex), "n_iter": w.n_iter,
+        "objective_exact_last": float(J_ex[-1])}))
+
+
 def time_to_objective(n_cases: int, batched: bool = False, log=None) -> dict:
     """Time for the plain solver, for the judged learned warm start (network
     and judge included) and for ordered subsets (Alg. 6, 64 subsets) to reach
@@ -233,10 +326,13 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
                          "reference kernel for scaling HBM byte counters")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64", "warm", "os"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64", "warm", "os", "sai"],
                     help="slice128 (default): the single 128^2 x 64q slice; batch64: the batched form; "
                          "warm: time to the plain objective with the learned warm start; os: sweeps of "
-                         "ordered subsets (Alg. 6, 64 subsets) on the slice")
+                         "ordered subsets (Alg. 6, 64 subsets) on the slice; sai: Alg. 5 with "
+                         "scatter-angle interpolation")
+    ap.add_argument("--sai-interp", default="linear", choices=["linear", "nearest"],
+                    help="sai: node rule of the timed table")
     ap.add_argument("--tto-cases", type=int, default=4,
                     help="held-out phantoms for the time-to-objective entry (0: skip; warm workload: 200)")
     ap.add_argument("--tune-cache", default=None, metavar="PATH",
@@ -262,6 +358,9 @@ def main():
         return
     if args.workload == "os":
         bench_os(args)
+        return
+    if args.workload == "sai":
+        bench_sai(args)
         return
     if args.workload == "warm":
         import torch

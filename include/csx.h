@@ -184,7 +184,7 @@ csx_status csx_recon_os(csx_geometry *h, const float *y, const float *r, float *
  * Builds the table on the host in float64 and keeps it, with two
  * [nvox][nt] float32 work arrays, on the handle; a later call replaces it.
  * Synchronous. */
-#define CSX_SAI_MAX_NODES 1024
+#define CSX_SAI_MAX_NODES 2048
 csx_status csx_sai_config(csx_geometry *h, int nt, int interp, double theta_max);
 
 /* The configuration in force (CSX_EINVAL before csx_sai_config); any output
@@ -199,7 +199,11 @@ csx_status csx_forward_sai(csx_geometry *h, const float *f, float *g, void *stre
 
 /* The exact transpose of csx_forward_sai: V_jt = sum_i A_ij T_ij y_i w_t(theta_ij)
  * (w_t: the pair's interpolation weight of node t), then b = V s
- * ([nvox][nt] x [nt][nq]).  Buffers as for csx_backproject.  Asynchronous. */
+ * ([nvox][nt] x [nt][nq]).  V is accumulated in 64-bit fixed point scaled to
+ * the launch's bound max(A) sum_i |y_i| (results do not depend on the order of
+ * the adds; bins below ~2^-40 of the bound lose relative precision).  A
+ * non-finite y gives NaN everywhere.  Buffers as for csx_backproject.
+ * Asynchronous. */
 csx_status csx_backproject_sai(csx_geometry *h, const float *y, float *b, void *stream);
 
 /* Operators of the solver: bit CSX_OP_FORWARD_SAI makes csx_recon_step,

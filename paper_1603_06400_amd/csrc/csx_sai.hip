@@ -37,12 +37,14 @@ struct SaiState {
     float *W = nullptr;            // [nvox][nt]
     float *V = nullptr;            // [nvox][nt]
     double *smid = nullptr;        // [nt - 1] sin(half the midpoint angle) / hc
+    double *sc = nullptr;          // [2] fixed-point scale of the adjoint's histograms and its inverse
+    double a_max = 0.0;            // largest pair weight A of the geometry
 };
 
 void release(SaiState *s)
 {
     if (!s) return;
-    void *ptrs[] = {s->S, s->St, s->W, s->V, s->smid};
+    void *ptrs[] = {s->S, s->St, s->W, s->V, s->smid, s->sc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete s;
@@ -255,21 +257,32 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
 
 // Adjoint pairs: one wave per voxel group (voxel j, and its mirror with LR),
 // lanes = pixel classes in 8 x 8 tiles; the weighted ratios go to the wave's
-// two angle histograms in LDS, which are then written to V.
+// two angle histograms in LDS, which are then written to V.  The histograms
+// hold 64-bit fixed point: a contribution v enters as trunc(v 2^s) with the
+// launch's scale 2^s (sc[0]; sc[1] = 2^-s) chosen so that every bin's total
+// stays below 2^61 in magnitude.  Integer adds are exact and associative, so
+// the totals do not depend on the order of the adds (LDS integer atomics also
+// run at full rate, unlike float ones), and the truncation error, below
+// 2^-61 of the bound per add, is far under float32 rounding of the result.
+__device__ __forceinline__ unsigned long long to_fixed(float v, double sc)
+{
+    return (unsigned long long)__double2ll_rz((double)v * sc);
+}
+
 template <int LR, int INTERP>
 __global__ void __launch_bounds__(256) k_adjoint_sai(KParams P, DevTables T, Lds L, const float *__restrict__ rho,
                                                      float *__restrict__ V, const double *__restrict__ smid, int nt,
-                                                     float inv_dth)
+                                                     float inv_dth, const double *__restrict__ sc)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     uint32_t *s_bits = (uint32_t *)(lds + L.mask);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    float *h0 = (float *)(lds + L.tile) + (size_t)wv * 2 * nt;
-    float *h1 = h0 + nt;
+    unsigned long long *h0 = (unsigned long long *)(lds + L.tile) + (size_t)wv * 2 * nt;
+    unsigned long long *h1 = h0 + nt;
     stage_mask(P, T, s_bits);
-    for (int k = lane; k < 2 * nt; k += 64) h0[k] = 0.0f;
+    for (int k = lane; k < 2 * nt; k += 64) h0[k] = 0ull;
     __syncthreads();
-    const int g = blockIdx.x * 4 + wv;
+    const int g = blockIdx.x * (blockDim.x >> 6) + wv;
     if (g >= P.n_groups) return;
     int j, j2;
     if (LR) {
@@ -281,6 +294,7 @@ __global__ void __launch_bounds__(256) k_adjoint_sai(KParams P, DevTables T, Lds
         j = g;
         j2 = g;
     }
+    const double scale = sc[0], inv_scale = sc[1];
     const VoxD vd = T.vd[j];
     const float2 vf = T.vf[j], vm = T.vm[j];
     const int half_y = P.ndy / 2;
@@ -310,24 +324,87 @@ __global__ void __launch_bounds__(256) k_adjoint_sai(KParams P, DevTables T, Lds
         float u0, u1;
         nodes<INTERP>(angle_of(P, k) * inv_dth, k, smid, nt, n0, u0, u1);
         const float c0 = A * w0, c1 = A * w1;
-        atomicAdd(&h0[n0], c0 * u0);
-        if (INTERP) atomicAdd(&h0[n0 + 1], c0 * u1);
+        atomicAdd(&h0[n0], to_fixed(c0 * u0, scale));
+        if (INTERP) atomicAdd(&h0[n0 + 1], to_fixed(c0 * u1, scale));
         if (LR) {
-            atomicAdd(&h1[n0], c1 * u0);
-            if (INTERP) atomicAdd(&h1[n0 + 1], c1 * u1);
+            atomicAdd(&h1[n0], to_fixed(c1 * u0, scale));
+            if (INTERP) atomicAdd(&h1[n0 + 1], to_fixed(c1 * u1, scale));
         }
     }
+    // scale 0 flags a non-finite bound (rho holds inf or NaN): NaN out
+    const float bad = __builtin_nanf("");
     float *vj = V + (size_t)j * nt;
-    for (int k = lane; k < nt; k += 64) vj[k] = h0[k];
+    for (int k = lane; k < nt; k += 64)
+        vj[k] = scale != 0.0 ? (float)((double)(long long)h0[k] * inv_scale) : bad;
     if (LR) {
         float *v2 = V + (size_t)j2 * nt;
-        for (int k = lane; k < nt; k += 64) v2[k] = h1[k];
+        for (int k = lane; k < nt; k += 64)
+            v2[k] = scale != 0.0 ? (float)((double)(long long)h1[k] * inv_scale) : bad;
     }
+}
+
+// Scale of the adjoint's fixed-point histograms: with B = a_max sum_i |rho_i|
+// (a_max: the largest pair weight A of the geometry) every contribution and
+// every bin total is at most B in magnitude (a pixel's weights over nodes sum
+// to 1); 2^s with 2^(s-61) B < 1.  One block, fixed summation order.
+__global__ void __launch_bounds__(256) k_sai_scale(const float *__restrict__ rho, int n, double a_max,
+                                                   double *__restrict__ sc)
+{
+    __shared__ double part[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += fabs((double)rho[i]);
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double B = a_max * part[0];
+        double s0 = 1.0, s1 = 1.0;
+        if (!(B < INFINITY)) {
+            s0 = 0.0;                        // inf or NaN
+        } else if (B > 0.0) {
+            int e;
+            (void)frexp(B, &e);              // B < 2^e
+            s0 = ldexp(1.0, 61 - e);
+            s1 = ldexp(1.0, e - 61);
+        }
+        sc[0] = s0;
+        sc[1] = s1;
+    }
+}
+
+// Largest pair weight A over all voxel-pixel pairs (the mask ignored): one
+// wave per voxel group, max over its pixel classes (the mirrors share them).
+template <int LR>
+__global__ void __launch_bounds__(256) k_sai_amax(KParams P, DevTables T, float *__restrict__ amax)
+{
+    const int lane = threadIdx.x & 63;
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= P.n_groups) return;
+    const int j = LR ? (g / (P.nx / 2)) * P.nx + g % (P.nx / 2) : g;
+    const VoxD vd = T.vd[j];
+    const float2 vf = T.vf[j];
+    const int half_y = P.ndy / 2;
+    float m = 0.0f;
+    for (int c = lane; c < P.ndx * half_y; c += 64) {
+        const int a = c % P.ndx, bu = half_y + c / P.ndx;
+        const double xp = (double)((float)(2 * a - P.ndx + 1) * (0.5f * P.pitch));
+        const double yp = (double)((float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch));
+        double k;
+        float A;
+        pair_factors(P, vd, vf, xp, yp, k, A);
+        m = fmaxf(m, A);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if (lane == 0) amax[g] = m;
 }
 
 int al16(int v) { return (v + 15) & ~15; }
 
-Lds sai_lds(const KParams &P, int hist_floats)
+Lds sai_lds(const KParams &P, int hist_bytes)
 {
     Lds L;
     int off = 0;
@@ -335,7 +412,7 @@ Lds sai_lds(const KParams &P, int hist_floats)
     L.mask = off;
     off += al16(P.mask_ny * 4);
     L.tile = off;
-    off += hist_floats * 4;
+    off += hist_bytes;
     L.total = off;
     return L;
 }
@@ -386,7 +463,7 @@ void csx_sai_free(csx_geometry *h)
 extern "C" csx_status csx_sai_config(csx_geometry *h, int nt, int interp, double theta_max)
 {
     if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
-    if (nt < 2 || nt > CSX_SAI_MAX_NODES) return csx_fail(CSX_EINVAL, "nt must be in [2, 1024]");
+    if (nt < 2 || nt > CSX_SAI_MAX_NODES) return csx_fail(CSX_EINVAL, "nt must be in [2, CSX_SAI_MAX_NODES]");
     if (interp != 0 && interp != 1) return csx_fail(CSX_EINVAL, "interp must be 0 (nearest) or 1 (linear)");
     if (!(std::isfinite(theta_max) && theta_max >= 0.0) || theta_max > M_PI)
         return csx_fail(CSX_EINVAL, "theta_max must be in [0, pi] (0: the largest pair angle)");
@@ -423,10 +500,27 @@ extern "C" csx_status csx_sai_config(csx_geometry *h, int nt, int interp, double
     if (e == hipSuccess) e = hipMalloc((void **)&s->St, sizeof(float) * St.size());
     if (e == hipSuccess) e = hipMalloc((void **)&s->W, sizeof(float) * (size_t)nvox * nt);
     if (e == hipSuccess) e = hipMalloc((void **)&s->V, sizeof(float) * (size_t)nvox * nt);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->sc, sizeof(double) * 2);
     if (e == hipSuccess) e = hipMalloc((void **)&s->smid, sizeof(double) * smid.size());
     if (e == hipSuccess) e = hipMemcpy(s->smid, smid.data(), sizeof(double) * smid.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->S, S.data(), sizeof(float) * S.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->St, St.data(), sizeof(float) * St.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {   // the largest pair weight, for the adjoint's fixed-point scale
+        const KParams &P = h->P;
+        float *am = nullptr;
+        e = hipMalloc((void **)&am, sizeof(float) * P.n_groups);
+        if (e == hipSuccess) {
+            if (P.lr)
+                hipLaunchKernelGGL(k_sai_amax<1>, dim3((P.n_groups + 3) / 4), dim3(256), 0, nullptr, P, h->t, am);
+            else
+                hipLaunchKernelGGL(k_sai_amax<0>, dim3((P.n_groups + 3) / 4), dim3(256), 0, nullptr, P, h->t, am);
+            e = hipGetLastError();
+            std::vector<float> hm(P.n_groups);
+            if (e == hipSuccess) e = hipMemcpy(hm.data(), am, sizeof(float) * P.n_groups, hipMemcpyDeviceToHost);
+            for (float v : hm) s->a_max = std::max(s->a_max, (double)v);
+            (void)hipFree(am);
+        }
+    }
     if (e != hipSuccess) {
         release(s);
         return csx_fail(CSX_EHIP, std::string("scatter-angle tables: ") + hipGetErrorString(e));
@@ -488,22 +582,25 @@ csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, h
     SaiState *s = state(h);
     if (!s) return csx_fail(CSX_EINVAL, "scatter-angle interpolation not configured");
     const KParams &P = h->P;
-    const Lds L = sai_lds(P, 4 * 2 * s->nt);
-    dim3 grid((P.n_groups + 3) / 4);
+    // per-wave histograms of 2 nt 64-bit words, at most 32 KiB per block
+    const int wpb = std::max(1, std::min(4, 2048 / s->nt));
+    const Lds L = sai_lds(P, wpb * 2 * s->nt * 8);
+    dim3 grid((P.n_groups + wpb - 1) / wpb);
+    hipLaunchKernelGGL(k_sai_scale, dim3(1), dim3(256), 0, st, rho, P.npix, s->a_max, s->sc);
     if (P.lr) {
         if (s->interp)
-            hipLaunchKernelGGL((k_adjoint_sai<1, 1>), grid, dim3(256), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
-                               s->inv_dth);
+            hipLaunchKernelGGL((k_adjoint_sai<1, 1>), grid, dim3(64 * wpb), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
+                               s->inv_dth, s->sc);
         else
-            hipLaunchKernelGGL((k_adjoint_sai<1, 0>), grid, dim3(256), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
-                               s->inv_dth);
+            hipLaunchKernelGGL((k_adjoint_sai<1, 0>), grid, dim3(64 * wpb), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
+                               s->inv_dth, s->sc);
     } else {
         if (s->interp)
-            hipLaunchKernelGGL((k_adjoint_sai<0, 1>), grid, dim3(256), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
-                               s->inv_dth);
+            hipLaunchKernelGGL((k_adjoint_sai<0, 1>), grid, dim3(64 * wpb), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
+                               s->inv_dth, s->sc);
         else
-            hipLaunchKernelGGL((k_adjoint_sai<0, 0>), grid, dim3(256), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
-                               s->inv_dth);
+            hipLaunchKernelGGL((k_adjoint_sai<0, 0>), grid, dim3(64 * wpb), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
+                               s->inv_dth, s->sc);
     }
     HIP_TRY(hipGetLastError());
     return gemm_nt(s->V, s->nt, s->St, s->nt, b, P.nq, P.nvox, P.nq, s->nt, st);

@@ -19,7 +19,7 @@ CSX_OK, CSX_EINVAL, CSX_EGEOM, CSX_EHIP, CSX_ENOMEM, CSX_ENUMERIC = 0, -1, -2, -
 TABLE_F32, TABLE_BF16 = 0, 1
 PSI_QUADRATIC, PSI_HUBER = 0, 1
 OP_FORWARD_SAI, OP_ADJOINT_SAI = 1, 2
-SAI_MAX_NODES = 1024
+SAI_MAX_NODES = 2048
 _NAMES = {CSX_EINVAL: "EINVAL", CSX_EGEOM: "EGEOM", CSX_EHIP: "EHIP", CSX_ENOMEM: "ENOMEM",
           CSX_ENUMERIC: "ENUMERIC"}
 

@@ -58,11 +58,11 @@ def test_sai_operators_match_oracle(oracle_mod, case, interp):
     assert_parity(host(geo.backproject_sai(dev(y))), o.adjoint_sai(y, nt, tm, interp), what="adjoint_sai")
 
 
-@pytest.mark.parametrize("nt", [2, 64, 250, 1024])
+@pytest.mark.parametrize("nt", [2, 64, 250, 1024, 2000, 2048])
 def test_sai_table_sizes_slice32(oracle_mod, nt):
     """Linear interpolation at the extremes of the table size (2 nodes: one
-    interval; 1024: the largest table) and the paper's 250, with the library's
-    own angle range."""
+    interval; 2048: the largest table, one wave per adjoint block), the
+    paper's 250 and 2000, with the library's own angle range."""
     w, g, f, y = workload_data("slice32")
     o = oracle_mod.Oracle(g)
     geo = csx.Geometry(g)
@@ -104,6 +104,29 @@ def test_sai_slice128_full_parity(oracle_mod):
     ge, be = host(geo.forward(dev(f))), host(geo.backproject(dev(y)))
     print(f"SAI nt=250 linear vs exact: forward {rel_l2(gs, ge):.3e} adjoint {rel_l2(bs, be):.3e}")
     assert rel_l2(gs, ge) < 2e-2 and rel_l2(bs, be) < 2e-2
+
+
+def test_sai_adjoint_scale_range(oracle_mod):
+    """The adjoint's fixed-point histograms follow the data's magnitude: y
+    scaled by 1e-20 and 1e20 gives b scaled alike, to the parity bar (near
+    1e30 the float32 histogram V itself would overflow); a NaN in y gives NaN
+    everywhere."""
+    w, g, f, y = workload_data("slice32")
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    geo.sai_config(250, "linear")
+    tm = geo.sai_info()["theta_max"]
+    ref = o.adjoint_sai(y, 250, tm, 1)
+    for k in (1e-20, 1e20):
+        assert_parity(host(geo.backproject_sai(dev(y * k))) / k, ref, what=f"adjoint_sai y*{k:g}")
+    # one large pixel among small ones: the small ones' share survives
+    y2 = y.copy()
+    y2.flat[77] = 1e6 * y.max()
+    assert_parity(host(geo.backproject_sai(dev(y2))), o.adjoint_sai(y2, 250, tm, 1), what="adjoint_sai spike")
+    yn = y.copy()
+    yn.flat[5] = np.nan
+    assert np.all(np.isnan(host(geo.backproject_sai(dev(yn)))))
+    assert_parity(host(geo.backproject_sai(dev(y))), ref, what="adjoint_sai after NaN")
 
 
 @pytest.mark.parametrize("interp", ["linear", "nearest"])
