@@ -34,7 +34,7 @@ struct SaiState {
     float inv_dth = 0.0f;          // (nt - 1) / theta_max
     float *S = nullptr;            // [nt][nq] spectral part
     float *St = nullptr;           // [nq][nt]
-    float *W = nullptr;            // [nvox][nt]
+    float *W = nullptr;            // W = f s^T in the tiled layout of WLayout
     float *V = nullptr;            // [nvox][nt]
     double *smid = nullptr;        // [nt - 1] sin(half the midpoint angle) / hc
     double *sc = nullptr;          // [2] fixed-point scale of the adjoint's histograms and its inverse
@@ -50,11 +50,35 @@ void release(SaiState *s)
     delete s;
 }
 
+// Placement of W = f s^T for the forward: tiled by the forward's 8 x 8 voxel
+// tiles, node-major inside a tile, W[set][tile][node][lane] with lane =
+// 8 (iz mod 8) + (ix mod 8), so that the 64 lanes of one forward load read
+// only the few node rows their tile spans.  With the x -> -x mirror the right
+// half (set 1) is stored at mirrored coordinates, so a voxel and its mirror
+// share tile and lane.
+struct WLayout {
+    int tiled = 0;       // 0: row-major C with ldc
+    int nx = 0, gw = 0, ntx = 0, ntiles = 0, lr = 0, nt = 0;
+};
+
+__device__ __forceinline__ size_t w_index(const WLayout &L, int j, int t)
+{
+    const int iz = j / L.nx;
+    int ix = j - iz * L.nx, set = 0;
+    if (L.lr && ix >= L.gw) {
+        set = 1;
+        ix = L.nx - 1 - ix;
+    }
+    const int tile = (iz >> 3) * L.ntx + (ix >> 3);
+    return ((((size_t)set * L.ntiles + tile) * L.nt + t) << 6) + (((iz & 7) << 3) | (ix & 7));
+}
+
 // C[M][N] = sum_k A[m][k] B[n][k]: 64 x 64 tiles, 4 waves of 16 rows, K in
 // steps of 32 staged in LDS.  Lane l of v_mfma_f32_16x16x4_f32 holds A[l%16][l/16]
 // and B[l/16][l%16] of its 16 x 4 / 4 x 16 operands; D[4 (l/16) + v][l%16].
 __global__ void __launch_bounds__(256) k_gemm_nt(const float *__restrict__ A, int lda, const float *__restrict__ B,
-                                                 int ldb, float *__restrict__ C, int ldc, int M, int N, int K)
+                                                 int ldb, float *__restrict__ C, int ldc, int M, int N, int K,
+                                                 WLayout WL)
 {
     __shared__ float sA[64][33];
     __shared__ float sB[64][33];
@@ -89,7 +113,7 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const float *__restrict__ A, in
         for (int v = 0; v < 4; ++v) {
             const int row = m0 + wave * 16 + 4 * (lane >> 4) + v;
             const int col = n0 + t * 16 + (lane & 15);
-            if (row < M && col < N) C[(size_t)row * ldc + col] = acc[t][v];
+            if (row < M && col < N) C[WL.tiled ? w_index(WL, row, col) : (size_t)row * ldc + col] = acc[t][v];
         }
 }
 
@@ -129,10 +153,11 @@ __device__ __forceinline__ float angle_of(const KParams &P, double kappa)
     return 2.0f * asinf(sh);
 }
 
+// W at the nodes t0 (and t0 + 1) of one lane's column of a tiled W block
 template <int INTERP>
-__device__ __forceinline__ float interp_w(const float *__restrict__ Wrow, int t0, float w0, float w1)
+__device__ __forceinline__ float interp_w(const float *__restrict__ Wcol, int t0, float w0, float w1)
 {
-    return INTERP == 0 ? Wrow[t0] : fmaf(w0, Wrow[t0], w1 * Wrow[t0 + 1]);
+    return INTERP == 0 ? Wcol[t0 << 6] : fmaf(w0, Wcol[t0 << 6], w1 * Wcol[(t0 + 1) << 6]);
 }
 
 // Forward pairs: one wave per pixel quad (as the exact forward), lanes = voxel
@@ -172,11 +197,10 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
         const int ix = (t % ntx) * 8 + (lane & 7), iz = (t / ntx) * 8 + (lane >> 3);
         if (ix >= gw || iz >= P.nz) continue;
         const int j = iz * P.nx + ix;
-        const int jm = LR ? iz * P.nx + (P.nx - 1 - ix) : j;
         const VoxD vd = T.vd[j];
         const float2 vf = T.vf[j], vm = T.vm[j];
-        const float *Wj = W + (size_t)j * nt;
-        const float *Wm = W + (size_t)jm * nt;
+        const float *Wj = W + (((size_t)t * nt) << 6) + lane;
+        const float *Wm = LR ? W + (((size_t)(ntiles + t) * nt) << 6) + lane : Wj;
         {
             const Cells c = mask_cells(P, vm, xpa, yp);
             float tau = 0.0f, tad = 0.0f, tbu = 0.0f, tbd = 0.0f;
@@ -418,10 +442,10 @@ Lds sai_lds(const KParams &P, int hist_bytes)
 }
 
 csx_status gemm_nt(const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M, int N, int K,
-                   hipStream_t s)
+                   hipStream_t s, WLayout WL = WLayout{})
 {
     dim3 grid((M + 63) / 64, (N + 63) / 64);
-    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, WL);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
@@ -448,6 +472,19 @@ double max_angle(const csx_geometry *h)
                 }
         }
     return best;
+}
+
+WLayout w_layout(const KParams &P, int nt)
+{
+    WLayout L;
+    L.tiled = 1;
+    L.nx = P.nx;
+    L.lr = P.lr;
+    L.gw = P.lr ? P.nx / 2 : P.nx;
+    L.ntx = (L.gw + 7) / 8;
+    L.ntiles = L.ntx * ((P.nz + 7) / 8);
+    L.nt = nt;
+    return L;
 }
 
 SaiState *state(const csx_geometry *h) { return static_cast<SaiState *>(h->sai); }
@@ -498,7 +535,8 @@ extern "C" csx_status csx_sai_config(csx_geometry *h, int nt, int interp, double
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc((void **)&s->S, sizeof(float) * S.size());
     if (e == hipSuccess) e = hipMalloc((void **)&s->St, sizeof(float) * St.size());
-    if (e == hipSuccess) e = hipMalloc((void **)&s->W, sizeof(float) * (size_t)nvox * nt);
+    const WLayout WL = w_layout(h->P, nt);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->W, sizeof(float) * ((size_t)(WL.lr ? 2 : 1) * WL.ntiles * nt << 6));
     if (e == hipSuccess) e = hipMalloc((void **)&s->V, sizeof(float) * (size_t)nvox * nt);
     if (e == hipSuccess) e = hipMalloc((void **)&s->sc, sizeof(double) * 2);
     if (e == hipSuccess) e = hipMalloc((void **)&s->smid, sizeof(double) * smid.size());
@@ -548,7 +586,7 @@ csx_status csx_launch_forward_sai(csx_geometry *h, const float *f, float *g, hip
     SaiState *s = state(h);
     if (!s) return csx_fail(CSX_EINVAL, "scatter-angle interpolation not configured");
     const KParams &P = h->P;
-    csx_status r = gemm_nt(f, P.nq, s->S, P.nq, s->W, s->nt, P.nvox, s->nt, P.nq, st);
+    csx_status r = gemm_nt(f, P.nq, s->S, P.nq, s->W, s->nt, P.nvox, s->nt, P.nq, st, w_layout(P, s->nt));
     if (r != CSX_OK) return r;
     const int gw = P.lr ? P.nx / 2 : P.nx;
     const int ntiles = ((gw + 7) / 8) * ((P.nz + 7) / 8);
