@@ -36,6 +36,7 @@ struct SaiState {
     float *St = nullptr;           // [nq][nt]
     float *W = nullptr;            // W = f s^T in the tiled layout of WLayout
     float *V = nullptr;            // [nvox][nt]
+    float *bpart = nullptr;        // K-split partials of b = V s [k_splits][nvox][nq]
     double *smid = nullptr;        // [nt - 1] sin(half the midpoint angle) / hc
     double *sc = nullptr;          // [2] fixed-point scale of the adjoint's histograms and its inverse
     double a_max = 0.0;            // largest pair weight A of the geometry
@@ -44,7 +45,7 @@ struct SaiState {
 void release(SaiState *s)
 {
     if (!s) return;
-    void *ptrs[] = {s->S, s->St, s->W, s->V, s->smid, s->sc};
+    void *ptrs[] = {s->S, s->St, s->W, s->V, s->bpart, s->smid, s->sc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete s;
@@ -78,22 +79,26 @@ __device__ __forceinline__ size_t w_index(const WLayout &L, int j, int t)
 // and B[l/16][l%16] of its 16 x 4 / 4 x 16 operands; D[4 (l/16) + v][l%16].
 __global__ void __launch_bounds__(256) k_gemm_nt(const float *__restrict__ A, int lda, const float *__restrict__ B,
                                                  int ldb, float *__restrict__ C, int ldc, int M, int N, int K,
-                                                 WLayout WL)
+                                                 int kspan, WLayout WL)
 {
     __shared__ float sA[64][33];
     __shared__ float sB[64][33];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    // split K: block z takes [kb, ke) and writes its partial product to the
+    // z-th [M][ldc] slice of C (row-major only)
+    const int kb = blockIdx.z * kspan, ke = min(K, kb + kspan);
+    C += (size_t)blockIdx.z * M * ldc;
     f4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int k0 = kb; k0 < ke; k0 += 32) {
         for (int e = tid; e < 64 * 32; e += 256) {
             const int r = e >> 5, c = e & 31;
             const int gk = k0 + c;
             const int gm = m0 + r, gn = n0 + r;
-            sA[r][c] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.f;
-            sB[r][c] = (gn < N && gk < K) ? B[(size_t)gn * ldb + gk] : 0.f;
+            sA[r][c] = (gm < M && gk < ke) ? A[(size_t)gm * lda + gk] : 0.f;
+            sB[r][c] = (gn < N && gk < ke) ? B[(size_t)gn * ldb + gk] : 0.f;
         }
         __syncthreads();
 #pragma unroll
@@ -367,24 +372,35 @@ __global__ void __launch_bounds__(256) k_adjoint_sai(KParams P, DevTables T, Lds
     }
 }
 
+// out = sum over z of part[z][i], in increasing z
+__global__ void __launch_bounds__(256) k_sum_slices(const float *__restrict__ part, int nz, int n,
+                                                    float *__restrict__ out)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float v = part[i];
+    for (int z = 1; z < nz; ++z) v += part[(size_t)z * n + i];
+    out[i] = v;
+}
+
 // Scale of the adjoint's fixed-point histograms: with B = a_max sum_i |rho_i|
 // (a_max: the largest pair weight A of the geometry) every contribution and
 // every bin total is at most B in magnitude (a pixel's weights over nodes sum
 // to 1); 2^s with 2^(s-61) B < 1.  One block, fixed summation order.
-__global__ void __launch_bounds__(256) k_sai_scale(const float *__restrict__ rho, int n, double a_max,
-                                                   double *__restrict__ sc)
+__global__ void __launch_bounds__(1024) k_sai_scale(const float *__restrict__ rho, int n, double a_max,
+                                                    double *__restrict__ sc)
 {
-    __shared__ double part[256];
+    __shared__ double part[16];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) acc += fabs((double)rho[i]);
-    part[threadIdx.x] = acc;
+    for (int i = threadIdx.x; i < n; i += 1024) acc += fabs((double)rho[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        const double B = a_max * part[0];
+        double tot = 0.0;
+        for (int w = 0; w < 16; ++w) tot += part[w];
+        const double B = a_max * tot;
         double s0 = 1.0, s1 = 1.0;
         if (!(B < INFINITY)) {
             s0 = 0.0;                        // inf or NaN
@@ -441,11 +457,24 @@ Lds sai_lds(const KParams &P, int hist_bytes)
     return L;
 }
 
-csx_status gemm_nt(const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M, int N, int K,
-                   hipStream_t s, WLayout WL = WLayout{})
+// The K-split count of a product: enough blocks to fill the chip when M x N
+// alone gives few (K chunks of 32 otherwise run one after another in a block).
+int k_splits(int M, int N, int K)
 {
-    dim3 grid((M + 63) / 64, (N + 63) / 64);
-    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, WL);
+    const int blocks = ((M + 63) / 64) * ((N + 63) / 64);
+    int z = 1;
+    while (z < 8 && blocks * z < 1024 && K / (2 * z) >= 32) z *= 2;
+    return z;
+}
+
+// C = A B^T; with ksplit > 1, C receives ksplit partial products (row-major,
+// ldc = N) and the caller sums them.
+csx_status gemm_nt(const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M, int N, int K,
+                   hipStream_t s, WLayout WL = WLayout{}, int ksplit = 1)
+{
+    const int kspan = ((K + ksplit - 1) / ksplit + 31) / 32 * 32;
+    dim3 grid((M + 63) / 64, (N + 63) / 64, (K + kspan - 1) / kspan);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, kspan, WL);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
@@ -539,6 +568,8 @@ extern "C" csx_status csx_sai_config(csx_geometry *h, int nt, int interp, double
     if (e == hipSuccess) e = hipMalloc((void **)&s->W, sizeof(float) * ((size_t)(WL.lr ? 2 : 1) * WL.ntiles * nt << 6));
     if (e == hipSuccess) e = hipMalloc((void **)&s->V, sizeof(float) * (size_t)nvox * nt);
     if (e == hipSuccess) e = hipMalloc((void **)&s->sc, sizeof(double) * 2);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&s->bpart, sizeof(float) * (size_t)k_splits(nvox, nq, nt) * nvox * nq);
     if (e == hipSuccess) e = hipMalloc((void **)&s->smid, sizeof(double) * smid.size());
     if (e == hipSuccess) e = hipMemcpy(s->smid, smid.data(), sizeof(double) * smid.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->S, S.data(), sizeof(float) * S.size(), hipMemcpyHostToDevice);
@@ -624,7 +655,7 @@ csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, h
     const int wpb = std::max(1, std::min(4, 2048 / s->nt));
     const Lds L = sai_lds(P, wpb * 2 * s->nt * 8);
     dim3 grid((P.n_groups + wpb - 1) / wpb);
-    hipLaunchKernelGGL(k_sai_scale, dim3(1), dim3(256), 0, st, rho, P.npix, s->a_max, s->sc);
+    hipLaunchKernelGGL(k_sai_scale, dim3(1), dim3(1024), 0, st, rho, P.npix, s->a_max, s->sc);
     if (P.lr) {
         if (s->interp)
             hipLaunchKernelGGL((k_adjoint_sai<1, 1>), grid, dim3(64 * wpb), L.total, st, P, h->t, L, rho, s->V, s->smid, s->nt,
@@ -641,7 +672,16 @@ csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, h
                                s->inv_dth, s->sc);
     }
     HIP_TRY(hipGetLastError());
-    return gemm_nt(s->V, s->nt, s->St, s->nt, b, P.nq, P.nvox, P.nq, s->nt, st);
+    const int z = k_splits(P.nvox, P.nq, s->nt);
+    if (z == 1) return gemm_nt(s->V, s->nt, s->St, s->nt, b, P.nq, P.nvox, P.nq, s->nt, st);
+    const int kspan = ((s->nt + z - 1) / z + 31) / 32 * 32;
+    const int nz = (s->nt + kspan - 1) / kspan;       // partial products written
+    csx_status r = gemm_nt(s->V, s->nt, s->St, s->nt, s->bpart, P.nq, P.nvox, P.nq, s->nt, st, WLayout{}, z);
+    if (r != CSX_OK) return r;
+    const int n = P.nvox * P.nq;
+    hipLaunchKernelGGL(k_sum_slices, dim3((n + 255) / 256), dim3(256), 0, st, s->bpart, nz, n, b);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
 }
 
 extern "C" csx_status csx_forward_sai(csx_geometry *h, const float *f, float *g, void *stream)
