@@ -21,6 +21,9 @@ Layers, each following the paper (Odinaka et al., arXiv:1603.06400):
 * ``forward_sai`` / ``adjoint_sai`` -- scatter-angle interpolation (Sec.
   III-B, the precompute and interpolate lines of Alg. 2 / Alg. 4): W(r,
   theta) of eq. q_integral on a uniform angle table, interpolated per pair.
+* ``forward_energy`` / ``adjoint_energy`` -- the energy-sensitive detector of
+  App. A (eq. energy_sensitive): each triple's contribution is kept in the
+  spectrum bin of its Bragg energy kappa q instead of being summed over E.
 
 Parity status: every function here is pinned by tests in tests/test_oracle_*.py
 (closed forms, brute force, invariants); the absolute normalisation C has no
@@ -83,6 +86,8 @@ def _load():
         lib.orc_adjoint_sai.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
         lib.orc_max_angle.argtypes = [gp]
         lib.orc_max_angle.restype = ctypes.c_double
+        lib.orc_forward_energy.argtypes = [gp, dp, dp]
+        lib.orc_adjoint_energy.argtypes = [gp, dp, dp]
         _lib = lib
     return _lib
 
@@ -202,6 +207,24 @@ class Oracle:
         out = np.zeros((g.nz, g.nx, g.nq))
         self._lib.orc_adjoint_sai(ctypes.byref(self._s), int(nt), int(interp), float(theta_max), _dptr(y),
                                   _dptr(out))
+        return out
+
+    def forward_energy(self, f: np.ndarray) -> np.ndarray:
+        """Energy-resolved detector (App. A eq. energy_sensitive): g_E[k][i]
+        collects the triples whose Bragg energy kappa q falls in spectrum bin k;
+        shape (ne, ndy, ndx)."""
+        g = self.geom
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(g.nz, g.nx, g.nq)
+        out = np.zeros((g.ne, g.ndy, g.ndx))
+        self._lib.orc_forward_energy(ctypes.byref(self._s), _dptr(f), _dptr(out))
+        return out
+
+    def adjoint_energy(self, y: np.ndarray) -> np.ndarray:
+        """The transpose of forward_energy; y of shape (ne, ndy, ndx)."""
+        g = self.geom
+        y = np.ascontiguousarray(y, dtype=np.float64).reshape(g.ne, g.ndy, g.ndx)
+        out = np.zeros((g.nz, g.nx, g.nq))
+        self._lib.orc_adjoint_energy(ctypes.byref(self._s), _dptr(y), _dptr(out))
         return out
 
     def census(self) -> dict:

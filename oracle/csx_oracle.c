@@ -351,6 +351,61 @@ void orc_adjoint_sai(const orc_geom *g, int nt, int interp, double theta_max, co
     }
 }
 
+/* ---- energy-sensitive detector (App. A, eq. energy_sensitive) -------------------------
+ * An energy-resolving pixel keeps the Bragg energy E = kappa q of each detected photon
+ * instead of integrating over E.  On the spectrum's own energy bins, triple (i, j, q_m)
+ * contributes H(i, j, q_m) f_jm to detector energy bin k = floor((kappa_ij q_m - e_lo)/dE)
+ * of pixel i, and to nothing when E is outside [e_lo, e_hi) (there Phi, hence H, is 0).
+ * The sum over k is the energy-integrating g of eq. energy_integrating_finite_detector.
+ * Layout of the energy-resolved detector data: [ne][ndy][ndx]. */
+static int energy_bin(const orc_geom *g, double E)
+{
+    double de = (g->e_hi - g->e_lo) / g->ne;
+    double k = floor((E - g->e_lo) / de);
+    if (k < 0.0 || k >= (double)g->ne) return -1;
+    return (int)k;
+}
+
+void orc_forward_energy(const orc_geom *g, const double *f, double *out)
+{
+    int npix = g->ndx * g->ndy, nvox = g->nx * g->nz;
+    memset(out, 0, sizeof(double) * (size_t)g->ne * npix);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < npix; ++i)
+        for (int j = 0; j < nvox; ++j) {
+            orc_pair p;
+            pair_factors(g, j, i, &p);
+            double w = g->C * p.Gso * p.God * p.T * p.dtheta;
+            const double *fj = f + (long)j * g->nq;
+            for (int m = 0; m < g->nq; ++m) {
+                int k = energy_bin(g, p.kappa * g->q[m]);
+                if (k < 0) continue;
+                out[(long)k * npix + i] += w * spectral_factor(g, &p, g->q[m]) * fj[m];
+            }
+        }
+}
+
+/* The transpose: b_jm = sum_i H(i, j, q_m) y[k(i, j, m)][i]. */
+void orc_adjoint_energy(const orc_geom *g, const double *y, double *out)
+{
+    int npix = g->ndx * g->ndy, nvox = g->nx * g->nz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < nvox; ++j) {
+        double *bj = out + (long)j * g->nq;
+        for (int m = 0; m < g->nq; ++m) bj[m] = 0.0;
+        for (int i = 0; i < npix; ++i) {
+            orc_pair p;
+            pair_factors(g, j, i, &p);
+            double w = g->C * p.Gso * p.God * p.T * p.dtheta;
+            for (int m = 0; m < g->nq; ++m) {
+                int k = energy_bin(g, p.kappa * g->q[m]);
+                if (k < 0) continue;
+                bj[m] += w * spectral_factor(g, &p, g->q[m]) * y[(long)k * npix + i];
+            }
+        }
+    }
+}
+
 /* Largest scatter angle over all voxel-pixel pairs. */
 double orc_max_angle(const orc_geom *g)
 {
