@@ -217,6 +217,26 @@ csx_status csx_backproject_sai(csx_geometry *h, const float *y, float *b, void *
 #define CSX_OP_ADJOINT_SAI 2
 csx_status csx_set_operator(csx_geometry *h, int ops);
 
+/* Energy-sensitive detector (App. A, eq. energy_sensitive): an
+ * energy-resolving pixel records each photon in the spectrum bin of its Bragg
+ * energy E = kappa q (the detector's bins are the spectrum's ne bins on
+ * [e_lo, e_hi)), so
+ *   g_E[k][i] = sum_j sum_{m: bin(kappa_ij q_m) = k} H(i, j, q_m) f_jm
+ * and sum_k g_E[k][i] is csx_forward's g_i.  f: device [nz][nx][nq]; gE:
+ * device [ne][ndy][ndx], overwritten.  Each wave adds its triples into
+ * 64-bit fixed-point histograms scaled to the launch's bound
+ * max(A) max(Phi) sum_jm q_m |f_jm| (results do not depend on the order of
+ * the adds); a non-finite f gives NaN everywhere.  Needs ne small enough for
+ * the histograms in LDS (about ne <= 180 with a 128-row mask; else
+ * CSX_EINVAL).  The first call on a handle also finds max(A) (synchronous) and
+ * allocates its partial images.  Asynchronous on `stream`. */
+csx_status csx_forward_energy(csx_geometry *h, const float *f, float *gE, void *stream);
+
+/* The transpose: b_jm = sum_i H(i, j, q_m) y_E[bin(kappa_ij q_m)][i].  yE:
+ * device [ne][ndy][ndx]; b: device [nz][nx][nq], overwritten.  Asynchronous
+ * on `stream` (keeps a Phi-weighted copy of yE, (ne + 2) npix floats). */
+csx_status csx_backproject_energy(csx_geometry *h, const float *yE, float *b, void *stream);
+
 /* Launch shape of a handle's operators; a tuner may change it (results do not
  * depend on it beyond float32 summation order).
  *   fwd_splits: the forward's voxel range is split over this many block rows

@@ -101,6 +101,7 @@ static void free_all(csx_geometry *h)
 {
     csx_os_free(h);
     csx_sai_free(h);
+    csx_energy_free(h);
     void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qblk, h->t.qv, h->t.phi32,
                     h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
                     h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags,

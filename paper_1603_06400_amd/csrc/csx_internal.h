@@ -71,6 +71,7 @@ struct DevTables {
 // LDS layout of an operator launch (byte offsets).
 struct Lds {
     int phi, mask, tile, total;
+    int hist = 0;       // energy-resolved forward: per-wave bin histograms
 };
 
 // One scan's share of a batched operator launch (device array).
@@ -126,6 +127,8 @@ struct csx_geometry {
     float *warm = nullptr;     // activations of the warm-start network
     size_t warm_cap = 0;       // floats in warm
     void *sai = nullptr;       // scatter-angle-interpolation tables (csx_sai.hip), on demand
+    void *energy = nullptr;    // energy-resolved operator buffers (csx_energy.hip), on demand
+    double a_max = 0.0;        // largest pair weight A of the geometry (0: not computed yet)
     int op_sai = 0;            // solver operators: bit 0 forward, bit 1 adjoint interpolated
     std::vector<double> q_host, phi_host;   // the descriptor's q nodes and spectrum
     int nbL = 0, nbR = 0;
@@ -175,6 +178,13 @@ csx_status csx_ensure_b1(csx_geometry *h, hipStream_t s);
 void csx_os_free(csx_geometry *h);
 // scatter-angle interpolation (csx_sai.hip)
 void csx_sai_free(csx_geometry *h);
+csx_status csx_pair_weight_max(csx_geometry *h, double *out);
+// energy-resolved operators (csx_ops.hip launchers, csx_energy.hip API)
+size_t csx_forward_energy_floats(const csx_geometry *h, int *lds_bytes);
+csx_status csx_launch_forward_energy(csx_geometry *h, const float *f, const double *sc, float *part,
+                                     size_t part_cap, float *gE, hipStream_t s);
+csx_status csx_launch_adjoint_energy(csx_geometry *h, const float *psi, float *b, hipStream_t s);
+void csx_energy_free(csx_geometry *h);
 csx_status csx_launch_forward_sai(csx_geometry *h, const float *f, float *g, hipStream_t s);
 csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, hipStream_t s);
 csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s);

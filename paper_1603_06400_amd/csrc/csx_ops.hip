@@ -46,7 +46,11 @@ namespace {
 // adjoint: one wave per voxel group (voxel j, and its mirror j2 with LR) and
 // q chunk; lanes = pixel classes (a, b_up), b_up in the upper half, 64 per batch.
 // ---------------------------------------------------------------------------
-template <int LR, int QW, int QU>
+// EN = 1: energy-resolved data (the energy-sensitive detector of App. A).
+// rho is then Psi [ne + 2][npix], Psi[k][i] = Phi_k y_E[k - 1][i] with zero
+// planes at the pad bins 0 and ne + 1, and a triple reads Psi at its own
+// spectrum bin and pixel instead of Phi times the pixel's ratio.
+template <int LR, int QW, int QU, int EN = 0>
 __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &T, const Lds &L,
                                              const double *__restrict__ qa,
                                              const double2 *__restrict__ qblk,
@@ -115,6 +119,7 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
     float r_u = 0.0f, r_d = 0.0f, r_bu = 0.0f, r_bd = 0.0f;
     auto load_rho = [&](int t) {
         int a, r;
+        if (EN) return;                         // read per node from Psi
         if (class_of(t, a, r)) {
             const int bu = half_y + r;
             const int bd = P.ndy - 1 - bu;
@@ -135,16 +140,32 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
         double kap = 0.0;
         float c0 = 0.0f, c1 = 0.0f;
         bool act = false;
+        // EN: the class's pair weight times each pixel's mask value, and the
+        // pixels' columns in Psi
+        float eu = 0.0f, ed = 0.0f, ebu = 0.0f, ebd = 0.0f;
+        const float *pu = rho, *pd = rho, *pbu = rho, *pbd = rho;
         if (has) {
             const int bu = half_y + r;
             const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
             const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
             const Cells c = mask_cells(P, vm, xp, yp);
             float w0 = 0.0f, w1 = 0.0f;
+            float tu = 0.0f, td = 0.0f, tbu = 0.0f, tbd = 0.0f;
             if (c.in_rows) {
                 const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
-                w0 = bitf(ru, c.col_a) * r_u + bitf(rd, c.col_a) * r_d;
-                if (LR) w1 = bitf(ru, c.col_b) * r_bu + bitf(rd, c.col_b) * r_bd;
+                tu = bitf(ru, c.col_a);
+                td = bitf(rd, c.col_a);
+                if (LR) {
+                    tbu = bitf(ru, c.col_b);
+                    tbd = bitf(rd, c.col_b);
+                }
+                if (EN) {
+                    w0 = tu + td;
+                    w1 = tbu + tbd;
+                } else {
+                    w0 = tu * r_u + td * r_d;
+                    if (LR) w1 = tbu * r_bu + tbd * r_bd;
+                }
             }
             if (w0 != 0.0f || w1 != 0.0f) {
                 double k;
@@ -155,9 +176,32 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
                     c1 = A * w1;
                     act = c0 != 0.0f || c1 != 0.0f;
                     if (act) kap = k;
+                    if (EN) {
+                        const int bd = P.ndy - 1 - bu;
+                        eu = A * tu;
+                        ed = A * td;
+                        pu = rho + bu * P.ndx + a;
+                        pd = rho + bd * P.ndx + a;
+                        if (LR) {
+                            const int ab = P.ndx - 1 - a;
+                            ebu = A * tbu;
+                            ebd = A * tbd;
+                            pbu = rho + bu * P.ndx + ab;
+                            pbd = rho + bd * P.ndx + ab;
+                        }
+                    }
                 }
             }
         }
+        // EN: sum over the class's pixels of A T Psi[kk][pixel] (zero weights
+        // skip their loads)
+        auto psi_sum = [&](uint32_t kk, float e1, const float *p1, float e2, const float *p2) -> float {
+            const size_t o = (size_t)kk * P.npix;
+            float v = 0.0f;
+            if (e1 != 0.0f) v = e1 * p1[o];
+            if (e2 != 0.0f) v = fmaf(e2, p2[o], v);
+            return v;
+        };
         if (t + 1 < ntiles) load_rho(t + 1);
         if (__ballot(act) == 0) continue;
         if (QU) {
@@ -176,9 +220,14 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
                     const int m = blk * 8 + mm;
                     const uint32_t kk = min((uint32_t)(int)u, top);
                     u += du;
-                    const float ph = spec(s_phi, kk);
-                    acc0[m] = fmaf(c0, ph, acc0[m]);
-                    if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
+                    if (EN) {
+                        acc0[m] += psi_sum(kk, eu, pu, ed, pd);
+                        if (LR) acc1[m] += psi_sum(kk, ebu, pbu, ebd, pbd);
+                    } else {
+                        const float ph = spec(s_phi, kk);
+                        acc0[m] = fmaf(c0, ph, acc0[m]);
+                        if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
+                    }
                 }
             }
         } else {
@@ -190,9 +239,15 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
-                    const float ph = spec(s_phi, spec_index(kap, qa_c[m], b0, top));
-                    acc0[m] = fmaf(c0, ph, acc0[m]);
-                    if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
+                    const uint32_t kk = spec_index(kap, qa_c[m], b0, top);
+                    if (EN) {
+                        acc0[m] += psi_sum(kk, eu, pu, ed, pd);
+                        if (LR) acc1[m] += psi_sum(kk, ebu, pbu, ebd, pbd);
+                    } else {
+                        const float ph = spec(s_phi, kk);
+                        acc0[m] = fmaf(c0, ph, acc0[m]);
+                        if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
+                    }
                 }
             }
         }
@@ -216,13 +271,22 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
 // batch) evaluating both mirror classes; the block's 8 waves share a q-major
 // tile of q f for the batch's voxels; blockIdx.y splits the voxel groups.
 // ---------------------------------------------------------------------------
-template <int LR, int QW, int QU>
+// EN = 1: energy-resolved output (the energy-sensitive detector of App. A).
+// Each lane adds a triple's contribution to the spectrum bin of its Bragg
+// energy instead of summing over bins: consecutive q nodes of a class that
+// fall in one bin form a run, and each run is added once per output pixel
+// into the wave's histograms in LDS (4 pixels x (ne + 2) bins, 64-bit fixed
+// point with the launch's scale sc[0] = 2^s, sc[1] = 2^-s: integer atomics,
+// totals independent of the add order).  part then holds [ne][npix] per
+// partial image.
+template <int LR, int QW, int QU, int EN = 0>
 __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &T, const Lds &L,
                                              const double *__restrict__ qa,
                                              const double2 *__restrict__ qblk,
                                              const float *__restrict__ f,
                                              float *__restrict__ part, int tiles_per_split,
-                                             int bx, int by, int bz, int gz)
+                                             int bx, int by, int bz, int gz,
+                                             const double *__restrict__ sc = nullptr)
 {
     constexpr int NB = QW / 8;
     constexpr int RPG = LR ? 2 : 1;             // voxel rows per group
@@ -237,6 +301,14 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
     stage_tables(P, T, s_phi, s_bits);
+    const int NE2 = P.ne + 2;
+    unsigned long long *hist = EN ? (unsigned long long *)(lds + L.hist) + (size_t)wv * 4 * NE2 : nullptr;
+    if (EN)
+        for (int k = lane; k < 4 * NE2; k += 64) hist[k] = 0ull;
+    const double fx_scale = EN ? sc[0] : 0.0;
+    auto fx = [&](float v) -> unsigned long long {
+        return (unsigned long long)__double2ll_rz((double)v * fx_scale);
+    };
 
     const int quad = bx * 8 + wv;               // 8 waves per block
     const bool wave_on = quad < P.n_quad;
@@ -378,6 +450,53 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
         if (__ballot(act1 || act2) == 0) continue;
         float w1a = 0.0f, w1b = 0.0f, w2a = 0.0f, w2b = 0.0f;
         const float *trow = s_tile + lane * RPG;
+        // EN: the current run of each class (bin 0 is a pad: no run yet)
+        uint32_t cur1 = 0u, cur2 = 0u;
+        float r1a = 0.0f, r1b = 0.0f, r2a = 0.0f, r2b = 0.0f;
+        auto flush1 = [&]() {
+            unsigned long long *hb = hist + cur1;
+            if (r1a != 0.0f) {
+                if (c10 != 0.0f) atomicAdd(hb, fx(c10 * r1a));
+                if (c11 != 0.0f) atomicAdd(hb + NE2, fx(c11 * r1a));
+            }
+            if (LR && r1b != 0.0f) {
+                if (c12 != 0.0f) atomicAdd(hb + 2 * NE2, fx(c12 * r1b));
+                if (c13 != 0.0f) atomicAdd(hb + 3 * NE2, fx(c13 * r1b));
+            }
+            r1a = 0.0f;
+            r1b = 0.0f;
+        };
+        auto flush2 = [&]() {
+            unsigned long long *hb = hist + cur2;
+            if (r2b != 0.0f) {
+                if (c20 != 0.0f) atomicAdd(hb, fx(c20 * r2b));
+                if (c21 != 0.0f) atomicAdd(hb + NE2, fx(c21 * r2b));
+            }
+            if (r2a != 0.0f) {
+                if (c22 != 0.0f) atomicAdd(hb + 2 * NE2, fx(c22 * r2a));
+                if (c23 != 0.0f) atomicAdd(hb + 3 * NE2, fx(c23 * r2a));
+            }
+            r2a = 0.0f;
+            r2b = 0.0f;
+        };
+        // one node of each class: p = Phi at the node's bin i, fa / fb = q f of
+        // voxel j / of its mirror
+        auto en_node = [&](uint32_t i1, float p1, uint32_t i2, float p2, float fa, float fb) {
+            if (i1 != cur1) {
+                flush1();
+                cur1 = i1;
+            }
+            r1a = fmaf(p1, fa, r1a);
+            if (LR) {
+                r1b = fmaf(p1, fb, r1b);
+                if (i2 != cur2) {
+                    flush2();
+                    cur2 = i2;
+                }
+                r2a = fmaf(p2, fa, r2a);
+                r2b = fmaf(p2, fb, r2b);
+            }
+        };
         if (QU) {
             const double qa0 = P.a0 + P.da * m0;
             const double u10 = fma(k1, qa0, b0), du1 = k1 * P.da;
@@ -399,16 +518,24 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
-                    const float p1 = spec(s_phi, min((uint32_t)(int)ua, top));
+                    const uint32_t i1 = min((uint32_t)(int)ua, top);
+                    const float p1 = spec(s_phi, i1);
                     ua += du1;
                     if (LR) {
-                        const float p2 = spec(s_phi, min((uint32_t)(int)ub, top));
+                        const uint32_t i2 = min((uint32_t)(int)ub, top);
+                        const float p2 = spec(s_phi, i2);
                         ub += du2;
                         const float2 fv = *(const float2 *)(trow + m * TS);
-                        w1a = fmaf(p1, fv.x, w1a);
-                        w1b = fmaf(p1, fv.y, w1b);
-                        w2a = fmaf(p2, fv.x, w2a);
-                        w2b = fmaf(p2, fv.y, w2b);
+                        if (EN) {
+                            en_node(i1, p1, i2, p2, fv.x, fv.y);
+                        } else {
+                            w1a = fmaf(p1, fv.x, w1a);
+                            w1b = fmaf(p1, fv.y, w1b);
+                            w2a = fmaf(p2, fv.x, w2a);
+                            w2b = fmaf(p2, fv.y, w2b);
+                        }
+                    } else if (EN) {
+                        en_node(i1, p1, 0u, 0.0f, trow[m * TS], 0.0f);
                     } else {
                         w1a = fmaf(p1, trow[m * TS], w1a);
                     }
@@ -425,19 +552,32 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
                     const double am = qa_c[m];
-                    const float p1 = spec(s_phi, spec_index(k1, am, b0, top));
+                    const uint32_t i1 = spec_index(k1, am, b0, top);
+                    const float p1 = spec(s_phi, i1);
                     if (LR) {
-                        const float p2 = spec(s_phi, spec_index(k2, am, b0, top));
+                        const uint32_t i2 = spec_index(k2, am, b0, top);
+                        const float p2 = spec(s_phi, i2);
                         const float2 fv = *(const float2 *)(trow + m * TS);
-                        w1a = fmaf(p1, fv.x, w1a);
-                        w1b = fmaf(p1, fv.y, w1b);
-                        w2a = fmaf(p2, fv.x, w2a);
-                        w2b = fmaf(p2, fv.y, w2b);
+                        if (EN) {
+                            en_node(i1, p1, i2, p2, fv.x, fv.y);
+                        } else {
+                            w1a = fmaf(p1, fv.x, w1a);
+                            w1b = fmaf(p1, fv.y, w1b);
+                            w2a = fmaf(p2, fv.x, w2a);
+                            w2b = fmaf(p2, fv.y, w2b);
+                        }
+                    } else if (EN) {
+                        en_node(i1, p1, 0u, 0.0f, trow[m * TS], 0.0f);
                     } else {
                         w1a = fmaf(p1, trow[m * TS], w1a);
                     }
                 }
             }
+        }
+        if (EN) {
+            flush1();
+            if (LR) flush2();
+            continue;
         }
         o0 = fmaf(c10, w1a, o0);
         o1 = fmaf(c11, w1a, o1);
@@ -451,6 +591,21 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
         }
     }
     if (!wave_on) return;
+    if (EN) {
+        // the histograms' bins 1..ne to float: partial image [ne][npix]
+        const double inv = sc[1];
+        const bool bad = fx_scale == 0.0;       // non-finite input
+        float *dst = part + (size_t)(by * gz + qc) * P.ne * P.npix;
+        const int bd = P.ndy - 1 - bu, ab = P.ndx - 1 - a;
+        const int px[4] = {bu * P.ndx + a, bd * P.ndx + a, bu * P.ndx + ab, bd * P.ndx + ab};
+        for (int k = lane; k < P.ne; k += 64)
+#pragma unroll
+            for (int o = 0; o < (LR ? 4 : 2); ++o) {
+                const long long v = (long long)hist[o * NE2 + k + 1];
+                dst[(size_t)k * P.npix + px[o]] = bad ? __builtin_nanf("") : (float)((double)v * inv);
+            }
+        return;
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         o0 += __shfl_xor(o0, off, 64);
@@ -492,6 +647,29 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
 {
     forward_body<LR, QW, QU>(P, T, L, qa, qblk, f, part, tiles_per_split, blockIdx.x,
                                  blockIdx.y, blockIdx.z, gridDim.z);
+}
+
+// Energy-resolved operators (the energy-sensitive detector of App. A).
+template <int LR, int QW, int QU>
+__global__ void __launch_bounds__(256) k_adjoint_energy(KParams P, DevTables T, Lds L,
+                                                        const double *__restrict__ qa,
+                                                        const double2 *__restrict__ qblk,
+                                                        const float *__restrict__ psi,
+                                                        float *__restrict__ b)
+{
+    adjoint_body<LR, QW, QU, 1>(P, T, L, qa, qblk, psi, b, blockIdx.x, blockIdx.y);
+}
+
+template <int LR, int QW, int QU>
+__global__ void __launch_bounds__(512) k_forward_energy(KParams P, DevTables T, Lds L,
+                                                        const double *__restrict__ qa,
+                                                        const double2 *__restrict__ qblk,
+                                                        const float *__restrict__ f,
+                                                        float *__restrict__ part, int tiles_per_split,
+                                                        const double *__restrict__ sc)
+{
+    forward_body<LR, QW, QU, 1>(P, T, L, qa, qblk, f, part, tiles_per_split, blockIdx.x, blockIdx.y,
+                                blockIdx.z, gridDim.z, sc);
 }
 
 // Batched launches: the blocks of several scans in one grid.  Block b belongs
@@ -650,7 +828,79 @@ struct RunAdjBatch {
     }
 };
 
+template <int LR, int QW, int QU>
+struct RunFwdE {
+    static void run(const OpShape &S, const csx_geometry *h, const float *f, float *part, const double *sc,
+                    hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_forward_energy<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t, S.L,
+                           h->t.qa, h->t.qblk, f, part, S.tps, sc);
+    }
+};
+
+template <int LR, int QW, int QU>
+struct RunAdjE {
+    static void run(const OpShape &S, const csx_geometry *h, const float *psi, float *b, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_adjoint_energy<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t, S.L,
+                           h->t.qa, h->t.qblk, psi, b);
+    }
+};
+
+// Launch shape of the energy-resolved forward: q chunks of <= 32 (the LDS
+// also holds the 8 waves' histograms), and enough voxel splits for ~2048
+// blocks.
+OpShape forward_energy_shape(const csx_geometry *h)
+{
+    OpShape S;
+    S.P = h->P;
+    S.P.qw = S.P.nq <= 16 ? 16 : 32;
+    S.P.qchunks = (S.P.nq + S.P.qw - 1) / S.P.qw;
+    S.L = lds_layout(S.P, true);
+    S.L.hist = (S.L.total + 15) & ~15;
+    S.L.total = S.L.hist + 8 * 4 * (S.P.ne + 2) * 8;
+    const int ntiles = fwd_tiles(S.P);
+    const int bx = (S.P.n_quad + 7) / 8;
+    const int splits = std::max(1, std::min(std::min(16, ntiles), 2048 / std::max(1, bx * S.P.qchunks)));
+    S.tps = (ntiles + splits - 1) / splits;
+    const int nsplit = (ntiles + S.tps - 1) / S.tps;
+    S.grid = dim3(bx, nsplit, S.P.qchunks);
+    S.block = dim3(512);
+    S.nparts = nsplit * S.P.qchunks;
+    S.variant = variant_of(S.P);
+    return S;
+}
+
 }  // namespace
+
+size_t csx_forward_energy_floats(const csx_geometry *h, int *lds_bytes)
+{
+    const OpShape S = forward_energy_shape(h);
+    if (lds_bytes) *lds_bytes = S.L.total;
+    return (size_t)S.nparts * h->P.ne * h->P.npix;
+}
+
+csx_status csx_launch_forward_energy(csx_geometry *h, const float *f, const double *sc, float *part,
+                                     size_t part_cap, float *gE, hipStream_t s)
+{
+    const OpShape S = forward_energy_shape(h);
+    const size_t n = (size_t)h->P.ne * h->P.npix;
+    if ((size_t)S.nparts * n > part_cap) return csx_fail(CSX_EINVAL, "energy partials too small");
+    if (S.L.total > 65536) return csx_fail(CSX_EINVAL, "energy-resolved forward: ne too large for LDS");
+    dispatch<RunFwdE>(S.variant, S, h, f, part, sc, s);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, S.nparts, (int)n, gE);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_adjoint_energy(csx_geometry *h, const float *psi, float *b, hipStream_t s)
+{
+    const OpShape S = csx_adjoint_shape(h);
+    dispatch<RunAdjE>(S.variant, S, h, psi, b, s);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
 
 hipEvent_t csx_timing_event(csx_geometry *h, int op)
 {

@@ -520,6 +520,31 @@ SaiState *state(const csx_geometry *h) { return static_cast<SaiState *>(h->sai);
 
 }  // namespace
 
+// max over all voxel-pixel pairs of the pair weight A (mask ignored), computed
+// once per handle
+csx_status csx_pair_weight_max(csx_geometry *h, double *out)
+{
+    if (h->a_max <= 0.0) {
+        const KParams &P = h->P;
+        float *am = nullptr;
+        HIP_TRY(hipMalloc((void **)&am, sizeof(float) * P.n_groups));
+        if (P.lr)
+            hipLaunchKernelGGL(k_sai_amax<1>, dim3((P.n_groups + 3) / 4), dim3(256), 0, nullptr, P, h->t, am);
+        else
+            hipLaunchKernelGGL(k_sai_amax<0>, dim3((P.n_groups + 3) / 4), dim3(256), 0, nullptr, P, h->t, am);
+        hipError_t e = hipGetLastError();
+        std::vector<float> hm(P.n_groups);
+        if (e == hipSuccess) e = hipMemcpy(hm.data(), am, sizeof(float) * P.n_groups, hipMemcpyDeviceToHost);
+        (void)hipFree(am);
+        if (e != hipSuccess) return csx_fail(CSX_EHIP, std::string("pair weight maximum: ") + hipGetErrorString(e));
+        double m = 0.0;
+        for (float v : hm) m = std::max(m, (double)v);
+        h->a_max = m;
+    }
+    *out = h->a_max;
+    return CSX_OK;
+}
+
 void csx_sai_free(csx_geometry *h)
 {
     release(state(h));
@@ -575,19 +600,10 @@ extern "C" csx_status csx_sai_config(csx_geometry *h, int nt, int interp, double
     if (e == hipSuccess) e = hipMemcpy(s->S, S.data(), sizeof(float) * S.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->St, St.data(), sizeof(float) * St.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) {   // the largest pair weight, for the adjoint's fixed-point scale
-        const KParams &P = h->P;
-        float *am = nullptr;
-        e = hipMalloc((void **)&am, sizeof(float) * P.n_groups);
-        if (e == hipSuccess) {
-            if (P.lr)
-                hipLaunchKernelGGL(k_sai_amax<1>, dim3((P.n_groups + 3) / 4), dim3(256), 0, nullptr, P, h->t, am);
-            else
-                hipLaunchKernelGGL(k_sai_amax<0>, dim3((P.n_groups + 3) / 4), dim3(256), 0, nullptr, P, h->t, am);
-            e = hipGetLastError();
-            std::vector<float> hm(P.n_groups);
-            if (e == hipSuccess) e = hipMemcpy(hm.data(), am, sizeof(float) * P.n_groups, hipMemcpyDeviceToHost);
-            for (float v : hm) s->a_max = std::max(s->a_max, (double)v);
-            (void)hipFree(am);
+        const csx_status st = csx_pair_weight_max(h, &s->a_max);
+        if (st != CSX_OK) {
+            release(s);
+            return st;
         }
     }
     if (e != hipSuccess) {

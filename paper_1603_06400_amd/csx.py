@@ -65,7 +65,8 @@ EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_g
            "csx_cnn_workspace_bytes", "csx_conv3x3_forward", "csx_conv3x3_backward_data",
            "csx_conv3x3_backward_weights", "csx_warm_loss", "csx_adam_step", "csx_to_half",
            "csx_warm_input", "csx_warm_output", "csx_warm_target", "csx_warm_start", "csx_recon_warm",
-           "csx_sai_config", "csx_sai_info", "csx_forward_sai", "csx_backproject_sai", "csx_set_operator"]
+           "csx_sai_config", "csx_sai_info", "csx_forward_sai", "csx_backproject_sai", "csx_set_operator",
+           "csx_forward_energy", "csx_backproject_energy"]
 
 
 class _WarmNet(ctypes.Structure):
@@ -116,6 +117,10 @@ def lib():
         L.csx_backproject_sai.restype = ctypes.c_int
         L.csx_set_operator.argtypes = [vp, ctypes.c_int]
         L.csx_set_operator.restype = ctypes.c_int
+        L.csx_forward_energy.argtypes = [vp, vp, vp, vp]
+        L.csx_forward_energy.restype = ctypes.c_int
+        L.csx_backproject_energy.argtypes = [vp, vp, vp, vp]
+        L.csx_backproject_energy.restype = ctypes.c_int
         L.csx_get_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
         L.csx_get_launch.restype = ctypes.c_int
         L.csx_set_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
@@ -218,6 +223,7 @@ class Geometry:
         self.geom = geom
         self.table_dtype = table_dtype
         self.nvox, self.npix, self.nq = geom.nx * geom.nz, geom.ndx * geom.ndy, int(len(geom.q))
+        self.ne = int(len(geom.phi))
         self.image_shape = (geom.nz, geom.nx, self.nq)
         self.detector_shape = (geom.ndy, geom.ndx)
         d, keep = make_desc(geom, table_dtype)
@@ -330,6 +336,20 @@ class Geometry:
         out = self.new_image() if out is None else out
         _check(lib().csx_backproject_sai(self._h, _dev(y, self.npix, "y"),
                                          _dev(out, self.nvox * self.nq, "b"), _stream()))
+        return out
+
+    def forward_energy(self, f: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Energy-resolved detector image [ne][ndy][ndx] (App. A eq. energy_sensitive)."""
+        out = torch.empty((self.ne,) + self.detector_shape, dtype=torch.float32, device="cuda") if out is None else out
+        _check(lib().csx_forward_energy(self._h, _dev(f, self.nvox * self.nq, "f"),
+                                        _dev(out, self.ne * self.npix, "gE"), _stream()))
+        return out
+
+    def backproject_energy(self, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Transpose of forward_energy; y of shape [ne][ndy][ndx]."""
+        out = self.new_image() if out is None else out
+        _check(lib().csx_backproject_energy(self._h, _dev(y, self.ne * self.npix, "yE"),
+                                            _dev(out, self.nvox * self.nq, "b"), _stream()))
         return out
 
     def set_operator(self, forward_sai: bool = False, adjoint_sai: bool = False) -> None:
