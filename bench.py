@@ -12,6 +12,7 @@ nominal voxel*pixel*q evaluations of one forward plus one adjoint
     python bench.py --workload warm [--tto-cases N]
     python bench.py --workload os [--steps K]
     python bench.py --workload sai [--steps K] [--sai-interp linear|nearest]
+    python bench.py --workload energy [--steps K]
 
 Prints one JSON line.  The roofline entry uses the work model of the direct
 evaluation (4 VALU lane-ops per open in-band triple, 60 per open pair, 10 per
@@ -297,6 +298,62 @@ def bench_sai(args):
         "objective_exact_last": float(J_ex[-1])}))
 
 
+def bench_energy(args):
+    """The energy-sensitive detector (App. A) on the 128^2 x 64q slice with a
+    64-bin energy-resolving detector: a step is one Alg. 5 iteration on the
+    [64][128][128] counts (forward, ratio, adjoint, update, objective).  The
+    counts are Poisson draws around the library's own energy-resolved forward
+    of the workload phantom (seeded).  Also reported: the event-timed energy
+    operators beside the energy-integrating ones."""
+    import torch
+
+    from paper_1603_06400_amd import csx, inputs
+
+    w = inputs.workload(WORKLOAD)
+    z = np.load(os.path.join(GOLDEN, f"{WORKLOAD}_counts.npz"))
+    g = w.geom.with_(C=float(z["C"]))
+    torch.cuda.set_device(0)
+    geo = csx.Geometry(g)
+    f_true = torch.tensor(inputs.phantom(w.geom, w.phantom_seed, w.n_rect), dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    yE = torch.poisson(geo.forward_energy(f_true).clamp_min(0.0), generator=gen)
+    y = torch.tensor(z["y"], dtype=torch.float32, device="cuda")
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    gE, b, gbuf = torch.empty_like(yE), geo.new_image(), geo.new_detector()
+    ops = {"forward_energy_ms": timed(lambda: geo.forward_energy(f_true, gE), 10),
+           "adjoint_energy_ms": timed(lambda: geo.backproject_energy(yE, b), 10),
+           "forward_exact_ms": timed(lambda: geo.forward(f_true, gbuf), 10),
+           "adjoint_exact_ms": timed(lambda: geo.backproject(y, b), 10)}
+    f = geo.new_image()
+    geo.recon_energy(yE, f, max(1, args.warmup), w.beta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = geo.recon_energy(yE, f, args.steps, w.beta)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
+    nominal = 2.0 * g.nvox * g.npix * g.nq
+    print(json.dumps({
+        "metric": "fwd+adjoint voxel*pixel*energy evals/s at 128^2 x 64q, Alg. 5 on energy-resolved counts "
+                  "(64 energy bins per pixel)",
+        "value": nominal / (ms * 1e-3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (Poisson around the library's forward)",
+        "config": {"workload": "slice128_energy", "ne": g.ne, "beta": w.beta, "nominal_evals_per_step": nominal},
+        "operators": ops, "objective": [float(J[0]), float(J[-1])]}))
+
+
 def time_to_objective(n_cases: int, batched: bool = False, log=None) -> dict:
     """Time for the plain solver, for the judged learned warm start (network
     and judge included) and for ordered subsets (Alg. 6, 64 subsets) to reach
@@ -326,11 +383,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
                          "reference kernel for scaling HBM byte counters")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64", "warm", "os", "sai"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64", "warm", "os", "sai", "energy"],
                     help="slice128 (default): the single 128^2 x 64q slice; batch64: the batched form; "
                          "warm: time to the plain objective with the learned warm start; os: sweeps of "
                          "ordered subsets (Alg. 6, 64 subsets) on the slice; sai: Alg. 5 with "
-                         "scatter-angle interpolation")
+                         "scatter-angle interpolation; energy: Alg. 5 on energy-resolved counts")
     ap.add_argument("--sai-interp", default="linear", choices=["linear", "nearest"],
                     help="sai: node rule of the timed table")
     ap.add_argument("--tto-cases", type=int, default=4,
@@ -361,6 +418,9 @@ def main():
         return
     if args.workload == "sai":
         bench_sai(args)
+        return
+    if args.workload == "energy":
+        bench_energy(args)
         return
     if args.workload == "warm":
         import torch

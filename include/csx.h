@@ -237,6 +237,15 @@ csx_status csx_forward_energy(csx_geometry *h, const float *f, float *gE, void *
  * on `stream` (keeps a Phi-weighted copy of yE, (ne + 2) npix floats). */
 csx_status csx_backproject_energy(csx_geometry *h, const float *yE, float *b, void *stream);
 
+/* Alg. 5 on energy-resolved counts: the Poisson likelihood over every pixel
+ * and energy bin, z = A_E f + r_E, b1 = A_E^T 1 (computed on the first call
+ * and kept), b2 = A_E^T (y_E / z), then the update and the objective of
+ * csx_recon (the handle's penalty).  yE, rE (NULL: 0): device [ne][ndy][ndx];
+ * f, init_uniform (f^0 = sum(yE) / sum(b1)), n_iter, beta and J_hist as for
+ * csx_recon.  Synchronises `stream`. */
+csx_status csx_recon_energy(csx_geometry *h, const float *yE, const float *rE, float *f, int init_uniform,
+                            int n_iter, double beta, double *J_hist, void *stream);
+
 /* Launch shape of a handle's operators; a tuner may change it (results do not
  * depend on it beyond float32 summation order).
  *   fwd_splits: the forward's voxel range is split over this many block rows

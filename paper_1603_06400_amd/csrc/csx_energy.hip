@@ -25,6 +25,13 @@ struct EnergyState {
     size_t part_cap = 0;       // floats in part
     float *psi = nullptr;      // adjoint input [ne + 2][npix]
     double *sc = nullptr;      // [2] fixed-point scale of the forward's histograms and its inverse
+    // Alg. 5 on energy-resolved data
+    float *gE = nullptr;       // [ne][npix] model mean
+    float *rhoE = nullptr;     // [ne][npix] y / z, then ones for the sensitivity
+    double *partL = nullptr;   // per-block data-fit partials
+    int *partF = nullptr;      // per-block flags
+    float *b1 = nullptr;       // [nvox][nq] sensitivity A_E^T 1
+    bool have_b1 = false;
 };
 
 EnergyState *state(const csx_geometry *h) { return static_cast<EnergyState *>(h->energy); }
@@ -112,7 +119,7 @@ void csx_energy_free(csx_geometry *h)
 {
     EnergyState *s = state(h);
     if (!s) return;
-    void *ptrs[] = {s->part, s->psi, s->sc};
+    void *ptrs[] = {s->part, s->psi, s->sc, s->gE, s->rhoE, s->partL, s->partF, s->b1};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete s;
@@ -150,4 +157,76 @@ extern "C" csx_status csx_backproject_energy(csx_geometry *h, const float *yE, f
                        h->t.phi16, h->P.td, h->P.ne, h->P.npix, s->psi);
     HIP_TRY(hipGetLastError());
     return csx_launch_adjoint_energy(h, s->psi, b, st);
+}
+
+namespace {
+
+csx_status ensure_solver(csx_geometry *h)
+{
+    csx_status r = ensure_state(h, true);
+    if (r != CSX_OK) return r;
+    r = ensure_state(h, false);
+    if (r != CSX_OK) return r;
+    EnergyState *s = state(h);
+    const size_t n = (size_t)h->P.ne * h->P.npix, nb = (n + 255) / 256;
+    if (!s->gE) HIP_TRY(hipMalloc((void **)&s->gE, sizeof(float) * n));
+    if (!s->rhoE) HIP_TRY(hipMalloc((void **)&s->rhoE, sizeof(float) * n));
+    if (!s->partL) HIP_TRY(hipMalloc((void **)&s->partL, sizeof(double) * nb));
+    if (!s->partF) HIP_TRY(hipMalloc((void **)&s->partF, sizeof(int) * nb));
+    if (!s->b1) HIP_TRY(hipMalloc((void **)&s->b1, sizeof(float) * (size_t)h->P.nvox * h->P.nq));
+    return CSX_OK;
+}
+
+#define EN_TRY(expr)                 \
+    do {                             \
+        csx_status s_ = (expr);      \
+        if (s_ != CSX_OK) return s_; \
+    } while (0)
+
+}  // namespace
+
+extern "C" csx_status csx_recon_energy(csx_geometry *h, const float *yE, const float *rE, float *f,
+                                       int init_uniform, int n_iter, double beta, double *J_hist, void *stream)
+{
+    if (!h || !yE || !f) return csx_fail(CSX_EINVAL, "NULL argument");
+    if (n_iter < 0) return csx_fail(CSX_EINVAL, "n_iter must be >= 0");
+    if (!(std::isfinite(beta) && beta >= 0.0)) return csx_fail(CSX_EINVAL, "beta must be finite and >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    EN_TRY(ensure_solver(h));
+    EnergyState *s = state(h);
+    const int n = h->P.ne * h->P.npix, nb = (n + 255) / 256, nimg = h->P.nvox * h->P.nq;
+    if (h->jhist_cap < n_iter + 1) {
+        if (h->jhist) HIP_TRY(hipFree(h->jhist));
+        h->jhist = nullptr;
+        h->jhist_cap = 0;
+        HIP_TRY(hipMalloc((void **)&h->jhist, sizeof(double) * (n_iter + 1)));
+        h->jhist_cap = n_iter + 1;
+    }
+    EN_TRY(csx_launch_clear_flags(h, st));
+    if (!s->have_b1) {   // b1 = A_E^T 1
+        EN_TRY(csx_launch_fill(s->rhoE, n, 1.0f, st));
+        EN_TRY(csx_backproject_energy(h, s->rhoE, s->b1, st));
+        s->have_b1 = true;
+    }
+    if (init_uniform) EN_TRY(csx_launch_uniform_start_n(h, yE, n, s->b1, f, st));
+    for (int t = 0; t <= n_iter; ++t) {
+        EN_TRY(csx_forward_energy(h, f, s->gE, st));                                    // z = A_E f (+ r)
+        const bool step = t < n_iter;
+        EN_TRY(csx_launch_ratio_n(n, s->gE, yE, rE, s->rhoE, s->partL, s->partF, step, st));
+        if (step) {
+            EN_TRY(csx_backproject_energy(h, s->rhoE, h->b2, st));                      // b2 = A_E^T (y / z)
+            EN_TRY(csx_launch_update_ex(h, f, s->b1, h->b2, beta, h->ftmp, st));        // f^{t+1}, R(f^t)
+        } else {
+            EN_TRY(csx_launch_update(h, f, beta, false, st));                           // R(f^T)
+        }
+        EN_TRY(csx_launch_objective_n(h, s->partL, nb, s->partF, beta, h->jhist + t, st));
+        if (step) EN_TRY(csx_launch_copy(h->ftmp, f, nimg, st));
+    }
+    int flags = 0;
+    HIP_TRY(hipMemcpyAsync(&flags, h->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (J_hist) HIP_TRY(hipMemcpyAsync(J_hist, h->jhist, sizeof(double) * (n_iter + 1), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (flags & 2) return csx_fail(CSX_EINVAL, "y holds negative or NaN counts");
+    if (flags & 1) return csx_fail(CSX_ENUMERIC, "y_i > 0 where the model mean is 0");
+    return CSX_OK;
 }

@@ -190,3 +190,9 @@ csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, h
 csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s);
 csx_status csx_launch_fill(float *dst, int n, float v, hipStream_t s);
 csx_status csx_launch_clear_flags(csx_geometry *h, hipStream_t s);
+csx_status csx_launch_ratio_n(int n, const float *g, const float *y, const float *r, float *rho, double *partL,
+                              int *partF, bool want_rho, hipStream_t s);
+csx_status csx_launch_objective_n(csx_geometry *h, const double *partL, int nL, const int *partF, double beta,
+                                  double *J, hipStream_t s);
+csx_status csx_launch_uniform_start_n(csx_geometry *h, const float *y, int ny, const float *b1, float *f,
+                                      hipStream_t s);

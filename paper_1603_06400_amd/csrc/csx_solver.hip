@@ -310,3 +310,36 @@ csx_status csx_launch_clear_flags(csx_geometry *h, hipStream_t s)
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
+
+// Pieces of Alg. 5 on data of any length (the energy-resolved detector's
+// [ne][npix] counts): the ratio and data-fit partials over n entries, the
+// objective from those partials, and the uniform start from a given b1.
+csx_status csx_launch_ratio_n(int n, const float *g, const float *y, const float *r, float *rho, double *partL,
+                              int *partF, bool want_rho, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ratio, dim3((n + 255) / 256), dim3(256), 0, s, n, g, y, r, rho, partL, partF,
+                       want_rho ? 1 : 0);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_objective_n(csx_geometry *h, const double *partL, int nL, const int *partF, double beta,
+                                  double *J, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, s, partL, nL, h->partR, h->nbR, partF, beta, h->flags,
+                       J, nullptr);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_uniform_start_n(csx_geometry *h, const float *y, int ny, const float *b1, float *f,
+                                      hipStream_t s)
+{
+    const int n = h->P.nvox * h->P.nq;
+    const int nb = CSX_SUM_BLOCKS;
+    hipLaunchKernelGGL(k_sum2_part, dim3(nb), dim3(256), 0, s, y, ny, b1, n, h->partS);
+    hipLaunchKernelGGL(k_sum2_final, dim3(1), dim3(256), 0, s, h->partS, nb, h->scal);
+    hipLaunchKernelGGL(k_fill_ratio, dim3((n + 255) / 256), dim3(256), 0, s, f, n, h->scal);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}

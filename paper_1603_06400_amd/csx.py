@@ -66,7 +66,7 @@ EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_g
            "csx_conv3x3_backward_weights", "csx_warm_loss", "csx_adam_step", "csx_to_half",
            "csx_warm_input", "csx_warm_output", "csx_warm_target", "csx_warm_start", "csx_recon_warm",
            "csx_sai_config", "csx_sai_info", "csx_forward_sai", "csx_backproject_sai", "csx_set_operator",
-           "csx_forward_energy", "csx_backproject_energy"]
+           "csx_forward_energy", "csx_backproject_energy", "csx_recon_energy"]
 
 
 class _WarmNet(ctypes.Structure):
@@ -121,6 +121,9 @@ def lib():
         L.csx_forward_energy.restype = ctypes.c_int
         L.csx_backproject_energy.argtypes = [vp, vp, vp, vp]
         L.csx_backproject_energy.restype = ctypes.c_int
+        L.csx_recon_energy.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_double), vp]
+        L.csx_recon_energy.restype = ctypes.c_int
         L.csx_get_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
         L.csx_get_launch.restype = ctypes.c_int
         L.csx_set_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
@@ -351,6 +354,17 @@ class Geometry:
         _check(lib().csx_backproject_energy(self._h, _dev(y, self.ne * self.npix, "yE"),
                                             _dev(out, self.nvox * self.nq, "b"), _stream()))
         return out
+
+    def recon_energy(self, y: torch.Tensor, f: torch.Tensor, n_iter: int, beta: float,
+                     r: Optional[torch.Tensor] = None, init_uniform: bool = True) -> np.ndarray:
+        """Alg. 5 on energy-resolved counts y [ne][ndy][ndx], in place on f; returns J(f^0..f^n)."""
+        rp = ctypes.c_void_p(None) if r is None else _dev(r, self.ne * self.npix, "rE")
+        hist = np.zeros(n_iter + 1, dtype=np.float64)
+        _check(lib().csx_recon_energy(self._h, _dev(y, self.ne * self.npix, "yE"), rp,
+                                      _dev(f, self.nvox * self.nq, "f"), int(bool(init_uniform)), int(n_iter),
+                                      float(beta), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      _stream()))
+        return hist
 
     def set_operator(self, forward_sai: bool = False, adjoint_sai: bool = False) -> None:
         """Operators of recon_step / recon / recon_warm: exact, or interpolated in angle."""

@@ -133,6 +133,34 @@ def test_energy_scale_range_and_nan(oracle_mod):
     assert_parity(host(geo.forward_energy(dev(f))), ref, what="forward_energy after NaN")
 
 
+def test_energy_recon_matches_oracle(oracle_mod):
+    """Alg. 5 on energy-resolved counts: the oracle's update driven by its
+    energy operators, the likelihood over every pixel and energy bin."""
+    w, g, f, y = workload_data("slice32")
+    o = oracle_mod.Oracle(g)
+    yE = np.random.Generator(np.random.PCG64(31)).poisson(o.forward_energy(f)).astype(np.float64)
+    geo = csx.Geometry(g)
+    fd = geo.new_image()
+    n = 5
+    J = geo.recon_energy(dev(yE), fd, n, w.beta)
+    b1 = o.adjoint_energy(np.ones((g.ne, g.ndy, g.ndx)))
+    fr = oracle_mod.uniform_start(yE, b1)
+    Jr = []
+    for t in range(n + 1):
+        z = o.forward_energy(fr)
+        Jr.append(oracle_mod.objective_from_mean(yE, z, fr, w.beta))
+        if t < n:
+            fr = oracle_mod.em_update(fr, b1, o.adjoint_energy(oracle_mod.poisson_ratio(yE, z)), w.beta)
+    assert rel_l2(host(fd), fr) <= 1e-4
+    np.testing.assert_allclose(J, Jr, rtol=1e-6)
+    assert np.all(np.diff(J) <= 1e-7 * np.abs(J[1:]))
+    # resuming equals one longer run
+    f2 = geo.new_image()
+    geo.recon_energy(dev(yE), f2, 2, w.beta)
+    geo.recon_energy(dev(yE), f2, 3, w.beta, init_uniform=False)
+    assert torch.equal(f2, fd)
+
+
 def test_energy_errors():
     w, g, f, y = workload_data("slice32")
     # 256 energy bins: the forward's histograms do not fit in LDS
@@ -144,6 +172,14 @@ def test_energy_errors():
     # the adjoint has no such limit
     ye = energy_data(g2, 9)
     assert np.all(np.isfinite(host(geo.backproject_energy(dev(ye)))))
+    with pytest.raises(csx.CsxError) as ei:
+        geo.recon_energy(dev(ye), geo.new_image(), 1, w.beta)
+    assert ei.value.code == csx.CSX_EINVAL
     geo1 = csx.Geometry(g)
     with pytest.raises(ValueError):
         geo1.forward_energy(dev(f), out=torch.empty(5, device="cuda"))
+    bad = energy_data(g, 10)
+    bad[3, 4, 5] = -1.0
+    with pytest.raises(csx.CsxError) as ei:
+        geo1.recon_energy(dev(bad), geo1.new_image(), 1, w.beta)
+    assert ei.value.code == csx.CSX_EINVAL
