@@ -25,6 +25,7 @@ struct EnergyState {
     size_t part_cap = 0;       // floats in part
     float *psi = nullptr;      // adjoint input [ne + 2][npix]
     double *sc = nullptr;      // [2] fixed-point scale of the forward's histograms and its inverse
+    double *scpart = nullptr;  // [SCALE_BLOCKS] partial sums of the scale's bound
     // Alg. 5 on energy-resolved data
     float *gE = nullptr;       // [ne][npix] model mean
     float *rhoE = nullptr;     // [ne][npix] y / z, then ones for the sensitivity
@@ -44,22 +45,34 @@ __device__ __forceinline__ float table_phi(const float *phi32, const uint16_t *p
 // Scale of the forward's fixed-point histograms: every run contribution and
 // every bin total of an output pixel is at most B = a_max phi_max sum_jm q_m
 // |f_jm| in magnitude (a voxel and q node reach a pixel through one bin);
-// 2^s with 2^(s-61) B < 1.  One block, fixed summation order.
-__global__ void __launch_bounds__(1024) k_energy_scale(const float *__restrict__ f, const float *__restrict__ qv,
-                                                       int nvox, int nq, double factor, double *__restrict__ sc)
+// 2^s with 2^(s-61) B < 1.  Block partial sums, then one block adds them in a
+// fixed order.
+constexpr int SCALE_BLOCKS = 256;
+
+__global__ void __launch_bounds__(256) k_energy_scale_part(const float *__restrict__ f, const float *__restrict__ qv,
+                                                           int nvox, int nq, double *__restrict__ part)
 {
-    __shared__ double part[16];
+    __shared__ double red[4];
     const long n = (long)nvox * nq;
     double acc = 0.0;
-    for (long i = threadIdx.x; i < n; i += 1024) acc += fabs((double)qv[i % nq] * (double)f[i]);
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)SCALE_BLOCKS * 256)
+        acc += fabs((double)qv[i % nq] * (double)f[i]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(64) k_energy_scale(const double *__restrict__ part, double factor,
+                                                     double *__restrict__ sc)
+{
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < SCALE_BLOCKS; k += 64) acc += part[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int w = 0; w < 16; ++w) tot += part[w];
-        const double B = factor * tot;
+        const double B = factor * acc;
         double s0 = 1.0, s1 = 1.0;
         if (!(B < INFINITY)) {
             s0 = 0.0;                        // inf or NaN in f
@@ -95,6 +108,7 @@ csx_status ensure_state(csx_geometry *h, bool forward)
         if (!s) return csx_fail(CSX_ENOMEM, "host allocation failed");
         h->energy = s;
         HIP_TRY(hipMalloc((void **)&s->sc, sizeof(double) * 2));
+        HIP_TRY(hipMalloc((void **)&s->scpart, sizeof(double) * SCALE_BLOCKS));
     }
     if (forward) {
         int lds = 0;
@@ -119,7 +133,7 @@ void csx_energy_free(csx_geometry *h)
 {
     EnergyState *s = state(h);
     if (!s) return;
-    void *ptrs[] = {s->part, s->psi, s->sc, s->gE, s->rhoE, s->partL, s->partF, s->b1};
+    void *ptrs[] = {s->part, s->psi, s->sc, s->scpart, s->gE, s->rhoE, s->partL, s->partF, s->b1};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete s;
@@ -140,7 +154,9 @@ extern "C" csx_status csx_forward_energy(csx_geometry *h, const float *f, float 
     // 1 + 2^-7 covers the bfloat16 rounding of the table
     const double factor = a_max * phi_max * (1.0 + 1.0 / 128.0);
     EnergyState *s = state(h);
-    hipLaunchKernelGGL(k_energy_scale, dim3(1), dim3(1024), 0, st, f, h->t.qv, h->P.nvox, h->P.nq, factor, s->sc);
+    hipLaunchKernelGGL(k_energy_scale_part, dim3(SCALE_BLOCKS), dim3(256), 0, st, f, h->t.qv, h->P.nvox, h->P.nq,
+                       s->scpart);
+    hipLaunchKernelGGL(k_energy_scale, dim3(1), dim3(64), 0, st, s->scpart, factor, s->sc);
     HIP_TRY(hipGetLastError());
     return csx_launch_forward_energy(h, f, s->sc, s->part, s->part_cap, gE, st);
 }

@@ -202,6 +202,18 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
             if (e2 != 0.0f) v = fmaf(e2, p2[o], v);
             return v;
         };
+        // the class's values at its current bin, reloaded only when the bin
+        // changes (consecutive q nodes share a bin); pad bins are 0
+        uint32_t cur = 0u;
+        float v0 = 0.0f, v1 = 0.0f;
+        auto en_node = [&](uint32_t kk) {
+            if (kk != cur) {
+                cur = kk;
+                const bool pad = kk == 0u || kk == top;
+                v0 = pad ? 0.0f : psi_sum(kk, eu, pu, ed, pd);
+                if (LR) v1 = pad ? 0.0f : psi_sum(kk, ebu, pbu, ebd, pbd);
+            }
+        };
         if (t + 1 < ntiles) load_rho(t + 1);
         if (__ballot(act) == 0) continue;
         if (QU) {
@@ -221,8 +233,9 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
                     const uint32_t kk = min((uint32_t)(int)u, top);
                     u += du;
                     if (EN) {
-                        acc0[m] += psi_sum(kk, eu, pu, ed, pd);
-                        if (LR) acc1[m] += psi_sum(kk, ebu, pbu, ebd, pbd);
+                        en_node(kk);
+                        acc0[m] += v0;
+                        if (LR) acc1[m] += v1;
                     } else {
                         const float ph = spec(s_phi, kk);
                         acc0[m] = fmaf(c0, ph, acc0[m]);
@@ -241,8 +254,9 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
                     const int m = blk * 8 + mm;
                     const uint32_t kk = spec_index(kap, qa_c[m], b0, top);
                     if (EN) {
-                        acc0[m] += psi_sum(kk, eu, pu, ed, pd);
-                        if (LR) acc1[m] += psi_sum(kk, ebu, pbu, ebd, pbd);
+                        en_node(kk);
+                        acc0[m] += v0;
+                        if (LR) acc1[m] += v1;
                     } else {
                         const float ph = spec(s_phi, kk);
                         acc0[m] = fmaf(c0, ph, acc0[m]);
@@ -896,7 +910,15 @@ csx_status csx_launch_forward_energy(csx_geometry *h, const float *f, const doub
 
 csx_status csx_launch_adjoint_energy(csx_geometry *h, const float *psi, float *b, hipStream_t s)
 {
-    const OpShape S = csx_adjoint_shape(h);
+    // q chunks of <= 32: the per-node gathers of Psi want more waves in flight
+    // than the 64-wide accumulators of the energy-integrating adjoint allow
+    OpShape S = csx_adjoint_shape(h);
+    if (S.P.qw > 32) {
+        S.P.qw = 32;
+        S.P.qchunks = (S.P.nq + 31) / 32;
+        S.grid.y = S.P.qchunks;
+        S.variant = variant_of(S.P);
+    }
     dispatch<RunAdjE>(S.variant, S, h, psi, b, s);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
