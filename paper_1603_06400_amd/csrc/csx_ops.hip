@@ -686,6 +686,131 @@ __global__ void __launch_bounds__(512) k_forward_energy(KParams P, DevTables T, 
                                 blockIdx.z, gridDim.z, sc);
 }
 
+// Energy-resolved adjoint with the Phi-weighted data staged in LDS: a block
+// of 16 waves (one voxel each) walks the pixel-class tiles together; for each
+// 8 x 8 tile of classes (a, upper row r) the block copies Psi[k][pixel] of the
+// tile's 128 pixels (rows bu and bd) for every bin k into LDS, slot u * 64 +
+// lane, so a lane reads its two pixels' values at a triple's bin from LDS.
+constexpr int EA_WAVES = 16;
+
+template <int QW, int QU>
+__global__ void __launch_bounds__(1024) k_adjoint_energy_tiled(KParams P, DevTables T, Lds L,
+                                                               const double *__restrict__ qa,
+                                                               const double2 *__restrict__ qblk,
+                                                               const float *__restrict__ psi,
+                                                               float *__restrict__ b)
+{
+    constexpr int NB = QW / 8;
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint32_t *s_bits = (uint32_t *)(lds + L.mask);
+    float *s_psi = (float *)(lds + L.tile);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < P.mask_ny; k += blockDim.x) s_bits[k] = T.maskbits[k];
+    const int NE2 = P.ne + 2;
+    const int j = blockIdx.x * EA_WAVES + wv;
+    const bool von = j < P.nvox;
+    VoxD vd = {0.0, 1.0, 1.0, 0.0};
+    float2 vf = {0.0f, 0.0f}, vm = {0.0f, 0.0f};
+    if (von) {
+        vd = T.vd[j];
+        vf = T.vf[j];
+        vm = T.vm[j];
+    }
+    const int m0 = blockIdx.y * QW;
+    const double *qa_c = qa + m0;
+    const double2 *qb_c = qblk + blockIdx.y * NB;
+    const double b0 = P.b0;
+    const uint32_t top = (uint32_t)(P.ne + 1);
+    float acc[QW];
+#pragma unroll
+    for (int m = 0; m < QW; ++m) acc[m] = 0.0f;
+    const int half_y = P.ndy / 2;
+    const int ntx = (P.ndx + 7) / 8;
+    const int ntiles = ntx * ((half_y + 7) / 8);
+    // staging: thread = one pixel slot (u or d row of a class) and every
+    // (blockDim / 128)-th bin
+    const int slot = threadIdx.x & 127, kstep = blockDim.x >> 7;
+    const int sc_ = slot & 63;
+    for (int t = 0; t < ntiles; ++t) {
+        const int ta = (t % ntx) * 8, tr = (t / ntx) * 8;
+        __syncthreads();
+        {
+            const int a = ta + (sc_ & 7), r = tr + (sc_ >> 3);
+            const bool valid = a < P.ndx && r < half_y;
+            const int bu = half_y + r;
+            const int row = (slot >> 6) ? P.ndy - 1 - bu : bu;
+            const float *src = psi + (valid ? row * P.ndx + a : 0);
+            for (int k = threadIdx.x >> 7; k < NE2; k += kstep)
+                s_psi[(k << 7) + slot] = valid ? src[(size_t)k * P.npix] : 0.0f;
+        }
+        __syncthreads();
+        if (!von) continue;
+        const int a = ta + (lane & 7), r = tr + (lane >> 3);
+        double kap = 0.0;
+        float eu = 0.0f, ed = 0.0f;
+        bool act = false;
+        if (a < P.ndx && r < half_y) {
+            const int bu = half_y + r;
+            const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
+            const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
+            const Cells c = mask_cells(P, vm, xp, yp);
+            if (c.in_rows) {
+                const float tu = bitf(s_bits[c.row_u], c.col_a), td = bitf(s_bits[c.row_d], c.col_a);
+                if (tu + td != 0.0f) {
+                    double k;
+                    float A;
+                    pair_factors(P, vd, vf, (double)xp, (double)yp, k, A);
+                    if (in_band(P, k)) {
+                        eu = A * tu;
+                        ed = A * td;
+                        kap = k;
+                        act = true;
+                    }
+                }
+            }
+        }
+        if (__ballot(act) == 0) continue;
+        const float *pu = s_psi + lane, *pd = s_psi + 64 + lane;
+        if (QU) {
+            const double u0 = fma(kap, P.a0 + P.da * m0, b0), du = kap * P.da;
+            int lo = QW, hi = -1;
+            if (act) band_range(P, u0, du, 0, QW, lo, hi);
+            const int wlo = wave_min(lo), whi = wave_max(hi);
+#pragma unroll
+            for (int blk = 0; blk < NB; ++blk) {
+                if (blk * 8 + 7 < wlo || blk * 8 > whi) continue;
+                double u = fma((double)(blk * 8), du, u0);
+#pragma unroll
+                for (int mm = 0; mm < 8; ++mm) {
+                    const int m = blk * 8 + mm;
+                    const uint32_t kk = min((uint32_t)(int)u, top);
+                    u += du;
+                    acc[m] = fmaf(eu, pu[kk << 7], fmaf(ed, pd[kk << 7], acc[m]));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int blk = 0; blk < NB; ++blk) {
+                const double2 qr = qb_c[blk];
+                const bool need = act && kap * qr.y >= P.band_lo && kap * qr.x < P.band_hi;
+                if (__ballot(need) == 0) continue;
+#pragma unroll
+                for (int mm = 0; mm < 8; ++mm) {
+                    const int m = blk * 8 + mm;
+                    const uint32_t kk = spec_index(kap, qa_c[m], b0, top);
+                    acc[m] = fmaf(eu, pu[kk << 7], fmaf(ed, pd[kk << 7], acc[m]));
+                }
+            }
+        }
+    }
+    if (!von) return;
+    WaveTransposeSum<QW, 32>::run(acc, lane);
+    const int mi = transposed_index<QW>(lane);
+    const int m = m0 + mi;
+    const bool writer = (lane & ((64 / QW) - 1)) == 0;
+    if (writer && m < P.nq) b[(size_t)j * P.nq + m] = acc[0] * T.qv[m];
+}
+
 // Batched launches: the blocks of several scans in one grid.  Block b belongs
 // to the job whose [begin, begin + blocks) range holds it (binary search over
 // the sorted begin offsets); its local index is decoded into that job's grid.
@@ -910,6 +1035,37 @@ csx_status csx_launch_forward_energy(csx_geometry *h, const float *f, const doub
 
 csx_status csx_launch_adjoint_energy(csx_geometry *h, const float *psi, float *b, hipStream_t s)
 {
+    {   // staged form when a tile of Psi fits in LDS
+        KParams P = h->P;
+        P.qw = P.nq <= 16 ? 16 : 32;
+        P.qchunks = (P.nq + P.qw - 1) / P.qw;
+        Lds L;
+        L.phi = 0;
+        L.mask = 0;
+        L.tile = ((P.mask_ny * 4) + 15) & ~15;
+        L.total = L.tile + (P.ne + 2) * 128 * 4;
+        if (L.total <= 48 * 1024) {
+            const dim3 grid((P.nvox + EA_WAVES - 1) / EA_WAVES, P.qchunks);
+            const dim3 block(64 * EA_WAVES);
+            if (P.qw == 16) {
+                if (P.qu)
+                    hipLaunchKernelGGL((k_adjoint_energy_tiled<16, 1>), grid, block, L.total, s, P, h->t, L,
+                                       h->t.qa, h->t.qblk, psi, b);
+                else
+                    hipLaunchKernelGGL((k_adjoint_energy_tiled<16, 0>), grid, block, L.total, s, P, h->t, L,
+                                       h->t.qa, h->t.qblk, psi, b);
+            } else {
+                if (P.qu)
+                    hipLaunchKernelGGL((k_adjoint_energy_tiled<32, 1>), grid, block, L.total, s, P, h->t, L,
+                                       h->t.qa, h->t.qblk, psi, b);
+                else
+                    hipLaunchKernelGGL((k_adjoint_energy_tiled<32, 0>), grid, block, L.total, s, P, h->t, L,
+                                       h->t.qa, h->t.qblk, psi, b);
+            }
+            HIP_TRY(hipGetLastError());
+            return CSX_OK;
+        }
+    }
     // q chunks of <= 32: the per-node gathers of Psi want more waves in flight
     // than the 64-wide accumulators of the energy-integrating adjoint allow
     OpShape S = csx_adjoint_shape(h);
