@@ -207,6 +207,25 @@ __device__ __forceinline__ void band_range(const KParams &P, double u0, double d
     hi = (int)h;
 }
 
+// 64-bit fixed point of a float contribution v at scale 2^s (|v| 2^s < 2^61):
+// x = v 2^s is exact in float, x = hi 2^32 + lo with lo in [0, 2^32), lo
+// formed by one exact FMA; rounds toward -inf (a deterministic choice).
+__device__ __forceinline__ unsigned long long fixed_of(float v, int s)
+{
+    const float x = __builtin_ldexpf(v, s);
+    const float hi = floorf(__builtin_ldexpf(x, -32));
+    const float lo = fmaf(-hi, 4294967296.0f, x);
+    return ((unsigned long long)(uint32_t)(int)hi << 32) + (unsigned long long)(uint32_t)lo;
+}
+
+// The exponent s of a fixed-point scale 2^s held as a double.
+__device__ __forceinline__ int scale_exponent(double sc)
+{
+    int e;
+    (void)frexp(sc, &e);
+    return e - 1;
+}
+
 template <int QW>
 __device__ __forceinline__ int transposed_index(int lane)
 {

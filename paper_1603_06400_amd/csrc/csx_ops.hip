@@ -320,9 +320,8 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
     if (EN)
         for (int k = lane; k < 4 * NE2; k += 64) hist[k] = 0ull;
     const double fx_scale = EN ? sc[0] : 0.0;
-    auto fx = [&](float v) -> unsigned long long {
-        return (unsigned long long)__double2ll_rz((double)v * fx_scale);
-    };
+    const int fx_exp = EN ? scale_exponent(fx_scale) : 0;
+    auto fx = [&](float v) -> unsigned long long { return fixed_of(v, fx_exp); };
 
     const int quad = bx * 8 + wv;               // 8 waves per block
     const bool wave_on = quad < P.n_quad;
