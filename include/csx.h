@@ -207,12 +207,13 @@ csx_status csx_forward_sai(csx_geometry *h, const float *f, float *g, void *stre
 csx_status csx_backproject_sai(csx_geometry *h, const float *y, float *b, void *stream);
 
 /* Operators of the solver: bit CSX_OP_FORWARD_SAI makes csx_recon_step,
- * csx_recon and csx_recon_warm use csx_forward_sai for A f (objectives
- * included), bit CSX_OP_ADJOINT_SAI makes them use csx_backproject_sai for
- * A^T rho and for the sensitivity A^T 1 (recomputed after a change).  With one
- * bit only, the adjoint is not the transpose of the forward and J need not
- * decrease.  ops != 0 needs csx_sai_config first; csx_recon_os and batches
- * return CSX_EINVAL while ops != 0.  Default 0 (exact operators). */
+ * csx_recon, csx_recon_warm and csx_recon_os use the interpolated forward for
+ * A f (and A_p f of a subset; objectives included), bit CSX_OP_ADJOINT_SAI
+ * makes them use the interpolated adjoint for A^T rho and for the
+ * sensitivities A^T 1 and A_p^T 1 (recomputed after a change).  With one bit
+ * only, the adjoint is not the transpose of the forward and J need not
+ * decrease.  ops != 0 needs csx_sai_config first; batches return CSX_EINVAL
+ * while ops != 0.  Default 0 (exact operators). */
 #define CSX_OP_FORWARD_SAI 1
 #define CSX_OP_ADJOINT_SAI 2
 csx_status csx_set_operator(csx_geometry *h, int ops);

@@ -187,6 +187,13 @@ csx_status csx_launch_adjoint_energy(csx_geometry *h, const float *psi, float *b
 void csx_energy_free(csx_geometry *h);
 csx_status csx_launch_forward_sai(csx_geometry *h, const float *f, float *g, hipStream_t s);
 csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, hipStream_t s);
+csx_status csx_launch_forward_sai_list(csx_geometry *h, const float *f, const int *quads, int n_quads, int splits,
+                                       const int *pix, int n_pix, const float *y, const float *r, float *rho,
+                                       hipStream_t s);
+csx_status csx_launch_adjoint_sai_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
+                                       hipStream_t s);
+csx_status csx_launch_sum_ratio_list(csx_geometry *h, int nparts, const int *pix, int n_pix, const float *y,
+                                     const float *r, float *rho, hipStream_t s);
 csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s);
 csx_status csx_launch_fill(float *dst, int n, float v, hipStream_t s);
 csx_status csx_launch_clear_flags(csx_geometry *h, hipStream_t s);

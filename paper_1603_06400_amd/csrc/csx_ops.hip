@@ -1205,6 +1205,14 @@ csx_status csx_launch_forward_list(csx_geometry *h, const float *f, const int *q
     return CSX_OK;
 }
 
+csx_status csx_launch_sum_ratio_list(csx_geometry *h, int nparts, const int *pix, int n_pix, const float *y,
+                                     const float *r, float *rho, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_ratio_list, dim3(n_pix), dim3(64), 0, s, h->part, nparts, h->P.npix, pix, y, r, rho);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
 csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
                                    hipStream_t s)
 {

@@ -31,7 +31,15 @@ struct OsState {
     int *cls = nullptr;                       // [n_sub][n_cls]
     int *pix = nullptr;                       // [n_sub][n_pix]
     float *b1 = nullptr;                      // [n_sub][nvox * nq]
+    int adj_op = 0;                           // CSX_OP_ADJOINT_SAI when b1 came from the interpolated adjoint
 };
+
+// subset adjoint with the handle's selected operator (exact or interpolated)
+csx_status adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b, hipStream_t s)
+{
+    return (h->op_sai & CSX_OP_ADJOINT_SAI) ? csx_launch_adjoint_sai_list(h, rho, cls, n_cls, b, s)
+                                            : csx_launch_adjoint_list(h, rho, cls, n_cls, b, s);
+}
 
 void release(OsState *o)
 {
@@ -115,13 +123,14 @@ csx_status build(csx_geometry *h, int rho_z, int rho_y, hipStream_t s, OsState *
     if ((e = hipMemcpyAsync(o->pix, pix.data(), sizeof(int) * pix.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
         return fail(e);
     for (int p = 0; p < o->n_sub; ++p) {
-        csx_status st = csx_launch_adjoint_list(h, h->ones, o->cls + (size_t)p * o->n_cls, o->n_cls,
-                                                o->b1 + (size_t)p * img, s);
+        csx_status st = adjoint_list(h, h->ones, o->cls + (size_t)p * o->n_cls, o->n_cls, o->b1 + (size_t)p * img,
+                                     s);
         if (st != CSX_OK) {
             release(o);
             return st;
         }
     }
+    o->adj_op = h->op_sai & CSX_OP_ADJOINT_SAI;
     *out = o;
     return CSX_OK;
 }
@@ -156,7 +165,6 @@ extern "C" csx_status csx_recon_os(csx_geometry *h, const float *y, const float 
     if (!h || !y || !f) return csx_fail(CSX_EINVAL, "NULL argument");
     if (n_iter < 0) return csx_fail(CSX_EINVAL, "n_iter must be >= 0");
     if (!(std::isfinite(beta) && beta >= 0.0)) return csx_fail(CSX_EINVAL, "beta must be finite and >= 0");
-    if (h->op_sai) return csx_fail(CSX_EINVAL, "ordered subsets use the exact operators (csx_set_operator(h, 0))");
     const KParams &P = h->P;
     if (rho_z < 1 || rho_y < 2 || rho_y % 2 || (P.ndy / 2) % rho_z || P.ndx % rho_y)
         return csx_fail(CSX_EINVAL, "partition needs rho_z | ndy/2, rho_y | ndx and rho_y even");
@@ -171,7 +179,8 @@ extern "C" csx_status csx_recon_os(csx_geometry *h, const float *y, const float 
     OS_TRY(csx_launch_clear_flags(h, s));
     OS_TRY(csx_ensure_b1(h, s));
     OsState *o = static_cast<OsState *>(h->os);
-    if (!o || o->rho_z != rho_z || o->rho_y != rho_y) {
+    const int adj_op = h->op_sai & CSX_OP_ADJOINT_SAI;   // the subset sensitivities follow the adjoint
+    if (!o || o->rho_z != rho_z || o->rho_y != rho_y || o->adj_op != adj_op) {
         HIP_TRY(hipStreamSynchronize(s));
         csx_os_free(h);
         OS_TRY(build(h, rho_z, rho_y, s, &o));
@@ -181,7 +190,8 @@ extern "C" csx_status csx_recon_os(csx_geometry *h, const float *y, const float 
     if (init_uniform) OS_TRY(csx_launch_uniform_start(h, y, f, s));
     const size_t img = (size_t)P.nvox * P.nq;
     auto objective = [&](const float *fc, int t) -> csx_status {
-        OS_TRY(csx_launch_forward(h, fc, h->gws, s));
+        OS_TRY((h->op_sai & CSX_OP_FORWARD_SAI) ? csx_launch_forward_sai(h, fc, h->gws, s)
+                                                 : csx_launch_forward(h, fc, h->gws, s));
         OS_TRY(csx_launch_ratio(h, y, r, false, s));
         OS_TRY(csx_launch_update(h, fc, beta, false, s));
         return csx_launch_objective(h, beta, h->jhist + t, nullptr, s);
@@ -191,9 +201,12 @@ extern "C" csx_status csx_recon_os(csx_geometry *h, const float *y, const float 
     for (int t = 0; t < n_iter; ++t) {
         float *cur = f, *nxt = h->ftmp;
         for (int p = 0; p < o->n_sub; ++p) {
-            OS_TRY(csx_launch_forward_list(h, cur, o->quads + (size_t)p * o->n_quads, o->n_quads, o->splits,
-                                           o->pix + (size_t)p * o->n_pix, o->n_pix, y, r, h->rho, s));
-            OS_TRY(csx_launch_adjoint_list(h, h->rho, o->cls + (size_t)p * o->n_cls, o->n_cls, h->b2, s));
+            const int *qd = o->quads + (size_t)p * o->n_quads, *px = o->pix + (size_t)p * o->n_pix;
+            if (h->op_sai & CSX_OP_FORWARD_SAI)
+                OS_TRY(csx_launch_forward_sai_list(h, cur, qd, o->n_quads, o->splits, px, o->n_pix, y, r, h->rho, s));
+            else
+                OS_TRY(csx_launch_forward_list(h, cur, qd, o->n_quads, o->splits, px, o->n_pix, y, r, h->rho, s));
+            OS_TRY(adjoint_list(h, h->rho, o->cls + (size_t)p * o->n_cls, o->n_cls, h->b2, s));
             OS_TRY(csx_launch_update_ex(h, cur, o->b1 + (size_t)p * img, h->b2, bp, nxt, s));
             std::swap(cur, nxt);
         }

@@ -194,14 +194,15 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int quad = blockIdx.x * 8 + wv;
     if (quad >= P.n_quad) return;
+    const int qq = P.quad_list ? P.quad_list[quad] : quad;   // a pixel subset's quads, or all
     int a, bu;
     if (LR) {
         const int hx = P.ndx / 2;
-        a = hx + quad % hx;
-        bu = P.ndy / 2 + quad / hx;
+        a = hx + qq % hx;
+        bu = P.ndy / 2 + qq / hx;
     } else {
-        a = quad % P.ndx;
-        bu = P.ndy / 2 + quad / P.ndx;
+        a = qq % P.ndx;
+        bu = P.ndy / 2 + qq / P.ndx;
     }
     const float xpa = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
     const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
@@ -338,11 +339,22 @@ __global__ void __launch_bounds__(256) k_adjoint_sai(KParams P, DevTables T, Lds
     const float2 vf = T.vf[j], vm = T.vm[j];
     const int half_y = P.ndy / 2;
     const int ntx = (P.ndx + 7) / 8;
-    const int ntiles = ntx * ((half_y + 7) / 8);
+    // pixel classes (column a, upper row r): 8 x 8 tiles of the detector, or
+    // 64 consecutive entries of a pixel subset's class list
+    const int ntiles = P.cls_list ? (P.n_cls + 63) / 64 : ntx * ((half_y + 7) / 8);
     for (int t = 0; t < ntiles; ++t) {
-        const int a = (t % ntx) * 8 + (lane & 7);
-        const int r = (t / ntx) * 8 + (lane >> 3);
-        if (a >= P.ndx || r >= half_y) continue;
+        int a, r;
+        if (P.cls_list) {
+            const int e = t * 64 + lane;
+            if (e >= P.n_cls) continue;
+            const int c = P.cls_list[e];
+            a = c % P.ndx;
+            r = c / P.ndx;
+        } else {
+            a = (t % ntx) * 8 + (lane & 7);
+            r = (t / ntx) * 8 + (lane >> 3);
+            if (a >= P.ndx || r >= half_y) continue;
+        }
         const int bu = half_y + r, bd = P.ndy - 1 - bu;
         const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
         const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
@@ -638,16 +650,20 @@ extern "C" csx_status csx_sai_info(const csx_geometry *h, int *nt, int *interp, 
     return CSX_OK;
 }
 
-csx_status csx_launch_forward_sai(csx_geometry *h, const float *f, float *g, hipStream_t st)
+namespace {
+
+// W = f s^T, then the pairs of the quads of P (all, or a subset's list) into
+// h->part; returns the number of partial images
+csx_status forward_sai_parts(csx_geometry *h, const KParams &P, const float *f, int splits_req, int *nparts,
+                             hipStream_t st)
 {
     SaiState *s = state(h);
     if (!s) return csx_fail(CSX_EINVAL, "scatter-angle interpolation not configured");
-    const KParams &P = h->P;
     csx_status r = gemm_nt(f, P.nq, s->S, P.nq, s->W, s->nt, P.nvox, s->nt, P.nq, st, w_layout(P, s->nt));
     if (r != CSX_OK) return r;
     const int gw = P.lr ? P.nx / 2 : P.nx;
     const int ntiles = ((gw + 7) / 8) * ((P.nz + 7) / 8);
-    const int splits = std::max(1, std::min(h->lc.fwd_splits, ntiles));
+    const int splits = std::max(1, std::min(splits_req, ntiles));
     const int tps = (ntiles + splits - 1) / splits;
     const int nsplit = (ntiles + tps - 1) / tps;
     if ((size_t)nsplit * P.npix > h->part_cap) return csx_fail(CSX_EINVAL, "forward partials too small");
@@ -669,14 +685,14 @@ csx_status csx_launch_forward_sai(csx_geometry *h, const float *f, float *g, hip
                                s->inv_dth, h->part, tps);
     }
     HIP_TRY(hipGetLastError());
-    return csx_launch_sum_parts(h, nsplit, g, st);
+    *nparts = nsplit;
+    return CSX_OK;
 }
 
-csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, hipStream_t st)
+csx_status adjoint_sai_impl(csx_geometry *h, const KParams &P, const float *rho, float *b, hipStream_t st)
 {
     SaiState *s = state(h);
     if (!s) return csx_fail(CSX_EINVAL, "scatter-angle interpolation not configured");
-    const KParams &P = h->P;
     // per-wave histograms of 2 nt 64-bit words, at most 32 KiB per block
     const int wpb = std::max(1, std::min(4, 2048 / s->nt));
     const Lds L = sai_lds(P, wpb * 2 * s->nt * 8);
@@ -708,6 +724,43 @@ csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, h
     hipLaunchKernelGGL(k_sum_slices, dim3((n + 255) / 256), dim3(256), 0, st, s->bpart, nz, n, b);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
+}
+
+}  // namespace
+
+csx_status csx_launch_forward_sai(csx_geometry *h, const float *f, float *g, hipStream_t st)
+{
+    int nparts = 0;
+    csx_status r = forward_sai_parts(h, h->P, f, h->lc.fwd_splits, &nparts, st);
+    if (r != CSX_OK) return r;
+    return csx_launch_sum_parts(h, nparts, g, st);
+}
+
+csx_status csx_launch_adjoint_sai(csx_geometry *h, const float *rho, float *b, hipStream_t st)
+{
+    return adjoint_sai_impl(h, h->P, rho, b, st);
+}
+
+csx_status csx_launch_forward_sai_list(csx_geometry *h, const float *f, const int *quads, int n_quads, int splits,
+                                       const int *pix, int n_pix, const float *y, const float *r, float *rho,
+                                       hipStream_t st)
+{
+    KParams P = h->P;
+    P.quad_list = quads;
+    P.n_quad = n_quads;
+    int nparts = 0;
+    csx_status e = forward_sai_parts(h, P, f, splits, &nparts, st);
+    if (e != CSX_OK) return e;
+    return csx_launch_sum_ratio_list(h, nparts, pix, n_pix, y, r, rho, st);
+}
+
+csx_status csx_launch_adjoint_sai_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
+                                       hipStream_t st)
+{
+    KParams P = h->P;
+    P.cls_list = cls;
+    P.n_cls = n_cls;
+    return adjoint_sai_impl(h, P, rho, b, st);
 }
 
 extern "C" csx_status csx_forward_sai(csx_geometry *h, const float *f, float *g, void *stream)

@@ -213,8 +213,52 @@ def test_sai_errors():
     with pytest.raises(csx.CsxError):
         csx._check(csx.lib().csx_set_operator(geo._h, 4))
     geo.set_operator(adjoint_sai=True)
+    b = csx.Batch([geo])
     with pytest.raises(csx.CsxError) as ei:
-        geo.recon_os(yd, geo.new_image(), 1, w.beta)
+        b.recon([yd], [geo.new_image()], 1, w.beta)
     assert ei.value.code == csx.CSX_EINVAL
     geo.set_operator()
-    geo.recon_os(yd, geo.new_image(), 1, w.beta)
+    b.recon([yd], [geo.new_image()], 1, w.beta)
+
+
+def test_sai_ordered_subsets_match_oracle(oracle_mod):
+    """Alg. 6 (64 subsets) with both operators interpolated, as the paper runs
+    its reconstructions: one sweep against the oracle's sub-steps driven by its
+    SAI operators (subset forward, subset adjoint, subset sensitivities); then
+    back to the exact operators, the exact sweep again."""
+    w, g, f, y = workload_data("slice32")
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    geo.sai_config(250, "linear")
+    tm = geo.sai_info()["theta_max"]
+    geo.set_operator(forward_sai=True, adjoint_sai=True)
+    fd = geo.new_image()
+    J = geo.recon_os(dev(y), fd, 1, w.beta, 8, 16)
+    subs = oracle_mod.os_partition(g.ndy, g.ndx, 8, 16)
+    P = len(subs)
+    fwd = lambda v: o.forward_sai(v, 250, tm, 1)
+    adj = lambda v: o.adjoint_sai(v, 250, tm, 1)
+    yf = y.reshape(-1)
+    b1 = []
+    for pix in subs:
+        ind = np.zeros(g.npix)
+        ind[pix] = 1.0
+        b1.append(adj(ind.reshape(g.ndy, g.ndx)))
+    fr = oracle_mod.uniform_start(y, adj(np.ones((g.ndy, g.ndx)))).reshape(g.nz, g.nx, g.nq)
+    J0 = oracle_mod.objective_from_mean(y, fwd(fr), fr, w.beta)
+    for p, pix in enumerate(subs):
+        rho = np.zeros(g.npix)
+        rho[pix] = oracle_mod.poisson_ratio(yf[pix], fwd(fr).reshape(-1)[pix])
+        fr = oracle_mod.em_update(fr, b1[p], adj(rho.reshape(g.ndy, g.ndx)), w.beta / P)
+    J1 = oracle_mod.objective_from_mean(y, fwd(fr), fr, w.beta)
+    assert rel_l2(host(fd), fr) <= 1e-4
+    np.testing.assert_allclose(J, [J0, J1], rtol=1e-5)
+    # the exact operators again: the subset sensitivities are rebuilt
+    geo.set_operator()
+    fe = geo.new_image()
+    Je = geo.recon_os(dev(y), fe, 1, w.beta, 8, 16)
+    ref = csx.Geometry(g)
+    fe2 = ref.new_image()
+    Je2 = ref.recon_os(dev(y), fe2, 1, w.beta, 8, 16)
+    assert torch.equal(fe, fe2)
+    np.testing.assert_array_equal(Je, Je2)
