@@ -14,10 +14,11 @@
 //             interpolation weights) collected in a per-wave LDS histogram,
 //             then b = V s, a dense [nvox x nt] x [nt x nq] product.
 //
-// The histogram adds are LDS atomics into memory that only the adding wave
-// touches; the lanes of one instruction are applied in a fixed order, so runs
-// are reproducible bit for bit (tested).  Interpolation: nearest node (the
-// paper's choice) or linear.
+// The histograms are 64-bit fixed point, added with LDS integer atomics into
+// memory that only the adding wave touches: integer adds are associative, so
+// the totals do not depend on the order of the adds and runs repeat bit for
+// bit (tested).  Interpolation: nearest node (the paper's choice) or linear;
+// the kernels also take a pixel subset's quad / class lists (ordered subsets).
 #include "csx_device.h"
 
 #include <cmath>
