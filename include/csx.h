@@ -228,8 +228,7 @@ csx_status csx_set_operator(csx_geometry *h, int ops);
  * 64-bit fixed-point histograms scaled to the launch's bound
  * max(A) max(Phi) sum_jm q_m |f_jm| (results do not depend on the order of
  * the adds); a non-finite f gives NaN everywhere.  Needs ne small enough for
- * the histograms in LDS (about ne <= 180 with a 128-row mask; else
- * CSX_EINVAL).  The first call on a handle also finds max(A) (synchronous) and
+ * the histograms in LDS (about ne <= 590; else CSX_EINVAL).  The first call on a handle also finds max(A) (synchronous) and
  * allocates its partial images.  Asynchronous on `stream`. */
 csx_status csx_forward_energy(csx_geometry *h, const float *f, float *gE, void *stream);
 

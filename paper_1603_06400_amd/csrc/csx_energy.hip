@@ -113,7 +113,7 @@ csx_status ensure_state(csx_geometry *h, bool forward)
     if (forward) {
         int lds = 0;
         const size_t need = csx_forward_energy_floats(h, &lds);
-        if (lds > 65536) return csx_fail(CSX_EINVAL, "energy-resolved forward: ne too large for LDS");
+        if (lds > CSX_LDS_MAX) return csx_fail(CSX_EINVAL, "energy-resolved forward: ne too large for LDS");
         if (need > s->part_cap) {
             if (s->part) HIP_TRY(hipFree(s->part));
             s->part = nullptr;

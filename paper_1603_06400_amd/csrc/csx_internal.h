@@ -13,6 +13,7 @@
 #define CSX_MAX_MASK_ROWS 4096
 #define CSX_MAX_MASK_PERIOD 32
 #define CSX_SUM_BLOCKS 256
+#define CSX_LDS_MAX (160 * 1024)   // LDS bytes one workgroup may use on gfx950
 
 csx_status csx_fail(csx_status s, const std::string &msg);
 

@@ -686,28 +686,41 @@ __global__ void __launch_bounds__(512) k_forward_energy(KParams P, DevTables T, 
 }
 
 // Energy-resolved adjoint with the Phi-weighted data staged in LDS: a block
-// of 16 waves (one voxel each) walks the pixel-class tiles together; for each
-// 8 x 8 tile of classes (a, upper row r) the block copies Psi[k][pixel] of the
-// tile's 128 pixels (rows bu and bd) for every bin k into LDS, slot u * 64 +
-// lane, so a lane reads its two pixels' values at a triple's bin from LDS.
-constexpr int EA_WAVES = 16;
-
-template <int QW, int QU>
-__global__ void __launch_bounds__(1024) k_adjoint_energy_tiled(KParams P, DevTables T, Lds L,
+// of waves (one voxel group each: voxel j and, with LR, its mirror j2) walks
+// the pixel-class tiles together; for each 8 x 8 tile of classes (a, upper
+// row r) the block copies Psi[k][pixel] of the tile's pixels for every bin k
+// into LDS, slot = set * 64 + lane with sets u = (bu, a), d = (bd, a) and,
+// with LR, (bu, -a), (bd, -a); a lane then reads its class's pixel values at
+// a triple's bin from LDS.
+template <int LR, int QW, int QU>
+__global__ void __launch_bounds__(LR ? 512 : 1024) k_adjoint_energy_tiled(KParams P, DevTables T, Lds L,
                                                                const double *__restrict__ qa,
                                                                const double2 *__restrict__ qblk,
                                                                const float *__restrict__ psi,
                                                                float *__restrict__ b)
 {
     constexpr int NB = QW / 8;
+    constexpr int NSET = LR ? 4 : 2;
+    constexpr int SLOTS = 64 * NSET;
     extern __shared__ __align__(16) unsigned char lds[];
     uint32_t *s_bits = (uint32_t *)(lds + L.mask);
     float *s_psi = (float *)(lds + L.tile);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int k = threadIdx.x; k < P.mask_ny; k += blockDim.x) s_bits[k] = T.maskbits[k];
     const int NE2 = P.ne + 2;
-    const int j = blockIdx.x * EA_WAVES + wv;
-    const bool von = j < P.nvox;
+    const int g = blockIdx.x * (blockDim.x >> 6) + wv;
+    const bool von = g < P.n_groups;
+    int j = 0, j2 = 0;
+    if (von) {
+        if (LR) {
+            const int half = P.nx / 2;
+            j = (g / half) * P.nx + g % half;
+            j2 = (g / half) * P.nx + (P.nx - 1 - g % half);
+        } else {
+            j = g;
+            j2 = g;
+        }
+    }
     VoxD vd = {0.0, 1.0, 1.0, 0.0};
     float2 vf = {0.0f, 0.0f}, vm = {0.0f, 0.0f};
     if (von) {
@@ -720,33 +733,36 @@ __global__ void __launch_bounds__(1024) k_adjoint_energy_tiled(KParams P, DevTab
     const double2 *qb_c = qblk + blockIdx.y * NB;
     const double b0 = P.b0;
     const uint32_t top = (uint32_t)(P.ne + 1);
-    float acc[QW];
+    float acc0[QW], acc1[QW];
 #pragma unroll
-    for (int m = 0; m < QW; ++m) acc[m] = 0.0f;
+    for (int m = 0; m < QW; ++m) {
+        acc0[m] = 0.0f;
+        acc1[m] = 0.0f;
+    }
     const int half_y = P.ndy / 2;
     const int ntx = (P.ndx + 7) / 8;
     const int ntiles = ntx * ((half_y + 7) / 8);
-    // staging: thread = one pixel slot (u or d row of a class) and every
-    // (blockDim / 128)-th bin
-    const int slot = threadIdx.x & 127, kstep = blockDim.x >> 7;
-    const int sc_ = slot & 63;
     for (int t = 0; t < ntiles; ++t) {
         const int ta = (t % ntx) * 8, tr = (t / ntx) * 8;
         __syncthreads();
-        {
-            const int a = ta + (sc_ & 7), r = tr + (sc_ >> 3);
+        // staging: thread = pixel slots slot0, slot0 + blockDim, ... and every bin
+        for (int slot = threadIdx.x % SLOTS; slot < SLOTS; slot += blockDim.x) {
+            const int c = slot & 63, set = slot >> 6;
+            const int a = ta + (c & 7), r = tr + (c >> 3);
             const bool valid = a < P.ndx && r < half_y;
             const int bu = half_y + r;
-            const int row = (slot >> 6) ? P.ndy - 1 - bu : bu;
-            const float *src = psi + (valid ? row * P.ndx + a : 0);
-            for (int k = threadIdx.x >> 7; k < NE2; k += kstep)
-                s_psi[(k << 7) + slot] = valid ? src[(size_t)k * P.npix] : 0.0f;
+            const int row = (set & 1) ? P.ndy - 1 - bu : bu;
+            const int col = (set & 2) ? P.ndx - 1 - a : a;
+            const float *src = psi + (valid ? row * P.ndx + col : 0);
+            const int k0 = threadIdx.x / SLOTS, kstep = max(1, (int)blockDim.x / SLOTS);
+            for (int k = k0; k < NE2; k += kstep) s_psi[k * SLOTS + slot] = valid ? src[(size_t)k * P.npix] : 0.0f;
+            if ((int)blockDim.x >= SLOTS) break;
         }
         __syncthreads();
         if (!von) continue;
         const int a = ta + (lane & 7), r = tr + (lane >> 3);
         double kap = 0.0;
-        float eu = 0.0f, ed = 0.0f;
+        float eu = 0.0f, ed = 0.0f, ebu = 0.0f, ebd = 0.0f;
         bool act = false;
         if (a < P.ndx && r < half_y) {
             const int bu = half_y + r;
@@ -754,14 +770,18 @@ __global__ void __launch_bounds__(1024) k_adjoint_energy_tiled(KParams P, DevTab
             const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
             const Cells c = mask_cells(P, vm, xp, yp);
             if (c.in_rows) {
-                const float tu = bitf(s_bits[c.row_u], c.col_a), td = bitf(s_bits[c.row_d], c.col_a);
-                if (tu + td != 0.0f) {
+                const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
+                const float tu = bitf(ru, c.col_a), td = bitf(rd, c.col_a);
+                const float tbu = LR ? bitf(ru, c.col_b) : 0.0f, tbd = LR ? bitf(rd, c.col_b) : 0.0f;
+                if (tu + td + tbu + tbd != 0.0f) {
                     double k;
                     float A;
                     pair_factors(P, vd, vf, (double)xp, (double)yp, k, A);
                     if (in_band(P, k)) {
                         eu = A * tu;
                         ed = A * td;
+                        ebu = A * tbu;
+                        ebd = A * tbd;
                         kap = k;
                         act = true;
                     }
@@ -769,7 +789,12 @@ __global__ void __launch_bounds__(1024) k_adjoint_energy_tiled(KParams P, DevTab
             }
         }
         if (__ballot(act) == 0) continue;
-        const float *pu = s_psi + lane, *pd = s_psi + 64 + lane;
+        const float *ps = s_psi + lane;
+        auto node = [&](int m, uint32_t kk) {
+            const float *row = ps + kk * SLOTS;
+            acc0[m] = fmaf(eu, row[0], fmaf(ed, row[64], acc0[m]));
+            if (LR) acc1[m] = fmaf(ebu, row[128], fmaf(ebd, row[192], acc1[m]));
+        };
         if (QU) {
             const double u0 = fma(kap, P.a0 + P.da * m0, b0), du = kap * P.da;
             int lo = QW, hi = -1;
@@ -781,10 +806,9 @@ __global__ void __launch_bounds__(1024) k_adjoint_energy_tiled(KParams P, DevTab
                 double u = fma((double)(blk * 8), du, u0);
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
-                    const int m = blk * 8 + mm;
                     const uint32_t kk = min((uint32_t)(int)u, top);
                     u += du;
-                    acc[m] = fmaf(eu, pu[kk << 7], fmaf(ed, pd[kk << 7], acc[m]));
+                    node(blk * 8 + mm, kk);
                 }
             }
         } else {
@@ -794,20 +818,21 @@ __global__ void __launch_bounds__(1024) k_adjoint_energy_tiled(KParams P, DevTab
                 const bool need = act && kap * qr.y >= P.band_lo && kap * qr.x < P.band_hi;
                 if (__ballot(need) == 0) continue;
 #pragma unroll
-                for (int mm = 0; mm < 8; ++mm) {
-                    const int m = blk * 8 + mm;
-                    const uint32_t kk = spec_index(kap, qa_c[m], b0, top);
-                    acc[m] = fmaf(eu, pu[kk << 7], fmaf(ed, pd[kk << 7], acc[m]));
-                }
+                for (int mm = 0; mm < 8; ++mm) node(blk * 8 + mm, spec_index(kap, qa_c[blk * 8 + mm], b0, top));
             }
         }
     }
     if (!von) return;
-    WaveTransposeSum<QW, 32>::run(acc, lane);
+    WaveTransposeSum<QW, 32>::run(acc0, lane);
+    if (LR) WaveTransposeSum<QW, 32>::run(acc1, lane);
     const int mi = transposed_index<QW>(lane);
     const int m = m0 + mi;
     const bool writer = (lane & ((64 / QW) - 1)) == 0;
-    if (writer && m < P.nq) b[(size_t)j * P.nq + m] = acc[0] * T.qv[m];
+    if (writer && m < P.nq) {
+        const float qm = T.qv[m];
+        b[(size_t)j * P.nq + m] = acc0[0] * qm;
+        if (LR) b[(size_t)j2 * P.nq + m] = acc1[0] * qm;
+    }
 }
 
 // Batched launches: the blocks of several scans in one grid.  Block b belongs
@@ -985,18 +1010,25 @@ struct RunAdjE {
     }
 };
 
-// Launch shape of the energy-resolved forward: q chunks of <= 32 (the LDS
-// also holds the 8 waves' histograms), and enough voxel splits for ~2048
-// blocks.
+// Launch shape of the energy-resolved forward: the widest q chunk whose LDS
+// (q f tile plus the 8 waves' histograms) fits, and enough voxel splits for
+// ~2048 blocks.
 OpShape forward_energy_shape(const csx_geometry *h)
 {
     OpShape S;
     S.P = h->P;
-    S.P.qw = S.P.nq <= 16 ? 16 : 32;
-    S.P.qchunks = (S.P.nq + S.P.qw - 1) / S.P.qw;
-    S.L = lds_layout(S.P, true);
-    S.L.hist = (S.L.total + 15) & ~15;
-    S.L.total = S.L.hist + 8 * 4 * (S.P.ne + 2) * 8;
+    S.P.qw = S.P.nq <= 16 ? 16 : (S.P.nq <= 32 ? 32 : 64);
+    auto lay = [&]() {
+        S.P.qchunks = (S.P.nq + S.P.qw - 1) / S.P.qw;
+        S.L = lds_layout(S.P, true);
+        S.L.hist = (S.L.total + 15) & ~15;
+        S.L.total = S.L.hist + 8 * 4 * (S.P.ne + 2) * 8;
+    };
+    lay();
+    while (S.L.total > CSX_LDS_MAX && S.P.qw > 16) {   // narrower q chunks leave room for the histograms
+        S.P.qw /= 2;
+        lay();
+    }
     const int ntiles = fwd_tiles(S.P);
     const int bx = (S.P.n_quad + 7) / 8;
     const int splits = std::max(1, std::min(std::min(16, ntiles), 2048 / std::max(1, bx * S.P.qchunks)));
@@ -1024,7 +1056,7 @@ csx_status csx_launch_forward_energy(csx_geometry *h, const float *f, const doub
     const OpShape S = forward_energy_shape(h);
     const size_t n = (size_t)h->P.ne * h->P.npix;
     if ((size_t)S.nparts * n > part_cap) return csx_fail(CSX_EINVAL, "energy partials too small");
-    if (S.L.total > 65536) return csx_fail(CSX_EINVAL, "energy-resolved forward: ne too large for LDS");
+    if (S.L.total > CSX_LDS_MAX) return csx_fail(CSX_EINVAL, "energy-resolved forward: ne too large for LDS");
     dispatch<RunFwdE>(S.variant, S, h, f, part, sc, s);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, S.nparts, (int)n, gE);
@@ -1034,33 +1066,40 @@ csx_status csx_launch_forward_energy(csx_geometry *h, const float *f, const doub
 
 csx_status csx_launch_adjoint_energy(csx_geometry *h, const float *psi, float *b, hipStream_t s)
 {
-    {   // staged form when a tile of Psi fits in LDS
+    {   // staged form when a tile of Psi fits in LDS (gfx950: up to 160 KiB per block)
         KParams P = h->P;
-        P.qw = P.nq <= 16 ? 16 : 32;
+        P.qw = P.nq <= 16 ? 16 : 32;   // (64-q chunks measured no faster: 2 waves / SIMD)
         P.qchunks = (P.nq + P.qw - 1) / P.qw;
-        Lds L;
-        L.phi = 0;
-        L.mask = 0;
-        L.tile = ((P.mask_ny * 4) + 15) & ~15;
-        L.total = L.tile + (P.ne + 2) * 128 * 4;
-        if (L.total <= 48 * 1024) {
-            const dim3 grid((P.nvox + EA_WAVES - 1) / EA_WAVES, P.qchunks);
-            const dim3 block(64 * EA_WAVES);
-            if (P.qw == 16) {
-                if (P.qu)
-                    hipLaunchKernelGGL((k_adjoint_energy_tiled<16, 1>), grid, block, L.total, s, P, h->t, L,
-                                       h->t.qa, h->t.qblk, psi, b);
-                else
-                    hipLaunchKernelGGL((k_adjoint_energy_tiled<16, 0>), grid, block, L.total, s, P, h->t, L,
-                                       h->t.qa, h->t.qblk, psi, b);
-            } else {
-                if (P.qu)
-                    hipLaunchKernelGGL((k_adjoint_energy_tiled<32, 1>), grid, block, L.total, s, P, h->t, L,
-                                       h->t.qa, h->t.qblk, psi, b);
-                else
-                    hipLaunchKernelGGL((k_adjoint_energy_tiled<32, 0>), grid, block, L.total, s, P, h->t, L,
-                                       h->t.qa, h->t.qblk, psi, b);
+        auto layout = [&](int nset) {
+            Lds L;
+            L.phi = 0;
+            L.mask = 0;
+            L.tile = ((P.mask_ny * 4) + 15) & ~15;
+            L.total = L.tile + (P.ne + 2) * 64 * nset * 4;
+            return L;
+        };
+        const bool lr = P.lr && layout(4).total <= CSX_LDS_MAX;
+        const Lds L = layout(lr ? 4 : 2);
+        if (L.total <= CSX_LDS_MAX) {
+            const int wpb = lr ? 8 : 16;      // waves per block (VGPRs: LR keeps two accumulator sets)
+            const int groups = lr ? P.n_groups : P.nvox;
+            if (!lr) {
+                P.lr = 0;
+                P.n_groups = P.nvox;
             }
+            const dim3 grid((groups + wpb - 1) / wpb, P.qchunks);
+            const dim3 block(64 * wpb);
+#define CSX_EA(LR_, QW_, QU_) \
+    hipLaunchKernelGGL((k_adjoint_energy_tiled<LR_, QW_, QU_>), grid, block, L.total, s, P, h->t, L, h->t.qa, \
+                       h->t.qblk, psi, b)
+            if (lr) {
+                if (P.qw == 16) { if (P.qu) CSX_EA(1, 16, 1); else CSX_EA(1, 16, 0); }
+                else { if (P.qu) CSX_EA(1, 32, 1); else CSX_EA(1, 32, 0); }
+            } else {
+                if (P.qw == 16) { if (P.qu) CSX_EA(0, 16, 1); else CSX_EA(0, 16, 0); }
+                else { if (P.qu) CSX_EA(0, 32, 1); else CSX_EA(0, 32, 0); }
+            }
+#undef CSX_EA
             HIP_TRY(hipGetLastError());
             return CSX_OK;
         }

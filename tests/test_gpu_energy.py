@@ -39,6 +39,8 @@ CASES = [
     (3, 12, 11, 14, 18, 80, 402.57, (-37.3, 41.1), 64),  # three 32-q chunks (forward), two (adjoint)
     (13, 34, 7, 22, 8, 70, 403.93, (-40.0, 40.0), 64),   # mirror path, voxel pairs beyond one batch
     (15, 16, 16, 16, 16, 8, 404.13, (-40.0, 40.0), 128),  # mirror path, 8 q nodes, 128 energy bins
+    (16, 10, 9, 12, 10, 24, 402.57, (-40.0, 40.0), 400),  # 400 bins: narrower forward chunks, unstaged adjoint
+    (17, 9, 8, 11, 10, 20, 404.77, (-37.3, 41.1), 300),  # 300 bins without the mirror: staged 2-pixel tiles
 ]
 
 
@@ -163,8 +165,8 @@ def test_energy_recon_matches_oracle(oracle_mod):
 
 def test_energy_errors():
     w, g, f, y = workload_data("slice32")
-    # 256 energy bins: the forward's histograms do not fit in LDS
-    g2 = g.with_(phi=inputs.kramers_histogram(256))
+    # 1024 energy bins: the forward's histograms do not fit in LDS
+    g2 = g.with_(phi=inputs.kramers_histogram(1024))
     geo = csx.Geometry(g2)
     with pytest.raises(csx.CsxError) as ei:
         geo.forward_energy(dev(f))
