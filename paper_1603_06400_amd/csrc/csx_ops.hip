@@ -392,12 +392,27 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
         load_vox(t0);
     }
 
+    // The energy-integrating forward double-buffers the q f tile (the next
+    // tile is written into the idle buffer after the current one is used: one
+    // block barrier per tile); the energy mode, whose histograms also live in
+    // LDS, keeps one buffer and two barriers.
+    constexpr bool DB = !EN;
+    constexpr int TBUF = QW * TS;
+    auto put_tile = [&](float *dst) {
+#pragma unroll
+        for (int k = 0; k < NPASS; ++k) dst[sm * TS + sr + k * RSTEP] = pre[k];
+    };
     float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
     for (int t = t0; t < t1; ++t) {
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < NPASS; ++k) s_tile[sm * TS + sr + k * RSTEP] = pre[k];
-        __syncthreads();
+        float *tile = s_tile + (DB ? ((t - t0) & 1) * TBUF : 0);
+        if (!DB) {
+            __syncthreads();
+            put_tile(tile);
+            __syncthreads();
+        } else if (t == t0) {
+            put_tile(tile);
+            __syncthreads();
+        }
         const VoxD vd = nvd;
         const float2 vf = nvf, vm = nvm;
         const bool valid = nvalid;
@@ -405,6 +420,9 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
             stage_load(t + 1);
             load_vox(t + 1);
         }
+        // the tile's work; a `continue` below leaves this block only, so the
+        // staging of the next tile and its barrier are reached by every thread
+        do {
         if (!wave_on) continue;
 
         // the lane's two classes: pixel column a (class 1) and its mirror (class 2)
@@ -462,7 +480,7 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
         }
         if (__ballot(act1 || act2) == 0) continue;
         float w1a = 0.0f, w1b = 0.0f, w2a = 0.0f, w2b = 0.0f;
-        const float *trow = s_tile + lane * RPG;
+        const float *trow = tile + lane * RPG;
         // EN: the current run of each class (bin 0 is a pad: no run yet)
         uint32_t cur1 = 0u, cur2 = 0u;
         float r1a = 0.0f, r1b = 0.0f, r2a = 0.0f, r2b = 0.0f;
@@ -601,6 +619,11 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
             o1 = fmaf(c21, w2b, o1);
             o2 = fmaf(c22, w2a, o2);
             o3 = fmaf(c23, w2a, o3);
+        }
+        } while (0);
+        if (DB) {
+            if (t + 1 < t1) put_tile(s_tile + ((t + 1 - t0) & 1) * TBUF);
+            __syncthreads();
         }
     }
     if (!wave_on) return;
@@ -903,7 +926,10 @@ __global__ void __launch_bounds__(64) k_sum_ratio_list(const float *__restrict__
     }
 }
 
-Lds lds_layout(const KParams &P, bool forward)
+// LDS of an operator launch: spectrum table, mask bits and, for the forward,
+// the q f tile (two buffers for the energy-integrating forward, one for the
+// energy-resolved one).
+Lds lds_layout(const KParams &P, bool forward, bool energy = false)
 {
     auto al = [](int v) { return (v + 15) & ~15; };
     Lds L;
@@ -913,7 +939,7 @@ Lds lds_layout(const KParams &P, bool forward)
     L.mask = off;
     off += al(P.mask_ny * 4);
     L.tile = off;
-    if (forward) off += P.qw * (64 * (P.lr ? 2 : 1) + 2) * 4;
+    if (forward) off += (energy ? 1 : 2) * P.qw * (64 * (P.lr ? 2 : 1) + 2) * 4;
     L.total = off;
     return L;
 }
@@ -1020,7 +1046,7 @@ OpShape forward_energy_shape(const csx_geometry *h)
     S.P.qw = S.P.nq <= 16 ? 16 : (S.P.nq <= 32 ? 32 : 64);
     auto lay = [&]() {
         S.P.qchunks = (S.P.nq + S.P.qw - 1) / S.P.qw;
-        S.L = lds_layout(S.P, true);
+        S.L = lds_layout(S.P, true, true);
         S.L.hist = (S.L.total + 15) & ~15;
         S.L.total = S.L.hist + 8 * 4 * (S.P.ne + 2) * 8;
     };
