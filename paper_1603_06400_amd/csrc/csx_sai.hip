@@ -128,6 +128,42 @@ __device__ __forceinline__ void stage_mask(const KParams &P, const DevTables &T,
     for (int k = threadIdx.x; k < P.mask_ny; k += blockDim.x) s_bits[k] = T.maskbits[k];
 }
 
+// The pair's half-angle sine and weight A in float32 only (the interpolated
+// operators with linear nodes need no float64 angle: a float32 angle moves an
+// interpolated value by far less than the float32 rounding of the sums).
+// Same identities as pair_factors: sin^2(theta/2) = |r x r'|^2 / (2 |r||s|
+// (|r||s| + r.s)), dtheta = atan(pitch |s_xz| / (|s|^2 - pitch^2/4)).
+__device__ __forceinline__ void pair_factors_f(const KParams &P, const VoxD &vd, float2 vf, float xp, float yp,
+                                               float &sh, float &A)
+{
+    const float x = (float)vd.x, z = (float)vd.z, R2 = (float)vd.R2;
+    const float sx = xp - x, sz = P.det_z - z;
+    const float h2 = fmaf(sx, sx, sz * sz);
+    const float s2 = fmaf(yp, yp, h2);
+    const float dot = fmaf(x, sx, z * sz);
+    const float cy = fmaf(z, xp, -x * P.det_z);
+    const float cross2 = fmaf(yp * yp, R2, cy * cy);
+    const float Rs = __builtin_amdgcn_sqrtf(R2 * s2);
+    const float den = 2.0f * Rs * (Rs + dot);
+    const float K2 = den * __builtin_amdgcn_rcpf(cross2);   // 1 / sin^2(theta/2)
+    sh = __builtin_amdgcn_rsqf(K2);
+    const float inv_s = __builtin_amdgcn_rsqf(s2);
+    const float God = vf.y * inv_s * inv_s * inv_s;
+    const float cos_t = dot * __builtin_amdgcn_rcpf(Rs);
+    const float cos_h = __builtin_amdgcn_sqrtf(0.5f * (1.0f + cos_t));
+    const float num = P.pitch * __builtin_amdgcn_sqrtf(h2);
+    const float dnm = s2 - P.hp2;
+    const float tq = num * __builtin_amdgcn_rcpf(dnm);
+    float dth;
+    if (dnm > 0.0f && tq < 0.05f) {
+        const float t2 = tq * tq;
+        dth = tq * fmaf(t2, fmaf(t2, 0.2f, -1.0f / 3.0f), 1.0f);
+    } else {
+        dth = atan2f(num, dnm);
+    }
+    A = vf.x * God * dth * fmaf(cos_t, cos_t, 1.0f) * cos_h * K2;
+}
+
 // Interpolation node(s) of an angle: u = theta (nt - 1) / theta_max, from
 // float32 arithmetic (error below 2e-4 spacings).  The nearest-node rule
 // settles angles within 2e-3 spacings of a midpoint exactly: theta is past
@@ -157,9 +193,9 @@ __device__ __forceinline__ void nodes(float u, double kappa, const double *__res
 // has s <= 0.35 (theta <= 41 degrees) the odd series of asin through s^15 is
 // used: coefficients (2n)! / (4^n (n!)^2 (2n + 1)), truncation below 1e-9
 // relative; otherwise the library asinf.
-__device__ __forceinline__ float angle_of(const KParams &P, double kappa)
+__device__ __forceinline__ float angle_of_sine(float s)
 {
-    const float s = fminf((float)P.hc * __builtin_amdgcn_rcpf((float)kappa), 1.0f);
+    s = fminf(s, 1.0f);
     if (__ballot(s > 0.35f) != 0) return 2.0f * asinf(s);
     const float x = s * s;
     float p = 143.0f / 10240.0f;
@@ -170,6 +206,28 @@ __device__ __forceinline__ float angle_of(const KParams &P, double kappa)
     p = fmaf(p, x, 3.0f / 40.0f);
     p = fmaf(p, x, 1.0f / 6.0f);
     return 2.0f * fmaf(s * x, p, s);
+}
+
+__device__ __forceinline__ float angle_of(const KParams &P, double kappa)
+{
+    return angle_of_sine((float)P.hc * __builtin_amdgcn_rcpf((float)kappa));
+}
+
+// One pair of a class: its angle's node coordinate u (for `nodes`), float64
+// kappa (the nearest-node rule's midpoint test; 0 with linear nodes) and A.
+template <int INTERP>
+__device__ __forceinline__ void sai_pair(const KParams &P, const VoxD &vd, float2 vf, float xp, float yp,
+                                         float inv_dth, float &u, double &kappa, float &A)
+{
+    if (INTERP == 0) {
+        pair_factors(P, vd, vf, (double)xp, (double)yp, kappa, A);
+        u = angle_of(P, kappa) * inv_dth;
+    } else {
+        float sh;
+        pair_factors_f(P, vd, vf, xp, yp, sh, A);
+        kappa = 0.0;
+        u = angle_of_sine(sh) * inv_dth;
+    }
 }
 
 // W at the nodes t0 (and t0 + 1) of one lane's column of a tiled W block
@@ -235,11 +293,11 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
             }
             if (tau + tad + tbu + tbd != 0.0f) {
                 double k;
-                float A;
-                pair_factors(P, vd, vf, (double)xpa, (double)yp, k, A);
+                float A, u;
+                sai_pair<INTERP>(P, vd, vf, xpa, yp, inv_dth, u, k, A);
                 int n0;
                 float w0, w1;
-                nodes<INTERP>(angle_of(P, k) * inv_dth, k, smid, nt, n0, w0, w1);
+                nodes<INTERP>(u, k, smid, nt, n0, w0, w1);
                 const float wa = interp_w<INTERP>(Wj, n0, w0, w1);
                 o0 = fmaf(A * tau, wa, o0);
                 o1 = fmaf(A * tad, wa, o1);
@@ -262,11 +320,11 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
             }
             if (tau + tad + tbu + tbd != 0.0f) {
                 double k;
-                float A;
-                pair_factors(P, vd, vf, -(double)xpa, (double)yp, k, A);
+                float A, u;
+                sai_pair<INTERP>(P, vd, vf, -xpa, yp, inv_dth, u, k, A);
                 int n0;
                 float w0, w1;
-                nodes<INTERP>(angle_of(P, k) * inv_dth, k, smid, nt, n0, w0, w1);
+                nodes<INTERP>(u, k, smid, nt, n0, w0, w1);
                 const float wa = interp_w<INTERP>(Wj, n0, w0, w1);
                 const float wb = interp_w<INTERP>(Wm, n0, w0, w1);
                 // pixel (-a) seen from voxel j is pixel (a) seen from the mirror voxel
@@ -370,11 +428,11 @@ __global__ void __launch_bounds__(256) k_adjoint_sai(KParams P, DevTables T, Lds
         }
         if (w0 == 0.0f && w1 == 0.0f) continue;
         double k;
-        float A;
-        pair_factors(P, vd, vf, (double)xp, (double)yp, k, A);
+        float A, u;
+        sai_pair<INTERP>(P, vd, vf, xp, yp, inv_dth, u, k, A);
         int n0;
         float u0, u1;
-        nodes<INTERP>(angle_of(P, k) * inv_dth, k, smid, nt, n0, u0, u1);
+        nodes<INTERP>(u, k, smid, nt, n0, u0, u1);
         const float c0 = A * w0, c1 = A * w1;
         atomicAdd(&h0[n0], fixed_of(c0 * u0, sexp));
         if (INTERP) atomicAdd(&h0[n0 + 1], fixed_of(c0 * u1, sexp));
