@@ -163,6 +163,25 @@ def test_energy_recon_matches_oracle(oracle_mod):
     assert torch.equal(f2, fd)
 
 
+def test_energy_zero_inputs_and_one_bin(oracle_mod):
+    """All-zero image and data (the fixed-point bound is 0) give exact zeros;
+    a one-bin spectrum makes the energy-resolved operators the
+    energy-integrating ones."""
+    w, g, f, y = workload_data("slice32")
+    geo = csx.Geometry(g)
+    assert np.all(host(geo.forward_energy(geo.new_image().zero_())) == 0)
+    assert np.all(host(geo.backproject_energy(torch.zeros((g.ne, g.ndy, g.ndx), device="cuda"))) == 0)
+    g1 = g.with_(phi=np.array([1.0]), e_lo=20.0, e_hi=160.0)
+    o1 = oracle_mod.Oracle(g1)
+    geo1 = csx.Geometry(g1)
+    assert geo1.ne == 1
+    ge = host(geo1.forward_energy(dev(f)))
+    assert_parity(ge, o1.forward_energy(f), what="forward_energy ne=1")
+    assert rel_l2(ge[0], host(geo1.forward(dev(f)))) <= 2e-6
+    ye = energy_data(g1, 11)
+    assert_parity(host(geo1.backproject_energy(dev(ye))), o1.adjoint_energy(ye), what="adjoint_energy ne=1")
+
+
 def test_energy_errors():
     w, g, f, y = workload_data("slice32")
     # 1024 energy bins: the forward's histograms do not fit in LDS

@@ -72,6 +72,38 @@ def test_sai_table_sizes_slice32(oracle_mod, nt):
     assert_parity(host(geo.backproject_sai(dev(y))), o.adjoint_sai(y, nt, tm, 1), what=f"adjoint_sai nt={nt}")
 
 
+@pytest.mark.parametrize("interp", ["linear", "nearest"])
+@pytest.mark.parametrize("tm", [0.3, float(np.pi / 6)])
+def test_sai_table_narrower_than_the_angles(oracle_mod, interp, tm):
+    """An explicit theta_max: 0.3 rad, below the 32^2 slice's largest pair
+    angle (0.334 rad), so that pairs beyond it take the last node on both
+    sides, and the paper's pi/6, a table wider than the angles."""
+    w, g, f, y = workload_data("slice32")
+    o = oracle_mod.Oracle(g)
+    assert (o.max_angle() > tm) == (tm < 0.33)
+    geo = csx.Geometry(g)
+    geo.sai_config(250, interp, tm)
+    assert geo.sai_info()["theta_max"] == tm
+    it = 1 if interp == "linear" else 0
+    assert_parity(host(geo.forward_sai(dev(f))), o.forward_sai(f, 250, tm, it), what="forward_sai clamp")
+    assert_parity(host(geo.backproject_sai(dev(y))), o.adjoint_sai(y, 250, tm, it), what="adjoint_sai clamp")
+
+
+def test_sai_many_q_nodes(oracle_mod):
+    """160 q nodes: the matrix-core products run a ragged K (W = f s^T) and a
+    ragged N and K split (b = V s)."""
+    g = ragged_geometry(31, 10, 9, 12, 10, 160, 402.57, x=(-40.0, 40.0))
+    o = oracle_mod.Oracle(g)
+    assert o.margins()["mask_edge_mm"] > 1e-4
+    geo = csx.Geometry(g)
+    tm = o.max_angle()
+    geo.sai_config(97, "linear", tm)
+    f = inputs.random_image(g, 51)
+    y = inputs.random_detector(g, 52)
+    assert_parity(host(geo.forward_sai(dev(f))), o.forward_sai(f, 97, tm, 1), what="forward_sai nq=160")
+    assert_parity(host(geo.backproject_sai(dev(y))), o.adjoint_sai(y, 97, tm, 1), what="adjoint_sai nq=160")
+
+
 def test_sai_theta_max_covers_every_pair(oracle_mod):
     for name in ["slice32", "slice128"]:
         w, g, f, y = workload_data(name)
