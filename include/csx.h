@@ -246,6 +246,14 @@ csx_status csx_backproject_energy(csx_geometry *h, const float *yE, float *b, vo
 csx_status csx_recon_energy(csx_geometry *h, const float *yE, const float *rE, float *f, int init_uniform,
                             int n_iter, double beta, double *J_hist, void *stream);
 
+/* Measurement helper (not part of the method): the float32 FMA issue rate of
+ * the current device in lane-operations per second, from one timed launch of
+ * independent FMA chains filling every SIMD (after one warm-up launch).  The
+ * operators' roofline fraction is quoted against the published rate (256 CUs
+ * x 4 SIMDs x 16 lanes x 2.4 GHz) and against this measured one.  Allocates
+ * and frees a small output buffer; synchronises `stream`. */
+csx_status csx_valu_peak(double *lane_ops_per_s, void *stream);
+
 /* Launch shape of a handle's operators; a tuner may change it (results do not
  * depend on it beyond float32 summation order).
  *   fwd_splits: the forward's voxel range is split over this many block rows

@@ -66,7 +66,7 @@ EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_g
            "csx_conv3x3_backward_weights", "csx_warm_loss", "csx_adam_step", "csx_to_half",
            "csx_warm_input", "csx_warm_output", "csx_warm_target", "csx_warm_start", "csx_recon_warm",
            "csx_sai_config", "csx_sai_info", "csx_forward_sai", "csx_backproject_sai", "csx_set_operator",
-           "csx_forward_energy", "csx_backproject_energy", "csx_recon_energy"]
+           "csx_forward_energy", "csx_backproject_energy", "csx_recon_energy", "csx_valu_peak"]
 
 
 class _WarmNet(ctypes.Structure):
@@ -124,6 +124,8 @@ def lib():
         L.csx_recon_energy.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        ctypes.POINTER(ctypes.c_double), vp]
         L.csx_recon_energy.restype = ctypes.c_int
+        L.csx_valu_peak.argtypes = [ctypes.POINTER(ctypes.c_double), vp]
+        L.csx_valu_peak.restype = ctypes.c_int
         L.csx_get_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
         L.csx_get_launch.restype = ctypes.c_int
         L.csx_set_launch.argtypes = [vp, ctypes.POINTER(_Launch)]
@@ -515,6 +517,13 @@ def to_half(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
         raise ValueError("size mismatch")
     _check(lib().csx_to_half(_img(x, torch.float32, "x"), _img(y, torch.float16, "y"), x.numel(), _stream()))
     return y
+
+
+def valu_peak() -> float:
+    """Measured float32 FMA issue rate of the current GPU (lane-ops/s)."""
+    v = ctypes.c_double()
+    _check(lib().csx_valu_peak(ctypes.byref(v), _stream()))
+    return v.value
 
 
 class Batch:

@@ -243,3 +243,13 @@ def test_sparse_masks_sampled(oracle_mod, name):
     yr = inputs.random_detector(g, 3)
     bb = host(geo.backproject(dev(yr))).reshape(g.nvox, g.nq)
     assert_parity(bb[vox], o.adjoint_voxels(yr, vox), what="adjoint sampled")
+
+
+def test_valu_peak_probe():
+    """The FMA-chain probe the roofline quotes beside the published rate: at
+    most the non-packed FP32 issue rate (256 CUs x 4 SIMDs x 16 lanes x
+    2.4 GHz), and at least a third of it (a whole-chip launch)."""
+    spec = 256 * 4 * 16 * 2.4e9
+    v = csx.valu_peak()
+    print(f"VALU FMA-chain rate {v / 1e12:.2f} T lane-ops/s ({v / spec:.3f} of {spec / 1e12:.2f})")
+    assert spec / 3 < v <= 1.02 * spec
