@@ -279,6 +279,22 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
     }
 }
 
+// Logical block of a forward launch.  The hardware deals blocks to the
+// eight XCDs round-robin by linear id; the renumbering gives each XCD a
+// contiguous share of the (quad group, q chunk, tile split) grid, with the
+// split slowest and the q chunk next, so an XCD fetches into its own L2 only
+// the part of f that its splits and q chunks cover.
+__device__ __forceinline__ void xcd_block(int &bx, int &by, int &bz)
+{
+    const int gx = gridDim.x, gz = gridDim.z, total = gx * gridDim.y * gz;
+    int lin = blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z);
+    if (total % 8 == 0) lin = (lin % 8) * (total / 8) + lin / 8;
+    bx = lin % gx;
+    const int r = lin / gx;
+    bz = r % gz;
+    by = r / gz;
+}
+
 // ---------------------------------------------------------------------------
 // forward: one wave per output group (the four mirror pixels (+-x', +-y') with
 // LR, else the two pixels (x', +-y')) and q chunk; lane = voxel group (64 per
@@ -681,8 +697,9 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
                                                  const float *__restrict__ f,
                                                  float *__restrict__ part, int tiles_per_split)
 {
-    forward_body<LR, QW, QU>(P, T, L, qa, qblk, f, part, tiles_per_split, blockIdx.x,
-                                 blockIdx.y, blockIdx.z, gridDim.z);
+    int bx, by, bz;
+    xcd_block(bx, by, bz);
+    forward_body<LR, QW, QU>(P, T, L, qa, qblk, f, part, tiles_per_split, bx, by, bz, gridDim.z);
 }
 
 // Energy-resolved operators (the energy-sensitive detector of App. A).
@@ -704,8 +721,9 @@ __global__ void __launch_bounds__(512) k_forward_energy(KParams P, DevTables T, 
                                                         float *__restrict__ part, int tiles_per_split,
                                                         const double *__restrict__ sc)
 {
-    forward_body<LR, QW, QU, 1>(P, T, L, qa, qblk, f, part, tiles_per_split, blockIdx.x, blockIdx.y,
-                                blockIdx.z, gridDim.z, sc);
+    int bx, by, bz;
+    xcd_block(bx, by, bz);
+    forward_body<LR, QW, QU, 1>(P, T, L, qa, qblk, f, part, tiles_per_split, bx, by, bz, gridDim.z, sc);
 }
 
 // Energy-resolved adjoint with the Phi-weighted data staged in LDS: a block
@@ -1163,10 +1181,12 @@ csx_launch csx_default_launch(const KParams &P)
     lc.fwd_qw = qw;
     lc.adj_qw = qw;
     const int qchunks = (P.nq + qw - 1) / qw;
-    // split the voxel tiles so that a forward launch holds >= ~8 waves per SIMD
+    // split the voxel tiles so that a forward launch holds >= ~8 waves per SIMD,
+    // and into at least 8 ranges: with the XCD-aware block numbering each XCD
+    // then reads one eighth of f into its L2
     const int bx = (P.n_quad + 7) / 8;
     const int target_waves = 8 * 4 * 256;
-    int splits = std::max(1, target_waves / std::max(1, bx * 8 * qchunks));
+    int splits = std::max(8, target_waves / std::max(1, bx * 8 * qchunks));
     splits = std::min(splits, std::max(1, fwd_tiles(P) / 2));
     lc.fwd_splits = std::min(splits, 64);
     return lc;
