@@ -207,6 +207,22 @@ __device__ __forceinline__ void band_range(const KParams &P, double u0, double d
     hi = (int)h;
 }
 
+// Logical block of a forward launch (exact or interpolated).  The hardware deals blocks to the
+// eight XCDs round-robin by linear id; the renumbering gives each XCD a
+// contiguous share of the (quad group, q chunk, tile split) grid, with the
+// split slowest and the q chunk next, so an XCD fetches into its own L2 only
+// the part of f that its splits and q chunks cover.
+__device__ __forceinline__ void xcd_block(int &bx, int &by, int &bz)
+{
+    const int gx = gridDim.x, gz = gridDim.z, total = gx * gridDim.y * gz;
+    int lin = blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z);
+    if (total % 8 == 0) lin = (lin % 8) * (total / 8) + lin / 8;
+    bx = lin % gx;
+    const int r = lin / gx;
+    bz = r % gz;
+    by = r / gz;
+}
+
 // 64-bit fixed point of a float contribution v at scale 2^s (|v| 2^s < 2^61):
 // x = v 2^s is exact in float, x = hi 2^32 + lo with lo in [0, 2^32), lo
 // formed by one exact FMA; rounds toward -inf (a deterministic choice).

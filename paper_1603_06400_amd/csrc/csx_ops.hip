@@ -279,22 +279,6 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
     }
 }
 
-// Logical block of a forward launch.  The hardware deals blocks to the
-// eight XCDs round-robin by linear id; the renumbering gives each XCD a
-// contiguous share of the (quad group, q chunk, tile split) grid, with the
-// split slowest and the q chunk next, so an XCD fetches into its own L2 only
-// the part of f that its splits and q chunks cover.
-__device__ __forceinline__ void xcd_block(int &bx, int &by, int &bz)
-{
-    const int gx = gridDim.x, gz = gridDim.z, total = gx * gridDim.y * gz;
-    int lin = blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z);
-    if (total % 8 == 0) lin = (lin % 8) * (total / 8) + lin / 8;
-    bx = lin % gx;
-    const int r = lin / gx;
-    bz = r % gz;
-    by = r / gz;
-}
-
 // ---------------------------------------------------------------------------
 // forward: one wave per output group (the four mirror pixels (+-x', +-y') with
 // LR, else the two pixels (x', +-y')) and q chunk; lane = voxel group (64 per

@@ -251,7 +251,10 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
     stage_mask(P, T, s_bits);
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int quad = blockIdx.x * 8 + wv;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);                     // each XCD reads its splits' tiles of W
+    (void)bz;
+    const int quad = bx * 8 + wv;
     if (quad >= P.n_quad) return;
     const int qq = P.quad_list ? P.quad_list[quad] : quad;   // a pixel subset's quads, or all
     int a, bu;
@@ -268,7 +271,7 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
     const int gw = LR ? P.nx / 2 : P.nx;
     const int ntx = (gw + 7) / 8;
     const int ntiles = ntx * ((P.nz + 7) / 8);
-    const int t0 = blockIdx.y * tiles_per_split;
+    const int t0 = by * tiles_per_split;
     const int t1 = min(ntiles, t0 + tiles_per_split);
     float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
     for (int t = t0; t < t1; ++t) {
@@ -345,7 +348,7 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
         }
     }
     if (lane == 0) {
-        float *dst = part + (size_t)blockIdx.y * P.npix;
+        float *dst = part + (size_t)by * P.npix;
         const int bd = P.ndy - 1 - bu;
         dst[bu * P.ndx + a] = o0;
         dst[bd * P.ndx + a] = o1;
