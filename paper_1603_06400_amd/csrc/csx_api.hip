@@ -206,6 +206,27 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
         P.qu = uni ? 1 : 0;
         P.a0 = d->q[0] / dE;
         P.da = dq / dE;
+        // Bin coordinates u = kappa q/dE + b0 of the uniform-grid operators: an
+        // idle lane holds b0 (kappa = 0); a lane in band has kappa < band_hi/q_min
+        // (the band test), so at any node up to the last padded one u stays
+        // below band_hi/q_min * q_top/dE + b0.  Zero pads around the table
+        // cover that range (two entries of margin each side for rounding); if
+        // they would not fit, the generic path (clamped index per node) runs.
+        P.spec_lo = 0;
+        P.spec_n = d->ne + 2;
+        if (uni) {
+            const double q_top = d->q[0] + dq * (nqp - 1);
+            const double u_hi = P.band_hi / qmin * (q_top / dE) + P.b0;
+            const double lo = std::floor(P.b0) - 2.0, hi = std::floor(u_hi) + 2.0;
+            const bool fits = qmin > 0.0 && std::isfinite(u_hi) && lo > -CSX_SPEC_MAX && hi < CSX_SPEC_MAX &&
+                              std::max(0.0, -lo) + std::max((double)d->ne + 1.0, hi) + 1.0 <= CSX_SPEC_MAX;
+            if (fits) {
+                P.spec_lo = std::max(0, (int)-lo);
+                P.spec_n = P.spec_lo + std::max(d->ne + 1, (int)hi) + 1;
+            } else {
+                P.qu = 0;
+            }
+        }
     }
     std::vector<double> qa(nqp, 0.0);
     std::vector<float> qv(nqp, 0.0f);

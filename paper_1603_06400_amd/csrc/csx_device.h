@@ -104,14 +104,19 @@ __device__ __forceinline__ uint32_t spec_index(double kappa, double qa, double b
     return min(k, top);
 }
 
-__device__ __forceinline__ void stage_tables(const KParams &P, const DevTables &T, float *s_phi,
+// Spectrum table and mask bits into LDS.  s_tab receives the P.spec_n-entry
+// padded table: entry k of the zero-padded spectrum [0, ne+1] at position
+// P.spec_lo + k, zeros around it.
+__device__ __forceinline__ void stage_tables(const KParams &P, const DevTables &T, float *s_tab,
                                              uint32_t *s_bits)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    if (P.td == CSX_TABLE_BF16) {
-        for (int k = tid; k < P.ne + 2; k += nt) s_phi[k] = bf16_to_f32(T.phi16[k]);
-    } else {
-        for (int k = tid; k < P.ne + 2; k += nt) s_phi[k] = T.phi32[k];
+    const bool b16 = P.td == CSX_TABLE_BF16;
+    for (int k = tid; k < P.spec_n; k += nt) {
+        const int e = k - P.spec_lo;
+        float v = 0.0f;
+        if (e >= 0 && e < P.ne + 2) v = b16 ? bf16_to_f32(T.phi16[e]) : T.phi32[e];
+        s_tab[k] = v;
     }
     for (int k = tid; k < P.mask_ny; k += nt) s_bits[k] = T.maskbits[k];
 }

@@ -14,6 +14,7 @@
 #define CSX_MAX_MASK_PERIOD 32
 #define CSX_SUM_BLOCKS 256
 #define CSX_LDS_MAX (160 * 1024)   // LDS bytes one workgroup may use on gfx950
+#define CSX_SPEC_MAX 2048          // largest padded spectrum table in LDS (floats)
 
 csx_status csx_fail(csx_status s, const std::string &msg);
 
@@ -39,6 +40,11 @@ struct KParams {
     double band_lo, band_hi;    // class in band iff kappa q_max >= band_lo and kappa q_min < band_hi
     double b0;                  // 1 - e_lo/dE: table index = floor(kappa q/dE + b0)
     int qu;                     // 1: uniform q grid q_m = q_0 + m dq
+    // spectrum table in LDS: spec_n floats, entry k of the zero-padded table
+    // [0, ne+1] at position spec_lo + k, zeros elsewhere; with a uniform grid
+    // the pads cover every bin coordinate a wave can reach, so its reads need
+    // no clamp
+    int spec_lo, spec_n;
     double a0, da;              // q_0/dE and dq/dE of a uniform grid
     double q_min, q_max;
     float half_my;

@@ -59,11 +59,11 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
 {
     constexpr int NB = QW / 8;
     extern __shared__ __align__(16) unsigned char lds[];
-    float *s_phi = (float *)(lds + L.phi);
+    float *s_phi = (float *)(lds + L.phi) + P.spec_lo;   // entry 0 of the padded table
     uint32_t *s_bits = (uint32_t *)(lds + L.mask);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
-    stage_tables(P, T, s_phi, s_bits);
+    stage_tables(P, T, (float *)(lds + L.phi), s_bits);
     __syncthreads();
     const int g = bx * (blockDim.x >> 6) + wv;
     if (g >= P.n_groups) return;
@@ -230,14 +230,17 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
-                    const uint32_t kk = min((uint32_t)(int)u, top);
+                    // the table's pads cover every coordinate: no clamp unless
+                    // the bin indexes the energy data
+                    const int ku = (int)u;
+                    const uint32_t kk = min((uint32_t)ku, top);
                     u += du;
                     if (EN) {
                         en_node(kk);
                         acc0[m] += v0;
                         if (LR) acc1[m] += v1;
                     } else {
-                        const float ph = spec(s_phi, kk);
+                        const float ph = s_phi[ku];
                         acc0[m] = fmaf(c0, ph, acc0[m]);
                         if (LR) acc1[m] = fmaf(c1, ph, acc1[m]);
                     }
@@ -309,12 +312,12 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
     constexpr int RSTEP = 512 / QW;             // rows staged per pass
     constexpr int NPASS = ROWS / RSTEP;
     extern __shared__ __align__(16) unsigned char lds[];
-    float *s_phi = (float *)(lds + L.phi);
+    float *s_phi = (float *)(lds + L.phi) + P.spec_lo;   // entry 0 of the padded table
     uint32_t *s_bits = (uint32_t *)(lds + L.mask);
     float *s_tile = (float *)(lds + L.tile);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
-    stage_tables(P, T, s_phi, s_bits);
+    stage_tables(P, T, (float *)(lds + L.phi), s_bits);
     const int NE2 = P.ne + 2;
     unsigned long long *hist = EN ? (unsigned long long *)(lds + L.hist) + (size_t)wv * 4 * NE2 : nullptr;
     if (EN)
@@ -549,12 +552,16 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
                     const int m = blk * 8 + mm;
-                    const uint32_t i1 = min((uint32_t)(int)ua, top);
-                    const float p1 = spec(s_phi, i1);
+                    // the table's pads cover every coordinate: no clamp unless
+                    // the bin keys an energy histogram
+                    const int c1 = (int)ua;
+                    const uint32_t i1 = min((uint32_t)c1, top);
+                    const float p1 = EN ? spec(s_phi, i1) : s_phi[c1];
                     ua += du1;
                     if (LR) {
-                        const uint32_t i2 = min((uint32_t)(int)ub, top);
-                        const float p2 = spec(s_phi, i2);
+                        const int c2 = (int)ub;
+                        const uint32_t i2 = min((uint32_t)c2, top);
+                        const float p2 = EN ? spec(s_phi, i2) : s_phi[c2];
                         ub += du2;
                         const float2 fv = *(const float2 *)(trow + m * TS);
                         if (EN) {
@@ -937,7 +944,7 @@ Lds lds_layout(const KParams &P, bool forward, bool energy = false)
     Lds L;
     int off = 0;
     L.phi = off;
-    off += al((P.ne + 2) * 4);
+    off += al(P.spec_n * 4);
     L.mask = off;
     off += al(P.mask_ny * 4);
     L.tile = off;

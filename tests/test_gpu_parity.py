@@ -253,3 +253,29 @@ def test_valu_peak_probe():
     v = csx.valu_peak()
     print(f"VALU FMA-chain rate {v / 1e12:.2f} T lane-ops/s ({v / spec:.3f} of {spec / 1e12:.2f})")
     assert spec / 3 < v <= 1.02 * spec
+
+
+@pytest.mark.parametrize("lr", [True, False])
+@pytest.mark.parametrize("case", ["high_e_lo", "q_near_zero"])
+def test_uniform_q_spectrum_pads(oracle_mod, case, lr):
+    """Uniform q grids at the ends of the padded spectrum table.  The uniform-grid
+    operators read the table at the bin coordinate kappa q/dE + b0 without a
+    clamp, from zero pads sized by the band test.  A high e_lo puts b0 far below
+    0 (a long lower pad); q_min near 0 makes the implied upper pad exceed the
+    table limit, and the clamped generic path runs instead."""
+    x = (-40.0, 40.0) if lr else (-37.3, 41.1)
+    g = ragged_geometry(41 + lr, 12, 10, 14, 12, 40, 402.57, x=x)
+    if case == "high_e_lo":
+        g = g.with_(e_lo=60.0, e_hi=160.0, phi=inputs.kramers_histogram(64, 60.0, 160.0))
+    else:
+        g = g.with_(q=np.linspace(0.02, 3.5, 40))
+    o = oracle_mod.Oracle(g)
+    assert o.margins()["mask_edge_mm"] > 1e-5
+    geo = csx.Geometry(g)
+    assert geo.info()["symmetric_lr"] == int(lr)
+    f = inputs.random_image(g, 51)
+    y = np.random.Generator(np.random.PCG64(52)).uniform(0.0, 1.0, (g.ndy, g.ndx))
+    ref = o.forward(f)
+    assert np.count_nonzero(ref) > ref.size // 4
+    assert_parity(host(geo.forward(dev(f))), ref, what=f"forward {case}")
+    assert_parity(host(geo.backproject(dev(y))), o.adjoint(y), what=f"adjoint {case}")
