@@ -898,9 +898,14 @@ __global__ void __launch_bounds__(512) k_forward_batch(const CsxJob *__restrict_
 {
     const int jb = find_job(begin, njobs, blockIdx.x);
     const CsxJob &J = jobs[jb];
-    const int local = blockIdx.x - begin[jb];
-    const int bx = local % J.gx, by = (local / J.gx) % J.gy, bz = local / (J.gx * J.gy);
-    forward_body<LR, QW, QU>(J.P, J.T, J.L, J.T.qa, J.T.qblk, J.in, J.out, J.tps, bx, by, bz,
+    // within each job, the XCD-aware numbering of the single-scan forward: the
+    // job's blocks on XCD x (= blockIdx.x mod 8, round-robin dispatch) take the
+    // x-th eighth of its (quad group, q chunk, split) grid, split slowest
+    int local = blockIdx.x - begin[jb];
+    const int n = J.gx * J.gy * J.gz;
+    if (n % 8 == 0) local = (int)(blockIdx.x % 8) * (n / 8) + local / 8;
+    const int bx = local % J.gx, r = local / J.gx;
+    forward_body<LR, QW, QU>(J.P, J.T, J.L, J.T.qa, J.T.qblk, J.in, J.out, J.tps, bx, r / J.gz, r % J.gz,
                                  J.gz);
 }
 
