@@ -221,10 +221,10 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
             const double u0 = fma(kap, P.a0 + P.da * m0, b0), du = kap * P.da;
             int lo = QW, hi = -1;
             if (act) band_range(P, u0, du, 0, QW, lo, hi);
-            const int wlo = wave_min(lo), whi = wave_max(hi);
 #pragma unroll
             for (int blk = 0; blk < NB; ++blk) {
-                if (blk * 8 + 7 < wlo || blk * 8 > whi) continue;
+                // skip a block no lane of the wave has in band (its triples add exact zeros)
+                if (__ballot(lo <= blk * 8 + 7 && hi >= blk * 8) == 0) continue;
                 // anchored by an FMA at each 8-node block, then one add per node
                 double u = fma((double)(blk * 8), du, u0);
 #pragma unroll
@@ -543,10 +543,10 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
                 lo = min(lo, l2);
                 hi = max(hi, h2);
             }
-            const int wlo = wave_min(lo), whi = wave_max(hi);
 #pragma unroll
             for (int blk = 0; blk < NB; ++blk) {
-                if (blk * 8 + 7 < wlo || blk * 8 > whi) continue;
+                // skip a block no lane of the wave has in band (its triples add exact zeros)
+                if (__ballot(lo <= blk * 8 + 7 && hi >= blk * 8) == 0) continue;
                 // anchored by an FMA at each 8-node block, then one add per node
                 double ua = fma((double)(blk * 8), du1, u10), ub = fma((double)(blk * 8), du2, u20);
 #pragma unroll
@@ -831,10 +831,10 @@ __global__ void __launch_bounds__(LR ? 512 : 1024) k_adjoint_energy_tiled(KParam
             const double u0 = fma(kap, P.a0 + P.da * m0, b0), du = kap * P.da;
             int lo = QW, hi = -1;
             if (act) band_range(P, u0, du, 0, QW, lo, hi);
-            const int wlo = wave_min(lo), whi = wave_max(hi);
 #pragma unroll
             for (int blk = 0; blk < NB; ++blk) {
-                if (blk * 8 + 7 < wlo || blk * 8 > whi) continue;
+                // skip a block no lane of the wave has in band (its triples add exact zeros)
+                if (__ballot(lo <= blk * 8 + 7 && hi >= blk * 8) == 0) continue;
                 double u = fma((double)(blk * 8), du, u0);
 #pragma unroll
                 for (int mm = 0; mm < 8; ++mm) {
