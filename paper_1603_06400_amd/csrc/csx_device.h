@@ -59,21 +59,26 @@ __device__ __forceinline__ void pair_factors(const KParams &P, const VoxD &vd, f
     const double dot = x * sx + z * sz;
     const double cy = z * xp - x * P.det_zd;
     const double cross2 = yp * yp * R2 + cy * cy;
+    // square roots from one float reciprocal square root y ~ 1/sqrt(v) each:
+    // sqrt(v) ~ v y, refined by one float64 Newton step (relative error of
+    // order 1e-14); y itself serves as 1/sqrt(v) in the float32 factors
     const double Rs2 = R2 * s2;
-    const float rs0 = __builtin_amdgcn_sqrtf((float)Rs2);
-    const double Rs = (double)rs0 + (Rs2 - (double)rs0 * (double)rs0) * (double)(0.5f * __builtin_amdgcn_rcpf(rs0));
+    const float yr = __builtin_amdgcn_rsqf((float)Rs2);
+    const float rs0 = (float)Rs2 * yr;
+    const double Rs = (double)rs0 + (Rs2 - (double)rs0 * (double)rs0) * (double)(0.5f * yr);
     const double den = 2.0 * Rs * (Rs + dot);
     const float r0 = __builtin_amdgcn_rcpf((float)cross2);
     const double inv = (double)r0 * (2.0 - cross2 * (double)r0);
     const double K2 = den * inv;   // 1 / sin^2(theta/2)
-    const float k0 = __builtin_amdgcn_sqrtf((float)K2);
-    const double k = (double)k0 + (K2 - (double)k0 * (double)k0) * (double)(0.5f * __builtin_amdgcn_rcpf(k0));
+    const float yk = __builtin_amdgcn_rsqf((float)K2);
+    const float k0 = (float)K2 * yk;
+    const double k = (double)k0 + (K2 - (double)k0 * (double)k0) * (double)(0.5f * yk);
     kappa = P.hc * k;
 
     const float s2f = (float)s2;
     const float inv_s = __builtin_amdgcn_rsqf(s2f);
     const float God = vf.y * inv_s * inv_s * inv_s;
-    const float cos_t = (float)dot * __builtin_amdgcn_rcpf((float)Rs);
+    const float cos_t = (float)dot * yr;
     const float cos_h = __builtin_amdgcn_sqrtf(0.5f * (1.0f + cos_t));
     const float num = P.pitch * __builtin_amdgcn_sqrtf((float)h2);
     const float dnm = s2f - P.hp2;
@@ -204,8 +209,10 @@ __device__ __forceinline__ int wave_max(int v)
 __device__ __forceinline__ void band_range(const KParams &P, double u0, double du, int m0, int qw,
                                            int &lo, int &hi)
 {
-    const float fu0 = (float)u0, fdu = (float)du;
-    const float a = (1.0f - fu0) / fdu, b = ((float)P.ne + 1.0f - fu0) / fdu;
+    // a float bound with one node of margin each side: the reciprocal's
+    // rounding (and that of the float coordinates) stays far inside it
+    const float fu0 = (float)u0, r = __builtin_amdgcn_rcpf((float)du);
+    const float a = (1.0f - fu0) * r, b = ((float)P.ne + 1.0f - fu0) * r;
     const float l = fmaxf(floorf(a) - 1.0f - (float)m0, -1.0f);
     const float h = fminf(floorf(b) + 1.0f - (float)m0, (float)qw);
     lo = (int)l;

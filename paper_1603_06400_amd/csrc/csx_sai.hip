@@ -143,13 +143,14 @@ __device__ __forceinline__ void pair_factors_f(const KParams &P, const VoxD &vd,
     const float dot = fmaf(x, sx, z * sz);
     const float cy = fmaf(z, xp, -x * P.det_z);
     const float cross2 = fmaf(yp * yp, R2, cy * cy);
-    const float Rs = __builtin_amdgcn_sqrtf(R2 * s2);
+    const float Rs2 = R2 * s2, yr = __builtin_amdgcn_rsqf(Rs2);   // 1 / (|r| |s|)
+    const float Rs = Rs2 * yr;
     const float den = 2.0f * Rs * (Rs + dot);
     const float K2 = den * __builtin_amdgcn_rcpf(cross2);   // 1 / sin^2(theta/2)
     sh = __builtin_amdgcn_rsqf(K2);
     const float inv_s = __builtin_amdgcn_rsqf(s2);
     const float God = vf.y * inv_s * inv_s * inv_s;
-    const float cos_t = dot * __builtin_amdgcn_rcpf(Rs);
+    const float cos_t = dot * yr;
     const float cos_h = __builtin_amdgcn_sqrtf(0.5f * (1.0f + cos_t));
     const float num = P.pitch * __builtin_amdgcn_sqrtf(h2);
     const float dnm = s2 - P.hp2;
