@@ -67,7 +67,8 @@ __device__ __forceinline__ void pair_factors(const KParams &P, const VoxD &vd, f
     const float rs0 = (float)Rs2 * yr;
     const double Rs = (double)rs0 + (Rs2 - (double)rs0 * (double)rs0) * (double)(0.5f * yr);
     const double den = 2.0 * Rs * (Rs + dot);
-    const float r0 = __builtin_amdgcn_rcpf((float)cross2);
+    const float yc = __builtin_amdgcn_rsqf((float)cross2);     // 1 / |r x s|
+    const float r0 = yc * yc;
     const double inv = (double)r0 * (2.0 - cross2 * (double)r0);
     const double K2 = den * inv;   // 1 / sin^2(theta/2)
     const float yk = __builtin_amdgcn_rsqf((float)K2);
@@ -79,7 +80,8 @@ __device__ __forceinline__ void pair_factors(const KParams &P, const VoxD &vd, f
     const float inv_s = __builtin_amdgcn_rsqf(s2f);
     const float God = vf.y * inv_s * inv_s * inv_s;
     const float cos_t = (float)dot * yr;
-    const float cos_h = __builtin_amdgcn_sqrtf(0.5f * (1.0f + cos_t));
+    // cos(theta/2) = sin(theta) / (2 sin(theta/2)), sin(theta) = |r x s| / (|r| |s|)
+    const float cos_h = 0.5f * ((float)cross2 * yc) * yr * k0;
     const float num = P.pitch * __builtin_amdgcn_sqrtf((float)h2);
     const float dnm = s2f - P.hp2;
     const float tq = num * __builtin_amdgcn_rcpf(dnm);

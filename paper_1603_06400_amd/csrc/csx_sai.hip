@@ -146,12 +146,14 @@ __device__ __forceinline__ void pair_factors_f(const KParams &P, const VoxD &vd,
     const float Rs2 = R2 * s2, yr = __builtin_amdgcn_rsqf(Rs2);   // 1 / (|r| |s|)
     const float Rs = Rs2 * yr;
     const float den = 2.0f * Rs * (Rs + dot);
-    const float K2 = den * __builtin_amdgcn_rcpf(cross2);   // 1 / sin^2(theta/2)
+    const float yc = __builtin_amdgcn_rsqf(cross2);          // 1 / |r x s|
+    const float K2 = den * (yc * yc);                         // 1 / sin^2(theta/2)
     sh = __builtin_amdgcn_rsqf(K2);
     const float inv_s = __builtin_amdgcn_rsqf(s2);
     const float God = vf.y * inv_s * inv_s * inv_s;
     const float cos_t = dot * yr;
-    const float cos_h = __builtin_amdgcn_sqrtf(0.5f * (1.0f + cos_t));
+    // cos(theta/2) = sin(theta) / (2 sin(theta/2)), sin(theta) = |r x s| / (|r| |s|)
+    const float cos_h = 0.5f * (cross2 * yc) * yr * (K2 * sh);
     const float num = P.pitch * __builtin_amdgcn_sqrtf(h2);
     const float dnm = s2 - P.hp2;
     const float tq = num * __builtin_amdgcn_rcpf(dnm);
