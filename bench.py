@@ -91,7 +91,7 @@ def cpu_baseline(g, f, y, n_pix=12288, n_vox=12288, one_core_div=16):
     finally:
         oracle.set_threads(cores)
     return {"value": evals / (tf + ta), "unit": "evals/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_info(), "slice32": oracle_slice32(),
             "sample": f"FP64 oracle: forward at {n_pix} random pixels + adjoint at {n_vox} random "
                       f"voxels of the {WORKLOAD} workload ({evals:.3e} evals, "
                       f"{tf:.1f} s + {ta:.1f} s)",
@@ -99,6 +99,88 @@ def cpu_baseline(g, f, y, n_pix=12288, n_vox=12288, one_core_div=16):
                          "sample": f"forward at {n_pix // one_core_div} + adjoint at "
                                    f"{n_vox // one_core_div} random outputs ({e1:.3e} evals, "
                                    f"{tf1:.1f} s + {ta1:.1f} s)"}}
+
+
+def host_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def oracle_slice32() -> dict:
+    """The FP64 oracle on the whole 32^2 x 32q slice: one forward, one adjoint
+    and the 20-iteration Alg. 5 run from the uniform start, on every host
+    thread."""
+    import oracle
+    from paper_1603_06400_amd import inputs
+    w = inputs.workload("slice32")
+    z = np.load(os.path.join(GOLDEN, "slice32_counts.npz"))
+    g = w.geom.with_(C=float(z["C"]))
+    y = z["y"].astype(np.float64)
+    o = oracle.Oracle(g)
+    f = inputs.phantom(w.geom, w.phantom_seed, w.n_rect)
+    t0 = time.perf_counter()
+    o.forward(f)
+    t1 = time.perf_counter()
+    o.adjoint(y)
+    t2 = time.perf_counter()
+    f0 = oracle.uniform_start(y, o.sensitivity())
+    t3 = time.perf_counter()
+    _, J = o.recon(y, None, f0, w.n_iter, w.beta)
+    t4 = time.perf_counter()
+    return {"forward_s": t1 - t0, "adjoint_s": t2 - t1, "recon_iters": w.n_iter,
+            "recon_s": t4 - t3, "J_last": float(J[-1]),
+            "evals_per_s": 2.0 * g.nvox * g.npix * g.nq / (t2 - t0)}
+
+
+def gpu_slice32(reps: int = 5) -> dict:
+    """The library on the same 32^2 x 32q slice: the 20-iteration Alg. 5 run
+    from the uniform start (uniform start and objectives included), median of
+    reps runs."""
+    import torch
+    from paper_1603_06400_amd import csx, inputs
+    w = inputs.workload("slice32")
+    z = np.load(os.path.join(GOLDEN, "slice32_counts.npz"))
+    g = w.geom.with_(C=float(z["C"]))
+    geo = csx.Geometry(g)
+    y = torch.tensor(z["y"], dtype=torch.float32, device="cuda")
+    f = geo.new_image()
+    geo.recon(y, f, w.n_iter, w.beta)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = geo.recon(y, f, w.n_iter, w.beta)
+        ts.append(time.perf_counter() - t0)
+    return {"recon_iters": w.n_iter, "recon_ms_median": float(np.median(ts)) * 1e3, "J_last": float(J[-1])}
+
+
+def operator_medians(geo, f, y, warm: int = 5, n: int = 50) -> dict:
+    """Forward and adjoint launches one at a time, each bracketed by HIP
+    events on the stream they run on: warm-ups, then the median of n."""
+    import torch
+    gbuf, bbuf = geo.new_detector(), geo.new_image()
+    out = {"warmup": warm, "n": n}
+    for name, fn in (("forward_ms", lambda: geo.forward(f, gbuf)), ("adjoint_ms", lambda: geo.backproject(y, bbuf))):
+        for _ in range(warm):
+            fn()
+        ev = []
+        for _ in range(n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            ev.append((e0, e1))
+        torch.cuda.synchronize()
+        out[name] = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    return out
 
 
 def bench_batch(args):
@@ -527,6 +609,8 @@ def main():
         "roofline": roofline,
         "objective_first_last": [float(Jh[0]), float(Jh[-1])] if args.steps else None,
     }
+    out["operator_median"] = operator_medians(geo, f_d, y_d)
+    out["slice32_gpu"] = gpu_slice32()
     if args.tto_cases > 0:
         tto = time_to_objective(args.tto_cases)
         out["time_to_objective"] = {k: tto[k] for k in ("cases", "target", "ms_plain_mean", "ms_warm_mean",
