@@ -257,7 +257,10 @@ csx_status csx_valu_peak(double *lane_ops_per_s, void *stream);
 /* Launch shape of a handle's operators; a tuner may change it (results do not
  * depend on it beyond float32 summation order).
  *   fwd_splits: the forward's voxel range is split over this many block rows
- *               (1..64); partial images are summed in a fixed order.
+ *               (1..64); partial images are summed in a fixed order.  Blocks
+ *               are numbered so that each of the 8 XCDs takes a contiguous
+ *               share of the splits: with a multiple of 8 each XCD's L2 holds
+ *               only its share of f.  Default: at least 8.
  *   fwd_qw, adj_qw: q lanes per chunk of the forward / adjoint (16, 32 or 64);
  *               nq is covered by ceil(nq / qw) chunks. */
 typedef struct {
