@@ -40,6 +40,11 @@
 
 #include "csx_device.h"
 
+// q nodes per skip block of the uniform-grid loops (adjoint, forward),
+// capped at the chunk width
+constexpr int QB_ADJ = 16;
+constexpr int QB_FWD = 16;
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -221,15 +226,16 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
             const double u0 = fma(kap, P.a0 + P.da * m0, b0), du = kap * P.da;
             int lo = QW, hi = -1;
             if (act) band_range(P, u0, du, 0, QW, lo, hi);
+            constexpr int BA = QB_ADJ < QW ? QB_ADJ : QW;
 #pragma unroll
-            for (int blk = 0; blk < NB; ++blk) {
+            for (int blk = 0; blk < QW / BA; ++blk) {
                 // skip a block no lane of the wave has in band (its triples add exact zeros)
-                if (__ballot(lo <= blk * 8 + 7 && hi >= blk * 8) == 0) continue;
-                // anchored by an FMA at each 8-node block, then one add per node
-                double u = fma((double)(blk * 8), du, u0);
+                if (__ballot(lo <= blk * BA + BA - 1 && hi >= blk * BA) == 0) continue;
+                // anchored by an FMA at each block's first node, then one add per node
+                double u = fma((double)(blk * BA), du, u0);
 #pragma unroll
-                for (int mm = 0; mm < 8; ++mm) {
-                    const int m = blk * 8 + mm;
+                for (int mm = 0; mm < BA; ++mm) {
+                    const int m = blk * BA + mm;
                     // the table's pads cover every coordinate: no clamp unless
                     // the bin indexes the energy data
                     const int ku = (int)u;
@@ -543,15 +549,16 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
                 lo = min(lo, l2);
                 hi = max(hi, h2);
             }
+            constexpr int BF = QB_FWD < QW ? QB_FWD : QW;
 #pragma unroll
-            for (int blk = 0; blk < NB; ++blk) {
+            for (int blk = 0; blk < QW / BF; ++blk) {
                 // skip a block no lane of the wave has in band (its triples add exact zeros)
-                if (__ballot(lo <= blk * 8 + 7 && hi >= blk * 8) == 0) continue;
-                // anchored by an FMA at each 8-node block, then one add per node
-                double ua = fma((double)(blk * 8), du1, u10), ub = fma((double)(blk * 8), du2, u20);
+                if (__ballot(lo <= blk * BF + BF - 1 && hi >= blk * BF) == 0) continue;
+                // anchored by an FMA at each block's first node, then one add per node
+                double ua = fma((double)(blk * BF), du1, u10), ub = fma((double)(blk * BF), du2, u20);
 #pragma unroll
-                for (int mm = 0; mm < 8; ++mm) {
-                    const int m = blk * 8 + mm;
+                for (int mm = 0; mm < BF; ++mm) {
+                    const int m = blk * BF + mm;
                     // the table's pads cover every coordinate: no clamp unless
                     // the bin keys an energy histogram
                     const int c1 = (int)ua;
