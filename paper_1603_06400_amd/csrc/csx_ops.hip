@@ -367,19 +367,34 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
     const int sr = threadIdx.x / QW;
     const float qs = (m0 + sm < P.nq) ? T.qv[m0 + sm] : 0.0f;
     float pre[NPASS];
+    // (raw f values; the q factor is applied when the tile is written to LDS).
+    // A tile and q chunk wholly inside the grid (a block-uniform test) loads
+    // without per-value checks, so the loads issue together and their latency
+    // overlaps the current tile's work.
     auto stage_load = [&](int t) {
         const int tx = t % ntx, ty = t / ntx;
+        if (tx * 8 + 8 <= gw && ty * 8 + 8 <= P.nz && m0 + QW <= P.nq) {
 #pragma unroll
-        for (int k = 0; k < NPASS; ++k) {
-            const int r = sr + k * RSTEP;
-            const int gl = r / RPG;
-            const int ix = tx * 8 + (gl & 7), iz = ty * 8 + (gl >> 3);
-            float v = 0.0f;
-            if (ix < gw && iz < P.nz && m0 + sm < P.nq) {
+            for (int k = 0; k < NPASS; ++k) {
+                const int r = sr + k * RSTEP;
+                const int gl = r / RPG;
+                const int ix = tx * 8 + (gl & 7), iz = ty * 8 + (gl >> 3);
                 const int vox = iz * P.nx + ((LR && (r & 1)) ? (P.nx - 1 - ix) : ix);
-                v = qs * f[(size_t)vox * P.nq + m0 + sm];
+                pre[k] = f[(size_t)vox * P.nq + m0 + sm];
             }
-            pre[k] = v;
+        } else {
+#pragma unroll
+            for (int k = 0; k < NPASS; ++k) {
+                const int r = sr + k * RSTEP;
+                const int gl = r / RPG;
+                const int ix = tx * 8 + (gl & 7), iz = ty * 8 + (gl >> 3);
+                float v = 0.0f;
+                if (ix < gw && iz < P.nz && m0 + sm < P.nq) {
+                    const int vox = iz * P.nx + ((LR && (r & 1)) ? (P.nx - 1 - ix) : ix);
+                    v = f[(size_t)vox * P.nq + m0 + sm];
+                }
+                pre[k] = v;
+            }
         }
     };
     // voxel records of the lane's group, prefetched one tile ahead
@@ -409,7 +424,7 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
     constexpr int TBUF = QW * TS;
     auto put_tile = [&](float *dst) {
 #pragma unroll
-        for (int k = 0; k < NPASS; ++k) dst[sm * TS + sr + k * RSTEP] = pre[k];
+        for (int k = 0; k < NPASS; ++k) dst[sm * TS + sr + k * RSTEP] = qs * pre[k];
     };
     float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
     for (int t = t0; t < t1; ++t) {
