@@ -7,7 +7,7 @@ and the float64 objective, all in the HIP library.  The metric counts the
 nominal voxel*pixel*q evaluations of one forward plus one adjoint
 (2 * 16384 * 16384 * 64 = 3.436e10) per step.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
     python bench.py --workload batch64 [--steps K] [--warmup W]
     python bench.py --workload warm [--tto-cases N]
     python bench.py --workload os [--steps K]
@@ -494,6 +494,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the median operator launches and the 32^2 slice run (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
                          "reference kernel for scaling HBM byte counters")
@@ -609,8 +611,9 @@ def main():
         "roofline": roofline,
         "objective_first_last": [float(Jh[0]), float(Jh[-1])] if args.steps else None,
     }
-    out["operator_median"] = operator_medians(geo, f_d, y_d)
-    out["slice32_gpu"] = gpu_slice32()
+    if not args.no_extras:
+        out["operator_median"] = operator_medians(geo, f_d, y_d)
+        out["slice32_gpu"] = gpu_slice32()
     if args.tto_cases > 0:
         tto = time_to_objective(args.tto_cases)
         out["time_to_objective"] = {k: tto[k] for k in ("cases", "target", "ms_plain_mean", "ms_warm_mean",
