@@ -809,7 +809,13 @@ __global__ void __launch_bounds__(LR ? 512 : 1024) k_adjoint_energy_tiled(KParam
             const int col = (set & 2) ? P.ndx - 1 - a : a;
             const float *src = psi + (valid ? row * P.ndx + col : 0);
             const int k0 = threadIdx.x / SLOTS, kstep = max(1, (int)blockDim.x / SLOTS);
-            for (int k = k0; k < NE2; k += kstep) s_psi[k * SLOTS + slot] = valid ? src[(size_t)k * P.npix] : 0.0f;
+            // unconditional loads (an invalid slot reads pixel 0 and stores 0),
+            // two in flight at a time
+#pragma unroll 2
+            for (int k = k0; k < NE2; k += kstep) {
+                const float v = src[(size_t)k * P.npix];
+                s_psi[k * SLOTS + slot] = valid ? v : 0.0f;
+            }
             if ((int)blockDim.x >= SLOTS) break;
         }
         __syncthreads();
