@@ -41,8 +41,15 @@ SRC = os.path.join(ROOT, "paper_1603_06400_amd", "csrc", "csx_ops.hip")
 
 
 def source_hash() -> str:
-    with open(SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the operator source's code (comments and whitespace removed), so
+    that the stored counters follow code changes but not comment edits."""
+    import re
+    with open(SRC, encoding="utf-8") as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def algorithmic_ops(census: dict) -> float:

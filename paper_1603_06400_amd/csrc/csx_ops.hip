@@ -16,26 +16,33 @@
 //  * lane = class.  Each lane evaluates its class's factors once and keeps
 //    kappa and the pair weights in its own registers; the q loop then runs
 //    inside the lane (fully unrolled over a chunk of <= 64 q), so no lane ever
-//    waits on a value another lane produced.  The per-q step is one FP64 add
-//    for the Bragg bin coordinate (an FMA anchors it at every 8th node), an
-//    unsigned clamp, a gather from the spectrum table in LDS and FP32 FMAs;
-//    on a non-uniform q grid q/dE comes from scalar loads.
-//  * blocks of 8 q nodes are skipped, uniformly for the wave, when no lane's
-//    Bragg energies kappa q can reach the spectrum band there.
+//    waits on a value another lane produced.  On a uniform q grid the per-q
+//    step is one FP64 add for the Bragg bin coordinate (an FMA anchors it at
+//    the first node of each 16-node block), its conversion to an integer, a
+//    gather from the spectrum table in LDS and FP32 FMAs; the table carries
+//    zero pads wide enough for every coordinate a wave can reach (sized on
+//    the host from the band test), so no clamp is needed.  On a non-uniform
+//    grid q/dE comes from scalar loads and each index is clamped onto the
+//    table's two zero pads.
+//  * q blocks (16 nodes on a uniform grid, 8 otherwise) are skipped, uniformly
+//    for the wave, when no lane's Bragg energies kappa q can reach the
+//    spectrum band there (one ballot per block).
 //  * the spectral bin of a triple is decided in float64 (kappa in float64
 //    from float32 seeds refined by one Newton step each; the bin coordinate
 //    q/dE * kappa + 1 - e_lo/dE by FP64 FMA, or on a uniform grid by an FMA
-//    at every 8th node and FP64 adds between, within 8 ulp): float64
-//    precision, so bin decisions agree with the float64 definition except
-//    within ~1e-13 of a bin edge.
+//    at each block's first node and FP64 adds between): float64 precision,
+//    so bin decisions agree with the float64 definition except within
+//    ~1e-13 of a bin edge.
 //  * adjoint: one wave per voxel (and its x-mirror) walks the pixel classes 64
 //    at a time, accumulating per-lane partial images acc[q]; one butterfly
 //    transpose-reduction per wave sums them over lanes (no atomics).
 //  * forward: one wave per group of mirror pixels; one lane per voxel (pair)
 //    evaluates both mirror classes and accumulates the paper's W(r, theta) =
 //    sum_q S f over the q chunk, reading q f from a q-major LDS tile shared by
-//    the block; the voxel range is split across blocks and the partial images
-//    are summed in a fixed order (bitwise reproducible).
+//    the block (double-buffered, the next tile's loads in flight during the
+//    current one); the voxel range is split across blocks, numbered so that
+//    each XCD reads its own share of f, and the partial images are summed in
+//    a fixed order (bitwise reproducible).
 #include "csx_internal.h"
 
 #include "csx_device.h"
