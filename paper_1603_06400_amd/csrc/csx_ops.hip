@@ -77,7 +77,8 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
 
     stage_tables(P, T, (float *)(lds + L.phi), s_bits);
     __syncthreads();
-    const int g = bx * (blockDim.x >> 6) + wv;
+    // wave-uniform (readfirstlane): the voxel records load into scalar registers
+    const int g = __builtin_amdgcn_readfirstlane(bx * (blockDim.x >> 6) + wv);
     if (g >= P.n_groups) return;
 
     int j, j2;
@@ -339,7 +340,8 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
     const int fx_exp = EN ? scale_exponent(fx_scale) : 0;
     auto fx = [&](float v) -> unsigned long long { return fixed_of(v, fx_exp); };
 
-    const int quad = bx * 8 + wv;               // 8 waves per block
+    // wave-uniform (readfirstlane): the pixel quad's values live in scalar registers
+    const int quad = __builtin_amdgcn_readfirstlane(bx * 8 + wv);   // 8 waves per block
     const bool wave_on = quad < P.n_quad;
     const int qq = wave_on ? (P.quad_list ? P.quad_list[quad] : quad) : 0;
     int a, bu;
