@@ -602,8 +602,10 @@ def main():
         dom, dom_ms, kname = "forward", fwd_ms, "k_forward"
     achieved = ops / (dom_ms * 1e-3)
     measured_peak = csx.valu_peak()
+    traffic = stored_traffic(kname)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": stored_traffic(kname),
+                "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                "traffic_GB_per_s": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9,
                 "ops_per_launch": ops, "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
                 "peak_measured": measured_peak / 1e12, "frac_of_measured": achieved / measured_peak}
 
