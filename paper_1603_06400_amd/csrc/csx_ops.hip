@@ -1337,6 +1337,16 @@ csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int 
     OpShape S = csx_adjoint_shape(h);
     S.P.cls_list = cls;
     S.P.n_cls = n_cls;
+    // a short class list (an ordered subset) gives each wave only a few
+    // tiles: 32-wide q chunks halve the per-wave reduction and the
+    // accumulator registers, which outweighs evaluating each class twice
+    // (the q sums are the same whatever the chunking)
+    if (S.P.qw == 64 && n_cls <= 4 * 64) {
+        S.P.qw = 32;
+        S.P.qchunks = (S.P.nq + 31) / 32;
+        S.grid.y = S.P.qchunks;
+        S.variant = variant_of(S.P);
+    }
     dispatch<RunAdj>(S.variant, S, h, rho, b, s);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
