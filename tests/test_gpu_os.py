@@ -56,6 +56,37 @@ def test_os_ragged_without_mirror(oracle_mod):
     np.testing.assert_allclose(J, ref_J, rtol=1e-5)
 
 
+@pytest.mark.parametrize("lr", [True, False])
+def test_os_wide_q_grid_matches_oracle(oracle_mod, lr):
+    """nq = 40 (64-wide default q chunks): the subset adjoints then run
+    32-wide chunks over their short class lists; the sweeps still follow the
+    oracle, and the subset adjoint equals the full-width one bitwise."""
+    x = (-40.0, 40.0) if lr else (-37.3, 41.1)
+    g = ragged_geometry(7 + lr, 12, 10, 16, 8, 40, 402.57, x=x)
+    o = oracle_mod.Oracle(g)
+    assert o.margins()["mask_edge_mm"] > 1e-5
+    f = np.random.Generator(np.random.PCG64(6)).uniform(0.0, 1.0, size=(g.nz, g.nx, g.nq))
+    y = np.random.Generator(np.random.PCG64(7)).poisson(np.maximum(o.forward(f), 0.0)).astype(np.float64)
+    geo = csx.Geometry(g)
+    assert geo.info()["symmetric_lr"] == int(lr)
+    assert geo.get_launch()["adj_qw"] == 64
+    subs = oracle_mod.os_partition(g.ndy, g.ndx, 2, 4)
+    f0 = oracle_mod.uniform_start(y, o.sensitivity())
+    ref_f, ref_J = o.recon_os(y, None, f0, 2, 1e-3, subs)
+    fd = geo.new_image()
+    J = geo.recon_os(dev(y), fd, 2, 1e-3, 2, 4)
+    assert rel_l2(host(fd), ref_f) <= 1e-4
+    np.testing.assert_allclose(J, ref_J, rtol=1e-5)
+    # the q sums do not depend on the chunk width: forcing 32-wide chunks for
+    # every adjoint gives the same sweeps bit for bit
+    lc = geo.get_launch()
+    geo.set_launch(lc["fwd_splits"], lc["fwd_qw"], 32)
+    f2 = geo.new_image()
+    J2 = geo.recon_os(dev(y), f2, 2, 1e-3, 2, 4)
+    assert torch.equal(f2, fd)
+    assert np.array_equal(J2, J)
+
+
 def test_one_subset_is_the_plain_solver():
     w, g, f, y = workload_data("slice32")
     geo = csx.Geometry(g)
