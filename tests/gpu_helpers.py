@@ -25,11 +25,14 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
 
 
-def assert_parity(got, ref, tol=1e-5, elem_tol=2e-3, what=""):
+def assert_parity(got, ref, tol=1e-5, elem_tol=1e-4, what=""):
     """rel-L2 within tol (the float32-vs-float64 bar), and every element within
     elem_tol of the largest reference magnitude: a guard against a wrong tile or
-    a ragged-tail slip, loose enough for a single float32 spectrum-bin flip
-    (one triple taking a neighbouring bin's flux) in a small element."""
+    a ragged-tail slip.  Spectrum bins and mask cells are decided in float64 on
+    both sides, so no triple changes bin or cell; what remains is float32
+    rounding of the factors and sums, far below 1e-4 of the largest element.
+    Returns the rel-L2 error; the worst element error (relative to the largest
+    reference magnitude) is printed."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     assert got.shape == ref.shape, (what, got.shape, ref.shape)
@@ -39,6 +42,7 @@ def assert_parity(got, ref, tol=1e-5, elem_tol=2e-3, what=""):
     scale = float(np.max(np.abs(ref))) if ref.size else 0.0
     if scale > 0:
         worst = float(np.max(np.abs(got - ref)))
+        print(f"[{what}: rel-L2 {e:.3e}, worst element {worst / scale:.3e} of max]", flush=True)
         assert worst <= elem_tol * scale, f"{what}: max abs err {worst:.3e} > {elem_tol:.0e} * {scale:.3e}"
     else:
         assert np.all(got == 0), what

@@ -155,3 +155,45 @@ def test_autotune_picks_a_valid_shape(oracle_mod, tmp_path):
     assert autotune.load_cache(path) == cache
     o = oracle_mod.Oracle(g)
     assert_parity(host(geo.forward(dev(f))), o.forward(f), what="forward tuned")
+
+
+def test_batch64_shapes_in_a_merged_launch(oracle_mod):
+    """Scans of the 64-scan batched workload at its largest shapes (128^2 x 64 q
+    and 96^2 x 32 q, with a 48^2 x 64 q and a 64^2 x 32 q scan) in one merged
+    batch: every scan bitwise equal to its own csx_recon run, and the two large
+    scans within the float32 bar of the oracle's Alg. 5 after 2 iterations."""
+    beta, n_iter = 1e-3, 2
+    picks = inputs.batch_scans()[:4]      # 48^2 x 64, 128^2 x 64, 96^2 x 32, 64^2 x 32
+    assert [(s.geom.nx, s.geom.nq) for s in picks] == [(48, 64), (128, 64), (96, 32), (64, 32)]
+    geoms, ys = [], []
+    for s in picks:
+        f = inputs.phantom(s.geom, s.phantom_seed, s.n_rect)
+        o1 = oracle_mod.Oracle(s.geom.with_(C=1.0))
+        a1f = o1.forward(f)
+        C = 1e4 / a1f.max()
+        geoms.append(s.geom.with_(C=C))
+        ys.append(inputs.poisson_counts(C * a1f, s.noise_seed))
+        print(f"[batch64 scan {s.geom.nx}^2 x {s.geom.nq} q: counts ready]", flush=True)
+    seq = [csx.Geometry(g) for g in geoms]
+    f_seq, J_seq = [], []
+    for geo, y in zip(seq, ys):
+        f = geo.new_image()
+        J_seq.append(geo.recon(dev(y), f, n_iter, beta))
+        f_seq.append(f)
+    bat = [csx.Geometry(g) for g in geoms]
+    for a, b in zip(seq, bat):
+        lc = a.get_launch()
+        b.set_launch(lc["fwd_splits"], lc["fwd_qw"], lc["adj_qw"])
+    f_bat = [g.new_image() for g in bat]
+    J_bat = csx.Batch(bat).recon([dev(y) for y in ys], f_bat, n_iter, beta)
+    for k in range(len(picks)):
+        assert torch.equal(f_seq[k], f_bat[k]), k
+        np.testing.assert_array_equal(J_seq[k], J_bat[k])
+    for k in (1, 2):
+        o = oracle_mod.Oracle(geoms[k])
+        f0 = oracle_mod.uniform_start(ys[k], o.sensitivity())
+        ref_f, ref_J = o.recon(ys[k], None, f0, n_iter, beta)
+        e = assert_parity(host(f_bat[k]), ref_f, what=f"batched {geoms[k].nx}^2 scan, {n_iter} iterations")
+        dJ = np.max(np.abs(J_bat[k] - ref_J) / ref_J)
+        print(f"batched {geoms[k].nx}^2 x {geoms[k].nq} q: f rel-L2 {e:.3e}, max |dJ|/J {dJ:.3e}")
+        assert dJ <= 1e-6
