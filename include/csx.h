@@ -9,8 +9,10 @@
  *                         mask plane, energy-integrating detector, spectrum),
  *                         with the per-voxel and spectrum tables that Alg. 2's
  *                         "Precompute" lines keep offline.
- *   csx_forward        -- Forward_project: g = A f, eqs. 1-2 (Alg. 1 / Alg. 2).
- *   csx_backproject    -- Back_project: b = A^T y (Alg. 3 / Alg. 4).
+ *   csx_forward        -- Forward_project: g = A f, eqs. 1-2, evaluated exactly
+ *                         as Alg. 1 defines it (no scatter-angle interpolation).
+ *   csx_backproject    -- Back_project: b = A^T y, evaluated exactly as Alg. 3
+ *                         defines it.
  *   csx_recon_step     -- one iteration of the EM-type algorithm (Alg. 5) for
  *                         the Poisson model y_i ~ Poisson((A f)_i + r_i) of
  *                         Sec. V with the penalised objective J = L + beta R,
@@ -112,7 +114,7 @@ void csx_free_geometry(csx_geometry *h);
 
 csx_status csx_get_info(const csx_geometry *h, csx_info *out);
 
-/* Forward_project (Sec. II eqs. 1-2): g_i = sum_j sum_m H(i, j, q_m) f_jm with
+/* Forward_project (Sec. II eqs. 1-2; Alg. 1): g_i = sum_j sum_m H(i, j, q_m) f_jm with
  * H = C Gso God T dtheta S(theta, q).  f: device [nz][nx][nq]; g: device
  * [ndy][ndx], overwritten.  Asynchronous on `stream`. */
 csx_status csx_forward(csx_geometry *h, const float *f, float *g, void *stream);
@@ -130,7 +132,10 @@ csx_status csx_backproject(csx_geometry *h, const float *y, float *b, void *stre
  * (= 0); f: device image, in/out; beta >= 0.  J_out: NULL, or a device double
  * that receives J(f^t) = L(f^t) + beta R(f^t) in float64 (+inf when some
  * y_i > 0 has zero model mean).  The first call on a handle also computes the
- * sensitivity image b1 = A^T 1 and keeps it.  Asynchronous on `stream`. */
+ * sensitivity image b1 = A^T 1 and keeps it.  Asynchronous on `stream`: the
+ * call returns before the data are seen, so it never returns CSX_ENUMERIC;
+ * that condition shows only as J = +inf in *J_out (csx_recon, which
+ * synchronises, returns CSX_ENUMERIC for it). */
 csx_status csx_recon_step(csx_geometry *h, const float *y, const float *r, float *f,
                           double beta, double *J_out, void *stream);
 

@@ -42,6 +42,14 @@ extern "C" csx_status csx_validate_desc(const csx_geometry_desc *d)
         return csx_fail(CSX_EINVAL, "unknown table_dtype");
     if (d->mask_nx > CSX_MAX_MASK_PERIOD || d->mask_ny > CSX_MAX_MASK_ROWS)
         return csx_fail(CSX_EGEOM, "mask must have <= 32 columns and <= 4096 rows");
+    // a mask crossing lies between the voxel and the pixel: its cell indices
+    // are bounded by the extents, kept below 2^21 for exact float conversion
+    {
+        const double ext_x = std::max({std::fabs(d->x_min), std::fabs(d->x_max), 0.5 * d->ndx * d->det_pitch});
+        const double ext_y = 0.5 * d->ndy * d->det_pitch;
+        if (ext_x / d->mask_pitch >= 2097152.0 || ext_y / d->mask_pitch + 0.5 * d->mask_ny >= 2097152.0)
+            return csx_fail(CSX_EGEOM, "mask crossings beyond 2^21 cells");
+    }
     const long nvox = (long)d->nx * d->nz, npix = (long)d->ndx * d->ndy;
     if (nvox * d->nq > (1L << 30) || npix > (1L << 28)) return csx_fail(CSX_EGEOM, "problem too large");
     if (d->ndx > (1 << 20) || d->ndy > (1 << 20)) return csx_fail(CSX_EGEOM, "detector too large");
@@ -179,7 +187,8 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     // per-voxel tables; with the x -> -x mirror the coordinates are mirrored
     // exactly (x of column nx-1-i is -x of column i)
     const int nvox = P.nvox;
-    std::vector<float2> vf(nvox), vm(nvox);
+    std::vector<float2> vf(nvox);
+    std::vector<double2> vm(nvox);
     std::vector<VoxD> vd(nvox);
     const double dx = (d->x_max - d->x_min) / d->nx, dz = (d->z_max - d->z_min) / d->nz;
     for (int iz = 0; iz < d->nz; ++iz)
@@ -192,7 +201,7 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
             const double t = (d->mask_z - z) / (d->det_z - z);
             const int j = iz * d->nx + ix;
             vf[j] = make_float2((float)(d->C * z / (R2 * R)), (float)(d->det_z - z));
-            vm[j] = make_float2((float)(t / d->mask_pitch), (float)((1.0 - t) * x / d->mask_pitch));
+            vm[j] = make_double2(t / d->mask_pitch, (1.0 - t) * x / d->mask_pitch);
             vd[j] = VoxD{x, z, R2, 0.0};
         }
     const int nqp = ((d->nq + 63) / 64) * 64;   // padded for any chunk width dividing 64

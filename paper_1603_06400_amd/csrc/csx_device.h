@@ -144,11 +144,24 @@ __device__ __forceinline__ int fmodp(const KParams &P, float v)
     return (int)fmaf(-(float)P.mask_nx, qf, v);
 }
 
-__device__ __forceinline__ Cells mask_cells(const KParams &P, float2 vm, float xp, float yp)
+// Centre of pixel index a on an axis of n pixels: (a - n/2 + 1/2) * pitch,
+// formed as (2a - n + 1) * (pitch/2), one rounding of the same real product.
+__device__ __forceinline__ double pixel_coord(const KParams &P, int a, int n)
+{
+    return (double)(2 * a - n + 1) * (0.5 * P.pitchd);
+}
+
+// The crossing of ray r -> r' with the mask plane, in cell units:
+// p = (t/pm) r' + ((1-t)/pm) (x, 0), t = (mask_z - z)/(det_z - z) (App. A).
+// The cell is decided in float64 -- the precision of the definition -- so a
+// crossing lands in the same cell as in the float64 evaluation except within
+// float64 rounding (~1e-13 mm) of a cell edge.  vm = {t/pm, (1-t) x/pm}.
+__device__ __forceinline__ Cells mask_cells(const KParams &P, double2 vm, double xp, double yp)
 {
     Cells c;
-    const float cx = floorf(fmaf(vm.x, xp, vm.y));
-    const int cy = (int)floorf(fmaf(vm.x, yp, P.half_my));
+    // |p| < 2^21 cells (validated), so the floors convert exactly
+    const float cx = (float)floor(fma(vm.x, xp, vm.y));
+    const int cy = (int)floor(fma(vm.x, yp, (double)P.half_my));
     c.col_a = fmodp(P, cx);
     c.col_b = fmodp(P, -cx - 1.0f);          // floor(-px) = -floor(px) - 1 off the cell edges
     c.row_u = cy;

@@ -58,14 +58,15 @@ struct KParams {
 };
 
 // Per-voxel records.  vf: {C*Gso, det_z - z} (float32); vm: {t/pm,
-// (1-t) x/pm} with t = (mask_z - z)/(det_z - z); vd: {x, z, x^2+z^2} (float64).
+// (1-t) x/pm} with t = (mask_z - z)/(det_z - z) (float64, the mask-cell
+// decision); vd: {x, z, x^2+z^2} (float64).
 struct VoxD {
     double x, z, R2, pad;
 };
 
 struct DevTables {
     float2 *vf = nullptr;
-    float2 *vm = nullptr;
+    double2 *vm = nullptr;
     VoxD *vd = nullptr;
     double *qa = nullptr;      // [qchunks*qw] q_m/dE (0 beyond nq)
     double2 *qblk = nullptr;   // [qchunks*qw/8] {min q, max q} of each block of 8 nodes

@@ -93,7 +93,7 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
     }
     const VoxD vd = T.vd[j];
     const float2 vf = T.vf[j];
-    const float2 vm = T.vm[j];
+    const double2 vm = T.vm[j];
     const int m0 = by * QW;
     const double *qa_c = qa + m0;
     const double2 *qb_c = qblk + by * NB;
@@ -159,8 +159,8 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
         const float *pu = rho, *pd = rho, *pbu = rho, *pbd = rho;
         if (has) {
             const int bu = half_y + r;
-            const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
-            const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
+            const double xp = pixel_coord(P, a, P.ndx);
+            const double yp = pixel_coord(P, bu, P.ndy);
             const Cells c = mask_cells(P, vm, xp, yp);
             float w0 = 0.0f, w1 = 0.0f;
             float tu = 0.0f, td = 0.0f, tbu = 0.0f, tbd = 0.0f;
@@ -183,7 +183,7 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
             if (w0 != 0.0f || w1 != 0.0f) {
                 double k;
                 float A;
-                pair_factors(P, vd, vf, (double)xp, (double)yp, k, A);
+                pair_factors(P, vd, vf, xp, yp, k, A);
                 if (in_band(P, k)) {
                     c0 = A * w0;
                     c1 = A * w1;
@@ -353,8 +353,8 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
         a = qq % P.ndx;
         bu = P.ndy / 2 + qq / P.ndx;
     }
-    const float xpa = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
-    const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
+    const double xpa = pixel_coord(P, a, P.ndx);
+    const double yp = pixel_coord(P, bu, P.ndy);
     const int qc = bz;
     const int m0 = qc * QW;
     const double *qa_c = qa + m0;
@@ -408,7 +408,8 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
     };
     // voxel records of the lane's group, prefetched one tile ahead
     VoxD nvd = {0.0, 1.0, 1.0, 0.0};
-    float2 nvf = {0.0f, 0.0f}, nvm = {0.0f, 0.0f};
+    float2 nvf = {0.0f, 0.0f};
+    double2 nvm = {0.0, 0.0};
     bool nvalid = false;
     auto load_vox = [&](int t) {
         const int ix = (t % ntx) * 8 + (lane & 7), iz = (t / ntx) * 8 + (lane >> 3);
@@ -447,7 +448,8 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
             __syncthreads();
         }
         const VoxD vd = nvd;
-        const float2 vf = nvf, vm = nvm;
+        const float2 vf = nvf;
+        const double2 vm = nvm;
         const bool valid = nvalid;
         if (t + 1 < t1) {
             stage_load(t + 1);
@@ -479,7 +481,7 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
                 if (tau + tad + tbu + tbd != 0.0f) {
                     double k;
                     float A;
-                    pair_factors(P, vd, vf, (double)xpa, (double)yp, k, A);
+                    pair_factors(P, vd, vf, xpa, yp, k, A);
                     if (in_band(P, k)) {
                         act1 = true;
                         k1 = k;
@@ -501,7 +503,7 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
                 if (tau + tad + tbu + tbd != 0.0f) {
                     double k;
                     float A;
-                    pair_factors(P, vd, vf, -(double)xpa, (double)yp, k, A);
+                    pair_factors(P, vd, vf, -xpa, yp, k, A);
                     if (in_band(P, k)) {
                         act2 = true;
                         k2 = k;
@@ -785,7 +787,8 @@ __global__ void __launch_bounds__(LR ? 512 : 1024) k_adjoint_energy_tiled(KParam
         }
     }
     VoxD vd = {0.0, 1.0, 1.0, 0.0};
-    float2 vf = {0.0f, 0.0f}, vm = {0.0f, 0.0f};
+    float2 vf = {0.0f, 0.0f};
+    double2 vm = {0.0, 0.0};
     if (von) {
         vd = T.vd[j];
         vf = T.vf[j];
@@ -835,8 +838,8 @@ __global__ void __launch_bounds__(LR ? 512 : 1024) k_adjoint_energy_tiled(KParam
         bool act = false;
         if (a < P.ndx && r < half_y) {
             const int bu = half_y + r;
-            const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
-            const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
+            const double xp = pixel_coord(P, a, P.ndx);
+            const double yp = pixel_coord(P, bu, P.ndy);
             const Cells c = mask_cells(P, vm, xp, yp);
             if (c.in_rows) {
                 const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
@@ -845,7 +848,7 @@ __global__ void __launch_bounds__(LR ? 512 : 1024) k_adjoint_energy_tiled(KParam
                 if (tu + td + tbu + tbd != 0.0f) {
                     double k;
                     float A;
-                    pair_factors(P, vd, vf, (double)xp, (double)yp, k, A);
+                    pair_factors(P, vd, vf, xp, yp, k, A);
                     if (in_band(P, k)) {
                         eu = A * tu;
                         ed = A * td;

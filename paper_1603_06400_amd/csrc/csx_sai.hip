@@ -269,8 +269,10 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
         a = qq % P.ndx;
         bu = P.ndy / 2 + qq / P.ndx;
     }
-    const float xpa = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
-    const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
+    const double xpad = pixel_coord(P, a, P.ndx);
+    const double ypd = pixel_coord(P, bu, P.ndy);
+    const float xpa = (float)xpad;
+    const float yp = (float)ypd;
     const int gw = LR ? P.nx / 2 : P.nx;
     const int ntx = (gw + 7) / 8;
     const int ntiles = ntx * ((P.nz + 7) / 8);
@@ -282,11 +284,12 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
         if (ix >= gw || iz >= P.nz) continue;
         const int j = iz * P.nx + ix;
         const VoxD vd = T.vd[j];
-        const float2 vf = T.vf[j], vm = T.vm[j];
+        const float2 vf = T.vf[j];
+        const double2 vm = T.vm[j];
         const float *Wj = W + (((size_t)t * nt) << 6) + lane;
         const float *Wm = LR ? W + (((size_t)(ntiles + t) * nt) << 6) + lane : Wj;
         {
-            const Cells c = mask_cells(P, vm, xpa, yp);
+            const Cells c = mask_cells(P, vm, xpad, ypd);
             float tau = 0.0f, tad = 0.0f, tbu = 0.0f, tbd = 0.0f;
             if (c.in_rows) {
                 const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
@@ -315,7 +318,7 @@ __global__ void __launch_bounds__(512) k_forward_sai(KParams P, DevTables T, Lds
             }
         }
         if (LR) {
-            const Cells c = mask_cells(P, vm, -xpa, yp);
+            const Cells c = mask_cells(P, vm, -xpad, ypd);
             float tau = 0.0f, tad = 0.0f, tbu = 0.0f, tbd = 0.0f;
             if (c.in_rows) {
                 const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
@@ -401,7 +404,8 @@ __global__ void __launch_bounds__(256) k_adjoint_sai(KParams P, DevTables T, Lds
     const double scale = sc[0], inv_scale = sc[1];
     const int sexp = scale_exponent(scale);
     const VoxD vd = T.vd[j];
-    const float2 vf = T.vf[j], vm = T.vm[j];
+    const float2 vf = T.vf[j];
+    const double2 vm = T.vm[j];
     const int half_y = P.ndy / 2;
     const int ntx = (P.ndx + 7) / 8;
     // pixel classes (column a, upper row r): 8 x 8 tiles of the detector, or
@@ -421,9 +425,11 @@ __global__ void __launch_bounds__(256) k_adjoint_sai(KParams P, DevTables T, Lds
             if (a >= P.ndx || r >= half_y) continue;
         }
         const int bu = half_y + r, bd = P.ndy - 1 - bu;
-        const float xp = (float)(2 * a - P.ndx + 1) * (0.5f * P.pitch);
-        const float yp = (float)(2 * bu - P.ndy + 1) * (0.5f * P.pitch);
-        const Cells c = mask_cells(P, vm, xp, yp);
+        const double xpd = pixel_coord(P, a, P.ndx);
+        const double ypd = pixel_coord(P, bu, P.ndy);
+        const float xp = (float)xpd;
+        const float yp = (float)ypd;
+        const Cells c = mask_cells(P, vm, xpd, ypd);
         if (!c.in_rows) continue;
         const uint32_t ru = s_bits[c.row_u], rd = s_bits[c.row_d];
         const float w0 = bitf(ru, c.col_a) * rho[bu * P.ndx + a] + bitf(rd, c.col_a) * rho[bd * P.ndx + a];

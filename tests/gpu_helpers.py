@@ -73,3 +73,54 @@ def ragged_geometry(seed, nx, nz, ndx, ndy, nq, z_min=402.57, ne=64, x=(-37.3, 4
         q=inputs.q_bin_centres(nq), ndx=ndx, ndy=ndy, det_pitch=det_pitch, det_z=800.0,
         mask_z=700.0, mask_pitch=1.0, mask=m, e_lo=20.0, e_hi=160.0,
         phi=inputs.kramers_histogram(ne), C=1e7)
+
+
+def near_edge_geometry(axis, delta, lr):
+    """A ragged geometry whose depth range is solved (at 50 digits) so that the
+    crossing of one ray with the mask plane lies `delta` mm from a cell edge
+    (axis "x": a column edge, "y": a row edge), with the two cells on either
+    side of that edge set to differ: a float32 cell decision (crossing error
+    ~3e-6 mm) would put delta = +-1e-9 on either side at random.  Returns
+    (geometry, (ix, iz, a, b)) with the critical voxel and pixel indices."""
+    import mpmath as mp
+    from fractions import Fraction
+    mp.mp.dps = 50
+    x = (-40.0, 40.0) if lr else (-37.3, 41.1)
+    g = ragged_geometry(61 + lr, 10, 6, 12, 10, 24, 402.57, x=x)
+    nz, dz = g.nz, (g.z_max - g.z_min) / g.nz
+    ix, iz, a, b = 3, 2, 9, 8
+    X = mp.mpf(g.x_min) + (ix + mp.mpf(1) / 2) * (mp.mpf(g.x_max) - mp.mpf(g.x_min)) / g.nx
+    XP = (a - mp.mpf(g.ndx) / 2 + mp.mpf(1) / 2) * g.det_pitch
+    YP = (b - mp.mpf(g.ndy) / 2 + mp.mpf(1) / 2) * g.det_pitch
+    MZ, DZ = mp.mpf(g.mask_z), mp.mpf(g.det_z)
+    Z0 = mp.mpf(g.z_min) + (iz + mp.mpf(1) / 2) * mp.mpf(dz)
+    t0 = (MZ - Z0) / (DZ - Z0)
+    if axis == "x":
+        K = mp.nint((1 - t0) * X + t0 * XP) + mp.mpf(delta)
+        Z = (X * (DZ - MZ) + XP * MZ - K * DZ) / (XP - K)
+    else:
+        K = mp.nint(t0 * YP) + mp.mpf(delta)
+        Z = (K * DZ - MZ * YP) / (K - YP)
+    z_min = float(Z - (iz + mp.mpf(1) / 2) * mp.mpf(dz))
+    g = g.with_(z_min=z_min, z_max=z_min + nz * dz)
+    # exact crossing of the critical ray for the float64 geometry, in cells
+    fz = Fraction(g.z_min) + (iz + Fraction(1, 2)) * (Fraction(g.z_max) - Fraction(g.z_min)) / g.nz
+    fx = Fraction(g.x_min) + (ix + Fraction(1, 2)) * (Fraction(g.x_max) - Fraction(g.x_min)) / g.nx
+    fxp = (a - Fraction(g.ndx, 2) + Fraction(1, 2)) * Fraction(g.det_pitch)
+    fyp = (b - Fraction(g.ndy, 2) + Fraction(1, 2)) * Fraction(g.det_pitch)
+    t = (Fraction(g.mask_z) - fz) / (Fraction(g.det_z) - fz)
+    px = (fx + t * (fxp - fx)) / Fraction(g.mask_pitch)
+    py = t * fyp / Fraction(g.mask_pitch) + Fraction(g.mask_ny, 2)
+    col, row = px.__floor__(), py.__floor__()
+    m = g.mask.copy()
+    if axis == "x":
+        edge = round(px)                 # the two columns meeting at the edge
+        m[row, (edge - 1) % g.mask_nx] = 0
+        m[row, edge % g.mask_nx] = 1
+    else:
+        edge = round(py)
+        m[edge - 1, col % g.mask_nx] = 0
+        m[edge, col % g.mask_nx] = 1
+    g = g.with_(mask=m)
+    T = int(m[row, col % g.mask_nx]) if 0 <= row < g.mask_ny else 0
+    return g, (ix, iz, a, b), T

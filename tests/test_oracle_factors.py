@@ -205,3 +205,17 @@ def test_mask_and_bin_margins_on_workload_lattices(oracle_mod):
     g = inputs.workload("slice32").geom
     mg = oracle_mod.Oracle(g).margins()
     assert mg["mask_edge_mm"] > 1e-3
+
+
+@pytest.mark.parametrize("lr", [0, 1])
+@pytest.mark.parametrize("delta", [1e-9, -1e-9])
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_mask_cell_at_a_near_tie(oracle_mod, axis, delta, lr):
+    """A crossing 1e-9 mm from a cell edge between an open and a closed cell:
+    the oracle's transmission equals the exact rational decision (App. A)."""
+    from .gpu_helpers import near_edge_geometry
+    g, (ix, iz, a, b), T = near_edge_geometry(axis, delta, lr)
+    o = oracle_mod.Oracle(g)
+    assert 5e-10 < o.margins()["mask_edge_mm"] < 2e-9
+    assert T == int(delta > 0)        # the sign of delta picks the open or the closed cell
+    assert o.pair(iz * g.nx + ix, b * g.ndx + a)["T"] == T
