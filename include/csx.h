@@ -119,6 +119,27 @@ csx_status csx_get_info(const csx_geometry *h, csx_info *out);
  * [ndy][ndx], overwritten.  Asynchronous on `stream`. */
 csx_status csx_forward(csx_geometry *h, const float *f, float *g, void *stream);
 
+/* Largest forward partial-image buffer of csx_forward_noalloc, in floats
+ * (4 MiB of device memory per GPU, held from the first csx_init_geometry on
+ * that GPU until the process ends). */
+#define CSX_SCRATCH_FLOATS (1 << 20)
+
+/* csx_forward without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same kernels and the same result, bit for bit, as
+ * csx_forward; the forward's partial images (splits x q chunks x npix
+ * floats, see csx_get_launch) go to a static device array of
+ * CSX_SCRATCH_FLOATS floats instead of the handle's workspace, so the call
+ * makes no hipMalloc / hipFree and records no timing events.  Returns
+ * CSX_EINVAL before any HIP call when the partials exceed CSX_SCRATCH_FLOATS
+ * (lower fwd_splits with csx_set_launch) or an argument is NULL.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams, or two host threads) race and must be serialised by the caller;
+ * no value needs to start at zero (every partial is written before it is
+ * read).  f: device [nz][nx][nq]; g: device [ndy][ndx], overwritten.
+ * Asynchronous on `stream`. */
+csx_status csx_forward_noalloc(const csx_geometry *h, const float *f, float *g, void *stream);
+
 /* Back_project (Alg. 3): b_jm = sum_i H(i, j, q_m) y_i.  y: device [ndy][ndx];
  * b: device [nz][nx][nq], overwritten.  Asynchronous on `stream`. */
 csx_status csx_backproject(csx_geometry *h, const float *y, float *b, void *stream);

@@ -5,9 +5,37 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 static thread_local std::string g_last_error;
+
+// Static scratch of csx_forward_noalloc: the forward's partial images live in
+// this file-scope device array (one copy per GPU, held until the process
+// ends) instead of the handle's workspace.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in); it uses the
+// device address that hipGetSymbolAddress returns, resolved once per device
+// at csx_init_geometry with that device current.
+static __device__ __align__(256) float scratch[CSX_SCRATCH_FLOATS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static csx_status resolve_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return csx_fail(CSX_EHIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return CSX_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return csx_fail(CSX_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (float *)p;
+    return CSX_OK;
+}
 
 csx_status csx_fail(csx_status s, const std::string &msg)
 {
@@ -136,8 +164,14 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     csx_status st = csx_validate_desc(d);
     if (st != CSX_OK) return st;
 
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    st = resolve_scratch(dev);
+    if (st != CSX_OK) return st;
+
     csx_geometry *h = new (std::nothrow) csx_geometry();
     if (!h) return csx_fail(CSX_ENOMEM, "host allocation failed");
+    h->device = dev;
     h->d = *d;
     h->q_host.assign(d->q, d->q + d->nq);
     h->phi_host.assign(d->phi, d->phi + d->ne);
@@ -386,6 +420,22 @@ extern "C" csx_status csx_forward(csx_geometry *h, const float *f, float *g, voi
 {
     if (!h || !f || !g) return csx_fail(CSX_EINVAL, "NULL argument");
     return csx_launch_forward(h, f, g, (hipStream_t)stream);
+}
+
+extern "C" csx_status csx_forward_noalloc(const csx_geometry *h, const float *f, float *g, void *stream)
+{
+    if (!h || !f || !g) return csx_fail(CSX_EINVAL, "NULL argument");
+    const size_t need = (size_t)csx_forward_shape(h).nparts * h->P.npix;
+    if (need > (size_t)CSX_SCRATCH_FLOATS)
+        return csx_fail(CSX_EINVAL, "forward partials (" + std::to_string(need) + " floats) exceed the static scratch (" +
+                                        std::to_string(CSX_SCRATCH_FLOATS) + " floats)");
+    float *p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        p = g_scratch_ptr[h->device];
+    }
+    if (!p) return csx_fail(CSX_EHIP, "static scratch not resolved for the handle's device");
+    return csx_launch_forward_parts(h, f, p, (size_t)CSX_SCRATCH_FLOATS, g, (hipStream_t)stream);
 }
 
 extern "C" csx_status csx_backproject(csx_geometry *h, const float *y, float *b, void *stream)

@@ -145,6 +145,7 @@ struct csx_geometry {
     bool timing = false;
     std::vector<hipEvent_t> ev[2];
     int ev_used[2] = {0, 0};
+    int device = 0;            // the HIP device current at csx_init_geometry
 };
 
 // operator launchers (csx_ops.hip)
@@ -159,6 +160,10 @@ csx_status csx_launch_forward_batch(const CsxJob *jobs_dev, const int *begin_dev
 csx_status csx_launch_adjoint_batch(const CsxJob *jobs_dev, const int *begin_dev, int njobs,
                                     int nblocks, int variant, int lds_bytes, hipStream_t s);
 csx_status csx_launch_sum_parts(csx_geometry *h, int nparts, float *g, hipStream_t s);
+// forward with the partial images in a caller-given buffer of part_cap floats
+// (no allocation; the handle's workspace is not touched)
+csx_status csx_launch_forward_parts(const csx_geometry *h, const float *f, float *part, size_t part_cap, float *g,
+                                    hipStream_t s);
 // subset operators: forward at the quads of a list (with its own split count)
 // finished by the count ratio rho = y / (A f + r) at the subset's pixels, and
 // the adjoint over the classes of a list

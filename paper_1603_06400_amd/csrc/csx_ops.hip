@@ -1034,10 +1034,10 @@ void dispatch(int variant, A &&...a)
 
 template <int LR, int QW, int QU>
 struct RunFwd {
-    static void run(const OpShape &S, const csx_geometry *h, const float *f, hipStream_t s)
+    static void run(const OpShape &S, const csx_geometry *h, const float *f, float *part, hipStream_t s)
     {
         hipLaunchKernelGGL((k_forward<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t,
-                           S.L, h->t.qa, h->t.qblk, f, h->part, S.tps);
+                           S.L, h->t.qa, h->t.qblk, f, part, S.tps);
     }
 };
 
@@ -1280,11 +1280,24 @@ csx_status csx_launch_forward(csx_geometry *h, const float *f, float *g, hipStre
     const OpShape S = csx_forward_shape(h);
     hipEvent_t e0 = csx_timing_event(h, 0), e1 = csx_timing_event(h, 0);
     if (e0) HIP_TRY(hipEventRecord(e0, s));
-    dispatch<RunFwd>(S.variant, S, h, f, s);
+    dispatch<RunFwd>(S.variant, S, h, f, h->part, s);
     HIP_TRY(hipGetLastError());
     csx_status st = csx_launch_sum_parts(h, S.nparts, g, s);
     if (st != CSX_OK) return st;
     if (e1) HIP_TRY(hipEventRecord(e1, s));
+    return CSX_OK;
+}
+
+csx_status csx_launch_forward_parts(const csx_geometry *h, const float *f, float *part, size_t part_cap, float *g,
+                                    hipStream_t s)
+{
+    const OpShape S = csx_forward_shape(h);
+    if ((size_t)S.nparts * h->P.npix > part_cap) return csx_fail(CSX_EINVAL, "forward partials exceed the buffer");
+    dispatch<RunFwd>(S.variant, S, h, f, part, s);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_parts, dim3((h->P.npix + 255) / 256), dim3(256), 0, s, (const float *)part,
+                       S.nparts, h->P.npix, g);
+    HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
 
@@ -1319,7 +1332,7 @@ csx_status csx_launch_forward_list(csx_geometry *h, const float *f, const int *q
 {
     const OpShape S = csx_forward_shape_list(h, quads, n_quads, splits);
     if ((size_t)S.nparts * h->P.npix > h->part_cap) return csx_fail(CSX_EINVAL, "forward partials too small");
-    dispatch<RunFwd>(S.variant, S, h, f, s);
+    dispatch<RunFwd>(S.variant, S, h, f, h->part, s);
     hipLaunchKernelGGL(k_sum_ratio_list, dim3(n_pix), dim3(64), 0, s, h->part, S.nparts, h->P.npix, pix, y, r,
                        rho);
     HIP_TRY(hipGetLastError());

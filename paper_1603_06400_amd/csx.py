@@ -20,6 +20,7 @@ TABLE_F32, TABLE_BF16 = 0, 1
 PSI_QUADRATIC, PSI_HUBER = 0, 1
 OP_FORWARD_SAI, OP_ADJOINT_SAI = 1, 2
 SAI_MAX_NODES = 2048
+SCRATCH_FLOATS = 1 << 20        # CSX_SCRATCH_FLOATS: static scratch of csx_forward_noalloc
 _NAMES = {CSX_EINVAL: "EINVAL", CSX_EGEOM: "EGEOM", CSX_EHIP: "EHIP", CSX_ENOMEM: "ENOMEM",
           CSX_ENUMERIC: "ENUMERIC"}
 
@@ -59,7 +60,7 @@ class _Info(ctypes.Structure):
 
 
 EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_get_info",
-           "csx_forward", "csx_backproject", "csx_recon_step", "csx_recon", "csx_recon_os", "csx_set_penalty",
+           "csx_forward", "csx_forward_noalloc", "csx_backproject", "csx_recon_step", "csx_recon", "csx_recon_os", "csx_set_penalty",
            "csx_get_launch", "csx_set_launch", "csx_batch_create", "csx_batch_free",
            "csx_batch_recon", "csx_batch_recon_n", "csx_timing_enable", "csx_timing_read", "csx_last_error",
            "csx_cnn_workspace_bytes", "csx_conv3x3_forward", "csx_conv3x3_backward_data",
@@ -94,6 +95,8 @@ def lib():
         L.csx_get_info.restype = ctypes.c_int
         L.csx_forward.argtypes = [vp, vp, vp, vp]
         L.csx_forward.restype = ctypes.c_int
+        L.csx_forward_noalloc.argtypes = [vp, vp, vp, vp]
+        L.csx_forward_noalloc.restype = ctypes.c_int
         L.csx_backproject.argtypes = [vp, vp, vp, vp]
         L.csx_backproject.restype = ctypes.c_int
         L.csx_recon_step.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
@@ -281,6 +284,13 @@ class Geometry:
         out = self.new_detector() if out is None else out
         _check(lib().csx_forward(self._h, _dev(f, self.nvox * self.nq, "f"),
                                  _dev(out, self.npix, "g"), _stream()))
+        return out
+
+    def forward_noalloc(self, f: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """csx_forward through the library's static scratch (no allocation);
+        out must be given."""
+        _check(lib().csx_forward_noalloc(self._h, _dev(f, self.nvox * self.nq, "f"),
+                                         _dev(out, self.npix, "g"), _stream()))
         return out
 
     def backproject(self, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
