@@ -14,11 +14,14 @@ nominal voxel*pixel*q evaluations of one forward plus one adjoint
     python bench.py --workload sai [--steps K] [--sai-interp linear|nearest]
     python bench.py --workload energy [--steps K]
 
-Prints one JSON line.  The roofline entry uses the work model of the direct
-evaluation (4 VALU lane-ops per open in-band triple, 60 per open pair, 10 per
-pair), the event-timed average duration of the dominant operator inside the
-timed region, and the non-packed FP32 VALU issue rate of the chip from its
-unit counts and clock; the rate an FMA-chain kernel reaches on the device is
+Prints one JSON line.  The roofline entry uses the work model of the
+operators as they run: 4 VALU lane-ops per open in-band triple, plus, when the
+pair factors are evaluated on the fly, 60 per open pair and 10 per pair, or,
+with the factor store (the default), 20 per stored class record read (the
+factor work itself is done once per geometry and is not counted); the
+event-timed average duration of the dominant operator inside the timed
+region; and the non-packed FP32 VALU issue rate of the chip from its unit
+counts and clock.  The rate an FMA-chain kernel reaches on the device is
 quoted beside it.
 """
 import argparse
@@ -36,6 +39,7 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "slice128"
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: 3.93e13 lane-ops/s
 OPS_PER_TRIPLE, OPS_PER_OPEN_PAIR, OPS_PER_PAIR = 4.0, 60.0, 10.0
+OPS_PER_RECORD = 20.0                     # factor store: unpack a class record, weights, band range
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 SRC = os.path.join(ROOT, "paper_1603_06400_amd", "csrc", "csx_ops.hip")
 
@@ -52,7 +56,12 @@ def source_hash() -> str:
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def algorithmic_ops(census: dict) -> float:
+def algorithmic_ops(census: dict, stored: bool = False, pairs_per_class: int = 4) -> float:
+    """VALU lane-ops of one operator launch: the q loop's triples, plus the
+    pair-factor work on the fly, or one class record per mirror class (4 pairs
+    with the x -> -x mirror) read from the factor store."""
+    if stored:
+        return OPS_PER_TRIPLE * census["open_triples_in_band"] + OPS_PER_RECORD * census["pairs"] / pairs_per_class
     return (OPS_PER_TRIPLE * census["open_triples_in_band"] + OPS_PER_OPEN_PAIR * census["open_pairs"]
             + OPS_PER_PAIR * census["pairs"])
 
@@ -595,7 +604,8 @@ def main():
 
     fwd_ms = tim["forward_ms"] / max(1, tim["forward_n"])
     adj_ms = tim["adjoint_ms"] / max(1, tim["adjoint_n"])
-    ops = algorithmic_ops(census)
+    store = geo.factor_store()
+    ops = algorithmic_ops(census, stored=store["on"], pairs_per_class=4 if geo.info()["symmetric_lr"] else 2)
     if adj_ms >= fwd_ms:
         dom, dom_ms, kname = "adjoint", adj_ms, "k_adjoint"
     else:
@@ -606,7 +616,10 @@ def main():
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
                 "traffic_GB_per_s": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9,
-                "ops_per_launch": ops, "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
+                "ops_per_launch": ops,
+                "op_model": ("4 per open in-band triple + 20 per stored class record" if store["on"] else
+                             "4 per open in-band triple + 60 per open pair + 10 per pair"),
+                "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
                 "peak_measured": measured_peak / 1e12, "frac_of_measured": achieved / measured_peak}
 
     out = {
@@ -618,6 +631,7 @@ def main():
                    "ne": g.ne, "mask_open": float(g.mask.mean()), "beta": w.beta,
                    "nominal_evals_per_step": nominal},
         "roofline": roofline,
+        "factor_store": {"on": store["on"], "bytes": store["bytes"], "build_ms": store["build_ms"]},
         "objective_first_last": [float(Jh[0]), float(Jh[-1])] if args.steps else None,
     }
     if not args.no_extras:

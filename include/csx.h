@@ -114,6 +114,30 @@ void csx_free_geometry(csx_geometry *h);
 
 csx_status csx_get_info(const csx_geometry *h, csx_info *out);
 
+/* Factor store (Sec. III's trade of offline against online computation,
+ * taken the other way than the paper's MATLAB implementation could afford):
+ * the exact operators' per-class pair factors -- kappa = hc / sin(theta/2)
+ * in float64, the weight A = C Gso God dtheta (1 + cos^2 theta) cos(theta/2)
+ * / sin^2(theta/2) and the four mirror pairs' mask values -- depend on the
+ * geometry only, so they can be evaluated once and read back by every
+ * forward and adjoint instead of being re-evaluated per call (16 bytes per
+ * adjoint class record, 32 per forward record: 2.1 GB at 128^2 voxels x
+ * 128^2 pixels).  The values are those the operators compute on the fly, by
+ * the same code; results agree with the on-the-fly operators to float32
+ * rounding.  Needs a uniform q grid.  csx_init_geometry builds the store
+ * when it needs at most CSX_STORE_AUTO_BYTES and a quarter of the device's
+ * free memory.  on = 1 builds it (CSX_ENOMEM if the allocation fails,
+ * CSX_EINVAL on a non-uniform q grid), on = 0 releases it; both synchronise
+ * the device.  The batched, ordered-subsets and warm-start paths use the
+ * store of each handle that has one; the energy-resolved and interpolated
+ * operators do not read it. */
+#define CSX_STORE_AUTO_BYTES (4LL << 30)
+csx_status csx_set_factor_store(csx_geometry *h, int on);
+
+/* Whether the handle holds a factor store, its device bytes and the time its
+ * build took in ms (any pointer may be NULL). */
+csx_status csx_get_factor_store(const csx_geometry *h, int *on, int64_t *bytes, double *build_ms);
+
 /* Forward_project (Sec. II eqs. 1-2; Alg. 1): g_i = sum_j sum_m H(i, j, q_m) f_jm with
  * H = C Gso God T dtheta S(theta, q).  f: device [nz][nx][nq]; g: device
  * [ndy][ndx], overwritten.  Asynchronous on `stream`. */

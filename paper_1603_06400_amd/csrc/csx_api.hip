@@ -3,6 +3,7 @@
 #include "csx_internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -141,10 +142,53 @@ static void free_all(csx_geometry *h)
     void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qblk, h->t.qv, h->t.phi32,
                     h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
                     h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags,
-                    h->fplain, h->warm, h->a1};
+                    h->fplain, h->warm, h->a1, h->t.ra, h->t.rf};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     release_events(h);
+}
+
+// Factor store: device records of every class's pair factors (uniform q
+// grids).  Builds them (on = 1) or releases them (on = 0); synchronous.
+static csx_status store_set(csx_geometry *h, bool on)
+{
+    HIP_TRY(hipDeviceSynchronize());
+    if (h->t.ra) HIP_TRY(hipFree(h->t.ra));
+    if (h->t.rf) HIP_TRY(hipFree(h->t.rf));
+    h->t.ra = nullptr;
+    h->t.rf = nullptr;
+    h->bytes -= h->store_bytes;
+    h->store_bytes = 0;
+    h->store_ms = 0.0;
+    if (!on) return CSX_OK;
+    if (!h->P.qu) return csx_fail(CSX_EINVAL, "the factor store needs a uniform q grid");
+    size_t na, nf;
+    csx_store_records(h->P, &na, &nf);
+    uint4 *ra = nullptr, *rf = nullptr;
+    if (hipMalloc((void **)&ra, na * sizeof(uint4)) != hipSuccess) {
+        (void)hipGetLastError();
+        return csx_fail(CSX_ENOMEM, "factor store (adjoint records)");
+    }
+    if (hipMalloc((void **)&rf, nf * 2 * sizeof(uint4)) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(ra);
+        return csx_fail(CSX_ENOMEM, "factor store (forward records)");
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    csx_status st = csx_launch_store(h, ra, rf, nullptr);
+    const hipError_t e = hipDeviceSynchronize();
+    if (st == CSX_OK && e != hipSuccess) st = csx_fail(CSX_EHIP, std::string("factor store: ") + hipGetErrorString(e));
+    if (st != CSX_OK) {
+        (void)hipFree(ra);
+        (void)hipFree(rf);
+        return st;
+    }
+    h->store_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    h->t.ra = ra;
+    h->t.rf = rf;
+    h->store_bytes = (int64_t)((na + 2 * nf) * sizeof(uint4));
+    h->bytes += h->store_bytes;
+    return CSX_OK;
 }
 
 #define CSX_TRY(expr)                        \
@@ -330,6 +374,17 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     CSX_TRY(dev_alloc(&h->flags, 1, B));
     CSX_TRY(csx_launch_fill(h->ones, P.npix, 1.0f, nullptr));
     CSX_TRY(csx_launch_clear_flags(h, nullptr));
+    // the factor store by default when it is small beside the device's free
+    // memory (at most CSX_STORE_AUTO_BYTES and a quarter of what is free)
+    if (P.qu) {
+        size_t na, nf, fr = 0, tot = 0;
+        csx_store_records(P, &na, &nf);
+        const size_t need = (na + 2 * nf) * sizeof(uint4);
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && need <= (size_t)CSX_STORE_AUTO_BYTES && need <= fr / 4) {
+            const csx_status ss = store_set(h, true);
+            if (ss != CSX_ENOMEM) CSX_TRY(ss);   // out of memory: the handle runs without a store
+        }
+    }
     {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) {
@@ -388,6 +443,23 @@ extern "C" csx_status csx_set_launch(csx_geometry *h, const csx_launch *lc)
         h->part = p;
         h->part_cap = need;
     }
+    return CSX_OK;
+}
+
+extern "C" csx_status csx_set_factor_store(csx_geometry *h, int on)
+{
+    if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
+    if (on != 0 && on != 1) return csx_fail(CSX_EINVAL, "on must be 0 or 1");
+    if (on && !h->P.qu) return csx_fail(CSX_EINVAL, "the factor store needs a uniform q grid");
+    return store_set(h, on == 1);
+}
+
+extern "C" csx_status csx_get_factor_store(const csx_geometry *h, int *on, int64_t *bytes, double *build_ms)
+{
+    if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
+    if (on) *on = h->t.ra ? 1 : 0;
+    if (bytes) *bytes = h->store_bytes;
+    if (build_ms) *build_ms = h->store_ms;
     return CSX_OK;
 }
 

@@ -269,6 +269,15 @@ __device__ __forceinline__ int scale_exponent(double sc)
     return e - 1;
 }
 
+// 16-byte load with the non-temporal hint (streamed records that no other
+// wave reads again: kept from displacing the L2-resident tables and images)
+__device__ __forceinline__ uint4 load_nt(const uint4 *p)
+{
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = __builtin_nontemporal_load((const u32x4 *)p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 template <int QW>
 __device__ __forceinline__ int transposed_index(int lane)
 {

@@ -74,7 +74,18 @@ struct DevTables {
     float *phi32 = nullptr;    // [ne+2] zero-padded spectrum, float32
     uint16_t *phi16 = nullptr; // [ne+2] zero-padded spectrum, bfloat16 bits
     uint32_t *maskbits = nullptr; // [mask_ny] bit c of row r = cell (c, r)
+    // factor store (uniform q grids): the pair factors of every class,
+    // computed once per geometry; null when the operators evaluate them on the fly
+    uint4 *ra = nullptr;       // adjoint records [n_groups][class tiles][64]: {kappa (f64), A, bits}
+    uint4 *rf = nullptr;       // forward records [n_quad][voxel tiles][64][2]: {kappa1, kappa2}, {A1, A2, bits, 0}
 };
+
+// Bits of a stored record: the mask values of the class's pairs, and whether
+// the class is active (some pair open and kappa in band).  Adjoint: bit 0
+// (y', column a), 1 (-y', a), 2 (y', -a), 3 (-y', -a), bit 4 active.
+// Forward: class 1 in bits 0-3 (tau, tad, tbu, tbd) and 4 (active), class 2
+// (the pixel column's mirror) in bits 8-11 and 12.
+#define CSX_REC_ACT 16u
 
 // LDS layout of an operator launch (byte offsets).
 struct Lds {
@@ -146,6 +157,8 @@ struct csx_geometry {
     std::vector<hipEvent_t> ev[2];
     int ev_used[2] = {0, 0};
     int device = 0;            // the HIP device current at csx_init_geometry
+    int64_t store_bytes = 0;   // device bytes of the factor store (0: none)
+    double store_ms = 0.0;     // time its build took (host clock, synchronised)
 };
 
 // operator launchers (csx_ops.hip)
@@ -174,6 +187,10 @@ csx_status csx_launch_forward_list(csx_geometry *h, const float *f, const int *q
 csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
                                    hipStream_t s);
 hipEvent_t csx_timing_event(csx_geometry *h, int op);
+// factor store: record counts (16-byte adjoint records, 32-byte forward
+// records) and the kernels that fill them from the handle's tables
+void csx_store_records(const KParams &P, size_t *n_adj, size_t *n_fwd);
+csx_status csx_launch_store(const csx_geometry *h, uint4 *ra, uint4 *rf, hipStream_t s);
 
 // solver pieces (csx_solver.hip)
 csx_status csx_launch_ratio(csx_geometry *h, const float *y, const float *r, bool want_rho,

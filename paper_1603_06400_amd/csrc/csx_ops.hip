@@ -62,13 +62,17 @@ namespace {
 // rho is then Psi [ne + 2][npix], Psi[k][i] = Phi_k y_E[k - 1][i] with zero
 // planes at the pad bins 0 and ne + 1, and a triple reads Psi at its own
 // spectrum bin and pixel instead of Phi times the pixel's ratio.
-template <int LR, int QW, int QU, int EN = 0>
+// ST = 1: the class factors come from the factor store (T.ra) instead of
+// being evaluated: the same values, computed once per geometry by
+// k_store_adjoint with the same code.
+template <int LR, int QW, int QU, int EN = 0, int ST = 0>
 __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &T, const Lds &L,
                                              const double *__restrict__ qa,
                                              const double2 *__restrict__ qblk,
                                              const float *__restrict__ rho, float *__restrict__ b,
                                              int bx, int by)
 {
+    static_assert(!(EN && ST), "the energy-resolved adjoint evaluates its factors");
     constexpr int NB = QW / 8;
     extern __shared__ __align__(16) unsigned char lds[];
     float *s_phi = (float *)(lds + L.phi) + P.spec_lo;   // entry 0 of the padded table
@@ -128,12 +132,26 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
         r = (t / ntx) * 8 + ly;
         return a < P.ndx && r < half_y;
     };
-    // detector values of the lane's class, prefetched one tile ahead
+    // detector values of the lane's class (and with ST its stored record),
+    // prefetched one tile ahead
     float r_u = 0.0f, r_d = 0.0f, r_bu = 0.0f, r_bd = 0.0f;
+    const int ntiles_all = ntx * ((half_y + 7) / 8);
+    double rk = 0.0;
+    float rA = 0.0f;
+    uint32_t rb = 0u;
     auto load_rho = [&](int t) {
         int a, r;
         if (EN) return;                         // read per node from Psi
+        if (ST) rb = 0u;
         if (class_of(t, a, r)) {
+            if (ST) {
+                // record of class (a, r): tile (r/8, a/8), lane 8 (r mod 8) + a mod 8
+                const size_t e = ((size_t)g * ntiles_all + (r >> 3) * ntx + (a >> 3)) * 64 + ((r & 7) << 3) + (a & 7);
+                const uint4 v = load_nt(T.ra + e);
+                rk = __longlong_as_double((long long)(((uint64_t)v.y << 32) | v.x));
+                rA = __uint_as_float(v.z);
+                rb = v.w;
+            }
             const int bu = half_y + r;
             const int bd = P.ndy - 1 - bu;
             r_u = rho[bu * P.ndx + a];
@@ -157,7 +175,24 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
         // pixels' columns in Psi
         float eu = 0.0f, ed = 0.0f, ebu = 0.0f, ebd = 0.0f;
         const float *pu = rho, *pd = rho, *pbu = rho, *pbd = rho;
-        if (has) {
+        if (ST) {
+            // as below, with A, kappa and the mask values read from the store
+            if (has && (rb & CSX_REC_ACT)) {
+                const float tu = (float)(rb & 1u), td = (float)((rb >> 1) & 1u);
+                const float w0 = tu * r_u + td * r_d;
+                float w1 = 0.0f;
+                if (LR) {
+                    const float tbu = (float)((rb >> 2) & 1u), tbd = (float)((rb >> 3) & 1u);
+                    w1 = tbu * r_bu + tbd * r_bd;
+                }
+                if (w0 != 0.0f || w1 != 0.0f) {
+                    c0 = rA * w0;
+                    c1 = rA * w1;
+                    act = c0 != 0.0f || c1 != 0.0f;
+                    if (act) kap = rk;
+                }
+            }
+        } else if (has) {
             const int bu = half_y + r;
             const double xp = pixel_coord(P, a, P.ndx);
             const double yp = pixel_coord(P, bu, P.ndy);
@@ -310,7 +345,9 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
 // point with the launch's scale sc[0] = 2^s, sc[1] = 2^-s: integer atomics,
 // totals independent of the add order).  part then holds [ne][npix] per
 // partial image.
-template <int LR, int QW, int QU, int EN = 0>
+// ST = 1: the two classes' factors come from the factor store (T.rf),
+// computed once per geometry by k_store_forward with the same code.
+template <int LR, int QW, int QU, int EN = 0, int ST = 0>
 __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &T, const Lds &L,
                                              const double *__restrict__ qa,
                                              const double2 *__restrict__ qblk,
@@ -319,6 +356,7 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
                                              int bx, int by, int bz, int gz,
                                              const double *__restrict__ sc = nullptr)
 {
+    static_assert(!(EN && ST), "the energy-resolved forward evaluates its factors");
     constexpr int NB = QW / 8;
     constexpr int RPG = LR ? 2 : 1;             // voxel rows per group
     constexpr int ROWS = 64 * RPG;              // tile rows per batch
@@ -406,15 +444,23 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
             }
         }
     };
-    // voxel records of the lane's group, prefetched one tile ahead
+    // voxel records of the lane's group (with ST the stored class records of
+    // (quad, group)), prefetched one tile ahead
     VoxD nvd = {0.0, 1.0, 1.0, 0.0};
     float2 nvf = {0.0f, 0.0f};
     double2 nvm = {0.0, 0.0};
     bool nvalid = false;
+    uint4 nr0 = make_uint4(0u, 0u, 0u, 0u), nr1 = make_uint4(0u, 0u, 0u, 0u);
     auto load_vox = [&](int t) {
         const int ix = (t % ntx) * 8 + (lane & 7), iz = (t / ntx) * 8 + (lane >> 3);
         nvalid = ix < gw && iz < P.nz;
-        if (nvalid) {
+        if (ST) {
+            if (nvalid) {
+                const size_t e = (((size_t)qq * ntiles + t) * 64 + lane) * 2;
+                nr0 = load_nt(T.rf + e);
+                nr1 = load_nt(T.rf + e + 1);
+            }
+        } else if (nvalid) {
             const int j = iz * P.nx + ix;
             nvd = T.vd[j];
             nvf = T.vf[j];
@@ -451,6 +497,7 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
         const float2 vf = nvf;
         const double2 vm = nvm;
         const bool valid = nvalid;
+        const uint4 r0 = nr0, r1 = nr1;
         if (t + 1 < t1) {
             stage_load(t + 1);
             load_vox(t + 1);
@@ -465,7 +512,29 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
         float c10 = 0.0f, c11 = 0.0f, c12 = 0.0f, c13 = 0.0f;
         float c20 = 0.0f, c21 = 0.0f, c22 = 0.0f, c23 = 0.0f;
         bool act1 = false, act2 = false;
-        if (valid) {
+        if (ST) {
+            // as below, with A, kappa and the mask values read from the store
+            const uint32_t rb = r1.z;
+            if (valid && (rb & CSX_REC_ACT)) {
+                const float A = __uint_as_float(r1.x);
+                act1 = true;
+                k1 = __longlong_as_double((long long)(((uint64_t)r0.y << 32) | r0.x));
+                c10 = A * (float)(rb & 1u);
+                c11 = A * (float)((rb >> 1) & 1u);
+                c12 = A * (float)((rb >> 2) & 1u);
+                c13 = A * (float)((rb >> 3) & 1u);
+            }
+            if (LR && valid && (rb & (CSX_REC_ACT << 8))) {
+                const float A = __uint_as_float(r1.y);
+                act2 = true;
+                k2 = __longlong_as_double((long long)(((uint64_t)r0.w << 32) | r0.z));
+                // O0, O1 <- mirror voxel (column a); O2, O3 <- voxel j (column -a)
+                c20 = A * (float)((rb >> 10) & 1u);
+                c21 = A * (float)((rb >> 11) & 1u);
+                c22 = A * (float)((rb >> 8) & 1u);
+                c23 = A * (float)((rb >> 9) & 1u);
+            }
+        } else if (valid) {
             {
                 const Cells c = mask_cells(P, vm, xpa, yp);
                 float tau = 0.0f, tad = 0.0f, tbu = 0.0f, tbd = 0.0f;
@@ -704,17 +773,17 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
     }
 }
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
                                                  const double *__restrict__ qa,
                                                  const double2 *__restrict__ qblk,
                                                  const float *__restrict__ rho,
                                                  float *__restrict__ b)
 {
-    adjoint_body<LR, QW, QU>(P, T, L, qa, qblk, rho, b, blockIdx.x, blockIdx.y);
+    adjoint_body<LR, QW, QU, 0, ST>(P, T, L, qa, qblk, rho, b, blockIdx.x, blockIdx.y);
 }
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
                                                  const double *__restrict__ qa,
                                                  const double2 *__restrict__ qblk,
@@ -723,7 +792,122 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
 {
     int bx, by, bz;
     xcd_block(bx, by, bz);
-    forward_body<LR, QW, QU>(P, T, L, qa, qblk, f, part, tiles_per_split, bx, by, bz, gridDim.z);
+    forward_body<LR, QW, QU, 0, ST>(P, T, L, qa, qblk, f, part, tiles_per_split, bx, by, bz, gridDim.z);
+}
+
+// Factor store of the adjoint: the record of voxel group g and pixel class
+// (a, r) in tile t, lane l -- kappa, A and the mask values exactly as
+// adjoint_body evaluates them, A = kappa = 0 and no bits when the class is
+// inactive (every pair closed, or kappa out of band).  One thread per record.
+template <int LR>
+__global__ void __launch_bounds__(256) k_store_adjoint(KParams P, DevTables T, uint4 *__restrict__ out)
+{
+    const int half_y = P.ndy / 2, ntx = (P.ndx + 7) / 8;
+    const int ntl = ntx * ((half_y + 7) / 8);
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)P.n_groups * ntl * 64) return;
+    const int g = (int)(idx / ((size_t)ntl * 64));
+    const int e = (int)(idx % ((size_t)ntl * 64));
+    const int t = e >> 6, lane = e & 63;
+    int j = g;
+    if (LR) {
+        const int half = P.nx / 2;
+        j = (g / half) * P.nx + g % half;
+    }
+    const int a = (t % ntx) * 8 + (lane & 7), r = (t / ntx) * 8 + (lane >> 3);
+    double k = 0.0;
+    float A = 0.0f;
+    uint32_t bits = 0u;
+    if (a < P.ndx && r < half_y) {
+        const int bu = half_y + r;
+        const double xp = pixel_coord(P, a, P.ndx);
+        const double yp = pixel_coord(P, bu, P.ndy);
+        const Cells c = mask_cells(P, T.vm[j], xp, yp);
+        if (c.in_rows) {
+            const uint32_t ru = T.maskbits[c.row_u], rd = T.maskbits[c.row_d];
+            bits = ((ru >> c.col_a) & 1u) | (((rd >> c.col_a) & 1u) << 1);
+            if (LR) bits |= (((ru >> c.col_b) & 1u) << 2) | (((rd >> c.col_b) & 1u) << 3);
+        }
+        if (bits) {
+            pair_factors(P, T.vd[j], T.vf[j], xp, yp, k, A);
+            if (in_band(P, k)) {
+                bits |= CSX_REC_ACT;
+            } else {
+                bits = 0u;
+                k = 0.0;
+                A = 0.0f;
+            }
+        }
+    }
+    const uint64_t ku = (uint64_t)__double_as_longlong(k);
+    out[idx] = make_uint4((uint32_t)ku, (uint32_t)(ku >> 32), __float_as_uint(A), bits);
+}
+
+// Factor store of the forward: for pixel quad qq and voxel group (tile t,
+// lane l) the two classes of forward_body -- class 1 at pixel column a,
+// class 2 at its mirror -a -- as two 16-byte words {kappa1, kappa2} and
+// {A1, A2, bits, 0}.  One thread per (quad, group).
+template <int LR>
+__global__ void __launch_bounds__(256) k_store_forward(KParams P, DevTables T, uint4 *__restrict__ out)
+{
+    const int gw = LR ? P.nx / 2 : P.nx;
+    const int ntx = (gw + 7) / 8;
+    const int ntl = ntx * ((P.nz + 7) / 8);
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)P.n_quad * ntl * 64) return;
+    const int qq = (int)(idx / ((size_t)ntl * 64));
+    const int e = (int)(idx % ((size_t)ntl * 64));
+    const int t = e >> 6, lane = e & 63;
+    int a, bu;
+    if (LR) {
+        const int hx = P.ndx / 2;
+        a = hx + qq % hx;
+        bu = P.ndy / 2 + qq / hx;
+    } else {
+        a = qq % P.ndx;
+        bu = P.ndy / 2 + qq / P.ndx;
+    }
+    const double xpa = pixel_coord(P, a, P.ndx);
+    const double yp = pixel_coord(P, bu, P.ndy);
+    const int ix = (t % ntx) * 8 + (lane & 7), iz = (t / ntx) * 8 + (lane >> 3);
+    double k1 = 0.0, k2 = 0.0;
+    float A1 = 0.0f, A2 = 0.0f;
+    uint32_t bits = 0u;
+    if (ix < gw && iz < P.nz) {
+        const int j = iz * P.nx + ix;
+        const VoxD vd = T.vd[j];
+        const float2 vf = T.vf[j];
+        const double2 vm = T.vm[j];
+        for (int cls = 0; cls < (LR ? 2 : 1); ++cls) {
+            const double xp = cls ? -xpa : xpa;
+            const Cells c = mask_cells(P, vm, xp, yp);
+            uint32_t b = 0u;
+            if (c.in_rows) {
+                const uint32_t ru = T.maskbits[c.row_u], rd = T.maskbits[c.row_d];
+                b = ((ru >> c.col_a) & 1u) | (((rd >> c.col_a) & 1u) << 1);
+                if (LR) b |= (((ru >> c.col_b) & 1u) << 2) | (((rd >> c.col_b) & 1u) << 3);
+            }
+            if (b) {
+                double k;
+                float A;
+                pair_factors(P, vd, vf, xp, yp, k, A);
+                if (in_band(P, k)) {
+                    bits |= (b | CSX_REC_ACT) << (8 * cls);
+                    if (cls) {
+                        k2 = k;
+                        A2 = A;
+                    } else {
+                        k1 = k;
+                        A1 = A;
+                    }
+                }
+            }
+        }
+    }
+    const uint64_t u1 = (uint64_t)__double_as_longlong(k1), u2 = (uint64_t)__double_as_longlong(k2);
+    const size_t o = idx * 2;
+    out[o] = make_uint4((uint32_t)u1, (uint32_t)(u1 >> 32), (uint32_t)u2, (uint32_t)(u2 >> 32));
+    out[o + 1] = make_uint4(__float_as_uint(A1), __float_as_uint(A2), bits, 0u);
 }
 
 // Energy-resolved operators (the energy-sensitive detector of App. A).
@@ -921,18 +1105,18 @@ __device__ __forceinline__ int find_job(const int *__restrict__ begin, int njobs
     return lo;
 }
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 __global__ void __launch_bounds__(256) k_adjoint_batch(const CsxJob *__restrict__ jobs,
                                                        const int *__restrict__ begin, int njobs)
 {
     const int jb = find_job(begin, njobs, blockIdx.x);
     const CsxJob &J = jobs[jb];
     const int local = blockIdx.x - begin[jb];
-    adjoint_body<LR, QW, QU>(J.P, J.T, J.L, J.T.qa, J.T.qblk, J.in, J.out, local % J.gx,
-                                 local / J.gx);
+    adjoint_body<LR, QW, QU, 0, ST>(J.P, J.T, J.L, J.T.qa, J.T.qblk, J.in, J.out, local % J.gx,
+                                        local / J.gx);
 }
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 __global__ void __launch_bounds__(512) k_forward_batch(const CsxJob *__restrict__ jobs,
                                                        const int *__restrict__ begin, int njobs)
 {
@@ -945,8 +1129,8 @@ __global__ void __launch_bounds__(512) k_forward_batch(const CsxJob *__restrict_
     const int n = J.gx * J.gy * J.gz;
     if (n % 8 == 0) local = (int)(blockIdx.x % 8) * (n / 8) + local / 8;
     const int bx = local % J.gx, r = local / J.gx;
-    forward_body<LR, QW, QU>(J.P, J.T, J.L, J.T.qa, J.T.qblk, J.in, J.out, J.tps, bx, r / J.gz, r % J.gz,
-                                 J.gz);
+    forward_body<LR, QW, QU, 0, ST>(J.P, J.T, J.L, J.T.qa, J.T.qblk, J.in, J.out, J.tps, bx, r / J.gz,
+                                        r % J.gz, J.gz);
 }
 
 // g_i = sum_p part[p][i] in a fixed order.
@@ -1011,82 +1195,87 @@ int log2i(int v)
     return r;
 }
 
-// Kernel template of a launch: bit 1 LR mirror, bit 2 uniform q, bits 3+
-// log2 of the q chunk width.  (The table dtype only changes table staging.)
-int variant_of(const KParams &P)
+// Kernel template of a launch: bit 0 factor store, bit 1 LR mirror, bit 2
+// uniform q, bits 3+ log2 of the q chunk width.  (The table dtype only
+// changes table staging.)
+int variant_of(const KParams &P, bool stored = false)
 {
-    return (P.lr ? 2 : 0) | (P.qu ? 4 : 0) | (log2i(P.qw) << 3);
+    return (stored && P.qu ? 1 : 0) | (P.lr ? 2 : 0) | (P.qu ? 4 : 0) | (log2i(P.qw) << 3);
 }
 
-// Template dispatch: variant -> kernel instance.
-template <template <int, int, int> class K, typename... A>
+// Template dispatch: variant -> kernel instance (the factor store exists on
+// uniform q grids only).
+template <template <int, int, int, int> class K, typename... A>
 void dispatch(int variant, A &&...a)
 {
-    const int lr = (variant >> 1) & 1, qu = (variant >> 2) & 1;
+    const int st = variant & 1, lr = (variant >> 1) & 1, qu = (variant >> 2) & 1;
     const int qw = 1 << (variant >> 3);
-#define CSX_CASE(LR_, QW_, QU_) \
-    if (lr == LR_ && qw == QW_ && qu == QU_) { K<LR_, QW_, QU_>::run(a...); return; }
-#define CSX_CASES_QW(LR_, QU_) CSX_CASE(LR_, 16, QU_) CSX_CASE(LR_, 32, QU_) CSX_CASE(LR_, 64, QU_)
-    CSX_CASES_QW(0, 0) CSX_CASES_QW(0, 1) CSX_CASES_QW(1, 0) CSX_CASES_QW(1, 1)
+#define CSX_CASE(LR_, QW_, QU_, ST_) \
+    if (lr == LR_ && qw == QW_ && qu == QU_ && st == ST_) { K<LR_, QW_, QU_, ST_>::run(a...); return; }
+#define CSX_CASES_QW(LR_, QU_, ST_) CSX_CASE(LR_, 16, QU_, ST_) CSX_CASE(LR_, 32, QU_, ST_) CSX_CASE(LR_, 64, QU_, ST_)
+    CSX_CASES_QW(0, 0, 0) CSX_CASES_QW(0, 1, 0) CSX_CASES_QW(1, 0, 0) CSX_CASES_QW(1, 1, 0)
+    CSX_CASES_QW(0, 1, 1) CSX_CASES_QW(1, 1, 1)
 #undef CSX_CASES_QW
 #undef CSX_CASE
 }
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 struct RunFwd {
     static void run(const OpShape &S, const csx_geometry *h, const float *f, float *part, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_forward<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t,
+        hipLaunchKernelGGL((k_forward<LR, QW, QU, ST>), S.grid, S.block, S.L.total, s, S.P, h->t,
                            S.L, h->t.qa, h->t.qblk, f, part, S.tps);
     }
 };
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 struct RunAdj {
     static void run(const OpShape &S, const csx_geometry *h, const float *rho, float *b,
                     hipStream_t s)
     {
-        hipLaunchKernelGGL((k_adjoint<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t,
+        hipLaunchKernelGGL((k_adjoint<LR, QW, QU, ST>), S.grid, S.block, S.L.total, s, S.P, h->t,
                            S.L, h->t.qa, h->t.qblk, rho, b);
     }
 };
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 struct RunFwdBatch {
     static void run(const CsxJob *jobs, const int *begin, int njobs, int nblocks, int lds,
                     hipStream_t s)
     {
-        hipLaunchKernelGGL((k_forward_batch<LR, QW, QU>), dim3(nblocks), dim3(512), lds, s,
+        hipLaunchKernelGGL((k_forward_batch<LR, QW, QU, ST>), dim3(nblocks), dim3(512), lds, s,
                            jobs, begin, njobs);
     }
 };
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 struct RunAdjBatch {
     static void run(const CsxJob *jobs, const int *begin, int njobs, int nblocks, int lds,
                     hipStream_t s)
     {
-        hipLaunchKernelGGL((k_adjoint_batch<LR, QW, QU>), dim3(nblocks), dim3(256), lds, s,
+        hipLaunchKernelGGL((k_adjoint_batch<LR, QW, QU, ST>), dim3(nblocks), dim3(256), lds, s,
                            jobs, begin, njobs);
     }
 };
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 struct RunFwdE {
     static void run(const OpShape &S, const csx_geometry *h, const float *f, float *part, const double *sc,
                     hipStream_t s)
     {
-        hipLaunchKernelGGL((k_forward_energy<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t, S.L,
-                           h->t.qa, h->t.qblk, f, part, S.tps, sc);
+        if constexpr (ST == 0)
+            hipLaunchKernelGGL((k_forward_energy<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t, S.L,
+                               h->t.qa, h->t.qblk, f, part, S.tps, sc);
     }
 };
 
-template <int LR, int QW, int QU>
+template <int LR, int QW, int QU, int ST>
 struct RunAdjE {
     static void run(const OpShape &S, const csx_geometry *h, const float *psi, float *b, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_adjoint_energy<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t, S.L,
-                           h->t.qa, h->t.qblk, psi, b);
+        if constexpr (ST == 0)
+            hipLaunchKernelGGL((k_adjoint_energy<LR, QW, QU>), S.grid, S.block, S.L.total, s, S.P, h->t, S.L,
+                               h->t.qa, h->t.qblk, psi, b);
     }
 };
 
@@ -1191,9 +1380,33 @@ csx_status csx_launch_adjoint_energy(csx_geometry *h, const float *psi, float *b
         S.P.qw = 32;
         S.P.qchunks = (S.P.nq + 31) / 32;
         S.grid.y = S.P.qchunks;
-        S.variant = variant_of(S.P);
     }
+    S.variant = variant_of(S.P);        // factors evaluated on the fly
     dispatch<RunAdjE>(S.variant, S, h, psi, b, s);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+void csx_store_records(const KParams &P, size_t *n_adj, size_t *n_fwd)
+{
+    const int half_y = P.ndy / 2;
+    const size_t adj_tiles = (size_t)((P.ndx + 7) / 8) * ((half_y + 7) / 8);
+    *n_adj = (size_t)P.n_groups * adj_tiles * 64;
+    *n_fwd = (size_t)P.n_quad * fwd_tiles(P) * 64;
+}
+
+csx_status csx_launch_store(const csx_geometry *h, uint4 *ra, uint4 *rf, hipStream_t s)
+{
+    size_t na, nf;
+    csx_store_records(h->P, &na, &nf);
+    const dim3 ga((unsigned)((na + 255) / 256)), gf((unsigned)((nf + 255) / 256));
+    if (h->P.lr) {
+        hipLaunchKernelGGL(k_store_adjoint<1>, ga, dim3(256), 0, s, h->P, h->t, ra);
+        hipLaunchKernelGGL(k_store_forward<1>, gf, dim3(256), 0, s, h->P, h->t, rf);
+    } else {
+        hipLaunchKernelGGL(k_store_adjoint<0>, ga, dim3(256), 0, s, h->P, h->t, ra);
+        hipLaunchKernelGGL(k_store_forward<0>, gf, dim3(256), 0, s, h->P, h->t, rf);
+    }
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
@@ -1248,7 +1461,7 @@ OpShape csx_forward_shape(const csx_geometry *h)
     S.grid = dim3((S.P.n_quad + 7) / 8, nsplit, S.P.qchunks);
     S.block = dim3(512);
     S.nparts = nsplit * S.P.qchunks;
-    S.variant = variant_of(S.P);
+    S.variant = variant_of(S.P, h->t.rf != nullptr);
     return S;
 }
 
@@ -1263,7 +1476,7 @@ OpShape csx_adjoint_shape(const csx_geometry *h)
     S.block = dim3(64 * h->adj_wpb);
     S.tps = 0;
     S.nparts = 0;
-    S.variant = variant_of(S.P);
+    S.variant = variant_of(S.P, h->t.ra != nullptr);
     return S;
 }
 
@@ -1361,7 +1574,7 @@ csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int 
         S.P.qw = 32;
         S.P.qchunks = (S.P.nq + 31) / 32;
         S.grid.y = S.P.qchunks;
-        S.variant = variant_of(S.P);
+        S.variant = variant_of(S.P, h->t.ra != nullptr);
     }
     dispatch<RunAdj>(S.variant, S, h, rho, b, s);
     HIP_TRY(hipGetLastError());

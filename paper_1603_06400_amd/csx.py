@@ -60,6 +60,7 @@ class _Info(ctypes.Structure):
 
 
 EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_get_info",
+           "csx_set_factor_store", "csx_get_factor_store",
            "csx_forward", "csx_forward_noalloc", "csx_backproject", "csx_recon_step", "csx_recon", "csx_recon_os", "csx_set_penalty",
            "csx_get_launch", "csx_set_launch", "csx_batch_create", "csx_batch_free",
            "csx_batch_recon", "csx_batch_recon_n", "csx_timing_enable", "csx_timing_read", "csx_last_error",
@@ -95,6 +96,11 @@ def lib():
         L.csx_get_info.restype = ctypes.c_int
         L.csx_forward.argtypes = [vp, vp, vp, vp]
         L.csx_forward.restype = ctypes.c_int
+        L.csx_set_factor_store.argtypes = [vp, ctypes.c_int]
+        L.csx_set_factor_store.restype = ctypes.c_int
+        L.csx_get_factor_store.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_double)]
+        L.csx_get_factor_store.restype = ctypes.c_int
         L.csx_forward_noalloc.argtypes = [vp, vp, vp, vp]
         L.csx_forward_noalloc.restype = ctypes.c_int
         L.csx_backproject.argtypes = [vp, vp, vp, vp]
@@ -263,6 +269,15 @@ class Geometry:
     def set_launch(self, fwd_splits: int, fwd_qw: int, adj_qw: int) -> None:
         lc = _Launch(int(fwd_splits), int(fwd_qw), int(adj_qw))
         _check(lib().csx_set_launch(self._h, ctypes.byref(lc)))
+
+    def set_factor_store(self, on: bool) -> None:
+        """Build (True) or release (False) the per-class pair-factor store."""
+        _check(lib().csx_set_factor_store(self._h, int(bool(on))))
+
+    def factor_store(self) -> dict:
+        on, nb, ms = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().csx_get_factor_store(self._h, ctypes.byref(on), ctypes.byref(nb), ctypes.byref(ms)))
+        return {"on": bool(on.value), "bytes": int(nb.value), "build_ms": float(ms.value)}
 
     def timing_enable(self, on: bool = True) -> None:
         _check(lib().csx_timing_enable(self._h, int(bool(on))))
