@@ -138,21 +138,50 @@ csx_status csx_set_factor_store(csx_geometry *h, int on);
  * build took in ms (any pointer may be NULL). */
 csx_status csx_get_factor_store(const csx_geometry *h, int *on, int64_t *bytes, double *build_ms);
 
+/* Interval form of the exact operators (Alg. 1 and Alg. 3 re-associated).
+ * The spectrum is a histogram, so a class's q sum depends on its Bragg
+ * factor kappa = hc / sin(theta/2) only through the spectrum bin of kappa q_m
+ * at each node m: the (ne + 1) nq bin thresholds kappa = beta(c, m), sorted,
+ * cut the kappa axis into intervals on which the sum is constant (Sec.
+ * III-B's angle table with its grid placed exactly where S changes).  The
+ * forward then builds, per voxel and call, the table F_j(t) = sum_m q_m f_jm
+ * Phi(bin) over the intervals t by one float64 prefix sum, and reads it once
+ * per class; the adjoint sums each class's weight A T rho into float64
+ * prefix sums over the intervals and takes one difference per (node, bin).
+ * Bin decisions are float64 FMAs per node, as in the direct kernels; the
+ * results equal the direct sums up to the order of the additions.  Set-up
+ * computes per class an 8-byte record (A, mask values, interval, rank in its
+ * voxel group's interval order): 0.5 GB at 128^2 x 128^2.  Applies when
+ * (ne + 1) nq < 16384, the upper-half detector has at most 16384 classes
+ * per voxel group and both kernels' tables fit in LDS; csx_init_geometry
+ * builds it then when it needs at most CSX_STORE_AUTO_BYTES and a quarter of
+ * the free memory.  While built, csx_forward, csx_forward_noalloc,
+ * csx_backproject and the solvers' full operators use it; subset and
+ * energy-resolved operators do not.  on = 1 builds (CSX_EINVAL when it does
+ * not apply, CSX_ENOMEM), on = 0 releases; both synchronise the device. */
+csx_status csx_set_interval_operators(csx_geometry *h, int on);
+
+/* Whether the interval operators are built, their device bytes, set-up time
+ * in ms and number of kappa intervals (any pointer may be NULL). */
+csx_status csx_get_interval_operators(const csx_geometry *h, int *on, int64_t *bytes, double *build_ms,
+                                      int *intervals);
+
 /* Forward_project (Sec. II eqs. 1-2; Alg. 1): g_i = sum_j sum_m H(i, j, q_m) f_jm with
  * H = C Gso God T dtheta S(theta, q).  f: device [nz][nx][nq]; g: device
  * [ndy][ndx], overwritten.  Asynchronous on `stream`. */
 csx_status csx_forward(csx_geometry *h, const float *f, float *g, void *stream);
 
 /* Largest forward partial-image buffer of csx_forward_noalloc, in floats
- * (4 MiB of device memory per GPU, held from the first csx_init_geometry on
+ * (16 MiB of device memory per GPU, held from the first csx_init_geometry on
  * that GPU until the process ends). */
-#define CSX_SCRATCH_FLOATS (1 << 20)
+#define CSX_SCRATCH_FLOATS (1 << 22)
 
 /* csx_forward without any allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same kernels and the same result, bit for bit, as
  * csx_forward; the forward's partial images (splits x q chunks x npix
- * floats, see csx_get_launch) go to a static device array of
+ * floats, see csx_get_launch; with the interval operators one image per
+ * workgroup, at most one per compute unit) go to a static device array of
  * CSX_SCRATCH_FLOATS floats instead of the handle's workspace, so the call
  * makes no hipMalloc / hipFree and records no timing events.  Returns
  * CSX_EINVAL before any HIP call when the partials exceed CSX_SCRATCH_FLOATS

@@ -18,7 +18,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
-SOURCES = ["csx_api.hip", "csx_ops.hip", "csx_solver.hip", "csx_batch.hip", "csx_cnn.hip", "csx_os.hip", "csx_sai.hip", "csx_energy.hip", "csx_probe.hip"]
+SOURCES = ["csx_api.hip", "csx_ops.hip", "csx_solver.hip", "csx_batch.hip", "csx_cnn.hip", "csx_os.hip", "csx_sai.hip", "csx_energy.hip", "csx_probe.hip", "csx_interval.hip"]
 
 
 def build(verbose: bool = False) -> str:

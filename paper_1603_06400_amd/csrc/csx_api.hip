@@ -136,13 +136,14 @@ static void release_events(csx_geometry *h)
 
 static void free_all(csx_geometry *h)
 {
+    csx_iv_free(h);
     csx_os_free(h);
     csx_sai_free(h);
     csx_energy_free(h);
     void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qblk, h->t.qv, h->t.phi32,
                     h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
                     h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags,
-                    h->fplain, h->warm, h->a1, h->t.ra, h->t.rf};
+                    h->fplain, h->warm, h->a1, h->t.ra, h->t.rf, h->t.ram, h->t.rfm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     release_events(h);
@@ -153,40 +154,50 @@ static void free_all(csx_geometry *h)
 static csx_status store_set(csx_geometry *h, bool on)
 {
     HIP_TRY(hipDeviceSynchronize());
-    if (h->t.ra) HIP_TRY(hipFree(h->t.ra));
-    if (h->t.rf) HIP_TRY(hipFree(h->t.rf));
+    void *old[] = {h->t.ra, h->t.rf, h->t.ram, h->t.rfm};
+    for (void *p : old)
+        if (p) HIP_TRY(hipFree(p));
     h->t.ra = nullptr;
     h->t.rf = nullptr;
+    h->t.ram = nullptr;
+    h->t.rfm = nullptr;
     h->bytes -= h->store_bytes;
     h->store_bytes = 0;
     h->store_ms = 0.0;
     if (!on) return CSX_OK;
     if (!h->P.qu) return csx_fail(CSX_EINVAL, "the factor store needs a uniform q grid");
+    if (h->P.nq >= 65535) return csx_fail(CSX_EINVAL, "the factor store holds q-node ranges in 16 bits");
     size_t na, nf;
     csx_store_records(h->P, &na, &nf);
     uint4 *ra = nullptr, *rf = nullptr;
-    if (hipMalloc((void **)&ra, na * sizeof(uint4)) != hipSuccess) {
+    uint32_t *ram = nullptr, *rfm = nullptr;
+    auto release = [&]() {
+        void *ps[] = {ra, rf, ram, rfm};
+        for (void *p : ps)
+            if (p) (void)hipFree(p);
+    };
+    if (hipMalloc((void **)&ra, na * sizeof(uint4)) != hipSuccess ||
+        hipMalloc((void **)&rf, nf * 2 * sizeof(uint4)) != hipSuccess ||
+        hipMalloc((void **)&ram, na / 64 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&rfm, nf / 64 * sizeof(uint32_t)) != hipSuccess) {
         (void)hipGetLastError();
-        return csx_fail(CSX_ENOMEM, "factor store (adjoint records)");
-    }
-    if (hipMalloc((void **)&rf, nf * 2 * sizeof(uint4)) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(ra);
-        return csx_fail(CSX_ENOMEM, "factor store (forward records)");
+        release();
+        return csx_fail(CSX_ENOMEM, "factor store");
     }
     const auto t0 = std::chrono::steady_clock::now();
-    csx_status st = csx_launch_store(h, ra, rf, nullptr);
+    csx_status st = csx_launch_store(h, ra, rf, ram, rfm, nullptr);
     const hipError_t e = hipDeviceSynchronize();
     if (st == CSX_OK && e != hipSuccess) st = csx_fail(CSX_EHIP, std::string("factor store: ") + hipGetErrorString(e));
     if (st != CSX_OK) {
-        (void)hipFree(ra);
-        (void)hipFree(rf);
+        release();
         return st;
     }
     h->store_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     h->t.ra = ra;
     h->t.rf = rf;
-    h->store_bytes = (int64_t)((na + 2 * nf) * sizeof(uint4));
+    h->t.ram = ram;
+    h->t.rfm = rfm;
+    h->store_bytes = (int64_t)((na + 2 * nf) * sizeof(uint4) + (na + nf) / 64 * sizeof(uint32_t));
     h->bytes += h->store_bytes;
     return CSX_OK;
 }
@@ -376,13 +387,24 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     CSX_TRY(csx_launch_clear_flags(h, nullptr));
     // the factor store by default when it is small beside the device's free
     // memory (at most CSX_STORE_AUTO_BYTES and a quarter of what is free)
-    if (P.qu) {
+    if (P.qu && P.nq < 65535) {
         size_t na, nf, fr = 0, tot = 0;
         csx_store_records(P, &na, &nf);
-        const size_t need = (na + 2 * nf) * sizeof(uint4);
+        const size_t need = (na + 2 * nf) * sizeof(uint4) + (na + nf) / 64 * sizeof(uint32_t);
         if (hipMemGetInfo(&fr, &tot) == hipSuccess && need <= (size_t)CSX_STORE_AUTO_BYTES && need <= fr / 4) {
             const csx_status ss = store_set(h, true);
             if (ss != CSX_ENOMEM) CSX_TRY(ss);   // out of memory: the handle runs without a store
+        }
+    }
+    // the interval-form operators by default where they apply (their records
+    // are 8 bytes per class: at most CSX_STORE_AUTO_BYTES and a quarter of
+    // the free memory)
+    if (csx_iv_feasible(P, nullptr, nullptr)) {
+        size_t fr = 0, tot = 0;
+        const size_t need = (size_t)P.n_groups * P.ndx * (P.ndy / 2) * 8;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && need <= (size_t)CSX_STORE_AUTO_BYTES && need <= fr / 4) {
+            const csx_status si = csx_iv_build(h);
+            if (si != CSX_ENOMEM) CSX_TRY(si);
         }
     }
     {
@@ -454,6 +476,25 @@ extern "C" csx_status csx_set_factor_store(csx_geometry *h, int on)
     return store_set(h, on == 1);
 }
 
+extern "C" csx_status csx_set_interval_operators(csx_geometry *h, int on)
+{
+    if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
+    if (on != 0 && on != 1) return csx_fail(CSX_EINVAL, "on must be 0 or 1");
+    if (on && !csx_iv_feasible(h->P, nullptr, nullptr))
+        return csx_fail(CSX_EINVAL, "interval operators: thresholds, classes or LDS beyond their limits");
+    HIP_TRY(hipDeviceSynchronize());
+    csx_iv_free(h);
+    return on ? csx_iv_build(h) : CSX_OK;
+}
+
+extern "C" csx_status csx_get_interval_operators(const csx_geometry *h, int *on, int64_t *bytes, double *build_ms,
+                                                 int *intervals)
+{
+    if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
+    csx_iv_info(h, on, bytes, build_ms, intervals);
+    return CSX_OK;
+}
+
 extern "C" csx_status csx_get_factor_store(const csx_geometry *h, int *on, int64_t *bytes, double *build_ms)
 {
     if (!h) return csx_fail(CSX_EINVAL, "NULL handle");
@@ -497,7 +538,7 @@ extern "C" csx_status csx_forward(csx_geometry *h, const float *f, float *g, voi
 extern "C" csx_status csx_forward_noalloc(const csx_geometry *h, const float *f, float *g, void *stream)
 {
     if (!h || !f || !g) return csx_fail(CSX_EINVAL, "NULL argument");
-    const size_t need = (size_t)csx_forward_shape(h).nparts * h->P.npix;
+    const size_t need = h->iv ? csx_iv_part_floats(h) : (size_t)csx_forward_shape(h).nparts * h->P.npix;
     if (need > (size_t)CSX_SCRATCH_FLOATS)
         return csx_fail(CSX_EINVAL, "forward partials (" + std::to_string(need) + " floats) exceed the static scratch (" +
                                         std::to_string(CSX_SCRATCH_FLOATS) + " floats)");

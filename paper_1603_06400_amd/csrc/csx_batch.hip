@@ -4,7 +4,9 @@
 // One iteration issues, per kernel variant, a single forward launch and a
 // single adjoint launch that cover every active scan's blocks (largest scans
 // first, so the small scans fill the tail), plus the per-scan float64
-// data-term, update and objective kernels.  The iteration is captured into a
+// data-term, update and objective kernels.  Scans whose operators take the
+// interval form (csx_interval.hip) launch them per scan: each of those
+// launches already spans every compute unit.  The iteration is captured into a
 // HIP graph on a private stream and replayed; the objective kernels index the
 // J history through a device iteration counter, so the replays need no host
 // work.  Scans may have their own iteration counts: the run goes in stages
@@ -79,6 +81,7 @@ static void make_groups(const std::vector<csx_geometry *> &hs, const std::vector
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return scan_cost(hs[a]) > scan_cost(hs[b]); });
     for (int k : order) {
+        if (hs[k]->iv) continue;   // interval-form operators: launched per scan
         const OpShape S = forward ? csx_forward_shape(hs[k]) : csx_adjoint_shape(hs[k]);
         Group *g = nullptr;
         for (Group &c : out)
@@ -180,10 +183,15 @@ static csx_status issue_iteration(csx_batch *b, const std::vector<int> &active, 
     for (const Group &g : b->fwd) BT_TRY(launch_group(g, true, s));
     for (int k : active) {
         csx_geometry *h = b->h[k];
-        BT_TRY(csx_launch_sum_parts(h, csx_forward_shape(h).nparts, h->gws, s));
+        if (h->iv)
+            BT_TRY(csx_iv_forward(h, f[k], nullptr, 0, h->gws, s));
+        else
+            BT_TRY(csx_launch_sum_parts(h, csx_forward_shape(h).nparts, h->gws, s));
         BT_TRY(csx_launch_ratio(h, y[k], r ? r[k] : nullptr, true, s));
     }
     for (const Group &g : b->adj) BT_TRY(launch_group(g, false, s));
+    for (int k : active)
+        if (b->h[k]->iv) BT_TRY(csx_iv_adjoint(b->h[k], b->h[k]->rho, b->h[k]->b2, s));
     for (int k : active) {
         csx_geometry *h = b->h[k];
         BT_TRY(csx_launch_update(h, f[k], beta, true, s));
@@ -304,6 +312,8 @@ extern "C" csx_status csx_batch_recon_n(csx_batch *b, const float *const *y, con
             BT_TRY(upload_jobs(g, b->h, false, in, outp, s));
             BT_TRY(launch_group(g, false, s));
         }
+        for (int k : need)
+            if (b->h[k]->iv) BT_TRY(csx_iv_adjoint(b->h[k], b->h[k]->ones, b->h[k]->b1, s));
         for (int k : need) b->h[k]->have_b1 = true;
         HIP_TRY(hipStreamSynchronize(s));   // the job tables are rebuilt below
     }

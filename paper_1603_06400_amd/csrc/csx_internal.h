@@ -78,6 +78,11 @@ struct DevTables {
     // computed once per geometry; null when the operators evaluate them on the fly
     uint4 *ra = nullptr;       // adjoint records [n_groups][class tiles][64]: {kappa (f64), A, bits}
     uint4 *rf = nullptr;       // forward records [n_quad][voxel tiles][64][2]: {kappa1, kappa2}, {A1, A2, bits, 0}
+    // node range of each record tile (a superset over its 64 lanes, both
+    // forward classes): first q node in the low 16 bits, last in the high
+    // 16 bits; first > last when no lane of the tile is active
+    uint32_t *ram = nullptr;   // [n_groups][class tiles]
+    uint32_t *rfm = nullptr;   // [n_quad][voxel tiles]
 };
 
 // Bits of a stored record: the mask values of the class's pairs, and whether
@@ -156,6 +161,7 @@ struct csx_geometry {
     bool timing = false;
     std::vector<hipEvent_t> ev[2];
     int ev_used[2] = {0, 0};
+    void *iv = nullptr;        // interval-form operators (csx_interval.hip), when built
     int device = 0;            // the HIP device current at csx_init_geometry
     int64_t store_bytes = 0;   // device bytes of the factor store (0: none)
     double store_ms = 0.0;     // time its build took (host clock, synchronised)
@@ -187,10 +193,22 @@ csx_status csx_launch_forward_list(csx_geometry *h, const float *f, const int *q
 csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
                                    hipStream_t s);
 hipEvent_t csx_timing_event(csx_geometry *h, int op);
+// interval-form exact operators (csx_interval.hip)
+bool csx_iv_feasible(const KParams &P, int *lds_f, int *lds_a);
+csx_status csx_iv_build(csx_geometry *h);
+void csx_iv_free(csx_geometry *h);
+// forward into g; partial images in part (part_cap floats) or, when part is
+// null, in the handle's own buffer
+csx_status csx_iv_forward(const csx_geometry *h, const float *f, float *part, size_t part_cap, float *g,
+                          hipStream_t s);
+csx_status csx_iv_adjoint(const csx_geometry *h, const float *rho, float *b, hipStream_t s);
+size_t csx_iv_part_floats(const csx_geometry *h);
+void csx_iv_info(const csx_geometry *h, int *on, int64_t *bytes, double *build_ms, int *intervals);
 // factor store: record counts (16-byte adjoint records, 32-byte forward
 // records) and the kernels that fill them from the handle's tables
 void csx_store_records(const KParams &P, size_t *n_adj, size_t *n_fwd);
-csx_status csx_launch_store(const csx_geometry *h, uint4 *ra, uint4 *rf, hipStream_t s);
+csx_status csx_launch_store(const csx_geometry *h, uint4 *ra, uint4 *rf, uint32_t *ram, uint32_t *rfm,
+                            hipStream_t s);
 
 // solver pieces (csx_solver.hip)
 csx_status csx_launch_ratio(csx_geometry *h, const float *y, const float *r, bool want_rho,

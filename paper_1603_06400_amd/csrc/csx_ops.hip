@@ -51,6 +51,9 @@
 // capped at the chunk width
 constexpr int QB_ADJ = 16;
 constexpr int QB_FWD = 16;
+// q nodes per skip block when the factor store supplies each tile's node
+// range (a wave-uniform scalar test per block, no ballot)
+constexpr int QB_ST = 4;
 
 namespace {
 
@@ -268,12 +271,31 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
             // uniform q grid: u_m = u0 + m du, in-band nodes in the wave's range
             const double u0 = fma(kap, P.a0 + P.da * m0, b0), du = kap * P.da;
             int lo = QW, hi = -1;
-            if (act) band_range(P, u0, du, 0, QW, lo, hi);
-            constexpr int BA = QB_ADJ < QW ? QB_ADJ : QW;
+            if (ST) {
+                // the tile's node range (a superset of its lanes' ranges),
+                // wave-uniform: from the store's tile record, or reduced over
+                // the lanes for a class list
+                if (P.cls_list) {
+                    if (act) band_range(P, u0, du, 0, QW, lo, hi);
+                    lo = wave_min(lo);
+                    hi = wave_max(hi);
+                } else {
+                    const uint32_t tm = __builtin_amdgcn_readfirstlane(T.ram[(size_t)g * ntiles_all + t]);
+                    lo = (int)(tm & 0xffffu) - m0;
+                    hi = (int)(tm >> 16) - m0;
+                }
+            } else if (act) {
+                band_range(P, u0, du, 0, QW, lo, hi);
+            }
+            constexpr int BA = ST ? QB_ST : (QB_ADJ < QW ? QB_ADJ : QW);
 #pragma unroll
             for (int blk = 0; blk < QW / BA; ++blk) {
                 // skip a block no lane of the wave has in band (its triples add exact zeros)
-                if (__ballot(lo <= blk * BA + BA - 1 && hi >= blk * BA) == 0) continue;
+                if (ST) {
+                    if (blk * BA + BA - 1 < lo || blk * BA > hi) continue;
+                } else if (__ballot(lo <= blk * BA + BA - 1 && hi >= blk * BA) == 0) {
+                    continue;
+                }
                 // anchored by an FMA at each block's first node, then one add per node
                 double u = fma((double)(blk * BA), du, u0);
 #pragma unroll
@@ -418,16 +440,29 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
     // A tile and q chunk wholly inside the grid (a block-uniform test) loads
     // without per-value checks, so the loads issue together and their latency
     // overlaps the current tile's work.
+    // In-grid tiles: row r = sr + k RSTEP of the tile is group gl = sr/RPG +
+    // k G (G = RSTEP/RPG), at column offset (gl mod 8) and row offset gl/8;
+    // RSTEP is even, so every row of a thread is a mirror row or none is.
+    // With sr/RPG < 8 when G = 4 and G a multiple of 8 otherwise, the offsets
+    // split as (g0 mod 8) + a_k and g0/8 + b_k, a_k = kG mod 8, b_k = kG/8:
+    // one 32-bit byte offset per thread and tile plus a per-k constant.
+    constexpr int G = RSTEP / RPG;
+    const int g0 = sr / RPG;
+    const bool mir = LR && (sr & 1);
+    const uint32_t row_bytes = (uint32_t)P.nx * P.nq * 4u;          // one voxel row of f
+    const int col_bytes = (mir ? -P.nq : P.nq) * 4;                 // one voxel column, signed
     auto stage_load = [&](int t) {
         const int tx = t % ntx, ty = t / ntx;
         if (tx * 8 + 8 <= gw && ty * 8 + 8 <= P.nz && m0 + QW <= P.nq) {
+            const int ix0 = tx * 8 + (g0 & 7);
+            const int col = mir ? (P.nx - 1 - ix0) : ix0;
+            const uint32_t e0 = (uint32_t)(((ty * 8 + (g0 >> 3)) * P.nx + col) * P.nq + m0 + sm) * 4u;
+            const char *fb = (const char *)f;
 #pragma unroll
             for (int k = 0; k < NPASS; ++k) {
-                const int r = sr + k * RSTEP;
-                const int gl = r / RPG;
-                const int ix = tx * 8 + (gl & 7), iz = ty * 8 + (gl >> 3);
-                const int vox = iz * P.nx + ((LR && (r & 1)) ? (P.nx - 1 - ix) : ix);
-                pre[k] = f[(size_t)vox * P.nq + m0 + sm];
+                const int ak = (k * G) & 7, bk = (k * G) >> 3;
+                const uint32_t o = e0 + (uint32_t)bk * row_bytes + (uint32_t)(ak * col_bytes);
+                pre[k] = *(const float *)(fb + o);
             }
         } else {
 #pragma unroll
@@ -498,6 +533,8 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
         const double2 vm = nvm;
         const bool valid = nvalid;
         const uint4 r0 = nr0, r1 = nr1;
+        // ST: node range of the (quad, tile) pair, low 16 bits first node, high 16 bits last
+        const uint32_t tmeta = ST ? __builtin_amdgcn_readfirstlane(T.rfm[(size_t)qq * ntiles + t]) : 0u;
         if (t + 1 < t1) {
             stage_load(t + 1);
             load_vox(t + 1);
@@ -637,18 +674,29 @@ __device__ __forceinline__ void forward_body(const KParams &P, const DevTables &
             const double u10 = fma(k1, qa0, b0), du1 = k1 * P.da;
             const double u20 = fma(k2, qa0, b0), du2 = k2 * P.da;
             int lo = QW, hi = -1;
-            if (act1) band_range(P, u10, du1, 0, QW, lo, hi);
-            if (LR && act2) {
-                int l2, h2;
-                band_range(P, u20, du2, 0, QW, l2, h2);
-                lo = min(lo, l2);
-                hi = max(hi, h2);
+            if (ST) {
+                // the (quad, tile) node range from the store: wave-uniform, a
+                // superset of both classes' ranges over the lanes
+                lo = (int)(tmeta & 0xffffu) - m0;
+                hi = (int)(tmeta >> 16) - m0;
+            } else {
+                if (act1) band_range(P, u10, du1, 0, QW, lo, hi);
+                if (LR && act2) {
+                    int l2, h2;
+                    band_range(P, u20, du2, 0, QW, l2, h2);
+                    lo = min(lo, l2);
+                    hi = max(hi, h2);
+                }
             }
-            constexpr int BF = QB_FWD < QW ? QB_FWD : QW;
+            constexpr int BF = ST ? QB_ST : (QB_FWD < QW ? QB_FWD : QW);
 #pragma unroll
             for (int blk = 0; blk < QW / BF; ++blk) {
                 // skip a block no lane of the wave has in band (its triples add exact zeros)
-                if (__ballot(lo <= blk * BF + BF - 1 && hi >= blk * BF) == 0) continue;
+                if (ST) {
+                    if (blk * BF + BF - 1 < lo || blk * BF > hi) continue;
+                } else if (__ballot(lo <= blk * BF + BF - 1 && hi >= blk * BF) == 0) {
+                    continue;
+                }
                 // anchored by an FMA at each block's first node, then one add per node
                 double ua = fma((double)(blk * BF), du1, u10), ub = fma((double)(blk * BF), du2, u20);
 #pragma unroll
@@ -795,12 +843,36 @@ __global__ void __launch_bounds__(512) k_forward(KParams P, DevTables T, Lds L,
     forward_body<LR, QW, QU, 0, ST>(P, T, L, qa, qblk, f, part, tiles_per_split, bx, by, bz, gridDim.z);
 }
 
+// Global q-node range [lo, hi] of a class with Bragg factor kappa on a
+// uniform grid: the nodes whose bin coordinate u_m = u0 + m du can lie in
+// [1, ne + 1), with one node of margin each side (nodes outside add exact
+// zeros, so a superset is always safe).  Empty (lo > hi) when inactive.
+__device__ __forceinline__ void node_range(const KParams &P, bool active, double kappa, int &lo, int &hi)
+{
+    lo = 0xffff;
+    hi = -1;
+    if (!active) return;
+    const double u0 = fma(kappa, P.a0, P.b0), du = kappa * P.da;
+    const double a = floor((1.0 - u0) / du) - 1.0, b = floor(((double)P.ne + 1.0 - u0) / du) + 1.0;
+    lo = (int)fmin(fmax(a, 0.0), (double)(P.nq - 1));
+    hi = (int)fmin(fmax(b, 0.0), (double)(P.nq - 1));
+}
+
+// Tile record of the node ranges of a wave's 64 lanes (lane 0 writes).
+__device__ __forceinline__ void write_tile_range(uint32_t *dst, int lo, int hi)
+{
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if ((threadIdx.x & 63) == 0) *dst = lo > hi ? 0xffffu : ((uint32_t)lo | ((uint32_t)hi << 16));
+}
+
 // Factor store of the adjoint: the record of voxel group g and pixel class
 // (a, r) in tile t, lane l -- kappa, A and the mask values exactly as
 // adjoint_body evaluates them, A = kappa = 0 and no bits when the class is
 // inactive (every pair closed, or kappa out of band).  One thread per record.
 template <int LR>
-__global__ void __launch_bounds__(256) k_store_adjoint(KParams P, DevTables T, uint4 *__restrict__ out)
+__global__ void __launch_bounds__(256) k_store_adjoint(KParams P, DevTables T, uint4 *__restrict__ out,
+                                                       uint32_t *__restrict__ meta)
 {
     const int half_y = P.ndy / 2, ntx = (P.ndx + 7) / 8;
     const int ntl = ntx * ((half_y + 7) / 8);
@@ -841,6 +913,9 @@ __global__ void __launch_bounds__(256) k_store_adjoint(KParams P, DevTables T, u
     }
     const uint64_t ku = (uint64_t)__double_as_longlong(k);
     out[idx] = make_uint4((uint32_t)ku, (uint32_t)(ku >> 32), __float_as_uint(A), bits);
+    int lo, hi;
+    node_range(P, (bits & CSX_REC_ACT) != 0u, k, lo, hi);
+    write_tile_range(meta + idx / 64, lo, hi);
 }
 
 // Factor store of the forward: for pixel quad qq and voxel group (tile t,
@@ -848,7 +923,8 @@ __global__ void __launch_bounds__(256) k_store_adjoint(KParams P, DevTables T, u
 // class 2 at its mirror -a -- as two 16-byte words {kappa1, kappa2} and
 // {A1, A2, bits, 0}.  One thread per (quad, group).
 template <int LR>
-__global__ void __launch_bounds__(256) k_store_forward(KParams P, DevTables T, uint4 *__restrict__ out)
+__global__ void __launch_bounds__(256) k_store_forward(KParams P, DevTables T, uint4 *__restrict__ out,
+                                                       uint32_t *__restrict__ meta)
 {
     const int gw = LR ? P.nx / 2 : P.nx;
     const int ntx = (gw + 7) / 8;
@@ -908,6 +984,10 @@ __global__ void __launch_bounds__(256) k_store_forward(KParams P, DevTables T, u
     const size_t o = idx * 2;
     out[o] = make_uint4((uint32_t)u1, (uint32_t)(u1 >> 32), (uint32_t)u2, (uint32_t)(u2 >> 32));
     out[o + 1] = make_uint4(__float_as_uint(A1), __float_as_uint(A2), bits, 0u);
+    int lo1, hi1, lo2, hi2;
+    node_range(P, (bits & CSX_REC_ACT) != 0u, k1, lo1, hi1);
+    node_range(P, (bits & (CSX_REC_ACT << 8)) != 0u, k2, lo2, hi2);
+    write_tile_range(meta + idx / 64, min(lo1, lo2), max(hi1, hi2));
 }
 
 // Energy-resolved operators (the energy-sensitive detector of App. A).
@@ -1395,17 +1475,18 @@ void csx_store_records(const KParams &P, size_t *n_adj, size_t *n_fwd)
     *n_fwd = (size_t)P.n_quad * fwd_tiles(P) * 64;
 }
 
-csx_status csx_launch_store(const csx_geometry *h, uint4 *ra, uint4 *rf, hipStream_t s)
+csx_status csx_launch_store(const csx_geometry *h, uint4 *ra, uint4 *rf, uint32_t *ram, uint32_t *rfm,
+                            hipStream_t s)
 {
     size_t na, nf;
     csx_store_records(h->P, &na, &nf);
     const dim3 ga((unsigned)((na + 255) / 256)), gf((unsigned)((nf + 255) / 256));
     if (h->P.lr) {
-        hipLaunchKernelGGL(k_store_adjoint<1>, ga, dim3(256), 0, s, h->P, h->t, ra);
-        hipLaunchKernelGGL(k_store_forward<1>, gf, dim3(256), 0, s, h->P, h->t, rf);
+        hipLaunchKernelGGL(k_store_adjoint<1>, ga, dim3(256), 0, s, h->P, h->t, ra, ram);
+        hipLaunchKernelGGL(k_store_forward<1>, gf, dim3(256), 0, s, h->P, h->t, rf, rfm);
     } else {
-        hipLaunchKernelGGL(k_store_adjoint<0>, ga, dim3(256), 0, s, h->P, h->t, ra);
-        hipLaunchKernelGGL(k_store_forward<0>, gf, dim3(256), 0, s, h->P, h->t, rf);
+        hipLaunchKernelGGL(k_store_adjoint<0>, ga, dim3(256), 0, s, h->P, h->t, ra, ram);
+        hipLaunchKernelGGL(k_store_forward<0>, gf, dim3(256), 0, s, h->P, h->t, rf, rfm);
     }
     HIP_TRY(hipGetLastError());
     return CSX_OK;
@@ -1490,13 +1571,18 @@ csx_status csx_launch_sum_parts(csx_geometry *h, int nparts, float *g, hipStream
 
 csx_status csx_launch_forward(csx_geometry *h, const float *f, float *g, hipStream_t s)
 {
-    const OpShape S = csx_forward_shape(h);
     hipEvent_t e0 = csx_timing_event(h, 0), e1 = csx_timing_event(h, 0);
     if (e0) HIP_TRY(hipEventRecord(e0, s));
-    dispatch<RunFwd>(S.variant, S, h, f, h->part, s);
-    HIP_TRY(hipGetLastError());
-    csx_status st = csx_launch_sum_parts(h, S.nparts, g, s);
-    if (st != CSX_OK) return st;
+    if (h->iv) {
+        csx_status st = csx_iv_forward(h, f, nullptr, 0, g, s);
+        if (st != CSX_OK) return st;
+    } else {
+        const OpShape S = csx_forward_shape(h);
+        dispatch<RunFwd>(S.variant, S, h, f, h->part, s);
+        HIP_TRY(hipGetLastError());
+        csx_status st = csx_launch_sum_parts(h, S.nparts, g, s);
+        if (st != CSX_OK) return st;
+    }
     if (e1) HIP_TRY(hipEventRecord(e1, s));
     return CSX_OK;
 }
@@ -1504,6 +1590,7 @@ csx_status csx_launch_forward(csx_geometry *h, const float *f, float *g, hipStre
 csx_status csx_launch_forward_parts(const csx_geometry *h, const float *f, float *part, size_t part_cap, float *g,
                                     hipStream_t s)
 {
+    if (h->iv) return csx_iv_forward(h, f, part, part_cap, g, s);
     const OpShape S = csx_forward_shape(h);
     if ((size_t)S.nparts * h->P.npix > part_cap) return csx_fail(CSX_EINVAL, "forward partials exceed the buffer");
     dispatch<RunFwd>(S.variant, S, h, f, part, s);
@@ -1516,11 +1603,16 @@ csx_status csx_launch_forward_parts(const csx_geometry *h, const float *f, float
 
 csx_status csx_launch_adjoint(csx_geometry *h, const float *rho, float *b, hipStream_t s)
 {
-    const OpShape S = csx_adjoint_shape(h);
     hipEvent_t e0 = csx_timing_event(h, 1), e1 = csx_timing_event(h, 1);
     if (e0) HIP_TRY(hipEventRecord(e0, s));
-    dispatch<RunAdj>(S.variant, S, h, rho, b, s);
-    HIP_TRY(hipGetLastError());
+    if (h->iv) {
+        csx_status st = csx_iv_adjoint(h, rho, b, s);
+        if (st != CSX_OK) return st;
+    } else {
+        const OpShape S = csx_adjoint_shape(h);
+        dispatch<RunAdj>(S.variant, S, h, rho, b, s);
+        HIP_TRY(hipGetLastError());
+    }
     if (e1) HIP_TRY(hipEventRecord(e1, s));
     return CSX_OK;
 }

@@ -20,7 +20,7 @@ TABLE_F32, TABLE_BF16 = 0, 1
 PSI_QUADRATIC, PSI_HUBER = 0, 1
 OP_FORWARD_SAI, OP_ADJOINT_SAI = 1, 2
 SAI_MAX_NODES = 2048
-SCRATCH_FLOATS = 1 << 20        # CSX_SCRATCH_FLOATS: static scratch of csx_forward_noalloc
+SCRATCH_FLOATS = 1 << 22        # CSX_SCRATCH_FLOATS: static scratch of csx_forward_noalloc
 _NAMES = {CSX_EINVAL: "EINVAL", CSX_EGEOM: "EGEOM", CSX_EHIP: "EHIP", CSX_ENOMEM: "ENOMEM",
           CSX_ENUMERIC: "ENUMERIC"}
 
@@ -60,7 +60,8 @@ class _Info(ctypes.Structure):
 
 
 EXPORTS = ["csx_validate_desc", "csx_init_geometry", "csx_free_geometry", "csx_get_info",
-           "csx_set_factor_store", "csx_get_factor_store",
+           "csx_set_factor_store", "csx_get_factor_store", "csx_set_interval_operators",
+           "csx_get_interval_operators",
            "csx_forward", "csx_forward_noalloc", "csx_backproject", "csx_recon_step", "csx_recon", "csx_recon_os", "csx_set_penalty",
            "csx_get_launch", "csx_set_launch", "csx_batch_create", "csx_batch_free",
            "csx_batch_recon", "csx_batch_recon_n", "csx_timing_enable", "csx_timing_read", "csx_last_error",
@@ -101,6 +102,11 @@ def lib():
         L.csx_get_factor_store.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_double)]
         L.csx_get_factor_store.restype = ctypes.c_int
+        L.csx_set_interval_operators.argtypes = [vp, ctypes.c_int]
+        L.csx_set_interval_operators.restype = ctypes.c_int
+        L.csx_get_interval_operators.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
+                                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+        L.csx_get_interval_operators.restype = ctypes.c_int
         L.csx_forward_noalloc.argtypes = [vp, vp, vp, vp]
         L.csx_forward_noalloc.restype = ctypes.c_int
         L.csx_backproject.argtypes = [vp, vp, vp, vp]
@@ -278,6 +284,17 @@ class Geometry:
         on, nb, ms = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double()
         _check(lib().csx_get_factor_store(self._h, ctypes.byref(on), ctypes.byref(nb), ctypes.byref(ms)))
         return {"on": bool(on.value), "bytes": int(nb.value), "build_ms": float(ms.value)}
+
+    def set_interval_operators(self, on: bool) -> None:
+        """Build (True) or release (False) the interval form of the exact operators."""
+        _check(lib().csx_set_interval_operators(self._h, int(bool(on))))
+
+    def interval_operators(self) -> dict:
+        on, nb, ms, nt = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int()
+        _check(lib().csx_get_interval_operators(self._h, ctypes.byref(on), ctypes.byref(nb), ctypes.byref(ms),
+                                                ctypes.byref(nt)))
+        return {"on": bool(on.value), "bytes": int(nb.value), "build_ms": float(ms.value),
+                "intervals": int(nt.value)}
 
     def timing_enable(self, on: bool = True) -> None:
         _check(lib().csx_timing_enable(self._h, int(bool(on))))

@@ -1,0 +1,87 @@
+"""The interval form of the exact operators against the FP64 oracle and
+against the direct kernels.
+
+The interval operators re-associate Alg. 1 and Alg. 3: per voxel a float64
+prefix sum over the sorted spectrum-bin thresholds (forward), per voxel group
+float64 prefix sums of the class weights over the same intervals (adjoint).
+They decide every spectrum bin by the same float64 FMA per node, so they must
+meet the oracle bar (rel-L2 <= 1e-5, element cap 1e-4 of the largest value)
+and agree with the direct kernels to float32 rounding of differently ordered
+sums (rel-L2 <= 1e-6)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1603_06400_amd import csx, inputs
+
+from .gpu_helpers import assert_parity, ragged_geometry, rel_l2, workload_data
+from .test_gpu_parity import RAGGED, SYMMETRIC
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+CASES = [("ragged", c) for c in RAGGED] + [("symmetric", c) for c in SYMMETRIC]
+
+
+@pytest.mark.parametrize("kind,case", CASES, ids=[f"{k[0]}{c[0]}" for k, c in CASES])
+def test_interval_operators_match_oracle_and_direct(oracle_mod, kind, case):
+    print(f"[interval {kind} {case}]", flush=True)
+    g = ragged_geometry(*case) if kind == "ragged" else ragged_geometry(*case, x=(-40.0, 40.0))
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    info = geo.interval_operators()
+    assert info["on"], info
+    assert info["intervals"] == (g.ne + 1) * g.nq + 1
+    f = inputs.random_image(g, 900 + case[0])
+    y = inputs.random_detector(g, 950 + case[0])
+    fi, bi = host(geo.forward(dev(f))), host(geo.backproject(dev(y)))
+    assert_parity(fi, o.forward(f), what="forward (intervals)")
+    assert_parity(bi, o.adjoint(y), what="adjoint (intervals)")
+    geo.set_interval_operators(False)
+    fd, bd = host(geo.forward(dev(f))), host(geo.backproject(dev(y)))
+    ef, eb = rel_l2(fi, fd), rel_l2(bi, bd)
+    print(f"[intervals vs direct: forward {ef:.2e}, adjoint {eb:.2e}]", flush=True)
+    assert ef <= 1e-6 and eb <= 1e-6
+
+
+def test_interval_operators_are_deterministic():
+    w, g, ftrue, y = workload_data("slice32")
+    geo = csx.Geometry(g)
+    f, yd = dev(ftrue), dev(y)
+    a, b = host(geo.forward(f)), host(geo.backproject(yd))
+    for _ in range(3):
+        assert np.array_equal(host(geo.forward(f)), a)
+        assert np.array_equal(host(geo.backproject(yd)), b)
+
+
+def test_interval_slice128_full_outputs(oracle_mod):
+    """Every output of the benchmark workload's operators against the oracle."""
+    w, g, ftrue, y = workload_data("slice128")
+    geo = csx.Geometry(g)
+    info = geo.interval_operators()
+    print(f"[slice128 intervals: {info['intervals']} intervals, {info['bytes'] / 2**20:.0f} MiB, "
+          f"set-up {info['build_ms']:.1f} ms]", flush=True)
+    assert info["on"]
+    o = oracle_mod.Oracle(g)
+    assert_parity(host(geo.forward(dev(ftrue))), o.forward(ftrue), what="slice128 forward (intervals)")
+    assert_parity(host(geo.backproject(dev(y))), o.adjoint(y), what="slice128 adjoint (intervals)")
+
+
+def test_interval_operators_refused_beyond_their_limits():
+    # (ne + 1) nq = 257 * 64 >= 16384 thresholds
+    g = ragged_geometry(1, 10, 7, 12, 10, 64, 402.57, ne=256)
+    geo = csx.Geometry(g)
+    assert not geo.interval_operators()["on"]
+    with pytest.raises(csx.CsxError) as ei:
+        geo.set_interval_operators(True)
+    assert ei.value.code == csx.CSX_EINVAL
+    geo.set_interval_operators(False)

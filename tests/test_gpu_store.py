@@ -32,6 +32,9 @@ def host(t):
 
 
 def _both_paths(geo, f, y):
+    # the class-record store serves the direct kernels (the interval form,
+    # when built, takes precedence for the full operators)
+    geo.set_interval_operators(False)
     assert geo.factor_store()["on"]
     fs, bs = host(geo.forward(dev(f))), host(geo.backproject(dev(y)))
     geo.set_factor_store(False)
@@ -78,13 +81,15 @@ def test_store_slice128_operators_and_step(oracle_mod):
     geo = csx.Geometry(g)
     info = geo.factor_store()
     print(f"[slice128 store: {info['bytes'] / 2**30:.2f} GiB, built in {info['build_ms']:.1f} ms]", flush=True)
-    # records: 16 B per (voxel group, class), 32 B per (pixel quad, voxel group)
+    # records: 16 B per (voxel group, class), 32 B per (pixel quad, voxel
+    # group), and a 4-byte node range per 64-record tile
     n_groups, n_cls, n_quad = 128 * 64, 128 * 64, 64 * 64
-    assert info["bytes"] == n_groups * n_cls * 16 + n_quad * n_groups * 32
+    assert info["bytes"] == n_groups * n_cls * 16 + n_quad * n_groups * 32 + (n_groups * n_cls + n_quad * n_groups) // 16
     fs, bs, fo, bo = _both_paths(geo, ftrue, y)
     assert np.array_equal(fs, fo) and np.array_equal(bs, bo)
     f0 = np.full(ftrue.shape, 0.3)
     out = []
+    geo.set_interval_operators(False)
     for on in (True, False):
         geo.set_factor_store(on)
         fd = dev(f0)
