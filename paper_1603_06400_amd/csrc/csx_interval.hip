@@ -55,12 +55,14 @@ struct IvState {
     double *coef = nullptr;     // [nt] q_m (Phi~[c] - Phi~[c-1]) of the sorted thresholds
     uint16_t *mt = nullptr;     // [nt] node m of each sorted threshold
     uint16_t *pp = nullptr;     // [nq][ne + 2] pos(c, m) + 1, c = 1 .. ne + 1
+    uint16_t *bpos = nullptr;   // [n_groups][nq][ne + 1] rank of the first class of each (node, bin)
     double *qd = nullptr;       // [nq] q nodes
     float *part = nullptr;      // [nblk][npix] forward partial images
     int nt = 0;                 // thresholds, (ne + 1) nq
     int n_slots = 0;            // classes per voxel group (LR: 2 per mirror pair)
     int n_items = 0;            // work items per group: mirror pairs (LR) or classes
     int np = 1;                 // forward: work items per thread (power of 2, <= 8)
+    int npa = 1;                // adjoint: work items per thread (power of 2, <= 16)
     int nblk_f = 0, nblk_a = 0;
     int lds_f = 0, lds_a = 0;
     int64_t bytes = 0;
@@ -72,6 +74,7 @@ struct IvArgs {
     const double *coef;
     const uint16_t *mt;
     const uint16_t *pp;
+    const uint16_t *bpos;
     const double *qd;
     int nt, n_slots, n_items, ngroups;
 };
@@ -152,7 +155,8 @@ __global__ void __launch_bounds__(256) k_iv_records(KParams P, DevTables T, int 
 // Rank of every class of a voxel group in the order of (t, slot): a bitonic
 // sort of the keys (t << 14 | slot) in LDS, one block per group.  The rank
 // goes to bits 18-31 of the record.
-__global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, uint2 *__restrict__ rec)
+__global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, uint2 *__restrict__ rec, int nq, int ne,
+                                                  const uint16_t *__restrict__ pp, uint16_t *__restrict__ bpos)
 {
     extern __shared__ uint32_t keys[];
     uint2 *rg = rec + (size_t)blockIdx.x * n_slots;
@@ -177,6 +181,22 @@ __global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, uint2 
     for (int s = threadIdx.x; s < n_slots; s += blockDim.x) {
         const int i = (int)(keys[s] & 0x3FFFu);
         rg[i].y = (rg[i].y & 0x3FFFFu) | ((uint32_t)s << 18);
+    }
+    // bin positions of the group: for node m and bin c (1 .. ne + 1) the
+    // number of classes whose interval is below pp(c, m) = pos(c, m) + 1,
+    // i.e. the rank of the first class at or past that threshold
+    const int nt = (ne + 1) * nq;
+    uint16_t *bg = bpos + (size_t)blockIdx.x * nt;
+    for (int k = threadIdx.x; k < nt; k += blockDim.x) {
+        const int m = k / (ne + 1), c = 1 + k % (ne + 1);
+        const uint32_t T = pp[(size_t)m * (ne + 2) + c];
+        int lo = 0, hi = n_slots;          // first sorted position with t >= T
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((keys[mid] >> 14) < T) lo = mid + 1;
+            else hi = mid;
+        }
+        bg[k] = (uint16_t)lo;
     }
 }
 
@@ -203,24 +223,6 @@ __device__ __forceinline__ double2 block_exclusive_scan(double a, double b, doub
         ob += s_tot[w].y;
     }
     return make_double2(oa + ia - a, ob + ib - b);
-}
-
-// Block-wide minimum of v over the threads after this one (INT_MAX if none).
-__device__ __forceinline__ int block_suffix_min(int v, int *s_imin)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int x = v;                                   // inclusive suffix min within the wave
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_down(x, d, 64);
-        if (lane + d < 64) x = min(x, u);
-    }
-    if (lane == 0) s_imin[wv] = x;
-    __syncthreads();
-    int r = __shfl_down(x, 1, 64);
-    if (lane == 63) r = 0x7FFFFFFF;
-    for (int w = wv + 1; w < IV_WAVES; ++w) r = min(r, s_imin[w]);
-    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -355,14 +357,37 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
     }
 }
 
-// g_i = sum_p part[p][i] in a fixed order.
-__global__ void __launch_bounds__(256) k_iv_sum(const float *__restrict__ part, int nparts, int n, float *__restrict__ g)
+// g_i = sum_p part[p][i] in a fixed order: 64 pixels per block (the lanes),
+// 16 slices of the partial images (the waves), each slice's loads issued
+// together, then the 16 slice sums added in slice order.
+__global__ void __launch_bounds__(1024) k_iv_sum(const float *__restrict__ part, int nparts, int n,
+                                                 float *__restrict__ g)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.0f;
-    for (int p = 0; p < nparts; ++p) s += part[(size_t)p * n + i];
-    g[i] = s;
+    __shared__ float s_part[16][64];
+    const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    float acc = 0.0f;
+    if (i < n) {
+        constexpr int U = 8;
+        for (int p0 = sl; p0 < nparts; p0 += 16 * U) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = p0 + 16 * u;
+                v[u] = p < nparts ? part[(size_t)p * n + i] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += v[u];
+        }
+    }
+    s_part[sl][lane] = acc;
+    __syncthreads();
+    if (sl == 0 && i < n) {
+        float t = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += s_part[k][lane];
+        g[i] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -370,40 +395,46 @@ __global__ void __launch_bounds__(256) k_iv_sum(const float *__restrict__ part, 
 // voxel groups, one group at a time: class weights into LDS at their rank,
 // float64 prefix sums at every interval, then per (m, c) differences.
 // ---------------------------------------------------------------------------
-template <int LR, int NP>
-__global__ void __launch_bounds__(IV_THREADS) k_iv_adjoint(KParams P, IvArgs V, const DevTables T,
-                                                           const float *__restrict__ rho, float *__restrict__ b,
-                                                           int pp_in_lds)
+// Adjoint: b = A^T rho.  Blocks of IVA_THREADS threads (two per compute
+// unit), each a contiguous range of voxel groups, one group at a time:
+//  1. every class's weights (voxel j: A (T_u rho_u + T_d rho_d); voxel j2:
+//     the mirror pixels) go to LDS at the class's rank in the group's
+//     interval order;
+//  2. prefix sums in rank order: thread k owns ranks [k SC, (k+1) SC) and
+//     keeps their exclusive prefix within the chunk (float32, skewed layout:
+//     rank p at p + p / SC) and the chunk's base (float64 block scan), so the
+//     prefix E(p) = base[p / SC] + loc[p] has float64 accuracy where it
+//     matters (no cancellation of large partial sums);
+//  3. the classes in bin c at node m are the ranks [P(m, c), P(m, c + 1)),
+//     P from the set-up: b_jm = q_m sum_c Phi~[c] (E(P(m, c+1)) - E(P(m, c))).
+constexpr int IVA_THREADS = 512;
+constexpr int IVA_WAVES = IVA_THREADS / 64;
+constexpr int IVA_SUB = 8;          // threads per node in the gather
+
+template <int LR, int NP, int SCL>
+__global__ void __launch_bounds__(IVA_THREADS, 4) k_iv_adjoint(KParams P, IvArgs V, const DevTables T,
+                                                            const float *__restrict__ rho, float *__restrict__ b)
 {
+    constexpr int SC = 1 << SCL;
     extern __shared__ __align__(16) unsigned char lds[];
-    double2 *s_W = (double2 *)lds;                                  // [nt + 2]
-    float2 *s_w = (float2 *)(s_W + V.nt + 2);                       // [n_slots]
-    uint16_t *s_t = (uint16_t *)(s_w + V.n_slots);                  // [n_slots]
-    uint8_t *s_mark = (uint8_t *)(s_t + V.n_slots);                 // [nt + 2]
-    float *s_phi = (float *)(((uintptr_t)(s_mark + V.nt + 2) + 15) & ~(uintptr_t)15);   // [ne + 2]
+    float2 *s_loc = (float2 *)lds;                                        // [(IVA_THREADS + 1) (SC + 1)]
+    double2 *s_base = (double2 *)(s_loc + (IVA_THREADS + 1) * (SC + 1));  // [IVA_THREADS + 1]
+    float *s_phi = (float *)(s_base + IVA_THREADS + 1);                   // [ne + 2]
     double2 *s_tot = (double2 *)(((uintptr_t)(s_phi + P.ne + 2) + 15) & ~(uintptr_t)15);
-    int *s_imin = (int *)(s_tot + IV_WAVES);
-    uint16_t *s_pp = (uint16_t *)(s_imin + IV_WAVES);               // [nq][ne + 2] when it fits
     const int tid = threadIdx.x;
-    for (int k = tid; k < P.ne + 2; k += IV_THREADS)
+    for (int k = tid; k < P.ne + 2; k += IVA_THREADS)
         s_phi[k] = P.td == CSX_TABLE_BF16 ? bf16_to_f32(T.phi16[k]) : T.phi32[k];
-    const int npp = P.nq * (P.ne + 2);
-    if (pp_in_lds)
-        for (int k = tid; k < npp; k += IV_THREADS) s_pp[k] = V.pp[k];
-    const uint16_t *pp = pp_in_lds ? s_pp : V.pp;
+    // ranks past the last class hold zero weight for every group
+    for (int k = tid; k < (IVA_THREADS + 1) * (SC + 1); k += IVA_THREADS) s_loc[k] = make_float2(0.0f, 0.0f);
     const int per = (V.ngroups + gridDim.x - 1) / gridDim.x;
     const int g0 = blockIdx.x * per, g1 = min(V.ngroups, g0 + per);
-    const int sper = (V.n_slots + IV_THREADS - 1) / IV_THREADS;
-    const int s0 = min(V.n_slots, tid * sper), s1 = min(V.n_slots, s0 + sper);
-    // this thread's share of the intervals 0 .. nt + 1 in the fill
-    const int wper = (V.nt + 2 + IV_THREADS - 1) / IV_THREADS;
-    const int w0 = min(V.nt + 2, tid * wper), w1 = min(V.nt + 2, w0 + wper);
     const int half_y = P.ndy / 2;
+    const int nt = V.nt, ne1 = P.ne + 1;
     // the detector values of the thread's items are the same for every group
     float ru[NP], rd[NP], rbu[NP], rbd[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-        const int p = tid + i * IV_THREADS;
+        const int p = tid + i * IVA_THREADS;
         ru[i] = rd[i] = rbu[i] = rbd[i] = 0.0f;
         if (p < V.n_items) {
             int a, r;
@@ -418,106 +449,88 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_adjoint(KParams P, IvArgs V, 
             }
         }
     }
-    // records of the thread's items, prefetched one group ahead
+    // records of the thread's items, prefetched one group ahead (item i's
+    // next record is requested as soon as its current one is used)
     uint4 nr[NP];
-    auto load_rec = [&](int g) {
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            const int p = tid + i * IV_THREADS;
-            nr[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (p < V.n_items && g < g1) {
-                const uint2 *rg = V.rec + (size_t)g * V.n_slots;
-                if (LR) {
-                    nr[i] = *(const uint4 *)(rg + 2 * p);
-                } else {
-                    const uint2 v = rg[p];
-                    nr[i] = make_uint4(v.x, v.y, 0u, 0u);
-                }
-            }
+    auto load_one = [&](int g, int i) -> uint4 {
+        const int p = tid + i * IVA_THREADS;
+        if (p < V.n_items && g < g1) {
+            const uint2 *rg = V.rec + (size_t)g * V.n_slots;
+            if (LR) return *(const uint4 *)(rg + 2 * p);
+            const uint2 v = rg[p];
+            return make_uint4(v.x, v.y, 0u, 0u);
         }
+        return make_uint4(0u, 0u, 0u, 0u);
     };
-    load_rec(g0);
+    auto E = [&](int p) -> double2 {
+        const double2 bs = s_base[p >> SCL];
+        const float2 l = s_loc[p + (p >> SCL)];
+        return make_double2(bs.x + (double)l.x, bs.y + (double)l.y);
+    };
+#pragma unroll
+    for (int i = 0; i < NP; ++i) nr[i] = load_one(g0, i);
     for (int g = g0; g < g1; ++g) {
         int j, j2;
         group_voxels(P, LR, g, j, j2);
-        for (int t = w0; t < w1; ++t) s_mark[t] = 0;
-        uint4 cr[NP];
-#pragma unroll
-        for (int i = 0; i < NP; ++i) cr[i] = nr[i];
-        load_rec(g + 1);
-        // class weights at their rank
+        // 1. class weights at their rank
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-            const int p = tid + i * IV_THREADS;
+            const uint4 cr = nr[i];
+            nr[i] = load_one(g + 1, i);
+            const int p = tid + i * IVA_THREADS;
             if (p >= V.n_items) continue;
-            const float A1 = __uint_as_float(cr[i].x);
-            const uint32_t w1 = cr[i].y;
+            const float A1 = __uint_as_float(cr.x);
+            const uint32_t w1 = cr.y;
             const float c10 = A1 * ((float)(w1 & 1u) * ru[i] + (float)((w1 >> 1) & 1u) * rd[i]);
             float c11 = 0.0f;
             if (LR) {
                 c11 = A1 * ((float)((w1 >> 2) & 1u) * rbu[i] + (float)((w1 >> 3) & 1u) * rbd[i]);
-                const float A2 = __uint_as_float(cr[i].z);
-                const uint32_t w2 = cr[i].w;
+                const float A2 = __uint_as_float(cr.z);
+                const uint32_t w2 = cr.w;
                 const float c20 = A2 * ((float)(w2 & 1u) * rbu[i] + (float)((w2 >> 1) & 1u) * rbd[i]);
                 const float c21 = A2 * ((float)((w2 >> 2) & 1u) * ru[i] + (float)((w2 >> 3) & 1u) * rd[i]);
-                s_w[w2 >> 18] = make_float2(c20, c21);
-                s_t[w2 >> 18] = (uint16_t)((w2 >> 4) & 0x3FFFu);
+                const int k2 = (int)(w2 >> 18);
+                s_loc[k2 + (k2 >> SCL)] = make_float2(c20, c21);
             }
-            s_w[w1 >> 18] = make_float2(c10, c11);
-            s_t[w1 >> 18] = (uint16_t)((w1 >> 4) & 0x3FFFu);
+            const int k1 = (int)(w1 >> 18);
+            s_loc[k1 + (k1 >> SCL)] = make_float2(c10, c11);
         }
         __syncthreads();
-        // prefix sums in rank order; W(t) = sum of weights with interval < t
-        double la = 0.0, lb = 0.0;
-        for (int s = s0; s < s1; ++s) {
-            const float2 w = s_w[s];
-            la += (double)w.x;
-            lb += (double)w.y;
-        }
-        double2 e = block_exclusive_scan(la, lb, s_tot);
-        // W at the first interval of every run of equal t (the classes are in
-        // t order), and the total at the sentinel nt + 1 ...
-        for (int s = s0; s < s1; ++s) {
-            const int ts = s_t[s];
-            if (s == 0 || (int)s_t[s - 1] != ts) {
-                s_W[ts] = e;
-                s_mark[ts] = 1;
+        // 2. chunk prefixes and bases
+        {
+            float2 *ch = s_loc + tid * (SC + 1);
+            float la = 0.0f, lb = 0.0f;
+            double da = 0.0, db = 0.0;
+#pragma unroll
+            for (int k = 0; k < SC; ++k) {
+                const float2 w = ch[k];
+                ch[k] = make_float2(la, lb);
+                la += w.x;
+                lb += w.y;
+                da += (double)w.x;
+                db += (double)w.y;
             }
-            const float2 w = s_w[s];
-            e.x += (double)w.x;
-            e.y += (double)w.y;
-            if (s == V.n_slots - 1) {
-                s_W[V.nt + 1] = e;
-                s_mark[V.nt + 1] = 1;
-            }
+            const double2 base = block_exclusive_scan(da, db, s_tot);
+            s_base[tid] = base;
+            if (tid == IVA_THREADS - 1) s_base[IVA_THREADS] = make_double2(base.x + da, base.y + db);
         }
         __syncthreads();
-        // ... and every other interval takes the value of the nearest marked
-        // one to its right (no class has t in between), in parallel
-        int lm = 0x7FFFFFFF;
-        for (int t = w1 - 1; t >= w0; --t)
-            if (s_mark[t]) lm = t;
-        int cur = block_suffix_min(lm, s_imin);
-        for (int t = w1 - 1; t >= w0; --t) {
-            if (s_mark[t]) cur = t;
-            else s_W[t] = s_W[cur];
-        }
-        __syncthreads();
-        // b_jm = q_m sum_c Phi~[c] (W(pp(c+1, m)) - W(pp(c, m))), 16 lanes per node
-        for (int mb = 0; mb < P.nq; mb += IV_THREADS / 16) {
-            const int m = mb + (tid >> 4), sub = tid & 15;
+        // 3. b_jm = q_m sum_c Phi~[c] (E(P(m, c+1)) - E(P(m, c))), IVA_SUB threads per node
+        const uint16_t *bg = V.bpos + (size_t)g * nt;
+        for (int mb = 0; mb < P.nq; mb += IVA_THREADS / IVA_SUB) {
+            const int m = mb + tid / IVA_SUB, sub = tid % IVA_SUB;
             double sa = 0.0, sb = 0.0;
             if (m < P.nq) {
-                const uint16_t *pm = pp + (size_t)m * (P.ne + 2);
-                for (int c = 1 + sub; c <= P.ne; c += 16) {
+                const uint16_t *pm = bg + (size_t)m * ne1;       // pm[c - 1] = P(m, c), c = 1 .. ne + 1
+                for (int c = 1 + sub; c <= P.ne; c += IVA_SUB) {
                     const double ph = (double)s_phi[c];
-                    const double2 hi = s_W[pm[c + 1]], lo = s_W[pm[c]];
+                    const double2 hi = E(pm[c]), lo = E(pm[c - 1]);
                     sa = fma(ph, hi.x - lo.x, sa);
                     sb = fma(ph, hi.y - lo.y, sb);
                 }
             }
 #pragma unroll
-            for (int d = 8; d > 0; d >>= 1) {
+            for (int d = IVA_SUB / 2; d > 0; d >>= 1) {
                 sa += __shfl_xor(sa, d, 64);
                 sb += __shfl_xor(sb, d, 64);
             }
@@ -527,6 +540,7 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_adjoint(KParams P, IvArgs V, 
                 if (LR) b[(size_t)j2 * P.nq + m] = (float)(qm * sb);
             }
         }
+        __syncthreads();   // the next group's weights overwrite s_loc
     }
 }
 
@@ -537,6 +551,7 @@ IvArgs iv_args(const csx_geometry *h, const IvState *v)
     a.coef = v->coef;
     a.mt = v->mt;
     a.pp = v->pp;
+    a.bpos = v->bpos;
     a.qd = v->qd;
     a.nt = v->nt;
     a.n_slots = v->n_slots;
@@ -556,7 +571,7 @@ csx_status iv_upload(T **dst, const std::vector<T> &src, int64_t &bytes)
 
 void iv_release(IvState *v)
 {
-    void *ps[] = {v->rec, v->coef, v->mt, v->pp, v->qd, v->part};
+    void *ps[] = {v->rec, v->coef, v->mt, v->pp, v->bpos, v->qd, v->part};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete v;
@@ -571,20 +586,15 @@ bool csx_iv_feasible(const KParams &P, int *lds_f, int *lds_a)
     const long nt = (long)(P.ne + 1) * P.nq;
     const long items = P.lr ? (long)(P.ndx / 2) * (P.ndy / 2) : (long)P.ndx * (P.ndy / 2);
     const long slots = P.lr ? 2 * items : items;
-    if (nt >= 16384 || slots > 16384 || items > 8L * IV_THREADS || 2 * P.nq > IV_THREADS) return false;
+    // intervals and ranks in 14 bits; the adjoint's ranks in IVA_THREADS
+    // chunks of 16; one f value per forward thread
+    if (nt >= 16384 || slots > 16 * IVA_THREADS || items > 8L * IV_THREADS || 2 * P.nq > IV_THREADS) return false;
     const long lf = ((nt * 10 + 15) & ~15L) + (nt + 1) * 8 + 2L * P.nq * 4 + 16 + IV_WAVES * 16;
-    const long la = (nt + 2) * 17 + slots * 10 + 16 + (P.ne + 2) * 4 + 16 + IV_WAVES * 20;
+    const long la = (long)(IVA_THREADS + 1) * 17 * 8 + (IVA_THREADS + 1) * 16 + (P.ne + 2) * 4 + 16 + IVA_WAVES * 16;
     if (lf > CSX_LDS_MAX || la > CSX_LDS_MAX) return false;
     if (lds_f) *lds_f = (int)lf;
     if (lds_a) *lds_a = (int)la;
     return true;
-}
-
-// LDS of the adjoint with its (node, bin) position table staged, if it fits.
-static int iv_adjoint_lds_with_pp(const KParams &P, int lds_a)
-{
-    const long l = lds_a + (long)P.nq * (P.ne + 2) * 2;
-    return l <= CSX_LDS_MAX ? (int)l : 0;
 }
 
 void csx_iv_free(csx_geometry *h)
@@ -673,9 +683,12 @@ csx_status csx_iv_build(csx_geometry *h)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
         cus = 256;
     {
-        const int per = (P.n_groups + cus - 1) / cus;            // groups per block
+        int per = (P.n_groups + cus - 1) / cus;                  // forward: one block per compute unit
         v->nblk_f = (P.n_groups + per - 1) / per;
-        v->nblk_a = v->nblk_f;
+        per = (P.n_groups + 2 * cus - 1) / (2 * cus);            // adjoint: two
+        v->nblk_a = (P.n_groups + per - 1) / per;
+        v->npa = 1;
+        while (v->npa * IVA_THREADS < v->n_items) v->npa *= 2;
     }
     csx_status st;
     if ((st = iv_upload(&v->coef, coef, v->bytes)) != CSX_OK) return bail(st);
@@ -683,12 +696,14 @@ csx_status csx_iv_build(csx_geometry *h)
     if ((st = iv_upload(&v->pp, pp, v->bytes)) != CSX_OK) return bail(st);
     if ((st = iv_upload(&v->qd, qd, v->bytes)) != CSX_OK) return bail(st);
     const size_t nrec = (size_t)P.n_groups * v->n_slots;
+    const size_t nbpos = (size_t)P.n_groups * nt;
     if (hipMalloc((void **)&v->rec, nrec * sizeof(uint2)) != hipSuccess ||
+        hipMalloc((void **)&v->bpos, nbpos * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc((void **)&v->part, (size_t)v->nblk_f * P.npix * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         return bail(csx_fail(CSX_ENOMEM, "interval operators: records"));
     }
-    v->bytes += (int64_t)(nrec * sizeof(uint2) + (size_t)v->nblk_f * P.npix * sizeof(float));
+    v->bytes += (int64_t)(nrec * sizeof(uint2) + nbpos * sizeof(uint16_t) + (size_t)v->nblk_f * P.npix * sizeof(float));
     const dim3 gr((unsigned)((nrec + 255) / 256));
     if (P.lr)
         hipLaunchKernelGGL(k_iv_records<1>, gr, dim3(256), 0, nullptr, P, h->t, v->n_slots, v->rec);
@@ -696,7 +711,8 @@ csx_status csx_iv_build(csx_geometry *h)
         hipLaunchKernelGGL(k_iv_records<0>, gr, dim3(256), 0, nullptr, P, h->t, v->n_slots, v->rec);
     int npow2 = 1;
     while (npow2 < v->n_slots) npow2 *= 2;
-    hipLaunchKernelGGL(k_iv_rank, dim3(P.n_groups), dim3(1024), npow2 * 4, nullptr, v->n_slots, npow2, v->rec);
+    hipLaunchKernelGGL(k_iv_rank, dim3(P.n_groups), dim3(1024), npow2 * 4, nullptr, v->n_slots, npow2, v->rec, nq, ne,
+                       (const uint16_t *)v->pp, v->bpos);
     {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return bail(csx_fail(CSX_EHIP, std::string("interval set-up: ") + hipGetErrorString(e)));
@@ -732,7 +748,7 @@ csx_status csx_iv_forward(const csx_geometry *h, const float *f, float *part, si
     }
 #undef CSX_IVF
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_iv_sum, dim3((h->P.npix + 255) / 256), dim3(256), 0, s, (const float *)part, v->nblk_f,
+    hipLaunchKernelGGL(k_iv_sum, dim3((h->P.npix + 63) / 64), dim3(1024), 0, s, (const float *)part, v->nblk_f,
                        h->P.npix, g);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
@@ -742,21 +758,20 @@ csx_status csx_iv_adjoint(const csx_geometry *h, const float *rho, float *b, hip
 {
     const IvState *v = (const IvState *)h->iv;
     const IvArgs a = iv_args(h, v);
-    const dim3 grid(v->nblk_a), block(IV_THREADS);
-    const int lpp = iv_adjoint_lds_with_pp(h->P, v->lds_a);
-    const int lds = lpp ? lpp : v->lds_a, in_lds = lpp ? 1 : 0;
+    const dim3 grid(v->nblk_a), block(IVA_THREADS);
 #define CSX_IVA(LR_, NP_) \
-    hipLaunchKernelGGL((k_iv_adjoint<LR_, NP_>), grid, block, lds, s, h->P, a, h->t, rho, b, in_lds)
+    hipLaunchKernelGGL((k_iv_adjoint<LR_, NP_, 4>), grid, block, v->lds_a, s, h->P, a, h->t, rho, b)
     if (h->P.lr) {
-        if (v->np == 1) CSX_IVA(1, 1);
-        else if (v->np == 2) CSX_IVA(1, 2);
-        else if (v->np == 4) CSX_IVA(1, 4);
+        if (v->npa == 1) CSX_IVA(1, 1);
+        else if (v->npa == 2) CSX_IVA(1, 2);
+        else if (v->npa == 4) CSX_IVA(1, 4);
         else CSX_IVA(1, 8);
     } else {
-        if (v->np == 1) CSX_IVA(0, 1);
-        else if (v->np == 2) CSX_IVA(0, 2);
-        else if (v->np == 4) CSX_IVA(0, 4);
-        else CSX_IVA(0, 8);
+        if (v->npa == 1) CSX_IVA(0, 1);
+        else if (v->npa == 2) CSX_IVA(0, 2);
+        else if (v->npa == 4) CSX_IVA(0, 4);
+        else if (v->npa == 8) CSX_IVA(0, 8);
+        else CSX_IVA(0, 16);
     }
 #undef CSX_IVA
     HIP_TRY(hipGetLastError());

@@ -5,7 +5,9 @@ kernels, same partial images, same fixed-order sum), on two calls in a row
 whose second input is smaller, and on a third call back at the larger size
 (the scratch keeps the last call's contents, which no result may depend on).
 A forward whose partial images exceed the scratch is refused before any launch,
-and fits after fewer voxel splits."""
+and fits after fewer voxel splits.  The consecutive calls run the interval
+form of the forward (its partial images, one per workgroup, in the scratch);
+the refusal case runs the direct forward."""
 import numpy as np
 import pytest
 
@@ -45,10 +47,12 @@ def test_noalloc_forward_equals_forward_on_consecutive_calls():
 
 
 def test_noalloc_forward_refuses_partials_beyond_the_scratch():
-    # 64^2 voxels (32 voxel tiles, 8 splits) against a 512^2 detector:
-    # 8 partial images of 262144 pixels, twice the scratch
-    g = inputs.standard_geometry(64, 16, ndet=512)
+    # 32 x 40 voxels (10 voxel tiles, 5 splits) against a 1024^2 detector:
+    # 5 partial images of 2^20 pixels, more than the 2^22-float scratch (the
+    # detector is too large for the interval form, so the direct forward runs)
+    g = inputs.standard_geometry(32, 16, ndet=1024).with_(nz=40)
     geo = csx.Geometry(g)
+    assert not geo.interval_operators()["on"]
     parts = geo.get_launch()["fwd_splits"] * geo.npix
     assert parts > csx.SCRATCH_FLOATS, parts
     f = _image(geo, 5)
