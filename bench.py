@@ -14,15 +14,18 @@ nominal voxel*pixel*q evaluations of one forward plus one adjoint
     python bench.py --workload sai [--steps K] [--sai-interp linear|nearest]
     python bench.py --workload energy [--steps K]
 
-Prints one JSON line.  The roofline entry uses the work model of the
-operators as they run: 4 VALU lane-ops per open in-band triple, plus, when the
-pair factors are evaluated on the fly, 60 per open pair and 10 per pair, or,
-with the factor store (the default), 20 per stored class record read (the
-factor work itself is done once per geometry and is not counted); the
+Prints one JSON line.  The operators run in interval form by default (the
+sum over q of a class read from per-voxel tables over the sorted spectrum-bin
+thresholds); each reads its 8-byte class records once per call, so the
+roofline entry is HBM-bound: algorithmic bytes per launch (class records,
+the adjoint's per-group bin positions, the input and output arrays) over the
 event-timed average duration of the dominant operator inside the timed
-region; and the non-packed FP32 VALU issue rate of the chip from its unit
-counts and clock.  The rate an FMA-chain kernel reaches on the device is
-quoted beside it.
+region, against 8 TB/s.  When the direct kernels run instead (the interval
+form switched off or not applicable), the entry is VALU-bound with their work
+model: 4 lane-ops per open in-band triple plus 60 per open pair and 10 per
+pair on the fly, or 20 per class record of the factor store, against the
+non-packed FP32 issue rate of the chip (an FMA-chain kernel's measured rate
+beside it).  Wall times of the bench's phases are printed with the line.
 """
 import argparse
 import hashlib
@@ -38,18 +41,21 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "slice128"
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: 3.93e13 lane-ops/s
+PEAK_HBM = 8.0e12                         # bytes/s
 OPS_PER_TRIPLE, OPS_PER_OPEN_PAIR, OPS_PER_PAIR = 4.0, 60.0, 10.0
 OPS_PER_RECORD = 20.0                     # factor store: unpack a class record, weights, band range
 GOLDEN = os.path.join(ROOT, "tests", "golden")
-SRC = os.path.join(ROOT, "paper_1603_06400_amd", "csrc", "csx_ops.hip")
+SRC = [os.path.join(ROOT, "paper_1603_06400_amd", "csrc", n) for n in ("csx_ops.hip", "csx_interval.hip")]
 
 
 def source_hash() -> str:
-    """Hash of the operator source's code (comments and whitespace removed), so
+    """Hash of the operator sources' code (comments and whitespace removed), so
     that the stored counters follow code changes but not comment edits."""
     import re
-    with open(SRC, encoding="utf-8") as fh:
-        text = fh.read()
+    text = ""
+    for path in ([SRC] if isinstance(SRC, str) else SRC):
+        with open(path, encoding="utf-8") as fh:
+            text += fh.read()
     text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
     text = re.sub(r"//[^\n]*", " ", text)
     text = " ".join(text.split())
@@ -64,6 +70,20 @@ def algorithmic_ops(census: dict, stored: bool = False, pairs_per_class: int = 4
         return OPS_PER_TRIPLE * census["open_triples_in_band"] + OPS_PER_RECORD * census["pairs"] / pairs_per_class
     return (OPS_PER_TRIPLE * census["open_triples_in_band"] + OPS_PER_OPEN_PAIR * census["open_pairs"]
             + OPS_PER_PAIR * census["pairs"])
+
+
+def interval_bytes(g, lr: bool) -> dict:
+    """Algorithmic HBM bytes of one interval-form forward and adjoint launch:
+    the 8-byte class records (every voxel group x every class of the upper
+    detector half), the adjoint's uint16 bin positions (one per node and bin
+    edge per group), the image and the detector arrays."""
+    groups = g.nz * (g.nx // 2) if lr else g.nz * g.nx
+    classes = g.ndx * (g.ndy // 2)
+    records = 8.0 * groups * classes
+    image, det = 4.0 * g.nvox * g.nq, 4.0 * g.npix
+    positions = 2.0 * groups * (g.ne + 1) * g.nq
+    return {"forward": records + image + det, "adjoint": records + positions + det + image,
+            "records": records, "positions": positions}
 
 
 def stored_traffic(kernel: str):
@@ -297,6 +317,8 @@ def bench_os(args):
 
     from paper_1603_06400_amd import csx, inputs
 
+    phases = {}
+    tp = time.perf_counter()
     w = inputs.workload(WORKLOAD)
     z = np.load(os.path.join(GOLDEN, f"{WORKLOAD}_counts.npz"))
     g = w.geom.with_(C=float(z["C"]))
@@ -333,6 +355,8 @@ def bench_sai(args):
 
     from paper_1603_06400_amd import csx, inputs
 
+    phases = {}
+    tp = time.perf_counter()
     w = inputs.workload(WORKLOAD)
     z = np.load(os.path.join(GOLDEN, f"{WORKLOAD}_counts.npz"))
     g = w.geom.with_(C=float(z["C"]))
@@ -439,6 +463,8 @@ def bench_energy(args):
 
     from paper_1603_06400_amd import csx, inputs
 
+    phases = {}
+    tp = time.perf_counter()
     w = inputs.workload(WORKLOAD)
     z = np.load(os.path.join(GOLDEN, f"{WORKLOAD}_counts.npz"))
     g = w.geom.with_(C=float(z["C"]))
@@ -569,6 +595,8 @@ def main():
 
     from paper_1603_06400_amd import csx, inputs
 
+    phases = {}
+    tp = time.perf_counter()
     w = inputs.workload(WORKLOAD)
     z = np.load(os.path.join(GOLDEN, f"{WORKLOAD}_counts.npz"))
     g = w.geom.with_(C=float(z["C"]))
@@ -577,6 +605,7 @@ def main():
         census = json.load(fh)
     torch.cuda.set_device(0)
     geo = csx.Geometry(g)
+    ivi = geo.interval_operators()
     y_d = torch.tensor(y, dtype=torch.float32, device="cuda")
     f_d = geo.new_image()
     J = torch.zeros(max(1, args.steps), dtype=torch.float64, device="cuda")
@@ -604,23 +633,37 @@ def main():
 
     fwd_ms = tim["forward_ms"] / max(1, tim["forward_n"])
     adj_ms = tim["adjoint_ms"] / max(1, tim["adjoint_n"])
+    phases["gpu_setup_and_timed_steps_s"] = time.perf_counter() - tp
     store = geo.factor_store()
-    ops = algorithmic_ops(census, stored=store["on"], pairs_per_class=4 if geo.info()["symmetric_lr"] else 2)
-    if adj_ms >= fwd_ms:
-        dom, dom_ms, kname = "adjoint", adj_ms, "k_adjoint"
+    lr = bool(geo.info()["symmetric_lr"])
+    dom = "adjoint" if adj_ms >= fwd_ms else "forward"
+    dom_ms = max(adj_ms, fwd_ms)
+    if ivi["on"]:
+        nb = interval_bytes(g, lr)
+        kname = "k_iv_adjoint" if dom == "adjoint" else "k_iv_forward"
+        achieved = nb[dom] / (dom_ms * 1e-3)
+        traffic = stored_traffic(kname)
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": traffic,
+                    "bytes_per_launch": nb[dom], "bytes_model": "8 B per class record + the adjoint's 2 B bin "
+                    "positions per (node, bin edge) and voxel group + image + detector arrays",
+                    "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
+                    "forward_GB_per_s": nb["forward"] / (fwd_ms * 1e-3) / 1e9,
+                    "adjoint_GB_per_s": nb["adjoint"] / (adj_ms * 1e-3) / 1e9}
     else:
-        dom, dom_ms, kname = "forward", fwd_ms, "k_forward"
-    achieved = ops / (dom_ms * 1e-3)
-    measured_peak = csx.valu_peak()
-    traffic = stored_traffic(kname)
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-                "traffic_GB_per_s": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9,
-                "ops_per_launch": ops,
-                "op_model": ("4 per open in-band triple + 20 per stored class record" if store["on"] else
-                             "4 per open in-band triple + 60 per open pair + 10 per pair"),
-                "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
-                "peak_measured": measured_peak / 1e12, "frac_of_measured": achieved / measured_peak}
+        ops = algorithmic_ops(census, stored=store["on"], pairs_per_class=4 if lr else 2)
+        kname = "k_adjoint" if dom == "adjoint" else "k_forward"
+        achieved = ops / (dom_ms * 1e-3)
+        measured_peak = csx.valu_peak()
+        traffic = stored_traffic(kname)
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                    "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                    "traffic_GB_per_s": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9,
+                    "ops_per_launch": ops,
+                    "op_model": ("4 per open in-band triple + 20 per stored class record" if store["on"] else
+                                 "4 per open in-band triple + 60 per open pair + 10 per pair"),
+                    "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
+                    "peak_measured": measured_peak / 1e12, "frac_of_measured": achieved / measured_peak}
 
     out = {
         "metric": "fwd+adjoint voxel*pixel*energy evals/s at 128^2 x 64q (one Alg. 5 iteration per step)",
@@ -631,21 +674,28 @@ def main():
                    "ne": g.ne, "mask_open": float(g.mask.mean()), "beta": w.beta,
                    "nominal_evals_per_step": nominal},
         "roofline": roofline,
-        "factor_store": {"on": store["on"], "bytes": store["bytes"], "build_ms": store["build_ms"]},
+        "operators": {"interval_form": ivi, "class_store": store},
         "objective_first_last": [float(Jh[0]), float(Jh[-1])] if args.steps else None,
     }
     if not args.no_extras:
+        tp = time.perf_counter()
         out["operator_median"] = operator_medians(geo, f_d, y_d)
         out["slice32_gpu"] = gpu_slice32()
+        phases["operator_medians_and_slice32_s"] = time.perf_counter() - tp
     if args.tto_cases > 0:
-        tto = time_to_objective(args.tto_cases)
+        tp = time.perf_counter()
+        tto = time_to_objective(args.tto_cases, batched=True)
         out["time_to_objective"] = {k: tto[k] for k in ("cases", "target", "ms_plain_mean", "ms_warm_mean",
                                                          "speedup_mean_time", "iters_plain_mean",
                                                          "iters_warm_mean", "accept_rate", "ms_os_mean",
-                                                         "os_sweeps_mean", "speedup_os_mean_time")}
+                                                         "os_sweeps_mean", "speedup_os_mean_time", "batched")}
+        phases["time_to_objective_s"] = time.perf_counter() - tp
     if not args.no_cpu_baseline:
+        tp = time.perf_counter()
         f_true = inputs.phantom(w.geom, w.phantom_seed, w.n_rect)
         out["cpu_baseline"] = cpu_baseline(g, f_true, y)
+        phases["cpu_baseline_s"] = time.perf_counter() - tp
+    out["phases_wall_s"] = phases
     print(json.dumps(out))
 
 

@@ -395,37 +395,49 @@ __global__ void __launch_bounds__(1024) k_iv_sum(const float *__restrict__ part,
 // voxel groups, one group at a time: class weights into LDS at their rank,
 // float64 prefix sums at every interval, then per (m, c) differences.
 // ---------------------------------------------------------------------------
-// Adjoint: b = A^T rho.  Blocks of IVA_THREADS threads (two per compute
-// unit), each a contiguous range of voxel groups, one group at a time:
+// Adjoint: b = A^T rho.  One block of IVA_THREADS threads per compute unit,
+// a contiguous range of voxel groups, one group at a time:
 //  1. every class's weights (voxel j: A (T_u rho_u + T_d rho_d); voxel j2:
-//     the mirror pixels) go to LDS at the class's rank in the group's
-//     interval order;
-//  2. prefix sums in rank order: thread k owns ranks [k SC, (k+1) SC) and
-//     keeps their exclusive prefix within the chunk (float32, skewed layout:
-//     rank p at p + p / SC) and the chunk's base (float64 block scan), so the
-//     prefix E(p) = base[p / SC] + loc[p] has float64 accuracy where it
-//     matters (no cancellation of large partial sums);
+//     the mirror pixels) go to LDS, in float64, at the class's rank in the
+//     group's interval order;
+//  2. float64 prefix sums in rank order: thread k owns ranks [k SC, (k+1) SC)
+//     and stores their exclusive prefix within the chunk (XOR-swizzled within
+//     the chunk against bank conflicts) and the chunk's base from a block
+//     scan, so E(p) = base[p / SC] + loc[p];
 //  3. the classes in bin c at node m are the ranks [P(m, c), P(m, c + 1)),
 //     P from the set-up: b_jm = q_m sum_c Phi~[c] (E(P(m, c+1)) - E(P(m, c))).
-constexpr int IVA_THREADS = 512;
+// The prefix sums are float64 end to end: a bin's sum is a difference of two
+// prefixes, and a bin holding only a few small weights next to large ones
+// (the lowest q nodes see only the smallest angles) needs that precision to
+// stay accurate relative to itself.
+constexpr int IVA_THREADS = 1024;
 constexpr int IVA_WAVES = IVA_THREADS / 64;
+constexpr int IVA_SC = 8;           // ranks per thread chunk
 constexpr int IVA_SUB = 8;          // threads per node in the gather
+constexpr int IVA_MAXV = 9;         // prefetched bin positions per thread (ne <= 8 IVA_SUB)
 
-template <int LR, int NP, int SCL>
-__global__ void __launch_bounds__(IVA_THREADS, 4) k_iv_adjoint(KParams P, IvArgs V, const DevTables T,
+__device__ __forceinline__ int iva_swz(int p)
+{
+    return (p & ~(IVA_SC - 1)) | ((p ^ (p >> 3)) & (IVA_SC - 1));
+}
+
+// PF = 1: nq <= IVA_THREADS / IVA_SUB and ne <= 8 IVA_SUB: thread (m, sub)
+// owns the consecutive bins c = 1 + sub CPT .. (sub + 1) CPT of node m and
+// holds their CPT + 1 bin positions in registers, loaded one group ahead.
+template <int LR, int NP, int PF>
+__global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V, const DevTables T,
                                                             const float *__restrict__ rho, float *__restrict__ b)
 {
-    constexpr int SC = 1 << SCL;
     extern __shared__ __align__(16) unsigned char lds[];
-    float2 *s_loc = (float2 *)lds;                                        // [(IVA_THREADS + 1) (SC + 1)]
-    double2 *s_base = (double2 *)(s_loc + (IVA_THREADS + 1) * (SC + 1));  // [IVA_THREADS + 1]
-    float *s_phi = (float *)(s_base + IVA_THREADS + 1);                   // [ne + 2]
+    double2 *s_loc = (double2 *)lds;                               // [(IVA_THREADS + 1) SC]
+    double2 *s_base = s_loc + (IVA_THREADS + 1) * IVA_SC;          // [IVA_THREADS + 1]
+    float *s_phi = (float *)(s_base + IVA_THREADS + 1);            // [ne + 2]
     double2 *s_tot = (double2 *)(((uintptr_t)(s_phi + P.ne + 2) + 15) & ~(uintptr_t)15);
     const int tid = threadIdx.x;
     for (int k = tid; k < P.ne + 2; k += IVA_THREADS)
         s_phi[k] = P.td == CSX_TABLE_BF16 ? bf16_to_f32(T.phi16[k]) : T.phi32[k];
     // ranks past the last class hold zero weight for every group
-    for (int k = tid; k < (IVA_THREADS + 1) * (SC + 1); k += IVA_THREADS) s_loc[k] = make_float2(0.0f, 0.0f);
+    for (int k = tid; k < (IVA_THREADS + 1) * IVA_SC; k += IVA_THREADS) s_loc[k] = make_double2(0.0, 0.0);
     const int per = (V.ngroups + gridDim.x - 1) / gridDim.x;
     const int g0 = blockIdx.x * per, g1 = min(V.ngroups, g0 + per);
     const int half_y = P.ndy / 2;
@@ -463,12 +475,33 @@ __global__ void __launch_bounds__(IVA_THREADS, 4) k_iv_adjoint(KParams P, IvArgs
         return make_uint4(0u, 0u, 0u, 0u);
     };
     auto E = [&](int p) -> double2 {
-        const double2 bs = s_base[p >> SCL];
-        const float2 l = s_loc[p + (p >> SCL)];
-        return make_double2(bs.x + (double)l.x, bs.y + (double)l.y);
+        const double2 bs = s_base[p / IVA_SC];
+        const double2 l = s_loc[iva_swz(p)];
+        return make_double2(bs.x + l.x, bs.y + l.y);
     };
+    // PF: this thread's node, first bin and bin count, and positions of the next group
+    const int pm_m = tid / IVA_SUB, pm_sub = tid % IVA_SUB;
+    const int cpt = (P.ne + IVA_SUB - 1) / IVA_SUB;
+    const int pc0 = 1 + pm_sub * cpt, pnc = max(0, min(P.ne, pc0 + cpt - 1) - pc0 + 1);
+    const bool pact = PF && pm_m < P.nq && pnc > 0;
+    // positions packed two per register (low half: even k)
+    constexpr int NPV = (IVA_MAXV + 1) / 2;
+    uint32_t pv[PF ? NPV : 1];
+    auto load_pos = [&](int g) {
+        if (!PF) return;
+#pragma unroll
+        for (int k = 0; k < NPV; ++k) pv[k] = 0u;
+        if (pact && g < g1) {
+            const uint16_t *row = V.bpos + (size_t)g * nt + (size_t)pm_m * ne1 + (pc0 - 1);
+#pragma unroll
+            for (int k = 0; k < IVA_MAXV; ++k)
+                if (k <= pnc) pv[k >> 1] |= (uint32_t)row[k] << (16 * (k & 1));
+        }
+    };
+    auto pos = [&](int k) -> int { return (int)((pv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu); };
 #pragma unroll
     for (int i = 0; i < NP; ++i) nr[i] = load_one(g0, i);
+    load_pos(g0);
     for (int g = g0; g < g1; ++g) {
         int j, j2;
         group_voxels(P, LR, g, j, j2);
@@ -489,44 +522,41 @@ __global__ void __launch_bounds__(IVA_THREADS, 4) k_iv_adjoint(KParams P, IvArgs
                 const uint32_t w2 = cr.w;
                 const float c20 = A2 * ((float)(w2 & 1u) * rbu[i] + (float)((w2 >> 1) & 1u) * rbd[i]);
                 const float c21 = A2 * ((float)((w2 >> 2) & 1u) * ru[i] + (float)((w2 >> 3) & 1u) * rd[i]);
-                const int k2 = (int)(w2 >> 18);
-                s_loc[k2 + (k2 >> SCL)] = make_float2(c20, c21);
+                s_loc[iva_swz((int)(w2 >> 18))] = make_double2((double)c20, (double)c21);
             }
-            const int k1 = (int)(w1 >> 18);
-            s_loc[k1 + (k1 >> SCL)] = make_float2(c10, c11);
+            s_loc[iva_swz((int)(w1 >> 18))] = make_double2((double)c10, (double)c11);
         }
         __syncthreads();
-        // 2. chunk prefixes and bases
+        // 2. chunk prefixes (in place) and bases
         {
-            float2 *ch = s_loc + tid * (SC + 1);
-            float la = 0.0f, lb = 0.0f;
-            double da = 0.0, db = 0.0;
+            const int c0 = tid * IVA_SC;
+            double la = 0.0, lb = 0.0;
 #pragma unroll
-            for (int k = 0; k < SC; ++k) {
-                const float2 w = ch[k];
-                ch[k] = make_float2(la, lb);
+            for (int k = 0; k < IVA_SC; ++k) {
+                const int q = iva_swz(c0 + k);
+                const double2 w = s_loc[q];
+                s_loc[q] = make_double2(la, lb);
                 la += w.x;
                 lb += w.y;
-                da += (double)w.x;
-                db += (double)w.y;
             }
-            const double2 base = block_exclusive_scan(da, db, s_tot);
+            const double2 base = block_exclusive_scan(la, lb, s_tot);
             s_base[tid] = base;
-            if (tid == IVA_THREADS - 1) s_base[IVA_THREADS] = make_double2(base.x + da, base.y + db);
+            if (tid == IVA_THREADS - 1) s_base[IVA_THREADS] = make_double2(base.x + la, base.y + lb);
         }
         __syncthreads();
         // 3. b_jm = q_m sum_c Phi~[c] (E(P(m, c+1)) - E(P(m, c))), IVA_SUB threads per node
-        const uint16_t *bg = V.bpos + (size_t)g * nt;
-        for (int mb = 0; mb < P.nq; mb += IVA_THREADS / IVA_SUB) {
-            const int m = mb + tid / IVA_SUB, sub = tid % IVA_SUB;
+        if (PF) {
             double sa = 0.0, sb = 0.0;
-            if (m < P.nq) {
-                const uint16_t *pm = bg + (size_t)m * ne1;       // pm[c - 1] = P(m, c), c = 1 .. ne + 1
-                for (int c = 1 + sub; c <= P.ne; c += IVA_SUB) {
-                    const double ph = (double)s_phi[c];
-                    const double2 hi = E(pm[c]), lo = E(pm[c - 1]);
+            if (pact) {
+                double2 lo = E(pos(0));
+#pragma unroll
+                for (int k = 1; k < IVA_MAXV; ++k) {
+                    if (k > pnc) break;
+                    const double2 hi = E(pos(k));
+                    const double ph = (double)s_phi[pc0 + k - 1];
                     sa = fma(ph, hi.x - lo.x, sa);
                     sb = fma(ph, hi.y - lo.y, sb);
+                    lo = hi;
                 }
             }
 #pragma unroll
@@ -534,10 +564,36 @@ __global__ void __launch_bounds__(IVA_THREADS, 4) k_iv_adjoint(KParams P, IvArgs
                 sa += __shfl_xor(sa, d, 64);
                 sb += __shfl_xor(sb, d, 64);
             }
-            if (m < P.nq && sub == 0) {
-                const double qm = V.qd[m];
-                b[(size_t)j * P.nq + m] = (float)(qm * sa);
-                if (LR) b[(size_t)j2 * P.nq + m] = (float)(qm * sb);
+            if (pm_m < P.nq && pm_sub == 0) {
+                const double qm = V.qd[pm_m];
+                b[(size_t)j * P.nq + pm_m] = (float)(qm * sa);
+                if (LR) b[(size_t)j2 * P.nq + pm_m] = (float)(qm * sb);
+            }
+            load_pos(g + 1);   // used after the next group's weights and prefixes
+        } else {
+            const uint16_t *bg = V.bpos + (size_t)g * nt;
+            for (int mb = 0; mb < P.nq; mb += IVA_THREADS / IVA_SUB) {
+                const int m = mb + tid / IVA_SUB, sub = tid % IVA_SUB;
+                double sa = 0.0, sb = 0.0;
+                if (m < P.nq) {
+                    const uint16_t *pm = bg + (size_t)m * ne1;       // pm[c - 1] = P(m, c), c = 1 .. ne + 1
+                    for (int c = 1 + sub; c <= P.ne; c += IVA_SUB) {
+                        const double ph = (double)s_phi[c];
+                        const double2 hi = E(pm[c]), lo = E(pm[c - 1]);
+                        sa = fma(ph, hi.x - lo.x, sa);
+                        sb = fma(ph, hi.y - lo.y, sb);
+                    }
+                }
+#pragma unroll
+                for (int d = IVA_SUB / 2; d > 0; d >>= 1) {
+                    sa += __shfl_xor(sa, d, 64);
+                    sb += __shfl_xor(sb, d, 64);
+                }
+                if (m < P.nq && sub == 0) {
+                    const double qm = V.qd[m];
+                    b[(size_t)j * P.nq + m] = (float)(qm * sa);
+                    if (LR) b[(size_t)j2 * P.nq + m] = (float)(qm * sb);
+                }
             }
         }
         __syncthreads();   // the next group's weights overwrite s_loc
@@ -588,9 +644,10 @@ bool csx_iv_feasible(const KParams &P, int *lds_f, int *lds_a)
     const long slots = P.lr ? 2 * items : items;
     // intervals and ranks in 14 bits; the adjoint's ranks in IVA_THREADS
     // chunks of 16; one f value per forward thread
-    if (nt >= 16384 || slots > 16 * IVA_THREADS || items > 8L * IV_THREADS || 2 * P.nq > IV_THREADS) return false;
+    if (nt >= 16384 || slots > IVA_SC * IVA_THREADS || items > 8L * IV_THREADS || 2 * P.nq > IV_THREADS) return false;
     const long lf = ((nt * 10 + 15) & ~15L) + (nt + 1) * 8 + 2L * P.nq * 4 + 16 + IV_WAVES * 16;
-    const long la = (long)(IVA_THREADS + 1) * 17 * 8 + (IVA_THREADS + 1) * 16 + (P.ne + 2) * 4 + 16 + IVA_WAVES * 16;
+    const long la = (long)(IVA_THREADS + 1) * IVA_SC * 16 + (IVA_THREADS + 1) * 16 + (P.ne + 2) * 4 + 16 +
+                    IVA_WAVES * 16;
     if (lf > CSX_LDS_MAX || la > CSX_LDS_MAX) return false;
     if (lds_f) *lds_f = (int)lf;
     if (lds_a) *lds_a = (int)la;
@@ -685,8 +742,7 @@ csx_status csx_iv_build(csx_geometry *h)
     {
         int per = (P.n_groups + cus - 1) / cus;                  // forward: one block per compute unit
         v->nblk_f = (P.n_groups + per - 1) / per;
-        per = (P.n_groups + 2 * cus - 1) / (2 * cus);            // adjoint: two
-        v->nblk_a = (P.n_groups + per - 1) / per;
+        v->nblk_a = v->nblk_f;                                   // adjoint: one as well
         v->npa = 1;
         while (v->npa * IVA_THREADS < v->n_items) v->npa *= 2;
     }
@@ -759,19 +815,23 @@ csx_status csx_iv_adjoint(const csx_geometry *h, const float *rho, float *b, hip
     const IvState *v = (const IvState *)h->iv;
     const IvArgs a = iv_args(h, v);
     const dim3 grid(v->nblk_a), block(IVA_THREADS);
-#define CSX_IVA(LR_, NP_) \
-    hipLaunchKernelGGL((k_iv_adjoint<LR_, NP_, 4>), grid, block, v->lds_a, s, h->P, a, h->t, rho, b)
+    const bool pf = h->P.nq <= IVA_THREADS / IVA_SUB && h->P.ne <= (IVA_MAXV - 1) * IVA_SUB;
+#define CSX_IVA(LR_, NP_)                                                                                     \
+    do {                                                                                                      \
+        if (pf)                                                                                               \
+            hipLaunchKernelGGL((k_iv_adjoint<LR_, NP_, 1>), grid, block, v->lds_a, s, h->P, a, h->t, rho, b); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_iv_adjoint<LR_, NP_, 0>), grid, block, v->lds_a, s, h->P, a, h->t, rho, b); \
+    } while (0)
     if (h->P.lr) {
         if (v->npa == 1) CSX_IVA(1, 1);
         else if (v->npa == 2) CSX_IVA(1, 2);
-        else if (v->npa == 4) CSX_IVA(1, 4);
-        else CSX_IVA(1, 8);
+        else CSX_IVA(1, 4);
     } else {
         if (v->npa == 1) CSX_IVA(0, 1);
         else if (v->npa == 2) CSX_IVA(0, 2);
         else if (v->npa == 4) CSX_IVA(0, 4);
-        else if (v->npa == 8) CSX_IVA(0, 8);
-        else CSX_IVA(0, 16);
+        else CSX_IVA(0, 8);
     }
 #undef CSX_IVA
     HIP_TRY(hipGetLastError());

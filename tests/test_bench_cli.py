@@ -26,6 +26,6 @@ def test_source_hash_ignores_comments(tmp_path, monkeypatch):
     c.write_text("int f(int x) { return x + 2; }\n")
     hashes = []
     for path in (a, b, c):
-        monkeypatch.setattr(bench, "SRC", str(path))
+        monkeypatch.setattr(bench, "SRC", [str(path)])
         hashes.append(bench.source_hash())
     assert hashes[0] == hashes[1] != hashes[2]

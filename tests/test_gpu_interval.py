@@ -85,3 +85,32 @@ def test_interval_operators_refused_beyond_their_limits():
         geo.set_interval_operators(True)
     assert ei.value.code == csx.CSX_EINVAL
     geo.set_interval_operators(False)
+
+
+@pytest.mark.parametrize("name", ["slice32", "slice128"])
+def test_interval_sensitivity_elementwise(oracle_mod, name):
+    """b1 = A^T 1 element by element, relative to each element's own value:
+    the solver's update divides by it, so a small entry (a q node that only
+    the smallest scatter angles reach) must be as accurate as a large one.
+    A bin's sum is a difference of two float64 prefix sums; in float32 such a
+    difference would carry an error of the order of the large neighbouring
+    weights."""
+    w, g, ftrue, y = workload_data(name)
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    assert geo.interval_operators()["on"]
+    ones = np.ones((g.ndy, g.ndx))
+    got = host(geo.backproject(dev(ones)))
+    ref = o.adjoint(ones) if name == "slice32" else None
+    if ref is None:
+        # 128^2: a sample of voxels, every q node (the oracle's per-voxel adjoint)
+        rng = np.random.Generator(np.random.PCG64(11))
+        vox = rng.choice(g.nvox, 96, replace=False)
+        ref = o.adjoint_voxels(ones, vox)
+        got = got.reshape(g.nvox, g.nq)[vox]
+    scale = np.abs(ref).max()
+    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-9 * scale)
+    k = np.unravel_index(np.argmax(rel), rel.shape)
+    print(f"[{name} b1: worst element-relative error {rel[k]:.2e} at {k} (value {ref[k]:.3e}, "
+          f"smallest nonzero {np.abs(ref[ref > 0]).min():.3e})]", flush=True)
+    assert rel.max() <= 1e-5
