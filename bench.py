@@ -73,16 +73,22 @@ def algorithmic_ops(census: dict, stored: bool = False, pairs_per_class: int = 4
 
 
 def interval_bytes(g, lr: bool) -> dict:
-    """Algorithmic HBM bytes of one interval-form forward and adjoint launch:
-    the 8-byte class records (every voxel group x every class of the upper
-    detector half), the adjoint's uint16 bin positions (one per node and bin
-    edge per group), the image and the detector arrays."""
+    """Algorithmic HBM bytes of one interval-form forward and adjoint launch.
+    Forward: the 8-byte class records of every voxel group (the upper
+    detector half's classes), the image and the detector.  Adjoint: the same
+    records in interval order (padded to chunks of 8), the uint16 prefix-table
+    index of every (node, bin edge) per group (rows of 72 entries when ne <= 64
+    and nq <= 128, else ne + 1 rounded up to 8), one position-mask byte per
+    chunk, the detector and the image."""
     groups = g.nz * (g.nx // 2) if lr else g.nz * g.nx
-    classes = g.ndx * (g.ndy // 2)
-    records = 8.0 * groups * classes
+    slots = g.ndx * (g.ndy // 2)
+    rstride = (slots + 7) // 8 * 8
+    es = 72 if (g.ne <= 64 and g.nq <= 128) else (g.ne + 1 + 7) // 8 * 8
+    records = 8.0 * groups * slots
     image, det = 4.0 * g.nvox * g.nq, 4.0 * g.npix
-    positions = 2.0 * groups * (g.ne + 1) * g.nq
-    return {"forward": records + image + det, "adjoint": records + positions + det + image,
+    records_a = 8.0 * groups * rstride
+    positions = 2.0 * groups * g.nq * es + 1.0 * groups * (rstride // 8)
+    return {"forward": records + image + det, "adjoint": records_a + positions + det + image,
             "records": records, "positions": positions}
 
 
@@ -645,8 +651,9 @@ def main():
         traffic = stored_traffic(kname)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
                     "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": traffic,
-                    "bytes_per_launch": nb[dom], "bytes_model": "8 B per class record + the adjoint's 2 B bin "
-                    "positions per (node, bin edge) and voxel group + image + detector arrays",
+                    "bytes_per_launch": nb[dom], "bytes_model": "8 B per class record (forward: slot order; adjoint: interval order) + the "
+                    "adjoint's 2 B table index per (node, bin edge) and 1 B position mask per 8 ranks, per "
+                    "voxel group + image + detector arrays",
                     "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
                     "forward_GB_per_s": nb["forward"] / (fwd_ms * 1e-3) / 1e9,
                     "adjoint_GB_per_s": nb["adjoint"] / (adj_ms * 1e-3) / 1e9}

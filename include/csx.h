@@ -152,8 +152,8 @@ csx_status csx_get_factor_store(const csx_geometry *h, int *on, int64_t *bytes, 
  * results equal the direct sums up to the order of the additions.  Set-up
  * computes per class an 8-byte record (A, mask values, interval, rank in its
  * voxel group's interval order): 0.5 GB at 128^2 x 128^2.  Applies when
- * (ne + 1) nq < 16384, the upper-half detector has at most 16384 classes
- * per voxel group and both kernels' tables fit in LDS; csx_init_geometry
+ * (ne + 1) nq < 16384, a voxel group has at most 8192 classes (pixels of
+ * the upper detector half) and both kernels' tables fit in LDS; csx_init_geometry
  * builds it then when it needs at most CSX_STORE_AUTO_BYTES and a quarter of
  * the free memory.  While built, csx_forward, csx_forward_noalloc,
  * csx_backproject and the solvers' full operators use it; subset and

@@ -49,20 +49,31 @@ namespace {
 
 constexpr int IV_THREADS = 1024;
 constexpr int IV_WAVES = IV_THREADS / 64;
+constexpr int IVA_THREADS = 1024;
+constexpr int IVA_WAVES = IVA_THREADS / 64;
+constexpr int IVA_SC = 8;                                // ranks per adjoint thread
+constexpr int IVA_SUB = 8;                               // adjoint gather threads per node
+constexpr int IVA_NW = IVA_SC * IVA_THREADS / 32 + 1;    // words of a position bitmap (0 .. 8192)
 
 struct IvState {
-    uint2 *rec = nullptr;       // [n_groups][n_slots] {A bits, w}
+    uint2 *rec = nullptr;       // [n_groups][n_slots] {A bits, w}, slot order (forward)
+    uint2 *reca = nullptr;      // [n_groups][rstride] {A bits, mask bits | slot << 4}, interval order (adjoint)
     double *coef = nullptr;     // [nt] q_m (Phi~[c] - Phi~[c-1]) of the sorted thresholds
     uint16_t *mt = nullptr;     // [nt] node m of each sorted threshold
     uint16_t *pp = nullptr;     // [nq][ne + 2] pos(c, m) + 1, c = 1 .. ne + 1
-    uint16_t *bpos = nullptr;   // [n_groups][nq][ne + 1] rank of the first class of each (node, bin)
+    uint16_t *emap = nullptr;   // [n_groups][nq][es] prefix-table index of P(m, c), entry c - 1
+    uint8_t *emask = nullptr;   // [n_groups][nch] bit i of byte k: position 8 k + i is in the prefix table
+    int *cnt = nullptr;         // [1] largest prefix-table size over the groups (set-up)
     double *qd = nullptr;       // [nq] q nodes
     float *part = nullptr;      // [nblk][npix] forward partial images
     int nt = 0;                 // thresholds, (ne + 1) nq
     int n_slots = 0;            // classes per voxel group (LR: 2 per mirror pair)
     int n_items = 0;            // work items per group: mirror pairs (LR) or classes
+    int rstride = 0;            // adjoint records per group, n_slots rounded up to a chunk
+    int nch = 0;                // rank chunks per group, rstride / IVA_SC
+    int es = 0;                 // emap entries per node (ne + 1 rounded up to 8)
+    int cap = 0;                // prefix-table entries between the two fixed ones (largest group)
     int np = 1;                 // forward: work items per thread (power of 2, <= 8)
-    int npa = 1;                // adjoint: work items per thread (power of 2, <= 16)
     int nblk_f = 0, nblk_a = 0;
     int lds_f = 0, lds_a = 0;
     int64_t bytes = 0;
@@ -71,12 +82,13 @@ struct IvState {
 
 struct IvArgs {
     const uint2 *rec;
+    const uint2 *reca;
     const double *coef;
     const uint16_t *mt;
-    const uint16_t *pp;
-    const uint16_t *bpos;
+    const uint16_t *emap;
+    const uint8_t *emask;
     const double *qd;
-    int nt, n_slots, n_items, ngroups;
+    int nt, n_slots, n_items, ngroups, rstride, nch, es, cap;
 };
 
 __device__ __forceinline__ void group_voxels(const KParams &P, int LR, int g, int &j, int &j2)
@@ -152,16 +164,33 @@ __global__ void __launch_bounds__(256) k_iv_records(KParams P, DevTables T, int 
     out[idx] = make_uint2(__float_as_uint(A), bits | (t << 4));
 }
 
-// Rank of every class of a voxel group in the order of (t, slot): a bitonic
-// sort of the keys (t << 14 | slot) in LDS, one block per group.  The rank
-// goes to bits 18-31 of the record.
-__global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, uint2 *__restrict__ rec, int nq, int ne,
-                                                  const uint16_t *__restrict__ pp, uint16_t *__restrict__ bpos)
+// The adjoint's tables of one voxel group, one block per group:
+//  - the rank of every class in the order of (t, slot), by a bitonic sort of
+//    the keys (t << 14 | slot) in LDS, and the records in that order,
+//    reca[rank] = {A, mask bits | slot << 4}, zero past n_slots;
+//  - for node m and bin edge c = 1 .. ne + 1 the position P(m, c), the rank
+//    of the first class whose t reaches pp(c, m) = pos(c, m) + 1 (so the
+//    classes in bin c at node m are the ranks [P(m, c), P(m, c + 1)));
+//  - the prefix table the adjoint keeps for the group: entry 0 is the empty
+//    prefix (P = 0), entry 1 the total (P = n_slots), entries 2, 3, ... the
+//    distinct positions strictly between, ascending.  emap holds each
+//    P(m, c) as its table entry (row stride es, zero past c = ne + 1), and
+//    emask bit i of byte k marks position 8 k + i as one of the entries.
+// cnt receives the largest number of in-between entries over the groups.
+__global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, int rstride, const uint2 *__restrict__ rec,
+                                                  uint2 *__restrict__ reca, int nq, int ne, int es, int nch,
+                                                  const uint16_t *__restrict__ pp, uint16_t *__restrict__ emap,
+                                                  uint8_t *__restrict__ emask, int *__restrict__ cnt)
 {
-    extern __shared__ uint32_t keys[];
-    uint2 *rg = rec + (size_t)blockIdx.x * n_slots;
+    extern __shared__ uint32_t keys[];        // [npow2], then the positions [nt] as uint16
+    __shared__ uint32_t s_bits[IVA_NW];
+    __shared__ uint32_t s_pre[IVA_NW];
+    const int nt = (ne + 1) * nq;
+    uint16_t *s_P = (uint16_t *)(keys + npow2);
+    const uint2 *rg = rec + (size_t)blockIdx.x * n_slots;
     for (int i = threadIdx.x; i < npow2; i += blockDim.x)
         keys[i] = i < n_slots ? (((rg[i].y >> 4) & 0x3FFFu) << 14) | (uint32_t)i : 0xFFFFFFFFu;
+    for (int w = threadIdx.x; w < IVA_NW; w += blockDim.x) s_bits[w] = 0u;
     __syncthreads();
     for (int k = 2; k <= npow2; k <<= 1)
         for (int d = k >> 1; d > 0; d >>= 1) {
@@ -178,15 +207,16 @@ __global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, uint2 
             }
             __syncthreads();
         }
-    for (int s = threadIdx.x; s < n_slots; s += blockDim.x) {
-        const int i = (int)(keys[s] & 0x3FFFu);
-        rg[i].y = (rg[i].y & 0x3FFFFu) | ((uint32_t)s << 18);
+    uint2 *ra = reca + (size_t)blockIdx.x * rstride;
+    for (int r = threadIdx.x; r < rstride; r += blockDim.x) {
+        uint2 v = make_uint2(0u, 0u);
+        if (r < n_slots) {
+            const uint32_t sl = keys[r] & 0x3FFFu;
+            const uint2 x = rg[sl];
+            v = make_uint2(x.x, (x.y & 0xFu) | (sl << 4));
+        }
+        ra[r] = v;
     }
-    // bin positions of the group: for node m and bin c (1 .. ne + 1) the
-    // number of classes whose interval is below pp(c, m) = pos(c, m) + 1,
-    // i.e. the rank of the first class at or past that threshold
-    const int nt = (ne + 1) * nq;
-    uint16_t *bg = bpos + (size_t)blockIdx.x * nt;
     for (int k = threadIdx.x; k < nt; k += blockDim.x) {
         const int m = k / (ne + 1), c = 1 + k % (ne + 1);
         const uint32_t T = pp[(size_t)m * (ne + 2) + c];
@@ -196,12 +226,55 @@ __global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, uint2 
             if ((keys[mid] >> 14) < T) lo = mid + 1;
             else hi = mid;
         }
-        bg[k] = (uint16_t)lo;
+        s_P[k] = (uint16_t)lo;
+        if (lo > 0 && lo < n_slots) atomicOr(&s_bits[lo >> 5], 1u << (lo & 31));
     }
+    __syncthreads();
+    // table entries before each bitmap word: one wave, 5 words per lane
+    if (threadIdx.x < 64) {
+        constexpr int WPL = (IVA_NW + 63) / 64;
+        const int lane = threadIdx.x;
+        int before[WPL], sum = 0;
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) {
+            const int w = lane * WPL + i;
+            before[i] = sum;
+            sum += w < IVA_NW ? __popc(s_bits[w]) : 0;
+        }
+        int incl = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += u;
+        }
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) {
+            const int w = lane * WPL + i;
+            if (w < IVA_NW) s_pre[w] = (uint32_t)(incl - sum + before[i]);
+        }
+        if (lane == 63) atomicMax(cnt, incl);
+    }
+    __syncthreads();
+    uint16_t *eg = emap + (size_t)blockIdx.x * nq * es;
+    for (int k = threadIdx.x; k < nq * es; k += blockDim.x) {
+        const int m = k / es, e = k % es;     // e = c - 1
+        uint32_t v = 0u;
+        if (e <= ne) {
+            const uint32_t P = s_P[m * (ne + 1) + e];
+            if (P >= (uint32_t)n_slots) v = 1u;
+            else if (P > 0u) v = 2u + s_pre[P >> 5] + __popc(s_bits[P >> 5] & ((1u << (P & 31u)) - 1u));
+        }
+        eg[k] = (uint16_t)v;
+    }
+    uint8_t *mg = emask + (size_t)blockIdx.x * nch;
+    for (int k = threadIdx.x; k < nch; k += blockDim.x) mg[k] = (uint8_t)(s_bits[k >> 2] >> (8 * (k & 3)));
 }
 
 // ---------------------------------------------------------------------------
-// Block-wide exclusive scan of a pair of float64 values (fixed order).
+// Block-wide exclusive scan of a pair of float64 values (fixed order): an
+// inclusive scan within each wave, the wave totals through LDS, and the sum
+// of the totals of the waves below by an xor tree across 16 lanes (every
+// row of 16 lanes holds the 16 totals).  At most 16 waves.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double2 block_exclusive_scan(double a, double b, double2 *s_tot)
 {
@@ -216,13 +289,18 @@ __device__ __forceinline__ double2 block_exclusive_scan(double a, double b, doub
         }
     }
     if (lane == 63) s_tot[wv] = make_double2(ia, ib);
+    double ea = __shfl_up(ia, 1, 64), eb = __shfl_up(ib, 1, 64);
+    if (lane == 0) ea = eb = 0.0;
     __syncthreads();
-    double oa = 0.0, ob = 0.0;
-    for (int w = 0; w < wv; ++w) {
-        oa += s_tot[w].x;
-        ob += s_tot[w].y;
+    const double2 t = s_tot[lane & 15];
+    const bool below = (lane & 15) < wv;
+    double oa = below ? t.x : 0.0, ob = below ? t.y : 0.0;
+#pragma unroll
+    for (int d = 8; d > 0; d >>= 1) {
+        oa += __shfl_xor(oa, d, 16);
+        ob += __shfl_xor(ob, d, 16);
     }
-    return make_double2(oa + ia - a, ob + ib - b);
+    return make_double2(oa + ea, ob + eb);
 }
 
 // ---------------------------------------------------------------------------
@@ -238,8 +316,8 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
     double *s_coef = (double *)lds;
     uint16_t *s_mt = (uint16_t *)(s_coef + V.nt);
     float2 *s_F = (float2 *)(lds + (((size_t)V.nt * 10 + 15) & ~(size_t)15));
-    float *s_f = (float *)(s_F + V.nt + 1);
-    double2 *s_tot = (double2 *)(((uintptr_t)(s_f + 2 * P.nq) + 15) & ~(uintptr_t)15);
+    float *s_f = (float *)(s_F + V.nt + 1);                                   // [2][2 nq]
+    double2 *s_tot = (double2 *)(((uintptr_t)(s_f + 4 * P.nq) + 15) & ~(uintptr_t)15);
     const int tid = threadIdx.x;
     for (int i = tid; i < V.nt; i += IV_THREADS) {
         s_coef[i] = V.coef[i];
@@ -276,7 +354,9 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
             }
         }
     };
-    // thread i < 2 nq carries f of the next group's voxel j (i < nq) or j2
+    // thread i < 2 nq carries f of a group's voxel j (i < nq) or j2; the
+    // values of group g sit in s_f[g & 1], written one group ahead, so the
+    // barrier that publishes a group's F table also publishes the next f
     auto load_f = [&](int g) -> float {
         if (tid >= 2 * P.nq || g >= g1) return 0.0f;
         int j, j2;
@@ -284,27 +364,28 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
         if (tid < P.nq) return f[(size_t)j * P.nq + tid];
         return LR ? f[(size_t)j2 * P.nq + tid - P.nq] : 0.0f;
     };
-    float fv = load_f(g0);
+    if (tid < 2 * P.nq) s_f[(g0 & 1) * 2 * P.nq + tid] = load_f(g0);
+    float fv = load_f(g0 + 1);
     load_rec(g0);
     __syncthreads();
     for (int g = g0; g < g1; ++g) {
-        if (tid < 2 * P.nq) s_f[tid] = fv;
-        fv = load_f(g + 1);
-        __syncthreads();
+        const float *sf = s_f + (g & 1) * 2 * P.nq;
+        if (tid < 2 * P.nq) s_f[((g + 1) & 1) * 2 * P.nq + tid] = fv;
+        fv = load_f(g + 2);
         // F tables of voxels j and j2: float64 prefix sums over the sorted thresholds
         double la = 0.0, lb = 0.0;
         for (int t = t0; t < t1; ++t) {
             const double c = s_coef[t];
             const int m = s_mt[t];
-            la = fma(c, (double)s_f[m], la);
-            lb = fma(c, (double)s_f[P.nq + m], lb);
+            la = fma(c, (double)sf[m], la);
+            lb = fma(c, (double)sf[P.nq + m], lb);
         }
         double2 run = block_exclusive_scan(la, lb, s_tot);
         for (int t = t0; t < t1; ++t) {
             const double c = s_coef[t];
             const int m = s_mt[t];
-            run.x = fma(c, (double)s_f[m], run.x);
-            run.y = fma(c, (double)s_f[P.nq + m], run.y);
+            run.x = fma(c, (double)sf[m], run.x);
+            run.y = fma(c, (double)sf[P.nq + m], run.y);
             s_F[t + 1] = make_float2((float)run.x, (float)run.y);
         }
         if (tid == 0) s_F[0] = make_float2(0.0f, 0.0f);
@@ -391,172 +472,200 @@ __global__ void __launch_bounds__(1024) k_iv_sum(const float *__restrict__ part,
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint: b = A^T rho.  Block = IV_THREADS threads, a contiguous range of
-// voxel groups, one group at a time: class weights into LDS at their rank,
-// float64 prefix sums at every interval, then per (m, c) differences.
-// ---------------------------------------------------------------------------
 // Adjoint: b = A^T rho.  One block of IVA_THREADS threads per compute unit,
-// a contiguous range of voxel groups, one group at a time:
-//  1. every class's weights (voxel j: A (T_u rho_u + T_d rho_d); voxel j2:
-//     the mirror pixels) go to LDS, in float64, at the class's rank in the
-//     group's interval order;
-//  2. float64 prefix sums in rank order: thread k owns ranks [k SC, (k+1) SC)
-//     and stores their exclusive prefix within the chunk (XOR-swizzled within
-//     the chunk against bank conflicts) and the chunk's base from a block
-//     scan, so E(p) = base[p / SC] + loc[p];
-//  3. the classes in bin c at node m are the ranks [P(m, c), P(m, c + 1)),
-//     P from the set-up: b_jm = q_m sum_c Phi~[c] (E(P(m, c+1)) - E(P(m, c))).
+// a contiguous range of voxel groups, one group at a time, two barriers per
+// group:
+//  A. thread k reads the records of ranks 8k .. 8k + 7 of the group (their
+//     interval order, stored so at set-up), looks up the detector values of
+//     each class's pixels in LDS and forms the class's weights for voxels j
+//     and j2 (A (T_u rho_u + T_d rho_d), float32 as in the direct kernels),
+//     then their exclusive prefix sums within the chunk in float64
+//     registers; a wave scan gives the chunk's offset within its wave;
+//  B. after the wave totals are in LDS, each thread adds the totals of the
+//     waves below and writes the prefix E(p) = sum of the weights of ranks
+//     < p at the positions p of its chunk that some (node, bin) edge needs,
+//     into a compact table (entry 0: E = 0, entry 1: the total);
+//  C. the classes in bin c at node m are the ranks [P(m, c), P(m, c + 1)), so
+//     b_jm = q_m sum_c Phi~[c] (E(P(m, c + 1)) - E(P(m, c))), IVA_SUB threads
+//     per node, the table indices of P loaded one group ahead.
 // The prefix sums are float64 end to end: a bin's sum is a difference of two
-// prefixes, and a bin holding only a few small weights next to large ones
+// prefixes, and a bin holding only a few small weights behind large ones
 // (the lowest q nodes see only the smallest angles) needs that precision to
 // stay accurate relative to itself.
-constexpr int IVA_THREADS = 1024;
-constexpr int IVA_WAVES = IVA_THREADS / 64;
-constexpr int IVA_SC = 8;           // ranks per thread chunk
-constexpr int IVA_SUB = 8;          // threads per node in the gather
-constexpr int IVA_MAXV = 9;         // prefetched bin positions per thread (ne <= 8 IVA_SUB)
-
-__device__ __forceinline__ int iva_swz(int p)
-{
-    return (p & ~(IVA_SC - 1)) | ((p ^ (p >> 3)) & (IVA_SC - 1));
-}
+template <int LR>
+struct IvRho {
+    using T = float2;      // detector values of a class: (upper, lower) pixel
+};
+template <>
+struct IvRho<1> {
+    using T = float4;      // of a mirror pair: (upper, lower) at column a, then at ndx - 1 - a
+};
 
 // PF = 1: nq <= IVA_THREADS / IVA_SUB and ne <= 8 IVA_SUB: thread (m, sub)
-// owns the consecutive bins c = 1 + sub CPT .. (sub + 1) CPT of node m and
-// holds their CPT + 1 bin positions in registers, loaded one group ahead.
-template <int LR, int NP, int PF>
+// owns bins c = 1 + 8 sub .. 8 + 8 sub of node m and holds the 9 table
+// indices of their edges in registers (one 16-byte and one 2-byte load from
+// rows of es = 72 entries).
+template <int LR, int PF>
 __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V, const DevTables T,
                                                             const float *__restrict__ rho, float *__restrict__ b)
 {
+    using RT = typename IvRho<LR>::T;
     extern __shared__ __align__(16) unsigned char lds[];
-    double2 *s_loc = (double2 *)lds;                               // [(IVA_THREADS + 1) SC]
-    double2 *s_base = s_loc + (IVA_THREADS + 1) * IVA_SC;          // [IVA_THREADS + 1]
-    float *s_phi = (float *)(s_base + IVA_THREADS + 1);            // [ne + 2]
-    double2 *s_tot = (double2 *)(((uintptr_t)(s_phi + P.ne + 2) + 15) & ~(uintptr_t)15);
-    const int tid = threadIdx.x;
-    for (int k = tid; k < P.ne + 2; k += IVA_THREADS)
-        s_phi[k] = P.td == CSX_TABLE_BF16 ? bf16_to_f32(T.phi16[k]) : T.phi32[k];
-    // ranks past the last class hold zero weight for every group
-    for (int k = tid; k < (IVA_THREADS + 1) * IVA_SC; k += IVA_THREADS) s_loc[k] = make_double2(0.0, 0.0);
-    const int per = (V.ngroups + gridDim.x - 1) / gridDim.x;
-    const int g0 = blockIdx.x * per, g1 = min(V.ngroups, g0 + per);
+    RT *s_rho = (RT *)lds;                                                              // [n_items]
+    double2 *s_E = (double2 *)(lds + (((size_t)V.n_items * sizeof(RT) + 15) & ~(size_t)15));  // [2 + cap]
+    double2 *s_wt = s_E + 2 + V.cap;                                                    // [IVA_WAVES]
+    int *s_wc = (int *)(s_wt + IVA_WAVES);                                              // [IVA_WAVES]
+    float *s_phi = (float *)(s_wc + IVA_WAVES);                                         // [nphi]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nphi = max(P.ne + 2, IVA_SC * IVA_SUB + 2);
+    for (int k = tid; k < nphi; k += IVA_THREADS)
+        s_phi[k] = k >= P.ne + 2 ? 0.0f : P.td == CSX_TABLE_BF16 ? bf16_to_f32(T.phi16[k]) : T.phi32[k];
+    // detector values of every item, the same for every group
     const int half_y = P.ndy / 2;
-    const int nt = V.nt, ne1 = P.ne + 1;
-    // the detector values of the thread's items are the same for every group
-    float ru[NP], rd[NP], rbu[NP], rbd[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        const int p = tid + i * IVA_THREADS;
-        ru[i] = rd[i] = rbu[i] = rbd[i] = 0.0f;
-        if (p < V.n_items) {
-            int a, r;
-            item_class(P, LR, p, 0, a, r);
-            const int bu = half_y + r, bd = P.ndy - 1 - bu;
-            ru[i] = rho[bu * P.ndx + a];
-            rd[i] = rho[bd * P.ndx + a];
-            if (LR) {
-                const int ab = P.ndx - 1 - a;
-                rbu[i] = rho[bu * P.ndx + ab];
-                rbd[i] = rho[bd * P.ndx + ab];
-            }
+    for (int p = tid; p < V.n_items; p += IVA_THREADS) {
+        int a, r;
+        item_class(P, LR, p, 0, a, r);
+        const int bu = half_y + r, bd = P.ndy - 1 - bu;
+        if constexpr (LR) {
+            const int ab = P.ndx - 1 - a;
+            s_rho[p] = make_float4(rho[bu * P.ndx + a], rho[bd * P.ndx + a], rho[bu * P.ndx + ab], rho[bd * P.ndx + ab]);
+        } else {
+            s_rho[p] = make_float2(rho[bu * P.ndx + a], rho[bd * P.ndx + a]);
         }
     }
-    // records of the thread's items, prefetched one group ahead (item i's
-    // next record is requested as soon as its current one is used)
-    uint4 nr[NP];
-    auto load_one = [&](int g, int i) -> uint4 {
-        const int p = tid + i * IVA_THREADS;
-        if (p < V.n_items && g < g1) {
-            const uint2 *rg = V.rec + (size_t)g * V.n_slots;
-            if (LR) return *(const uint4 *)(rg + 2 * p);
-            const uint2 v = rg[p];
-            return make_uint4(v.x, v.y, 0u, 0u);
+    if (tid == 0) s_E[0] = make_double2(0.0, 0.0);
+    const int per = (V.ngroups + gridDim.x - 1) / gridDim.x;
+    const int g0 = blockIdx.x * per, g1 = min(V.ngroups, g0 + per);
+    // records and position bits of the thread's chunk, one group ahead
+    const bool own = tid < V.nch;
+    uint4 nr[IVA_SC / 2];
+    uint32_t nm = 0u;
+    auto load_chunk = [&](int g) {
+        if (own && g < g1) {
+            const uint4 *src = (const uint4 *)(V.reca + (size_t)g * V.rstride + (size_t)tid * IVA_SC);
+#pragma unroll
+            for (int i = 0; i < IVA_SC / 2; ++i) nr[i] = src[i];
+            nm = V.emask[(size_t)g * V.nch + tid];
+        } else {
+#pragma unroll
+            for (int i = 0; i < IVA_SC / 2; ++i) nr[i] = make_uint4(0u, 0u, 0u, 0u);
+            nm = 0u;
         }
-        return make_uint4(0u, 0u, 0u, 0u);
     };
-    auto E = [&](int p) -> double2 {
-        const double2 bs = s_base[p / IVA_SC];
-        const double2 l = s_loc[iva_swz(p)];
-        return make_double2(bs.x + l.x, bs.y + l.y);
-    };
-    // PF: this thread's node, first bin and bin count, and positions of the next group
-    const int pm_m = tid / IVA_SUB, pm_sub = tid % IVA_SUB;
-    const int cpt = (P.ne + IVA_SUB - 1) / IVA_SUB;
-    const int pc0 = 1 + pm_sub * cpt, pnc = max(0, min(P.ne, pc0 + cpt - 1) - pc0 + 1);
-    const bool pact = PF && pm_m < P.nq && pnc > 0;
-    // positions packed two per register (low half: even k)
-    constexpr int NPV = (IVA_MAXV + 1) / 2;
-    uint32_t pv[PF ? NPV : 1];
-    auto load_pos = [&](int g) {
+    // PF: this thread's node and bins, and the table indices of their edges
+    const int pm = tid / IVA_SUB, ps = tid % IVA_SUB;
+    const bool pact = PF && pm < P.nq;
+    uint4 ev = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t e8 = 0u;
+    auto load_emap = [&](int g) {
         if (!PF) return;
-#pragma unroll
-        for (int k = 0; k < NPV; ++k) pv[k] = 0u;
         if (pact && g < g1) {
-            const uint16_t *row = V.bpos + (size_t)g * nt + (size_t)pm_m * ne1 + (pc0 - 1);
-#pragma unroll
-            for (int k = 0; k < IVA_MAXV; ++k)
-                if (k <= pnc) pv[k >> 1] |= (uint32_t)row[k] << (16 * (k & 1));
+            const uint16_t *row = V.emap + ((size_t)g * P.nq + pm) * V.es + ps * IVA_SC;
+            ev = *(const uint4 *)row;
+            e8 = row[IVA_SC];
+        } else {
+            ev = make_uint4(0u, 0u, 0u, 0u);
+            e8 = 0u;
         }
     };
-    auto pos = [&](int k) -> int { return (int)((pv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu); };
-#pragma unroll
-    for (int i = 0; i < NP; ++i) nr[i] = load_one(g0, i);
-    load_pos(g0);
+    load_chunk(g0);
+    load_emap(g0);
+    __syncthreads();
     for (int g = g0; g < g1; ++g) {
         int j, j2;
         group_voxels(P, LR, g, j, j2);
-        // 1. class weights at their rank
+        // A. weights of the chunk's classes and their prefixes within the chunk
+        uint4 cr[IVA_SC / 2];
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            const uint4 cr = nr[i];
-            nr[i] = load_one(g + 1, i);
-            const int p = tid + i * IVA_THREADS;
-            if (p >= V.n_items) continue;
-            const float A1 = __uint_as_float(cr.x);
-            const uint32_t w1 = cr.y;
-            const float c10 = A1 * ((float)(w1 & 1u) * ru[i] + (float)((w1 >> 1) & 1u) * rd[i]);
-            float c11 = 0.0f;
-            if (LR) {
-                c11 = A1 * ((float)((w1 >> 2) & 1u) * rbu[i] + (float)((w1 >> 3) & 1u) * rbd[i]);
-                const float A2 = __uint_as_float(cr.z);
-                const uint32_t w2 = cr.w;
-                const float c20 = A2 * ((float)(w2 & 1u) * rbu[i] + (float)((w2 >> 1) & 1u) * rbd[i]);
-                const float c21 = A2 * ((float)((w2 >> 2) & 1u) * ru[i] + (float)((w2 >> 3) & 1u) * rd[i]);
-                s_loc[iva_swz((int)(w2 >> 18))] = make_double2((double)c20, (double)c21);
+        for (int i = 0; i < IVA_SC / 2; ++i) cr[i] = nr[i];
+        const uint32_t msk = nm;
+        load_chunk(g + 1);
+        double2 loc[IVA_SC];
+        double la = 0.0, lb = 0.0;
+#pragma unroll
+        for (int i = 0; i < IVA_SC; ++i) {
+            loc[i] = make_double2(la, lb);
+            const float A = __uint_as_float((i & 1) ? cr[i >> 1].z : cr[i >> 1].x);
+            const uint32_t w = (i & 1) ? cr[i >> 1].w : cr[i >> 1].y;
+            const uint32_t sl = w >> 4;
+            float c0, c1 = 0.0f;
+            if constexpr (LR) {
+                // slot 2p is column a of item p, slot 2p + 1 its mirror column
+                const float4 q = s_rho[sl >> 1];
+                const bool mir = (sl & 1u) != 0u;
+                const float u0 = mir ? q.z : q.x, d0 = mir ? q.w : q.y;
+                const float u1 = mir ? q.x : q.z, d1 = mir ? q.y : q.w;
+                c0 = A * ((float)(w & 1u) * u0 + (float)((w >> 1) & 1u) * d0);
+                c1 = A * ((float)((w >> 2) & 1u) * u1 + (float)((w >> 3) & 1u) * d1);
+            } else {
+                const float2 q = s_rho[sl];
+                c0 = A * ((float)(w & 1u) * q.x + (float)((w >> 1) & 1u) * q.y);
             }
-            s_loc[iva_swz((int)(w1 >> 18))] = make_double2((double)c10, (double)c11);
+            la += (double)c0;
+            lb += (double)c1;
+        }
+        const int cn = __popc(msk);
+        double ia = la, ib = lb;
+        int ic = cn;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double ua = __shfl_up(ia, d, 64), ub = __shfl_up(ib, d, 64);
+            const int uc = __shfl_up(ic, d, 64);
+            if (lane >= d) {
+                ia += ua;
+                ib += ub;
+                ic += uc;
+            }
+        }
+        if (lane == 63) {
+            s_wt[wv] = make_double2(ia, ib);
+            s_wc[wv] = ic;
+        }
+        double ea = __shfl_up(ia, 1, 64), eb = __shfl_up(ib, 1, 64);
+        int ec = __shfl_up(ic, 1, 64);
+        if (lane == 0) {
+            ea = eb = 0.0;
+            ec = 0;
         }
         __syncthreads();
-        // 2. chunk prefixes (in place) and bases
+        // B. prefixes at the chunk's table positions
         {
-            const int c0 = tid * IVA_SC;
-            double la = 0.0, lb = 0.0;
+            const double2 t = s_wt[lane & 15];
+            const int tc = s_wc[lane & 15];
+            const bool below = (lane & 15) < wv;
+            double oa = below ? t.x : 0.0, ob = below ? t.y : 0.0;
+            int oc = below ? tc : 0;
 #pragma unroll
-            for (int k = 0; k < IVA_SC; ++k) {
-                const int q = iva_swz(c0 + k);
-                const double2 w = s_loc[q];
-                s_loc[q] = make_double2(la, lb);
-                la += w.x;
-                lb += w.y;
+            for (int d = 8; d > 0; d >>= 1) {
+                oa += __shfl_xor(oa, d, 16);
+                ob += __shfl_xor(ob, d, 16);
+                oc += __shfl_xor(oc, d, 16);
             }
-            const double2 base = block_exclusive_scan(la, lb, s_tot);
-            s_base[tid] = base;
-            if (tid == IVA_THREADS - 1) s_base[IVA_THREADS] = make_double2(base.x + la, base.y + lb);
+            const double ba = oa + ea, bb = ob + eb;
+            int ci = 2 + oc + ec;
+#pragma unroll
+            for (int i = 0; i < IVA_SC; ++i)
+                if ((msk >> i) & 1u) {
+                    s_E[ci] = make_double2(ba + loc[i].x, bb + loc[i].y);
+                    ++ci;
+                }
+            if (tid == IVA_THREADS - 1) s_E[1] = make_double2(oa + ia, ob + ib);
         }
         __syncthreads();
-        // 3. b_jm = q_m sum_c Phi~[c] (E(P(m, c+1)) - E(P(m, c))), IVA_SUB threads per node
-        if (PF) {
+        // C. b_jm = q_m sum_c Phi~[c] (E(P(m, c + 1)) - E(P(m, c)))
+        if constexpr (PF) {
             double sa = 0.0, sb = 0.0;
             if (pact) {
-                double2 lo = E(pos(0));
+                const uint32_t ew[4] = {ev.x, ev.y, ev.z, ev.w};
+                double2 E[IVA_SC + 1];
 #pragma unroll
-                for (int k = 1; k < IVA_MAXV; ++k) {
-                    if (k > pnc) break;
-                    const double2 hi = E(pos(k));
-                    const double ph = (double)s_phi[pc0 + k - 1];
-                    sa = fma(ph, hi.x - lo.x, sa);
-                    sb = fma(ph, hi.y - lo.y, sb);
-                    lo = hi;
+                for (int k = 0; k < IVA_SC; ++k) E[k] = s_E[(ew[k >> 1] >> (16 * (k & 1))) & 0xFFFFu];
+                E[IVA_SC] = s_E[e8];
+#pragma unroll
+                for (int k = 0; k < IVA_SC; ++k) {
+                    const double ph = (double)s_phi[1 + ps * IVA_SC + k];
+                    sa = fma(ph, E[k + 1].x - E[k].x, sa);
+                    sb = fma(ph, E[k + 1].y - E[k].y, sb);
                 }
             }
 #pragma unroll
@@ -564,22 +673,21 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
                 sa += __shfl_xor(sa, d, 64);
                 sb += __shfl_xor(sb, d, 64);
             }
-            if (pm_m < P.nq && pm_sub == 0) {
-                const double qm = V.qd[pm_m];
-                b[(size_t)j * P.nq + pm_m] = (float)(qm * sa);
-                if (LR) b[(size_t)j2 * P.nq + pm_m] = (float)(qm * sb);
+            if (pact && ps == 0) {
+                const double qm = V.qd[pm];
+                b[(size_t)j * P.nq + pm] = (float)(qm * sa);
+                if (LR) b[(size_t)j2 * P.nq + pm] = (float)(qm * sb);
             }
-            load_pos(g + 1);   // used after the next group's weights and prefixes
+            load_emap(g + 1);   // used after the next group's two barriers
         } else {
-            const uint16_t *bg = V.bpos + (size_t)g * nt;
             for (int mb = 0; mb < P.nq; mb += IVA_THREADS / IVA_SUB) {
                 const int m = mb + tid / IVA_SUB, sub = tid % IVA_SUB;
                 double sa = 0.0, sb = 0.0;
                 if (m < P.nq) {
-                    const uint16_t *pm = bg + (size_t)m * ne1;       // pm[c - 1] = P(m, c), c = 1 .. ne + 1
+                    const uint16_t *em = V.emap + ((size_t)g * P.nq + m) * V.es;   // em[c - 1]: edge c
                     for (int c = 1 + sub; c <= P.ne; c += IVA_SUB) {
                         const double ph = (double)s_phi[c];
-                        const double2 hi = E(pm[c]), lo = E(pm[c - 1]);
+                        const double2 hi = s_E[em[c]], lo = s_E[em[c - 1]];
                         sa = fma(ph, hi.x - lo.x, sa);
                         sb = fma(ph, hi.y - lo.y, sb);
                     }
@@ -596,7 +704,8 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
                 }
             }
         }
-        __syncthreads();   // the next group's weights overwrite s_loc
+        // the next group's phase B overwrites s_E only after its first barrier,
+        // and its phase A writes s_wt only after this group's second one
     }
 }
 
@@ -604,15 +713,20 @@ IvArgs iv_args(const csx_geometry *h, const IvState *v)
 {
     IvArgs a;
     a.rec = v->rec;
+    a.reca = v->reca;
     a.coef = v->coef;
     a.mt = v->mt;
-    a.pp = v->pp;
-    a.bpos = v->bpos;
+    a.emap = v->emap;
+    a.emask = v->emask;
     a.qd = v->qd;
     a.nt = v->nt;
     a.n_slots = v->n_slots;
     a.n_items = v->n_items;
     a.ngroups = h->P.n_groups;
+    a.rstride = v->rstride;
+    a.nch = v->nch;
+    a.es = v->es;
+    a.cap = v->cap;
     return a;
 }
 
@@ -627,27 +741,40 @@ csx_status iv_upload(T **dst, const std::vector<T> &src, int64_t &bytes)
 
 void iv_release(IvState *v)
 {
-    void *ps[] = {v->rec, v->coef, v->mt, v->pp, v->bpos, v->qd, v->part};
+    void *ps[] = {v->rec, v->reca, v->coef, v->mt, v->pp, v->emap, v->emask, v->cnt, v->qd, v->part};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete v;
 }
 
+// The adjoint's PF form: every node's bins fit 8 threads of 8 bins.
+bool iva_pf(const KParams &P)
+{
+    return P.nq <= IVA_THREADS / IVA_SUB && P.ne <= IVA_SC * IVA_SUB;
+}
+
+// LDS of the adjoint with a prefix table of cap in-between entries.
+long iva_lds(const KParams &P, long items, long cap)
+{
+    const long rho = ((items * (P.lr ? 16 : 8)) + 15) & ~15L;
+    return rho + (2 + cap) * 16 + IVA_WAVES * 16 + IVA_WAVES * 4 + (long)std::max(P.ne + 2, IVA_SC * IVA_SUB + 2) * 4;
+}
+
 }  // namespace
 
 // Feasibility of the interval operators for a geometry: thresholds and ranks
-// in 14 bits, and both kernels' LDS within one workgroup's budget.
+// in 14 bits, and both kernels' LDS within one workgroup's budget (the
+// adjoint's with an empty prefix table; the set-up checks the real one).
 bool csx_iv_feasible(const KParams &P, int *lds_f, int *lds_a)
 {
     const long nt = (long)(P.ne + 1) * P.nq;
     const long items = P.lr ? (long)(P.ndx / 2) * (P.ndy / 2) : (long)P.ndx * (P.ndy / 2);
     const long slots = P.lr ? 2 * items : items;
-    // intervals and ranks in 14 bits; the adjoint's ranks in IVA_THREADS
-    // chunks of 16; one f value per forward thread
+    // intervals and slots in 14 bits, ranks in IVA_THREADS chunks of IVA_SC,
+    // one f value per forward thread
     if (nt >= 16384 || slots > IVA_SC * IVA_THREADS || items > 8L * IV_THREADS || 2 * P.nq > IV_THREADS) return false;
-    const long lf = ((nt * 10 + 15) & ~15L) + (nt + 1) * 8 + 2L * P.nq * 4 + 16 + IV_WAVES * 16;
-    const long la = (long)(IVA_THREADS + 1) * IVA_SC * 16 + (IVA_THREADS + 1) * 16 + (P.ne + 2) * 4 + 16 +
-                    IVA_WAVES * 16;
+    const long lf = ((nt * 10 + 15) & ~15L) + (nt + 1) * 8 + 4L * P.nq * 4 + 16 + IV_WAVES * 16;
+    const long la = iva_lds(P, items, 0);
     if (lf > CSX_LDS_MAX || la > CSX_LDS_MAX) return false;
     if (lds_f) *lds_f = (int)lf;
     if (lds_a) *lds_a = (int)la;
@@ -732,19 +859,19 @@ csx_status csx_iv_build(csx_geometry *h)
     v->nt = nt;
     v->n_items = P.lr ? (P.ndx / 2) * (P.ndy / 2) : P.ndx * (P.ndy / 2);
     v->n_slots = P.lr ? 2 * v->n_items : v->n_items;
+    v->rstride = (v->n_slots + IVA_SC - 1) / IVA_SC * IVA_SC;
+    v->nch = v->rstride / IVA_SC;
+    v->es = iva_pf(P) ? IVA_SC * IVA_SUB + IVA_SC : (ne + 1 + 7) / 8 * 8;
     v->np = 1;
     while (v->np * IV_THREADS < v->n_items) v->np *= 2;
     v->lds_f = lds_f;
-    v->lds_a = lds_a;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
         cus = 256;
     {
-        int per = (P.n_groups + cus - 1) / cus;                  // forward: one block per compute unit
+        int per = (P.n_groups + cus - 1) / cus;                  // one block per compute unit
         v->nblk_f = (P.n_groups + per - 1) / per;
-        v->nblk_a = v->nblk_f;                                   // adjoint: one as well
-        v->npa = 1;
-        while (v->npa * IVA_THREADS < v->n_items) v->npa *= 2;
+        v->nblk_a = v->nblk_f;
     }
     csx_status st;
     if ((st = iv_upload(&v->coef, coef, v->bytes)) != CSX_OK) return bail(st);
@@ -752,14 +879,24 @@ csx_status csx_iv_build(csx_geometry *h)
     if ((st = iv_upload(&v->pp, pp, v->bytes)) != CSX_OK) return bail(st);
     if ((st = iv_upload(&v->qd, qd, v->bytes)) != CSX_OK) return bail(st);
     const size_t nrec = (size_t)P.n_groups * v->n_slots;
-    const size_t nbpos = (size_t)P.n_groups * nt;
+    const size_t nreca = (size_t)P.n_groups * v->rstride;
+    const size_t nemap = (size_t)P.n_groups * nq * v->es;
+    const size_t nemask = (size_t)P.n_groups * v->nch;
     if (hipMalloc((void **)&v->rec, nrec * sizeof(uint2)) != hipSuccess ||
-        hipMalloc((void **)&v->bpos, nbpos * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc((void **)&v->reca, nreca * sizeof(uint2)) != hipSuccess ||
+        hipMalloc((void **)&v->emap, nemap * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc((void **)&v->emask, nemask) != hipSuccess ||
+        hipMalloc((void **)&v->cnt, sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&v->part, (size_t)v->nblk_f * P.npix * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         return bail(csx_fail(CSX_ENOMEM, "interval operators: records"));
     }
-    v->bytes += (int64_t)(nrec * sizeof(uint2) + nbpos * sizeof(uint16_t) + (size_t)v->nblk_f * P.npix * sizeof(float));
+    v->bytes += (int64_t)((nrec + nreca) * sizeof(uint2) + nemap * sizeof(uint16_t) + nemask + sizeof(int) +
+                          (size_t)v->nblk_f * P.npix * sizeof(float));
+    if (hipMemset(v->cnt, 0, sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(csx_fail(CSX_EHIP, "interval set-up: clearing the table counter"));
+    }
     const dim3 gr((unsigned)((nrec + 255) / 256));
     if (P.lr)
         hipLaunchKernelGGL(k_iv_records<1>, gr, dim3(256), 0, nullptr, P, h->t, v->n_slots, v->rec);
@@ -767,14 +904,25 @@ csx_status csx_iv_build(csx_geometry *h)
         hipLaunchKernelGGL(k_iv_records<0>, gr, dim3(256), 0, nullptr, P, h->t, v->n_slots, v->rec);
     int npow2 = 1;
     while (npow2 < v->n_slots) npow2 *= 2;
-    hipLaunchKernelGGL(k_iv_rank, dim3(P.n_groups), dim3(1024), npow2 * 4, nullptr, v->n_slots, npow2, v->rec, nq, ne,
-                       (const uint16_t *)v->pp, v->bpos);
+    const size_t lds_rank = (size_t)npow2 * 4 + (((size_t)nt * 2 + 15) & ~(size_t)15);
+    hipLaunchKernelGGL(k_iv_rank, dim3(P.n_groups), dim3(1024), lds_rank, nullptr, v->n_slots, npow2, v->rstride,
+                       (const uint2 *)v->rec, v->reca, nq, ne, v->es, v->nch, (const uint16_t *)v->pp, v->emap,
+                       v->emask, v->cnt);
     {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return bail(csx_fail(CSX_EHIP, std::string("interval set-up: ") + hipGetErrorString(e)));
         const hipError_t e2 = hipDeviceSynchronize();
         if (e2 != hipSuccess) return bail(csx_fail(CSX_EHIP, std::string("interval set-up: ") + hipGetErrorString(e2)));
     }
+    // the adjoint's prefix table must fit beside the detector values
+    if (hipMemcpy(&v->cap, v->cnt, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(csx_fail(CSX_EHIP, "interval set-up: reading the table size"));
+    }
+    const long la = iva_lds(P, v->n_items, v->cap);
+    if (la > CSX_LDS_MAX)
+        return bail(csx_fail(CSX_EINVAL, "interval operators: the adjoint's prefix table exceeds LDS"));
+    v->lds_a = (int)la;
     v->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     h->bytes += v->bytes;
     h->iv = v;
@@ -815,23 +963,15 @@ csx_status csx_iv_adjoint(const csx_geometry *h, const float *rho, float *b, hip
     const IvState *v = (const IvState *)h->iv;
     const IvArgs a = iv_args(h, v);
     const dim3 grid(v->nblk_a), block(IVA_THREADS);
-    const bool pf = h->P.nq <= IVA_THREADS / IVA_SUB && h->P.ne <= (IVA_MAXV - 1) * IVA_SUB;
-#define CSX_IVA(LR_, NP_)                                                                                     \
-    do {                                                                                                      \
-        if (pf)                                                                                               \
-            hipLaunchKernelGGL((k_iv_adjoint<LR_, NP_, 1>), grid, block, v->lds_a, s, h->P, a, h->t, rho, b); \
-        else                                                                                                  \
-            hipLaunchKernelGGL((k_iv_adjoint<LR_, NP_, 0>), grid, block, v->lds_a, s, h->P, a, h->t, rho, b); \
-    } while (0)
+    const bool pf = iva_pf(h->P);
+#define CSX_IVA(LR_, PF_) \
+    hipLaunchKernelGGL((k_iv_adjoint<LR_, PF_>), grid, block, v->lds_a, s, h->P, a, h->t, rho, b)
     if (h->P.lr) {
-        if (v->npa == 1) CSX_IVA(1, 1);
-        else if (v->npa == 2) CSX_IVA(1, 2);
-        else CSX_IVA(1, 4);
+        if (pf) CSX_IVA(1, 1);
+        else CSX_IVA(1, 0);
     } else {
-        if (v->npa == 1) CSX_IVA(0, 1);
-        else if (v->npa == 2) CSX_IVA(0, 2);
-        else if (v->npa == 4) CSX_IVA(0, 4);
-        else CSX_IVA(0, 8);
+        if (pf) CSX_IVA(0, 1);
+        else CSX_IVA(0, 0);
     }
 #undef CSX_IVA
     HIP_TRY(hipGetLastError());
