@@ -73,6 +73,7 @@ struct IvState {
     int nch = 0;                // rank chunks per group, rstride / IVA_SC
     int es = 0;                 // emap entries per node (ne + 1 rounded up to 8)
     int cap = 0;                // prefix-table entries between the two fixed ones (largest group)
+    int ncell = 0;              // detector cells of the upper half (columns x rows)
     int np = 1;                 // forward: work items per thread (power of 2, <= 8)
     int nblk_f = 0, nblk_a = 0;
     int lds_f = 0, lds_a = 0;
@@ -88,7 +89,7 @@ struct IvArgs {
     const uint16_t *emap;
     const uint8_t *emask;
     const double *qd;
-    int nt, n_slots, n_items, ngroups, rstride, nch, es, cap;
+    int nt, n_slots, n_items, ngroups, rstride, nch, es, cap, ncell;
 };
 
 __device__ __forceinline__ void group_voxels(const KParams &P, int LR, int g, int &j, int &j2)
@@ -167,7 +168,12 @@ __global__ void __launch_bounds__(256) k_iv_records(KParams P, DevTables T, int 
 // The adjoint's tables of one voxel group, one block per group:
 //  - the rank of every class in the order of (t, slot), by a bitonic sort of
 //    the keys (t << 14 | slot) in LDS, and the records in that order,
-//    reca[rank] = {A, mask bits | slot << 4}, zero past n_slots;
+//    reca[rank] = {A, i_j | i_j2 << 15}: for voxel j and (LR) j2 the index of
+//    the class's detector term in the adjoint's per-call table of three
+//    entries per detector cell (column, upper row) -- 3 cell + 0 for the
+//    upper pixel alone, + 1 for the lower one, + 2 for both, as the mask
+//    values select -- or 3 ncell, a zero entry, when both pairs are closed;
+//    past n_slots, A = 0 and both indices 3 ncell;
 //  - for node m and bin edge c = 1 .. ne + 1 the position P(m, c), the rank
 //    of the first class whose t reaches pp(c, m) = pos(c, m) + 1 (so the
 //    classes in bin c at node m are the ranks [P(m, c), P(m, c + 1)));
@@ -177,7 +183,8 @@ __global__ void __launch_bounds__(256) k_iv_records(KParams P, DevTables T, int 
 //    P(m, c) as its table entry (row stride es, zero past c = ne + 1), and
 //    emask bit i of byte k marks position 8 k + i as one of the entries.
 // cnt receives the largest number of in-between entries over the groups.
-__global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, int rstride, const uint2 *__restrict__ rec,
+template <int LR>
+__global__ void __launch_bounds__(1024) k_iv_rank(KParams P, int n_slots, int npow2, int rstride, const uint2 *__restrict__ rec,
                                                   uint2 *__restrict__ reca, int nq, int ne, int es, int nch,
                                                   const uint16_t *__restrict__ pp, uint16_t *__restrict__ emap,
                                                   uint8_t *__restrict__ emask, int *__restrict__ cnt)
@@ -208,12 +215,23 @@ __global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, int rs
             __syncthreads();
         }
     uint2 *ra = reca + (size_t)blockIdx.x * rstride;
+    const uint32_t Z = 3u * (uint32_t)(P.ndx * (P.ndy / 2));
     for (int r = threadIdx.x; r < rstride; r += blockDim.x) {
-        uint2 v = make_uint2(0u, 0u);
+        uint2 v = make_uint2(0u, Z | (Z << 15));
         if (r < n_slots) {
             const uint32_t sl = keys[r] & 0x3FFFu;
             const uint2 x = rg[sl];
-            v = make_uint2(x.x, (x.y & 0xFu) | (sl << 4));
+            const uint32_t bits = x.y & 0xFu;
+            // slot 2p is column a of item p, slot 2p + 1 its mirror column
+            int a, row;
+            item_class(P, LR, LR ? (int)(sl >> 1) : (int)sl, LR ? (int)(sl & 1u) : 0, a, row);
+            auto term = [&](uint32_t up, uint32_t dn, int col) -> uint32_t {
+                if (!up && !dn) return Z;
+                return 3u * (uint32_t)(row * P.ndx + col) + (up ? (dn ? 2u : 0u) : 1u);
+            };
+            const uint32_t i0 = term(bits & 1u, (bits >> 1) & 1u, a);
+            const uint32_t i1 = LR ? term((bits >> 2) & 1u, (bits >> 3) & 1u, P.ndx - 1 - a) : Z;
+            v = make_uint2(x.x, i0 | (i1 << 15));
         }
         ra[r] = v;
     }
@@ -271,36 +289,121 @@ __global__ void __launch_bounds__(1024) k_iv_rank(int n_slots, int npow2, int rs
 }
 
 // ---------------------------------------------------------------------------
+// Wave-level scans and sums through DPP lane moves (row shifts within rows of
+// 16 lanes, then the row broadcasts of lanes 15 and 31), so that no step
+// waits on an LDS permute.  Lanes without a source add zero.  The order of
+// the additions is fixed, so results are reproducible.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+
+constexpr int DPP_SHR1 = 0x111, DPP_SHR2 = 0x112, DPP_SHR4 = 0x114, DPP_SHR8 = 0x118;
+constexpr int DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141;
+
+// a lane move over all rows whose lanes without a source read zero
+template <int CTRL>
+__device__ __forceinline__ double dppz_f64(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// inclusive scan within each row of 16 lanes
+__device__ __forceinline__ double row_scan(double x)
+{
+    x += dppz_f64<DPP_SHR1>(x);
+    x += dppz_f64<DPP_SHR2>(x);
+    x += dppz_f64<DPP_SHR4>(x);
+    x += dppz_f64<DPP_SHR8>(x);
+    return x;
+}
+
+__device__ __forceinline__ int row_scan(int x)
+{
+    x += dpp_i32<DPP_SHR1, 0xf>(x);
+    x += dpp_i32<DPP_SHR2, 0xf>(x);
+    x += dpp_i32<DPP_SHR4, 0xf>(x);
+    x += dpp_i32<DPP_SHR8, 0xf>(x);
+    return x;
+}
+
+// inclusive scan over the 64 lanes of a wave
+__device__ __forceinline__ double wave_scan(double x)
+{
+    x = row_scan(x);
+    x += dpp_f64<DPP_BCAST15, 0xa>(x);
+    x += dpp_f64<DPP_BCAST31, 0xc>(x);
+    return x;
+}
+
+__device__ __forceinline__ int wave_scan(int x)
+{
+    x = row_scan(x);
+    x += dpp_i32<DPP_BCAST15, 0xa>(x);
+    x += dpp_i32<DPP_BCAST31, 0xc>(x);
+    return x;
+}
+
+// sum over each group of 8 lanes (every lane of the group gets it)
+__device__ __forceinline__ double oct_sum(double x)
+{
+    x += dppz_f64<DPP_XOR1>(x);
+    x += dppz_f64<DPP_XOR2>(x);
+    x += dppz_f64<DPP_HALF_MIRROR>(x);
+    return x;
+}
+
+__device__ __forceinline__ double read_lane(double v, int l)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum of the first wv of 16 values held by lanes 0 .. 15 of every row (v =
+// value of wave lane & 15): a row scan, then lane wv - 1 read as a scalar.
+__device__ __forceinline__ double sum_below(double v, int wv)
+{
+    const double s = row_scan(v);
+    return wv > 0 ? read_lane(s, wv - 1) : 0.0;
+}
+
+__device__ __forceinline__ int sum_below(int v, int wv)
+{
+    const int s = row_scan(v);
+    return wv > 0 ? __builtin_amdgcn_readlane(s, wv - 1) : 0;
+}
+
+// ---------------------------------------------------------------------------
 // Block-wide exclusive scan of a pair of float64 values (fixed order): an
 // inclusive scan within each wave, the wave totals through LDS, and the sum
-// of the totals of the waves below by an xor tree across 16 lanes (every
-// row of 16 lanes holds the 16 totals).  At most 16 waves.
+// of the totals of the waves below.  At most 16 waves.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double2 block_exclusive_scan(double a, double b, double2 *s_tot)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double ia = a, ib = b;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double ua = __shfl_up(ia, d, 64), ub = __shfl_up(ib, d, 64);
-        if (lane >= d) {
-            ia += ua;
-            ib += ub;
-        }
-    }
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const double ia = wave_scan(a), ib = wave_scan(b);
     if (lane == 63) s_tot[wv] = make_double2(ia, ib);
-    double ea = __shfl_up(ia, 1, 64), eb = __shfl_up(ib, 1, 64);
-    if (lane == 0) ea = eb = 0.0;
     __syncthreads();
     const double2 t = s_tot[lane & 15];
-    const bool below = (lane & 15) < wv;
-    double oa = below ? t.x : 0.0, ob = below ? t.y : 0.0;
-#pragma unroll
-    for (int d = 8; d > 0; d >>= 1) {
-        oa += __shfl_xor(oa, d, 16);
-        ob += __shfl_xor(ob, d, 16);
-    }
-    return make_double2(oa + ea, ob + eb);
+    const double oa = sum_below(t.x, wv), ob = sum_below(t.y, wv);
+    return make_double2(oa + (ia - a), ob + (ib - b));
 }
 
 // ---------------------------------------------------------------------------
@@ -308,7 +411,7 @@ __device__ __forceinline__ double2 block_exclusive_scan(double a, double b, doub
 // groups; thread k owns work items k, k + IV_THREADS, ... (NP of them) and
 // keeps their pixels' sums in registers; partial image per block.
 // ---------------------------------------------------------------------------
-template <int LR, int NP>
+template <int LR, int NP, int TPM>
 __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, const float *__restrict__ f,
                                                            float *__restrict__ part)
 {
@@ -372,21 +475,28 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
         const float *sf = s_f + (g & 1) * 2 * P.nq;
         if (tid < 2 * P.nq) s_f[((g + 1) & 1) * 2 * P.nq + tid] = fv;
         fv = load_f(g + 2);
-        // F tables of voxels j and j2: float64 prefix sums over the sorted thresholds
+        // F tables of voxels j and j2: float64 prefix sums over the sorted
+        // thresholds, TPM per thread (loads issued together, kept for pass 2)
+        double ca[TPM];
+        int mm[TPM];
+#pragma unroll
+        for (int k = 0; k < TPM; ++k) {
+            const bool in = t0 + k < t1;
+            ca[k] = in ? s_coef[t0 + k] : 0.0;
+            mm[k] = in ? (int)s_mt[t0 + k] : 0;
+        }
         double la = 0.0, lb = 0.0;
-        for (int t = t0; t < t1; ++t) {
-            const double c = s_coef[t];
-            const int m = s_mt[t];
-            la = fma(c, (double)sf[m], la);
-            lb = fma(c, (double)sf[P.nq + m], lb);
+#pragma unroll
+        for (int k = 0; k < TPM; ++k) {
+            la = fma(ca[k], (double)sf[mm[k]], la);
+            lb = fma(ca[k], (double)sf[P.nq + mm[k]], lb);
         }
         double2 run = block_exclusive_scan(la, lb, s_tot);
-        for (int t = t0; t < t1; ++t) {
-            const double c = s_coef[t];
-            const int m = s_mt[t];
-            run.x = fma(c, (double)sf[m], run.x);
-            run.y = fma(c, (double)sf[P.nq + m], run.y);
-            s_F[t + 1] = make_float2((float)run.x, (float)run.y);
+#pragma unroll
+        for (int k = 0; k < TPM; ++k) {
+            run.x = fma(ca[k], (double)sf[mm[k]], run.x);
+            run.y = fma(ca[k], (double)sf[P.nq + mm[k]], run.y);
+            if (t0 + k < t1) s_F[t0 + k + 1] = make_float2((float)run.x, (float)run.y);
         }
         if (tid == 0) s_F[0] = make_float2(0.0f, 0.0f);
         __syncthreads();
@@ -492,15 +602,6 @@ __global__ void __launch_bounds__(1024) k_iv_sum(const float *__restrict__ part,
 // prefixes, and a bin holding only a few small weights behind large ones
 // (the lowest q nodes see only the smallest angles) needs that precision to
 // stay accurate relative to itself.
-template <int LR>
-struct IvRho {
-    using T = float2;      // detector values of a class: (upper, lower) pixel
-};
-template <>
-struct IvRho<1> {
-    using T = float4;      // of a mirror pair: (upper, lower) at column a, then at ndx - 1 - a
-};
-
 // PF = 1: nq <= IVA_THREADS / IVA_SUB and ne <= 8 IVA_SUB: thread (m, sub)
 // owns bins c = 1 + 8 sub .. 8 + 8 sub of node m and holds the 9 table
 // indices of their edges in registers (one 16-byte and one 2-byte load from
@@ -509,48 +610,44 @@ template <int LR, int PF>
 __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V, const DevTables T,
                                                             const float *__restrict__ rho, float *__restrict__ b)
 {
-    using RT = typename IvRho<LR>::T;
     extern __shared__ __align__(16) unsigned char lds[];
-    RT *s_rho = (RT *)lds;                                                              // [n_items]
-    double2 *s_E = (double2 *)(lds + (((size_t)V.n_items * sizeof(RT) + 15) & ~(size_t)15));  // [2 + cap]
-    double2 *s_wt = s_E + 2 + V.cap;                                                    // [IVA_WAVES]
-    int *s_wc = (int *)(s_wt + IVA_WAVES);                                              // [IVA_WAVES]
-    float *s_phi = (float *)(s_wc + IVA_WAVES);                                         // [nphi]
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const size_t ntab = ((size_t)V.ncell * 3 + 1) * sizeof(float);
+    float *s_tab = (float *)lds;                                     // [3 ncell + 1]
+    double2 *s_E = (double2 *)(lds + ((ntab + 15) & ~(size_t)15));   // [2 + cap]
+    double2 *s_wt = s_E + 2 + V.cap;                                 // [IVA_WAVES]
+    int *s_wc = (int *)(s_wt + IVA_WAVES);                           // [IVA_WAVES]
+    double *s_phi = (double *)(s_wc + IVA_WAVES);                    // [nphi]
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nphi = max(P.ne + 2, IVA_SC * IVA_SUB + 2);
     for (int k = tid; k < nphi; k += IVA_THREADS)
-        s_phi[k] = k >= P.ne + 2 ? 0.0f : P.td == CSX_TABLE_BF16 ? bf16_to_f32(T.phi16[k]) : T.phi32[k];
-    // detector values of every item, the same for every group
+        s_phi[k] = k >= P.ne + 2 ? 0.0 : (double)(P.td == CSX_TABLE_BF16 ? bf16_to_f32(T.phi16[k]) : T.phi32[k]);
+    // detector terms of every cell (column, upper row): rho_u, rho_d and
+    // rho_u + rho_d, the same for every group; then the zero entry
     const int half_y = P.ndy / 2;
-    for (int p = tid; p < V.n_items; p += IVA_THREADS) {
-        int a, r;
-        item_class(P, LR, p, 0, a, r);
-        const int bu = half_y + r, bd = P.ndy - 1 - bu;
-        if constexpr (LR) {
-            const int ab = P.ndx - 1 - a;
-            s_rho[p] = make_float4(rho[bu * P.ndx + a], rho[bd * P.ndx + a], rho[bu * P.ndx + ab], rho[bd * P.ndx + ab]);
-        } else {
-            s_rho[p] = make_float2(rho[bu * P.ndx + a], rho[bd * P.ndx + a]);
-        }
+    for (int c = tid; c < V.ncell; c += IVA_THREADS) {
+        const int col = c % P.ndx, bu = half_y + c / P.ndx, bd = P.ndy - 1 - bu;
+        const float u = rho[bu * P.ndx + col], d = rho[bd * P.ndx + col];
+        s_tab[3 * c] = u;
+        s_tab[3 * c + 1] = d;
+        s_tab[3 * c + 2] = u + d;
     }
+    if (tid == 0) s_tab[3 * V.ncell] = 0.0f;
     if (tid == 0) s_E[0] = make_double2(0.0, 0.0);
     const int per = (V.ngroups + gridDim.x - 1) / gridDim.x;
     const int g0 = blockIdx.x * per, g1 = min(V.ngroups, g0 + per);
-    // records and position bits of the thread's chunk, one group ahead
+    if (g0 >= g1) return;
+    // records and position bits of the thread's chunk; a thread past the
+    // last chunk reads the last one and contributes nothing.  Group g + 1 is
+    // loaded (clamped to the block's last group) into the register set that
+    // group g does not use.
     const bool own = tid < V.nch;
-    uint4 nr[IVA_SC / 2];
-    uint32_t nm = 0u;
-    auto load_chunk = [&](int g) {
-        if (own && g < g1) {
-            const uint4 *src = (const uint4 *)(V.reca + (size_t)g * V.rstride + (size_t)tid * IVA_SC);
+    const int ch = own ? tid : V.nch - 1;
+    auto load_chunk = [&](int g, uint4 (&r)[IVA_SC / 2], uint32_t &m) {
+        const int gg = min(g, g1 - 1);
+        const uint4 *src = (const uint4 *)(V.reca + (size_t)gg * V.rstride + (size_t)ch * IVA_SC);
 #pragma unroll
-            for (int i = 0; i < IVA_SC / 2; ++i) nr[i] = src[i];
-            nm = V.emask[(size_t)g * V.nch + tid];
-        } else {
-#pragma unroll
-            for (int i = 0; i < IVA_SC / 2; ++i) nr[i] = make_uint4(0u, 0u, 0u, 0u);
-            nm = 0u;
-        }
+        for (int i = 0; i < IVA_SC / 2; ++i) r[i] = src[i];
+        m = V.emask[(size_t)gg * V.nch + ch];
     };
     // PF: this thread's node and bins, and the table indices of their edges
     const int pm = tid / IVA_SUB, ps = tid % IVA_SUB;
@@ -558,28 +655,18 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
     uint4 ev = make_uint4(0u, 0u, 0u, 0u);
     uint32_t e8 = 0u;
     auto load_emap = [&](int g) {
-        if (!PF) return;
-        if (pact && g < g1) {
-            const uint16_t *row = V.emap + ((size_t)g * P.nq + pm) * V.es + ps * IVA_SC;
+        if (PF && pact) {
+            const uint16_t *row = V.emap + ((size_t)min(g, g1 - 1) * P.nq + pm) * V.es + ps * IVA_SC;
             ev = *(const uint4 *)row;
             e8 = row[IVA_SC];
-        } else {
-            ev = make_uint4(0u, 0u, 0u, 0u);
-            e8 = 0u;
         }
     };
-    load_chunk(g0);
-    load_emap(g0);
-    __syncthreads();
-    for (int g = g0; g < g1; ++g) {
+    auto group = [&](int g, const uint4 (&cr)[IVA_SC / 2], uint32_t cm, uint4 (&nr)[IVA_SC / 2], uint32_t &nm) {
         int j, j2;
         group_voxels(P, LR, g, j, j2);
+        load_chunk(g + 1, nr, nm);
         // A. weights of the chunk's classes and their prefixes within the chunk
-        uint4 cr[IVA_SC / 2];
-#pragma unroll
-        for (int i = 0; i < IVA_SC / 2; ++i) cr[i] = nr[i];
-        const uint32_t msk = nm;
-        load_chunk(g + 1);
+        const uint32_t msk = own ? cm : 0u;
         double2 loc[IVA_SC];
         double la = 0.0, lb = 0.0;
 #pragma unroll
@@ -587,62 +674,30 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
             loc[i] = make_double2(la, lb);
             const float A = __uint_as_float((i & 1) ? cr[i >> 1].z : cr[i >> 1].x);
             const uint32_t w = (i & 1) ? cr[i >> 1].w : cr[i >> 1].y;
-            const uint32_t sl = w >> 4;
-            float c0, c1 = 0.0f;
-            if constexpr (LR) {
-                // slot 2p is column a of item p, slot 2p + 1 its mirror column
-                const float4 q = s_rho[sl >> 1];
-                const bool mir = (sl & 1u) != 0u;
-                const float u0 = mir ? q.z : q.x, d0 = mir ? q.w : q.y;
-                const float u1 = mir ? q.x : q.z, d1 = mir ? q.y : q.w;
-                c0 = A * ((float)(w & 1u) * u0 + (float)((w >> 1) & 1u) * d0);
-                c1 = A * ((float)((w >> 2) & 1u) * u1 + (float)((w >> 3) & 1u) * d1);
-            } else {
-                const float2 q = s_rho[sl];
-                c0 = A * ((float)(w & 1u) * q.x + (float)((w >> 1) & 1u) * q.y);
-            }
+            // A (T_u rho_u + T_d rho_d) through the cell table, as the direct
+            // kernels form it: the entry is rho_u, rho_d or their float32 sum
+            const float c0 = A * s_tab[w & 0x7FFFu];
+            const float c1 = LR ? A * s_tab[w >> 15] : 0.0f;
             la += (double)c0;
             lb += (double)c1;
         }
+        if (!own) la = lb = 0.0;
         const int cn = __popc(msk);
-        double ia = la, ib = lb;
-        int ic = cn;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const double ua = __shfl_up(ia, d, 64), ub = __shfl_up(ib, d, 64);
-            const int uc = __shfl_up(ic, d, 64);
-            if (lane >= d) {
-                ia += ua;
-                ib += ub;
-                ic += uc;
-            }
-        }
+        const double ia = wave_scan(la), ib = wave_scan(lb);
+        const int ic = wave_scan(cn);
         if (lane == 63) {
             s_wt[wv] = make_double2(ia, ib);
             s_wc[wv] = ic;
-        }
-        double ea = __shfl_up(ia, 1, 64), eb = __shfl_up(ib, 1, 64);
-        int ec = __shfl_up(ic, 1, 64);
-        if (lane == 0) {
-            ea = eb = 0.0;
-            ec = 0;
         }
         __syncthreads();
         // B. prefixes at the chunk's table positions
         {
             const double2 t = s_wt[lane & 15];
             const int tc = s_wc[lane & 15];
-            const bool below = (lane & 15) < wv;
-            double oa = below ? t.x : 0.0, ob = below ? t.y : 0.0;
-            int oc = below ? tc : 0;
-#pragma unroll
-            for (int d = 8; d > 0; d >>= 1) {
-                oa += __shfl_xor(oa, d, 16);
-                ob += __shfl_xor(ob, d, 16);
-                oc += __shfl_xor(oc, d, 16);
-            }
-            const double ba = oa + ea, bb = ob + eb;
-            int ci = 2 + oc + ec;
+            const double oa = sum_below(t.x, wv), ob = sum_below(t.y, wv);
+            const int oc = sum_below(tc, wv);
+            const double ba = oa + (ia - la), bb = ob + (ib - lb);
+            int ci = 2 + oc + (ic - cn);
 #pragma unroll
             for (int i = 0; i < IVA_SC; ++i)
                 if ((msk >> i) & 1u) {
@@ -663,16 +718,13 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
                 E[IVA_SC] = s_E[e8];
 #pragma unroll
                 for (int k = 0; k < IVA_SC; ++k) {
-                    const double ph = (double)s_phi[1 + ps * IVA_SC + k];
+                    const double ph = s_phi[1 + ps * IVA_SC + k];
                     sa = fma(ph, E[k + 1].x - E[k].x, sa);
                     sb = fma(ph, E[k + 1].y - E[k].y, sb);
                 }
             }
-#pragma unroll
-            for (int d = IVA_SUB / 2; d > 0; d >>= 1) {
-                sa += __shfl_xor(sa, d, 64);
-                sb += __shfl_xor(sb, d, 64);
-            }
+            sa = oct_sum(sa);
+            sb = oct_sum(sb);
             if (pact && ps == 0) {
                 const double qm = V.qd[pm];
                 b[(size_t)j * P.nq + pm] = (float)(qm * sa);
@@ -686,17 +738,14 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
                 if (m < P.nq) {
                     const uint16_t *em = V.emap + ((size_t)g * P.nq + m) * V.es;   // em[c - 1]: edge c
                     for (int c = 1 + sub; c <= P.ne; c += IVA_SUB) {
-                        const double ph = (double)s_phi[c];
+                        const double ph = s_phi[c];
                         const double2 hi = s_E[em[c]], lo = s_E[em[c - 1]];
                         sa = fma(ph, hi.x - lo.x, sa);
                         sb = fma(ph, hi.y - lo.y, sb);
                     }
                 }
-#pragma unroll
-                for (int d = IVA_SUB / 2; d > 0; d >>= 1) {
-                    sa += __shfl_xor(sa, d, 64);
-                    sb += __shfl_xor(sb, d, 64);
-                }
+                sa = oct_sum(sa);
+                sb = oct_sum(sb);
                 if (m < P.nq && sub == 0) {
                     const double qm = V.qd[m];
                     b[(size_t)j * P.nq + m] = (float)(qm * sa);
@@ -706,6 +755,15 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
         }
         // the next group's phase B overwrites s_E only after its first barrier,
         // and its phase A writes s_wt only after this group's second one
+    };
+    uint4 ra[IVA_SC / 2], rb[IVA_SC / 2];
+    uint32_t ma = 0u, mb = 0u;
+    load_chunk(g0, ra, ma);
+    load_emap(g0);
+    __syncthreads();
+    for (int g = g0; g < g1; g += 2) {
+        group(g, ra, ma, rb, mb);
+        if (g + 1 < g1) group(g + 1, rb, mb, ra, ma);
     }
 }
 
@@ -727,6 +785,7 @@ IvArgs iv_args(const csx_geometry *h, const IvState *v)
     a.nch = v->nch;
     a.es = v->es;
     a.cap = v->cap;
+    a.ncell = v->ncell;
     return a;
 }
 
@@ -753,11 +812,13 @@ bool iva_pf(const KParams &P)
     return P.nq <= IVA_THREADS / IVA_SUB && P.ne <= IVA_SC * IVA_SUB;
 }
 
-// LDS of the adjoint with a prefix table of cap in-between entries.
-long iva_lds(const KParams &P, long items, long cap)
+// LDS of the adjoint with a prefix table of cap in-between entries: the
+// cell table, the prefix table, wave totals and the float64 spectrum.
+long iva_lds(const KParams &P, long cap)
 {
-    const long rho = ((items * (P.lr ? 16 : 8)) + 15) & ~15L;
-    return rho + (2 + cap) * 16 + IVA_WAVES * 16 + IVA_WAVES * 4 + (long)std::max(P.ne + 2, IVA_SC * IVA_SUB + 2) * 4;
+    const long cells = (long)P.ndx * (P.ndy / 2);
+    return (((cells * 3 + 1) * 4 + 15) & ~15L) + (2 + cap) * 16 + IVA_WAVES * 16 + IVA_WAVES * 4 +
+           (long)std::max(P.ne + 2, IVA_SC * IVA_SUB + 2) * 8;
 }
 
 }  // namespace
@@ -770,11 +831,12 @@ bool csx_iv_feasible(const KParams &P, int *lds_f, int *lds_a)
     const long nt = (long)(P.ne + 1) * P.nq;
     const long items = P.lr ? (long)(P.ndx / 2) * (P.ndy / 2) : (long)P.ndx * (P.ndy / 2);
     const long slots = P.lr ? 2 * items : items;
-    // intervals and slots in 14 bits, ranks in IVA_THREADS chunks of IVA_SC,
-    // one f value per forward thread
+    // intervals and slots in 14 bits, ranks in IVA_THREADS chunks of IVA_SC
+    // (so the adjoint's 3 ncell + 1 cell-table entries, ncell = slots, index
+    // in 15 bits), one f value per forward thread
     if (nt >= 16384 || slots > IVA_SC * IVA_THREADS || items > 8L * IV_THREADS || 2 * P.nq > IV_THREADS) return false;
     const long lf = ((nt * 10 + 15) & ~15L) + (nt + 1) * 8 + 4L * P.nq * 4 + 16 + IV_WAVES * 16;
-    const long la = iva_lds(P, items, 0);
+    const long la = iva_lds(P, 0);
     if (lf > CSX_LDS_MAX || la > CSX_LDS_MAX) return false;
     if (lds_f) *lds_f = (int)lf;
     if (lds_a) *lds_a = (int)la;
@@ -862,6 +924,7 @@ csx_status csx_iv_build(csx_geometry *h)
     v->rstride = (v->n_slots + IVA_SC - 1) / IVA_SC * IVA_SC;
     v->nch = v->rstride / IVA_SC;
     v->es = iva_pf(P) ? IVA_SC * IVA_SUB + IVA_SC : (ne + 1 + 7) / 8 * 8;
+    v->ncell = P.ndx * (P.ndy / 2);
     v->np = 1;
     while (v->np * IV_THREADS < v->n_items) v->np *= 2;
     v->lds_f = lds_f;
@@ -905,23 +968,27 @@ csx_status csx_iv_build(csx_geometry *h)
     int npow2 = 1;
     while (npow2 < v->n_slots) npow2 *= 2;
     const size_t lds_rank = (size_t)npow2 * 4 + (((size_t)nt * 2 + 15) & ~(size_t)15);
-    hipLaunchKernelGGL(k_iv_rank, dim3(P.n_groups), dim3(1024), lds_rank, nullptr, v->n_slots, npow2, v->rstride,
-                       (const uint2 *)v->rec, v->reca, nq, ne, v->es, v->nch, (const uint16_t *)v->pp, v->emap,
-                       v->emask, v->cnt);
+#define CSX_IVR(LR_)                                                                                             \
+    hipLaunchKernelGGL(k_iv_rank<LR_>, dim3(P.n_groups), dim3(1024), lds_rank, nullptr, P, v->n_slots, npow2,     \
+                       v->rstride, (const uint2 *)v->rec, v->reca, nq, ne, v->es, v->nch, (const uint16_t *)v->pp, \
+                       v->emap, v->emask, v->cnt)
+    if (P.lr) CSX_IVR(1);
+    else CSX_IVR(0);
+#undef CSX_IVR
     {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return bail(csx_fail(CSX_EHIP, std::string("interval set-up: ") + hipGetErrorString(e)));
         const hipError_t e2 = hipDeviceSynchronize();
         if (e2 != hipSuccess) return bail(csx_fail(CSX_EHIP, std::string("interval set-up: ") + hipGetErrorString(e2)));
     }
-    // the adjoint's prefix table must fit beside the detector values
+    // the adjoint's prefix table must fit beside the cell table
     if (hipMemcpy(&v->cap, v->cnt, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
         (void)hipGetLastError();
         return bail(csx_fail(CSX_EHIP, "interval set-up: reading the table size"));
     }
-    const long la = iva_lds(P, v->n_items, v->cap);
+    const long la = iva_lds(P, v->cap);
     if (la > CSX_LDS_MAX)
-        return bail(csx_fail(CSX_EINVAL, "interval operators: the adjoint's prefix table exceeds LDS"));
+        return bail(csx_fail(CSX_EINVAL, "interval operators: the adjoint's tables exceed LDS"));
     v->lds_a = (int)la;
     v->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     h->bytes += v->bytes;
@@ -937,19 +1004,26 @@ csx_status csx_iv_forward(const csx_geometry *h, const float *f, float *part, si
     else if ((size_t)v->nblk_f * h->P.npix > part_cap) return csx_fail(CSX_EINVAL, "forward partials exceed the buffer");
     const IvArgs a = iv_args(h, v);
     const dim3 grid(v->nblk_f), block(IV_THREADS);
-#define CSX_IVF(LR_, NP_) \
-    hipLaunchKernelGGL((k_iv_forward<LR_, NP_>), grid, block, v->lds_f, s, h->P, a, f, part)
+#define CSX_IVF(LR_, NP_, TPM_) \
+    hipLaunchKernelGGL((k_iv_forward<LR_, NP_, TPM_>), grid, block, v->lds_f, s, h->P, a, f, part)
+#define CSX_IVF_T(LR_, NP_)           \
+    do {                              \
+        if (tpm8) CSX_IVF(LR_, NP_, 8); \
+        else CSX_IVF(LR_, NP_, 16);   \
+    } while (0)
+    // thresholds per thread in the F scan
+    const bool tpm8 = (v->nt + IV_THREADS - 1) / IV_THREADS <= 8;
     if (h->P.lr) {
-        if (v->np == 1) CSX_IVF(1, 1);
-        else if (v->np == 2) CSX_IVF(1, 2);
-        else if (v->np == 4) CSX_IVF(1, 4);
-        else CSX_IVF(1, 8);
+        if (v->np == 1) CSX_IVF_T(1, 1);
+        else if (v->np == 2) CSX_IVF_T(1, 2);
+        else CSX_IVF_T(1, 4);
     } else {
-        if (v->np == 1) CSX_IVF(0, 1);
-        else if (v->np == 2) CSX_IVF(0, 2);
-        else if (v->np == 4) CSX_IVF(0, 4);
-        else CSX_IVF(0, 8);
+        if (v->np == 1) CSX_IVF_T(0, 1);
+        else if (v->np == 2) CSX_IVF_T(0, 2);
+        else if (v->np == 4) CSX_IVF_T(0, 4);
+        else CSX_IVF_T(0, 8);
     }
+#undef CSX_IVF_T
 #undef CSX_IVF
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_iv_sum, dim3((h->P.npix + 63) / 64), dim3(1024), 0, s, (const float *)part, v->nblk_f,
