@@ -390,23 +390,6 @@ __device__ __forceinline__ int sum_below(int v, int wv)
 }
 
 // ---------------------------------------------------------------------------
-// Block-wide exclusive scan of a pair of float64 values (fixed order): an
-// inclusive scan within each wave, the wave totals through LDS, and the sum
-// of the totals of the waves below.  At most 16 waves.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double2 block_exclusive_scan(double a, double b, double2 *s_tot)
-{
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const double ia = wave_scan(a), ib = wave_scan(b);
-    if (lane == 63) s_tot[wv] = make_double2(ia, ib);
-    __syncthreads();
-    const double2 t = s_tot[lane & 15];
-    const double oa = sum_below(t.x, wv), ob = sum_below(t.y, wv);
-    return make_double2(oa + (ia - a), ob + (ib - b));
-}
-
-// ---------------------------------------------------------------------------
 // Forward: g = A f.  Block = IV_THREADS threads, a contiguous range of voxel
 // groups; thread k owns work items k, k + IV_THREADS, ... (NP of them) and
 // keeps their pixels' sums in registers; partial image per block.
@@ -418,10 +401,12 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
     extern __shared__ __align__(16) unsigned char lds[];
     double *s_coef = (double *)lds;
     uint16_t *s_mt = (uint16_t *)(s_coef + V.nt);
-    float2 *s_F = (float2 *)(lds + (((size_t)V.nt * 10 + 15) & ~(size_t)15));
-    float *s_f = (float *)(s_F + V.nt + 1);                                   // [2][2 nq]
-    double2 *s_tot = (double2 *)(((uintptr_t)(s_f + 4 * P.nq) + 15) & ~(uintptr_t)15);
-    const int tid = threadIdx.x;
+    const size_t fst = ((size_t)(V.nt + 1) * 8 + 15) & ~(size_t)15;                   // bytes per F table
+    float2 *s_F0 = (float2 *)(lds + (((size_t)V.nt * 10 + 15) & ~(size_t)15));      // [2][nt + 1]
+    double *s_f = (double *)((unsigned char *)s_F0 + 2 * fst);                       // [2][2 nq]
+    double2 *s_tot = (double2 *)(s_f + 4 * P.nq);                                    // [IV_WAVES]
+    auto s_F = [&](int g) { return (float2 *)((unsigned char *)s_F0 + (g & 1) * fst); };
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int i = tid; i < V.nt; i += IV_THREADS) {
         s_coef[i] = V.coef[i];
         s_mt[i] = V.mt[i];
@@ -429,7 +414,7 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
     // groups of this block
     const int per = (V.ngroups + gridDim.x - 1) / gridDim.x;
     const int g0 = blockIdx.x * per, g1 = min(V.ngroups, g0 + per);
-    // thresholds of this thread in the scan
+    // thresholds of this thread in the scan (at most TPM)
     const int tper = (V.nt + IV_THREADS - 1) / IV_THREADS;
     const int t0 = min(V.nt, tid * tper), t1 = min(V.nt, t0 + tper);
 
@@ -439,27 +424,24 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
     for (int i = 0; i < NP; ++i)
 #pragma unroll
         for (int k = 0; k < NO; ++k) o[i][k] = 0.0f;
-    // records of the thread's items, prefetched one group ahead
-    uint4 nr[NP];
-    auto load_rec = [&](int g) {
+    // records of the thread's items; group g + 1 is loaded (clamped to the
+    // block's last group, items clamped to the last one) into the register
+    // set that group g does not use
+    auto load_rec = [&](int g, uint4 (&r)[NP]) {
+        const uint2 *rg = V.rec + (size_t)min(g, g1 - 1) * V.n_slots;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-            const int p = tid + i * IV_THREADS;
-            nr[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (p < V.n_items && g < g1) {
-                const uint2 *rg = V.rec + (size_t)g * V.n_slots;
-                if (LR) {
-                    nr[i] = *(const uint4 *)(rg + 2 * p);
-                } else {
-                    const uint2 v = rg[p];
-                    nr[i] = make_uint4(v.x, v.y, 0u, 0u);
-                }
+            const int p = min(tid + i * IV_THREADS, V.n_items - 1);
+            if (LR) {
+                r[i] = *(const uint4 *)(rg + 2 * p);
+            } else {
+                const uint2 v = rg[p];
+                r[i] = make_uint4(v.x, v.y, 0u, 0u);
             }
         }
     };
     // thread i < 2 nq carries f of a group's voxel j (i < nq) or j2; the
-    // values of group g sit in s_f[g & 1], written one group ahead, so the
-    // barrier that publishes a group's F table also publishes the next f
+    // values of group g sit in s_f[g & 1] (float64)
     auto load_f = [&](int g) -> float {
         if (tid >= 2 * P.nq || g >= g1) return 0.0f;
         int j, j2;
@@ -467,49 +449,71 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
         if (tid < P.nq) return f[(size_t)j * P.nq + tid];
         return LR ? f[(size_t)j2 * P.nq + tid - P.nq] : 0.0f;
     };
-    if (tid < 2 * P.nq) s_f[(g0 & 1) * 2 * P.nq + tid] = load_f(g0);
-    float fv = load_f(g0 + 1);
-    load_rec(g0);
-    __syncthreads();
-    for (int g = g0; g < g1; ++g) {
-        const float *sf = s_f + (g & 1) * 2 * P.nq;
-        if (tid < 2 * P.nq) s_f[((g + 1) & 1) * 2 * P.nq + tid] = fv;
-        fv = load_f(g + 2);
-        // F tables of voxels j and j2: float64 prefix sums over the sorted
-        // thresholds, TPM per thread (loads issued together, kept for pass 2)
-        double ca[TPM];
-        int mm[TPM];
-#pragma unroll
+    // F tables of group g's voxels j and j2: float64 prefix sums over the
+    // sorted thresholds, in two parts around a barrier.  Part 1: the thread's
+    // local sums (with at most 5 thresholds per thread their prefixes stay
+    // in registers) and the wave scan of the sums, wave totals to s_tot.
+    constexpr int KEEP = TPM <= 5;
+    constexpr int UNR = TPM > 5 ? 4 : TPM;
+    double la[KEEP ? TPM : 1], lb[KEEP ? TPM : 1];
+    double sa = 0.0, sb = 0.0, ia = 0.0, ib = 0.0;
+    auto scan1 = [&](int g) {
+        const double *sf = s_f + (g & 1) * 2 * P.nq;
+        sa = sb = 0.0;
+#pragma unroll UNR
         for (int k = 0; k < TPM; ++k) {
             const bool in = t0 + k < t1;
-            ca[k] = in ? s_coef[t0 + k] : 0.0;
-            mm[k] = in ? (int)s_mt[t0 + k] : 0;
+            const double c = in ? s_coef[t0 + k] : 0.0;
+            const int m = in ? (int)s_mt[t0 + k] : 0;
+            sa = fma(c, sf[m], sa);
+            sb = fma(c, sf[P.nq + m], sb);
+            if constexpr (KEEP) {
+                la[k] = sa;
+                lb[k] = sb;
+            }
         }
-        double la = 0.0, lb = 0.0;
+        ia = wave_scan(sa);
+        ib = wave_scan(sb);
+        if (lane == 63) s_tot[wv] = make_double2(ia, ib);
+    };
+    // Part 2 (after the barrier): the totals of the waves below, then F at
+    // every threshold of the thread into s_F(g).
+    auto scan2 = [&](int g) {
+        const double2 t = s_tot[lane & 15];
+        const double ba = sum_below(t.x, wv) + (ia - sa), bb = sum_below(t.y, wv) + (ib - sb);
+        float2 *F = s_F(g);
+        if constexpr (KEEP) {
 #pragma unroll
-        for (int k = 0; k < TPM; ++k) {
-            la = fma(ca[k], (double)sf[mm[k]], la);
-            lb = fma(ca[k], (double)sf[P.nq + mm[k]], lb);
+            for (int k = 0; k < TPM; ++k)
+                if (t0 + k < t1) F[t0 + k + 1] = make_float2((float)(ba + la[k]), (float)(bb + lb[k]));
+        } else {
+            const double *sf = s_f + (g & 1) * 2 * P.nq;
+            double ra = 0.0, rb = 0.0;
+#pragma unroll UNR
+            for (int k = 0; k < TPM; ++k) {
+                const bool in = t0 + k < t1;
+                const double c = in ? s_coef[t0 + k] : 0.0;
+                const int m = in ? (int)s_mt[t0 + k] : 0;
+                ra = fma(c, sf[m], ra);
+                rb = fma(c, sf[P.nq + m], rb);
+                if (in) F[t0 + k + 1] = make_float2((float)(ba + ra), (float)(bb + rb));
+            }
         }
-        double2 run = block_exclusive_scan(la, lb, s_tot);
-#pragma unroll
-        for (int k = 0; k < TPM; ++k) {
-            run.x = fma(ca[k], (double)sf[mm[k]], run.x);
-            run.y = fma(ca[k], (double)sf[P.nq + mm[k]], run.y);
-            if (t0 + k < t1) s_F[t0 + k + 1] = make_float2((float)run.x, (float)run.y);
-        }
-        if (tid == 0) s_F[0] = make_float2(0.0f, 0.0f);
-        __syncthreads();
-        uint4 cr[NP];
-#pragma unroll
-        for (int i = 0; i < NP; ++i) cr[i] = nr[i];
-        load_rec(g + 1);
+        if (tid == 0) F[0] = make_float2(0.0f, 0.0f);
+    };
+    // One group per barrier pair: group g's class reads and the first scan
+    // part of group g + 1 share an interval, the second part and the f values
+    // of group g + 2 the next one.  F tables and f values are double-buffered
+    // by group parity; each buffer is rewritten two barriers after its last read.
+    auto group = [&](int g, const uint4 (&cr)[NP], uint4 (&nr)[NP], float &fv) {
+        load_rec(g + 1, nr);
+        const float2 *F = s_F(g);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
             // class of column a (record x, y) and, with LR, of column ndx-1-a (z, w)
             const float A1 = __uint_as_float(cr[i].x);
             const uint32_t w1 = cr[i].y;
-            const float2 F1 = s_F[(w1 >> 4) & 0x3FFFu];
+            const float2 F1 = F[(w1 >> 4) & 0x3FFFu];
             const float a1 = A1 * F1.x;
             o[i][0] = fmaf(a1, (float)(w1 & 1u), o[i][0]);           // (a, u) <- voxel j
             o[i][1] = fmaf(a1, (float)((w1 >> 1) & 1u), o[i][1]);    // (a, d) <- voxel j
@@ -519,13 +523,38 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
                 o[i][3] = fmaf(b1, (float)((w1 >> 3) & 1u), o[i][3]);    // (-a, d) <- voxel j2
                 const float A2 = __uint_as_float(cr[i].z);
                 const uint32_t w2 = cr[i].w;
-                const float2 F2 = s_F[(w2 >> 4) & 0x3FFFu];
+                const float2 F2 = F[(w2 >> 4) & 0x3FFFu];
                 const float a2 = A2 * F2.x, b2 = A2 * F2.y;
                 o[i][2] = fmaf(a2, (float)(w2 & 1u), o[i][2]);           // (-a, u) <- voxel j
                 o[i][3] = fmaf(a2, (float)((w2 >> 1) & 1u), o[i][3]);    // (-a, d) <- voxel j
                 o[i][0] = fmaf(b2, (float)((w2 >> 2) & 1u), o[i][0]);    // (a, u) <- voxel j2
                 o[i][1] = fmaf(b2, (float)((w2 >> 3) & 1u), o[i][1]);    // (a, d) <- voxel j2
             }
+        }
+        const bool more = g + 1 < g1;
+        if (more) scan1(g + 1);
+        __syncthreads();
+        if (more) scan2(g + 1);
+        if (tid < 2 * P.nq) s_f[(g & 1) * 2 * P.nq + tid] = (double)fv;   // group g + 2
+        fv = load_f(g + 3);
+        __syncthreads();
+    };
+    if (g0 < g1) {
+        if (tid < 2 * P.nq) {
+            s_f[(g0 & 1) * 2 * P.nq + tid] = (double)load_f(g0);
+            s_f[((g0 + 1) & 1) * 2 * P.nq + tid] = (double)load_f(g0 + 1);
+        }
+        float fv = load_f(g0 + 2);
+        uint4 ra[NP], rb[NP];
+        load_rec(g0, ra);
+        __syncthreads();
+        scan1(g0);
+        __syncthreads();
+        scan2(g0);
+        __syncthreads();
+        for (int g = g0; g < g1; g += 2) {
+            group(g, ra, rb, fv);
+            if (g + 1 < g1) group(g + 1, rb, ra, fv);
         }
     }
     // partial image of this block: every pixel is written once
@@ -835,7 +864,7 @@ bool csx_iv_feasible(const KParams &P, int *lds_f, int *lds_a)
     // (so the adjoint's 3 ncell + 1 cell-table entries, ncell = slots, index
     // in 15 bits), one f value per forward thread
     if (nt >= 16384 || slots > IVA_SC * IVA_THREADS || items > 8L * IV_THREADS || 2 * P.nq > IV_THREADS) return false;
-    const long lf = ((nt * 10 + 15) & ~15L) + (nt + 1) * 8 + 4L * P.nq * 4 + 16 + IV_WAVES * 16;
+    const long lf = ((nt * 10 + 15) & ~15L) + 2 * (((nt + 1) * 8 + 15) & ~15L) + 4L * P.nq * 8 + IV_WAVES * 16;
     const long la = iva_lds(P, 0);
     if (lf > CSX_LDS_MAX || la > CSX_LDS_MAX) return false;
     if (lds_f) *lds_f = (int)lf;
@@ -1006,13 +1035,14 @@ csx_status csx_iv_forward(const csx_geometry *h, const float *f, float *part, si
     const dim3 grid(v->nblk_f), block(IV_THREADS);
 #define CSX_IVF(LR_, NP_, TPM_) \
     hipLaunchKernelGGL((k_iv_forward<LR_, NP_, TPM_>), grid, block, v->lds_f, s, h->P, a, f, part)
-#define CSX_IVF_T(LR_, NP_)           \
-    do {                              \
-        if (tpm8) CSX_IVF(LR_, NP_, 8); \
-        else CSX_IVF(LR_, NP_, 16);   \
+#define CSX_IVF_T(LR_, NP_)               \
+    do {                                  \
+        if (tper <= 5) CSX_IVF(LR_, NP_, 5);      \
+        else if (tper <= 8) CSX_IVF(LR_, NP_, 8); \
+        else CSX_IVF(LR_, NP_, 16);       \
     } while (0)
     // thresholds per thread in the F scan
-    const bool tpm8 = (v->nt + IV_THREADS - 1) / IV_THREADS <= 8;
+    const int tper = (v->nt + IV_THREADS - 1) / IV_THREADS;
     if (h->P.lr) {
         if (v->np == 1) CSX_IVF_T(1, 1);
         else if (v->np == 2) CSX_IVF_T(1, 2);
