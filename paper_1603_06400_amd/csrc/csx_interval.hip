@@ -311,7 +311,7 @@ __device__ __forceinline__ int dpp_i32(int v)
 
 constexpr int DPP_SHR1 = 0x111, DPP_SHR2 = 0x112, DPP_SHR4 = 0x114, DPP_SHR8 = 0x118;
 constexpr int DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
-constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_ROW_MIRROR = 0x140;
 
 // a lane move over all rows whose lanes without a source read zero
 template <int CTRL>
@@ -359,12 +359,15 @@ __device__ __forceinline__ int wave_scan(int x)
     return x;
 }
 
-// sum over each group of 8 lanes (every lane of the group gets it)
-__device__ __forceinline__ double oct_sum(double x)
+// sum over each group of 8 (W = 8) or 16 (W = 16) lanes, every lane of the
+// group getting it
+template <int W>
+__device__ __forceinline__ double group_sum(double x)
 {
     x += dppz_f64<DPP_XOR1>(x);
     x += dppz_f64<DPP_XOR2>(x);
     x += dppz_f64<DPP_HALF_MIRROR>(x);
+    if (W == 16) x += dppz_f64<DPP_ROW_MIRROR>(x);
     return x;
 }
 
@@ -631,10 +634,12 @@ __global__ void __launch_bounds__(1024) k_iv_sum(const float *__restrict__ part,
 // prefixes, and a bin holding only a few small weights behind large ones
 // (the lowest q nodes see only the smallest angles) needs that precision to
 // stay accurate relative to itself.
-// PF = 1: nq <= IVA_THREADS / IVA_SUB and ne <= 8 IVA_SUB: thread (m, sub)
-// owns bins c = 1 + 8 sub .. 8 + 8 sub of node m and holds the 9 table
-// indices of their edges in registers (one 16-byte and one 2-byte load from
-// rows of es = 72 entries).
+// PF = 1 (nq <= 128, ne <= 64): thread (m, sub), sub < 8, owns bins
+// c = 1 + 8 sub .. 8 + 8 sub of node m; PF = 2 (nq <= 64, ne <= 64): 16
+// threads per node, 4 bins each, so that every wave takes part.  A thread
+// holds the table indices of its bins' edges in registers (rows of es = 72
+// entries, loaded one group ahead).  PF = 0: 8 threads per node walk the
+// bins with stride 8, indices read when used.
 template <int LR, int PF>
 __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V, const DevTables T,
                                                             const float *__restrict__ rho, float *__restrict__ b)
@@ -679,15 +684,26 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
         m = V.emask[(size_t)gg * V.nch + ch];
     };
     // PF: this thread's node and bins, and the table indices of their edges
-    const int pm = tid / IVA_SUB, ps = tid % IVA_SUB;
+    constexpr int PSUB = PF == 2 ? 16 : IVA_SUB, PCPT = PF == 2 ? 4 : IVA_SC;
+    const int pm = tid / PSUB, ps = tid % PSUB;
     const bool pact = PF && pm < P.nq;
-    uint4 ev = make_uint4(0u, 0u, 0u, 0u);
-    uint32_t e8 = 0u;
+    uint32_t ew[PCPT / 2] = {};
+    uint32_t elast = 0u;
     auto load_emap = [&](int g) {
         if (PF && pact) {
-            const uint16_t *row = V.emap + ((size_t)min(g, g1 - 1) * P.nq + pm) * V.es + ps * IVA_SC;
-            ev = *(const uint4 *)row;
-            e8 = row[IVA_SC];
+            const uint16_t *row = V.emap + ((size_t)min(g, g1 - 1) * P.nq + pm) * V.es + ps * PCPT;
+            if constexpr (PCPT == 8) {
+                const uint4 v = *(const uint4 *)row;
+                ew[0] = v.x;
+                ew[1] = v.y;
+                ew[2] = v.z;
+                ew[3] = v.w;
+            } else {
+                const uint2 v = *(const uint2 *)row;
+                ew[0] = v.x;
+                ew[1] = v.y;
+            }
+            elast = row[PCPT];
         }
     };
     auto group = [&](int g, const uint4 (&cr)[IVA_SC / 2], uint32_t cm, uint4 (&nr)[IVA_SC / 2], uint32_t &nm) {
@@ -740,20 +756,19 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
         if constexpr (PF) {
             double sa = 0.0, sb = 0.0;
             if (pact) {
-                const uint32_t ew[4] = {ev.x, ev.y, ev.z, ev.w};
-                double2 E[IVA_SC + 1];
+                double2 E[PCPT + 1];
 #pragma unroll
-                for (int k = 0; k < IVA_SC; ++k) E[k] = s_E[(ew[k >> 1] >> (16 * (k & 1))) & 0xFFFFu];
-                E[IVA_SC] = s_E[e8];
+                for (int k = 0; k < PCPT; ++k) E[k] = s_E[(ew[k >> 1] >> (16 * (k & 1))) & 0xFFFFu];
+                E[PCPT] = s_E[elast];
 #pragma unroll
-                for (int k = 0; k < IVA_SC; ++k) {
-                    const double ph = s_phi[1 + ps * IVA_SC + k];
+                for (int k = 0; k < PCPT; ++k) {
+                    const double ph = s_phi[1 + ps * PCPT + k];
                     sa = fma(ph, E[k + 1].x - E[k].x, sa);
                     sb = fma(ph, E[k + 1].y - E[k].y, sb);
                 }
             }
-            sa = oct_sum(sa);
-            sb = oct_sum(sb);
+            sa = group_sum<PSUB>(sa);
+            sb = group_sum<PSUB>(sb);
             if (pact && ps == 0) {
                 const double qm = V.qd[pm];
                 b[(size_t)j * P.nq + pm] = (float)(qm * sa);
@@ -773,8 +788,8 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
                         sb = fma(ph, hi.y - lo.y, sb);
                     }
                 }
-                sa = oct_sum(sa);
-                sb = oct_sum(sb);
+                sa = group_sum<IVA_SUB>(sa);
+                sb = group_sum<IVA_SUB>(sb);
                 if (m < P.nq && sub == 0) {
                     const double qm = V.qd[m];
                     b[(size_t)j * P.nq + m] = (float)(qm * sa);
@@ -835,10 +850,13 @@ void iv_release(IvState *v)
     delete v;
 }
 
-// The adjoint's PF form: every node's bins fit 8 threads of 8 bins.
-bool iva_pf(const KParams &P)
+// The adjoint's gather form: 2 (16 threads of 4 bins per node), 1 (8
+// threads of 8 bins) or 0 (8 threads, bins with stride 8).
+int iva_pf(const KParams &P)
 {
-    return P.nq <= IVA_THREADS / IVA_SUB && P.ne <= IVA_SC * IVA_SUB;
+    if (P.ne > IVA_SC * IVA_SUB) return 0;
+    if (P.nq <= IVA_THREADS / 16) return 2;
+    return P.nq <= IVA_THREADS / IVA_SUB ? 1 : 0;
 }
 
 // LDS of the adjoint with a prefix table of cap in-between entries: the
@@ -952,7 +970,7 @@ csx_status csx_iv_build(csx_geometry *h)
     v->n_slots = P.lr ? 2 * v->n_items : v->n_items;
     v->rstride = (v->n_slots + IVA_SC - 1) / IVA_SC * IVA_SC;
     v->nch = v->rstride / IVA_SC;
-    v->es = iva_pf(P) ? IVA_SC * IVA_SUB + IVA_SC : (ne + 1 + 7) / 8 * 8;
+    v->es = iva_pf(P) ? IVA_SC * IVA_SUB + IVA_SC : (ne + 1 + 7) / 8 * 8;   // PF rows: 72, 16-byte aligned
     v->ncell = P.ndx * (P.ndy / 2);
     v->np = 1;
     while (v->np * IV_THREADS < v->n_items) v->np *= 2;
@@ -1067,14 +1085,16 @@ csx_status csx_iv_adjoint(const csx_geometry *h, const float *rho, float *b, hip
     const IvState *v = (const IvState *)h->iv;
     const IvArgs a = iv_args(h, v);
     const dim3 grid(v->nblk_a), block(IVA_THREADS);
-    const bool pf = iva_pf(h->P);
+    const int pf = iva_pf(h->P);
 #define CSX_IVA(LR_, PF_) \
     hipLaunchKernelGGL((k_iv_adjoint<LR_, PF_>), grid, block, v->lds_a, s, h->P, a, h->t, rho, b)
     if (h->P.lr) {
-        if (pf) CSX_IVA(1, 1);
+        if (pf == 2) CSX_IVA(1, 2);
+        else if (pf == 1) CSX_IVA(1, 1);
         else CSX_IVA(1, 0);
     } else {
-        if (pf) CSX_IVA(0, 1);
+        if (pf == 2) CSX_IVA(0, 2);
+        else if (pf == 1) CSX_IVA(0, 1);
         else CSX_IVA(0, 0);
     }
 #undef CSX_IVA

@@ -53,6 +53,33 @@ def test_interval_operators_match_oracle_and_direct(oracle_mod, kind, case):
     assert ef <= 1e-6 and eb <= 1e-6
 
 
+# the adjoint's bin gather takes three forms: 16 threads of 4 bins per node
+# (nq <= 64, ne <= 64), 8 threads of 8 bins (nq <= 128) and a strided walk
+# (more nodes, or more than 64 spectrum bins); the cases above reach the
+# first two, these the third
+GATHER = [
+    ("ragged", (21, 10, 7, 12, 10, 24, 402.57), 96),      # ne > 64
+    ("symmetric", (22, 8, 5, 10, 6, 136, 404.77), 40),    # nq > 128
+]
+
+
+@pytest.mark.parametrize("kind,case,ne", GATHER, ids=["ne96", "nq136"])
+def test_interval_strided_gather(oracle_mod, kind, case, ne):
+    print(f"[interval gather {kind} {case} ne={ne}]", flush=True)
+    kw = {"ne": ne} if kind == "ragged" else {"ne": ne, "x": (-40.0, 40.0)}
+    g = ragged_geometry(*case, **kw)
+    o = oracle_mod.Oracle(g)
+    geo = csx.Geometry(g)
+    assert geo.interval_operators()["on"]
+    f = inputs.random_image(g, 970 + case[0])
+    y = inputs.random_detector(g, 980 + case[0])
+    bi = host(geo.backproject(dev(y)))
+    assert_parity(host(geo.forward(dev(f))), o.forward(f), what="forward (intervals)")
+    assert_parity(bi, o.adjoint(y), what="adjoint (intervals)")
+    geo.set_interval_operators(False)
+    assert rel_l2(bi, host(geo.backproject(dev(y)))) <= 1e-6
+
+
 def test_interval_operators_are_deterministic():
     w, g, ftrue, y = workload_data("slice32")
     geo = csx.Geometry(g)
