@@ -142,7 +142,7 @@ static void free_all(csx_geometry *h)
     csx_energy_free(h);
     void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qblk, h->t.qv, h->t.phi32,
                     h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
-                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags,
+                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags, h->ucount,
                     h->fplain, h->warm, h->a1, h->t.ra, h->t.rf, h->t.ram, h->t.rfm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -379,10 +379,14 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     h->nbR = (int)((nimg + 255) / 256);
     CSX_TRY(dev_alloc(&h->partL, h->nbL, B));
     CSX_TRY(dev_alloc(&h->partR, h->nbR, B));
+    h->nbRu = h->nbR;
     CSX_TRY(dev_alloc(&h->partF, h->nbL, B));
     CSX_TRY(dev_alloc(&h->partS, 2 * CSX_SUM_BLOCKS, B));
     CSX_TRY(dev_alloc(&h->scal, 8, B));
     CSX_TRY(dev_alloc(&h->flags, 1, B));
+    CSX_TRY(dev_alloc(&h->ucount, 1, B));
+    CSX_TRY(hipMemset(h->ucount, 0, sizeof(unsigned int)) == hipSuccess ? CSX_OK
+                                                                         : csx_fail(CSX_EHIP, "clearing a counter"));
     CSX_TRY(csx_launch_fill(h->ones, P.npix, 1.0f, nullptr));
     CSX_TRY(csx_launch_clear_flags(h, nullptr));
     // the factor store by default when it is small beside the device's free
@@ -593,8 +597,9 @@ static csx_status step_impl(csx_geometry *h, const float *y, const float *r, flo
     ST_TRY(solver_forward(h, f, h->gws, s));                    // z = A f^t (+ r below)
     ST_TRY(csx_launch_ratio(h, y, r, true, s));                 // rho = y / z, data-fit partials
     ST_TRY(solver_adjoint(h, h->rho, h->b2, s));                // b2 = A^T rho
-    ST_TRY(csx_launch_update(h, f, beta, true, s));             // f^{t+1} into ftmp, R(f^t) partials
-    if (J) ST_TRY(csx_launch_objective(h, beta, J, nullptr, s)); // J(f^t)
+    // f^{t+1} into ftmp, R(f^t) partials and J(f^t)
+    if (J) ST_TRY(csx_launch_update_obj(h, f, beta, true, J, nullptr, s));
+    else ST_TRY(csx_launch_update(h, f, beta, true, s));
     return csx_launch_copy(h->ftmp, f, h->P.nvox * h->P.nq, s);
 }
 
@@ -628,8 +633,7 @@ extern "C" csx_status csx_recon(csx_geometry *h, const float *y, const float *r,
     // J at the final iterate
     ST_TRY(solver_forward(h, f, h->gws, s));
     ST_TRY(csx_launch_ratio(h, y, r, false, s));
-    ST_TRY(csx_launch_update(h, f, beta, false, s));
-    ST_TRY(csx_launch_objective(h, beta, h->jhist + n_iter, nullptr, s));
+    ST_TRY(csx_launch_update_obj(h, f, beta, false, h->jhist + n_iter, nullptr, s));
     int flags = 0;
     HIP_TRY(hipMemcpyAsync(&flags, h->flags, sizeof(int), hipMemcpyDeviceToHost, s));
     if (J_hist)

@@ -92,43 +92,129 @@ __device__ __forceinline__ void potential(double d, double delta, double &R, dou
     }
 }
 
+// The objective's inputs, for an update launch that also forms J (the last
+// block to finish adds every block's partials in a fixed order).
+struct ObjArgs {
+    const double *partL;        // [nL] data-fit partials of K3
+    const int *partF;           // [nL] flags of K3
+    int nL;
+    int *flags;                 // combined flags
+    double *J;                  // J[iter ? *iter : 0]
+    const int *iter;
+    unsigned int *count;        // blocks done; zero between launches
+};
+
+// J = sum partL + beta * sum partR in a fixed order by one block, flags
+// combined (J = +inf when some y_i > 0 met a zero mean).
+__device__ void objective_block(const double *__restrict__ partL, int nL, const double *__restrict__ partR, int nR,
+                                const int *__restrict__ partF, double beta, int *__restrict__ flags,
+                                double *__restrict__ J, const int *__restrict__ iter, double *s_red, int *s_flag)
+{
+    if (threadIdx.x == 0) *s_flag = 0;
+    __syncthreads();
+    double a = 0.0, b = 0.0;
+    int fl = 0;
+    for (int k = threadIdx.x; k < nL; k += blockDim.x) {
+        a += partL[k];
+        fl |= partF[k];
+    }
+    for (int k = threadIdx.x; k < nR; k += blockDim.x) b += partR[k];
+    if (fl) atomicOr(s_flag, fl);
+    const double ta = block_sum_d(a, s_red);
+    __syncthreads();
+    const double tb = block_sum_d(b, s_red);
+    if (threadIdx.x == 0) {
+        *flags = *s_flag;
+        J[iter ? *iter : 0] = (*s_flag & 1) ? INFINITY : ta + beta * tb;
+    }
+}
+
+// VEC consecutive q nodes of one voxel per thread (VEC divides nq; 16-byte
+// loads and stores when VEC = 4).  OBJ = 1: the block that finishes last
+// (device-scope fence, then a counter) also forms J from every block's
+// partials; the counter returns to zero for the next launch, so launches of
+// one handle must be ordered (one stream).
+template <int VEC, int OBJ>
 __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const float *__restrict__ fh,
                                                 const float *__restrict__ b1,
                                                 const float *__restrict__ b2, double beta,
                                                 float *__restrict__ fout,
-                                                double *__restrict__ partR, int do_update, double delta)
+                                                double *__restrict__ partR, int do_update, double delta, ObjArgs oa)
 {
     __shared__ double s_red[4];
+    __shared__ int s_flag;
     const int n = nx * nz * nq;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
     double R = 0.0;
-    if (e < n) {
-        const int m = e % nq;
-        const int j = e / nq;
+    if (e0 < n) {
+        const int j = e0 / nq;
         const int ix = j % nx, iz = j / nx;
-        const double fj = fh[e];
-        double s = 0.0, w = 0.0;
-        if (ix > 0) potential(fj - fh[e - nq], delta, R, s, w);
-        if (ix < nx - 1) potential(fj - fh[e + nq], delta, R, s, w);
-        if (iz > 0) potential(fj - fh[e - (size_t)nx * nq], delta, R, s, w);
-        if (iz < nz - 1) potential(fj - fh[e + (size_t)nx * nq], delta, R, s, w);
+        const size_t row = (size_t)nx * nq;
+        float c[VEC], l[VEC], r[VEC], u[VEC], d[VEC];
+        auto ld = [&](const float *p, float (&v)[VEC]) {
+            if constexpr (VEC == 4) {
+                const float4 t = *(const float4 *)p;
+                v[0] = t.x;
+                v[1] = t.y;
+                v[2] = t.z;
+                v[3] = t.w;
+            } else {
+                v[0] = *p;
+            }
+        };
+        ld(fh + e0, c);
+        if (ix > 0) ld(fh + e0 - nq, l);
+        if (ix < nx - 1) ld(fh + e0 + nq, r);
+        if (iz > 0) ld(fh + e0 - row, u);
+        if (iz < nz - 1) ld(fh + e0 + row, d);
+        float vb1[VEC], vb2[VEC], out[VEC];
         if (do_update) {
-            // b3 + b4 = 4 sum omega, b5 + b6 = 2 sum psi' (symmetric neighbourhood, w_jk = 1)
-            const double b34 = 4.0 * w;
-            const double chi1 = beta * b34;
-            const double chi2 = (double)b1[e] + beta * (-fj * b34 + 2.0 * s);
-            const double chi3 = fj * (double)b2[e];
-            double out;
-            const double disc = sqrt(chi2 * chi2 + 4.0 * chi1 * chi3);
-            if (chi2 > 0.0) out = 2.0 * chi3 / (chi2 + disc);
-            else if (chi1 > 0.0) out = (-chi2 + disc) / (2.0 * chi1);
-            else out = fj;
-            fout[e] = (float)out;
+            ld(b1 + e0, vb1);
+            ld(b2 + e0, vb2);
         }
-        (void)m;
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+            const double fj = c[k];
+            double s = 0.0, w = 0.0;
+            if (ix > 0) potential(fj - l[k], delta, R, s, w);
+            if (ix < nx - 1) potential(fj - r[k], delta, R, s, w);
+            if (iz > 0) potential(fj - u[k], delta, R, s, w);
+            if (iz < nz - 1) potential(fj - d[k], delta, R, s, w);
+            if (do_update) {
+                // b3 + b4 = 4 sum omega, b5 + b6 = 2 sum psi' (symmetric neighbourhood, w_jk = 1)
+                const double b34 = 4.0 * w;
+                const double chi1 = beta * b34;
+                const double chi2 = (double)vb1[k] + beta * (-fj * b34 + 2.0 * s);
+                const double chi3 = fj * (double)vb2[k];
+                double o;
+                const double disc = sqrt(chi2 * chi2 + 4.0 * chi1 * chi3);
+                if (chi2 > 0.0) o = 2.0 * chi3 / (chi2 + disc);
+                else if (chi1 > 0.0) o = (-chi2 + disc) / (2.0 * chi1);
+                else o = fj;
+                out[k] = (float)o;
+            }
+        }
+        if (do_update) {
+            if constexpr (VEC == 4) *(float4 *)(fout + e0) = make_float4(out[0], out[1], out[2], out[3]);
+            else fout[e0] = out[0];
+        }
     }
     const double t = block_sum_d(R, s_red);
     if (threadIdx.x == 0) partR[blockIdx.x] = t;
+    if constexpr (OBJ) {
+        __shared__ int s_last;
+        if (threadIdx.x == 0) {
+            __threadfence();
+            s_last = atomicAdd(oa.count, 1u) == gridDim.x - 1;
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            objective_block(oa.partL, oa.nL, partR, gridDim.x, oa.partF, beta, oa.flags, oa.J, oa.iter, s_red,
+                            &s_flag);
+            if (threadIdx.x == 0) *oa.count = 0u;
+        }
+    }
 }
 
 // K5: J = sum partL + beta * sum partR in a fixed order, one block; the
@@ -142,23 +228,7 @@ __global__ void __launch_bounds__(256) k_objective(const double *__restrict__ pa
 {
     __shared__ double s_red[4];
     __shared__ int s_flag;
-    if (threadIdx.x == 0) s_flag = 0;
-    __syncthreads();
-    double a = 0.0, b = 0.0;
-    int fl = 0;
-    for (int k = threadIdx.x; k < nL; k += blockDim.x) {
-        a += partL[k];
-        fl |= partF[k];
-    }
-    for (int k = threadIdx.x; k < nR; k += blockDim.x) b += partR[k];
-    if (fl) atomicOr(&s_flag, fl);
-    const double ta = block_sum_d(a, s_red);
-    __syncthreads();
-    const double tb = block_sum_d(b, s_red);
-    if (threadIdx.x == 0) {
-        *flags = s_flag;
-        J[iter ? *iter : 0] = (s_flag & 1) ? INFINITY : ta + beta * tb;
-    }
+    objective_block(partL, nL, partR, nR, partF, beta, flags, J, iter, s_red, &s_flag);
 }
 
 __global__ void k_iter_incr(int *iter) { *iter += 1; }
@@ -220,6 +290,12 @@ __global__ void k_copy(const float *__restrict__ s, float *__restrict__ d, int n
     if (e < n) d[e] = s[e];
 }
 
+__global__ void k_copy4(const float4 *__restrict__ s, float4 *__restrict__ d, int n4)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n4) d[e] = s[e];
+}
+
 __global__ void k_clear_int(int *p) { *p = 0; }
 
 }  // namespace
@@ -233,30 +309,62 @@ csx_status csx_launch_ratio(csx_geometry *h, const float *y, const float *r, boo
     return CSX_OK;
 }
 
+// The update's vector width: 4 q nodes per thread when nq is a multiple of 4
+// and every array is 16-byte aligned, else 1.
+static int update_vec(const csx_geometry *h, const void *a, const void *b, const void *c, const void *d)
+{
+    const uintptr_t al = (uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)d;
+    return (h->P.nq % 4 == 0 && (al & 15) == 0) ? 4 : 1;
+}
+
+static csx_status launch_update(csx_geometry *h, const float *f, const float *b1, const float *b2, double beta,
+                                float *fout, bool do_update, const ObjArgs *oa, hipStream_t s)
+{
+    const KParams &P = h->P;
+    const long n = (long)P.nvox * P.nq;
+    const int vec = update_vec(h, f, b1, b2, fout);
+    const int nb = (int)((n + 256L * vec - 1) / (256L * vec));
+    h->nbRu = nb;
+    ObjArgs a{};
+    if (oa) a = *oa;
+#define CSX_UPD(V_, O_)                                                                                           \
+    hipLaunchKernelGGL((k_update<V_, O_>), dim3(nb), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout, \
+                       h->partR, do_update ? 1 : 0, h->psi_delta, a)
+    if (vec == 4) {
+        if (oa) CSX_UPD(4, 1);
+        else CSX_UPD(4, 0);
+    } else {
+        if (oa) CSX_UPD(1, 1);
+        else CSX_UPD(1, 0);
+    }
+#undef CSX_UPD
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
 csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool do_update,
                              hipStream_t s)
 {
-    const KParams &P = h->P;
-    hipLaunchKernelGGL(k_update, dim3(h->nbR), dim3(256), 0, s, P.nx, P.nz, P.nq, f, h->b1, h->b2,
-                       beta, h->ftmp, h->partR, do_update ? 1 : 0, h->psi_delta);
-    HIP_TRY(hipGetLastError());
-    return CSX_OK;
+    return launch_update(h, f, h->b1, h->b2, beta, h->ftmp, do_update, nullptr, s);
+}
+
+csx_status csx_launch_update_obj(csx_geometry *h, const float *f, double beta, bool do_update, double *J,
+                                 const int *iter, hipStream_t s)
+{
+    const ObjArgs oa{h->partL, h->partF, h->nbL, h->flags, J, iter, h->ucount};
+    return launch_update(h, f, h->b1, h->b2, beta, h->ftmp, do_update, &oa, s);
 }
 
 csx_status csx_launch_update_ex(csx_geometry *h, const float *f, const float *b1, const float *b2,
                                 double beta, float *fout, hipStream_t s)
 {
-    const KParams &P = h->P;
-    hipLaunchKernelGGL(k_update, dim3(h->nbR), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout,
-                       h->partR, 1, h->psi_delta);
-    HIP_TRY(hipGetLastError());
-    return CSX_OK;
+    return launch_update(h, f, b1, b2, beta, fout, true, nullptr, s);
 }
 
 csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, const int *iter,
                                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, s, h->partL, h->nbL, h->partR, h->nbR,
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, s, h->partL, h->nbL, h->partR, h->nbRu,
                        h->partF, beta, h->flags, J, iter);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
@@ -292,7 +400,11 @@ csx_status csx_launch_uniform_start(csx_geometry *h, const float *y, float *f, h
 
 csx_status csx_launch_copy(const float *src, float *dst, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_copy, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n);
+    if (n % 4 == 0 && (((uintptr_t)src | (uintptr_t)dst) & 15) == 0)
+        hipLaunchKernelGGL(k_copy4, dim3((n / 4 + 255) / 256), dim3(256), 0, s, (const float4 *)src, (float4 *)dst,
+                           n / 4);
+    else
+        hipLaunchKernelGGL(k_copy, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
@@ -326,7 +438,7 @@ csx_status csx_launch_ratio_n(int n, const float *g, const float *y, const float
 csx_status csx_launch_objective_n(csx_geometry *h, const double *partL, int nL, const int *partF, double beta,
                                   double *J, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, s, partL, nL, h->partR, h->nbR, partF, beta, h->flags,
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, s, partL, nL, h->partR, h->nbRu, partF, beta, h->flags,
                        J, nullptr);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
