@@ -142,7 +142,7 @@ static void free_all(csx_geometry *h)
     csx_energy_free(h);
     void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qblk, h->t.qv, h->t.phi32,
                     h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
-                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags, h->ucount,
+                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags,
                     h->fplain, h->warm, h->a1, h->t.ra, h->t.rf, h->t.ram, h->t.rfm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -384,9 +384,6 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     CSX_TRY(dev_alloc(&h->partS, 2 * CSX_SUM_BLOCKS, B));
     CSX_TRY(dev_alloc(&h->scal, 8, B));
     CSX_TRY(dev_alloc(&h->flags, 1, B));
-    CSX_TRY(dev_alloc(&h->ucount, 1, B));
-    CSX_TRY(hipMemset(h->ucount, 0, sizeof(unsigned int)) == hipSuccess ? CSX_OK
-                                                                         : csx_fail(CSX_EHIP, "clearing a counter"));
     CSX_TRY(csx_launch_fill(h->ones, P.npix, 1.0f, nullptr));
     CSX_TRY(csx_launch_clear_flags(h, nullptr));
     // the factor store by default when it is small beside the device's free
@@ -597,9 +594,8 @@ static csx_status step_impl(csx_geometry *h, const float *y, const float *r, flo
     ST_TRY(solver_forward(h, f, h->gws, s));                    // z = A f^t (+ r below)
     ST_TRY(csx_launch_ratio(h, y, r, true, s));                 // rho = y / z, data-fit partials
     ST_TRY(solver_adjoint(h, h->rho, h->b2, s));                // b2 = A^T rho
-    // f^{t+1} into ftmp, R(f^t) partials and J(f^t)
-    if (J) ST_TRY(csx_launch_update_obj(h, f, beta, true, J, nullptr, s));
-    else ST_TRY(csx_launch_update(h, f, beta, true, s));
+    ST_TRY(csx_launch_update(h, f, beta, true, s));             // f^{t+1} into ftmp, R(f^t) partials
+    if (J) return csx_launch_copy_objective(h, f, beta, J, nullptr, s);   // f^{t+1} into f, J(f^t)
     return csx_launch_copy(h->ftmp, f, h->P.nvox * h->P.nq, s);
 }
 
@@ -633,7 +629,8 @@ extern "C" csx_status csx_recon(csx_geometry *h, const float *y, const float *r,
     // J at the final iterate
     ST_TRY(solver_forward(h, f, h->gws, s));
     ST_TRY(csx_launch_ratio(h, y, r, false, s));
-    ST_TRY(csx_launch_update_obj(h, f, beta, false, h->jhist + n_iter, nullptr, s));
+    ST_TRY(csx_launch_update(h, f, beta, false, s));
+    ST_TRY(csx_launch_objective(h, beta, h->jhist + n_iter, nullptr, s));
     int flags = 0;
     HIP_TRY(hipMemcpyAsync(&flags, h->flags, sizeof(int), hipMemcpyDeviceToHost, s));
     if (J_hist)

@@ -194,8 +194,8 @@ static csx_status issue_iteration(csx_batch *b, const std::vector<int> &active, 
         if (b->h[k]->iv) BT_TRY(csx_iv_adjoint(b->h[k], b->h[k]->rho, b->h[k]->b2, s));
     for (int k : active) {
         csx_geometry *h = b->h[k];
-        BT_TRY(csx_launch_update_obj(h, f[k], beta, true, b->J_dev + k * jstride, b->iter_dev, s));
-        BT_TRY(csx_launch_copy(h->ftmp, f[k], h->P.nvox * h->P.nq, s));
+        BT_TRY(csx_launch_update(h, f[k], beta, true, s));
+        BT_TRY(csx_launch_copy_objective(h, f[k], beta, b->J_dev + k * jstride, b->iter_dev, s));
     }
     return csx_launch_iter_incr(b->iter_dev, s);
 }
@@ -208,7 +208,8 @@ static csx_status final_objective(csx_batch *b, int k, const float *y, const flo
     csx_geometry *h = b->h[k];
     BT_TRY(csx_launch_forward(h, f, h->gws, s));
     BT_TRY(csx_launch_ratio(h, y, r, false, s));
-    return csx_launch_update_obj(h, f, beta, false, b->J_dev + k * jstride, b->iter_dev, s);
+    BT_TRY(csx_launch_update(h, f, beta, false, s));
+    return csx_launch_objective(h, beta, b->J_dev + k * jstride, b->iter_dev, s);
 }
 
 // Replaces the groups by those of the active scans and uploads their job

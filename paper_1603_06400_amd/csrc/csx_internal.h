@@ -142,7 +142,6 @@ struct csx_geometry {
     double *jhist = nullptr;   // device J history (grown on demand)
     int jhist_cap = 0;
     int *partF = nullptr;      // per-block flags of the data term
-    unsigned int *ucount = nullptr;   // blocks done of an update launch that forms J (zero between launches)
     int *flags = nullptr;      // flags of the last objective: bit 0: y_i > 0 with zero
                                // mean; bit 1: y_i < 0 or NaN
     double psi_delta = 0.0;    // penalty potential: 0 quadratic, > 0 Huber scale
@@ -217,9 +216,10 @@ csx_status csx_launch_ratio(csx_geometry *h, const float *y, const float *r, boo
                             hipStream_t s);
 csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool do_update,
                              hipStream_t s);
-// The update followed, in its last block, by the objective J(f) (J[iter ? *iter : 0]).
-csx_status csx_launch_update_obj(csx_geometry *h, const float *f, double beta, bool do_update, double *J,
-                                 const int *iter, hipStream_t s);
+// ftmp copied back into f, and in one extra block the objective J (J[iter ? *iter : 0])
+// from the partials of the preceding ratio and update launches.
+csx_status csx_launch_copy_objective(csx_geometry *h, float *f, double beta, double *J, const int *iter,
+                                     hipStream_t s);
 csx_status csx_launch_update_ex(csx_geometry *h, const float *f, const float *b1, const float *b2,
                                 double beta, float *fout, hipStream_t s);
 csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, const int *iter,

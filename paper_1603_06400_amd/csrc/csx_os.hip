@@ -193,7 +193,8 @@ extern "C" csx_status csx_recon_os(csx_geometry *h, const float *y, const float 
         OS_TRY((h->op_sai & CSX_OP_FORWARD_SAI) ? csx_launch_forward_sai(h, fc, h->gws, s)
                                                  : csx_launch_forward(h, fc, h->gws, s));
         OS_TRY(csx_launch_ratio(h, y, r, false, s));
-        return csx_launch_update_obj(h, fc, beta, false, h->jhist + t, nullptr, s);
+        OS_TRY(csx_launch_update(h, fc, beta, false, s));
+        return csx_launch_objective(h, beta, h->jhist + t, nullptr, s);
     };
     OS_TRY(objective(f, 0));
     const double bp = beta / o->n_sub;

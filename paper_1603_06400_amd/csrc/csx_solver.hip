@@ -92,18 +92,6 @@ __device__ __forceinline__ void potential(double d, double delta, double &R, dou
     }
 }
 
-// The objective's inputs, for an update launch that also forms J (the last
-// block to finish adds every block's partials in a fixed order).
-struct ObjArgs {
-    const double *partL;        // [nL] data-fit partials of K3
-    const int *partF;           // [nL] flags of K3
-    int nL;
-    int *flags;                 // combined flags
-    double *J;                  // J[iter ? *iter : 0]
-    const int *iter;
-    unsigned int *count;        // blocks done; zero between launches
-};
-
 // J = sum partL + beta * sum partR in a fixed order by one block, flags
 // combined (J = +inf when some y_i > 0 met a zero mean).
 __device__ void objective_block(const double *__restrict__ partL, int nL, const double *__restrict__ partR, int nR,
@@ -130,19 +118,15 @@ __device__ void objective_block(const double *__restrict__ partL, int nL, const 
 }
 
 // VEC consecutive q nodes of one voxel per thread (VEC divides nq; 16-byte
-// loads and stores when VEC = 4).  OBJ = 1: the block that finishes last
-// (device-scope fence, then a counter) also forms J from every block's
-// partials; the counter returns to zero for the next launch, so launches of
-// one handle must be ordered (one stream).
-template <int VEC, int OBJ>
+// loads and stores when VEC = 4).
+template <int VEC>
 __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const float *__restrict__ fh,
                                                 const float *__restrict__ b1,
                                                 const float *__restrict__ b2, double beta,
                                                 float *__restrict__ fout,
-                                                double *__restrict__ partR, int do_update, double delta, ObjArgs oa)
+                                                double *__restrict__ partR, int do_update, double delta)
 {
     __shared__ double s_red[4];
-    __shared__ int s_flag;
     const int n = nx * nz * nq;
     const int e0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
     double R = 0.0;
@@ -201,20 +185,6 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
     }
     const double t = block_sum_d(R, s_red);
     if (threadIdx.x == 0) partR[blockIdx.x] = t;
-    if constexpr (OBJ) {
-        __shared__ int s_last;
-        if (threadIdx.x == 0) {
-            __threadfence();
-            s_last = atomicAdd(oa.count, 1u) == gridDim.x - 1;
-        }
-        __syncthreads();
-        if (s_last) {
-            __threadfence();
-            objective_block(oa.partL, oa.nL, partR, gridDim.x, oa.partF, beta, oa.flags, oa.J, oa.iter, s_red,
-                            &s_flag);
-            if (threadIdx.x == 0) *oa.count = 0u;
-        }
-    }
 }
 
 // K5: J = sum partL + beta * sum partR in a fixed order, one block; the
@@ -296,6 +266,26 @@ __global__ void k_copy4(const float4 *__restrict__ s, float4 *__restrict__ d, in
     if (e < n4) d[e] = s[e];
 }
 
+// The copy of the updated image back, with one extra block (the last) that
+// forms the objective from the partials of the ratio and update launches
+// before it (n % 4 == 0, 16-byte aligned arrays).
+__global__ void __launch_bounds__(256) k_copy4_objective(const float4 *__restrict__ s, float4 *__restrict__ d,
+                                                         int n4, const double *__restrict__ partL, int nL,
+                                                         const double *__restrict__ partR, int nR,
+                                                         const int *__restrict__ partF, double beta,
+                                                         int *__restrict__ flags, double *__restrict__ J,
+                                                         const int *__restrict__ iter)
+{
+    if (blockIdx.x == gridDim.x - 1) {
+        __shared__ double s_red[4];
+        __shared__ int s_flag;
+        objective_block(partL, nL, partR, nR, partF, beta, flags, J, iter, s_red, &s_flag);
+        return;
+    }
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n4) d[e] = s[e];
+}
+
 __global__ void k_clear_int(int *p) { *p = 0; }
 
 }  // namespace
@@ -318,26 +308,19 @@ static int update_vec(const csx_geometry *h, const void *a, const void *b, const
 }
 
 static csx_status launch_update(csx_geometry *h, const float *f, const float *b1, const float *b2, double beta,
-                                float *fout, bool do_update, const ObjArgs *oa, hipStream_t s)
+                                float *fout, bool do_update, hipStream_t s)
 {
     const KParams &P = h->P;
     const long n = (long)P.nvox * P.nq;
     const int vec = update_vec(h, f, b1, b2, fout);
     const int nb = (int)((n + 256L * vec - 1) / (256L * vec));
     h->nbRu = nb;
-    ObjArgs a{};
-    if (oa) a = *oa;
-#define CSX_UPD(V_, O_)                                                                                           \
-    hipLaunchKernelGGL((k_update<V_, O_>), dim3(nb), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout, \
-                       h->partR, do_update ? 1 : 0, h->psi_delta, a)
-    if (vec == 4) {
-        if (oa) CSX_UPD(4, 1);
-        else CSX_UPD(4, 0);
-    } else {
-        if (oa) CSX_UPD(1, 1);
-        else CSX_UPD(1, 0);
-    }
-#undef CSX_UPD
+    if (vec == 4)
+        hipLaunchKernelGGL(k_update<4>, dim3(nb), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout, h->partR,
+                           do_update ? 1 : 0, h->psi_delta);
+    else
+        hipLaunchKernelGGL(k_update<1>, dim3(nb), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout, h->partR,
+                           do_update ? 1 : 0, h->psi_delta);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
@@ -345,20 +328,29 @@ static csx_status launch_update(csx_geometry *h, const float *f, const float *b1
 csx_status csx_launch_update(csx_geometry *h, const float *f, double beta, bool do_update,
                              hipStream_t s)
 {
-    return launch_update(h, f, h->b1, h->b2, beta, h->ftmp, do_update, nullptr, s);
-}
-
-csx_status csx_launch_update_obj(csx_geometry *h, const float *f, double beta, bool do_update, double *J,
-                                 const int *iter, hipStream_t s)
-{
-    const ObjArgs oa{h->partL, h->partF, h->nbL, h->flags, J, iter, h->ucount};
-    return launch_update(h, f, h->b1, h->b2, beta, h->ftmp, do_update, &oa, s);
+    return launch_update(h, f, h->b1, h->b2, beta, h->ftmp, do_update, s);
 }
 
 csx_status csx_launch_update_ex(csx_geometry *h, const float *f, const float *b1, const float *b2,
                                 double beta, float *fout, hipStream_t s)
 {
-    return launch_update(h, f, b1, b2, beta, fout, true, nullptr, s);
+    return launch_update(h, f, b1, b2, beta, fout, true, s);
+}
+
+csx_status csx_launch_copy_objective(csx_geometry *h, float *f, double beta, double *J, const int *iter,
+                                     hipStream_t s)
+{
+    const int n = h->P.nvox * h->P.nq;
+    if (n % 4 != 0 || (((uintptr_t)h->ftmp | (uintptr_t)f) & 15) != 0) {
+        csx_status st = csx_launch_copy(h->ftmp, f, n, s);
+        if (st != CSX_OK) return st;
+        return csx_launch_objective(h, beta, J, iter, s);
+    }
+    const int nb = (n / 4 + 255) / 256;
+    hipLaunchKernelGGL(k_copy4_objective, dim3(nb + 1), dim3(256), 0, s, (const float4 *)h->ftmp, (float4 *)f, n / 4,
+                       h->partL, h->nbL, h->partR, h->nbRu, h->partF, beta, h->flags, J, iter);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
 }
 
 csx_status csx_launch_objective(csx_geometry *h, double beta, double *J, const int *iter,
