@@ -47,6 +47,9 @@
 
 namespace {
 
+// Blocks have up to 1024 threads (the register budget is set for that); the
+// launch takes the smallest of 256, 512, 1024 that covers a voxel group's
+// work, so that with small detectors several blocks share a compute unit.
 constexpr int IV_THREADS = 1024;
 constexpr int IV_WAVES = IV_THREADS / 64;
 constexpr int IVA_THREADS = 1024;
@@ -75,6 +78,8 @@ struct IvState {
     int cap = 0;                // prefix-table entries between the two fixed ones (largest group)
     int ncell = 0;              // detector cells of the upper half (columns x rows)
     int np = 1;                 // forward: work items per thread (power of 2, <= 8)
+    int th_f = 0, th_a = 0;     // threads per block of the forward and the adjoint
+    int cus = 256;              // compute units of the device
     int nblk_f = 0, nblk_a = 0;
     int lds_f = 0, lds_a = 0;
     int64_t bytes = 0;
@@ -393,8 +398,8 @@ __device__ __forceinline__ int sum_below(int v, int wv)
 }
 
 // ---------------------------------------------------------------------------
-// Forward: g = A f.  Block = IV_THREADS threads, a contiguous range of voxel
-// groups; thread k owns work items k, k + IV_THREADS, ... (NP of them) and
+// Forward: g = A f.  Block = TH <= IV_THREADS threads, a contiguous range of
+// voxel groups; thread k owns work items k, k + TH, ... (NP of them) and
 // keeps their pixels' sums in registers; partial image per block.
 // ---------------------------------------------------------------------------
 template <int LR, int NP, int TPM>
@@ -410,7 +415,8 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
     double2 *s_tot = (double2 *)(s_f + 4 * P.nq);                                    // [IV_WAVES]
     auto s_F = [&](int g) { return (float2 *)((unsigned char *)s_F0 + (g & 1) * fst); };
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int i = tid; i < V.nt; i += IV_THREADS) {
+    const int TH = blockDim.x;
+    for (int i = tid; i < V.nt; i += TH) {
         s_coef[i] = V.coef[i];
         s_mt[i] = V.mt[i];
     }
@@ -418,7 +424,7 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
     const int per = (V.ngroups + gridDim.x - 1) / gridDim.x;
     const int g0 = blockIdx.x * per, g1 = min(V.ngroups, g0 + per);
     // thresholds of this thread in the scan (at most TPM)
-    const int tper = (V.nt + IV_THREADS - 1) / IV_THREADS;
+    const int tper = (V.nt + TH - 1) / TH;
     const int t0 = min(V.nt, tid * tper), t1 = min(V.nt, t0 + tper);
 
     constexpr int NO = LR ? 4 : 2;
@@ -434,7 +440,7 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
         const uint2 *rg = V.rec + (size_t)min(g, g1 - 1) * V.n_slots;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-            const int p = min(tid + i * IV_THREADS, V.n_items - 1);
+            const int p = min(tid + i * TH, V.n_items - 1);
             if (LR) {
                 r[i] = *(const uint4 *)(rg + 2 * p);
             } else {
@@ -565,7 +571,7 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
     const int half_y = P.ndy / 2;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-        const int p = tid + i * IV_THREADS;
+        const int p = tid + i * TH;
         if (p >= V.n_items) continue;
         int a, r;
         item_class(P, LR, p, 0, a, r);
@@ -614,7 +620,8 @@ __global__ void __launch_bounds__(1024) k_iv_sum(const float *__restrict__ part,
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint: b = A^T rho.  One block of IVA_THREADS threads per compute unit,
+// Adjoint: b = A^T rho.  Blocks of TH <= IVA_THREADS threads (one per compute
+// unit at 128^2),
 // a contiguous range of voxel groups, one group at a time, two barriers per
 // group:
 //  A. thread k reads the records of ranks 8k .. 8k + 7 of the group (their
@@ -653,12 +660,13 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
     double *s_phi = (double *)(s_wc + IVA_WAVES);                    // [nphi]
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nphi = max(P.ne + 2, IVA_SC * IVA_SUB + 2);
-    for (int k = tid; k < nphi; k += IVA_THREADS)
+    const int TH = blockDim.x;
+    for (int k = tid; k < nphi; k += TH)
         s_phi[k] = k >= P.ne + 2 ? 0.0 : (double)(P.td == CSX_TABLE_BF16 ? bf16_to_f32(T.phi16[k]) : T.phi32[k]);
     // detector terms of every cell (column, upper row): rho_u, rho_d and
     // rho_u + rho_d, the same for every group; then the zero entry
     const int half_y = P.ndy / 2;
-    for (int c = tid; c < V.ncell; c += IVA_THREADS) {
+    for (int c = tid; c < V.ncell; c += TH) {
         const int col = c % P.ndx, bu = half_y + c / P.ndx, bd = P.ndy - 1 - bu;
         const float u = rho[bu * P.ndx + col], d = rho[bd * P.ndx + col];
         s_tab[3 * c] = u;
@@ -749,7 +757,7 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
                     s_E[ci] = make_double2(ba + loc[i].x, bb + loc[i].y);
                     ++ci;
                 }
-            if (tid == IVA_THREADS - 1) s_E[1] = make_double2(oa + ia, ob + ib);
+            if (tid == TH - 1) s_E[1] = make_double2(oa + ia, ob + ib);
         }
         __syncthreads();
         // C. b_jm = q_m sum_c Phi~[c] (E(P(m, c + 1)) - E(P(m, c)))
@@ -776,7 +784,7 @@ __global__ void __launch_bounds__(IVA_THREADS) k_iv_adjoint(KParams P, IvArgs V,
             }
             load_emap(g + 1);   // used after the next group's two barriers
         } else {
-            for (int mb = 0; mb < P.nq; mb += IVA_THREADS / IVA_SUB) {
+            for (int mb = 0; mb < P.nq; mb += TH / IVA_SUB) {
                 const int m = mb + tid / IVA_SUB, sub = tid % IVA_SUB;
                 double sa = 0.0, sb = 0.0;
                 if (m < P.nq) {
@@ -850,13 +858,41 @@ void iv_release(IvState *v)
     delete v;
 }
 
-// The adjoint's gather form: 2 (16 threads of 4 bins per node), 1 (8
-// threads of 8 bins) or 0 (8 threads, bins with stride 8).
-int iva_pf(const KParams &P)
+// The adjoint's gather form for blocks of th threads: 2 (16 threads of 4
+// bins per node), 1 (8 threads of 8 bins) or 0 (8 threads, bins with stride
+// 8, nodes in passes of th / 8).
+int iva_pf(const KParams &P, int th)
 {
     if (P.ne > IVA_SC * IVA_SUB) return 0;
-    if (P.nq <= IVA_THREADS / 16) return 2;
-    return P.nq <= IVA_THREADS / IVA_SUB ? 1 : 0;
+    if (P.nq <= th / 16) return 2;
+    return P.nq <= th / IVA_SUB ? 1 : 0;
+}
+
+// Blocks of a launch over n groups: as many as the compute units hold at
+// once (by threads and by LDS), each taking a contiguous range of groups.
+int iv_blocks(int n, int cus, int th, int lds)
+{
+    const int per_cu = std::max(1, std::min(IV_THREADS / th, (int)(CSX_LDS_MAX / std::max(lds, 1))));
+    const int per = (n + cus * per_cu - 1) / (cus * per_cu);
+    return (n + per - 1) / per;
+}
+
+// Block sizes: the smallest of 256, 512, 1024 threads that covers a group's
+// rank chunks (adjoint) or its work items at <= 4 (LR) or 8 per thread, its
+// f values and <= 8 thresholds per thread (forward).
+int iva_threads(long nch)
+{
+    for (int th = 256; th <= IVA_THREADS; th *= 2)
+        if (nch <= th) return th;
+    return 0;
+}
+
+int iv_threads(const KParams &P, long items, long nt)
+{
+    const long npmax = P.lr ? 4 : 8;
+    for (int th = 256; th <= IV_THREADS; th *= 2)
+        if (items <= npmax * th && 2L * P.nq <= th && nt <= 8L * th) return th;
+    return IV_THREADS;
 }
 
 // LDS of the adjoint with a prefix table of cap in-between entries: the
@@ -970,19 +1006,20 @@ csx_status csx_iv_build(csx_geometry *h)
     v->n_slots = P.lr ? 2 * v->n_items : v->n_items;
     v->rstride = (v->n_slots + IVA_SC - 1) / IVA_SC * IVA_SC;
     v->nch = v->rstride / IVA_SC;
-    v->es = iva_pf(P) ? IVA_SC * IVA_SUB + IVA_SC : (ne + 1 + 7) / 8 * 8;   // PF rows: 72, 16-byte aligned
+    v->th_a = iva_threads(v->nch);
+    v->th_f = iv_threads(P, v->n_items, nt);
+    v->es = iva_pf(P, v->th_a) ? IVA_SC * IVA_SUB + IVA_SC : (ne + 1 + 7) / 8 * 8;   // PF rows: 72, 16-byte aligned
     v->ncell = P.ndx * (P.ndy / 2);
     v->np = 1;
-    while (v->np * IV_THREADS < v->n_items) v->np *= 2;
+    while (v->np * v->th_f < v->n_items) v->np *= 2;
     v->lds_f = lds_f;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
         cus = 256;
-    {
-        int per = (P.n_groups + cus - 1) / cus;                  // one block per compute unit
-        v->nblk_f = (P.n_groups + per - 1) / per;
-        v->nblk_a = v->nblk_f;
-    }
+    v->cus = cus;
+    // as many blocks as the compute units hold at once (threads and LDS),
+    // each a contiguous range of groups
+    v->nblk_f = iv_blocks(P.n_groups, cus, v->th_f, lds_f);
     csx_status st;
     if ((st = iv_upload(&v->coef, coef, v->bytes)) != CSX_OK) return bail(st);
     if ((st = iv_upload(&v->mt, mt, v->bytes)) != CSX_OK) return bail(st);
@@ -1037,6 +1074,7 @@ csx_status csx_iv_build(csx_geometry *h)
     if (la > CSX_LDS_MAX)
         return bail(csx_fail(CSX_EINVAL, "interval operators: the adjoint's tables exceed LDS"));
     v->lds_a = (int)la;
+    v->nblk_a = iv_blocks(P.n_groups, v->cus, v->th_a, v->lds_a);
     v->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     h->bytes += v->bytes;
     h->iv = v;
@@ -1050,7 +1088,7 @@ csx_status csx_iv_forward(const csx_geometry *h, const float *f, float *part, si
     if (!part) part = v->part;
     else if ((size_t)v->nblk_f * h->P.npix > part_cap) return csx_fail(CSX_EINVAL, "forward partials exceed the buffer");
     const IvArgs a = iv_args(h, v);
-    const dim3 grid(v->nblk_f), block(IV_THREADS);
+    const dim3 grid(v->nblk_f), block(v->th_f);
 #define CSX_IVF(LR_, NP_, TPM_) \
     hipLaunchKernelGGL((k_iv_forward<LR_, NP_, TPM_>), grid, block, v->lds_f, s, h->P, a, f, part)
 #define CSX_IVF_T(LR_, NP_)               \
@@ -1060,7 +1098,7 @@ csx_status csx_iv_forward(const csx_geometry *h, const float *f, float *part, si
         else CSX_IVF(LR_, NP_, 16);       \
     } while (0)
     // thresholds per thread in the F scan
-    const int tper = (v->nt + IV_THREADS - 1) / IV_THREADS;
+    const int tper = (v->nt + v->th_f - 1) / v->th_f;
     if (h->P.lr) {
         if (v->np == 1) CSX_IVF_T(1, 1);
         else if (v->np == 2) CSX_IVF_T(1, 2);
@@ -1084,8 +1122,8 @@ csx_status csx_iv_adjoint(const csx_geometry *h, const float *rho, float *b, hip
 {
     const IvState *v = (const IvState *)h->iv;
     const IvArgs a = iv_args(h, v);
-    const dim3 grid(v->nblk_a), block(IVA_THREADS);
-    const int pf = iva_pf(h->P);
+    const dim3 grid(v->nblk_a), block(v->th_a);
+    const int pf = iva_pf(h->P, v->th_a);
 #define CSX_IVA(LR_, PF_) \
     hipLaunchKernelGGL((k_iv_adjoint<LR_, PF_>), grid, block, v->lds_a, s, h->P, a, h->t, rho, b)
     if (h->P.lr) {
