@@ -328,6 +328,75 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_paper(args):
+    """The paper's simulation shape (Sec. VII): 28^2 voxels x 79 q, a 1536 x
+    2048 detector of 0.19 mm pixels, stand-ins for the spectrum and mask, the
+    two-vial phantom.  Beyond the interval form's limits, so the direct
+    operators run; the adjoint splits its pixel classes into tile ranges.  A
+    step is one Alg. 5 iteration (Poisson counts around the phantom's forward,
+    peak mean 1e4).  Context: the paper's Table 1 times this shape's operators
+    in MATLAB on a 12-core CPU."""
+    import torch
+
+    from paper_1603_06400_amd import csx, inputs
+
+    torch.cuda.set_device(0)
+    g0 = inputs.paper_geometry()
+    unit = csx.Geometry(g0)
+    ftrue = torch.tensor(inputs.paper_phantom(g0), dtype=torch.float32, device="cuda")
+    mean = unit.forward(ftrue).double().cpu().numpy()
+    unit.close()
+    C = 1e4 / float(mean.max())
+    g = g0.with_(C=C)
+    geo = csx.Geometry(g)
+    y = torch.tensor(inputs.poisson_counts(C * mean, 1), dtype=torch.float32, device="cuda")
+    f = geo.new_image()
+    geo.recon(y, f, max(1, args.warmup), 1e-3, init_uniform=True)
+
+    def med(fn, n=10):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    gout, bout = geo.new_detector(), geo.new_image()
+    fwd = med(lambda: geo.forward(f, gout))
+    adj = med(lambda: geo.backproject(y, bout))
+    lc = geo.get_launch()
+    geo.set_launch(lc["fwd_splits"], lc["fwd_qw"], lc["adj_qw"], 1)
+    adj1 = med(lambda: geo.backproject(y, bout))
+    geo.set_launch(lc["fwd_splits"], lc["fwd_qw"], lc["adj_qw"], lc["adj_splits"])
+    J = torch.zeros(max(1, args.steps), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        geo.recon_step(y, f, 1e-3, J=J[k:k + 1])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
+    trip = float(g.nvox) * g.npix * g.nq
+    print(json.dumps({
+        "metric": "fwd+adjoint voxel*pixel*energy evals/s, paper shape 28^2 x 79q x 1536x2048 (one Alg. 5 "
+                  "iteration per step)",
+        "value": 2.0 * trip / (ms * 1e-3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "paper_shape", "voxels": [g.nz, g.nx], "nq": g.nq, "detector": [g.ndy, g.ndx],
+                   "ne": g.ne, "triples_per_operator": trip, "operators": "direct (beyond the interval form)",
+                   "launch": lc},
+        "forward_ms": fwd, "adjoint_ms": adj, "adjoint_ms_unsplit": adj1,
+        "objective_first_last": [float(J[0]), float(J[-1])] if args.steps else None,
+        "context": {"paper_table1_matlab_12core_s": {"forward_no_opt": 10516.88, "backward_no_opt": 10512.32,
+                                                      "forward_sai": 319.45, "backward_sai": 1191.05}},
+    }))
+
+
 def bench_os(args):
     """Ordered subsets (Alg. 6) with the paper's 64-subset partition on the
     128^2 x 64q slice and its stored counts: a step is one sweep over all
@@ -562,11 +631,12 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
                          "reference kernel for scaling HBM byte counters")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64", "warm", "os", "sai", "energy"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch64", "warm", "os", "sai", "energy", "paper"],
                     help="slice128 (default): the single 128^2 x 64q slice; batch64: the batched form; "
                          "warm: time to the plain objective with the learned warm start; os: sweeps of "
                          "ordered subsets (Alg. 6, 64 subsets) on the slice; sai: Alg. 5 with "
-                         "scatter-angle interpolation; energy: Alg. 5 on energy-resolved counts")
+                         "scatter-angle interpolation; energy: Alg. 5 on energy-resolved counts; paper: the paper's "
+                         "28^2 x 79q x 1536x2048 shape (direct operators)")
     ap.add_argument("--sai-interp", default="linear", choices=["linear", "nearest"],
                     help="sai: node rule of the timed table")
     ap.add_argument("--tto-cases", type=int, default=4,
@@ -594,6 +664,9 @@ def main():
         return
     if args.workload == "os":
         bench_os(args)
+        return
+    if args.workload == "paper":
+        bench_paper(args)
         return
     if args.workload == "sai":
         bench_sai(args)

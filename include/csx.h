@@ -341,11 +341,20 @@ csx_status csx_valu_peak(double *lane_ops_per_s, void *stream);
  *               share of the splits: with a multiple of 8 each XCD's L2 holds
  *               only its share of f.  Default: at least 8.
  *   fwd_qw, adj_qw: q lanes per chunk of the forward / adjoint (16, 32 or 64);
- *               nq is covered by ceil(nq / qw) chunks. */
+ *               nq is covered by ceil(nq / qw) chunks.
+ *   adj_splits: the direct adjoint's pixel classes are split into this many
+ *               contiguous tile ranges (1..64), one wave per voxel group, q
+ *               chunk and range, the ranges' partial images summed in a fixed
+ *               order: with few voxel groups (a small voxel grid) the adjoint
+ *               otherwise holds too few waves to fill the device.  0 in
+ *               csx_set_launch: the default, enough ranges for about 4 waves
+ *               per SIMD.  The interval form, batches and subsets do not
+ *               split. */
 typedef struct {
     int fwd_splits;
     int fwd_qw;
     int adj_qw;
+    int adj_splits;
 } csx_launch;
 
 csx_status csx_get_launch(const csx_geometry *h, csx_launch *out);

@@ -1,7 +1,8 @@
 """Launch-shape autotuner of the operators.
 
 For one geometry handle it times the forward over voxel-split counts and q
-chunk widths, and the adjoint over q chunk widths (HIP events on the current
+chunk widths, and the adjoint over q chunk widths and pixel-class splits (the
+direct adjoint's tile ranges; HIP events on the current
 stream, median of a few launches), keeps the fastest shape, and caches it per
 size class in a JSON file so that scans of the same shape are tuned once.
 The shape changes only the float32 summation order of the results.
@@ -18,6 +19,7 @@ from . import csx
 
 SPLITS = (1, 2, 4, 8, 16, 32)
 QWS = (16, 32, 64)
+ADJ_SPLITS = (1, 2, 4, 8, 16)
 
 
 def size_key(geo: "csx.Geometry") -> str:
@@ -63,7 +65,7 @@ def _time(fn, reps: int) -> float:
     return times[len(times) // 2]
 
 
-def tune(geo: "csx.Geometry", reps: int = 5, splits=SPLITS, qws=QWS) -> dict:
+def tune(geo: "csx.Geometry", reps: int = 5, splits=SPLITS, qws=QWS, adj_splits=ADJ_SPLITS) -> dict:
     """Times the candidate shapes on synthetic buffers; sets and returns the best."""
     f = torch.rand(geo.image_shape, device="cuda")
     y = torch.rand(geo.detector_shape, device="cuda")
@@ -77,12 +79,13 @@ def tune(geo: "csx.Geometry", reps: int = 5, splits=SPLITS, qws=QWS) -> dict:
             t = _time(lambda: geo.forward(f, g), reps)
             if best_f is None or t < best_f[0]:
                 best_f = (t, sp, qw)
-        geo.set_launch(start["fwd_splits"], start["fwd_qw"], qw)
-        t = _time(lambda: geo.backproject(y, b), reps)
-        if best_a is None or t < best_a[0]:
-            best_a = (t, qw)
-    geo.set_launch(best_f[1], best_f[2], best_a[1])
-    return {"fwd_splits": best_f[1], "fwd_qw": best_f[2], "adj_qw": best_a[1],
+        for asp in adj_splits:
+            geo.set_launch(start["fwd_splits"], start["fwd_qw"], qw, asp)
+            t = _time(lambda: geo.backproject(y, b), reps)
+            if best_a is None or t < best_a[0]:
+                best_a = (t, qw, asp)
+    geo.set_launch(best_f[1], best_f[2], best_a[1], best_a[2])
+    return {"fwd_splits": best_f[1], "fwd_qw": best_f[2], "adj_qw": best_a[1], "adj_splits": best_a[2],
             "forward_ms": best_f[0], "adjoint_ms": best_a[0]}
 
 
@@ -94,5 +97,5 @@ def tuned(geo: "csx.Geometry", cache: Optional[Dict[str, dict]] = None, reps: in
     if key not in cache:
         cache[key] = tune(geo, reps=reps)
     c = cache[key]
-    geo.set_launch(c["fwd_splits"], c["fwd_qw"], c["adj_qw"])
+    geo.set_launch(c["fwd_splits"], c["fwd_qw"], c["adj_qw"], c.get("adj_splits", 0))
     return c

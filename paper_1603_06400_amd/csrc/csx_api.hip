@@ -142,7 +142,7 @@ static void free_all(csx_geometry *h)
     csx_energy_free(h);
     void *ptrs[] = {h->t.vf, h->t.vm, h->t.vd, h->t.qa, h->t.qblk, h->t.qv, h->t.phi32,
                     h->t.phi16, h->t.maskbits, h->part, h->gws, h->rho, h->ones, h->b1,
-                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags,
+                    h->b2, h->ftmp, h->partL, h->partR, h->partF, h->partS, h->scal, h->jhist, h->flags, h->apart,
                     h->fplain, h->warm, h->a1, h->t.ra, h->t.rf, h->t.ram, h->t.rfm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -375,6 +375,10 @@ extern "C" csx_status csx_init_geometry(const csx_geometry_desc *d, csx_geometry
     CSX_TRY(dev_alloc(&h->b1, nimg, B));
     CSX_TRY(dev_alloc(&h->b2, nimg, B));
     CSX_TRY(dev_alloc(&h->ftmp, nimg, B));
+    if (h->lc.adj_splits > 1) {
+        h->apart_cap = (size_t)h->lc.adj_splits * nimg;
+        CSX_TRY(dev_alloc(&h->apart, h->apart_cap, B));
+    }
     h->nbL = (P.npix + 255) / 256;
     h->nbR = (int)((nimg + 255) / 256);
     CSX_TRY(dev_alloc(&h->partL, h->nbL, B));
@@ -449,10 +453,26 @@ extern "C" csx_status csx_get_launch(const csx_geometry *h, csx_launch *out)
 extern "C" csx_status csx_set_launch(csx_geometry *h, const csx_launch *lc)
 {
     if (!h || !lc) return csx_fail(CSX_EINVAL, "NULL argument");
-    if (!csx_launch_valid(*lc))
-        return csx_fail(CSX_EINVAL, "launch shape: qw must be 16, 32 or 64 and 1 <= fwd_splits <= 64");
+    csx_launch nl = *lc;
+    if (nl.adj_splits == 0) nl.adj_splits = csx_default_adj_splits(h->P, nl.adj_qw);
+    if (!csx_launch_valid(nl))
+        return csx_fail(CSX_EINVAL, "launch shape: qw must be 16, 32 or 64, 1 <= fwd_splits <= 64 and "
+                                    "0 <= adj_splits <= 64");
+    const size_t aneed = nl.adj_splits > 1 ? (size_t)nl.adj_splits * h->P.nvox * h->P.nq : 0;
+    if (aneed > h->apart_cap) {
+        HIP_TRY(hipDeviceSynchronize());
+        float *p = nullptr;
+        if (hipMalloc((void **)&p, aneed * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            return csx_fail(CSX_ENOMEM, "adjoint partials");
+        }
+        if (h->apart) HIP_TRY(hipFree(h->apart));
+        h->bytes += (int64_t)((aneed - h->apart_cap) * sizeof(float));
+        h->apart = p;
+        h->apart_cap = aneed;
+    }
     const csx_launch old = h->lc;
-    h->lc = *lc;
+    h->lc = nl;
     const size_t need = (size_t)csx_forward_shape(h).nparts * h->P.npix;
     if (need > h->part_cap) {
         HIP_TRY(hipDeviceSynchronize());

@@ -55,6 +55,9 @@ struct KParams {
     // column a, pixel row ndy/2 + r); otherwise all quads and classes
     const int *quad_list = nullptr;
     const int *cls_list = nullptr;
+    // the adjoint's pixel-class tiles split into asplit contiguous ranges
+    // (blockIdx.z), each writing its own partial image (full adjoint only)
+    int asplit = 1;
 };
 
 // Per-voxel records.  vf: {C*Gso, det_z - z} (float32); vm: {t/pm,
@@ -135,6 +138,8 @@ struct csx_geometry {
     float *b1 = nullptr;       // [nvox*nq] sensitivity
     float *b2 = nullptr;       // [nvox*nq]
     float *ftmp = nullptr;     // [nvox*nq]
+    float *apart = nullptr;    // [adj_splits][nvox*nq] partial images of a split direct adjoint
+    size_t apart_cap = 0;      // floats in apart
     double *partL = nullptr;   // per-block data-fit partials
     double *partR = nullptr;   // per-block penalty partials
     double *partS = nullptr;   // [2 * CSX_SUM_BLOCKS] partial sums of the uniform start
@@ -172,6 +177,7 @@ struct csx_geometry {
 csx_status csx_launch_forward(csx_geometry *h, const float *f, float *g, hipStream_t s);
 csx_status csx_launch_adjoint(csx_geometry *h, const float *rho, float *b, hipStream_t s);
 csx_launch csx_default_launch(const KParams &P);
+int csx_default_adj_splits(const KParams &P, int adj_qw);
 bool csx_launch_valid(const csx_launch &lc);
 OpShape csx_forward_shape(const csx_geometry *h);
 OpShape csx_adjoint_shape(const csx_geometry *h);

@@ -73,7 +73,7 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
                                              const double *__restrict__ qa,
                                              const double2 *__restrict__ qblk,
                                              const float *__restrict__ rho, float *__restrict__ b,
-                                             int bx, int by)
+                                             int bx, int by, int bz = 0)
 {
     static_assert(!(EN && ST), "the energy-resolved adjoint evaluates its factors");
     constexpr int NB = QW / 8;
@@ -166,9 +166,17 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
             }
         }
     };
-    load_rho(0);
+    // split adjoint: this wave's contiguous range of tiles, into partial image bz
+    int tb = 0, te = ntiles;
+    if (P.asplit > 1 && !P.cls_list) {
+        const int per = (ntiles + P.asplit - 1) / P.asplit;
+        tb = min(ntiles, bz * per);
+        te = min(ntiles, tb + per);
+        b += (size_t)bz * P.nvox * P.nq;
+    }
+    if (tb < te) load_rho(tb);
 
-    for (int t = 0; t < ntiles; ++t) {
+    for (int t = tb; t < te; ++t) {
         int a = 0, r = 0;
         const bool has = class_of(t, a, r);
         double kap = 0.0;
@@ -265,7 +273,7 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
                 if (LR) v1 = pad ? 0.0f : psi_sum(kk, ebu, pbu, ebd, pbd);
             }
         };
-        if (t + 1 < ntiles) load_rho(t + 1);
+        if (t + 1 < te) load_rho(t + 1);
         if (__ballot(act) == 0) continue;
         if (QU) {
             // uniform q grid: u_m = u0 + m du, in-band nodes in the wave's range
@@ -828,7 +836,7 @@ __global__ void __launch_bounds__(256) k_adjoint(KParams P, DevTables T, Lds L,
                                                  const float *__restrict__ rho,
                                                  float *__restrict__ b)
 {
-    adjoint_body<LR, QW, QU, 0, ST>(P, T, L, qa, qblk, rho, b, blockIdx.x, blockIdx.y);
+    adjoint_body<LR, QW, QU, 0, ST>(P, T, L, qa, qblk, rho, b, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <int LR, int QW, int QU, int ST>
@@ -1504,6 +1512,19 @@ hipEvent_t csx_timing_event(csx_geometry *h, int op)
     return v[h->ev_used[op]++];
 }
 
+// Default tile ranges of the direct adjoint: enough for about 4 waves per
+// SIMD (one wave per voxel group, q chunk and range), each range at least 4
+// tiles of 64 classes.
+int csx_default_adj_splits(const KParams &P, int adj_qw)
+{
+    const long qchunks = (P.nq + adj_qw - 1) / adj_qw;
+    const long waves = std::max(1L, (long)P.n_groups * qchunks);
+    const long ntiles = (long)((P.ndx + 7) / 8) * ((P.ndy / 2 + 7) / 8);
+    long sp = (4L * 4 * 256 + waves - 1) / waves;
+    sp = std::min(sp, std::max(1L, ntiles / 4));
+    return (int)std::max(1L, std::min(sp, 64L));
+}
+
 csx_launch csx_default_launch(const KParams &P)
 {
     csx_launch lc;
@@ -1519,13 +1540,15 @@ csx_launch csx_default_launch(const KParams &P)
     int splits = std::max(8, target_waves / std::max(1, bx * 8 * qchunks));
     splits = std::min(splits, std::max(1, fwd_tiles(P) / 2));
     lc.fwd_splits = std::min(splits, 64);
+    lc.adj_splits = csx_default_adj_splits(P, lc.adj_qw);
     return lc;
 }
 
 bool csx_launch_valid(const csx_launch &lc)
 {
     auto okq = [](int q) { return q == 16 || q == 32 || q == 64; };
-    return okq(lc.fwd_qw) && okq(lc.adj_qw) && lc.fwd_splits >= 1 && lc.fwd_splits <= 64;
+    return okq(lc.fwd_qw) && okq(lc.adj_qw) && lc.fwd_splits >= 1 && lc.fwd_splits <= 64 && lc.adj_splits >= 1 &&
+           lc.adj_splits <= 64;
 }
 
 OpShape csx_forward_shape(const csx_geometry *h)
@@ -1609,8 +1632,19 @@ csx_status csx_launch_adjoint(csx_geometry *h, const float *rho, float *b, hipSt
         csx_status st = csx_iv_adjoint(h, rho, b, s);
         if (st != CSX_OK) return st;
     } else {
-        const OpShape S = csx_adjoint_shape(h);
-        dispatch<RunAdj>(S.variant, S, h, rho, b, s);
+        OpShape S = csx_adjoint_shape(h);
+        const int sp = h->lc.adj_splits;
+        if (sp > 1 && (size_t)sp * h->P.nvox * h->P.nq <= h->apart_cap) {
+            // tile ranges into partial images, added in range order
+            S.P.asplit = sp;
+            S.grid.z = sp;
+            dispatch<RunAdj>(S.variant, S, h, rho, h->apart, s);
+            const int n = h->P.nvox * h->P.nq;
+            hipLaunchKernelGGL(k_sum_parts, dim3((n + 255) / 256), dim3(256), 0, s, (const float *)h->apart, sp, n,
+                               b);
+        } else {
+            dispatch<RunAdj>(S.variant, S, h, rho, b, s);
+        }
         HIP_TRY(hipGetLastError());
     }
     if (e1) HIP_TRY(hipEventRecord(e1, s));

@@ -50,7 +50,8 @@ class _Desc(ctypes.Structure):
 
 
 class _Launch(ctypes.Structure):
-    _fields_ = [("fwd_splits", ctypes.c_int), ("fwd_qw", ctypes.c_int), ("adj_qw", ctypes.c_int)]
+    _fields_ = [("fwd_splits", ctypes.c_int), ("fwd_qw", ctypes.c_int), ("adj_qw", ctypes.c_int),
+                ("adj_splits", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -272,8 +273,9 @@ class Geometry:
         _check(lib().csx_get_launch(self._h, ctypes.byref(out)))
         return {k: getattr(out, k) for k, _ in _Launch._fields_}
 
-    def set_launch(self, fwd_splits: int, fwd_qw: int, adj_qw: int) -> None:
-        lc = _Launch(int(fwd_splits), int(fwd_qw), int(adj_qw))
+    def set_launch(self, fwd_splits: int, fwd_qw: int, adj_qw: int, adj_splits: int = 0) -> None:
+        """adj_splits = 0: the default split of the direct adjoint's pixel classes."""
+        lc = _Launch(int(fwd_splits), int(fwd_qw), int(adj_qw), int(adj_splits))
         _check(lib().csx_set_launch(self._h, ctypes.byref(lc)))
 
     def set_factor_store(self, on: bool) -> None:

@@ -217,6 +217,38 @@ def workload(name: str) -> Workload:
     raise KeyError(name)
 
 
+def paper_geometry(mask_seed: int = 17, open_frac: float = 0.5, ne: int = 64, C: float = 1.0) -> ScanGeometry:
+    """The shape of the paper's simulation (Sec. VII) with stand-ins for what
+    it measured: 28 x 28 voxels of 2.5 mm (x) by 3.04 mm (z), 70 mm across and
+    85.12 mm deep, centred at z = 1035 mm; a 1536 x 2048 detector of 0.19 mm
+    pixels at z = 1546.5 mm, the secondary mask 100 mm in front of it; 79 q
+    nodes evenly spaced from 0.1 to 4.0 nm^-1 (0.01 to 0.4 A^-1, both ends
+    included).  Stand-ins: a seeded random mask of 1 mm cells (period 16, 320
+    rows, covering every ray) and a Kramers spectrum to 125 kVp in ne bins on
+    [20, 125) keV."""
+    return ScanGeometry(
+        nx=28, nz=28, x_min=-35.0, x_max=35.0, z_min=1035.0 - 42.56, z_max=1035.0 + 42.56,
+        q=np.linspace(0.1, 4.0, 79), ndx=1536, ndy=2048, det_pitch=0.19, det_z=1546.5,
+        mask_z=1446.5, mask_pitch=1.0, mask=make_mask(mask_seed, 320, MASK_PERIOD, open_frac),
+        e_lo=20.0, e_hi=125.0, phi=kramers_histogram(ne, 20.0, 125.0, kvp=125.0), C=C)
+
+
+def paper_phantom(geom: ScanGeometry, sigma: float = PEAK_SIGMA) -> np.ndarray:
+    """Two 4 x 4-voxel vials 20 mm apart across the fan, each holding a
+    material with a Gaussian-peak form factor (peaks at 1.9 and 2.7 nm^-1 in
+    one, 2.3 nm^-1 in the other); background 0."""
+    f = np.zeros((geom.nz, geom.nx, geom.nq), dtype=np.float64)
+    dx = (geom.x_max - geom.x_min) / geom.nx
+    kz = geom.nz // 2 - 2
+    for xc, peaks in ((-10.0, ((1.0, 1.9), (0.6, 2.7))), (10.0, ((0.8, 2.3),))):
+        i0 = int(round((xc - geom.x_min) / dx)) - 2
+        prof = np.zeros(geom.nq)
+        for a, mu in peaks:
+            prof += a * np.exp(-(geom.q - mu) ** 2 / (2.0 * sigma * sigma))
+        f[kz:kz + 4, i0:i0 + 4, :] += prof[None, None, :]
+    return f
+
+
 @dataclass
 class BatchScan:
     geom: ScanGeometry

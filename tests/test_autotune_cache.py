@@ -34,7 +34,7 @@ def test_cache_round_trip_and_reuse(tmp_path, monkeypatch):
 
     def fake_tune(geo, reps=5):
         calls.append(geo)
-        return {"fwd_splits": 4, "fwd_qw": 32, "adj_qw": 64, "forward_ms": 1.0, "adjoint_ms": 2.0}
+        return {"fwd_splits": 4, "fwd_qw": 32, "adj_qw": 64, "adj_splits": 2, "forward_ms": 1.0, "adjoint_ms": 2.0}
 
     monkeypatch.setattr(autotune, "tune", fake_tune)
     cache = {}
@@ -42,7 +42,7 @@ def test_cache_round_trip_and_reuse(tmp_path, monkeypatch):
     g2 = FakeGeo(inputs.standard_geometry(16, 8, ndet=10))
     autotune.tuned(g1, cache)
     autotune.tuned(g2, cache)
-    assert len(calls) == 1 and g2.shapes == [(4, 32, 64)]
+    assert len(calls) == 1 and g2.shapes == [(4, 32, 64, 2)]
     autotune.save_cache(cache, path)
     assert autotune.load_cache(path) == cache
     (tmp_path / "bad.json").write_text("{not json")

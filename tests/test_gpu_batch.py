@@ -123,13 +123,17 @@ def test_batch_scan_matches_oracle(oracle_mod):
     assert np.max(np.abs(J[0] - ref_J)) <= 1e-6 * abs(ref_J[0])
 
 
-@pytest.mark.parametrize("shape", [(1, 64, 64), (3, 32, 32), (7, 16, 64), (64, 64, 16), (2, 32, 64)])
+@pytest.mark.parametrize("shape", [(1, 64, 64, 1), (3, 32, 32, 3), (7, 16, 64, 16), (64, 64, 16, 1),
+                                   (2, 32, 64, 64)])
 def test_launch_shapes_keep_parity(oracle_mod, shape):
+    """Every shape, with the direct operators (the interval form does not
+    split) and with the adjoint's pixel classes in 1 to 64 tile ranges."""
     w, g, f, y = workload_data("slice32")
     o = oracle_mod.Oracle(g)
     geo = csx.Geometry(g)
+    geo.set_interval_operators(False)
     geo.set_launch(*shape)
-    assert geo.get_launch() == dict(zip(("fwd_splits", "fwd_qw", "adj_qw"), shape))
+    assert geo.get_launch() == dict(zip(("fwd_splits", "fwd_qw", "adj_qw", "adj_splits"), shape))
     assert_parity(host(geo.forward(dev(f))), o.forward(f), what=f"forward {shape}")
     assert_parity(host(geo.backproject(dev(y))), o.adjoint(y), what=f"adjoint {shape}")
 
@@ -137,7 +141,7 @@ def test_launch_shapes_keep_parity(oracle_mod, shape):
 def test_launch_shape_validation():
     w, g, f, y = workload_data("slice32")
     geo = csx.Geometry(g)
-    for bad in [(0, 64, 64), (65, 64, 64), (1, 48, 64), (1, 64, 8)]:
+    for bad in [(0, 64, 64), (65, 64, 64), (1, 48, 64), (1, 64, 8), (1, 64, 64, 65), (1, 64, 64, -1)]:
         with pytest.raises(csx.CsxError) as ei:
             geo.set_launch(*bad)
         assert ei.value.code == csx.CSX_EINVAL
