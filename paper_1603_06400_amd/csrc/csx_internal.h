@@ -58,6 +58,10 @@ struct KParams {
     // the adjoint's pixel-class tiles split into asplit contiguous ranges
     // (blockIdx.z), each writing its own partial image (full adjoint only)
     int asplit = 1;
+    // with a class list: the factor store in list order, the record of entry
+    // e of group g at T.ra[g * ra_gs + e] and the node range of its 64-entry
+    // chunk at T.ram[(g * ra_gs + e) / 64]; 0: the tile-major store
+    long ra_gs = 0;
 };
 
 // Per-voxel records.  vf: {C*Gso, det_z - z} (float32); vm: {t/pm,
@@ -119,6 +123,7 @@ struct OpShape {
     int tps;            // forward: voxel tiles per split
     int nparts;         // forward: partial images (splits x q chunks)
     int variant;        // kernel template: bit 1 LR, bit 2 uniform q, bits 3+ log2 qw
+    const DevTables *T = nullptr;   // tables of the launch when not the handle's own
 };
 
 struct csx_geometry {
@@ -197,8 +202,16 @@ OpShape csx_forward_shape_list(const csx_geometry *h, const int *quads, int n_qu
 csx_status csx_launch_forward_list(csx_geometry *h, const float *f, const int *quads, int n_quads, int splits,
                                    const int *pix, int n_pix, const float *y, const float *r, float *rho,
                                    hipStream_t s);
+// ra_list, ram_list, ra_gs: the factor store in the list's order (from
+// csx_launch_store_list), or null for the tile-major store.
 csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
-                                   hipStream_t s);
+                                   hipStream_t s, const uint4 *ra_list = nullptr, const uint32_t *ram_list = nullptr,
+                                   long ra_gs = 0);
+// The adjoint's factor-store records in the order of n_sub class lists of
+// n_cls entries each, padded to cls_pad (a multiple of 64): out [n_groups]
+// [n_sub][cls_pad], meta one node range per 64 records.
+csx_status csx_launch_store_list(const csx_geometry *h, const int *cls, int n_cls, int n_sub, int cls_pad, uint4 *out,
+                                 uint32_t *meta, hipStream_t s);
 hipEvent_t csx_timing_event(csx_geometry *h, int op);
 // interval-form exact operators (csx_interval.hip)
 bool csx_iv_feasible(const KParams &P, int *lds_f, int *lds_a);

@@ -148,8 +148,11 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
         if (ST) rb = 0u;
         if (class_of(t, a, r)) {
             if (ST) {
-                // record of class (a, r): tile (r/8, a/8), lane 8 (r mod 8) + a mod 8
-                const size_t e = ((size_t)g * ntiles_all + (r >> 3) * ntx + (a >> 3)) * 64 + ((r & 7) << 3) + (a & 7);
+                // record of class (a, r): tile (r/8, a/8), lane 8 (r mod 8) + a mod 8,
+                // or entry t 64 + lane of a list-order store
+                const size_t e = P.ra_gs ? (size_t)g * P.ra_gs + (size_t)t * 64 + lane
+                                         : ((size_t)g * ntiles_all + (r >> 3) * ntx + (a >> 3)) * 64 +
+                                               ((r & 7) << 3) + (a & 7);
                 const uint4 v = load_nt(T.ra + e);
                 rk = __longlong_as_double((long long)(((uint64_t)v.y << 32) | v.x));
                 rA = __uint_as_float(v.z);
@@ -283,7 +286,12 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
                 // the tile's node range (a superset of its lanes' ranges),
                 // wave-uniform: from the store's tile record, or reduced over
                 // the lanes for a class list
-                if (P.cls_list) {
+                if (P.cls_list && P.ra_gs) {
+                    const uint32_t tm =
+                        __builtin_amdgcn_readfirstlane(T.ram[((size_t)g * P.ra_gs + (size_t)t * 64) / 64]);
+                    lo = (int)(tm & 0xffffu) - m0;
+                    hi = (int)(tm >> 16) - m0;
+                } else if (P.cls_list) {
                     if (act) band_range(P, u0, du, 0, QW, lo, hi);
                     lo = wave_min(lo);
                     hi = wave_max(hi);
@@ -879,25 +887,18 @@ __device__ __forceinline__ void write_tile_range(uint32_t *dst, int lo, int hi)
 // adjoint_body evaluates them, A = kappa = 0 and no bits when the class is
 // inactive (every pair closed, or kappa out of band).  One thread per record.
 template <int LR>
-__global__ void __launch_bounds__(256) k_store_adjoint(KParams P, DevTables T, uint4 *__restrict__ out,
-                                                       uint32_t *__restrict__ meta)
+__device__ __forceinline__ uint4 adjoint_record(const KParams &P, const DevTables &T, int g, int a, int r,
+                                                double &k, uint32_t &bits)
 {
-    const int half_y = P.ndy / 2, ntx = (P.ndx + 7) / 8;
-    const int ntl = ntx * ((half_y + 7) / 8);
-    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (size_t)P.n_groups * ntl * 64) return;
-    const int g = (int)(idx / ((size_t)ntl * 64));
-    const int e = (int)(idx % ((size_t)ntl * 64));
-    const int t = e >> 6, lane = e & 63;
+    const int half_y = P.ndy / 2;
     int j = g;
     if (LR) {
         const int half = P.nx / 2;
         j = (g / half) * P.nx + g % half;
     }
-    const int a = (t % ntx) * 8 + (lane & 7), r = (t / ntx) * 8 + (lane >> 3);
-    double k = 0.0;
+    k = 0.0;
     float A = 0.0f;
-    uint32_t bits = 0u;
+    bits = 0u;
     if (a < P.ndx && r < half_y) {
         const int bu = half_y + r;
         const double xp = pixel_coord(P, a, P.ndx);
@@ -920,7 +921,52 @@ __global__ void __launch_bounds__(256) k_store_adjoint(KParams P, DevTables T, u
         }
     }
     const uint64_t ku = (uint64_t)__double_as_longlong(k);
-    out[idx] = make_uint4((uint32_t)ku, (uint32_t)(ku >> 32), __float_as_uint(A), bits);
+    return make_uint4((uint32_t)ku, (uint32_t)(ku >> 32), __float_as_uint(A), bits);
+}
+
+template <int LR>
+__global__ void __launch_bounds__(256) k_store_adjoint(KParams P, DevTables T, uint4 *__restrict__ out,
+                                                       uint32_t *__restrict__ meta)
+{
+    const int half_y = P.ndy / 2, ntx = (P.ndx + 7) / 8;
+    const int ntl = ntx * ((half_y + 7) / 8);
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)P.n_groups * ntl * 64) return;
+    const int g = (int)(idx / ((size_t)ntl * 64));
+    const int e = (int)(idx % ((size_t)ntl * 64));
+    const int t = e >> 6, lane = e & 63;
+    const int a = (t % ntx) * 8 + (lane & 7), r = (t / ntx) * 8 + (lane >> 3);
+    double k;
+    uint32_t bits;
+    out[idx] = adjoint_record<LR>(P, T, g, a, r, k, bits);
+    int lo, hi;
+    node_range(P, (bits & CSX_REC_ACT) != 0u, k, lo, hi);
+    write_tile_range(meta + idx / 64, lo, hi);
+}
+
+// The same records in the order of class lists: list p of n_sub, n_cls
+// classes each (class = r ndx + a), padded to cls_pad (a multiple of 64;
+// the padding is inactive); record of (group g, list p, entry e) at
+// (g n_sub + p) cls_pad + e, node range per 64 entries.  One thread per record.
+template <int LR>
+__global__ void __launch_bounds__(256) k_store_adjoint_list(KParams P, DevTables T, const int *__restrict__ cls,
+                                                            int n_cls, int n_sub, int cls_pad,
+                                                            uint4 *__restrict__ out, uint32_t *__restrict__ meta)
+{
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)P.n_groups * n_sub * cls_pad) return;
+    const int g = (int)(idx / ((size_t)n_sub * cls_pad));
+    const int rem = (int)(idx % ((size_t)n_sub * cls_pad));
+    const int p = rem / cls_pad, e = rem % cls_pad;
+    int a = P.ndx, r = P.ndy;                  // padding: outside the detector, inactive
+    if (e < n_cls) {
+        const int c = cls[(size_t)p * n_cls + e];
+        a = c % P.ndx;
+        r = c / P.ndx;
+    }
+    double k;
+    uint32_t bits;
+    out[idx] = adjoint_record<LR>(P, T, g, a, r, k, bits);
     int lo, hi;
     node_range(P, (bits & CSX_REC_ACT) != 0u, k, lo, hi);
     write_tile_range(meta + idx / 64, lo, hi);
@@ -1321,8 +1367,9 @@ struct RunAdj {
     static void run(const OpShape &S, const csx_geometry *h, const float *rho, float *b,
                     hipStream_t s)
     {
-        hipLaunchKernelGGL((k_adjoint<LR, QW, QU, ST>), S.grid, S.block, S.L.total, s, S.P, h->t,
-                           S.L, h->t.qa, h->t.qblk, rho, b);
+        const DevTables &T = S.T ? *S.T : h->t;
+        hipLaunchKernelGGL((k_adjoint<LR, QW, QU, ST>), S.grid, S.block, S.L.total, s, S.P, T,
+                           S.L, T.qa, T.qblk, rho, b);
     }
 };
 
@@ -1496,6 +1543,21 @@ csx_status csx_launch_store(const csx_geometry *h, uint4 *ra, uint4 *rf, uint32_
         hipLaunchKernelGGL(k_store_adjoint<0>, ga, dim3(256), 0, s, h->P, h->t, ra, ram);
         hipLaunchKernelGGL(k_store_forward<0>, gf, dim3(256), 0, s, h->P, h->t, rf, rfm);
     }
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_launch_store_list(const csx_geometry *h, const int *cls, int n_cls, int n_sub, int cls_pad, uint4 *out,
+                                 uint32_t *meta, hipStream_t s)
+{
+    const size_t n = (size_t)h->P.n_groups * n_sub * cls_pad;
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (h->P.lr)
+        hipLaunchKernelGGL(k_store_adjoint_list<1>, g, dim3(256), 0, s, h->P, h->t, cls, n_cls, n_sub, cls_pad, out,
+                           meta);
+    else
+        hipLaunchKernelGGL(k_store_adjoint_list<0>, g, dim3(256), 0, s, h->P, h->t, cls, n_cls, n_sub, cls_pad, out,
+                           meta);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
@@ -1687,11 +1749,19 @@ csx_status csx_launch_sum_ratio_list(csx_geometry *h, int nparts, const int *pix
 }
 
 csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b,
-                                   hipStream_t s)
+                                   hipStream_t s, const uint4 *ra_list, const uint32_t *ram_list, long ra_gs)
 {
     OpShape S = csx_adjoint_shape(h);
     S.P.cls_list = cls;
     S.P.n_cls = n_cls;
+    DevTables T = h->t;
+    if (ra_list && h->t.ra) {
+        // the factor store in this list's order
+        T.ra = const_cast<uint4 *>(ra_list);
+        T.ram = const_cast<uint32_t *>(ram_list);
+        S.P.ra_gs = ra_gs;
+        S.T = &T;
+    }
     // a short class list (an ordered subset) gives each wave only a few
     // tiles: 32-wide q chunks halve the per-wave reduction and the
     // accumulator registers, which outweighs evaluating each class twice

@@ -32,19 +32,29 @@ struct OsState {
     int *pix = nullptr;                       // [n_sub][n_pix]
     float *b1 = nullptr;                      // [n_sub][nvox * nq]
     int adj_op = 0;                           // CSX_OP_ADJOINT_SAI when b1 came from the interpolated adjoint
+    // the adjoint's factor store in subset order (with the handle's store):
+    // a subset's records of one voxel group are contiguous, so a wave's
+    // 64 lanes read 1 KB in one piece instead of 64 records from 64 tiles
+    uint4 *ra = nullptr;                      // [n_groups][n_sub][cls_pad]
+    uint32_t *ram = nullptr;                  // node range per 64 records
+    int cls_pad = 0;
 };
 
 // subset adjoint with the handle's selected operator (exact or interpolated)
-csx_status adjoint_list(csx_geometry *h, const float *rho, const int *cls, int n_cls, float *b, hipStream_t s)
+csx_status adjoint_list(csx_geometry *h, const OsState *o, int p, const float *rho, float *b, hipStream_t s)
 {
-    return (h->op_sai & CSX_OP_ADJOINT_SAI) ? csx_launch_adjoint_sai_list(h, rho, cls, n_cls, b, s)
-                                            : csx_launch_adjoint_list(h, rho, cls, n_cls, b, s);
+    const int *cls = o->cls + (size_t)p * o->n_cls;
+    if (h->op_sai & CSX_OP_ADJOINT_SAI) return csx_launch_adjoint_sai_list(h, rho, cls, o->n_cls, b, s);
+    if (o->ra && h->t.ra)
+        return csx_launch_adjoint_list(h, rho, cls, o->n_cls, b, s, o->ra + (size_t)p * o->cls_pad,
+                                       o->ram + (size_t)p * (o->cls_pad / 64), (long)o->n_sub * o->cls_pad);
+    return csx_launch_adjoint_list(h, rho, cls, o->n_cls, b, s);
 }
 
 void release(OsState *o)
 {
     if (!o) return;
-    void *ptrs[] = {o->quads, o->cls, o->pix, o->b1};
+    void *ptrs[] = {o->quads, o->cls, o->pix, o->b1, o->ra, o->ram};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete o;
@@ -122,9 +132,29 @@ csx_status build(csx_geometry *h, int rho_z, int rho_y, hipStream_t s, OsState *
         return fail(e);
     if ((e = hipMemcpyAsync(o->pix, pix.data(), sizeof(int) * pix.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
         return fail(e);
+    // the adjoint's factor store in subset order, when the handle has a store
+    // and the copy is small beside the device's free memory
+    if (h->t.ra) {
+        o->cls_pad = (o->n_cls + 63) / 64 * 64;
+        const size_t nrec = (size_t)P.n_groups * o->n_sub * o->cls_pad;
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && nrec * sizeof(uint4) <= (size_t)CSX_STORE_AUTO_BYTES &&
+            nrec * sizeof(uint4) <= fr / 4 && hipMalloc((void **)&o->ra, nrec * sizeof(uint4)) == hipSuccess &&
+            hipMalloc((void **)&o->ram, nrec / 64 * sizeof(uint32_t)) == hipSuccess) {
+            csx_status st = csx_launch_store_list(h, o->cls, o->n_cls, o->n_sub, o->cls_pad, o->ra, o->ram, s);
+            if (st != CSX_OK) {
+                release(o);
+                return st;
+            }
+        } else {
+            (void)hipGetLastError();
+            if (o->ra) (void)hipFree(o->ra);
+            o->ra = nullptr;
+            o->ram = nullptr;
+        }
+    }
     for (int p = 0; p < o->n_sub; ++p) {
-        csx_status st = adjoint_list(h, h->ones, o->cls + (size_t)p * o->n_cls, o->n_cls, o->b1 + (size_t)p * img,
-                                     s);
+        csx_status st = adjoint_list(h, o, p, h->ones, o->b1 + (size_t)p * img, s);
         if (st != CSX_OK) {
             release(o);
             return st;
@@ -206,7 +236,7 @@ extern "C" csx_status csx_recon_os(csx_geometry *h, const float *y, const float 
                 OS_TRY(csx_launch_forward_sai_list(h, cur, qd, o->n_quads, o->splits, px, o->n_pix, y, r, h->rho, s));
             else
                 OS_TRY(csx_launch_forward_list(h, cur, qd, o->n_quads, o->splits, px, o->n_pix, y, r, h->rho, s));
-            OS_TRY(adjoint_list(h, h->rho, o->cls + (size_t)p * o->n_cls, o->n_cls, h->b2, s));
+            OS_TRY(adjoint_list(h, o, p, h->rho, h->b2, s));
             OS_TRY(csx_launch_update_ex(h, cur, o->b1 + (size_t)p * img, h->b2, bp, nxt, s));
             std::swap(cur, nxt);
         }
