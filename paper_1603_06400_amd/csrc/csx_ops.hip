@@ -1763,10 +1763,12 @@ csx_status csx_launch_adjoint_list(csx_geometry *h, const float *rho, const int 
         S.T = &T;
     }
     // a short class list (an ordered subset) gives each wave only a few
-    // tiles: 32-wide q chunks halve the per-wave reduction and the
-    // accumulator registers, which outweighs evaluating each class twice
-    // (the q sums are the same whatever the chunking)
-    if (S.P.qw == 64 && n_cls <= 4 * 64) {
+    // tiles: when the pair factors are evaluated, 32-wide q chunks halve the
+    // per-wave reduction and the accumulator registers, which outweighs
+    // evaluating each class twice; with the store in list order, reading a
+    // record twice costs more than the wider reduction (the q sums are the
+    // same whatever the chunking)
+    if (S.P.qw == 64 && n_cls <= 4 * 64 && !(ra_list && h->t.ra)) {
         S.P.qw = 32;
         S.P.qchunks = (S.P.nq + 31) / 32;
         S.grid.y = S.P.qchunks;
