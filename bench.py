@@ -334,7 +334,7 @@ def bench_paper(args):
     two-vial phantom.  Beyond the interval form's limits, so the direct
     operators run; the adjoint splits its pixel classes into tile ranges.  A
     step is one Alg. 5 iteration (Poisson counts around the phantom's forward,
-    peak mean 1e4).  Context: the paper's Table 1 times this shape's operators
+    peak mean 1e4), timed with the autotuner's launch shape.  Context: the paper's Table 1 times this shape's operators
     in MATLAB on a 12-core CPU."""
     import torch
 
@@ -373,6 +373,11 @@ def bench_paper(args):
     geo.set_launch(lc["fwd_splits"], lc["fwd_qw"], lc["adj_qw"], 1)
     adj1 = med(lambda: geo.backproject(y, bout))
     geo.set_launch(lc["fwd_splits"], lc["fwd_qw"], lc["adj_qw"], lc["adj_splits"])
+    # the autotuner's shape (q chunk widths, forward voxel splits, adjoint class ranges)
+    from paper_1603_06400_amd import autotune
+    tuned = autotune.tune(geo, reps=3)
+    fwd_t = med(lambda: geo.forward(f, gout))
+    adj_t = med(lambda: geo.backproject(y, bout))
     J = torch.zeros(max(1, args.steps), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -389,8 +394,10 @@ def bench_paper(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "paper_shape", "voxels": [g.nz, g.nx], "nq": g.nq, "detector": [g.ndy, g.ndx],
                    "ne": g.ne, "triples_per_operator": trip, "operators": "direct (beyond the interval form)",
-                   "launch": lc},
-        "forward_ms": fwd, "adjoint_ms": adj, "adjoint_ms_unsplit": adj1,
+                   "launch": geo.get_launch()},
+        "default_launch": {"forward_ms": fwd, "adjoint_ms": adj, "adjoint_ms_unsplit": adj1},
+        "tuned_launch": {"shape": {k: tuned[k] for k in ("fwd_splits", "fwd_qw", "adj_qw", "adj_splits")},
+                         "forward_ms": fwd_t, "adjoint_ms": adj_t},
         "objective_first_last": [float(J[0]), float(J[-1])] if args.steps else None,
         "context": {"paper_table1_matlab_12core_s": {"forward_no_opt": 10516.88, "backward_no_opt": 10512.32,
                                                       "forward_sai": 319.45, "backward_sai": 1191.05}},
