@@ -118,8 +118,10 @@ __device__ void objective_block(const double *__restrict__ partL, int nL, const 
 }
 
 // VEC consecutive q nodes of one voxel per thread (VEC divides nq; 16-byte
-// loads and stores when VEC = 4).
-template <int VEC>
+// loads and stores when VEC = 4).  HUB = 0: the quadratic potential (delta
+// is not read), 1: Huber's.  Lemma 1's root takes one division: its
+// numerator and denominator are chosen first.
+template <int VEC, int HUB>
 __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const float *__restrict__ fh,
                                                 const float *__restrict__ b1,
                                                 const float *__restrict__ b2, double beta,
@@ -160,22 +162,27 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
         for (int k = 0; k < VEC; ++k) {
             const double fj = c[k];
             double s = 0.0, w = 0.0;
-            if (ix > 0) potential(fj - l[k], delta, R, s, w);
-            if (ix < nx - 1) potential(fj - r[k], delta, R, s, w);
-            if (iz > 0) potential(fj - u[k], delta, R, s, w);
-            if (iz < nz - 1) potential(fj - d[k], delta, R, s, w);
+            const double dl = HUB ? delta : 0.0;
+            if (ix > 0) potential(fj - l[k], dl, R, s, w);
+            if (ix < nx - 1) potential(fj - r[k], dl, R, s, w);
+            if (iz > 0) potential(fj - u[k], dl, R, s, w);
+            if (iz < nz - 1) potential(fj - d[k], dl, R, s, w);
             if (do_update) {
                 // b3 + b4 = 4 sum omega, b5 + b6 = 2 sum psi' (symmetric neighbourhood, w_jk = 1)
                 const double b34 = 4.0 * w;
                 const double chi1 = beta * b34;
                 const double chi2 = (double)vb1[k] + beta * (-fj * b34 + 2.0 * s);
                 const double chi3 = fj * (double)vb2[k];
-                double o;
                 const double disc = sqrt(chi2 * chi2 + 4.0 * chi1 * chi3);
-                if (chi2 > 0.0) o = 2.0 * chi3 / (chi2 + disc);
-                else if (chi1 > 0.0) o = (-chi2 + disc) / (2.0 * chi1);
-                else o = fj;
-                out[k] = (float)o;
+                double num = fj, den = 1.0;
+                if (chi2 > 0.0) {
+                    num = 2.0 * chi3;
+                    den = chi2 + disc;
+                } else if (chi1 > 0.0) {
+                    num = -chi2 + disc;
+                    den = 2.0 * chi1;
+                }
+                out[k] = (float)(num / den);
             }
         }
         if (do_update) {
@@ -315,12 +322,18 @@ static csx_status launch_update(csx_geometry *h, const float *f, const float *b1
     const int vec = update_vec(h, f, b1, b2, fout);
     const int nb = (int)((n + 256L * vec - 1) / (256L * vec));
     h->nbRu = nb;
-    if (vec == 4)
-        hipLaunchKernelGGL(k_update<4>, dim3(nb), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout, h->partR,
-                           do_update ? 1 : 0, h->psi_delta);
-    else
-        hipLaunchKernelGGL(k_update<1>, dim3(nb), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout, h->partR,
-                           do_update ? 1 : 0, h->psi_delta);
+#define CSX_UPD(V_, H_)                                                                                       \
+    hipLaunchKernelGGL((k_update<V_, H_>), dim3(nb), dim3(256), 0, s, P.nx, P.nz, P.nq, f, b1, b2, beta, fout, \
+                       h->partR, do_update ? 1 : 0, h->psi_delta)
+    const bool hub = h->psi_delta > 0.0;
+    if (vec == 4) {
+        if (hub) CSX_UPD(4, 1);
+        else CSX_UPD(4, 0);
+    } else {
+        if (hub) CSX_UPD(1, 1);
+        else CSX_UPD(1, 0);
+    }
+#undef CSX_UPD
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }
