@@ -1,6 +1,7 @@
 // csx_solver.hip -- the Poisson data term, the separable-surrogate update
 // and the float64 objective of the EM-type algorithm (Alg. 5; Sec. V; App. B).
 #include "csx_internal.h"
+#include "csx_update.h"
 
 #include <cmath>
 
@@ -64,34 +65,6 @@ __global__ void __launch_bounds__(256) k_ratio(int n, const float *__restrict__ 
     }
 }
 
-// ---------------------------------------------------------------------------
-// K4 separable-surrogate update (App. B, eq. f_update) for psi(t) = t^2/2,
-// 4 in-slice neighbours at the same q, unit weights; evaluated in float64:
-//   b3 + b4 = 4 |N_j|, b5 + b6 = 2 sum_k (fhat_j - fhat_k)
-//   chi1 = beta (b3+b4), chi2 = b1 + beta(-fhat (b3+b4) + b5 + b6), chi3 = fhat b2
-//   f = 2 chi3 / (chi2 + sqrt(chi2^2 + 4 chi1 chi3))       if chi2 > 0
-//     = (-chi2 + sqrt(chi2^2 + 4 chi1 chi3)) / (2 chi1)    if chi2 <= 0, chi1 > 0
-//     = fhat                                               otherwise (unseen voxel, beta = 0)
-// The first form is Lemma 1's root multiplied through by its conjugate.
-// Also accumulates R(fhat) = sum_j sum_k (fhat_j - fhat_k)^2 / 2 per block.
-// ---------------------------------------------------------------------------
-// Potential psi of the penalty at a neighbour difference d: adds psi(d) to R,
-// psi'(d) to s and omega(d) = psi'(d)/d to w.  delta <= 0: quadratic t^2/2;
-// delta > 0: Huber's potential (t^2/2 inside |t| <= delta, linear outside).
-__device__ __forceinline__ void potential(double d, double delta, double &R, double &s, double &w)
-{
-    const double ad = fabs(d);
-    if (delta <= 0.0 || ad <= delta) {
-        R += 0.5 * d * d;
-        s += d;
-        w += 1.0;
-    } else {
-        R += delta * ad - 0.5 * delta * delta;
-        s += d > 0.0 ? delta : -delta;
-        w += delta / ad;
-    }
-}
-
 // J = sum partL + beta * sum partR in a fixed order by one block, flags
 // combined (J = +inf when some y_i > 0 met a zero mean).
 __device__ void objective_block(const double *__restrict__ partL, int nL, const double *__restrict__ partR, int nR,
@@ -117,10 +90,14 @@ __device__ void objective_block(const double *__restrict__ partL, int nL, const 
     }
 }
 
+// ---------------------------------------------------------------------------
+// K4 separable-surrogate update (App. B, eq. f_update) with 4 in-slice
+// neighbours at the same q and unit weights, per element as in csx_update.h;
+// also accumulates R(fhat) = sum_j sum_k psi(fhat_j - fhat_k) per block.
+// ---------------------------------------------------------------------------
 // VEC consecutive q nodes of one voxel per thread (VEC divides nq; 16-byte
 // loads and stores when VEC = 4).  HUB = 0: the quadratic potential (delta
-// is not read), 1: Huber's.  Lemma 1's root takes one division: its
-// numerator and denominator are chosen first.
+// is not read), 1: Huber's.
 template <int VEC, int HUB>
 __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const float *__restrict__ fh,
                                                 const float *__restrict__ b1,
@@ -136,7 +113,7 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
         const int j = e0 / nq;
         const int ix = j % nx, iz = j / nx;
         const size_t row = (size_t)nx * nq;
-        float c[VEC], l[VEC], r[VEC], u[VEC], d[VEC];
+        float c[VEC], l[VEC] = {}, r[VEC] = {}, u[VEC] = {}, d[VEC] = {};
         auto ld = [&](const float *p, float (&v)[VEC]) {
             if constexpr (VEC == 4) {
                 const float4 t = *(const float4 *)p;
@@ -162,28 +139,8 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
         for (int k = 0; k < VEC; ++k) {
             const double fj = c[k];
             double s = 0.0, w = 0.0;
-            const double dl = HUB ? delta : 0.0;
-            if (ix > 0) potential(fj - l[k], dl, R, s, w);
-            if (ix < nx - 1) potential(fj - r[k], dl, R, s, w);
-            if (iz > 0) potential(fj - u[k], dl, R, s, w);
-            if (iz < nz - 1) potential(fj - d[k], dl, R, s, w);
-            if (do_update) {
-                // b3 + b4 = 4 sum omega, b5 + b6 = 2 sum psi' (symmetric neighbourhood, w_jk = 1)
-                const double b34 = 4.0 * w;
-                const double chi1 = beta * b34;
-                const double chi2 = (double)vb1[k] + beta * (-fj * b34 + 2.0 * s);
-                const double chi3 = fj * (double)vb2[k];
-                const double disc = sqrt(chi2 * chi2 + 4.0 * chi1 * chi3);
-                double num = fj, den = 1.0;
-                if (chi2 > 0.0) {
-                    num = 2.0 * chi3;
-                    den = chi2 + disc;
-                } else if (chi1 > 0.0) {
-                    num = -chi2 + disc;
-                    den = 2.0 * chi1;
-                }
-                out[k] = (float)(num / den);
-            }
+            neighbour_terms<HUB>(fj, l[k], r[k], u[k], d[k], ix, iz, nx, nz, delta, R, s, w);
+            if (do_update) out[k] = surrogate_root(fj, s, w, vb1[k], vb2[k], beta);
         }
         if (do_update) {
             if constexpr (VEC == 4) *(float4 *)(fout + e0) = make_float4(out[0], out[1], out[2], out[3]);
