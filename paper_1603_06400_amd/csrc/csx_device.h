@@ -175,10 +175,39 @@ __device__ __forceinline__ float bitf(uint32_t row, int col)
     return (float)((row >> col) & 1u);
 }
 
+// Lane exchanges of the butterfly below.  dpp_row<C>: the value of another
+// lane of the same 16-lane row (C = 0x100 + d: lane l + d, 0x110 + d: lane
+// l - d; lanes whose source is outside the row read 0).
+template <int C>
+__device__ __forceinline__ float dpp_row(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), C, 0xf, 0xf, true));
+}
+
+// One butterfly step at distance D for the pair (lo, hi): lanes with bit D
+// clear keep lo and add their partner's (lane l ^ D) lo, lanes with bit D set
+// keep hi and add their partner's hi.  D = 32 and 16 use gfx950's lane swaps
+// (lanes 32..63 of the first operand with lanes 0..31 of the second, and odd
+// 16-lane rows of the first with even rows of the second), smaller D row
+// shifts: no LDS traffic.
+template <int D>
+__device__ __forceinline__ float butterfly(float lo, float hi, bool up)
+{
+    if constexpr (D == 32 || D == 16) {
+        const auto r = D == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false)
+                               : __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+        const float tu = hi + dpp_row<0x110 + D>(hi);   // partner l - D
+        const float td = lo + dpp_row<0x100 + D>(lo);   // partner l + D
+        return up ? tu : td;
+    }
+}
+
 // Sum of v[0..N) over the 64 lanes of the wave, butterfly style: at each
 // distance d the lanes with bit d set keep the upper half of their values and
-// send the lower half to their partner (and vice versa), so after six steps
-// lane l holds the total for index l >> (6 - log2 N).
+// take their partner's (lane l ^ d) upper half, the others the lower halves,
+// so after six steps lane l holds the total for index l >> (6 - log2 N).
 template <int N, int D>
 struct WaveTransposeSum {
     static __device__ __forceinline__ void run(float *v, int lane)
@@ -189,14 +218,10 @@ struct WaveTransposeSum {
             constexpr int H = N / 2;
             const bool up = (lane & D) != 0;
 #pragma unroll
-            for (int i = 0; i < H; ++i) {
-                const float send = up ? v[i] : v[H + i];
-                const float keep = up ? v[H + i] : v[i];
-                v[i] = keep + __shfl_xor(send, D, 64);
-            }
+            for (int i = 0; i < H; ++i) v[i] = butterfly<D>(v[i], v[H + i], up);
             WaveTransposeSum<H, D / 2>::run(v, lane);
         } else {
-            v[0] += __shfl_xor(v[0], D, 64);
+            v[0] = butterfly<D>(v[0], v[0], (lane & D) != 0);
             WaveTransposeSum<1, D / 2>::run(v, lane);
         }
     }

@@ -83,10 +83,14 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
     stage_tables(P, T, (float *)(lds + L.phi), s_bits);
-    __syncthreads();
-    // wave-uniform (readfirstlane): the voxel records load into scalar registers
-    const int g = __builtin_amdgcn_readfirstlane(bx * (blockDim.x >> 6) + wv);
-    if (g >= P.n_groups) return;
+    // wave-uniform (readfirstlane): the voxel records load into scalar
+    // registers.  The wave's first global reads (voxel records, the first
+    // tile's detector values and records, the output node) are issued before
+    // the tables' barrier; a wave past the last group reads group 0's and
+    // leaves after it.
+    const int g_w = __builtin_amdgcn_readfirstlane(bx * (blockDim.x >> 6) + wv);
+    const bool live = g_w < P.n_groups;
+    const int g = live ? g_w : 0;
 
     int j, j2;
     if (LR) {
@@ -141,11 +145,18 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
     const int ntiles_all = ntx * ((half_y + 7) / 8);
     double rk = 0.0;
     float rA = 0.0f;
-    uint32_t rb = 0u;
+    uint32_t rb = 0u, rtm = 0u;
     auto load_rho = [&](int t) {
         int a, r;
         if (EN) return;                         // read per node from Psi
-        if (ST) rb = 0u;
+        if (ST) {
+            rb = 0u;
+            // the tile's node range: a superset of its lanes' ranges, from
+            // the store's tile record (wave-uniform)
+            if (QU && (P.ra_gs || !P.cls_list))
+                rtm = __builtin_amdgcn_readfirstlane(
+                    T.ram[P.ra_gs ? ((size_t)g * P.ra_gs + (size_t)t * 64) / 64 : (size_t)g * ntiles_all + t]);
+        }
         if (class_of(t, a, r)) {
             if (ST) {
                 // record of class (a, r): tile (r/8, a/8), lane 8 (r mod 8) + a mod 8,
@@ -178,8 +189,16 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
         b += (size_t)bz * P.nvox * P.nq;
     }
     if (tb < te) load_rho(tb);
+    // the lane's output node after the q reduction, and its q value
+    const int m_out = m0 + transposed_index<QW>(lane);
+    const bool writer = (lane & ((64 / QW) - 1)) == 0 && m_out < P.nq;
+    const float qm = writer ? T.qv[m_out] : 0.0f;
+    __syncthreads();
+    if (!live) return;
 
     for (int t = tb; t < te; ++t) {
+        const uint32_t tm_cur = rtm;   // the tile's node range (store), read ahead with its records
+        (void)tm_cur;
         int a = 0, r = 0;
         const bool has = class_of(t, a, r);
         double kap = 0.0;
@@ -286,19 +305,13 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
                 // the tile's node range (a superset of its lanes' ranges),
                 // wave-uniform: from the store's tile record, or reduced over
                 // the lanes for a class list
-                if (P.cls_list && P.ra_gs) {
-                    const uint32_t tm =
-                        __builtin_amdgcn_readfirstlane(T.ram[((size_t)g * P.ra_gs + (size_t)t * 64) / 64]);
-                    lo = (int)(tm & 0xffffu) - m0;
-                    hi = (int)(tm >> 16) - m0;
-                } else if (P.cls_list) {
+                if (P.cls_list && !P.ra_gs) {
                     if (act) band_range(P, u0, du, 0, QW, lo, hi);
                     lo = wave_min(lo);
                     hi = wave_max(hi);
                 } else {
-                    const uint32_t tm = __builtin_amdgcn_readfirstlane(T.ram[(size_t)g * ntiles_all + t]);
-                    lo = (int)(tm & 0xffffu) - m0;
-                    hi = (int)(tm >> 16) - m0;
+                    lo = (int)(tm_cur & 0xffffu) - m0;
+                    hi = (int)(tm_cur >> 16) - m0;
                 }
             } else if (act) {
                 band_range(P, u0, du, 0, QW, lo, hi);
@@ -358,14 +371,10 @@ __device__ __forceinline__ void adjoint_body(const KParams &P, const DevTables &
     }
     WaveTransposeSum<QW, 32>::run(acc0, lane);
     if (LR) WaveTransposeSum<QW, 32>::run(acc1, lane);
-    const int mi = transposed_index<QW>(lane);
-    const int m = m0 + mi;
     (void)qb_c;
-    const bool writer = (lane & ((64 / QW) - 1)) == 0;
-    if (writer && m < P.nq) {
-        const float qm = T.qv[m];
-        b[(size_t)j * P.nq + m] = acc0[0] * qm;
-        if (LR) b[(size_t)j2 * P.nq + m] = acc1[0] * qm;
+    if (writer) {
+        b[(size_t)j * P.nq + m_out] = acc0[0] * qm;
+        if (LR) b[(size_t)j2 * P.nq + m_out] = acc1[0] * qm;
     }
 }
 
