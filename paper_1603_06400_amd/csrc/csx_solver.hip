@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
         const int j = e0 / nq;
         const int ix = j % nx, iz = j / nx;
         const size_t row = (size_t)nx * nq;
-        float c[VEC], l[VEC] = {}, r[VEC] = {}, u[VEC] = {}, d[VEC] = {};
+        float c[VEC], l[VEC], r[VEC], u[VEC], d[VEC];
         auto ld = [&](const float *p, float (&v)[VEC]) {
             if constexpr (VEC == 4) {
                 const float4 t = *(const float4 *)p;
@@ -125,11 +125,13 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
                 v[0] = *p;
             }
         };
+        // a neighbour outside the grid reads the centre
         ld(fh + e0, c);
-        if (ix > 0) ld(fh + e0 - nq, l);
-        if (ix < nx - 1) ld(fh + e0 + nq, r);
-        if (iz > 0) ld(fh + e0 - row, u);
-        if (iz < nz - 1) ld(fh + e0 + row, d);
+        ld(fh + e0 - (ix > 0 ? nq : 0), l);
+        ld(fh + e0 + (ix < nx - 1 ? nq : 0), r);
+        ld(fh + e0 - (iz > 0 ? row : 0), u);
+        ld(fh + e0 + (iz < nz - 1 ? row : 0), d);
+        const int nin = (ix > 0) + (ix < nx - 1) + (iz > 0) + (iz < nz - 1);
         float vb1[VEC], vb2[VEC], out[VEC];
         if (do_update) {
             ld(b1 + e0, vb1);
@@ -139,7 +141,8 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
         for (int k = 0; k < VEC; ++k) {
             const double fj = c[k];
             double s = 0.0, w = 0.0;
-            neighbour_terms<HUB>(fj, l[k], r[k], u[k], d[k], ix, iz, nx, nz, delta, R, s, w);
+            if (HUB) neighbour_terms<1>(fj, l[k], r[k], u[k], d[k], ix, iz, nx, nz, delta, R, s, w);
+            else neighbour_terms_quad(fj, l[k], r[k], u[k], d[k], nin, R, s, w);
             if (do_update) out[k] = surrogate_root(fj, s, w, vb1[k], vb2[k], beta);
         }
         if (do_update) {

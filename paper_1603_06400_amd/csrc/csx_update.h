@@ -38,6 +38,24 @@ __device__ __forceinline__ void neighbour_terms(double fj, float l, float r, flo
     if (iz < nz - 1) potential<HUB>(fj - d, delta, R, s, w);
 }
 
+// The quadratic potential over the 4 neighbours, branch-free: a neighbour
+// outside the grid is given the centre value (difference 0 adds nothing to R
+// or s) and w is the number inside, nin.  Same sums as neighbour_terms<0>.
+__device__ __forceinline__ void neighbour_terms_quad(double fj, float l, float r, float u, float d, int nin, double &R,
+                                                     double &s, double &w)
+{
+    const double dl = fj - l, dr = fj - r, du = fj - u, dd = fj - d;
+    R += 0.5 * dl * dl;
+    R += 0.5 * dr * dr;
+    R += 0.5 * du * du;
+    R += 0.5 * dd * dd;
+    s += dl;
+    s += dr;
+    s += du;
+    s += dd;
+    w += (double)nin;
+}
+
 // Lemma 1's root for one element, unit weights over a symmetric neighbourhood:
 //   b3 + b4 = 4 sum omega, b5 + b6 = 2 sum psi'
 //   chi1 = beta (b3+b4), chi2 = b1 + beta(-fhat (b3+b4) + b5 + b6), chi3 = fhat b2
