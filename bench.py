@@ -332,10 +332,11 @@ def bench_paper(args):
     """The paper's simulation shape (Sec. VII): 28^2 voxels x 79 q, a 1536 x
     2048 detector of 0.19 mm pixels, stand-ins for the spectrum and mask, the
     two-vial phantom.  Beyond the interval form's limits, so the direct
-    operators run; the adjoint splits its pixel classes into tile ranges.  A
-    step is one Alg. 5 iteration (Poisson counts around the phantom's forward,
-    peak mean 1e4), timed with the autotuner's launch shape.  Context: the paper's Table 1 times this shape's operators
-    in MATLAB on a 12-core CPU."""
+    operators run, reading the factor store (22.8 GB, built at init); the
+    adjoint splits its pixel classes into tile ranges.  A step is one Alg. 5
+    iteration (Poisson counts around the phantom's forward, peak mean 1e4),
+    timed with the autotuner's launch shape.  Context: the paper's Table 1
+    times this shape's operators in MATLAB on a 12-core CPU."""
     import torch
 
     from paper_1603_06400_amd import csx, inputs
@@ -395,6 +396,7 @@ def bench_paper(args):
         "config": {"workload": "paper_shape", "voxels": [g.nz, g.nx], "nq": g.nq, "detector": [g.ndy, g.ndx],
                    "ne": g.ne, "triples_per_operator": trip, "operators": "direct (beyond the interval form)",
                    "launch": geo.get_launch()},
+        "factor_store": geo.factor_store(),
         "default_launch": {"forward_ms": fwd, "adjoint_ms": adj, "adjoint_ms_unsplit": adj1},
         "tuned_launch": {"shape": {k: tuned[k] for k in ("fwd_splits", "fwd_qw", "adj_qw", "adj_splits")},
                          "forward_ms": fwd_t, "adjoint_ms": adj_t},

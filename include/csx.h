@@ -124,14 +124,16 @@ csx_status csx_get_info(const csx_geometry *h, csx_info *out);
  * adjoint class record, 32 per forward record: 2.1 GB at 128^2 voxels x
  * 128^2 pixels).  The values are those the operators compute on the fly, by
  * the same code; results agree with the on-the-fly operators to float32
- * rounding.  Needs a uniform q grid.  csx_init_geometry builds the store
- * when it needs at most CSX_STORE_AUTO_BYTES and a quarter of the device's
- * free memory.  on = 1 builds it (CSX_ENOMEM if the allocation fails,
+ * rounding.  Needs a uniform q grid whose zero-padded spectrum table (every
+ * bin coordinate kappa q_m / dE + b0 an in-band class can reach at any node)
+ * fits 8192 entries.  csx_init_geometry builds the store when it needs at
+ * most CSX_STORE_AUTO_BYTES and a quarter of the device's free memory
+ * (the paper's 28^2 x 79 q shape with its 1536 x 2048 detector: 22.8 GB).  on = 1 builds it (CSX_ENOMEM if the allocation fails,
  * CSX_EINVAL on a non-uniform q grid), on = 0 releases it; both synchronise
  * the device.  The batched, ordered-subsets and warm-start paths use the
  * store of each handle that has one; the energy-resolved and interpolated
  * operators do not read it. */
-#define CSX_STORE_AUTO_BYTES (4LL << 30)
+#define CSX_STORE_AUTO_BYTES (32LL << 30)
 csx_status csx_set_factor_store(csx_geometry *h, int on);
 
 /* Whether the handle holds a factor store, its device bytes and the time its

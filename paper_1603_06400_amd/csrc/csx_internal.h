@@ -14,7 +14,7 @@
 #define CSX_MAX_MASK_PERIOD 32
 #define CSX_SUM_BLOCKS 256
 #define CSX_LDS_MAX (160 * 1024)   // LDS bytes one workgroup may use on gfx950
-#define CSX_SPEC_MAX 2048          // largest padded spectrum table in LDS (floats)
+#define CSX_SPEC_MAX 8192          // largest padded spectrum table in LDS (floats, 32 KB)
 
 csx_status csx_fail(csx_status s, const std::string &msg);
 

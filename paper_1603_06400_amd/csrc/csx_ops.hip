@@ -1591,7 +1591,11 @@ int csx_default_adj_splits(const KParams &P, int adj_qw)
     const long qchunks = (P.nq + adj_qw - 1) / adj_qw;
     const long waves = std::max(1L, (long)P.n_groups * qchunks);
     const long ntiles = (long)((P.ndx + 7) / 8) * ((P.ndy / 2 + 7) / 8);
-    long sp = (4L * 4 * 256 + waves - 1) / waves;
+    // a launch of fewer than ~4 waves per SIMD (few voxel groups, e.g. the
+    // paper's 28^2 voxels) is split to ~12: its waves are long (many class
+    // tiles each), so more of them in flight hide their latencies
+    if (waves >= 4L * 4 * 256) return 1;
+    long sp = (12L * 4 * 256 + waves - 1) / waves;
     sp = std::min(sp, std::max(1L, ntiles / 4));
     return (int)std::max(1L, std::min(sp, 64L));
 }
@@ -1600,15 +1604,26 @@ csx_launch csx_default_launch(const KParams &P)
 {
     csx_launch lc;
     const int qw = P.nq <= 16 ? 16 : (P.nq <= 32 ? 32 : 64);
-    lc.fwd_qw = qw;
     lc.adj_qw = qw;
-    const int qchunks = (P.nq + qw - 1) / qw;
+    // the forward's q chunk: narrower when its two q f tiles beside a long
+    // spectrum table would leave room for only one 512-thread block per
+    // compute unit
+    int fq = qw;
+    while (fq > 16) {
+        KParams Q = P;
+        Q.qw = fq;
+        if (lds_layout(Q, true).total <= CSX_LDS_MAX / 2) break;
+        fq /= 2;
+    }
+    lc.fwd_qw = fq;
+    const int qchunks = (P.nq + fq - 1) / fq;
     // split the voxel tiles so that a forward launch holds >= ~8 waves per SIMD,
-    // and into at least 8 ranges: with the XCD-aware block numbering each XCD
-    // then reads one eighth of f into its L2
+    // and, when f is larger than 1 MB, into at least 8 ranges: with the
+    // XCD-aware block numbering each XCD then reads one eighth of f into its L2
     const int bx = (P.n_quad + 7) / 8;
     const int target_waves = 8 * 4 * 256;
-    int splits = std::max(8, target_waves / std::max(1, bx * 8 * qchunks));
+    const int min_splits = (long)P.nvox * P.nq * 4 > (1L << 20) ? 8 : 1;
+    int splits = std::max(min_splits, target_waves / std::max(1, bx * 8 * qchunks));
     splits = std::min(splits, std::max(1, fwd_tiles(P) / 2));
     lc.fwd_splits = std::min(splits, 64);
     lc.adj_splits = csx_default_adj_splits(P, lc.adj_qw);
