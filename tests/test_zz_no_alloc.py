@@ -47,12 +47,15 @@ def test_noalloc_forward_equals_forward_on_consecutive_calls():
 
 
 def test_noalloc_forward_refuses_partials_beyond_the_scratch():
-    # 32 x 40 voxels (10 voxel tiles, 5 splits) against a 1024^2 detector:
-    # 5 partial images of 2^20 pixels, more than the 2^22-float scratch (the
-    # detector is too large for the interval form, so the direct forward runs)
+    # 32 x 40 voxels (10 voxel tiles) against a 1024^2 detector, the forward
+    # split 5 ways: 5 partial images of 2^20 pixels, more than the 2^22-float
+    # scratch (the detector is too large for the interval form, so the direct
+    # forward runs)
     g = inputs.standard_geometry(32, 16, ndet=1024).with_(nz=40)
     geo = csx.Geometry(g)
     assert not geo.interval_operators()["on"]
+    lc = geo.get_launch()
+    geo.set_launch(5, lc["fwd_qw"], lc["adj_qw"])
     parts = geo.get_launch()["fwd_splits"] * geo.npix
     assert parts > csx.SCRATCH_FLOATS, parts
     f = _image(geo, 5)
