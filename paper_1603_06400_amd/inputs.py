@@ -181,9 +181,12 @@ def random_detector(geom: ScanGeometry, seed: int, lo: float = 0.0, hi: float = 
 
 
 def poisson_counts(mean: np.ndarray, seed: int) -> np.ndarray:
-    """Integer Poisson counts with the given mean (returned as float64)."""
+    """Integer Poisson counts with the given mean (returned as float64).  A
+    mean below zero counts as zero: a float32 forward of a nonnegative image
+    can return -1e-15 of its maximum where the exact value is 0 (the interval
+    form takes differences of prefix sums).  NaN still raises."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return rng.poisson(np.asarray(mean, dtype=np.float64)).astype(np.float64)
+    return rng.poisson(np.maximum(np.asarray(mean, dtype=np.float64), 0.0)).astype(np.float64)
 
 
 # ----------------------------------------------------------------------------

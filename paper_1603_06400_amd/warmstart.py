@@ -338,7 +338,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-eval", type=int, default=200)
-    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--iters", type=int, default=50, help="plain iterations whose objective is the target")
+    ap.add_argument("--target-iters", type=int, default=0,
+                    help="iterations of the reconstructions the network is trained on (default: --iters)")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -363,7 +365,8 @@ def main(argv=None):
         t_pairs = t_train = 0.0
     else:
         t0 = time.perf_counter()
-        X, T = make_pairs(geo, inputs.warm_cases("train", args.n_train), args.iters, w.beta, args.delta, log)
+        t_iters = args.target_iters or args.iters
+        X, T = make_pairs(geo, inputs.warm_cases("train", args.n_train), t_iters, w.beta, args.delta, log)
         t_pairs = time.perf_counter() - t0
         net = WarmNet.init(args.seed, args.delta)
         t0 = time.perf_counter()
@@ -371,7 +374,8 @@ def main(argv=None):
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         del X, T
-        meta = {"n_train": args.n_train, "iters": args.iters, "epochs": args.epochs, "batch": args.batch,
+        meta = {"n_train": args.n_train, "iters": args.iters, "target_iters": t_iters, "epochs": args.epochs,
+                "batch": args.batch,
                 "lr": args.lr, "seed": args.seed, "loss": hist, "beta": w.beta, "delta": args.delta}
         net.save(os.path.join(args.out, "warm_slice128.npz"), meta)
     rows = evaluate(geo, net, inputs.warm_cases("eval", args.n_eval), args.iters, w.beta, args.k_judge, log=log)
