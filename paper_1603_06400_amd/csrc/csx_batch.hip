@@ -5,10 +5,8 @@
 // single adjoint launch that cover every active scan's blocks (largest scans
 // first, so the small scans fill the tail), plus the per-scan float64
 // data-term, update and objective kernels.  Scans whose operators take the
-// interval form (csx_interval.hip) launch them per scan; those scans are
-// dealt (largest first, onto the least loaded) to BT_SIDE side streams forked
-// from and joined back into the private stream, so that the short launches of
-// small scans overlap one another.  The iteration is captured into a
+// interval form (csx_interval.hip) launch them per scan: each of those
+// launches already spans every compute unit.  The iteration is captured into a
 // HIP graph on a private stream and replayed; the objective kernels index the
 // J history through a device iteration counter, so the replays need no host
 // work.  Scans may have their own iteration counts: the run goes in stages
@@ -41,15 +39,11 @@ double scan_cost(const csx_geometry *h)
 
 }  // namespace
 
-constexpr int BT_SIDE = 4;   // side streams of the interval-form scans (2: 7.38, 4: 6.91, 8: 6.96 ms at batch64)
-
 struct csx_batch {
     std::vector<csx_geometry *> h;
     std::vector<Group> fwd, adj;
     hipStream_t st = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipStream_t side[BT_SIDE] = {};
-    hipEvent_t ev_fork = nullptr, ev_join[BT_SIDE] = {};
     int *iter_dev = nullptr;
     double *J_dev = nullptr;
     size_t J_cap = 0;
@@ -74,11 +68,6 @@ extern "C" void csx_batch_free(csx_batch *b)
     if (b->J_dev) (void)hipFree(b->J_dev);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
-    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-    for (int i = 0; i < BT_SIDE; ++i) {
-        if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
-        if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
-    }
     if (b->st) (void)hipStreamDestroy(b->st);
     delete b;
 }
@@ -180,13 +169,8 @@ extern "C" csx_status csx_batch_create(csx_geometry *const *scans, int n, csx_ba
     if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipMalloc((void **)&b->iter_dev, sizeof(int)) != hipSuccess)
         return bail(csx_fail(CSX_EHIP, "batch stream / events / counter"));
-    for (int i = 0; i < BT_SIDE; ++i)
-        if (hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming) != hipSuccess)
-            return bail(csx_fail(CSX_EHIP, "batch side streams / events"));
     *out = b;
     return CSX_OK;
 }
@@ -196,50 +180,23 @@ static csx_status issue_iteration(csx_batch *b, const std::vector<int> &active, 
                                   const float *const *r, float *const *f, double beta, size_t jstride,
                                   hipStream_t s)
 {
-    // the interval-form scans, dealt to the side streams by cost
-    std::vector<int> ivs;
-    for (int k : active)
-        if (b->h[k]->iv) ivs.push_back(k);
-    std::stable_sort(ivs.begin(), ivs.end(),
-                     [&](int a, int c) { return scan_cost(b->h[a]) > scan_cost(b->h[c]); });
-    const int nside = std::min<int>(BT_SIDE, (int)ivs.size());
-    std::vector<std::vector<int>> lane(nside);
-    std::vector<double> load(nside, 0.0);
-    for (int k : ivs) {
-        const int i = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        lane[i].push_back(k);
-        load[i] += scan_cost(b->h[k]);
-    }
-    if (nside > 0) HIP_TRY(hipEventRecord(b->ev_fork, s));
-    for (int i = 0; i < nside; ++i) {
-        hipStream_t si = b->side[i];
-        HIP_TRY(hipStreamWaitEvent(si, b->ev_fork, 0));
-        for (int k : lane[i]) {
-            csx_geometry *h = b->h[k];
-            BT_TRY(csx_iv_forward(h, f[k], nullptr, 0, h->gws, si));
-            BT_TRY(csx_launch_ratio(h, y[k], r ? r[k] : nullptr, true, si));
-            BT_TRY(csx_iv_adjoint(h, h->rho, h->b2, si));
-            BT_TRY(csx_launch_update(h, f[k], beta, true, si));
-            BT_TRY(csx_launch_copy_objective(h, f[k], beta, b->J_dev + k * jstride, b->iter_dev, si));
-        }
-        HIP_TRY(hipEventRecord(b->ev_join[i], si));
-    }
-    // the scans on the direct operators: merged launches on the private stream
     for (const Group &g : b->fwd) BT_TRY(launch_group(g, true, s));
     for (int k : active) {
         csx_geometry *h = b->h[k];
-        if (h->iv) continue;
-        BT_TRY(csx_launch_sum_parts(h, csx_forward_shape(h).nparts, h->gws, s));
+        if (h->iv)
+            BT_TRY(csx_iv_forward(h, f[k], nullptr, 0, h->gws, s));
+        else
+            BT_TRY(csx_launch_sum_parts(h, csx_forward_shape(h).nparts, h->gws, s));
         BT_TRY(csx_launch_ratio(h, y[k], r ? r[k] : nullptr, true, s));
     }
     for (const Group &g : b->adj) BT_TRY(launch_group(g, false, s));
+    for (int k : active)
+        if (b->h[k]->iv) BT_TRY(csx_iv_adjoint(b->h[k], b->h[k]->rho, b->h[k]->b2, s));
     for (int k : active) {
         csx_geometry *h = b->h[k];
-        if (h->iv) continue;
         BT_TRY(csx_launch_update(h, f[k], beta, true, s));
         BT_TRY(csx_launch_copy_objective(h, f[k], beta, b->J_dev + k * jstride, b->iter_dev, s));
     }
-    for (int i = 0; i < nside; ++i) HIP_TRY(hipStreamWaitEvent(s, b->ev_join[i], 0));
     return csx_launch_iter_incr(b->iter_dev, s);
 }
 
@@ -298,6 +255,10 @@ static csx_status replay(csx_batch *b, const std::vector<int> &active, const flo
         return csx_fail(CSX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
     for (int t = 0; t < steps && e == hipSuccess; ++t) e = hipGraphLaunch(exec, s);
+    // the executable graph (and the streams the runtime gives its parallel
+    // branches) is destroyed only once its launches have finished
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
     (void)hipGraphExecDestroy(exec);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return csx_fail(CSX_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
