@@ -19,7 +19,7 @@ Every step runs in the HIP library: convolutions on the matrix cores
 (binary16 operands, float32 accumulation), loss, Adam, the input and output
 maps and the solver.  This module holds device buffers and sequences calls.
 
-    python -m paper_1603_06400_amd.warmstart --n-train 2000 --n-eval 200 --out DIR
+    python -m paper_1603_06400_amd.warmstart --n-train 2000 --target-iters 300 --n-eval 200 --out DIR
 """
 from __future__ import annotations
 
@@ -36,6 +36,7 @@ import torch
 from . import csx, inputs
 
 CHANNELS = inputs.WARM_CHANNELS
+BATCH_CHUNK_MAX = 4          # scans per batch in evaluate_batched (the size every measured run used)
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warm_slice128.npz")
 
 
@@ -240,7 +241,12 @@ def evaluate_batched(g, net: WarmNet, cases, n_iter: int, beta: float, k_judge: 
     solver run case after case (each for the iterations it needs) against the
     warm path batched over `chunk` scans at a time (network per scan, the judge
     as two batched k-iteration runs, then one batched continuation in which
-    each scan runs the iterations it needs)."""
+    each scan runs the iterations it needs).  At most BATCH_CHUNK_MAX scans
+    per batch: with the batch's scans on parallel graph branches (since taken
+    out), 25-scan batches ended the process with a segmentation fault whose
+    cause is not found, and they stay off until it is."""
+    if min(chunk, len(cases)) > BATCH_CHUNK_MAX:
+        raise ValueError(f"batched warm evaluation takes at most {BATCH_CHUNK_MAX} scans per batch")
     geos = [csx.Geometry(g) for _ in range(min(chunk, len(cases)))]
     batch = csx.Batch(geos)
     t_plain = t_warm = 0.0
@@ -298,7 +304,8 @@ def evaluate_batched(g, net: WarmNet, cases, n_iter: int, beta: float, k_judge: 
     return {"cases": len(cases), "chunk": chunk, "k_judge": k_judge, "rel": rel,
             "total_s_plain_sequential": t_plain, "total_s_warm_batched": t_warm,
             "speedup_total": t_plain / t_warm, "accept_rate": accepted / len(cases),
-            "iters_plain_mean": float(np.mean(iters_plain)), "iters_warm_mean": float(np.mean(iters_warm))}
+            "iters_plain_mean": float(np.mean(iters_plain)), "iters_warm_mean": float(np.mean(iters_warm)),
+            "iters_plain_per_case": [int(n) for n in iters_plain], "iters_warm_per_case": [int(n) for n in iters_warm]}
 
 
 def summarize(rows) -> dict:
