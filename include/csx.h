@@ -341,17 +341,21 @@ csx_status csx_valu_peak(double *lane_ops_per_s, void *stream);
  *               (1..64); partial images are summed in a fixed order.  Blocks
  *               are numbered so that each of the 8 XCDs takes a contiguous
  *               share of the splits: with a multiple of 8 each XCD's L2 holds
- *               only its share of f.  Default: at least 8.
+ *               only its share of f.  Default: enough block rows for about
+ *               8 waves per SIMD, and at least 8 when f is larger than 1 MB.
  *   fwd_qw, adj_qw: q lanes per chunk of the forward / adjoint (16, 32 or 64);
- *               nq is covered by ceil(nq / qw) chunks.
+ *               nq is covered by ceil(nq / qw) chunks.  Default: the
+ *               smallest width covering nq, at most 64; the forward's is
+ *               halved while its LDS (two q f tiles beside the spectrum
+ *               table) would exceed half of a compute unit's.
  *   adj_splits: the direct adjoint's pixel classes are split into this many
  *               contiguous tile ranges (1..64), one wave per voxel group, q
  *               chunk and range, the ranges' partial images summed in a fixed
  *               order: with few voxel groups (a small voxel grid) the adjoint
  *               otherwise holds too few waves to fill the device.  0 in
- *               csx_set_launch: the default, enough ranges for about 4 waves
- *               per SIMD.  The interval form, batches and subsets do not
- *               split. */
+ *               csx_set_launch: the default, 1 when the unsplit launch holds
+ *               at least 4 waves per SIMD, else enough ranges for about 12.
+ *               The interval form, batches and subsets do not split. */
 typedef struct {
     int fwd_splits;
     int fwd_qw;

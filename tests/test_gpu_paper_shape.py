@@ -35,8 +35,14 @@ def test_paper_shape_runs_the_split_direct_adjoint(paper):
     g, geo = paper
     assert not geo.interval_operators()["on"]
     lc = geo.get_launch()
-    print(f"[paper shape: launch {lc}]", flush=True)
+    st = geo.factor_store()
+    print(f"[paper shape: launch {lc}, factor store {st['bytes'] / 2**30:.1f} GiB in {st['build_ms']:.1f} ms]",
+          flush=True)
     assert lc["adj_splits"] > 1
+    # the uniform-q path with its factor store; the forward's q chunk narrowed
+    # beside the 19.6 KB spectrum table; f is small, so no voxel split
+    assert st["on"]
+    assert lc["fwd_qw"] <= 32 and lc["fwd_splits"] == 1
 
 
 def test_paper_shape_forward_sampled(oracle_mod, paper):
