@@ -6,7 +6,10 @@
 // first, so the small scans fill the tail), plus the per-scan float64
 // data-term, update and objective kernels.  Scans whose operators take the
 // interval form (csx_interval.hip) launch them per scan: each of those
-// launches already spans every compute unit.  The iteration is captured into a
+// launches already spans every compute unit.  Their elementwise work (the sum
+// of the forward's partial images, the count ratio, the update and the
+// copy-back with the objective) runs in one launch per kernel covering every
+// such scan (ElemJob tables).  The iteration is captured into a
 // HIP graph on a private stream and replayed; the objective kernels index the
 // J history through a device iteration counter, so the replays need no host
 // work.  Scans may have their own iteration counts: the run goes in stages
@@ -47,6 +50,15 @@ struct csx_batch {
     int *iter_dev = nullptr;
     double *J_dev = nullptr;
     size_t J_cap = 0;
+    // the interval-form scans' batched elementwise launches: jobs and, per
+    // launch (sum, ratio, update, copy-back), each job's first block
+    bool elem = false;
+    int elem_hub = 0;
+    std::vector<ElemJob> ej;
+    std::vector<int> eb;          // [4][n]
+    int enb[4] = {0, 0, 0, 0};
+    ElemJob *ej_dev = nullptr;
+    int *eb_dev = nullptr;
 };
 
 static void free_groups(std::vector<Group> &gs)
@@ -65,6 +77,8 @@ extern "C" void csx_batch_free(csx_batch *b)
     free_groups(b->fwd);
     free_groups(b->adj);
     if (b->iter_dev) (void)hipFree(b->iter_dev);
+    if (b->ej_dev) (void)hipFree(b->ej_dev);
+    if (b->eb_dev) (void)hipFree(b->eb_dev);
     if (b->J_dev) (void)hipFree(b->J_dev);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -169,8 +183,10 @@ extern "C" csx_status csx_batch_create(csx_geometry *const *scans, int n, csx_ba
     if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc((void **)&b->iter_dev, sizeof(int)) != hipSuccess)
-        return bail(csx_fail(CSX_EHIP, "batch stream / events / counter"));
+        hipMalloc((void **)&b->iter_dev, sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&b->ej_dev, sizeof(ElemJob) * n) != hipSuccess ||
+        hipMalloc((void **)&b->eb_dev, sizeof(int) * 4 * n) != hipSuccess)
+        return bail(csx_fail(CSX_EHIP, "batch stream / events / counter / job tables"));
     *out = b;
     return CSX_OK;
 }
@@ -180,24 +196,108 @@ static csx_status issue_iteration(csx_batch *b, const std::vector<int> &active, 
                                   const float *const *r, float *const *f, double beta, size_t jstride,
                                   hipStream_t s)
 {
+    const int n = (int)b->h.size(), nj = (int)b->ej.size();
     for (const Group &g : b->fwd) BT_TRY(launch_group(g, true, s));
     for (int k : active) {
         csx_geometry *h = b->h[k];
+        if (h->iv && b->elem) {
+            BT_TRY(csx_iv_forward_parts(h, f[k], s));
+            continue;
+        }
         if (h->iv)
             BT_TRY(csx_iv_forward(h, f[k], nullptr, 0, h->gws, s));
         else
             BT_TRY(csx_launch_sum_parts(h, csx_forward_shape(h).nparts, h->gws, s));
         BT_TRY(csx_launch_ratio(h, y[k], r ? r[k] : nullptr, true, s));
     }
+    if (b->elem) {
+        BT_TRY(csx_launch_iv_sum_batch(b->ej_dev, b->eb_dev, nj, b->enb[0], s));
+        BT_TRY(csx_launch_elem_batch(0, b->ej_dev, b->eb_dev + n, nj, b->enb[1], beta, 0, nullptr, s));
+    }
     for (const Group &g : b->adj) BT_TRY(launch_group(g, false, s));
     for (int k : active)
         if (b->h[k]->iv) BT_TRY(csx_iv_adjoint(b->h[k], b->h[k]->rho, b->h[k]->b2, s));
+    if (b->elem) {
+        BT_TRY(csx_launch_elem_batch(1, b->ej_dev, b->eb_dev + 2 * n, nj, b->enb[2], beta, b->elem_hub, nullptr, s));
+        BT_TRY(csx_launch_elem_batch(2, b->ej_dev, b->eb_dev + 3 * n, nj, b->enb[3], beta, 0, b->iter_dev, s));
+    }
     for (int k : active) {
         csx_geometry *h = b->h[k];
+        if (h->iv && b->elem) continue;
         BT_TRY(csx_launch_update(h, f[k], beta, true, s));
         BT_TRY(csx_launch_copy_objective(h, f[k], beta, b->J_dev + k * jstride, b->iter_dev, s));
     }
     return csx_launch_iter_incr(b->iter_dev, s);
+}
+
+// The ElemJob tables of the active interval-form scans for this call's
+// buffers, when every such scan takes the 4-node update and the 16-byte copy
+// (nq % 4 == 0, aligned images) and all use one penalty; else those scans
+// keep their single-scan launches.
+static csx_status elem_jobs(csx_batch *b, const std::vector<int> &active, const float *const *y,
+                            const float *const *r, float *const *f, size_t jstride, hipStream_t s)
+{
+    b->elem = false;
+    b->ej.clear();
+    const int n = (int)b->h.size();
+    std::vector<int> ivs;
+    for (int k : active)
+        if (b->h[k]->iv) ivs.push_back(k);
+    if (ivs.empty()) return CSX_OK;
+    int hub = -1;
+    for (int k : ivs) {
+        const csx_geometry *h = b->h[k];
+        const long ne = (long)h->P.nvox * h->P.nq;
+        const uintptr_t al = (uintptr_t)f[k] | (uintptr_t)h->b1 | (uintptr_t)h->b2 | (uintptr_t)h->ftmp;
+        const int hk = h->psi_delta > 0.0 ? 1 : 0;
+        if (h->P.nq % 4 != 0 || ne % 4 != 0 || (al & 15) != 0 || (hub >= 0 && hk != hub)) return CSX_OK;
+        hub = hk;
+    }
+    b->eb.assign(4 * (size_t)n, 0);
+    int nb[4] = {0, 0, 0, 0};
+    for (size_t i = 0; i < ivs.size(); ++i) {
+        const int k = ivs[i];
+        csx_geometry *h = b->h[k];
+        const KParams &P = h->P;
+        const int ne = P.nvox * P.nq;
+        ElemJob J;
+        std::memset(&J, 0, sizeof(J));
+        csx_iv_parts(h, &J.part, &J.nparts);
+        J.npix = P.npix;
+        J.g = h->gws;
+        J.y = y[k];
+        J.r = r ? r[k] : nullptr;
+        J.rho = h->rho;
+        J.partL = h->partL;
+        J.partF = h->partF;
+        J.nx = P.nx;
+        J.nz = P.nz;
+        J.nq = P.nq;
+        J.f = f[k];
+        J.b1 = h->b1;
+        J.b2 = h->b2;
+        J.ftmp = h->ftmp;
+        J.partR = h->partR;
+        J.delta = h->psi_delta;
+        J.fdst = f[k];
+        J.nL = h->nbL;
+        J.nR = (ne / 4 + 255) / 256;   // the update's blocks (4 nodes per thread)
+        h->nbRu = J.nR;
+        J.flags = h->flags;
+        J.J = b->J_dev + (size_t)k * jstride;
+        const int blocks[4] = {(P.npix + 63) / 64, h->nbL, J.nR, (ne / 4 + 255) / 256 + 1};
+        for (int w = 0; w < 4; ++w) {
+            b->eb[(size_t)w * n + i] = nb[w];
+            nb[w] += blocks[w];
+        }
+        b->ej.push_back(J);
+    }
+    for (int w = 0; w < 4; ++w) b->enb[w] = nb[w];
+    HIP_TRY(hipMemcpyAsync(b->ej_dev, b->ej.data(), sizeof(ElemJob) * b->ej.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->eb_dev, b->eb.data(), sizeof(int) * b->eb.size(), hipMemcpyHostToDevice, s));
+    b->elem = true;
+    b->elem_hub = hub;
+    return CSX_OK;
 }
 
 // J at scan k's current iterate, stored at its iteration counter (single-scan
@@ -338,6 +438,7 @@ extern "C" csx_status csx_batch_recon_n(csx_batch *b, const float *const *y, con
                 if (n_iter[k] >= c) active.push_back(k);
             HIP_TRY(hipStreamSynchronize(s));   // the previous job tables may still be read
             BT_TRY(regroup(b, active, f, s));
+            BT_TRY(elem_jobs(b, active, y, r, f, jstride, s));
             BT_TRY(replay(b, active, y, r, f, beta, jstride, c - done, s));
             done = c;
         }

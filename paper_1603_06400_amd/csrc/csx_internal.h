@@ -222,6 +222,39 @@ void csx_iv_free(csx_geometry *h);
 csx_status csx_iv_forward(const csx_geometry *h, const float *f, float *part, size_t part_cap, float *g,
                           hipStream_t s);
 csx_status csx_iv_adjoint(const csx_geometry *h, const float *rho, float *b, hipStream_t s);
+// The interval forward's kernel alone (its partial images into the handle's
+// buffer); csx_iv_parts gives that buffer and its image count.
+csx_status csx_iv_forward_parts(const csx_geometry *h, const float *f, hipStream_t s);
+void csx_iv_parts(const csx_geometry *h, const float **part, int *nparts);
+
+// One scan's share of the batched elementwise launches: the sum of its
+// interval forward's partial images into g, the count ratio, the update
+// (4 q nodes per thread) into ftmp and the copy-back into f with the
+// objective at J[*iter].  Each launch covers every job's blocks (job k's from
+// begin[k]), each block doing what the single-scan launch's block of the same
+// index does, so results are bitwise those of the single-scan launches.
+struct ElemJob {
+    const float *part;
+    int nparts, npix;
+    float *g;
+    const float *y, *r;
+    float *rho;
+    double *partL;
+    int *partF;
+    int nx, nz, nq;
+    const float *f, *b1, *b2;
+    float *ftmp;
+    double *partR;
+    double delta;
+    float *fdst;
+    int nL, nR;
+    int *flags;
+    double *J;
+};
+csx_status csx_launch_iv_sum_batch(const ElemJob *jobs, const int *begin, int njobs, int nblocks, hipStream_t s);
+// which: 0 ratio, 1 update (hub: Huber's potential), 2 copy-back + objective
+csx_status csx_launch_elem_batch(int which, const ElemJob *jobs, const int *begin, int njobs, int nblocks, double beta,
+                                 int hub, const int *iter, hipStream_t s);
 size_t csx_iv_part_floats(const csx_geometry *h);
 void csx_iv_info(const csx_geometry *h, int *on, int64_t *bytes, double *build_ms, int *intervals);
 // factor store: record counts (16-byte adjoint records, 32-byte forward

@@ -588,13 +588,12 @@ __global__ void __launch_bounds__(IV_THREADS) k_iv_forward(KParams P, IvArgs V, 
 
 // g_i = sum_p part[p][i] in a fixed order: 64 pixels per block (the lanes),
 // 16 slices of the partial images (the waves), each slice's loads issued
-// together, then the 16 slice sums added in slice order.
-__global__ void __launch_bounds__(1024) k_iv_sum(const float *__restrict__ part, int nparts, int n,
-                                                 float *__restrict__ g)
+// together, then the 16 slice sums added in slice order.  bx: the block.
+__device__ __forceinline__ void iv_sum_body(const float *__restrict__ part, int nparts, int n, float *__restrict__ g,
+                                            int bx, float (*s_part)[64])
 {
-    __shared__ float s_part[16][64];
     const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + lane;
+    const int i = bx * 64 + lane;
     float acc = 0.0f;
     if (i < n) {
         constexpr int U = 8;
@@ -617,6 +616,29 @@ __global__ void __launch_bounds__(1024) k_iv_sum(const float *__restrict__ part,
         for (int k = 0; k < 16; ++k) t += s_part[k][lane];
         g[i] = t;
     }
+}
+
+__global__ void __launch_bounds__(1024) k_iv_sum(const float *__restrict__ part, int nparts, int n,
+                                                 float *__restrict__ g)
+{
+    __shared__ float s_part[16][64];
+    iv_sum_body(part, nparts, n, g, blockIdx.x, s_part);
+}
+
+// The same for the jobs of a batch: block b belongs to the job whose block
+// range [begin[k], begin[k + 1]) holds it.
+__global__ void __launch_bounds__(1024) k_iv_sum_batch(const ElemJob *__restrict__ jobs, const int *__restrict__ begin,
+                                                       int njobs)
+{
+    __shared__ float s_part[16][64];
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const ElemJob &J = jobs[lo];
+    iv_sum_body(J.part, J.nparts, J.npix, J.g, (int)blockIdx.x - begin[lo], s_part);
 }
 
 // ---------------------------------------------------------------------------
@@ -1112,8 +1134,28 @@ csx_status csx_iv_forward(const csx_geometry *h, const float *f, float *part, si
 #undef CSX_IVF_T
 #undef CSX_IVF
     HIP_TRY(hipGetLastError());
+    if (!g) return CSX_OK;   // the kernel alone (csx_iv_forward_parts)
     hipLaunchKernelGGL(k_iv_sum, dim3((h->P.npix + 63) / 64), dim3(1024), 0, s, (const float *)part, v->nblk_f,
                        h->P.npix, g);
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
+
+csx_status csx_iv_forward_parts(const csx_geometry *h, const float *f, hipStream_t s)
+{
+    return csx_iv_forward(h, f, nullptr, 0, nullptr, s);
+}
+
+void csx_iv_parts(const csx_geometry *h, const float **part, int *nparts)
+{
+    const IvState *v = (const IvState *)h->iv;
+    *part = v->part;
+    *nparts = v->nblk_f;
+}
+
+csx_status csx_launch_iv_sum_batch(const ElemJob *jobs, const int *begin, int njobs, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iv_sum_batch, dim3(nblocks), dim3(1024), 0, s, jobs, begin, njobs);
     HIP_TRY(hipGetLastError());
     return CSX_OK;
 }

@@ -25,17 +25,15 @@ __device__ __forceinline__ double block_sum_d(double v, double *s_red)
     return t;
 }
 
-__global__ void __launch_bounds__(256) k_ratio(int n, const float *__restrict__ g,
-                                               const float *__restrict__ y,
-                                               const float *__restrict__ r,
-                                               float *__restrict__ rho, double *__restrict__ partL,
-                                               int *__restrict__ partF, int want_rho)
+// bx: the block (blockIdx.x of the single-scan launch)
+__device__ __forceinline__ void ratio_body(int n, const float *__restrict__ g, const float *__restrict__ y,
+                                           const float *__restrict__ r, float *__restrict__ rho,
+                                           double *__restrict__ partL, int *__restrict__ partF, int want_rho,
+                                           int bx, double *s_red, int &s_flag)
 {
-    __shared__ double s_red[4];
-    __shared__ int s_flag;
     if (threadIdx.x == 0) s_flag = 0;
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = bx * blockDim.x + threadIdx.x;
     double L = 0.0;
     int flag = 0;
     if (i < n) {
@@ -60,9 +58,20 @@ __global__ void __launch_bounds__(256) k_ratio(int n, const float *__restrict__ 
     if (flag) atomicOr(&s_flag, flag);
     const double t = block_sum_d(L, s_red);
     if (threadIdx.x == 0) {
-        partL[blockIdx.x] = t;
-        partF[blockIdx.x] = s_flag;
+        partL[bx] = t;
+        partF[bx] = s_flag;
     }
+}
+
+__global__ void __launch_bounds__(256) k_ratio(int n, const float *__restrict__ g,
+                                               const float *__restrict__ y,
+                                               const float *__restrict__ r,
+                                               float *__restrict__ rho, double *__restrict__ partL,
+                                               int *__restrict__ partF, int want_rho)
+{
+    __shared__ double s_red[4];
+    __shared__ int s_flag;
+    ratio_body(n, g, y, r, rho, partL, partF, want_rho, blockIdx.x, s_red, s_flag);
 }
 
 // J = sum partL + beta * sum partR in a fixed order by one block, flags
@@ -99,15 +108,13 @@ __device__ void objective_block(const double *__restrict__ partL, int nL, const 
 // loads and stores when VEC = 4).  HUB = 0: the quadratic potential (delta
 // is not read), 1: Huber's.
 template <int VEC, int HUB>
-__global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const float *__restrict__ fh,
-                                                const float *__restrict__ b1,
-                                                const float *__restrict__ b2, double beta,
-                                                float *__restrict__ fout,
-                                                double *__restrict__ partR, int do_update, double delta)
+__device__ __forceinline__ void update_body(int nx, int nz, int nq, const float *__restrict__ fh,
+                                            const float *__restrict__ b1, const float *__restrict__ b2, double beta,
+                                            float *__restrict__ fout, double *__restrict__ partR, int do_update,
+                                            double delta, int bx, double *s_red)
 {
-    __shared__ double s_red[4];
     const int n = nx * nz * nq;
-    const int e0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+    const int e0 = (bx * blockDim.x + threadIdx.x) * VEC;
     double R = 0.0;
     if (e0 < n) {
         const int j = e0 / nq;
@@ -151,7 +158,18 @@ __global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const fl
         }
     }
     const double t = block_sum_d(R, s_red);
-    if (threadIdx.x == 0) partR[blockIdx.x] = t;
+    if (threadIdx.x == 0) partR[bx] = t;
+}
+
+template <int VEC, int HUB>
+__global__ void __launch_bounds__(256) k_update(int nx, int nz, int nq, const float *__restrict__ fh,
+                                                const float *__restrict__ b1,
+                                                const float *__restrict__ b2, double beta,
+                                                float *__restrict__ fout,
+                                                double *__restrict__ partR, int do_update, double delta)
+{
+    __shared__ double s_red[4];
+    update_body<VEC, HUB>(nx, nz, nq, fh, b1, b2, beta, fout, partR, do_update, delta, blockIdx.x, s_red);
 }
 
 // K5: J = sum partL + beta * sum partR in a fixed order, one block; the
@@ -253,9 +271,78 @@ __global__ void __launch_bounds__(256) k_copy4_objective(const float4 *__restric
     if (e < n4) d[e] = s[e];
 }
 
+// The batched form's jobs (ElemJob): block b belongs to the job whose block
+// range [begin[k], begin[k + 1]) holds it, and does what block b - begin[k]
+// of the job's single-scan launch does.
+__device__ __forceinline__ int elem_job(const int *__restrict__ begin, int njobs, int b)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_ratio_batch(const ElemJob *__restrict__ jobs, const int *__restrict__ begin,
+                                                     int njobs)
+{
+    __shared__ double s_red[4];
+    __shared__ int s_flag;
+    const int k = elem_job(begin, njobs, blockIdx.x);
+    const ElemJob &J = jobs[k];
+    ratio_body(J.npix, J.g, J.y, J.r, J.rho, J.partL, J.partF, 1, (int)blockIdx.x - begin[k], s_red, s_flag);
+}
+
+template <int HUB>
+__global__ void __launch_bounds__(256) k_update_batch(const ElemJob *__restrict__ jobs, const int *__restrict__ begin,
+                                                      int njobs, double beta)
+{
+    __shared__ double s_red[4];
+    const int k = elem_job(begin, njobs, blockIdx.x);
+    const ElemJob &J = jobs[k];
+    update_body<4, HUB>(J.nx, J.nz, J.nq, J.f, J.b1, J.b2, beta, J.ftmp, J.partR, 1, J.delta,
+                        (int)blockIdx.x - begin[k], s_red);
+}
+
+// copy-back blocks, then the job's objective block last
+__global__ void __launch_bounds__(256) k_copy4_objective_batch(const ElemJob *__restrict__ jobs,
+                                                               const int *__restrict__ begin, int njobs, double beta,
+                                                               const int *__restrict__ iter)
+{
+    const int k = elem_job(begin, njobs, blockIdx.x);
+    const ElemJob &J = jobs[k];
+    const int b = (int)blockIdx.x - begin[k];
+    const int n4 = J.nx * J.nz * J.nq / 4;
+    if (b == (n4 + 255) / 256) {
+        __shared__ double s_red[4];
+        __shared__ int s_flag;
+        objective_block(J.partL, J.nL, J.partR, J.nR, J.partF, beta, J.flags, J.J, iter, s_red, &s_flag);
+        return;
+    }
+    const int e = b * blockDim.x + threadIdx.x;
+    if (e < n4) ((float4 *)J.fdst)[e] = ((const float4 *)J.ftmp)[e];
+}
+
 __global__ void k_clear_int(int *p) { *p = 0; }
 
 }  // namespace
+
+csx_status csx_launch_elem_batch(int which, const ElemJob *jobs, const int *begin, int njobs, int nblocks, double beta,
+                                 int hub, const int *iter, hipStream_t s)
+{
+    if (which == 0) {
+        hipLaunchKernelGGL(k_ratio_batch, dim3(nblocks), dim3(256), 0, s, jobs, begin, njobs);
+    } else if (which == 1) {
+        if (hub) hipLaunchKernelGGL(k_update_batch<1>, dim3(nblocks), dim3(256), 0, s, jobs, begin, njobs, beta);
+        else hipLaunchKernelGGL(k_update_batch<0>, dim3(nblocks), dim3(256), 0, s, jobs, begin, njobs, beta);
+    } else {
+        hipLaunchKernelGGL(k_copy4_objective_batch, dim3(nblocks), dim3(256), 0, s, jobs, begin, njobs, beta, iter);
+    }
+    HIP_TRY(hipGetLastError());
+    return CSX_OK;
+}
 
 csx_status csx_launch_ratio(csx_geometry *h, const float *y, const float *r, bool want_rho,
                             hipStream_t s)
