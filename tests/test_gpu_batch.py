@@ -201,3 +201,38 @@ def test_batch64_shapes_in_a_merged_launch(oracle_mod):
         dJ = np.max(np.abs(J_bat[k] - ref_J) / ref_J)
         print(f"batched {geoms[k].nx}^2 x {geoms[k].nq} q: f rel-L2 {e:.3e}, max |dJ|/J {dJ:.3e}")
         assert dJ <= 1e-6
+
+
+@pytest.mark.parametrize("direct_one", [False, True], ids=["all_interval", "one_direct"])
+def test_batch_merged_elementwise_equals_sequential(direct_one):
+    """Scans whose q counts are multiples of 4 take the merged elementwise
+    launches (partial-image sums, ratios, updates, copy-backs of every
+    interval-form scan in one launch each); with one scan on the direct
+    operators beside them, that scan keeps its own launches.  Either way the
+    batch reproduces the sequential runs bitwise, per-scan iteration counts
+    included."""
+    scans = [s for s in mixed_scans() if s[0].nq % 4 == 0]
+    assert len(scans) >= 4
+    geos = [csx.Geometry(g) for g, _ in scans]
+    geos2 = [csx.Geometry(g) for g, _ in scans]
+    if direct_one:
+        geos[1].set_interval_operators(False)
+        geos2[1].set_interval_operators(False)
+    assert sum(g.interval_operators()["on"] for g in geos2) >= 3
+    ys = [dev(counts_for(geo, f, 11 + k)) for k, (geo, (_, f)) in enumerate(zip(geos, scans))]
+    counts = [3, 5, 0, 4, 2][:len(scans)]
+    beta = 1e-3
+    f_seq, J_seq = [], []
+    for geo, y, n in zip(geos, ys, counts):
+        f = geo.new_image()
+        J_seq.append(geo.recon(y, f, n, beta))
+        f_seq.append(f)
+    for a, b in zip(geos, geos2):
+        lc = a.get_launch()
+        b.set_launch(lc["fwd_splits"], lc["fwd_qw"], lc["adj_qw"])
+    batch = csx.Batch(geos2)
+    f_bat = [g.new_image() for g in geos2]
+    J_bat = batch.recon(ys, f_bat, counts, beta)
+    for k in range(len(scans)):
+        assert torch.equal(f_seq[k], f_bat[k]), k
+        np.testing.assert_array_equal(J_seq[k], J_bat[k][:counts[k] + 1])
