@@ -63,9 +63,13 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        # CSX_ORACLE_LIB: another build of the same source (the sanitizer test's)
+        path = os.environ.get("CSX_ORACLE_LIB")
+        if not path:
+            if not os.path.exists(_LIB):
+                build(force=False)
+            path = _LIB
+        lib = ctypes.CDLL(path)
         P = ctypes.POINTER
         gp = P(_OrcGeom)
         dp = P(ctypes.c_double)
